@@ -1,0 +1,349 @@
+"""SP-SVM in plain FP64 NumPy: the oracle the GPU library is checked against (test infrastructure only).
+
+Problem (section 4, "Sparse primal optimization", Eq. 4, with the bias omitted as section 2 allows):
+
+    F(beta) = 1/2 beta^T K_JJ beta + C/2 sum_i max(0, 1 - y_i o_i)^2,    o = K_XJ beta,
+
+where K_XJ[i, k] = k(x_i, x_{J_k}) with the RBF kernel of section 2 and K_JJ = K_XJ[J, :]. The code
+works with f = F / C, i.e. with lambda = 1 / C on the regulariser:
+
+    f(beta) = lambda/2 beta^T K_JJ beta + 1/2 sum_i max(0, a_i)^2,   a_i = 1 - y_i o_i.
+
+The squared hinge and unconstrained beta are the two relaxations of section 4 ("Primal optimization",
+Eq. 3) that make Newton's method applicable. Training alternates greedy basis selection and Newton
+re-optimisation of Eq. 4 on the grown basis, as section 4 describes.
+
+Readings of what the paper leaves open (the details are in Keerthi et al., which is not reproduced):
+
+* Bias b = 0 throughout.
+* Candidate score: the exact decrease of f when only the new coefficient is optimised, the other
+  coefficients held fixed (a one-dimensional convex piecewise-quadratic problem, solved exactly).
+* Argmax ties: a strictly larger score wins; equal scores go to the lower training-row index.
+* A new basis member enters with its one-dimensional optimum as coefficient; Newton starts from there.
+* Duplicate rows (identical feature vectors) give identical kernel columns and a singular K_JJ, so a
+  row whose duplicate group already has a basis member is never drawn (as J stood at the start of the
+  stage) and scores -inf (as J stands at the time of scoring).
+* Newton direction d = -H^{-1} grad f with the generalised Hessian H = lambda K_JJ + K_I^T K_I over the
+  violators I = {i : y_i o_i < 1}; step length by exact minimisation of f along d (t >= 0).
+  H is re-formed only when I changes. Stop when ||grad f|| <= tol * max(1, ||grad f at entry||), when
+  the exact step decreases f by no more than ftol * f, when no descent is possible, or after max_iter
+  iterations.
+* Cholesky failure: retry with H + mu * mean(diag H) * I for mu in (1e-14, 1e-12, 1e-10, 1e-8), then
+  give up (NotPositiveDefinite).
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+import scipy.linalg
+
+from .kernel import rbf_block
+from .rng import draw_candidates, stage_size
+
+JITTER = (1e-14, 1e-12, 1e-10, 1e-8)
+
+
+class NotPositiveDefinite(RuntimeError):
+    pass
+
+
+# ------------------------------------------------------------------------------------------------ objective
+def objective(KXJ: np.ndarray, KJJ: np.ndarray, y: np.ndarray, beta: np.ndarray, lam: float) -> float:
+    """f(beta) = lambda/2 beta^T K_JJ beta + 1/2 sum max(0, 1 - y_i o_i)^2 (Eq. 4 divided by C)."""
+    if beta.size == 0:
+        return 0.5 * float(y.shape[0])
+    o = KXJ @ beta
+    a = 1.0 - y * o
+    return 0.5 * lam * float(beta @ (KJJ @ beta)) + 0.5 * float(np.sum(np.maximum(0.0, a) ** 2))
+
+
+def gradient(KXJ: np.ndarray, KJJ: np.ndarray, y: np.ndarray, beta: np.ndarray, lam: float) -> np.ndarray:
+    """grad f = lambda K_JJ beta - sum_{i in I} y_i a_i k_i, with k_i row i of K_XJ."""
+    o = KXJ @ beta
+    a = 1.0 - y * o
+    act = a > 0
+    return lam * (KJJ @ beta) - KXJ[act].T @ (y[act] * a[act])
+
+
+def cholesky_jitter(H: np.ndarray) -> np.ndarray:
+    """Lower Cholesky factor of H, with the jitter retry schedule on failure."""
+    try:
+        return np.linalg.cholesky(H)
+    except np.linalg.LinAlgError:
+        pass
+    scale = float(np.mean(np.diag(H)))
+    for mu in JITTER:
+        try:
+            return np.linalg.cholesky(H + mu * scale * np.eye(H.shape[0]))
+        except np.linalg.LinAlgError:
+            continue
+    raise NotPositiveDefinite("H is not positive definite after the jitter schedule")
+
+
+# ------------------------------------------------------------------------------------- 1-D exact minimisers
+def _segment_root(a, b, lam_c1, lam_c2, rep):
+    """Root of the linear piece of the derivative on the segment holding ``rep`` (active set fixed there)."""
+    act = a - rep * b > 0
+    return (float(np.sum(a[act] * b[act])) - lam_c1) / (lam_c2 + float(np.sum(b[act] * b[act])))
+
+
+def exact_line_search(a: np.ndarray, b: np.ndarray, lam: float, c1: float, c2: float):
+    """Minimise phi(t) = lambda (t c1 + t^2 c2 / 2) + 1/2 sum max(0, a_i - t b_i)^2 over t >= 0.
+
+    With a_i = 1 - y_i o_i, b_i = y_i delta_i (delta = K_XJ d), c1 = beta^T K_JJ d, c2 = d^T K_JJ d this is
+    f(beta + t d) up to a constant. phi' is continuous, piecewise linear and increasing. The breakpoints
+    a_i / b_i are sorted, the segment holding the root is found by bisection over them (phi' evaluated by
+    a full sum each time), and the root is solved on that segment.
+    Returns (t*, phi(0) - phi(t*)).
+    """
+    def dphi(t):
+        return lam * (c1 + t * c2) - float(np.sum(b * np.maximum(0.0, a - t * b)))
+
+    if dphi(0.0) >= 0.0:
+        return 0.0, 0.0
+    nz = b != 0
+    bp = a[nz] / b[nz]
+    bp = np.unique(bp[bp > 0])
+    lo, hi = 0, bp.size
+    while lo < hi:  # first breakpoint where phi' >= 0
+        mid = (lo + hi) // 2
+        if dphi(bp[mid]) >= 0.0:
+            hi = mid
+        else:
+            lo = mid + 1
+    left = bp[lo - 1] if lo > 0 else 0.0
+    right = bp[lo] if lo < bp.size else math.inf
+    rep = 0.5 * (left + right) if math.isfinite(right) else left + 1.0
+    t = _segment_root(a, b, lam * c1, lam * c2, rep)
+    t = min(max(t, left), right)
+    return t, _decrease(a, b, t, lam * c1, lam * c2)
+
+
+def _decrease(a, b, t, lam_c1, lam_c2):
+    """phi(0) - phi(t) summed term by term (no cancellation between two large totals)."""
+    a0 = np.maximum(0.0, a)
+    at = np.maximum(0.0, a - t * b)
+    return 0.5 * float(np.sum((a0 - at) * (a0 + at))) - (t * lam_c1 + 0.5 * t * t * lam_c2)
+
+
+def score_candidate(a: np.ndarray, b: np.ndarray, lam: float, o_c: float):
+    """Exact decrease of f from adding one basis point c with coefficient s, others fixed.
+
+    psi(s) - f = lambda (s o_c + s^2 / 2) + 1/2 sum [max(0, a_i - s b_i)^2 - max(0, a_i)^2],
+    with a_i = 1 - y_i o_i, b_i = y_i k(x_i, x_c), o_c = (K_XJ beta)_c and k(x_c, x_c) = 1.
+    s ranges over all reals. Returns (s*, Delta = psi(0) - psi(s*) >= 0).
+    """
+    def dpsi(s):
+        return lam * (o_c + s) - float(np.sum(b * np.maximum(0.0, a - s * b)))
+
+    nz = b != 0
+    bp = np.unique(a[nz] / b[nz])
+    lo, hi = 0, bp.size
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if dpsi(bp[mid]) >= 0.0:
+            hi = mid
+        else:
+            lo = mid + 1
+    left = bp[lo - 1] if lo > 0 else -math.inf
+    right = bp[lo] if lo < bp.size else math.inf
+    if math.isfinite(left) and math.isfinite(right):
+        rep = 0.5 * (left + right)
+    elif math.isfinite(left):
+        rep = left + 1.0
+    elif math.isfinite(right):
+        rep = right - 1.0
+    else:
+        rep = 0.0
+    s = _segment_root(a, b, lam * o_c, lam, rep)
+    s = min(max(s, left), right)
+    return s, _decrease(a, b, s, lam * o_c, lam)
+
+
+# ------------------------------------------------------------------------------------------------- Newton
+@dataclasses.dataclass
+class NewtonInfo:
+    iterations: int = 0
+    factorizations: int = 0
+    grad_norm0: float = 0.0
+    grad_norm: float = 0.0
+    f_trace: list = dataclasses.field(default_factory=list)
+    steps: list = dataclasses.field(default_factory=list)
+
+
+def newton_solve(KXJ: np.ndarray, KJJ: np.ndarray, y: np.ndarray, lam: float, beta: np.ndarray,
+                 tol: float = 1e-10, ftol: float = 1e-14, max_iter: int = 50):
+    """Minimise f over beta for a fixed basis (the re-optimisation of Eq. 4), from ``beta``.
+
+    Each iteration: o = K_XJ beta, I = {a_i > 0}, g = grad f; H = lambda K_JJ + K_I^T K_I (re-formed when I
+    changed), d = -H^{-1} g by Cholesky, exact line search along d.
+    """
+    beta = np.array(beta, dtype=np.float64, copy=True)
+    info = NewtonInfo()
+    if beta.size == 0:
+        return beta, info
+    fact_act = None
+    L = None
+    for it in range(max_iter):
+        o = KXJ @ beta
+        a = 1.0 - y * o
+        act = a > 0
+        g = gradient(KXJ, KJJ, y, beta, lam)
+        gn = float(np.linalg.norm(g))
+        if it == 0:
+            info.grad_norm0 = gn
+        info.grad_norm = gn
+        f_now = 0.5 * lam * float(beta @ (KJJ @ beta)) + 0.5 * float(np.sum(np.maximum(0.0, a) ** 2))
+        info.f_trace.append(f_now)
+        if gn <= tol * max(1.0, info.grad_norm0):
+            break
+        if fact_act is None or not np.array_equal(fact_act, act):
+            H = lam * KJJ + KXJ[act].T @ KXJ[act]
+            L = cholesky_jitter(H)
+            fact_act = act
+            info.factorizations += 1
+        d = -scipy.linalg.cho_solve((L, True), g)
+        delta = KXJ @ d
+        t, dec = exact_line_search(a, y * delta, lam, float(beta @ (KJJ @ d)), float(d @ (KJJ @ d)))
+        info.iterations = it + 1
+        info.steps.append((t, dec))
+        if t == 0.0:
+            break
+        beta = beta + t * d
+        if dec <= ftol * f_now:
+            info.f_trace.append(f_now - dec)
+            break
+    return beta, info
+
+
+# ------------------------------------------------------------------------------------------- selection
+def duplicate_groups(X: np.ndarray) -> np.ndarray:
+    """Group id per row: rows with identical feature vectors share an id."""
+    _, inv = np.unique(np.asarray(X, dtype=np.float64), axis=0, return_inverse=True)
+    return np.asarray(inv).reshape(-1)
+
+
+@dataclasses.dataclass
+class TrainResult:
+    J: np.ndarray
+    beta: np.ndarray
+    F: float  # paper-scale objective C * f
+    f_trace: list  # f after every addition and every Newton iterate (must not increase)
+    gaps: list  # per addition step: (best - second best) / best score
+    stages: list  # number of additions per stage
+    newton_iters: list
+
+
+def _validate(X, y, C, gamma, J_max, groups):
+    if not (np.isfinite(C) and C > 0 and np.isfinite(gamma) and gamma > 0):
+        raise ValueError("C and gamma must be finite and positive")
+    if not np.all((y == 1.0) | (y == -1.0)):
+        raise ValueError("labels must be exactly +1 or -1")
+    if not np.all(np.isfinite(X)):
+        raise ValueError("X holds NaN or Inf")
+    if not (1 <= J_max <= int(groups.max()) + 1):
+        raise ValueError("J_max must lie in [1, number of distinct rows]")
+
+
+def train(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J_max: int, seed: int = 0, kappa: int = 59,
+          growth: float = 0.25, cap: int = 256, tol: float = 1e-10, ftol: float = 1e-14, max_iter: int = 50,
+          max_steps: Optional[int] = None) -> TrainResult:
+    """Greedy basis growth with Newton re-optimisation after each stage (section 4).
+
+    ``max_steps`` (timing samples only) stops after that many addition steps, skipping the final Newton.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = X.shape[0]
+    groups = duplicate_groups(X)
+    _validate(X, y, C, gamma, J_max, groups)
+    lam = 1.0 / C
+    J: list[int] = []
+    beta = np.zeros(0)
+    KXJ = np.zeros((n, 0))
+    o = np.zeros(n)
+    used_groups: set = set()
+    f_trace = [0.5 * n]
+    gaps, stages, newton_iters = [], [], []
+    t = 0
+    while len(J) < J_max:
+        cs = stage_size(len(J), J_max, growth, cap)
+        frozen = set(used_groups)
+        draws = [draw_candidates(seed, t + q, n, kappa, lambda i: groups[i] in frozen) for q in range(cs)]
+        added = 0
+        new_cols = []
+        for q in range(cs):
+            best = None  # (score, index, s, column)
+            second = -math.inf
+            a = 1.0 - y * o
+            for c in draws[q]:
+                if groups[c] in used_groups:
+                    continue
+                k = rbf_block(X, X[c:c + 1], gamma)[:, 0]
+                s, dl = score_candidate(a, y * k, lam, float(o[c]))
+                if best is None or dl > best[0] or (dl == best[0] and c < best[1]):
+                    if best is not None:
+                        second = max(second, best[0])
+                    best = (dl, c, s, k)
+                else:
+                    second = max(second, dl)
+            if best is None:
+                continue
+            dl, c, s, k = best
+            gaps.append((dl - second) / dl if dl > 0 and math.isfinite(second) else math.inf)
+            J.append(c)
+            used_groups.add(groups[c])
+            beta = np.append(beta, s)
+            o = o + s * k
+            new_cols.append(k)
+            f_trace.append(f_trace[-1] - dl)
+            added += 1
+        t += cs
+        stages.append(added)
+        if added == 0:
+            break
+        KXJ = np.concatenate([KXJ, np.stack(new_cols, axis=1)], axis=1)
+        if max_steps is not None and t >= max_steps:
+            break
+        KJJ = KXJ[J, :]
+        beta, info = newton_solve(KXJ, KJJ, y, lam, beta, tol=tol, ftol=ftol, max_iter=max_iter)
+        newton_iters.append(info.iterations)
+        f_trace.extend(info.f_trace[1:])
+        o = KXJ @ beta
+    KJJ = KXJ[J, :]
+    F = C * objective(KXJ, KJJ, y, beta, lam)
+    return TrainResult(np.array(J, dtype=np.int64), beta, F, f_trace, gaps, stages, newton_iters)
+
+
+def solve_fixed_J(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J, beta0=None, tol: float = 1e-10,
+                  ftol: float = 1e-14, max_iter: int = 50):
+    """Newton re-optimisation of Eq. 4 on a given basis J, from beta0 (default 0).
+
+    Returns (beta, F, info) with F the paper-scale objective at the returned beta.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    J = np.asarray(J, dtype=np.int64)
+    KXJ = rbf_block(X, X[J], gamma)
+    KJJ = KXJ[J, :]
+    lam = 1.0 / C
+    b0 = np.zeros(J.size) if beta0 is None else np.asarray(beta0, dtype=np.float64)
+    beta, info = newton_solve(KXJ, KJJ, y, lam, b0, tol=tol, ftol=ftol, max_iter=max_iter)
+    return beta, C * objective(KXJ, KJJ, y, beta, lam), info
+
+
+def objective_at(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J, beta) -> float:
+    """Paper-scale F(beta) on basis J, everything recomputed in FP64 from X."""
+    X = np.asarray(X, dtype=np.float64)
+    J = np.asarray(J, dtype=np.int64)
+    KXJ = rbf_block(X, X[J], gamma)
+    return C * objective(KXJ, KXJ[J, :], np.asarray(y, dtype=np.float64), np.asarray(beta, np.float64), 1.0 / C)
+
+
+def predict(X_basis: np.ndarray, beta: np.ndarray, gamma: float, Xt: np.ndarray) -> np.ndarray:
+    """Decision values sum_k beta_k k(x, x_{J_k}) for each row x of Xt."""
+    return rbf_block(Xt, X_basis, gamma) @ np.asarray(beta, dtype=np.float64)

@@ -1,0 +1,410 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test checks one part of the oracle against a closed form, a published value, a brute-force
+enumeration, the dual problem, or a derivative-free search. The helpers return an error measure so
+that ``test_oracle_mutations.py`` can plant mistakes in the oracle and check that these pins catch them.
+"""
+
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import rng as orng
+from oracle import spsvm as osp
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_lines(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return [ln.strip() for ln in fh if ln.strip() and not ln.startswith("#")]
+
+
+# ------------------------------------------------------------------------------------------------ kernel
+def rbf_closed_form_error():
+    err = 0.0
+    for ln in _golden_lines("rbf_closed_form.txt"):
+        xs, zs, g, d2 = [p.strip() for p in ln.split(";")]
+        x = np.array([float(v) for v in xs.split(",")])
+        z = np.array([float(v) for v in zs.split(",")])
+        want = math.exp(-float(g) * float(d2))
+        got = oracle.rbf_block(x[None], z[None], float(g))[0, 0]
+        err = max(err, abs(got - want) / want)
+    return err
+
+
+def test_rbf_closed_form():
+    assert rbf_closed_form_error() < 1e-15
+
+
+def test_rbf_diagonal_and_symmetry():
+    r = np.random.default_rng(0)
+    X = r.standard_normal((37, 11))
+    K = oracle.rbf_block(X, X, 0.3)
+    assert np.array_equal(np.diag(K), np.ones(37))
+    assert np.array_equal(K, K.T)
+    assert np.all((K > 0) & (K <= 1))
+
+
+def test_rbf_c_and_numpy_agree():
+    from oracle.kernel import rbf_block_numpy
+
+    r = np.random.default_rng(1)
+    X = r.standard_normal((50, 13))
+    Z = r.standard_normal((7, 13))
+    a = oracle.rbf_block(X, Z, 0.2)
+    b = rbf_block_numpy(X, Z, 0.2)
+    assert np.max(np.abs(a - b)) < 1e-15
+
+
+# ------------------------------------------------------------------------------------------------ RNG
+def test_splitmix64_published_outputs():
+    want = [int(v, 16) for v in _golden_lines("splitmix64_seed0.txt")]
+    assert orng.splitmix64_stream(0, len(want)) == want
+
+
+def test_candidate_draw_rules():
+    n, kappa = 1000, 59
+    blocked = set(range(0, 1000, 3))
+    c = orng.draw_candidates(7, 5, n, kappa, lambda i: i in blocked)
+    assert len(c) == kappa and len(set(c)) == kappa
+    assert all(0 <= i < n and i not in blocked for i in c)
+    # the same step of the same seed draws the same indices; another step draws others
+    assert c == orng.draw_candidates(7, 5, n, kappa, lambda i: i in blocked)
+    assert c != orng.draw_candidates(7, 6, n, kappa, lambda i: i in blocked)
+    # few rows available: fewer than kappa candidates, after at most 64 kappa attempts
+    c2 = orng.draw_candidates(7, 5, 10, kappa, lambda i: i != 3)
+    assert c2 == [3]
+
+
+def test_candidate_index_is_high_bits_scaled():
+    # index = floor(hi32(z) * n / 2^32): check against exact rational arithmetic on the published stream
+    z = orng.splitmix64_stream(0, 1)[0]
+    for n in (1, 2, 123, 100000, 2**31 + 11):
+        assert orng.scaled_index(z, n) == (z >> 32) * n // 2**32
+        assert 0 <= orng.scaled_index(z, n) < n
+
+
+def test_stage_schedule():
+    want = [int(v) for v in _golden_lines("stage_schedule_jmax100.txt")[0].split()]
+    got, J = [], 0
+    while J < 100:
+        c = orng.stage_size(J, 100)
+        got.append(c)
+        J += c
+    assert got == want
+
+
+# --------------------------------------------------------------------------------- one-dimensional solves
+def _golden_section(fun, lo, hi, iters=200):
+    g = (math.sqrt(5) - 1) / 2
+    a, b = lo, hi
+    c, d = b - g * (b - a), a + g * (b - a)
+    fc, fd = fun(c), fun(d)
+    for _ in range(iters):
+        if fc <= fd:
+            b, d, fd = d, c, fc
+            c = b - g * (b - a)
+            fc = fun(c)
+        else:
+            a, c, fc = c, d, fd
+            d = a + g * (b - a)
+            fd = fun(d)
+    return 0.5 * (a + b)
+
+
+def _phi(a, b, lam, c1, c2, t):
+    return lam * (t * c1 + 0.5 * t * t * c2) + 0.5 * float(np.sum(np.maximum(0.0, a - t * b) ** 2))
+
+
+def line_search_error(seeds=range(20)):
+    """max over random piecewise-quadratics of |t* - t_golden| / (1 + t) and of the decrease mismatch."""
+    worst = 0.0
+    for sd in seeds:
+        r = np.random.default_rng(100 + sd)
+        n = int(r.integers(5, 200))
+        a = r.standard_normal(n) * 2
+        b = r.standard_normal(n)
+        lam = float(r.uniform(0.01, 3))
+        c2 = float(r.uniform(0.1, 5))
+        c1 = float(r.standard_normal()) * 3
+        if lam * c1 - float(np.sum(b * np.maximum(0, a))) >= 0:
+            c1 = -abs(c1) - float(np.sum(np.abs(b) * np.maximum(0, a))) / lam - 1.0  # force a descent direction
+        t, dec = osp.exact_line_search(a, b, lam, c1, c2)
+        # a dense grid brackets the minimiser, golden section refines it
+        hi = 1.0
+        while _phi(a, b, lam, c1, c2, hi) < _phi(a, b, lam, c1, c2, hi / 2):
+            hi *= 2
+        grid = np.linspace(0, hi, 20001)
+        vals = np.array([_phi(a, b, lam, c1, c2, v) for v in grid])
+        k = int(np.argmin(vals))
+        tg = _golden_section(lambda v: _phi(a, b, lam, c1, c2, v), grid[max(k - 1, 0)], grid[min(k + 1, grid.size - 1)])
+        worst = max(worst, abs(t - tg) / (1 + abs(tg)))
+        direct = _phi(a, b, lam, c1, c2, 0.0) - _phi(a, b, lam, c1, c2, t)
+        worst = max(worst, abs(dec - direct) / (1 + abs(direct)))
+    return worst
+
+
+def test_line_search_matches_grid_and_golden_section():
+    assert line_search_error() < 1e-7
+
+
+def test_line_search_no_descent_gives_zero():
+    a = np.array([1.0, -1.0])
+    b = np.array([-1.0, 1.0])
+    assert osp.exact_line_search(a, b, 1.0, 5.0, 1.0) == (0.0, 0.0)
+
+
+def test_line_search_closed_form_without_breakpoints():
+    # every term stays active on [0, t*]: t* = (sum a b - lam c1) / (lam c2 + sum b^2)
+    a = np.array([10.0, 12.0, 9.0])
+    b = np.array([0.5, 0.25, 1.0])
+    lam, c1, c2 = 0.5, -1.0, 2.0
+    t, _ = osp.exact_line_search(a, b, lam, c1, c2)
+    want = (a @ b - lam * c1) / (lam * c2 + b @ b)
+    assert np.all(a - want * b > 0)
+    assert abs(t - want) < 1e-15 * want
+
+
+def score_error(seeds=range(20)):
+    worst = 0.0
+    for sd in seeds:
+        r = np.random.default_rng(200 + sd)
+        n = int(r.integers(5, 150))
+        a = r.standard_normal(n) * 2
+        b = r.standard_normal(n) * r.uniform(0.1, 2)
+        lam = float(r.uniform(0.01, 3))
+        oc = float(r.standard_normal())
+
+        def psi(s):
+            return lam * (s * oc + 0.5 * s * s) + 0.5 * float(np.sum(np.maximum(0.0, a - s * b) ** 2))
+
+        s, dl = osp.score_candidate(a, b, lam, oc)
+        R = 1.0
+        while psi(R) < psi(R / 2) or psi(-R) < psi(-R / 2):
+            R *= 2
+        grid = np.linspace(-R, R, 40001)
+        vals = np.array([psi(v) for v in grid])
+        k = int(np.argmin(vals))
+        sg = _golden_section(psi, grid[max(k - 1, 0)], grid[min(k + 1, grid.size - 1)])
+        worst = max(worst, abs(s - sg) / (1 + abs(sg)))
+        worst = max(worst, abs(dl - (psi(0) - psi(s))) / (1 + abs(dl)))
+        assert dl >= 0
+    return worst
+
+
+def test_candidate_score_matches_grid_and_golden_section():
+    assert score_error() < 1e-7
+
+
+# -------------------------------------------------------------------------------------- Newton, fixed J
+def _tiny(n, d, seed, dup=False):
+    r = np.random.default_rng(seed)
+    X = r.standard_normal((n, d))
+    y = np.where(r.standard_normal(n) + X[:, 0] > 0, 1.0, -1.0)
+    if dup:
+        X[1] = X[0]
+    return X, y
+
+
+def violator_enumeration_error(seeds=range(6)):
+    """For tiny n, the optimum at fixed J is the unique self-consistent violator set's solution."""
+    worst = 0.0
+    for sd in seeds:
+        n, d = 10, 3
+        X, y = _tiny(n, d, 300 + sd)
+        J = np.array([0, 3, 7, 8])
+        C, gamma = [0.5, 2.0, 10.0][sd % 3], 0.4
+        K = oracle.rbf_block(X, X[J], gamma)
+        KJJ = K[J]
+        lam = 1 / C
+        consistent = []
+        for mask in itertools.product([False, True], repeat=n):
+            I = np.array(mask)
+            H = lam * KJJ + K[I].T @ K[I]
+            beta = np.linalg.solve(H, K[I].T @ y[I])
+            if np.array_equal(y * (K @ beta) < 1, I):
+                consistent.append(beta)
+        assert len(consistent) == 1
+        beta, F, _ = osp.solve_fixed_J(X, y, C, gamma, J)
+        worst = max(worst, float(np.max(np.abs(beta - consistent[0])) / (1 + np.max(np.abs(consistent[0])))))
+    return worst
+
+
+def test_newton_matches_violator_enumeration():
+    assert violator_enumeration_error() < 1e-9
+
+
+def dual_qp_error(seeds=range(5)):
+    """J = all points is Chapelle's primal (Eq. 3). Its optimum equals the L2-SVM dual
+    max_{alpha >= 0} sum alpha - 1/2 alpha^T Q alpha - |alpha|^2 / (2C), Q = (y y^T) * K, solved by
+    enumerating supports; beta = y * alpha and primal = dual."""
+    worst = 0.0
+    for sd in seeds:
+        n = 9
+        X, y = _tiny(n, 2, 400 + sd)
+        C, gamma = [0.7, 3.0, 20.0, 1.0, 5.0][sd], 0.6
+        K = oracle.rbf_block(X, X, gamma)
+        Q = np.outer(y, y) * K
+        found = []
+        for mask in itertools.product([False, True], repeat=n):
+            S = np.array(mask)
+            alpha = np.zeros(n)
+            if S.any():
+                alpha[S] = np.linalg.solve(Q[np.ix_(S, S)] + np.eye(S.sum()) / C, np.ones(S.sum()))
+            if np.any(alpha[S] < 0):
+                continue
+            if np.any((Q @ alpha)[~S] < 1):
+                continue
+            found.append(alpha)
+        assert len(found) == 1
+        alpha = found[0]
+        dual = alpha.sum() - 0.5 * alpha @ Q @ alpha - alpha @ alpha / (2 * C)
+        beta, F, _ = osp.solve_fixed_J(X, y, C, gamma, np.arange(n))
+        worst = max(worst, abs(F - dual) / abs(dual))
+        worst = max(worst, float(np.max(np.abs(beta - y * alpha)) / (1 + np.max(np.abs(alpha)))))
+    return worst
+
+
+def test_full_basis_matches_dual_qp():
+    assert dual_qp_error() < 1e-10
+
+
+def kernel_ridge_error():
+    """With a tiny C every point stays a violator and the optimum is a ridge solve."""
+    X, y = _tiny(60, 4, 500)
+    J = np.arange(0, 60, 4)
+    C, gamma = 1e-3, 0.3
+    K = oracle.rbf_block(X, X[J], gamma)
+    lam = 1 / C
+    want = np.linalg.solve(lam * K[J] + K.T @ K, K.T @ y)
+    assert np.all(y * (K @ want) < 1)
+    beta, F, _ = osp.solve_fixed_J(X, y, C, gamma, J)
+    Kf = oracle.rbf_block(X, X, gamma)
+    full = np.linalg.solve(lam * Kf + Kf @ Kf, Kf @ y)  # J = all points: (lam I + K) beta = y when K is PD
+    assert np.all(y * (Kf @ full) < 1)
+    betaf, _, _ = osp.solve_fixed_J(X, y, C, gamma, np.arange(60))
+    return max(float(np.max(np.abs(beta - want)) / np.max(np.abs(want))),
+               float(np.max(np.abs(betaf - full)) / np.max(np.abs(full))))
+
+
+def test_kernel_ridge_special_case():
+    assert kernel_ridge_error() < 1e-9
+
+
+def test_gradient_vanishes_at_solution_exact_sum():
+    X, y = _tiny(300, 5, 600)
+    J = np.arange(0, 300, 10)
+    C, gamma = 4.0, 0.25
+    beta, F, info = osp.solve_fixed_J(X, y, C, gamma, J)
+    K = oracle.rbf_block(X, X[J], gamma)
+    o = [math.fsum(K[i, k] * beta[k] for k in range(J.size)) for i in range(300)]
+    a = [1 - y[i] * o[i] for i in range(300)]
+    g = [math.fsum([o[J[k]] / C] + [-y[i] * a[i] * K[i, k] for i in range(300) if a[i] > 0]) for k in range(J.size)]
+    scale = math.fsum(abs(y[i] * a[i] * K[i, k]) for k in range(J.size) for i in range(300) if a[i] > 0)
+    assert max(abs(v) for v in g) <= 1e-12 * scale
+
+
+# ------------------------------------------------------------------------------------- selection, train
+def selection_bruteforce_mismatches(n=40, steps=12, seed=700):
+    """Replays the oracle's first additions: for each drawn candidate set, the best candidate by a direct
+    search (append the column, minimise the full objective over the new coefficient by golden section)
+    must be the one the oracle picked, with the same objective."""
+    X, y = _tiny(n, 3, seed)
+    C, gamma = 2.0, 0.5
+    lam = 1 / C
+    res = osp.train(X, y, C, gamma, J_max=steps, seed=3, kappa=6)
+    J, beta = [], np.zeros(0)
+    mism = 0
+    groups = osp.duplicate_groups(X)
+    t = 0
+    # replay the first stages (|J| < 8 gives one addition per stage)
+    for step in range(min(steps, 8)):
+        used = set(groups[j] for j in J)
+        cands = orng.draw_candidates(3, t, n, 6, lambda i: groups[i] in used)
+        best = None
+        for c in cands:
+            Jc = J + [c]
+            K = oracle.rbf_block(X, X[Jc], gamma)
+
+            def f(s):
+                return osp.objective(K, K[Jc], y, np.append(beta, s), lam)
+
+            R = 1.0
+            while f(R) < f(R / 2) or f(-R) < f(-R / 2):
+                R *= 2
+            grid = np.linspace(-R, R, 4001)
+            k = int(np.argmin([f(v) for v in grid]))
+            s = _golden_section(f, grid[max(k - 1, 0)], grid[min(k + 1, 4000)])
+            val = f(s)
+            if best is None or val < best[0] - 1e-12 or (abs(val - best[0]) <= 1e-12 and c < best[1]):
+                best = (val, c, s)
+        J.append(best[1])
+        if best[1] != res.J[step]:
+            mism += 1
+        # Newton after the stage, from the greedy coefficient
+        K = oracle.rbf_block(X, X[J], gamma)
+        beta, _ = osp.newton_solve(K, K[J], y, lam, np.append(beta, best[2]))
+        t += 1
+    return mism
+
+
+def test_selection_matches_bruteforce():
+    assert selection_bruteforce_mismatches() == 0
+
+
+def test_train_monotone_and_consistent():
+    X, y = _tiny(400, 4, 800)
+    res = osp.train(X, y, 1.0, 0.5, J_max=40, seed=1)
+    ft = np.array(res.f_trace)
+    assert np.all(np.diff(ft) <= 1e-12 * ft[0])
+    assert len(res.J) == 40 and len(set(res.J.tolist())) == 40
+    assert sum(res.stages) == 40
+    # the returned objective equals the objective recomputed from (J, beta)
+    F = osp.objective_at(X, y, 1.0, 0.5, res.J, res.beta)
+    assert abs(F - res.F) <= 1e-12 * F
+    # the final beta is the optimum for its J
+    beta2, F2, _ = osp.solve_fixed_J(X, y, 1.0, 0.5, res.J)
+    assert abs(F2 - res.F) <= 1e-10 * F2
+
+
+def test_duplicate_rows_never_share_the_basis():
+    r = np.random.default_rng(900)
+    base = r.standard_normal((30, 3))
+    X = np.concatenate([base, base, base[:10]])  # 70 rows, 30 distinct
+    y = np.where(X[:, 0] + 0.3 * r.standard_normal(70) > 0, 1.0, -1.0)
+    y[30:60] = y[:30]
+    y[60:] = y[:10]
+    res = osp.train(X, y, 1.0, 0.5, J_max=30, seed=2, kappa=8)
+    g = osp.duplicate_groups(X)
+    assert len(set(g[res.J].tolist())) == len(res.J)
+    with pytest.raises(ValueError):
+        osp.train(X, y, 1.0, 0.5, J_max=31)
+
+
+def test_argument_validation():
+    X, y = _tiny(20, 2, 1)
+    with pytest.raises(ValueError):
+        osp.train(X, y, 0.0, 0.5, 5)
+    with pytest.raises(ValueError):
+        osp.train(X, y, 1.0, -1.0, 5)
+    bad = y.copy()
+    bad[3] = 0.5
+    with pytest.raises(ValueError):
+        osp.train(X, bad, 1.0, 0.5, 5)
+    Xn = X.copy()
+    Xn[2, 1] = np.nan
+    with pytest.raises(ValueError):
+        osp.train(Xn, y, 1.0, 0.5, 5)
+
+
+def test_cholesky_jitter_schedule():
+    H = np.array([[1.0, 1.0], [1.0, 1.0]])  # PSD, singular: first retry with mu = 1e-14 fails?
+    L = osp.cholesky_jitter(H)
+    assert np.allclose(L @ L.T, H, atol=1e-7)
+    with pytest.raises(osp.NotPositiveDefinite):
+        osp.cholesky_jitter(np.array([[1.0, 0.0], [0.0, -1.0]]))
