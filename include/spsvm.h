@@ -1,0 +1,154 @@
+/*
+ * spsvm.h - C ABI of the SP-SVM training library for AMD Instinct MI355X (gfx950).
+ *
+ * The library trains the sparse primal SVM of section 4 of "Parallel Support Vector Machines in
+ * Practice" ("Sparse primal optimization", Eq. 4) with the RBF kernel of section 2:
+ *
+ *   min_beta  F(beta) = 1/2 beta^T K_JJ beta + C/2 sum_i max(0, 1 - y_i sum_k beta_k k(x_i, x_{J_k}))^2,
+ *   k(x, z) = exp(-gamma ||x - z||^2),
+ *
+ * over a basis J of training rows that is grown greedily (random candidate subsets, each candidate
+ * scored by the loss reduction it brings) and re-optimised by Newton's method after each stage of
+ * additions. The bias term is omitted, as section 2 allows. Every step runs in HIP kernels on the GPU;
+ * the host only orchestrates launches.
+ *
+ * Conventions for every call:
+ *  - Pointers named "device" are HIP device pointers; the caller owns them and keeps them alive and
+ *    unmodified for the duration of the call. "host" pointers are ordinary CPU memory.
+ *  - Matrices are row-major and dense, with rows contiguous (row i of X starts at X + i * d).
+ *  - The stream argument is a hipStream_t passed as void*; NULL means the default stream. Calls are
+ *    synchronous with respect to the host: they return after their GPU work has finished.
+ *  - Every call returns a status code; no C++ exception crosses this interface. On failure, any
+ *    output model pointer is set to NULL and spsvm_last_error() describes the failure.
+ *  - Results are deterministic: the same inputs, options and device give bitwise-identical outputs
+ *    (fixed reduction orders, no floating-point atomics).
+ */
+#ifndef SPSVM_H
+#define SPSVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPSVM_OK = 0,
+  SPSVM_E_INVALID_ARG = 1,    /* an argument is out of range; nothing was launched */
+  SPSVM_E_OUT_OF_MEMORY = 2,  /* a model or host staging allocation failed */
+  SPSVM_E_HIP = 3,            /* a HIP runtime call failed; the message carries hipGetErrorString */
+  SPSVM_E_NOT_PD = 4,         /* the Newton matrix stayed non positive definite after the jitter retries */
+  SPSVM_E_NO_CONVERGENCE = 5, /* reserved: Newton hitting its iteration cap is reported in stats, not here */
+  SPSVM_E_WORKSPACE = 6       /* workspace pointer missing, misaligned (256 B) or smaller than required */
+} spsvm_status;
+
+/* Arithmetic used for the kernel values and the Newton matrix.
+ *  SPSVM_F64: everything in FP64 (distances, kernel block, Newton matrix).
+ *  SPSVM_F32: distances and kernel block in FP32 (FP32 MFMA), Newton matrix from FP32 products
+ *             accumulated in FP64; Cholesky, solves, line search, scores and objective in FP64.
+ *  SPSVM_MIXED: as F32, but squared distances from BF16 MFMA products with a hi/lo split
+ *             correction (x = hi + lo, both BF16; x.z ~ hi.hi + hi.lo + lo.hi). */
+typedef enum { SPSVM_F64 = 0, SPSVM_F32 = 1, SPSVM_MIXED = 2 } spsvm_precision;
+
+/* Element type of a feature matrix handed to the library. */
+typedef enum { SPSVM_DT_F32 = 0, SPSVM_DT_F64 = 1 } spsvm_dtype;
+
+typedef struct {
+  uint32_t struct_size;    /* sizeof(spsvm_options); set by spsvm_options_default */
+  uint64_t seed;           /* candidate-sampling seed (SplitMix64 streams, one per addition step) */
+  int32_t kappa;           /* candidates drawn per addition step, 1..64; default 59 */
+  double growth;           /* stage size = max(1, min(chunk_cap, floor(growth * |J|))); default 0.25 */
+  int32_t chunk_cap;       /* upper bound of the stage size, 1..4096; default 256 */
+  double newton_tol;       /* stop when ||grad f|| <= tol * max(1, ||grad f at entry||); default 1e-10 */
+  double newton_ftol;      /* stop when an exact step lowers f by <= ftol * f; default 1e-14 */
+  int32_t newton_max_iter; /* Newton iterations per re-optimisation, >= 1; default 50 */
+  spsvm_precision precision; /* default SPSVM_F32 */
+  int32_t log_level;       /* 0 silent; 1 one line per stage on stderr; 2 one line per Newton iteration */
+} spsvm_options;
+
+typedef struct spsvm_model spsvm_model; /* opaque, owned by the library */
+
+/* Training statistics of a model (filled by spsvm_model_stats). */
+typedef struct {
+  int64_t stages;           /* re-optimisation stages run */
+  int64_t additions;        /* basis vectors added by greedy selection */
+  int64_t newton_iters;     /* Newton iterations over all stages */
+  int64_t factorizations;   /* Cholesky factorisations of the Newton matrix (incl. jitter retries) */
+  int64_t score_passes;     /* O(n) passes spent on candidate scoring */
+  int64_t ls_passes;        /* O(n) passes spent in exact line searches */
+  int64_t iter_cap_hits;    /* re-optimisations stopped by newton_max_iter */
+  int64_t n_sv;             /* margin violators (y_i o_i < 1) at the returned solution */
+  double grad_norm;         /* ||grad f|| at the returned solution (f = F / C) */
+  double seconds_select;    /* wall time in greedy selection */
+  double seconds_newton;    /* wall time in Newton re-optimisation */
+} spsvm_stats;
+
+/* Fills *opt with the defaults listed above. */
+void spsvm_options_default(spsvm_options* opt);
+
+/* Bytes of device workspace spsvm_train needs for n rows, d features and up to J_max basis vectors
+ * with these options (NULL = defaults). The sizes of the kernel block n x J_max and the
+ * candidate block n x 64 dominate. */
+spsvm_status spsvm_train_workspace_bytes(int64_t n, int64_t d, int64_t J_max, const spsvm_options* opt,
+                                         size_t* bytes);
+
+/* Greedy SP-SVM training (section 4, Eq. 4): grows J to J_max rows and returns J and beta.
+ *  X:   device, n x d, element type xdt, finite values.
+ *  y:   device, n labels, each exactly +1.0f or -1.0f.
+ *  C, gamma: finite and > 0. J_max: 1 <= J_max <= number of distinct rows of X.
+ *  workspace: device, at least spsvm_train_workspace_bytes(...) bytes, 256-byte aligned; its
+ *    contents on entry do not matter and are undefined on return. No other device memory is
+ *    allocated except the returned model (X_J and beta copies).
+ *  out: receives the model; free it with spsvm_model_free.
+ * Rows with identical feature vectors (compared by a 64-bit hash of their values) never both
+ * enter J. If fewer than J_max rows can be added (all candidates blocked), training stops early
+ * and the model holds fewer basis vectors. */
+spsvm_status spsvm_train(const void* X, spsvm_dtype xdt, const float* y, int64_t n, int64_t d, double C,
+                         double gamma, int64_t J_max, const spsvm_options* opt, void* workspace,
+                         size_t ws_bytes, void* stream, spsvm_model** out);
+
+/* Bytes of device workspace spsvm_train_fixed_basis needs (m basis vectors). */
+spsvm_status spsvm_fixed_workspace_bytes(int64_t n, int64_t d, int64_t m, const spsvm_options* opt,
+                                         size_t* bytes);
+
+/* Newton re-optimisation of Eq. 4 on a given basis (no selection): computes the kernel block
+ * K(X, X_J) for all n rows and the m given rows, then minimises F from beta = 0.
+ *  J: host, m distinct row indices in [0, n), rows pairwise distinct in value.
+ * Other arguments as for spsvm_train. */
+spsvm_status spsvm_train_fixed_basis(const void* X, spsvm_dtype xdt, const float* y, int64_t n, int64_t d,
+                                     double C, double gamma, const int64_t* J, int64_t m,
+                                     const spsvm_options* opt, void* workspace, size_t ws_bytes, void* stream,
+                                     spsvm_model** out);
+
+/* Reads a model. Any output pointer may be NULL.
+ *  m: number of basis vectors. J_idx: host, capacity >= m, receives the training-row indices of J in
+ *  the order they were added. beta: host, capacity >= m. objective: F(beta) of Eq. 4 (paper scale),
+ *  evaluated by the GPU at the returned beta. */
+spsvm_status spsvm_model_get(const spsvm_model* model, int64_t* m, int64_t* J_idx, double* beta,
+                             double* objective);
+
+/* Copies the training statistics of a model into *stats. */
+spsvm_status spsvm_model_stats(const spsvm_model* model, spsvm_stats* stats);
+
+/* Decision values out[i] = sum_k beta_k exp(-gamma ||xt_i - x_{J_k}||^2) (the classifier of Eq. 4
+ * without bias), evaluated in the model's precision with FP64 accumulation.
+ *  Xt: device, n_t x d, element type xdt. out: device, n_t doubles. The n_t x m kernel block is never
+ *  stored. The model keeps its own copy of X_J, so the training X need not be alive. */
+spsvm_status spsvm_predict(const spsvm_model* model, const void* Xt, spsvm_dtype xdt, int64_t n_t, double* out,
+                           void* stream);
+
+/* Releases a model; NULL is allowed. */
+void spsvm_model_free(spsvm_model* model);
+
+/* Static text for a status code. */
+const char* spsvm_status_string(spsvm_status s);
+
+/* Detail of the last failure on the calling thread ("" if none). Valid until the next call. */
+const char* spsvm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPSVM_H */

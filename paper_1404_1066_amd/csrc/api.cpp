@@ -1,0 +1,267 @@
+// C ABI of the SP-SVM library (declared in include/spsvm.h). Argument checks, status codes and the
+// thread-local error text; the work itself is in trainer.cpp and the kernels.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "trainer.h"
+
+namespace {
+thread_local std::string g_last_error;
+
+spsvm_status fail(spsvm_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+template <typename F>
+spsvm_status guarded(F&& body) {
+  try {
+    g_last_error.clear();
+    body();
+    return SPSVM_OK;
+  } catch (const spsvm::Failure& e) {
+    return fail((spsvm_status)e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(SPSVM_E_OUT_OF_MEMORY, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(SPSVM_E_HIP, e.what());
+  } catch (...) {
+    return fail(SPSVM_E_HIP, "unknown failure");
+  }
+}
+
+spsvm_options resolve(const spsvm_options* opt) {
+  spsvm_options o;
+  spsvm_options_default(&o);
+  if (opt) {
+    if (opt->struct_size != sizeof(spsvm_options))
+      throw spsvm::Failure(SPSVM_E_INVALID_ARG, "spsvm_options.struct_size mismatch (use spsvm_options_default)");
+    o = *opt;
+  }
+  if (o.kappa < 1 || o.kappa > 64) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "kappa must lie in [1, 64]");
+  if (!(o.growth >= 0.0) || !std::isfinite(o.growth)) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "growth must be >= 0");
+  if (o.chunk_cap < 1 || o.chunk_cap > 4096) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "chunk_cap must lie in [1, 4096]");
+  if (!(o.newton_tol >= 0.0) || !(o.newton_ftol >= 0.0))
+    throw spsvm::Failure(SPSVM_E_INVALID_ARG, "newton tolerances must be >= 0");
+  if (o.newton_max_iter < 1) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "newton_max_iter must be >= 1");
+  if (o.precision != SPSVM_F64 && o.precision != SPSVM_F32)
+    throw spsvm::Failure(SPSVM_E_INVALID_ARG, "precision must be SPSVM_F64 or SPSVM_F32");
+  return o;
+}
+
+void check_problem(const void* X, spsvm_dtype xdt, const float* y, int64_t n, int64_t d, double C, double gamma,
+                   int64_t J_max) {
+  using spsvm::Failure;
+  if (!X || !y) throw Failure(SPSVM_E_INVALID_ARG, "X and y must be device pointers");
+  if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
+  if (n < 1 || n > 0x7fffffffLL) throw Failure(SPSVM_E_INVALID_ARG, "n must lie in [1, 2^31 - 1]");
+  if (d < 1) throw Failure(SPSVM_E_INVALID_ARG, "d must be >= 1");
+  if (!(C > 0.0) || !std::isfinite(C)) throw Failure(SPSVM_E_INVALID_ARG, "C must be finite and > 0");
+  if (!(gamma > 0.0) || !std::isfinite(gamma)) throw Failure(SPSVM_E_INVALID_ARG, "gamma must be finite and > 0");
+  if (J_max < 1 || J_max > n || J_max > 65536) throw Failure(SPSVM_E_INVALID_ARG, "J_max must lie in [1, min(n, 65536)]");
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+}  // namespace
+
+extern "C" {
+
+void spsvm_options_default(spsvm_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(spsvm_options);
+  o->seed = 0;
+  o->kappa = 59;
+  o->growth = 0.25;
+  o->chunk_cap = 256;
+  o->newton_tol = 1e-10;
+  o->newton_ftol = 1e-14;
+  o->newton_max_iter = 50;
+  o->precision = SPSVM_F32;
+  o->log_level = 0;
+}
+
+spsvm_status spsvm_train_workspace_bytes(int64_t n, int64_t d, int64_t J_max, const spsvm_options* opt, size_t* bytes) {
+  return guarded([&] {
+    if (!bytes) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bytes must not be NULL");
+    if (n < 1 || d < 1 || J_max < 1 || J_max > n) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad sizes");
+    *bytes = spsvm::make_plan(n, d, J_max, resolve(opt), true).bytes;
+  });
+}
+
+spsvm_status spsvm_fixed_workspace_bytes(int64_t n, int64_t d, int64_t m, const spsvm_options* opt, size_t* bytes) {
+  return guarded([&] {
+    if (!bytes) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bytes must not be NULL");
+    if (n < 1 || d < 1 || m < 1 || m > n) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad sizes");
+    *bytes = spsvm::make_plan(n, d, m, resolve(opt), false).bytes;
+  });
+}
+
+spsvm_status spsvm_train(const void* X, spsvm_dtype xdt, const float* y, int64_t n, int64_t d, double C, double gamma,
+                         int64_t J_max, const spsvm_options* opt, void* workspace, size_t ws_bytes, void* stream,
+                         spsvm_model** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!out) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "out must not be NULL");
+    const spsvm_options o = resolve(opt);
+    check_problem(X, xdt, y, n, d, C, gamma, J_max);
+    *out = spsvm::run_train(X, xdt == SPSVM_DT_F64, y, n, d, C, gamma, J_max, o, workspace, ws_bytes,
+                            as_stream(stream), nullptr);
+  });
+}
+
+spsvm_status spsvm_train_fixed_basis(const void* X, spsvm_dtype xdt, const float* y, int64_t n, int64_t d, double C,
+                                     double gamma, const int64_t* J, int64_t m, const spsvm_options* opt,
+                                     void* workspace, size_t ws_bytes, void* stream, spsvm_model** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!out) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "out must not be NULL");
+    if (!J) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "J must be a host array");
+    const spsvm_options o = resolve(opt);
+    check_problem(X, xdt, y, n, d, C, gamma, m);
+    *out = spsvm::run_train(X, xdt == SPSVM_DT_F64, y, n, d, C, gamma, m, o, workspace, ws_bytes, as_stream(stream), J);
+  });
+}
+
+spsvm_status spsvm_model_get(const spsvm_model* md, int64_t* m, int64_t* J_idx, double* beta, double* objective) {
+  return guarded([&] {
+    if (!md) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "model must not be NULL");
+    if (m) *m = md->m;
+    if (J_idx && md->m) std::memcpy(J_idx, md->J.data(), md->m * sizeof(int64_t));
+    if (beta && md->m) std::memcpy(beta, md->beta.data(), md->m * sizeof(double));
+    if (objective) *objective = md->objective;
+  });
+}
+
+spsvm_status spsvm_model_stats(const spsvm_model* md, spsvm_stats* stats) {
+  return guarded([&] {
+    if (!md || !stats) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "model and stats must not be NULL");
+    *stats = md->stats;
+  });
+}
+
+spsvm_status spsvm_predict(const spsvm_model* md, const void* Xt, spsvm_dtype xdt, int64_t n_t, double* out,
+                           void* stream) {
+  return guarded([&] {
+    if (!md) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "model must not be NULL");
+    if (n_t < 0) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "n_t must be >= 0");
+    if (n_t == 0) return;
+    if (!Xt || !out) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "Xt and out must be device pointers");
+    if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
+    spsvm::run_predict(md, Xt, xdt == SPSVM_DT_F64, n_t, out, as_stream(stream));
+  });
+}
+
+void spsvm_model_free(spsvm_model* md) { delete md; }
+
+const char* spsvm_status_string(spsvm_status s) {
+  switch (s) {
+    case SPSVM_OK: return "ok";
+    case SPSVM_E_INVALID_ARG: return "invalid argument";
+    case SPSVM_E_OUT_OF_MEMORY: return "out of memory";
+    case SPSVM_E_HIP: return "HIP runtime error";
+    case SPSVM_E_NOT_PD: return "Newton matrix not positive definite";
+    case SPSVM_E_NO_CONVERGENCE: return "no convergence";
+    case SPSVM_E_WORKSPACE: return "workspace missing, misaligned or too small";
+  }
+  return "unknown status";
+}
+
+const char* spsvm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------ components
+#include "../../include/spsvm_components.h"
+#include "launch.h"
+
+extern "C" {
+
+spsvm_status spsvm_rbf_block(const void* X, spsvm_dtype xdt, int64_t n, int64_t d, const int32_t* idx, int64_t ncols,
+                             spsvm_precision precision, double gamma, void* out, int64_t ldo, void* workspace,
+                             size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    using spsvm::Failure;
+    if (!X || !idx || !out) throw Failure(SPSVM_E_INVALID_ARG, "X, idx and out must be device pointers");
+    if (n < 0 || d < 1 || ncols < 0 || ncols > 0x7fffffff || ldo < ncols)
+      throw Failure(SPSVM_E_INVALID_ARG, "bad sizes");
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) throw Failure(SPSVM_E_INVALID_ARG, "gamma must be finite and > 0");
+    if (precision != SPSVM_F64 && precision != SPSVM_F32) throw Failure(SPSVM_E_INVALID_ARG, "bad precision");
+    if (!workspace || ((uintptr_t)workspace & 255u) || ws_bytes < (size_t)n * 8)
+      throw Failure(SPSVM_E_WORKSPACE, "workspace must be 256-byte aligned with >= n * 8 bytes");
+    hipStream_t st = as_stream(stream);
+    const bool xd = xdt == SPSVM_DT_F64;
+    if (precision == SPSVM_F64) {
+      double* nrm = (double*)workspace;
+      if (xd) {
+        spsvm::launch_row_norms<double, double>((const double*)X, n, d, nrm, st);
+        spsvm::launch_kblock<double, double>((const double*)X, n, d, nrm, idx, (int)ncols, (double*)out, ldo, gamma, st);
+      } else {
+        spsvm::launch_row_norms<float, double>((const float*)X, n, d, nrm, st);
+        spsvm::launch_kblock<float, double>((const float*)X, n, d, nrm, idx, (int)ncols, (double*)out, ldo, gamma, st);
+      }
+    } else {
+      float* nrm = (float*)workspace;
+      if (xd) {
+        spsvm::launch_row_norms<double, float>((const double*)X, n, d, nrm, st);
+        spsvm::launch_kblock<double, float>((const double*)X, n, d, nrm, idx, (int)ncols, (float*)out, ldo, gamma, st);
+      } else {
+        spsvm::launch_row_norms<float, float>((const float*)X, n, d, nrm, st);
+        spsvm::launch_kblock<float, float>((const float*)X, n, d, nrm, idx, (int)ncols, (float*)out, ldo, gamma, st);
+      }
+    }
+    SPSVM_HIP(hipStreamSynchronize(st));
+  });
+}
+
+static size_t solve_ws(int64_t m) {
+  return (size_t)spsvm::round_up((int64_t)spsvm::ceil_div(m, spsvm::kCholNB) * spsvm::kCholNB * spsvm::kCholNB * 8, 256) +
+         (size_t)spsvm::round_up(m * 8, 256) + 256;
+}
+
+spsvm_status spsvm_newton_solve_workspace_bytes(int64_t m, size_t* bytes) {
+  return guarded([&] {
+    if (!bytes || m < 1) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "m must be >= 1 and bytes not NULL");
+    *bytes = solve_ws(m);
+  });
+}
+
+spsvm_status spsvm_newton_solve(double* H, int64_t ldh, int64_t m, const double* g, double* x, void* workspace,
+                                size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    using spsvm::Failure;
+    if (!H || !g || !x) throw Failure(SPSVM_E_INVALID_ARG, "H, g and x must be device pointers");
+    if (m < 1 || m > 65536 || ldh < m) throw Failure(SPSVM_E_INVALID_ARG, "bad sizes");
+    if (!workspace || ((uintptr_t)workspace & 255u) || ws_bytes < solve_ws(m))
+      throw Failure(SPSVM_E_WORKSPACE, "workspace missing, misaligned or too small");
+    hipStream_t st = as_stream(stream);
+    char* w = (char*)workspace;
+    double* Linv = (double*)w;
+    w += spsvm::round_up((int64_t)spsvm::ceil_div(m, spsvm::kCholNB) * spsvm::kCholNB * spsvm::kCholNB * 8, 256);
+    double* z = (double*)w;
+    w += spsvm::round_up(m * 8, 256);
+    spsvm::NewtonScalars* sc = (spsvm::NewtonScalars*)w;
+    SPSVM_HIP(hipMemsetAsync(sc, 0, sizeof(spsvm::NewtonScalars), st));
+    spsvm::launch_cholesky(H, ldh, (int)m, Linv, sc, st);
+    spsvm::launch_chol_solve(H, ldh, (int)m, Linv, g, x, z, st);
+    int32_t fl = 0;
+    SPSVM_HIP(hipMemcpyAsync(&fl, &sc->fail, 4, hipMemcpyDeviceToHost, st));
+    SPSVM_HIP(hipStreamSynchronize(st));
+    if (fl) throw Failure(SPSVM_E_NOT_PD, "Cholesky met a non-positive or non-finite pivot");
+  });
+}
+
+spsvm_status spsvm_candidate_draw(uint64_t seed, int64_t t, int64_t n, int32_t kappa, int32_t* out) {
+  return guarded([&] {
+    if (!out || n < 1 || n > 0x7fffffffLL || kappa < 1 || kappa > 64 || t < 0)
+      throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad arguments");
+    std::vector<uint64_t> hashes((size_t)n);
+    for (int64_t i = 0; i < n; ++i) hashes[i] = (uint64_t)i;  // all distinct, none blocked
+    spsvm::draw_step(seed, t, n, kappa, hashes, {}, out);
+  });
+}
+
+}  // extern "C"

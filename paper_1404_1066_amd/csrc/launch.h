@@ -1,0 +1,122 @@
+// Launchers of the SP-SVM kernels (host side). All launches go to the given stream; none synchronises.
+#pragma once
+
+#include "common.h"
+
+namespace spsvm {
+
+// ------------------------------------------------------------------------------ shared device structs
+// One candidate slot of a selection step (exact one-dimensional minimisation, see select.hip).
+struct CandState {
+  double s, s_prev, lo, hi;  // evaluation point, previous point, bracket of the root of psi'
+  double oc;                 // o at the candidate's row
+  double score;              // exact decrease of f when done
+  int32_t idx;               // training row, -1 for an empty slot
+  int32_t status;            // 0 active, 1 done, 2 skipped
+  int32_t newton;            // s is the Newton root of the previous point's segment
+  int32_t passes;
+};
+constexpr int kCandSlots = 64;
+
+// Result of a selection step.
+struct Selection {
+  double s;       // coefficient of the new basis vector
+  double score;   // decrease of f
+  int32_t valid;  // 0 when no candidate could be scored
+  int32_t slot;   // candidate slot (column of the candidate block)
+  int32_t idx;    // training row
+  int32_t pos;    // position in J (column of K_XJ)
+};
+
+// Line-search state along d (exact minimisation of f(beta + t d), t >= 0).
+struct LineState {
+  double t, t_prev, lo, hi;
+  double c1, c2;   // beta . delta_J, d . delta_J (delta = K_XJ d)
+  double dec;      // f(beta) - f(beta + t d) when done
+  int32_t status;  // 0 active, 1 done
+  int32_t newton;
+  int32_t passes;
+  int32_t pad;
+};
+
+// Per-iteration scalars of the Newton loop, copied to the host.
+struct NewtonScalars {
+  double sum_a2;   // sum_i max(0, 1 - y_i o_i)^2
+  double gnorm2;   // ||grad f||^2
+  double beta_oJ;  // beta . o_J = beta^T K_JJ beta
+  double trace;    // trace of H (jitter scale)
+  int32_t n_sv;    // |I|
+  int32_t flips;   // rows whose violator status differs from the last factorisation
+  int32_t fail;    // Cholesky met a non-positive pivot
+  int32_t n_active_sel;  // candidates still being scored
+};
+
+// ----------------------------------------------------------------------------------------- kblock.hip
+template <typename TX, typename TK>
+void launch_row_norms(const TX* X, int64_t n, int64_t d, TK* out, hipStream_t st);
+template <typename TX>
+void launch_row_hash(const TX* X, int64_t n, int64_t d, uint64_t* out, hipStream_t st);
+template <typename TX, typename TK>
+void launch_kblock(const TX* X, int64_t n, int64_t d, const TK* xnorm, const int32_t* cidx, int ncols, TK* out,
+                   int64_t ldo, double gamma, hipStream_t st);
+template <typename TX, typename TK>
+void launch_predict(const TX* Xt, int64_t n, int64_t d, const TK* Z, const TK* znorm, int m, const double* beta,
+                    double* out, double gamma, hipStream_t st);
+template <typename TX>
+void launch_check_inputs(const TX* X, int64_t total, const float* y, int64_t n, int32_t* flags, hipStream_t st);
+template <typename TX, typename TK>
+void launch_gather_rows(const TX* X, int64_t d, const int64_t* idx, int64_t m, TK* out, hipStream_t st);
+
+// ----------------------------------------------------------------------------------------- select.hip
+// Score slots for step `step` of the candidate table (kCandSlots indices per step, -1 = empty).
+void launch_score_init(const int32_t* cand, const double* o, const uint64_t* hash, const uint64_t* stage_hash,
+                       int n_stage, CandState* st, NewtonScalars* sc, hipStream_t s);
+template <typename TK>
+void launch_score_round(const TK* Kc, const float* y, const double* o, int64_t n, double lam, CandState* st,
+                        double* partial, int nblk, NewtonScalars* sc, hipStream_t s);
+template <typename TK>
+void launch_select_append(const CandState* st, const uint64_t* hash, uint64_t* stage_hash, int q, const TK* Kc,
+                          int64_t n, double* o, TK* KXJ, int64_t ldk, int64_t* J, double* beta, int32_t* m_dev,
+                          Selection* sel, hipStream_t s);
+int score_blocks(int64_t n);
+
+// ----------------------------------------------------------------------------------------- newton.hip
+template <typename TK>
+void launch_gemv(const TK* K, int64_t ldk, int64_t n, int m, const double* x, double* out, hipStream_t s);
+void launch_compact(const double* o, const float* y, int64_t n, const uint8_t* act_ref, uint8_t* act_out,
+                    int32_t* I, int32_t* blk_count, double* blk_sum, int32_t* blk_flips, NewtonScalars* sc,
+                    hipStream_t s);
+int compact_blocks(int64_t n);
+template <typename TK>
+void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv, const double* o, const float* y,
+                     const int64_t* J, const double* beta, double lam, double* partial, int nchunk, double* g,
+                     NewtonScalars* sc, hipStream_t s);
+int gradient_chunks(int m, int n_sv);
+template <typename TK>
+void launch_syrk(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv, int nsplit, double* partial,
+                 hipStream_t s);
+template <typename TK>
+void launch_syrk_reduce(const TK* K, int64_t ldk, int m, const int64_t* J, double lam, const double* partial,
+                        int nsplit, double diag_add, double* H, int64_t ldh, hipStream_t s);
+void launch_trace(const double* H, int64_t ldh, int m, NewtonScalars* sc, hipStream_t s);
+int syrk_tiles(int m);
+int syrk_splits(int m, int n_sv);
+size_t syrk_partial_doubles(int m_max);
+void launch_c1c2(const double* beta, const double* dvec, const double* delta, const int64_t* J, int m, LineState* ls,
+                 hipStream_t s);
+void launch_ls_round(const double* o, const double* delta, const float* y, int64_t n, double lam, LineState* ls,
+                     double* partial, int nblk, hipStream_t s);
+void launch_apply_step(const LineState* ls, double* beta, const double* dvec, int m, double* o, const double* delta,
+                       int64_t n, hipStream_t s);
+void launch_scale(double* v, int m, double a, hipStream_t s);
+
+// ------------------------------------------------------------------------------------------- chol.hip
+constexpr int kCholNB = 64;
+// In-place lower Cholesky of H (m x m, leading dimension ldh); Linv receives the inverses of the diagonal
+// blocks (ceil(m/64) blocks of 64 x 64). Sets sc->fail on a non-positive or non-finite pivot.
+void launch_cholesky(double* H, int64_t ldh, int m, double* Linv, NewtonScalars* sc, hipStream_t s);
+// x = -L^{-T} L^{-1} g using the factor and the diagonal-block inverses.
+void launch_chol_solve(const double* L, int64_t ldh, int m, const double* Linv, const double* g, double* x,
+                       double* work, hipStream_t s);
+
+}  // namespace spsvm

@@ -1,0 +1,477 @@
+// Host orchestration of SP-SVM training (section 4, "Sparse primal optimization"): stages of greedy
+// basis additions, each followed by Newton re-optimisation of Eq. 4. Every O(n) or larger step is a
+// kernel; the host draws candidate indices, launches, and reads back a few scalars per iteration.
+#include "trainer.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+
+#include "launch.h"
+
+spsvm_model::~spsvm_model() {
+  if (XJ) (void)hipFree(XJ);
+  if (XJnorm) (void)hipFree(XJnorm);
+  if (beta_dev) (void)hipFree(beta_dev);
+}
+
+namespace spsvm {
+
+// ------------------------------------------------------------------------------------ candidate draws
+static constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+static inline uint64_t splitmix_finalise(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void draw_step(uint64_t seed, int64_t t, int64_t n, int kappa, const std::vector<uint64_t>& row_hash,
+               const std::vector<uint64_t>& blocked_sorted, int32_t* out64) {
+  for (int c = 0; c < kCandSlots; ++c) out64[c] = -1;
+  uint64_t state = seed ^ ((uint64_t)(t + 1) * kGolden);
+  int got = 0;
+  for (int attempt = 0; attempt < 64 * kappa && got < kappa; ++attempt) {
+    state += kGolden;
+    const uint64_t z = splitmix_finalise(state);
+    const int32_t idx = (int32_t)(((z >> 32) * (uint64_t)n) >> 32);
+    bool seen = false;
+    for (int c = 0; c < got; ++c) seen |= out64[c] == idx;
+    if (seen) continue;
+    if (std::binary_search(blocked_sorted.begin(), blocked_sorted.end(), row_hash[idx])) continue;
+    out64[got++] = idx;
+  }
+}
+
+int64_t stage_size(int64_t J, int64_t J_max, double growth, int64_t cap) {
+  const int64_t g = (int64_t)std::floor(growth * (double)J);
+  return std::min<int64_t>(J_max - J, std::max<int64_t>(1, std::min<int64_t>(cap, g)));
+}
+
+// ------------------------------------------------------------------------------------------ workspace
+Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection) {
+  Plan p;
+  p.n = n;
+  p.d = d;
+  p.J_max = J_max;
+  p.tk_double = opt.precision == SPSVM_F64;
+  p.ldk = round_up(J_max, 4);
+  p.ldh = round_up(J_max, 4);
+  const size_t tk = p.tk_double ? 8 : 4;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (size_t)round_up((int64_t)std::max<size_t>(bytes, 1), 256);
+    return at;
+  };
+  const int64_t nb_c = compact_blocks(n), nb_s = score_blocks(n);
+  const int64_t cap = with_selection ? opt.chunk_cap : 1;
+  p.xnorm = take(n * tk);
+  p.hash = take(n * 8);
+  p.KXJ = take((size_t)n * p.ldk * tk);
+  p.Kc = take(with_selection ? (size_t)n * kCandSlots * tk : 0);
+  p.o = take(n * 8);
+  p.delta = take(n * 8);
+  p.act0 = take(n);
+  p.act1 = take(n);
+  p.I = take(n * 4);
+  p.cblk_cnt = take(nb_c * 4);
+  p.cblk_sum = take(nb_c * 8);
+  p.cblk_flips = take(nb_c * 4);
+  p.J = take(J_max * 8);
+  p.J32 = take(J_max * 4);
+  p.beta = take(J_max * 8);
+  p.dvec = take(J_max * 8);
+  p.g = take(J_max * 8);
+  p.z = take(J_max * 8);
+  p.H = take((size_t)J_max * p.ldh * 8);
+  p.Linv = take((size_t)ceil_div(J_max, kCholNB) * kCholNB * kCholNB * 8);
+  p.syrk_part = take(syrk_partial_doubles((int)J_max) * 8);
+  p.grad_part = take((size_t)1024 * 256 * 8);
+  p.cand_state = take(kCandSlots * sizeof(CandState));
+  p.sel = take(sizeof(Selection));
+  p.ls = take(sizeof(LineState));
+  p.scalars = take(sizeof(NewtonScalars));
+  p.score_part = take((size_t)nb_s * kCandSlots * 4 * 8);
+  p.ls_part = take((size_t)nb_s * 6 * 8);
+  p.cand_table = take((size_t)cap * kCandSlots * 4);
+  p.stage_hash = take(cap * 8);
+  p.m_dev = take(4);
+  p.flags = take(8);
+  p.bytes = off;
+  return p;
+}
+
+// ----------------------------------------------------------------------------------------- the trainer
+namespace {
+
+struct Pinned {
+  void* p = nullptr;
+  explicit Pinned(size_t bytes) { SPSVM_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault)); }
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+using clk = std::chrono::steady_clock;
+constexpr size_t kPinnedScalars = 16384;  // bytes of pinned memory for scalar read-backs
+static double secs(clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); }
+
+template <typename TX, typename TK>
+struct Impl {
+  const TX* X;
+  const float* y;
+  int64_t n, d, J_max;
+  double C, gamma, lam;
+  spsvm_options opt;
+  hipStream_t st;
+  Plan p;
+  char* base;
+  Pinned pin;
+  spsvm_stats stats{};
+
+  TK *xnorm, *KXJ, *Kc;
+  uint64_t *hash, *stage_hash;
+  double *o, *delta, *beta, *dvec, *g, *z, *H, *Linv, *syrk_part, *grad_part, *score_part, *ls_part, *cblk_sum;
+  uint8_t *act_fact, *act_cur;
+  int32_t *I, *cblk_cnt, *cblk_flips, *cand_table, *m_dev, *flags, *J32;
+  int64_t* J;
+  CandState* cst;
+  Selection* sel;
+  LineState* ls;
+  NewtonScalars* sc;
+  std::vector<uint64_t> hash_host;
+
+  template <typename T>
+  T* at(size_t off) {
+    return reinterpret_cast<T*>(base + off);
+  }
+
+  Impl(const TX* X_, const float* y_, int64_t n_, int64_t d_, double C_, double g_, int64_t Jm, const spsvm_options& o_,
+       void* ws, hipStream_t s, const Plan& plan)
+      : X(X_), y(y_), n(n_), d(d_), J_max(Jm), C(C_), gamma(g_), lam(1.0 / C_), opt(o_), st(s), p(plan),
+        base((char*)ws), pin(kPinnedScalars + (size_t)o_.chunk_cap * kCandSlots * 4) {
+    xnorm = at<TK>(p.xnorm);
+    KXJ = at<TK>(p.KXJ);
+    Kc = at<TK>(p.Kc);
+    hash = at<uint64_t>(p.hash);
+    stage_hash = at<uint64_t>(p.stage_hash);
+    o = at<double>(p.o);
+    delta = at<double>(p.delta);
+    beta = at<double>(p.beta);
+    dvec = at<double>(p.dvec);
+    g = at<double>(p.g);
+    z = at<double>(p.z);
+    H = at<double>(p.H);
+    Linv = at<double>(p.Linv);
+    syrk_part = at<double>(p.syrk_part);
+    grad_part = at<double>(p.grad_part);
+    score_part = at<double>(p.score_part);
+    ls_part = at<double>(p.ls_part);
+    cblk_sum = at<double>(p.cblk_sum);
+    act_fact = at<uint8_t>(p.act0);
+    act_cur = at<uint8_t>(p.act1);
+    I = at<int32_t>(p.I);
+    cblk_cnt = at<int32_t>(p.cblk_cnt);
+    cblk_flips = at<int32_t>(p.cblk_flips);
+    cand_table = at<int32_t>(p.cand_table);
+    m_dev = at<int32_t>(p.m_dev);
+    flags = at<int32_t>(p.flags);
+    J32 = at<int32_t>(p.J32);
+    J = at<int64_t>(p.J);
+    cst = at<CandState>(p.cand_state);
+    sel = at<Selection>(p.sel);
+    ls = at<LineState>(p.ls);
+    sc = at<NewtonScalars>(p.scalars);
+  }
+
+  void sync() { SPSVM_HIP(hipStreamSynchronize(st)); }
+
+  template <typename T>
+  T read(const T* dev) {
+    SPSVM_HIP(hipMemcpyAsync(pin.p, dev, sizeof(T), hipMemcpyDeviceToHost, st));
+    sync();
+    T v;
+    std::memcpy(&v, pin.p, sizeof(T));
+    return v;
+  }
+
+  // ---------------------------------------------------------------------------------------- preparation
+  void prepare() {
+    SPSVM_HIP(hipMemsetAsync(flags, 0, 8, st));
+    launch_check_inputs<TX>(X, n * d, y, n, flags, st);
+    launch_row_hash<TX>(X, n, d, hash, st);
+    launch_row_norms<TX, TK>(X, n, d, xnorm, st);
+    hash_host.resize(n);
+    SPSVM_HIP(hipMemcpyAsync(hash_host.data(), hash, n * 8, hipMemcpyDeviceToHost, st));
+    SPSVM_HIP(hipMemcpyAsync(pin.p, flags, 8, hipMemcpyDeviceToHost, st));
+    sync();
+    int32_t f[2];
+    std::memcpy(f, pin.p, 8);
+    if (f[0]) throw Failure(SPSVM_E_INVALID_ARG, "X holds NaN or Inf");
+    if (f[1]) throw Failure(SPSVM_E_INVALID_ARG, "labels must be exactly +1 or -1");
+    std::vector<uint64_t> hs = hash_host;
+    std::sort(hs.begin(), hs.end());
+    const int64_t distinct = std::unique(hs.begin(), hs.end()) - hs.begin();
+    if (J_max > distinct)
+      throw Failure(SPSVM_E_INVALID_ARG, "J_max (" + std::to_string(J_max) + ") exceeds the number of distinct rows (" +
+                                             std::to_string(distinct) + ")");
+  }
+
+  // ------------------------------------------------------------------------------------ Newton at fixed J
+  // Returns the number of iterations.
+  int newton(int m) {
+    if (m <= 0) return 0;
+    launch_gemv<TK>(KXJ, p.ldk, n, m, beta, o, st);
+    bool fact_valid = false;
+    double g0 = 0.0;
+    int it = 0;
+    for (; it < opt.newton_max_iter; ++it) {
+      launch_compact(o, y, n, fact_valid ? act_fact : nullptr, act_cur, I, cblk_cnt, cblk_sum, cblk_flips, sc, st);
+      NewtonScalars s = read(sc);
+      const int nchunk = gradient_chunks(m, s.n_sv);
+      launch_gradient<TK>(KXJ, p.ldk, m, I, s.n_sv, o, y, J, beta, lam, grad_part, nchunk, g, sc, st);
+      s = read(sc);
+      const double gn = std::sqrt(s.gnorm2);
+      const double f = 0.5 * lam * s.beta_oJ + 0.5 * s.sum_a2;
+      if (it == 0) g0 = gn;
+      if (opt.log_level >= 2)
+        std::fprintf(stderr, "[spsvm]   newton it=%d m=%d f=%.15e |g|=%.3e n_sv=%d flips=%d\n", it, m, f, gn, s.n_sv,
+                     s.flips);
+      if (gn <= opt.newton_tol * std::max(1.0, g0)) break;
+      if (!fact_valid || s.flips > 0) {
+        factorize(m, s.n_sv);
+        fact_valid = true;
+        std::swap(act_fact, act_cur);
+      }
+      launch_chol_solve(H, p.ldh, m, Linv, g, dvec, z, st);
+      launch_gemv<TK>(KXJ, p.ldk, n, m, dvec, delta, st);
+      launch_c1c2(beta, dvec, delta, J, m, ls, st);
+      const int nblk = score_blocks(n);
+      LineState L;
+      int rounds = 0;
+      for (;;) {
+        for (int r = 0; r < 3; ++r) launch_ls_round(o, delta, y, n, lam, ls, ls_part, nblk, st);
+        rounds += 3;
+        L = read(ls);
+        if (L.status != 0 || rounds >= 66) break;
+      }
+      stats.ls_passes += L.passes;
+      launch_apply_step(ls, beta, dvec, m, o, delta, n, st);
+      if (L.t == 0.0) {
+        ++it;
+        break;
+      }
+      if (L.dec <= opt.newton_ftol * f) {
+        ++it;
+        break;
+      }
+    }
+    if (it >= opt.newton_max_iter) stats.iter_cap_hits += 1;
+    stats.newton_iters += it;
+    return it;
+  }
+
+  void factorize(int m, int n_sv) {
+    const int nsplit = syrk_splits(m, n_sv);
+    launch_syrk<TK>(KXJ, p.ldk, m, I, n_sv, nsplit, syrk_part, st);
+    launch_syrk_reduce<TK>(KXJ, p.ldk, m, J, lam, syrk_part, nsplit, 0.0, H, p.ldh, st);
+    SPSVM_HIP(hipMemsetAsync(&sc->fail, 0, 4, st));
+    launch_cholesky(H, p.ldh, m, Linv, sc, st);
+    stats.factorizations += 1;
+    if (read(&sc->fail) == 0) return;
+    // jitter retries: H + mu * mean(diag H) * I
+    launch_syrk_reduce<TK>(KXJ, p.ldk, m, J, lam, syrk_part, nsplit, 0.0, H, p.ldh, st);
+    launch_trace(H, p.ldh, m, sc, st);
+    const double mean_diag = read(&sc->trace) / m;
+    for (double mu : {1e-14, 1e-12, 1e-10, 1e-8}) {
+      launch_syrk_reduce<TK>(KXJ, p.ldk, m, J, lam, syrk_part, nsplit, mu * mean_diag, H, p.ldh, st);
+      SPSVM_HIP(hipMemsetAsync(&sc->fail, 0, 4, st));
+      launch_cholesky(H, p.ldh, m, Linv, sc, st);
+      stats.factorizations += 1;
+      if (read(&sc->fail) == 0) return;
+    }
+    throw Failure(SPSVM_E_NOT_PD, "Newton matrix not positive definite after jitter retries (m=" + std::to_string(m) + ")");
+  }
+
+  // Objective and residual statistics at the current beta (o is recomputed).
+  void final_eval(int m, double* F, NewtonScalars* out) {
+    if (m == 0) {
+      *F = C * 0.5 * (double)n;
+      return;
+    }
+    launch_gemv<TK>(KXJ, p.ldk, n, m, beta, o, st);
+    launch_compact(o, y, n, nullptr, act_cur, I, cblk_cnt, cblk_sum, cblk_flips, sc, st);
+    NewtonScalars s = read(sc);
+    launch_gradient<TK>(KXJ, p.ldk, m, I, s.n_sv, o, y, J, beta, lam, grad_part, gradient_chunks(m, s.n_sv), g, sc, st);
+    s = read(sc);
+    *out = s;
+    *F = C * (0.5 * lam * s.beta_oJ + 0.5 * s.sum_a2);
+  }
+
+  // ------------------------------------------------------------------------------------ greedy training
+  int select_and_optimise() {
+    int m = 0;
+    int64_t t = 0;
+    std::vector<uint64_t> blocked;  // sorted hashes of J's rows
+    std::vector<int32_t> table((size_t)opt.chunk_cap * kCandSlots);
+    SPSVM_HIP(hipMemsetAsync(o, 0, n * 8, st));
+    SPSVM_HIP(hipMemsetAsync(m_dev, 0, 4, st));
+    const int nblk = score_blocks(n);
+    while (m < J_max) {
+      const auto t0 = clk::now();
+      const int cs = (int)stage_size(m, J_max, opt.growth, opt.chunk_cap);
+      for (int q = 0; q < cs; ++q) draw_step(opt.seed, t + q, n, opt.kappa, hash_host, blocked, &table[(size_t)q * kCandSlots]);
+      int32_t* tp = (int32_t*)((char*)pin.p + kPinnedScalars);
+      std::memcpy(tp, table.data(), (size_t)cs * kCandSlots * 4);
+      SPSVM_HIP(hipMemcpyAsync(cand_table, tp, (size_t)cs * kCandSlots * 4, hipMemcpyHostToDevice, st));
+      for (int q = 0; q < cs; ++q) {
+        const int32_t* cq = cand_table + (size_t)q * kCandSlots;
+        launch_kblock<TX, TK>(X, n, d, xnorm, cq, kCandSlots, Kc, kCandSlots, gamma, st);
+        launch_score_init(cq, o, hash, stage_hash, q, cst, sc, st);
+        int rounds = 0;
+        for (;;) {
+          for (int r = 0; r < 4; ++r) launch_score_round<TK>(Kc, y, o, n, lam, cst, score_part, nblk, sc, st);
+          rounds += 4;
+          if (rounds >= 64 || read(&sc->n_active_sel) == 0) break;
+        }
+        stats.score_passes += rounds;
+        launch_select_append<TK>(cst, hash, stage_hash, q, Kc, n, o, KXJ, p.ldk, J, beta, m_dev, sel, st);
+      }
+      t += cs;
+      const int m_new = read(m_dev);
+      stats.additions += m_new - m;
+      if (m_new > m) {
+        std::vector<int64_t> jn(m_new - m);
+        SPSVM_HIP(hipMemcpyAsync(jn.data(), J + m, (m_new - m) * 8, hipMemcpyDeviceToHost, st));
+        sync();
+        for (int64_t j : jn) blocked.push_back(hash_host[j]);
+        std::sort(blocked.begin(), blocked.end());
+      }
+      const auto t1 = clk::now();
+      stats.seconds_select += secs(t0, t1);
+      if (m_new == m) break;
+      m = m_new;
+      const int its = newton(m);
+      stats.stages += 1;
+      const auto t2 = clk::now();
+      stats.seconds_newton += secs(t1, t2);
+      if (opt.log_level >= 1)
+        std::fprintf(stderr, "[spsvm] stage %lld |J|=%d added=%d newton_iters=%d select=%.3fs newton=%.3fs\n",
+                     (long long)stats.stages, m, cs, its, secs(t0, t1), secs(t1, t2));
+    }
+    return m;
+  }
+
+  int fixed_basis(const int64_t* Jh, int64_t m) {
+    std::vector<uint64_t> hs(m);
+    for (int64_t k = 0; k < m; ++k) {
+      if (Jh[k] < 0 || Jh[k] >= n) throw Failure(SPSVM_E_INVALID_ARG, "basis index out of range");
+      hs[k] = hash_host[Jh[k]];
+    }
+    std::sort(hs.begin(), hs.end());
+    if (std::unique(hs.begin(), hs.end()) != hs.end())
+      throw Failure(SPSVM_E_INVALID_ARG, "basis rows must be pairwise distinct in value");
+    std::vector<int32_t> j32(Jh, Jh + m);
+    SPSVM_HIP(hipMemcpyAsync(J, Jh, m * 8, hipMemcpyHostToDevice, st));
+    SPSVM_HIP(hipMemcpyAsync(J32, j32.data(), m * 4, hipMemcpyHostToDevice, st));
+    const auto t0 = clk::now();
+    launch_kblock<TX, TK>(X, n, d, xnorm, J32, (int)m, KXJ, p.ldk, gamma, st);
+    SPSVM_HIP(hipMemsetAsync(beta, 0, m * 8, st));
+    sync();
+    const auto t1 = clk::now();
+    stats.seconds_select += secs(t0, t1);
+    newton((int)m);
+    stats.stages = 1;
+    stats.seconds_newton += secs(t1, clk::now());
+    return (int)m;
+  }
+
+  spsvm_model* build_model(int m) {
+    double F = 0.0;
+    NewtonScalars s{};
+    final_eval(m, &F, &s);
+    stats.n_sv = s.n_sv;
+    stats.grad_norm = std::sqrt(s.gnorm2);
+    auto* md = new spsvm_model();
+    try {
+      md->m = m;
+      md->d = d;
+      md->tk_double = std::is_same<TK, double>::value;
+      md->C = C;
+      md->gamma = gamma;
+      md->objective = F;
+      md->stats = stats;
+      md->J.resize(m);
+      md->beta.resize(m);
+      if (m > 0) {
+        SPSVM_HIP(hipMemcpyAsync(md->J.data(), J, m * 8, hipMemcpyDeviceToHost, st));
+        SPSVM_HIP(hipMemcpyAsync(md->beta.data(), beta, m * 8, hipMemcpyDeviceToHost, st));
+        SPSVM_HIP(hipMalloc(&md->XJ, (size_t)m * d * sizeof(TK)));
+        SPSVM_HIP(hipMalloc(&md->XJnorm, (size_t)m * sizeof(TK)));
+        SPSVM_HIP(hipMalloc(&md->beta_dev, (size_t)m * 8));
+        launch_gather_rows<TX, TK>(X, d, J, m, (TK*)md->XJ, st);
+        launch_row_norms<TK, TK>((const TK*)md->XJ, m, d, (TK*)md->XJnorm, st);
+        SPSVM_HIP(hipMemcpyAsync(md->beta_dev, beta, m * 8, hipMemcpyDeviceToDevice, st));
+        sync();
+      }
+    } catch (...) {
+      delete md;
+      throw;
+    }
+    return md;
+  }
+};
+
+template <typename TX, typename TK>
+spsvm_model* train_typed(const TX* X, const float* y, int64_t n, int64_t d, double C, double gamma, int64_t J_max,
+                         const spsvm_options& opt, void* ws, const Plan& plan, hipStream_t st, const int64_t* J_fixed) {
+  Impl<TX, TK> im(X, y, n, d, C, gamma, J_max, opt, ws, st, plan);
+  im.prepare();
+  const int m = J_fixed ? im.fixed_basis(J_fixed, J_max) : im.select_and_optimise();
+  return im.build_model(m);
+}
+
+}  // namespace
+
+spsvm_model* run_train(const void* X, bool x_double, const float* y, int64_t n, int64_t d, double C, double gamma,
+                       int64_t J_max, const spsvm_options& opt, void* ws, size_t ws_bytes, hipStream_t stream,
+                       const int64_t* J_fixed) {
+  const Plan plan = make_plan(n, d, J_max, opt, J_fixed == nullptr);
+  if (!ws || ((uintptr_t)ws & 255u)) throw Failure(SPSVM_E_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
+  if (ws_bytes < plan.bytes)
+    throw Failure(SPSVM_E_WORKSPACE, "workspace too small: need " + std::to_string(plan.bytes) + " bytes, got " +
+                                         std::to_string(ws_bytes));
+  const bool tk_double = opt.precision == SPSVM_F64;
+  if (x_double)
+    return tk_double ? train_typed<double, double>((const double*)X, y, n, d, C, gamma, J_max, opt, ws, plan, stream, J_fixed)
+                     : train_typed<double, float>((const double*)X, y, n, d, C, gamma, J_max, opt, ws, plan, stream, J_fixed);
+  return tk_double ? train_typed<float, double>((const float*)X, y, n, d, C, gamma, J_max, opt, ws, plan, stream, J_fixed)
+                   : train_typed<float, float>((const float*)X, y, n, d, C, gamma, J_max, opt, ws, plan, stream, J_fixed);
+}
+
+void run_predict(const spsvm_model* md, const void* Xt, bool x_double, int64_t n_t, double* out, hipStream_t st) {
+  if (md->m == 0) {
+    SPSVM_HIP(hipMemsetAsync(out, 0, n_t * 8, st));
+  } else if (md->tk_double) {
+    if (x_double)
+      launch_predict<double, double>((const double*)Xt, n_t, md->d, (const double*)md->XJ, (const double*)md->XJnorm,
+                                     (int)md->m, md->beta_dev, out, md->gamma, st);
+    else
+      launch_predict<float, double>((const float*)Xt, n_t, md->d, (const double*)md->XJ, (const double*)md->XJnorm,
+                                    (int)md->m, md->beta_dev, out, md->gamma, st);
+  } else {
+    if (x_double)
+      launch_predict<double, float>((const double*)Xt, n_t, md->d, (const float*)md->XJ, (const float*)md->XJnorm,
+                                    (int)md->m, md->beta_dev, out, md->gamma, st);
+    else
+      launch_predict<float, float>((const float*)Xt, n_t, md->d, (const float*)md->XJ, (const float*)md->XJnorm,
+                                   (int)md->m, md->beta_dev, out, md->gamma, st);
+  }
+  SPSVM_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace spsvm

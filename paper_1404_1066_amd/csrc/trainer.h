@@ -1,0 +1,52 @@
+// Host-side orchestration of SP-SVM training (stage loop, selection steps, Newton loop).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/spsvm.h"
+#include "common.h"
+
+struct spsvm_model {
+  int64_t m = 0, d = 0;
+  int tk_double = 0;  // kernel values / basis copy in FP64 (else FP32)
+  double C = 1.0, gamma = 1.0, objective = 0.0;
+  std::vector<int64_t> J;
+  std::vector<double> beta;
+  void* XJ = nullptr;      // device, m x d, element type FP64 or FP32 (tk_double)
+  void* XJnorm = nullptr;  // device, m
+  double* beta_dev = nullptr;
+  spsvm_stats stats{};
+  ~spsvm_model();
+};
+
+namespace spsvm {
+
+// SplitMix64 candidate draws for addition step t (same definition as the published generator:
+// state advanced by 0x9E3779B97F4A7C15, output finalised with shifts 30/27/31).
+void draw_step(uint64_t seed, int64_t t, int64_t n, int kappa, const std::vector<uint64_t>& row_hash,
+               const std::vector<uint64_t>& blocked_sorted, int32_t* out64);
+int64_t stage_size(int64_t J, int64_t J_max, double growth, int64_t cap);
+
+struct Plan {
+  int64_t n = 0, d = 0, J_max = 0, ldk = 0, ldh = 0;
+  bool tk_double = false;
+  size_t bytes = 0;
+  // offsets into the workspace
+  size_t xnorm, hash, KXJ, Kc, o, delta, act0, act1, I, cblk_cnt, cblk_sum, cblk_flips, J, J32, beta, dvec, g, z,
+      H, Linv, syrk_part, grad_part, cand_state, sel, ls, scalars, score_part, ls_part, cand_table, stage_hash, m_dev,
+      flags;
+};
+
+Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection);
+
+// Runs training; returns a new model (caller owns) or throws Failure.
+spsvm_model* run_train(const void* X, bool x_double, const float* y, int64_t n, int64_t d, double C, double gamma,
+                       int64_t J_max, const spsvm_options& opt, void* ws, size_t ws_bytes, hipStream_t stream,
+                       const int64_t* J_fixed /*nullptr = greedy selection*/);
+
+void run_predict(const spsvm_model* model, const void* Xt, bool x_double, int64_t n_t, double* out,
+                 hipStream_t stream);
+
+}  // namespace spsvm
