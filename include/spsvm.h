@@ -39,14 +39,16 @@ typedef enum {
   SPSVM_E_OUT_OF_MEMORY = 2,  /* a model or host staging allocation failed */
   SPSVM_E_HIP = 3,            /* a HIP runtime call failed; the message carries hipGetErrorString */
   SPSVM_E_NOT_PD = 4,         /* the Newton matrix stayed non positive definite after the jitter retries */
-  SPSVM_E_NO_CONVERGENCE = 5, /* reserved: Newton hitting its iteration cap is reported in stats, not here */
+  SPSVM_E_NO_CONVERGENCE = 5, /* the objective or gradient became non-finite (Newton hitting its iteration
+                                 cap is not an error; it is counted in spsvm_stats.iter_cap_hits) */
   SPSVM_E_WORKSPACE = 6       /* workspace pointer missing, misaligned (256 B) or smaller than required */
 } spsvm_status;
 
 /* Arithmetic used for the kernel values and the Newton matrix.
  *  SPSVM_F64: everything in FP64 (distances, kernel block, Newton matrix).
- *  SPSVM_F32: distances and kernel block in FP32 (FP32 MFMA), Newton matrix from FP32 products
- *             accumulated in FP64; Cholesky, solves, line search, scores and objective in FP64.
+ *  SPSVM_F32: distances and the n x |J| kernel block in FP32 (FP32 MFMA); the Newton matrix is
+ *             accumulated on FP64 MFMA from the FP32 kernel values (their products are exact in FP64);
+ *             the |J| x |J| regulariser K_JJ, Cholesky, solves, line search, scores and objective in FP64.
  *  SPSVM_MIXED: as F32, but squared distances from BF16 MFMA products with a hi/lo split
  *             correction (x = hi + lo, both BF16; x.z ~ hi.hi + hi.lo + lo.hi). */
 typedef enum { SPSVM_F64 = 0, SPSVM_F32 = 1, SPSVM_MIXED = 2 } spsvm_precision;

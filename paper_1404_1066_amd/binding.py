@@ -214,13 +214,13 @@ def workspace_bytes(n: int, d: int, J_max: int, fixed: bool = False, **opts) -> 
     return b.value
 
 
-def _workspace(nbytes: int, device, workspace: Optional[torch.Tensor]) -> torch.Tensor:
+def _workspace(nbytes: int, device, workspace: Optional[torch.Tensor]):
+    """(tensor, size in bytes). A caller-given workspace is passed with its own size; the library checks it."""
     if workspace is not None:
-        if workspace.numel() * workspace.element_size() < nbytes:
-            raise ValueError("workspace tensor too small")
-        return workspace
+        _need_gpu(workspace, "workspace")
+        return workspace, workspace.numel() * workspace.element_size()
     # torch's caching allocator returns 512-byte aligned blocks
-    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
 
 
 def train(X: torch.Tensor, y: torch.Tensor, C: float, gamma: float, J_max: int, workspace=None, stream=None,
@@ -233,8 +233,7 @@ def train(X: torch.Tensor, y: torch.Tensor, C: float, gamma: float, J_max: int, 
         raise TypeError("y must be float32")
     n, d = X.shape
     o = options(**opts)
-    nbytes = workspace_bytes(n, d, J_max, **opts)
-    ws = _workspace(nbytes, X.device, workspace)
+    ws, nbytes = _workspace(workspace_bytes(n, d, J_max, **opts), X.device, workspace)
     out = ctypes.c_void_p()
     _check(load().spsvm_train(ctypes.c_void_p(X.data_ptr()), _dtype_code(X), ctypes.c_void_p(y.data_ptr()), n, d,
                               float(C), float(gamma), int(J_max), ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()),
@@ -254,8 +253,7 @@ def train_fixed_basis(X: torch.Tensor, y: torch.Tensor, C: float, gamma: float, 
     n, d = X.shape
     Jh = np.ascontiguousarray(np.asarray(J, dtype=np.int64))
     o = options(**opts)
-    nbytes = workspace_bytes(n, d, Jh.size, fixed=True, **opts)
-    ws = _workspace(nbytes, X.device, workspace)
+    ws, nbytes = _workspace(workspace_bytes(n, d, Jh.size, fixed=True, **opts), X.device, workspace)
     out = ctypes.c_void_p()
     _check(load().spsvm_train_fixed_basis(ctypes.c_void_p(X.data_ptr()), _dtype_code(X), ctypes.c_void_p(y.data_ptr()),
                                           n, d, float(C), float(gamma),

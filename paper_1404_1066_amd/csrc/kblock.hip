@@ -300,6 +300,17 @@ void launch_gather_rows(const TX* X, int64_t d, const int64_t* idx, int64_t m, T
   SPSVM_LAUNCHED();
 }
 
+__global__ void k_iota(int32_t* out, int64_t m) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
+    out[k] = (int32_t)k;
+}
+
+void launch_iota(int32_t* out, int64_t m, hipStream_t st) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_iota, dim3((unsigned)std::min<int64_t>(ceil_div(m, 256), 256)), dim3(256), 0, st, out, m);
+  SPSVM_LAUNCHED();
+}
+
 // ------------------------------------------------------------------------------------- input checks
 // flags[0] |= some X value is NaN or infinite; flags[1] |= some label is not exactly +1 or -1.
 template <typename TX>

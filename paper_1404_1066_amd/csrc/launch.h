@@ -43,7 +43,7 @@ struct LineState {
 struct NewtonScalars {
   double sum_a2;   // sum_i max(0, 1 - y_i o_i)^2
   double gnorm2;   // ||grad f||^2
-  double beta_oJ;  // beta . o_J = beta^T K_JJ beta
+  double beta_oJ;  // beta^T K_JJ beta
   double trace;    // trace of H (jitter scale)
   int32_t n_sv;    // |I|
   int32_t flips;   // rows whose violator status differs from the last factorisation
@@ -66,6 +66,7 @@ template <typename TX>
 void launch_check_inputs(const TX* X, int64_t total, const float* y, int64_t n, int32_t* flags, hipStream_t st);
 template <typename TX, typename TK>
 void launch_gather_rows(const TX* X, int64_t d, const int64_t* idx, int64_t m, TK* out, hipStream_t st);
+void launch_iota(int32_t* out, int64_t m, hipStream_t st);
 
 // ----------------------------------------------------------------------------------------- select.hip
 // Score slots for step `step` of the candidate table (kCandSlots indices per step, -1 = empty).
@@ -89,21 +90,19 @@ void launch_compact(const double* o, const float* y, int64_t n, const uint8_t* a
 int compact_blocks(int64_t n);
 template <typename TK>
 void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv, const double* o, const float* y,
-                     const int64_t* J, const double* beta, double lam, double* partial, int nchunk, double* g,
+                     const double* v, const double* beta, double lam, double* partial, int nchunk, double* g,
                      NewtonScalars* sc, hipStream_t s);
 int gradient_chunks(int m, int n_sv);
 template <typename TK>
 void launch_syrk(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv, int nsplit, double* partial,
                  hipStream_t s);
-template <typename TK>
-void launch_syrk_reduce(const TK* K, int64_t ldk, int m, const int64_t* J, double lam, const double* partial,
-                        int nsplit, double diag_add, double* H, int64_t ldh, hipStream_t s);
+void launch_syrk_reduce(const double* KJJ, int m, double lam, const double* partial, int nsplit, double diag_add,
+                        double* H, int64_t ldh, hipStream_t s);
 void launch_trace(const double* H, int64_t ldh, int m, NewtonScalars* sc, hipStream_t s);
 int syrk_tiles(int m);
 int syrk_splits(int m, int n_sv);
 size_t syrk_partial_doubles(int m_max);
-void launch_c1c2(const double* beta, const double* dvec, const double* delta, const int64_t* J, int m, LineState* ls,
-                 hipStream_t s);
+void launch_c1c2(const double* beta, const double* dvec, const double* w, int m, LineState* ls, hipStream_t s);
 void launch_ls_round(const double* o, const double* delta, const float* y, int64_t n, double lam, LineState* ls,
                      double* partial, int nblk, hipStream_t s);
 void launch_apply_step(const LineState* ls, double* beta, const double* dvec, int m, double* o, const double* delta,

@@ -1,7 +1,9 @@
 // Newton re-optimisation of Eq. 4 on a fixed basis J (section 4, "Sparse primal optimization"; Newton's
 // method on the squared-hinge primal of section 4, "Primal optimization"):
 //   f(beta) = lambda/2 beta^T K_JJ beta + 1/2 sum_i max(0, a_i)^2,  a_i = 1 - y_i o_i,  o = K_XJ beta,
-//   grad f  = lambda o_J + K_I^T (o_I - y_I),     H = lambda K_JJ + K_I^T K_I,   I = {i : a_i > 0}.
+//   grad f  = lambda K_JJ beta + K_I^T (o_I - y_I),     H = lambda K_JJ + K_I^T K_I,   I = {i : a_i > 0}.
+// K_JJ is kept as its own FP64 matrix (computed from the basis rows), so the regulariser stays positive
+// definite whatever precision the n x |J| block K_XJ is stored in.
 // Kernels: GEMV o = K_XJ x (one wave per row), violator compaction (wave ballot + block prefix sums),
 // gradient (GEMV^T over the compacted rows), the SYRK of H over the compacted rows with MFMA, and the
 // exact line search along d (bracketed semismooth Newton on the piecewise-linear derivative).
@@ -141,20 +143,19 @@ __global__ __launch_bounds__(256) void k_grad_partial(const TK* __restrict__ K, 
   partial[(int64_t)blockIdx.y * m + k] = acc;
 }
 
+// g = lambda v + sum of the chunk partials, with v = K_JJ beta; also |g|^2 and beta . v = beta^T K_JJ beta.
 __global__ __launch_bounds__(1024) void k_grad_finish(int m, const double* __restrict__ partial, int nchunk,
-                                                      const double* __restrict__ o, const int64_t* __restrict__ J,
-                                                      const double* __restrict__ beta, double lam,
-                                                      double* __restrict__ g, NewtonScalars* sc) {
+                                                      const double* __restrict__ v, const double* __restrict__ beta,
+                                                      double lam, double* __restrict__ g, NewtonScalars* sc) {
   __shared__ double rd[16];
   double gn = 0.0, bo = 0.0;
   for (int k = threadIdx.x; k < m; k += 1024) {
-    const double oj = o[J[k]];
     double s = 0.0;
     for (int c = 0; c < nchunk; ++c) s += partial[(int64_t)c * m + k];
-    s += lam * oj;
+    s += lam * v[k];
     g[k] = s;
     gn += s * s;
-    bo += beta[k] * oj;
+    bo += beta[k] * v[k];
   }
   gn = block_sum(gn, rd);
   bo = block_sum(bo, rd);
@@ -173,23 +174,24 @@ int gradient_chunks(int m, int n_sv) {
 
 template <typename TK>
 void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv, const double* o, const float* y,
-                     const int64_t* J, const double* beta, double lam, double* partial, int nchunk, double* g,
+                     const double* v, const double* beta, double lam, double* partial, int nchunk, double* g,
                      NewtonScalars* sc, hipStream_t s) {
   const int rows = (int)std::max<int64_t>(1, ceil_div(n_sv, nchunk));
   hipLaunchKernelGGL((k_grad_partial<TK>), dim3((unsigned)ceil_div(m, 256), nchunk), dim3(256), 0, s, K, ldk, m, I,
                      n_sv, rows, o, y, partial);
   SPSVM_LAUNCHED();
-  hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(1024), 0, s, m, partial, nchunk, o, J, beta, lam, g, sc);
+  hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(1024), 0, s, m, partial, nchunk, v, beta, lam, g, sc);
   SPSVM_LAUNCHED();
 }
 
 // ------------------------------------------------------------------------------------------------ SYRK
 // Partial H tiles over a range of violator rows: P[split][tile] = sum_{r in split} K[I_r, T_r]^T K[I_r, T_c]
-// for the lower tiles (T_r >= T_c) of 64 x 64. Rows are staged 32 at a time, transposed into LDS so that
-// each MFMA operand fetch is a 4-wide read along the row index (the contraction dimension). FP32 products
-// accumulate in FP32 MFMA registers for at most kSyrkFlush rows, then into FP64 registers.
+// for the lower tiles (T_r >= T_c) of 64 x 64. Rows are staged 32 at a time, converted to FP64 and
+// transposed into LDS so that each MFMA operand fetch is a 4-wide read along the row index (the contraction
+// dimension). The products run on FP64 MFMA: a product of two FP32 values is exact in FP64, so the Gram
+// part of H is accumulated to FP64 accuracy and stays positive semi-definite even when the basis columns are
+// nearly dependent (FP32 accumulation loses that).
 constexpr int SY_T = 64, SY_BK = 32, SY_LD = SY_BK + 4;
-constexpr int kSyrkFlush = 4096;
 
 __device__ __forceinline__ void tile_of(int t, int& tr, int& tc) {
   int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -200,33 +202,11 @@ __device__ __forceinline__ void tile_of(int t, int& tr, int& tc) {
 }
 
 template <typename TK>
-struct SyMfma;
-template <>
-struct SyMfma<float> {
-  using acc_t = floatx4;
-  using vec4 = floatx4;
-  static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) * 4 + r; }
-};
-template <>
-struct SyMfma<double> {
-  using acc_t = doublex4;
-  using vec4 = doublex4;
-  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-};
-
-template <typename TK>
 __global__ __launch_bounds__(256) void k_syrk(const TK* __restrict__ K, int64_t ldk, int m,
                                               const int32_t* __restrict__ I, int n_sv, int rows_per_split, int ntiles,
                                               double* __restrict__ partial) {
-  using M = SyMfma<TK>;
-  __shared__ __attribute__((aligned(32))) TK At[SY_T][SY_LD];
-  __shared__ __attribute__((aligned(32))) TK Bt[SY_T][SY_LD];
+  __shared__ __attribute__((aligned(32))) double At[SY_T][SY_LD];
+  __shared__ __attribute__((aligned(32))) double Bt[SY_T][SY_LD];
   int tr, tc;
   tile_of(blockIdx.x, tr, tc);
   const bool diag = tr == tc;
@@ -234,27 +214,21 @@ __global__ __launch_bounds__(256) void k_syrk(const TK* __restrict__ K, int64_t 
   const int hi = lo + rows_per_split < n_sv ? lo + rows_per_split : n_sv;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, i16 = lane & 15;
   const int wr = w >> 1, wc = w & 1;
-  typename M::acc_t acc[2][2];
-  double acc64[2][2][4];
+  doublex4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      acc[i][j] = typename M::acc_t{0, 0, 0, 0};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
-    }
+    for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0, 0, 0, 0};
   const int ca = tr * SY_T, cb = tc * SY_T;
-  int since = 0;
   for (int r0 = lo; r0 < hi; r0 += SY_BK) {
-    TK va[8], vb[8];
+    double va[8], vb[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int idx = tid + e * 256, rr = idx >> 6, cc = idx & 63;
       const int rrow = r0 + rr;
       const int64_t row = rrow < hi ? (int64_t)I[rrow] : -1;
-      va[e] = (row >= 0 && ca + cc < m) ? K[row * ldk + ca + cc] : (TK)0;
-      vb[e] = (!diag && row >= 0 && cb + cc < m) ? K[row * ldk + cb + cc] : (TK)0;
+      va[e] = (row >= 0 && ca + cc < m) ? (double)K[row * ldk + ca + cc] : 0.0;
+      vb[e] = (!diag && row >= 0 && cb + cc < m) ? (double)K[row * ldk + cb + cc] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -264,32 +238,21 @@ __global__ __launch_bounds__(256) void k_syrk(const TK* __restrict__ K, int64_t 
       if (!diag) Bt[cc][rr] = vb[e];
     }
     __syncthreads();
-    TK(*Bp)[SY_LD] = diag ? At : Bt;
+    double(*Bp)[SY_LD] = diag ? At : Bt;
 #pragma unroll
     for (int kk = 0; kk < SY_BK; kk += 16) {
-      typename M::vec4 av[2], bv[2];
+      doublex4 av[2], bv[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) av[i] = *(const typename M::vec4*)&At[wr * 32 + i * 16 + i16][kk + 4 * g];
+      for (int i = 0; i < 2; ++i) av[i] = *(const doublex4*)&At[wr * 32 + i * 16 + i16][kk + 4 * g];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bv[j] = *(const typename M::vec4*)&Bp[wc * 32 + j * 16 + i16][kk + 4 * g];
+      for (int j = 0; j < 2; ++j) bv[j] = *(const doublex4*)&Bp[wc * 32 + j * 16 + i16][kk + 4 * g];
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = M::step(av[i][s], bv[j][s], acc[i][j]);
-    }
-    since += SY_BK;
-    if (since >= kSyrkFlush) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
-          acc[i][j] = typename M::acc_t{0, 0, 0, 0};
-        }
-      since = 0;
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
     }
   }
   double* out = partial + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * (SY_T * SY_T);
@@ -299,8 +262,8 @@ __global__ __launch_bounds__(256) void k_syrk(const TK* __restrict__ K, int64_t 
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int rr = wr * 32 + i * 16 + M::row(lane, r), cc = wc * 32 + j * 16 + i16;
-        out[rr * SY_T + cc] = acc64[i][j][r] + (double)acc[i][j][r];
+        const int rr = wr * 32 + i * 16 + (lane >> 4) + 4 * r, cc = wc * 32 + j * 16 + i16;
+        out[rr * SY_T + cc] = acc[i][j][r];
       }
 }
 
@@ -336,10 +299,9 @@ void launch_syrk(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv, in
   SPSVM_LAUNCHED();
 }
 
-// H (lower triangle) = lambda K_JJ + sum of the split partials (+ diag_add on the diagonal).
-template <typename TK>
-__global__ __launch_bounds__(256) void k_syrk_reduce(const TK* __restrict__ K, int64_t ldk, int m,
-                                                     const int64_t* __restrict__ J, double lam,
+// H (lower triangle) = lambda K_JJ + sum of the split partials (+ diag_add on the diagonal); K_JJ is the FP64
+// kernel matrix of the basis rows (row-major, leading dimension ldh).
+__global__ __launch_bounds__(256) void k_syrk_reduce(const double* __restrict__ KJJ, int m, double lam,
                                                      const double* __restrict__ partial, int nsplit, int ntiles,
                                                      double diag_add, double* __restrict__ H, int64_t ldh) {
   int tr, tc;
@@ -348,19 +310,17 @@ __global__ __launch_bounds__(256) void k_syrk_reduce(const TK* __restrict__ K, i
     const int idx = threadIdx.x + e * 256, r = idx >> 6, c = idx & 63;
     const int gr = tr * SY_T + r, gc = tc * SY_T + c;
     if (gr >= m || gc >= m || gc > gr) continue;
-    double s = lam * (double)K[J[gr] * ldk + gc];
+    double s = lam * KJJ[(int64_t)gr * ldh + gc];
     for (int p = 0; p < nsplit; ++p) s += partial[((int64_t)p * ntiles + blockIdx.x) * (SY_T * SY_T) + idx];
     if (gr == gc) s += diag_add;
     H[(int64_t)gr * ldh + gc] = s;
   }
 }
 
-template <typename TK>
-void launch_syrk_reduce(const TK* K, int64_t ldk, int m, const int64_t* J, double lam, const double* partial,
-                        int nsplit, double diag_add, double* H, int64_t ldh, hipStream_t s) {
+void launch_syrk_reduce(const double* KJJ, int m, double lam, const double* partial, int nsplit, double diag_add,
+                        double* H, int64_t ldh, hipStream_t s) {
   const int nt = syrk_tiles(m);
-  hipLaunchKernelGGL((k_syrk_reduce<TK>), dim3(nt), dim3(256), 0, s, K, ldk, m, J, lam, partial, nsplit, nt,
-                     diag_add, H, ldh);
+  hipLaunchKernelGGL(k_syrk_reduce, dim3(nt), dim3(256), 0, s, KJJ, m, lam, partial, nsplit, nt, diag_add, H, ldh);
   SPSVM_LAUNCHED();
 }
 
@@ -379,16 +339,14 @@ void launch_trace(const double* H, int64_t ldh, int m, NewtonScalars* sc, hipStr
 
 // ---------------------------------------------------------------------------------------- line search
 // phi(t) = f(beta + t d) = const + lambda (t c1 + t^2 c2 / 2) + 1/2 sum max(0, a_i - t b_i)^2,
-// a_i = 1 - y_i o_i, b_i = y_i delta_i, delta = K_XJ d, c1 = beta . delta_J, c2 = d . delta_J.
+// a_i = 1 - y_i o_i, b_i = y_i delta_i, delta = K_XJ d, c1 = beta^T K_JJ d, c2 = d^T K_JJ d (from w = K_JJ d).
 __global__ __launch_bounds__(256) void k_c1c2(const double* __restrict__ beta, const double* __restrict__ dvec,
-                                              const double* __restrict__ delta, const int64_t* __restrict__ J, int m,
-                                              LineState* ls) {
+                                              const double* __restrict__ w, int m, LineState* ls) {
   __shared__ double rd[4];
   double a = 0.0, b = 0.0;
   for (int k = threadIdx.x; k < m; k += 256) {
-    const double dj = delta[J[k]];
-    a += beta[k] * dj;
-    b += dvec[k] * dj;
+    a += beta[k] * w[k];
+    b += dvec[k] * w[k];
   }
   a = block_sum(a, rd);
   b = block_sum(b, rd);
@@ -409,9 +367,8 @@ __global__ __launch_bounds__(256) void k_c1c2(const double* __restrict__ beta, c
   }
 }
 
-void launch_c1c2(const double* beta, const double* dvec, const double* delta, const int64_t* J, int m, LineState* ls,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_c1c2, dim3(1), dim3(256), 0, s, beta, dvec, delta, J, m, ls);
+void launch_c1c2(const double* beta, const double* dvec, const double* w, int m, LineState* ls, hipStream_t s) {
+  hipLaunchKernelGGL(k_c1c2, dim3(1), dim3(256), 0, s, beta, dvec, w, m, ls);
   SPSVM_LAUNCHED();
 }
 
@@ -578,16 +535,12 @@ void launch_scale(double* v, int m, double a, hipStream_t s) {
 template void launch_gemv<float>(const float*, int64_t, int64_t, int, const double*, double*, hipStream_t);
 template void launch_gemv<double>(const double*, int64_t, int64_t, int, const double*, double*, hipStream_t);
 template void launch_gradient<float>(const float*, int64_t, int, const int32_t*, int, const double*, const float*,
-                                     const int64_t*, const double*, double, double*, int, double*, NewtonScalars*,
+                                     const double*, const double*, double, double*, int, double*, NewtonScalars*,
                                      hipStream_t);
 template void launch_gradient<double>(const double*, int64_t, int, const int32_t*, int, const double*, const float*,
-                                      const int64_t*, const double*, double, double*, int, double*, NewtonScalars*,
+                                      const double*, const double*, double, double*, int, double*, NewtonScalars*,
                                       hipStream_t);
 template void launch_syrk<float>(const float*, int64_t, int, const int32_t*, int, int, double*, hipStream_t);
 template void launch_syrk<double>(const double*, int64_t, int, const int32_t*, int, int, double*, hipStream_t);
-template void launch_syrk_reduce<float>(const float*, int64_t, int, const int64_t*, double, const double*, int, double,
-                                        double*, int64_t, hipStream_t);
-template void launch_syrk_reduce<double>(const double*, int64_t, int, const int64_t*, double, const double*, int,
-                                         double, double*, int64_t, hipStream_t);
 
 }  // namespace spsvm

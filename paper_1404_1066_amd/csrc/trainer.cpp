@@ -101,6 +101,12 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.stage_hash = take(cap * 8);
   p.m_dev = take(4);
   p.flags = take(8);
+  p.XJ64 = take((size_t)J_max * d * 8);
+  p.xjnorm = take(J_max * 8);
+  p.KJJ = take((size_t)J_max * p.ldh * 8);
+  p.vJ = take(J_max * 8);
+  p.wJ = take(J_max * 8);
+  p.iota = take(J_max * 4);
   p.bytes = off;
   return p;
 }
@@ -136,6 +142,8 @@ struct Impl {
   TK *xnorm, *KXJ, *Kc;
   uint64_t *hash, *stage_hash;
   double *o, *delta, *beta, *dvec, *g, *z, *H, *Linv, *syrk_part, *grad_part, *score_part, *ls_part, *cblk_sum;
+  double *XJ64, *xjnorm, *KJJ, *vJ, *wJ;
+  int32_t* iota;
   uint8_t *act_fact, *act_cur;
   int32_t *I, *cblk_cnt, *cblk_flips, *cand_table, *m_dev, *flags, *J32;
   int64_t* J;
@@ -186,6 +194,20 @@ struct Impl {
     sel = at<Selection>(p.sel);
     ls = at<LineState>(p.ls);
     sc = at<NewtonScalars>(p.scalars);
+    XJ64 = at<double>(p.XJ64);
+    xjnorm = at<double>(p.xjnorm);
+    KJJ = at<double>(p.KJJ);
+    vJ = at<double>(p.vJ);
+    wJ = at<double>(p.wJ);
+    iota = at<int32_t>(p.iota);
+  }
+
+  // Basis rows m0..m1 of J gathered into XJ64 (FP64), then the FP64 kernel matrix K_JJ of the first m1 rows.
+  void update_basis(int m0, int m1) {
+    if (m1 <= m0) return;
+    launch_gather_rows<TX, double>(X, d, J + m0, m1 - m0, XJ64 + (size_t)m0 * d, st);
+    launch_row_norms<double, double>(XJ64 + (size_t)m0 * d, m1 - m0, d, xjnorm + m0, st);
+    launch_kblock<double, double>(XJ64, m1, d, xjnorm, iota, m1, KJJ, p.ldh, gamma, st);
   }
 
   void sync() { SPSVM_HIP(hipStreamSynchronize(st)); }
@@ -202,6 +224,7 @@ struct Impl {
   // ---------------------------------------------------------------------------------------- preparation
   void prepare() {
     SPSVM_HIP(hipMemsetAsync(flags, 0, 8, st));
+    launch_iota(iota, J_max, st);
     launch_check_inputs<TX>(X, n * d, y, n, flags, st);
     launch_row_hash<TX>(X, n, d, hash, st);
     launch_row_norms<TX, TK>(X, n, d, xnorm, st);
@@ -233,10 +256,13 @@ struct Impl {
       launch_compact(o, y, n, fact_valid ? act_fact : nullptr, act_cur, I, cblk_cnt, cblk_sum, cblk_flips, sc, st);
       NewtonScalars s = read(sc);
       const int nchunk = gradient_chunks(m, s.n_sv);
-      launch_gradient<TK>(KXJ, p.ldk, m, I, s.n_sv, o, y, J, beta, lam, grad_part, nchunk, g, sc, st);
+      launch_gemv<double>(KJJ, p.ldh, m, m, beta, vJ, st);
+      launch_gradient<TK>(KXJ, p.ldk, m, I, s.n_sv, o, y, vJ, beta, lam, grad_part, nchunk, g, sc, st);
       s = read(sc);
       const double gn = std::sqrt(s.gnorm2);
       const double f = 0.5 * lam * s.beta_oJ + 0.5 * s.sum_a2;
+      if (!std::isfinite(f) || !std::isfinite(gn))
+        throw Failure(SPSVM_E_NO_CONVERGENCE, "non-finite objective or gradient in Newton (m=" + std::to_string(m) + ")");
       if (it == 0) g0 = gn;
       if (opt.log_level >= 2)
         std::fprintf(stderr, "[spsvm]   newton it=%d m=%d f=%.15e |g|=%.3e n_sv=%d flips=%d\n", it, m, f, gn, s.n_sv,
@@ -249,7 +275,8 @@ struct Impl {
       }
       launch_chol_solve(H, p.ldh, m, Linv, g, dvec, z, st);
       launch_gemv<TK>(KXJ, p.ldk, n, m, dvec, delta, st);
-      launch_c1c2(beta, dvec, delta, J, m, ls, st);
+      launch_gemv<double>(KJJ, p.ldh, m, m, dvec, wJ, st);
+      launch_c1c2(beta, dvec, wJ, m, ls, st);
       const int nblk = score_blocks(n);
       LineState L;
       int rounds = 0;
@@ -278,17 +305,17 @@ struct Impl {
   void factorize(int m, int n_sv) {
     const int nsplit = syrk_splits(m, n_sv);
     launch_syrk<TK>(KXJ, p.ldk, m, I, n_sv, nsplit, syrk_part, st);
-    launch_syrk_reduce<TK>(KXJ, p.ldk, m, J, lam, syrk_part, nsplit, 0.0, H, p.ldh, st);
+    launch_syrk_reduce(KJJ, m, lam, syrk_part, nsplit, 0.0, H, p.ldh, st);
     SPSVM_HIP(hipMemsetAsync(&sc->fail, 0, 4, st));
     launch_cholesky(H, p.ldh, m, Linv, sc, st);
     stats.factorizations += 1;
     if (read(&sc->fail) == 0) return;
     // jitter retries: H + mu * mean(diag H) * I
-    launch_syrk_reduce<TK>(KXJ, p.ldk, m, J, lam, syrk_part, nsplit, 0.0, H, p.ldh, st);
+    launch_syrk_reduce(KJJ, m, lam, syrk_part, nsplit, 0.0, H, p.ldh, st);
     launch_trace(H, p.ldh, m, sc, st);
     const double mean_diag = read(&sc->trace) / m;
     for (double mu : {1e-14, 1e-12, 1e-10, 1e-8}) {
-      launch_syrk_reduce<TK>(KXJ, p.ldk, m, J, lam, syrk_part, nsplit, mu * mean_diag, H, p.ldh, st);
+      launch_syrk_reduce(KJJ, m, lam, syrk_part, nsplit, mu * mean_diag, H, p.ldh, st);
       SPSVM_HIP(hipMemsetAsync(&sc->fail, 0, 4, st));
       launch_cholesky(H, p.ldh, m, Linv, sc, st);
       stats.factorizations += 1;
@@ -306,7 +333,8 @@ struct Impl {
     launch_gemv<TK>(KXJ, p.ldk, n, m, beta, o, st);
     launch_compact(o, y, n, nullptr, act_cur, I, cblk_cnt, cblk_sum, cblk_flips, sc, st);
     NewtonScalars s = read(sc);
-    launch_gradient<TK>(KXJ, p.ldk, m, I, s.n_sv, o, y, J, beta, lam, grad_part, gradient_chunks(m, s.n_sv), g, sc, st);
+    launch_gemv<double>(KJJ, p.ldh, m, m, beta, vJ, st);
+    launch_gradient<TK>(KXJ, p.ldk, m, I, s.n_sv, o, y, vJ, beta, lam, grad_part, gradient_chunks(m, s.n_sv), g, sc, st);
     s = read(sc);
     *out = s;
     *F = C * (0.5 * lam * s.beta_oJ + 0.5 * s.sum_a2);
@@ -354,6 +382,7 @@ struct Impl {
       const auto t1 = clk::now();
       stats.seconds_select += secs(t0, t1);
       if (m_new == m) break;
+      update_basis(m, m_new);
       m = m_new;
       const int its = newton(m);
       stats.stages += 1;
@@ -380,6 +409,7 @@ struct Impl {
     SPSVM_HIP(hipMemcpyAsync(J32, j32.data(), m * 4, hipMemcpyHostToDevice, st));
     const auto t0 = clk::now();
     launch_kblock<TX, TK>(X, n, d, xnorm, J32, (int)m, KXJ, p.ldk, gamma, st);
+    update_basis(0, (int)m);
     SPSVM_HIP(hipMemsetAsync(beta, 0, m * 8, st));
     sync();
     const auto t1 = clk::now();

@@ -36,7 +36,7 @@ struct Plan {
   // offsets into the workspace
   size_t xnorm, hash, KXJ, Kc, o, delta, act0, act1, I, cblk_cnt, cblk_sum, cblk_flips, J, J32, beta, dvec, g, z,
       H, Linv, syrk_part, grad_part, cand_state, sel, ls, scalars, score_part, ls_part, cand_table, stage_hash, m_dev,
-      flags;
+      flags, XJ64, xjnorm, KJJ, vJ, wJ, iota;
 };
 
 Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection);
