@@ -67,6 +67,12 @@ typedef struct {
   int32_t newton_max_iter; /* Newton iterations per re-optimisation, >= 1; default 50 */
   spsvm_precision precision; /* default SPSVM_F32 */
   int32_t log_level;       /* 0 silent; 1 one line per stage on stderr; 2 one line per Newton iteration */
+  int32_t profile;         /* bit mask of kernels to time with HIP events on the call's stream (results in
+                              spsvm_stats): 1 kernel block, 2 Newton-matrix SYRK, 4 candidate-score passes,
+                              8 Cholesky factorisations; 0 (default) records nothing */
+  double refactor_frac;    /* the Newton matrix is re-formed and re-factorised when more than this fraction of
+                              the violator set changed since the last factorisation (else the last factor is
+                              reused; the exact line search keeps every step a descent step); default 0.002 */
 } spsvm_options;
 
 typedef struct spsvm_model spsvm_model; /* opaque, owned by the library */
@@ -80,10 +86,27 @@ typedef struct {
   int64_t score_passes;     /* O(n) passes spent on candidate scoring */
   int64_t ls_passes;        /* O(n) passes spent in exact line searches */
   int64_t iter_cap_hits;    /* re-optimisations stopped by newton_max_iter */
+  int64_t stage_redos;      /* selection stages rerun with more scoring passes */
+  int64_t incremental_factorizations; /* Newton matrices updated from the rows that joined or left the
+                                         violator set instead of being recomputed */
   int64_t n_sv;             /* margin violators (y_i o_i < 1) at the returned solution */
   double grad_norm;         /* ||grad f|| at the returned solution (f = F / C) */
   double seconds_select;    /* wall time in greedy selection */
   double seconds_newton;    /* wall time in Newton re-optimisation */
+  /* Per-kernel GPU time (HIP events) and algorithmic work, for the kernels selected by
+   * spsvm_options.profile; zero otherwise. */
+  int64_t kblock_launches;  /* kernel-block GEMMs (candidate blocks and basis blocks) */
+  double kblock_seconds;
+  double kblock_flops;      /* 2 n N d per launch, N = columns computed */
+  int64_t syrk_launches;    /* Newton-matrix SYRKs */
+  double syrk_seconds;
+  double syrk_flops;        /* n_sv m (m + 1) per launch (lower triangle, multiply-add = 2) */
+  int64_t score_launches;   /* candidate-score passes over the n rows */
+  double score_seconds;
+  double score_bytes;       /* n (kappa sizeof(K) + 12) per pass: candidate columns, o (FP64), y (FP32) */
+  int64_t chol_calls;       /* Cholesky factorisations (all panel kernels of one factorisation) */
+  double chol_seconds;
+  double chol_flops;        /* m^3 / 3 per factorisation */
 } spsvm_stats;
 
 /* Fills *opt with the defaults listed above. */

@@ -57,6 +57,8 @@ class Options(ctypes.Structure):
         ("newton_max_iter", ctypes.c_int32),
         ("precision", ctypes.c_int),
         ("log_level", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
+        ("refactor_frac", ctypes.c_double),
     ]
 
 
@@ -69,10 +71,24 @@ class Stats(ctypes.Structure):
         ("score_passes", ctypes.c_int64),
         ("ls_passes", ctypes.c_int64),
         ("iter_cap_hits", ctypes.c_int64),
+        ("stage_redos", ctypes.c_int64),
+        ("incremental_factorizations", ctypes.c_int64),
         ("n_sv", ctypes.c_int64),
         ("grad_norm", ctypes.c_double),
         ("seconds_select", ctypes.c_double),
         ("seconds_newton", ctypes.c_double),
+        ("kblock_launches", ctypes.c_int64),
+        ("kblock_seconds", ctypes.c_double),
+        ("kblock_flops", ctypes.c_double),
+        ("syrk_launches", ctypes.c_int64),
+        ("syrk_seconds", ctypes.c_double),
+        ("syrk_flops", ctypes.c_double),
+        ("score_launches", ctypes.c_int64),
+        ("score_seconds", ctypes.c_double),
+        ("score_bytes", ctypes.c_double),
+        ("chol_calls", ctypes.c_int64),
+        ("chol_seconds", ctypes.c_double),
+        ("chol_flops", ctypes.c_double),
     ]
 
     def as_dict(self):

@@ -47,6 +47,8 @@ spsvm_options resolve(const spsvm_options* opt) {
   if (!(o.newton_tol >= 0.0) || !(o.newton_ftol >= 0.0))
     throw spsvm::Failure(SPSVM_E_INVALID_ARG, "newton tolerances must be >= 0");
   if (o.newton_max_iter < 1) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "newton_max_iter must be >= 1");
+  if (!(o.refactor_frac >= 0.0) || !std::isfinite(o.refactor_frac))
+    throw spsvm::Failure(SPSVM_E_INVALID_ARG, "refactor_frac must be finite and >= 0");
   if (o.precision != SPSVM_F64 && o.precision != SPSVM_F32)
     throw spsvm::Failure(SPSVM_E_INVALID_ARG, "precision must be SPSVM_F64 or SPSVM_F32");
   return o;
@@ -82,6 +84,8 @@ void spsvm_options_default(spsvm_options* o) {
   o->newton_max_iter = 50;
   o->precision = SPSVM_F32;
   o->log_level = 0;
+  o->profile = 0;
+  o->refactor_frac = 0.002;
 }
 
 spsvm_status spsvm_train_workspace_bytes(int64_t n, int64_t d, int64_t J_max, const spsvm_options* opt, size_t* bytes) {

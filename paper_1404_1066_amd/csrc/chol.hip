@@ -16,85 +16,127 @@ namespace spsvm {
 constexpr int NB = kCholNB;
 constexpr int NB_LD = NB + 1;
 
+// Factor the 64 x 64 diagonal block in LDS and write L_kk and its inverse. Thread t owns column t & 63 and
+// rows (t >> 6) + 4 r, so every step is one parallel sweep followed by one barrier:
+//  factor step j:  A[i][l] -= A[i][j] A[l][j] / A[j][j]  for j < l <= i (column j itself is scaled at the end);
+//  inverse step p: X[i][c] -= L[i][p] X[p][c] / L[p][p]   for i > p      (rows of X are scaled at the end).
 __global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ H, int64_t ldh, int m, int k0,
                                                     double* __restrict__ Linv, NewtonScalars* sc) {
   __shared__ double A[NB][NB_LD];
-  __shared__ double Li[NB][NB_LD];
-  __shared__ int bad;
+  __shared__ double X[NB][NB_LD];
+  __shared__ double dg[NB];
   const int nb = m - k0 < NB ? m - k0 : NB;
-  const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
+  const int tid = threadIdx.x, col = tid & 63, r0 = tid >> 6;
   for (int e = tid; e < NB * NB; e += 256) {
     const int r = e / NB, c = e % NB;
     A[r][c] = (r < nb && c <= r) ? H[(int64_t)(k0 + r) * ldh + k0 + c] : (r == c ? 1.0 : 0.0);
+    X[r][c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    if (tid == 0) {
-      const double p = A[j][j];
-      if (!(p > 0.0) || !(p < __builtin_huge_val())) {
-        bad = 1;
-        A[j][j] = 1.0;
-      } else {
-        A[j][j] = sqrt(p);
-      }
-    }
-    __syncthreads();
+  bool bad = false;
+  for (int j = 0; j < NB; ++j) {
     const double piv = A[j][j];
-    for (int i = j + 1 + tid; i < nb; i += 256) A[i][j] /= piv;
-    __syncthreads();
-    const int rem = nb - j - 1;
-    for (int e = tid; e < rem * rem; e += 256) {
-      const int i = j + 1 + e / rem, l = j + 1 + e % rem;
-      if (l <= i) A[i][l] -= A[i][j] * A[l][j];
+    if (tid == 0) bad |= !(piv > 0.0) || !(piv < __builtin_huge_val());
+    const double rp = (piv > 0.0 && piv < __builtin_huge_val()) ? 1.0 / piv : 0.0;
+    if (col > j) {
+      // all LDS reads of the step first, then the writes (keeps the reads pipelined)
+      double aij[16], aic[16];
+      const double alj = A[col][j] * rp;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        aij[q] = A[r0 + 4 * q][j];
+        aic[q] = A[r0 + 4 * q][col];
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (r0 + 4 * q >= col) A[r0 + 4 * q][col] = aic[q] - aij[q] * alj;
     }
     __syncthreads();
   }
-  // inverse of the lower-triangular diagonal block, one column per thread (forward substitution)
   if (tid < NB) {
-    const int c = tid;
-    for (int i = 0; i < NB; ++i) {
-      double v;
-      if (i < c) {
-        v = 0.0;
-      } else {
-        double s = (i == c) ? 1.0 : 0.0;
-        for (int p = c; p < i; ++p) s -= A[i][p] * Li[p][c];
-        v = s / A[i][i];
-      }
-      Li[i][c] = v;
-    }
+    const double p = A[tid][tid];
+    dg[tid] = (p > 0.0 && p < __builtin_huge_val()) ? sqrt(p) : 1.0;
   }
   __syncthreads();
+  // L[i][c] = A[i][c] / sqrt(A[c][c]) below the diagonal, sqrt(A[c][c]) on it
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int i = r0 + 4 * q;
+    if (i > col) A[i][col] /= dg[col];
+  }
+  __syncthreads();
+  if (tid < NB) A[tid][tid] = dg[tid];
+  __syncthreads();
+  // inverse of the lower-triangular L: column-oriented forward substitution on X = I
+  for (int p = 0; p < NB; ++p) {
+    const double xp = X[p][col] / A[p][p];
+    double aip[16], xic[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      aip[q] = A[r0 + 4 * q][p];
+      xic[q] = X[r0 + 4 * q][col];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (r0 + 4 * q > p) X[r0 + 4 * q][col] = xic[q] - aip[q] * xp;
+    __syncthreads();
+  }
   double* Lo = Linv + (int64_t)(k0 / NB) * NB * NB;
   for (int e = tid; e < NB * NB; e += 256) {
     const int r = e / NB, c = e % NB;
-    Lo[e] = Li[r][c];
+    Lo[e] = (c <= r) ? X[r][c] / A[r][r] : 0.0;
     if (r < nb && c <= r) H[(int64_t)(k0 + r) * ldh + k0 + c] = A[r][c];
   }
   if (tid == 0 && bad) sc->fail = 1;
 }
 
-// Rows r >= k0 + 64: L[r, panel] = H[r, panel] Linv^T.
+// Rows r >= k0 + 64: L[r, panel] = H[r, panel] Linv^T, a 64 x 64 x 64 product per workgroup on FP64 MFMA.
+constexpr int TU_LD = NB + 4;
+
 __global__ __launch_bounds__(256) void k_trsm_panel(double* __restrict__ H, int64_t ldh, int m, int k0,
                                                     const double* __restrict__ Linv) {
-  __shared__ double Li[NB][NB_LD];
-  __shared__ double B[NB][NB_LD];
-  const int tid = threadIdx.x;
+  __shared__ __attribute__((aligned(32))) double Bm[NB][TU_LD];
+  __shared__ __attribute__((aligned(32))) double Li[NB][TU_LD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, i16 = lane & 15;
   const int r0 = k0 + NB + blockIdx.x * NB;
   const double* Lo = Linv + (int64_t)(k0 / NB) * NB * NB;
   for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e / NB, c = e % NB;
+    const int r = e >> 6, c = e & 63;
     Li[r][c] = Lo[e];
-    B[r][c] = (r0 + r < m) ? H[(int64_t)(r0 + r) * ldh + k0 + c] : 0.0;
+    Bm[r][c] = (r0 + r < m) ? H[(int64_t)(r0 + r) * ldh + k0 + c] : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e / NB, j = e % NB;
-    double s = 0.0;
-    for (int p = 0; p <= j; ++p) s += B[r][p] * Li[j][p];
-    if (r0 + r < m) H[(int64_t)(r0 + r) * ldh + k0 + j] = s;
+  const int wr = w >> 1, wc = w & 1;
+  doublex4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0, 0, 0, 0};
+#pragma unroll
+  for (int kk = 0; kk < NB; kk += 16) {
+    doublex4 av[2], bv[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) av[i] = *(const doublex4*)&Bm[wr * 32 + i * 16 + i16][kk + 4 * g];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bv[j] = *(const doublex4*)&Li[wc * 32 + j * 16 + i16][kk + 4 * g];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
   }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = r0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+        const int cc = wc * 32 + j * 16 + i16;
+        if (rr < m) H[(int64_t)rr * ldh + k0 + cc] = acc[i][j][r];
+      }
 }
 
 // Trailing update of the lower tiles at or below the diagonal of the remaining matrix.
@@ -105,8 +147,6 @@ __device__ __forceinline__ void tri_tile(int t, int& tr, int& tc) {
   tr = r;
   tc = t - r * (r + 1) / 2;
 }
-
-constexpr int TU_LD = NB + 4;
 
 __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ H, int64_t ldh, int m, int k0) {
   __shared__ __attribute__((aligned(32))) double Pa[NB][TU_LD];

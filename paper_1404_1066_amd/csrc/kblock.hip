@@ -116,12 +116,14 @@ struct KTile {
       for (int j = 0; j < 4; ++j) acc[i][j] = typename M::acc_t{0, 0, 0, 0};
   }
 
-  // acc += A[r0 .. r0+128) . B[rows of this column tile]^T over all d features.
+  // acc += A[r0 .. r0+128) . B[rows of this column tile]^T over all d features. The next chunk's global
+  // loads are issued into registers before the current chunk's MFMAs, so they overlap.
   __device__ __forceinline__ void run(const TA* __restrict__ A, int64_t nA, int64_t r0, const TB* __restrict__ B,
                                       const int32_t* __restrict__ bidx, int64_t c0, int ncols, int64_t d,
                                       TK (*As)[KB_LD], TK (*Bs)[KB_LD]) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int g = lane >> 4, i16 = lane & 15;
+    const int kk_a = tid & 31;  // every element this thread stages sits in column kk_a of the chunk
     int64_t brow[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -129,31 +131,29 @@ struct KTile {
       const int64_t col = c0 + c;
       brow[e] = col < ncols ? (bidx ? (int64_t)bidx[col] : col) : -1;
     }
+    const TA* arow[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int64_t row = r0 + ((tid + e * 256) >> 5);
+      arow[e] = row < nA ? A + row * d : nullptr;
+    }
+    TK ra[16], rb[8];
+    auto fetch = [&](int64_t k0) {
+      const bool kin = k0 + kk_a < d;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) ra[e] = (arow[e] && kin) ? (TK)arow[e][k0 + kk_a] : (TK)0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rb[e] = (brow[e] >= 0 && kin) ? (TK)B[brow[e] * d + k0 + kk_a] : (TK)0;
+    };
+    fetch(0);
     for (int64_t k0 = 0; k0 < d; k0 += KB_BK) {
-      TK ra[16], rb[8];
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int idx = tid + e * 256, r = idx >> 5, k = idx & 31;
-        const int64_t row = r0 + r;
-        ra[e] = (row < nA && k0 + k < d) ? (TK)A[row * d + k0 + k] : (TK)0;
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = (tid + e * 256) & 31;
-        rb[e] = (brow[e] >= 0 && k0 + k < d) ? (TK)B[brow[e] * d + k0 + k] : (TK)0;
-      }
       __syncthreads();
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int idx = tid + e * 256;
-        As[idx >> 5][idx & 31] = ra[e];
-      }
+      for (int e = 0; e < 16; ++e) As[(tid + e * 256) >> 5][kk_a] = ra[e];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int idx = tid + e * 256;
-        Bs[idx >> 5][idx & 31] = rb[e];
-      }
+      for (int e = 0; e < 8; ++e) Bs[(tid + e * 256) >> 5][kk_a] = rb[e];
       __syncthreads();
+      if (k0 + KB_BK < d) fetch(k0 + KB_BK);
 #pragma unroll
       for (int kk = 0; kk < KB_BK; kk += 16) {
         typename M::vec4 av[2], bv[4];

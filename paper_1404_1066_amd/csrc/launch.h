@@ -49,6 +49,7 @@ struct NewtonScalars {
   int32_t flips;   // rows whose violator status differs from the last factorisation
   int32_t fail;    // Cholesky met a non-positive pivot
   int32_t n_active_sel;  // candidates still being scored
+  int32_t n_in, n_out;   // rows that joined / left the violator set since the last Newton matrix
 };
 
 // ----------------------------------------------------------------------------------------- kblock.hip
@@ -72,13 +73,16 @@ void launch_iota(int32_t* out, int64_t m, hipStream_t st);
 // Score slots for step `step` of the candidate table (kCandSlots indices per step, -1 = empty).
 void launch_score_init(const int32_t* cand, const double* o, const uint64_t* hash, const uint64_t* stage_hash,
                        int n_stage, CandState* st, NewtonScalars* sc, hipStream_t s);
+// One scoring pass over the n rows for all active slots (partial sums per workgroup), then one workgroup per
+// slot reduces them and advances the slot. Both kernels return at once when every slot is settled.
 template <typename TK>
-void launch_score_round(const TK* Kc, const float* y, const double* o, int64_t n, double lam, CandState* st,
-                        double* partial, int nblk, NewtonScalars* sc, hipStream_t s);
+void launch_score_pass(const TK* Kc, const float* y, const double* o, int64_t n, const CandState* st,
+                       double* partial, int nblk, hipStream_t s);
+void launch_score_update(CandState* st, const double* partial, int nblk, double lam, hipStream_t s);
 template <typename TK>
 void launch_select_append(const CandState* st, const uint64_t* hash, uint64_t* stage_hash, int q, const TK* Kc,
                           int64_t n, double* o, TK* KXJ, int64_t ldk, int64_t* J, double* beta, int32_t* m_dev,
-                          Selection* sel, hipStream_t s);
+                          Selection* sel, int32_t* incomplete, hipStream_t s);
 int score_blocks(int64_t n);
 
 // ----------------------------------------------------------------------------------------- newton.hip
@@ -93,14 +97,22 @@ void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv
                      const double* v, const double* beta, double lam, double* partial, int nchunk, double* g,
                      NewtonScalars* sc, hipStream_t s);
 int gradient_chunks(int m, int n_sv);
+// SYRK partials over the rows I[0..n_rows) for the lower 128 x 128 tiles tile_lo..tile_hi-1 (tiles numbered
+// row by row: tile t = tr (tr + 1) / 2 + tc).
 template <typename TK>
-void launch_syrk(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv, int nsplit, double* partial,
-                 hipStream_t s);
-void launch_syrk_reduce(const double* KJJ, int m, double lam, const double* partial, int nsplit, double diag_add,
-                        double* H, int64_t ldh, hipStream_t s);
+void launch_syrk(const TK* K, int64_t ldk, int m, const int32_t* I, int n_rows, int tile_lo, int tile_hi, int nsplit,
+                 double* partial, hipStream_t s);
+// mode 0: H = lambda K_JJ + partials; +1: H += partials; -1: H -= partials (same tile range as the SYRK).
+void launch_syrk_reduce(const double* KJJ, int m, double lam, const double* partial, int nsplit, int tile_lo,
+                        int tile_hi, int mode, double* H, int64_t ldh, hipStream_t s);
+void launch_add_diag(double* H, int64_t ldh, int m, double v, hipStream_t s);
+void launch_flip_lists(const uint8_t* act_new, const uint8_t* act_old, int64_t n, int32_t* cnt_in, int32_t* cnt_out,
+                       int32_t* F_in, int32_t* F_out, NewtonScalars* sc, hipStream_t s);
 void launch_trace(const double* H, int64_t ldh, int m, NewtonScalars* sc, hipStream_t s);
 int syrk_tiles(int m);
-int syrk_splits(int m, int n_sv);
+int syrk_tile_rows(int m);
+int syrk_tile_size();
+int syrk_splits(int ntiles, int n_rows);
 size_t syrk_partial_doubles(int m_max);
 void launch_c1c2(const double* beta, const double* dvec, const double* w, int m, LineState* ls, hipStream_t s);
 void launch_ls_round(const double* o, const double* delta, const float* y, int64_t n, double lam, LineState* ls,

@@ -143,31 +143,59 @@ __global__ __launch_bounds__(256) void k_grad_partial(const TK* __restrict__ K, 
   partial[(int64_t)blockIdx.y * m + k] = acc;
 }
 
-// g = lambda v + sum of the chunk partials, with v = K_JJ beta; also |g|^2 and beta . v = beta^T K_JJ beta.
-__global__ __launch_bounds__(1024) void k_grad_finish(int m, const double* __restrict__ partial, int nchunk,
+// g = lambda v + sum of the chunk partials, with v = K_JJ beta. Each workgroup owns 64 columns; lane group j
+// (of 16) sums chunks j, j + 16, ... and thread k adds the 16 group sums in order. Per-workgroup partial sums
+// of |g|^2 and beta . v go to blk (2 doubles per workgroup).
+__global__ __launch_bounds__(1024) void k_grad_reduce(int m, const double* __restrict__ partial, int nchunk,
                                                       const double* __restrict__ v, const double* __restrict__ beta,
-                                                      double lam, double* __restrict__ g, NewtonScalars* sc) {
-  __shared__ double rd[16];
-  double gn = 0.0, bo = 0.0;
-  for (int k = threadIdx.x; k < m; k += 1024) {
-    double s = 0.0;
-    for (int c = 0; c < nchunk; ++c) s += partial[(int64_t)c * m + k];
-    s += lam * v[k];
-    g[k] = s;
-    gn += s * s;
-    bo += beta[k] * v[k];
+                                                      double lam, double* __restrict__ g, double* __restrict__ blk) {
+  __shared__ double red[16][64];
+  __shared__ double rd[2];
+  const int c = threadIdx.x & 63, j = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + c;
+  double a = 0.0;
+  if (k < m)
+    for (int q = j; q < nchunk; q += 16) a += partial[(int64_t)q * m + k];
+  red[j][c] = a;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double gn = 0.0, bo = 0.0;
+    if (k < m) {
+      double s = 0.0;
+      for (int q = 0; q < 16; ++q) s += red[q][c];
+      s += lam * v[k];
+      g[k] = s;
+      gn = s * s;
+      bo = beta[k] * v[k];
+    }
+    gn = wave_sum(gn);
+    bo = wave_sum(bo);
+    if (threadIdx.x == 0) {
+      blk[2 * blockIdx.x] = gn;
+      blk[2 * blockIdx.x + 1] = bo;
+    }
   }
-  gn = block_sum(gn, rd);
-  bo = block_sum(bo, rd);
+}
+
+__global__ __launch_bounds__(64) void k_grad_norms(int nblk, const double* __restrict__ blk, NewtonScalars* sc) {
+  double gn = 0.0, bo = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) {
+    gn += blk[2 * b];
+    bo += blk[2 * b + 1];
+  }
+  gn = wave_sum(gn);
+  bo = wave_sum(bo);
   if (threadIdx.x == 0) {
     sc->gnorm2 = gn;
     sc->beta_oJ = bo;
   }
 }
 
+// Chunks of violator rows for the gradient partials; nchunk * m + 2 * ceil(m / 64) <= 1024 * 256 doubles
+// (the partial buffer) for every m <= 65536.
 int gradient_chunks(int m, int n_sv) {
   const int colblocks = (int)ceil_div(std::max(m, 1), 256);
-  int c = std::max(1, 1024 / colblocks);
+  int c = std::max(1, 1024 / colblocks - 1);
   c = std::min<int>(c, (int)std::max<int64_t>(1, ceil_div(n_sv, 64)));
   return c;
 }
@@ -180,18 +208,22 @@ void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv
   hipLaunchKernelGGL((k_grad_partial<TK>), dim3((unsigned)ceil_div(m, 256), nchunk), dim3(256), 0, s, K, ldk, m, I,
                      n_sv, rows, o, y, partial);
   SPSVM_LAUNCHED();
-  hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(1024), 0, s, m, partial, nchunk, v, beta, lam, g, sc);
+  const int nb = (int)ceil_div(m, 64);
+  double* blk = partial + (int64_t)nchunk * m;  // the partial buffer holds 1024 * 256 doubles; see gradient_chunks
+  hipLaunchKernelGGL(k_grad_reduce, dim3(nb), dim3(1024), 0, s, m, partial, nchunk, v, beta, lam, g, blk);
+  SPSVM_LAUNCHED();
+  hipLaunchKernelGGL(k_grad_norms, dim3(1), dim3(64), 0, s, nb, blk, sc);
   SPSVM_LAUNCHED();
 }
 
 // ------------------------------------------------------------------------------------------------ SYRK
 // Partial H tiles over a range of violator rows: P[split][tile] = sum_{r in split} K[I_r, T_r]^T K[I_r, T_c]
-// for the lower tiles (T_r >= T_c) of 64 x 64. Rows are staged 32 at a time, converted to FP64 and
-// transposed into LDS so that each MFMA operand fetch is a 4-wide read along the row index (the contraction
-// dimension). The products run on FP64 MFMA: a product of two FP32 values is exact in FP64, so the Gram
-// part of H is accumulated to FP64 accuracy and stays positive semi-definite even when the basis columns are
-// nearly dependent (FP32 accumulation loses that).
-constexpr int SY_T = 64, SY_BK = 32, SY_LD = SY_BK + 4;
+// for the lower tiles (T_r >= T_c) of 128 x 128. Each workgroup (4 waves, 2 x 2, each 64 x 64 = 4 x 4 MFMA
+// blocks) stages 16 gathered rows at a time in LDS in their natural layout; in an MFMA step lane group g
+// supplies row kk + g, so no transpose is needed. The next rows are loaded into registers during the MFMAs.
+// The products run on FP64 MFMA: a product of two FP32 values is exact in FP64, so the Gram part of H is
+// accumulated to FP64 accuracy and stays positive semi-definite even for nearly dependent basis columns.
+constexpr int SY_T = 128, SY_BK = 16, SY_LD = SY_T + 4;
 
 __device__ __forceinline__ void tile_of(int t, int& tr, int& tc) {
   int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -204,66 +236,83 @@ __device__ __forceinline__ void tile_of(int t, int& tr, int& tc) {
 template <typename TK>
 __global__ __launch_bounds__(256) void k_syrk(const TK* __restrict__ K, int64_t ldk, int m,
                                               const int32_t* __restrict__ I, int n_sv, int rows_per_split, int ntiles,
-                                              double* __restrict__ partial) {
-  __shared__ __attribute__((aligned(32))) double At[SY_T][SY_LD];
-  __shared__ __attribute__((aligned(32))) double Bt[SY_T][SY_LD];
+                                              int tile_base, double* __restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) double At[SY_BK][SY_LD];
+  __shared__ __attribute__((aligned(16))) double Bt[SY_BK][SY_LD];
   int tr, tc;
-  tile_of(blockIdx.x, tr, tc);
+  tile_of(tile_base + blockIdx.x, tr, tc);
   const bool diag = tr == tc;
   const int lo = blockIdx.y * rows_per_split;
   const int hi = lo + rows_per_split < n_sv ? lo + rows_per_split : n_sv;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, i16 = lane & 15;
   const int wr = w >> 1, wc = w & 1;
-  doublex4 acc[2][2];
+  const int cc = tid & 127, rr0 = tid >> 7;  // this thread stages column cc of rows rr0, rr0 + 2, ...
+  const int ca = tr * SY_T + cc, cb = tc * SY_T + cc;
+  const bool a_in = ca < m, b_in = !diag && cb < m;
+  doublex4 acc[4][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0, 0, 0, 0};
-  const int ca = tr * SY_T, cb = tc * SY_T;
+    for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0, 0, 0, 0};
+  // Software pipeline: the row indices of chunk c + 2 and the values of chunk c + 1 are in flight while
+  // chunk c is multiplied, so no load waits on a just-loaded index.
+  double va[8], vb[8];
+  int32_t ix[8];
+  auto fetch_idx = [&](int r0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int rrow = r0 + rr0 + 2 * e;
+      ix[e] = rrow < hi ? I[rrow] : -1;
+    }
+  };
+  auto fetch_val = [&]() {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t row = ix[e];
+      va[e] = (row >= 0 && a_in) ? (double)K[row * ldk + ca] : 0.0;
+      vb[e] = (row >= 0 && b_in) ? (double)K[row * ldk + cb] : 0.0;
+    }
+  };
+  if (lo < hi) {
+    fetch_idx(lo);
+    fetch_val();
+    fetch_idx(lo + SY_BK);
+  }
   for (int r0 = lo; r0 < hi; r0 += SY_BK) {
-    double va[8], vb[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int idx = tid + e * 256, rr = idx >> 6, cc = idx & 63;
-      const int rrow = r0 + rr;
-      const int64_t row = rrow < hi ? (int64_t)I[rrow] : -1;
-      va[e] = (row >= 0 && ca + cc < m) ? (double)K[row * ldk + ca + cc] : 0.0;
-      vb[e] = (!diag && row >= 0 && cb + cc < m) ? (double)K[row * ldk + cb + cc] : 0.0;
-    }
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int idx = tid + e * 256, rr = idx >> 6, cc = idx & 63;
-      At[cc][rr] = va[e];
-      if (!diag) Bt[cc][rr] = vb[e];
+      At[rr0 + 2 * e][cc] = va[e];
+      Bt[rr0 + 2 * e][cc] = vb[e];
     }
     __syncthreads();
+    if (r0 + SY_BK < hi) {
+      fetch_val();
+      fetch_idx(r0 + 2 * SY_BK);
+    }
     double(*Bp)[SY_LD] = diag ? At : Bt;
 #pragma unroll
-    for (int kk = 0; kk < SY_BK; kk += 16) {
-      doublex4 av[2], bv[2];
+    for (int kk = 0; kk < SY_BK; kk += 4) {
+      double av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) av[i] = *(const doublex4*)&At[wr * 32 + i * 16 + i16][kk + 4 * g];
+      for (int i = 0; i < 4; ++i) av[i] = At[kk + g][wr * 64 + i * 16 + i16];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bv[j] = *(const doublex4*)&Bp[wc * 32 + j * 16 + i16][kk + 4 * g];
+      for (int j = 0; j < 4; ++j) bv[j] = Bp[kk + g][wc * 64 + j * 16 + i16];
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
   }
   double* out = partial + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * (SY_T * SY_T);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int rr = wr * 32 + i * 16 + (lane >> 4) + 4 * r, cc = wc * 32 + j * 16 + i16;
-        out[rr * SY_T + cc] = acc[i][j][r];
+        const int orow = wr * 64 + i * 16 + (lane >> 4) + 4 * r, ocol = wc * 64 + j * 16 + i16;
+        out[orow * SY_T + ocol] = acc[i][j][r];
       }
 }
 
@@ -272,55 +321,162 @@ int syrk_tiles(int m) {
   return t * (t + 1) / 2;
 }
 
-int syrk_splits(int m, int n_sv) {
-  const int nt = syrk_tiles(m);
-  int s = (int)ceil_div(1024, nt);
+// Row splits per tile: enough workgroups to cover the chip about four times (memory-level parallelism for the
+// gathered rows), at least 256 rows per split, at most 256 splits.
+int syrk_splits(int nt, int n_sv) {
+  int s = (int)ceil_div(1024, std::max(nt, 1));
   s = std::min<int>(s, (int)std::max<int64_t>(1, ceil_div(n_sv, 256)));
-  return std::max(1, std::min(s, 64));
+  return std::max(1, std::min(s, 256));
 }
 
 size_t syrk_partial_doubles(int m_max) {
   size_t best = 0;
-  // the split count only shrinks as m grows, so the bound over m <= m_max is reached at some tile count
   for (int t = 1; t <= ceil_div(std::max(m_max, 1), SY_T); ++t) {
     const int nt = t * (t + 1) / 2;
-    const int s = std::max(1, std::min<int>((int)ceil_div(1024, nt), 64));
+    const int s = std::max(1, std::min<int>((int)ceil_div(1024, nt), 256));
     best = std::max(best, (size_t)s * nt * SY_T * SY_T);
   }
   return best;
 }
 
+int syrk_tile_rows(int m) { return (int)ceil_div(m, SY_T); }
+int syrk_tile_size() { return SY_T; }
+
 template <typename TK>
-void launch_syrk(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv, int nsplit, double* partial,
-                 hipStream_t s) {
-  const int nt = syrk_tiles(m);
-  const int rows = (int)std::max<int64_t>(1, ceil_div(n_sv, nsplit));
-  hipLaunchKernelGGL((k_syrk<TK>), dim3(nt, nsplit), dim3(256), 0, s, K, ldk, m, I, n_sv, rows, nt, partial);
+void launch_syrk(const TK* K, int64_t ldk, int m, const int32_t* I, int n_rows, int tile_lo, int tile_hi, int nsplit,
+                 double* partial, hipStream_t s) {
+  const int nt = tile_hi - tile_lo;
+  if (nt <= 0) return;
+  const int rows = (int)std::max<int64_t>(1, ceil_div(n_rows, nsplit));
+  hipLaunchKernelGGL((k_syrk<TK>), dim3(nt, nsplit), dim3(256), 0, s, K, ldk, m, I, n_rows, rows, nt, tile_lo,
+                     partial);
   SPSVM_LAUNCHED();
 }
 
-// H (lower triangle) = lambda K_JJ + sum of the split partials (+ diag_add on the diagonal); K_JJ is the FP64
-// kernel matrix of the basis rows (row-major, leading dimension ldh).
+// For the tiles tile_lo.. of the lower triangle: mode 0 sets H = lambda K_JJ + sum of the split partials,
+// mode +1 adds the partial sums to H, mode -1 subtracts them (rows that joined or left the violator set).
+// K_JJ is the FP64 kernel matrix of the basis rows (row-major, leading dimension ldh).
 __global__ __launch_bounds__(256) void k_syrk_reduce(const double* __restrict__ KJJ, int m, double lam,
                                                      const double* __restrict__ partial, int nsplit, int ntiles,
-                                                     double diag_add, double* __restrict__ H, int64_t ldh) {
+                                                     int tile_lo, int mode, double* __restrict__ H, int64_t ldh) {
   int tr, tc;
-  tile_of(blockIdx.x, tr, tc);
-  for (int e = 0; e < 16; ++e) {
-    const int idx = threadIdx.x + e * 256, r = idx >> 6, c = idx & 63;
-    const int gr = tr * SY_T + r, gc = tc * SY_T + c;
-    if (gr >= m || gc >= m || gc > gr) continue;
-    double s = lam * KJJ[(int64_t)gr * ldh + gc];
-    for (int p = 0; p < nsplit; ++p) s += partial[((int64_t)p * ntiles + blockIdx.x) * (SY_T * SY_T) + idx];
-    if (gr == gc) s += diag_add;
-    H[(int64_t)gr * ldh + gc] = s;
+  tile_of(tile_lo + blockIdx.x, tr, tc);
+  const int idx = blockIdx.y * 256 + threadIdx.x, r = idx / SY_T, c = idx % SY_T;
+  const int gr = tr * SY_T + r, gc = tc * SY_T + c;
+  if (gr >= m || gc >= m || gc > gr) return;
+  double s = 0.0;
+  for (int p = 0; p < nsplit; ++p) s += partial[((int64_t)p * ntiles + blockIdx.x) * (SY_T * SY_T) + idx];
+  double* h = H + (int64_t)gr * ldh + gc;
+  if (mode == 0)
+    *h = lam * KJJ[(int64_t)gr * ldh + gc] + s;
+  else if (mode > 0)
+    *h += s;
+  else
+    *h -= s;
+}
+
+void launch_syrk_reduce(const double* KJJ, int m, double lam, const double* partial, int nsplit, int tile_lo,
+                        int tile_hi, int mode, double* H, int64_t ldh, hipStream_t s) {
+  const int nt = tile_hi - tile_lo;
+  if (nt <= 0) return;
+  hipLaunchKernelGGL(k_syrk_reduce, dim3(nt, SY_T * SY_T / 256), dim3(256), 0, s, KJJ, m, lam, partial, nsplit, nt,
+                     tile_lo, mode, H, ldh);
+  SPSVM_LAUNCHED();
+}
+
+__global__ void k_add_diag(double* __restrict__ H, int64_t ldh, int m, double v) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < m; k += gridDim.x * blockDim.x) H[(int64_t)k * ldh + k] += v;
+}
+
+void launch_add_diag(double* H, int64_t ldh, int m, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_diag, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(m, 256), 64))),
+                     dim3(256), 0, s, H, ldh, m, v);
+  SPSVM_LAUNCHED();
+}
+
+// --------------------------------------------------------------------------------------- flipped rows
+// Lists of rows whose violator status differs between act_new and act_old: joined (new 1, old 0) and left
+// (new 0, old 1), each in ascending order. Same block scheme as the violator compaction.
+__global__ __launch_bounds__(256) void k_flip_count(const uint8_t* __restrict__ act_new,
+                                                    const uint8_t* __restrict__ act_old, int64_t n,
+                                                    int32_t* __restrict__ cnt_in, int32_t* __restrict__ cnt_out) {
+  __shared__ int ri[4];
+  const int64_t lo = (int64_t)blockIdx.x * kCompactRows;
+  int a = 0, b = 0;
+  for (int j = 0; j < kCompactRows / 256; ++j) {
+    const int64_t i = lo + j * 256 + threadIdx.x;
+    if (i < n) {
+      a += act_new[i] && !act_old[i];
+      b += !act_new[i] && act_old[i];
+    }
+  }
+  a = block_sum_int(a, ri);
+  b = block_sum_int(b, ri);
+  if (threadIdx.x == 0) {
+    cnt_in[blockIdx.x] = a;
+    cnt_out[blockIdx.x] = b;
   }
 }
 
-void launch_syrk_reduce(const double* KJJ, int m, double lam, const double* partial, int nsplit, double diag_add,
-                        double* H, int64_t ldh, hipStream_t s) {
-  const int nt = syrk_tiles(m);
-  hipLaunchKernelGGL(k_syrk_reduce, dim3(nt), dim3(256), 0, s, KJJ, m, lam, partial, nsplit, nt, diag_add, H, ldh);
+__global__ __launch_bounds__(256) void k_flip_write(const uint8_t* __restrict__ act_new,
+                                                    const uint8_t* __restrict__ act_old, int64_t n,
+                                                    const int32_t* __restrict__ cnt_in,
+                                                    const int32_t* __restrict__ cnt_out, int nblk,
+                                                    int32_t* __restrict__ F_in, int32_t* __restrict__ F_out,
+                                                    NewtonScalars* sc) {
+  __shared__ int ri[4];
+  __shared__ int wc[2][4];
+  int pa = 0, pb = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) {
+    pa += cnt_in[b];
+    pb += cnt_out[b];
+  }
+  int off_in = block_sum_int(pa, ri), off_out = block_sum_int(pb, ri);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t lo = (int64_t)blockIdx.x * kCompactRows;
+  for (int j = 0; j < kCompactRows / 256; ++j) {
+    const int64_t i = lo + j * 256 + threadIdx.x;
+    int vi = 0, vo = 0;
+    if (i < n) {
+      vi = act_new[i] && !act_old[i];
+      vo = !act_new[i] && act_old[i];
+    }
+    const unsigned long long mi = __ballot(vi), mo = __ballot(vo);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (lane == 0) {
+      wc[0][w] = __popcll(mi);
+      wc[1][w] = __popcll(mo);
+    }
+    __syncthreads();
+    int bi = off_in, bo = off_out;
+    for (int q = 0; q < w; ++q) {
+      bi += wc[0][q];
+      bo += wc[1][q];
+    }
+    if (vi) F_in[bi + __popcll(mi & below)] = (int32_t)i;
+    if (vo) F_out[bo + __popcll(mo & below)] = (int32_t)i;
+    off_in += wc[0][0] + wc[0][1] + wc[0][2] + wc[0][3];
+    off_out += wc[1][0] + wc[1][1] + wc[1][2] + wc[1][3];
+    __syncthreads();
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int a = 0, b = 0;
+    for (int q = 0; q < nblk; ++q) {
+      a += cnt_in[q];
+      b += cnt_out[q];
+    }
+    sc->n_in = a;
+    sc->n_out = b;
+  }
+}
+
+void launch_flip_lists(const uint8_t* act_new, const uint8_t* act_old, int64_t n, int32_t* cnt_in, int32_t* cnt_out,
+                       int32_t* F_in, int32_t* F_out, NewtonScalars* sc, hipStream_t s) {
+  const int nblk = compact_blocks(n);
+  hipLaunchKernelGGL(k_flip_count, dim3(nblk), dim3(256), 0, s, act_new, act_old, n, cnt_in, cnt_out);
+  SPSVM_LAUNCHED();
+  hipLaunchKernelGGL(k_flip_write, dim3(nblk), dim3(256), 0, s, act_new, act_old, n, cnt_in, cnt_out, nblk, F_in,
+                     F_out, sc);
   SPSVM_LAUNCHED();
 }
 
@@ -409,13 +565,26 @@ __global__ __launch_bounds__(256) void k_ls_pass(const double* __restrict__ o, c
   }
 }
 
-__global__ void k_ls_update(LineState* ls, const double* __restrict__ partial, int nblk, double lam) {
+__global__ __launch_bounds__(256) void k_ls_update(LineState* ls, const double* __restrict__ partial, int nblk,
+                                                   double lam) {
+  __shared__ double red[6][256];
+  if (ls->status != 0) return;
+  {
+    double a[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += 256)
+      for (int k = 0; k < 6; ++k) a[k] += partial[(int64_t)b * 6 + k];
+    for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = a[k];
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {  // fixed-order tree
+    if (threadIdx.x < w)
+      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
   if (threadIdx.x != 0) return;
   LineState s = *ls;
-  if (s.status != 0) return;
-  double v[6] = {0, 0, 0, 0, 0, 0};
-  for (int b = 0; b < nblk; ++b)
-    for (int k = 0; k < 6; ++k) v[k] += partial[(int64_t)b * 6 + k];
+  double v[6];
+  for (int k = 0; k < 6; ++k) v[k] = red[k][0];
   const double P = v[2], Q = v[3], V = v[4], F = v[5];
   const double lc1 = lam * s.c1, lc2 = lam * s.c2;
   bool done = false;
@@ -501,7 +670,7 @@ void launch_ls_round(const double* o, const double* delta, const float* y, int64
   const int64_t rows = ceil_div(n, nblk);
   hipLaunchKernelGGL(k_ls_pass, dim3(nblk), dim3(256), 0, s, o, delta, y, n, rows, ls, partial);
   SPSVM_LAUNCHED();
-  hipLaunchKernelGGL(k_ls_update, dim3(1), dim3(64), 0, s, ls, partial, nblk, lam);
+  hipLaunchKernelGGL(k_ls_update, dim3(1), dim3(256), 0, s, ls, partial, nblk, lam);
   SPSVM_LAUNCHED();
 }
 
@@ -540,7 +709,8 @@ template void launch_gradient<float>(const float*, int64_t, int, const int32_t*,
 template void launch_gradient<double>(const double*, int64_t, int, const int32_t*, int, const double*, const float*,
                                       const double*, const double*, double, double*, int, double*, NewtonScalars*,
                                       hipStream_t);
-template void launch_syrk<float>(const float*, int64_t, int, const int32_t*, int, int, double*, hipStream_t);
-template void launch_syrk<double>(const double*, int64_t, int, const int32_t*, int, int, double*, hipStream_t);
+template void launch_syrk<float>(const float*, int64_t, int, const int32_t*, int, int, int, int, double*, hipStream_t);
+template void launch_syrk<double>(const double*, int64_t, int, const int32_t*, int, int, int, int, double*,
+                                  hipStream_t);
 
 }  // namespace spsvm

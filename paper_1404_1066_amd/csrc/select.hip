@@ -56,24 +56,78 @@ void launch_score_init(const int32_t* cand, const double* o, const uint64_t* has
   SPSVM_LAUNCHED();
 }
 
-// One pass: thread (wave q, lane c) handles slot c on rows lo + q, lo + q + 4, ... of this block's range.
+// Advance one slot after a pass (sums P, Q, V and the flip count F at the slot's current point s).
+__device__ __forceinline__ bool bracket_next(double x, double g, double r, double& lo, double& hi, double& nx,
+                                             int& newton);
+constexpr int kMaxPasses = 64;
+
+__device__ __forceinline__ int advance_slot(CandState& s, double P, double Q, double V, double F, double lam) {
+  s.passes += 1;
+  const double g = lam * (s.oc + s.s) - (P - s.s * Q);
+  bool done = (s.newton && F == 0.0) || g == 0.0;
+  int still = 0;
+  if (!done) {
+    const double r = (P - lam * s.oc) / (lam + Q);
+    double nx;
+    int nw;
+    if (bracket_next(s.s, g, r, s.lo, s.hi, nx, nw) && s.passes < kMaxPasses) {
+      s.s_prev = s.s;
+      s.s = nx;
+      s.newton = nw;
+      still = 1;
+    } else {
+      done = true;  // bracket exhausted or pass cap: keep the current point
+    }
+  }
+  if (done) {
+    s.status = 1;
+    s.score = -(lam * (s.s * s.oc + 0.5 * s.s * s.s) + 0.5 * V);
+  }
+  return still;
+}
+
+// One pass over the rows for every active slot. Thread (wave q, lane c) handles slot c on rows lo + q, lo + q + 4,
+// ... of its workgroup's range, two rows per iteration with separate accumulators; the four waves' sums are
+// added in wave order and written as this workgroup's partial record {P, Q, V, flips} per slot.
 template <typename TK>
 __global__ __launch_bounds__(256) void k_score_pass(const TK* __restrict__ Kc, const float* __restrict__ y,
                                                     const double* __restrict__ o, int64_t n, int64_t rows_per_blk,
-                                                    const CandState* __restrict__ st, double* __restrict__ partial,
-                                                    const NewtonScalars* __restrict__ sc) {
-  if (sc->n_active_sel == 0) return;
+                                                    const CandState* __restrict__ st, double* __restrict__ partial) {
   __shared__ double sh[4][4][kCandSlots];
   const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int status = st[c].status;
+  if (!__any(status == 0)) return;  // every slot is settled (same answer in every wave and workgroup)
   double P = 0.0, Q = 0.0, V = 0.0, F = 0.0;
   if (status == 0) {
     const double s = st[c].s, sp = st[c].s_prev;
     const bool chk = st[c].passes > 0;
     const int64_t lo = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t hi = lo + rows_per_blk < n ? lo + rows_per_blk : n;
-    int fl = 0;
-    for (int64_t i = lo + q; i < hi; i += 4) {
+    double P2 = 0.0, Q2 = 0.0, V2 = 0.0;
+    int fl = 0, fl2 = 0;
+    int64_t i = lo + q;
+    for (; i + 4 < hi; i += 8) {
+      const double y0 = (double)y[i], y1 = (double)y[i + 4];
+      const double a0 = 1.0 - y0 * o[i], a1 = 1.0 - y1 * o[i + 4];
+      const double b0 = y0 * (double)Kc[i * kCandSlots + c], b1 = y1 * (double)Kc[(i + 4) * kCandSlots + c];
+      const double e0 = a0 - s * b0, e1 = a1 - s * b1;
+      if (e0 > 0.0) {
+        P += a0 * b0;
+        Q += b0 * b0;
+      }
+      if (e1 > 0.0) {
+        P2 += a1 * b1;
+        Q2 += b1 * b1;
+      }
+      const double u0 = fmax(a0, 0.0), w0 = fmax(e0, 0.0), u1 = fmax(a1, 0.0), w1 = fmax(e1, 0.0);
+      V += (w0 - u0) * (w0 + u0);
+      V2 += (w1 - u1) * (w1 + u1);
+      if (chk) {
+        fl += ((e0 > 0.0) != (a0 - sp * b0 > 0.0)) ? 1 : 0;
+        fl2 += ((e1 > 0.0) != (a1 - sp * b1 > 0.0)) ? 1 : 0;
+      }
+    }
+    for (; i < hi; i += 4) {
       const double yi = (double)y[i];
       const double a = 1.0 - yi * o[i];
       const double b = yi * (double)Kc[i * kCandSlots + c];
@@ -86,7 +140,10 @@ __global__ __launch_bounds__(256) void k_score_pass(const TK* __restrict__ Kc, c
       V += (w - u) * (w + u);
       if (chk) fl += ((e > 0.0) != (a - sp * b > 0.0)) ? 1 : 0;
     }
-    F = (double)fl;
+    P += P2;
+    Q += Q2;
+    V += V2;
+    F = (double)(fl + fl2);
   }
   sh[q][0][c] = P;
   sh[q][1][c] = Q;
@@ -97,6 +154,35 @@ __global__ __launch_bounds__(256) void k_score_pass(const TK* __restrict__ Kc, c
     double* out = partial + ((int64_t)blockIdx.x * kCandSlots + c) * 4;
 #pragma unroll
     for (int k = 0; k < 4; ++k) out[k] = sh[0][k][c] + sh[1][k][c] + sh[2][k][c] + sh[3][k][c];
+  }
+}
+
+// One workgroup per slot: reduce the slot's partial records over the workgroups of the pass with a fixed
+// tree, then advance the slot.
+__global__ __launch_bounds__(256) void k_score_update(CandState* __restrict__ st, const double* __restrict__ partial,
+                                                      int nblk, double lam) {
+  __shared__ double red[4][256];
+  const int c = blockIdx.x;
+  if (st[c].status != 0) return;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+    const double* p = partial + ((int64_t)b * kCandSlots + c) * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] += p[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    CandState cs = st[c];
+    advance_slot(cs, red[0][0], red[1][0], red[2][0], red[3][0], lam);
+    st[c] = cs;
   }
 }
 
@@ -125,63 +211,21 @@ __device__ __forceinline__ bool bracket_next(double x, double g, double r, doubl
   return nx > lo && nx < hi;
 }
 
-constexpr int kMaxPasses = 64;
-
-// 64 threads: reduce the partials of each active slot in block order and advance it.
-__global__ void k_score_update(CandState* __restrict__ st, const double* __restrict__ partial, int nblk, double lam,
-                               NewtonScalars* sc) {
-  __shared__ int red[1];
-  if (sc->n_active_sel == 0) return;
-  const int c = threadIdx.x;
-  CandState s = st[c];
-  int still = 0;
-  if (s.status == 0) {
-    double P = 0.0, Q = 0.0, V = 0.0, F = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-      const double* p = partial + ((int64_t)b * kCandSlots + c) * 4;
-      P += p[0];
-      Q += p[1];
-      V += p[2];
-      F += p[3];
-    }
-    s.passes += 1;
-    const double g = lam * (s.oc + s.s) - (P - s.s * Q);
-    bool done = (s.newton && F == 0.0) || g == 0.0;
-    if (!done) {
-      const double r = (P - lam * s.oc) / (lam + Q);
-      double nx;
-      int nw;
-      if (bracket_next(s.s, g, r, s.lo, s.hi, nx, nw) && s.passes < kMaxPasses) {
-        s.s_prev = s.s;
-        s.s = nx;
-        s.newton = nw;
-        still = 1;
-      } else {
-        done = true;  // bracket exhausted or pass cap: keep the current point
-      }
-    }
-    if (done) {
-      s.status = 1;
-      s.score = -(lam * (s.s * s.oc + 0.5 * s.s * s.s) + 0.5 * V);
-    }
-    st[c] = s;
-  }
-  const int na = block_sum_int(still, red);
-  if (c == 0) sc->n_active_sel = na;
-}
-
 int score_blocks(int64_t n) {
-  int64_t b = ceil_div(n, 512);
+  int64_t b = ceil_div(n, 128);
   return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
 }
 
 template <typename TK>
-void launch_score_round(const TK* Kc, const float* y, const double* o, int64_t n, double lam, CandState* st,
-                        double* partial, int nblk, NewtonScalars* sc, hipStream_t s) {
+void launch_score_pass(const TK* Kc, const float* y, const double* o, int64_t n, const CandState* st,
+                       double* partial, int nblk, hipStream_t s) {
   const int64_t rows = round_up(ceil_div(n, nblk), 4);
-  hipLaunchKernelGGL((k_score_pass<TK>), dim3(nblk), dim3(256), 0, s, Kc, y, o, n, rows, st, partial, sc);
+  hipLaunchKernelGGL((k_score_pass<TK>), dim3(nblk), dim3(256), 0, s, Kc, y, o, n, rows, st, partial);
   SPSVM_LAUNCHED();
-  hipLaunchKernelGGL(k_score_update, dim3(1), dim3(kCandSlots), 0, s, st, partial, nblk, lam, sc);
+}
+
+void launch_score_update(CandState* st, const double* partial, int nblk, double lam, hipStream_t s) {
+  hipLaunchKernelGGL(k_score_update, dim3(kCandSlots), dim3(256), 0, s, st, partial, nblk, lam);
   SPSVM_LAUNCHED();
 }
 
@@ -189,10 +233,11 @@ void launch_score_round(const TK* Kc, const float* y, const double* o, int64_t n
 // then append the winner to J and beta.
 __global__ void k_select(const CandState* __restrict__ st, const uint64_t* __restrict__ hash,
                          uint64_t* __restrict__ stage_hash, int q, int64_t* __restrict__ J, double* __restrict__ beta,
-                         int32_t* __restrict__ m_dev, Selection* __restrict__ sel) {
+                         int32_t* __restrict__ m_dev, Selection* __restrict__ sel, int32_t* __restrict__ incomplete) {
   const int c = threadIdx.x;
   const CandState s = st[c];
-  const bool ok = s.status == 1 && s.idx >= 0 && !(s.score != s.score);
+  const int pending = __any(s.status == 0);  // a slot still being scored: this step must be redone
+  const bool ok = !pending && s.status == 1 && s.idx >= 0 && !(s.score != s.score);
   double best = ok ? s.score : -__builtin_huge_val();
   int bidx = ok ? s.idx : 0x7fffffff;
   int bslot = c;
@@ -207,6 +252,7 @@ __global__ void k_select(const CandState* __restrict__ st, const uint64_t* __res
     }
   }
   if (c == 0) {
+    if (pending) *incomplete = 1;
     Selection r;
     r.valid = bidx != 0x7fffffff;
     r.slot = bslot;
@@ -241,23 +287,24 @@ __global__ __launch_bounds__(256) void k_append(const Selection* __restrict__ se
 template <typename TK>
 void launch_select_append(const CandState* st, const uint64_t* hash, uint64_t* stage_hash, int q, const TK* Kc,
                           int64_t n, double* o, TK* KXJ, int64_t ldk, int64_t* J, double* beta, int32_t* m_dev,
-                          Selection* sel, hipStream_t s) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(kCandSlots), 0, s, st, hash, stage_hash, q, J, beta, m_dev, sel);
+                          Selection* sel, int32_t* incomplete, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(kCandSlots), 0, s, st, hash, stage_hash, q, J, beta, m_dev, sel,
+                     incomplete);
   SPSVM_LAUNCHED();
   const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), 2048);
   hipLaunchKernelGGL((k_append<TK>), dim3((unsigned)blocks), dim3(256), 0, s, sel, Kc, n, o, KXJ, ldk);
   SPSVM_LAUNCHED();
 }
 
-template void launch_score_round<float>(const float*, const float*, const double*, int64_t, double, CandState*,
-                                        double*, int, NewtonScalars*, hipStream_t);
-template void launch_score_round<double>(const double*, const float*, const double*, int64_t, double, CandState*,
-                                         double*, int, NewtonScalars*, hipStream_t);
+template void launch_score_pass<float>(const float*, const float*, const double*, int64_t, const CandState*, double*,
+                                       int, hipStream_t);
+template void launch_score_pass<double>(const double*, const float*, const double*, int64_t, const CandState*,
+                                        double*, int, hipStream_t);
 template void launch_select_append<float>(const CandState*, const uint64_t*, uint64_t*, int, const float*, int64_t,
-                                          double*, float*, int64_t, int64_t*, double*, int32_t*, Selection*,
+                                          double*, float*, int64_t, int64_t*, double*, int32_t*, Selection*, int32_t*,
                                           hipStream_t);
 template void launch_select_append<double>(const CandState*, const uint64_t*, uint64_t*, int, const double*, int64_t,
                                            double*, double*, int64_t, int64_t*, double*, int32_t*, Selection*,
-                                           hipStream_t);
+                                           int32_t*, hipStream_t);
 
 }  // namespace spsvm

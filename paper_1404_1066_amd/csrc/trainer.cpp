@@ -107,6 +107,14 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.vJ = take(J_max * 8);
   p.wJ = take(J_max * 8);
   p.iota = take(J_max * 4);
+  p.ticket = take(4);
+  p.incomplete = take(4);
+  p.o_stage = take(with_selection ? n * 8 : 0);
+  p.Hf = take((size_t)J_max * p.ldh * 8);
+  p.F_in = take(n * 4);
+  p.F_out = take(n * 4);
+  p.fcnt_in = take(nb_c * 4);
+  p.fcnt_out = take(nb_c * 4);
   p.bytes = off;
   return p;
 }
@@ -126,6 +134,69 @@ using clk = std::chrono::steady_clock;
 constexpr size_t kPinnedScalars = 16384;  // bytes of pinned memory for scalar read-backs
 static double secs(clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); }
 
+// HIP-event timing of selected kernels on the training stream. Pairs of events bracket each timed launch;
+// elapsed times are collected after the stream has been synchronised.
+struct Profiler {
+  hipStream_t st = nullptr;
+  int mask = 0;
+  struct Pending {
+    hipEvent_t a, b;
+    int cat;
+    double work;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pending> pending;
+  double seconds[4] = {0, 0, 0, 0}, work[4] = {0, 0, 0, 0};
+  int64_t count[4] = {0, 0, 0, 0};
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    SPSVM_HIP(hipEventCreate(&e));
+    return e;
+  }
+  template <class F>
+  void timed(int cat, double w, F&& launch) {
+    if (!(mask & (1 << cat))) {
+      launch();
+      return;
+    }
+    hipEvent_t a = get(), b = get();
+    SPSVM_HIP(hipEventRecord(a, st));
+    launch();
+    SPSVM_HIP(hipEventRecord(b, st));
+    pending.push_back({a, b, cat, w});
+    if (pending.size() >= 2048) {
+      SPSVM_HIP(hipStreamSynchronize(st));
+      flush();
+    }
+  }
+  void flush() {  // the stream must have been synchronised
+    for (const Pending& p : pending) {
+      float ms = 0.f;
+      SPSVM_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+      seconds[p.cat] += 1e-3 * ms;
+      work[p.cat] += p.work;
+      count[p.cat] += 1;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  ~Profiler() {
+    for (const Pending& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+enum { kProfKblock = 0, kProfSyrk = 1, kProfScore = 2, kProfChol = 3 };
+
 template <typename TX, typename TK>
 struct Impl {
   const TX* X;
@@ -138,12 +209,16 @@ struct Impl {
   char* base;
   Pinned pin;
   spsvm_stats stats{};
+  Profiler prof;
 
   TK *xnorm, *KXJ, *Kc;
   uint64_t *hash, *stage_hash;
   double *o, *delta, *beta, *dvec, *g, *z, *H, *Linv, *syrk_part, *grad_part, *score_part, *ls_part, *cblk_sum;
-  double *XJ64, *xjnorm, *KJJ, *vJ, *wJ;
-  int32_t* iota;
+  double *XJ64, *xjnorm, *KJJ, *vJ, *wJ, *o_stage, *Hf;
+  int32_t *iota, *incomplete, *F_in, *F_out, *fcnt_in, *fcnt_out;
+  bool hb_valid = false;  // H (unfactored) holds lambda K_JJ + K_I^T K_I for the first m_fact basis vectors and
+  int m_fact = 0;         // the violator status in act_fact
+  unsigned int* ticket;
   uint8_t *act_fact, *act_cur;
   int32_t *I, *cblk_cnt, *cblk_flips, *cand_table, *m_dev, *flags, *J32;
   int64_t* J;
@@ -162,6 +237,8 @@ struct Impl {
        void* ws, hipStream_t s, const Plan& plan)
       : X(X_), y(y_), n(n_), d(d_), J_max(Jm), C(C_), gamma(g_), lam(1.0 / C_), opt(o_), st(s), p(plan),
         base((char*)ws), pin(kPinnedScalars + (size_t)o_.chunk_cap * kCandSlots * 4) {
+    prof.st = s;
+    prof.mask = o_.profile;
     xnorm = at<TK>(p.xnorm);
     KXJ = at<TK>(p.KXJ);
     Kc = at<TK>(p.Kc);
@@ -200,6 +277,14 @@ struct Impl {
     vJ = at<double>(p.vJ);
     wJ = at<double>(p.wJ);
     iota = at<int32_t>(p.iota);
+    ticket = at<unsigned int>(p.ticket);
+    incomplete = at<int32_t>(p.incomplete);
+    o_stage = at<double>(p.o_stage);
+    Hf = at<double>(p.Hf);
+    F_in = at<int32_t>(p.F_in);
+    F_out = at<int32_t>(p.F_out);
+    fcnt_in = at<int32_t>(p.fcnt_in);
+    fcnt_out = at<int32_t>(p.fcnt_out);
   }
 
   // Basis rows m0..m1 of J gathered into XJ64 (FP64), then the FP64 kernel matrix K_JJ of the first m1 rows.
@@ -210,7 +295,10 @@ struct Impl {
     launch_kblock<double, double>(XJ64, m1, d, xjnorm, iota, m1, KJJ, p.ldh, gamma, st);
   }
 
-  void sync() { SPSVM_HIP(hipStreamSynchronize(st)); }
+  void sync() {
+    SPSVM_HIP(hipStreamSynchronize(st));
+    prof.flush();
+  }
 
   template <typename T>
   T read(const T* dev) {
@@ -253,7 +341,7 @@ struct Impl {
     double g0 = 0.0;
     int it = 0;
     for (; it < opt.newton_max_iter; ++it) {
-      launch_compact(o, y, n, fact_valid ? act_fact : nullptr, act_cur, I, cblk_cnt, cblk_sum, cblk_flips, sc, st);
+      launch_compact(o, y, n, hb_valid ? act_fact : nullptr, act_cur, I, cblk_cnt, cblk_sum, cblk_flips, sc, st);
       NewtonScalars s = read(sc);
       const int nchunk = gradient_chunks(m, s.n_sv);
       launch_gemv<double>(KJJ, p.ldh, m, m, beta, vJ, st);
@@ -268,12 +356,12 @@ struct Impl {
         std::fprintf(stderr, "[spsvm]   newton it=%d m=%d f=%.15e |g|=%.3e n_sv=%d flips=%d\n", it, m, f, gn, s.n_sv,
                      s.flips);
       if (gn <= opt.newton_tol * std::max(1.0, g0)) break;
-      if (!fact_valid || s.flips > 0) {
+      if (!fact_valid || s.flips > opt.refactor_frac * std::max(1, s.n_sv)) {
         factorize(m, s.n_sv);
         fact_valid = true;
         std::swap(act_fact, act_cur);
       }
-      launch_chol_solve(H, p.ldh, m, Linv, g, dvec, z, st);
+      launch_chol_solve(Hf, p.ldh, m, Linv, g, dvec, z, st);
       launch_gemv<TK>(KXJ, p.ldk, n, m, dvec, delta, st);
       launch_gemv<double>(KJJ, p.ldh, m, m, dvec, wJ, st);
       launch_c1c2(beta, dvec, wJ, m, ls, st);
@@ -302,22 +390,62 @@ struct Impl {
     return it;
   }
 
+  // Forms H = lambda K_JJ + K_I^T K_I for the current basis (m) and violator status (act_cur), then factors a
+  // copy. Tile rows of H that already existed at the last factorisation are updated with the rows that joined
+  // or left the violator set (exact FP64 products, so the update loses nothing); the remaining tile rows are
+  // recomputed over all violators. A full recomputation is chosen when it is cheaper.
   void factorize(int m, int n_sv) {
-    const int nsplit = syrk_splits(m, n_sv);
-    launch_syrk<TK>(KXJ, p.ldk, m, I, n_sv, nsplit, syrk_part, st);
-    launch_syrk_reduce(KJJ, m, lam, syrk_part, nsplit, 0.0, H, p.ldh, st);
+    const int B = syrk_tile_size();
+    const int T = syrk_tile_rows(m), ntile = T * (T + 1) / 2;
+    int tr0 = 0, n_in = 0, n_out = 0;
+    if (hb_valid) {
+      launch_flip_lists(act_cur, act_fact, n, fcnt_in, fcnt_out, F_in, F_out, sc, st);
+      const NewtonScalars s = read(sc);
+      n_in = s.n_in;
+      n_out = s.n_out;
+      const int t0 = m_fact / B;
+      const double r0 = (double)t0 * B;
+      const double cost_inc = (double)(n_in + n_out) * r0 * r0 + (double)n_sv * ((double)m * m - r0 * r0);
+      const double cost_full = (double)n_sv * m * m;
+      if (cost_inc < 0.8 * cost_full) tr0 = t0;
+    }
+    const int t_old = tr0 * (tr0 + 1) / 2;
+    const double r0 = (double)tr0 * B;
+    auto syrk_part = [&](const int32_t* rows, int nrows, int lo, int hi, int mode, double work) {
+      if (nrows <= 0 || hi <= lo) return;
+      const int ns = syrk_splits(hi - lo, nrows);
+      prof.timed(kProfSyrk, work, [&] { launch_syrk<TK>(KXJ, p.ldk, m, rows, nrows, lo, hi, ns, this->syrk_part, st); });
+      launch_syrk_reduce(KJJ, m, lam, this->syrk_part, ns, lo, hi, mode, H, p.ldh, st);
+    };
+    if (tr0 > 0) {
+      syrk_part(F_in, n_in, 0, t_old, +1, (double)n_in * r0 * (r0 + 1.0));
+      syrk_part(F_out, n_out, 0, t_old, -1, (double)n_out * r0 * (r0 + 1.0));
+      stats.incremental_factorizations += 1;
+    }
+    if (t_old < ntile) {
+      if (n_sv > 0) {
+        syrk_part(I, n_sv, t_old, ntile, 0, (double)n_sv * ((double)m * (m + 1.0) - r0 * (r0 + 1.0)));
+      } else {  // no violators: H = lambda K_JJ on the recomputed tiles
+        launch_syrk<TK>(KXJ, p.ldk, m, I, 0, t_old, ntile, 1, this->syrk_part, st);
+        launch_syrk_reduce(KJJ, m, lam, this->syrk_part, 1, t_old, ntile, 0, H, p.ldh, st);
+      }
+    }
+    hb_valid = true;
+    m_fact = m;
+    // factor a copy of H (H itself is kept for the next update)
+    SPSVM_HIP(hipMemcpyAsync(Hf, H, (size_t)m * p.ldh * 8, hipMemcpyDeviceToDevice, st));
     SPSVM_HIP(hipMemsetAsync(&sc->fail, 0, 4, st));
-    launch_cholesky(H, p.ldh, m, Linv, sc, st);
+    prof.timed(kProfChol, (double)m * m * m / 3.0, [&] { launch_cholesky(Hf, p.ldh, m, Linv, sc, st); });
     stats.factorizations += 1;
     if (read(&sc->fail) == 0) return;
     // jitter retries: H + mu * mean(diag H) * I
-    launch_syrk_reduce(KJJ, m, lam, syrk_part, nsplit, 0.0, H, p.ldh, st);
     launch_trace(H, p.ldh, m, sc, st);
     const double mean_diag = read(&sc->trace) / m;
     for (double mu : {1e-14, 1e-12, 1e-10, 1e-8}) {
-      launch_syrk_reduce(KJJ, m, lam, syrk_part, nsplit, mu * mean_diag, H, p.ldh, st);
+      SPSVM_HIP(hipMemcpyAsync(Hf, H, (size_t)m * p.ldh * 8, hipMemcpyDeviceToDevice, st));
+      launch_add_diag(Hf, p.ldh, m, mu * mean_diag, st);
       SPSVM_HIP(hipMemsetAsync(&sc->fail, 0, 4, st));
-      launch_cholesky(H, p.ldh, m, Linv, sc, st);
+      launch_cholesky(Hf, p.ldh, m, Linv, sc, st);
       stats.factorizations += 1;
       if (read(&sc->fail) == 0) return;
     }
@@ -348,6 +476,7 @@ struct Impl {
     std::vector<int32_t> table((size_t)opt.chunk_cap * kCandSlots);
     SPSVM_HIP(hipMemsetAsync(o, 0, n * 8, st));
     SPSVM_HIP(hipMemsetAsync(m_dev, 0, 4, st));
+    SPSVM_HIP(hipMemsetAsync(ticket, 0, 4, st));
     const int nblk = score_blocks(n);
     while (m < J_max) {
       const auto t0 = clk::now();
@@ -356,18 +485,36 @@ struct Impl {
       int32_t* tp = (int32_t*)((char*)pin.p + kPinnedScalars);
       std::memcpy(tp, table.data(), (size_t)cs * kCandSlots * 4);
       SPSVM_HIP(hipMemcpyAsync(cand_table, tp, (size_t)cs * kCandSlots * 4, hipMemcpyHostToDevice, st));
-      for (int q = 0; q < cs; ++q) {
-        const int32_t* cq = cand_table + (size_t)q * kCandSlots;
-        launch_kblock<TX, TK>(X, n, d, xnorm, cq, kCandSlots, Kc, kCandSlots, gamma, st);
-        launch_score_init(cq, o, hash, stage_hash, q, cst, sc, st);
-        int rounds = 0;
-        for (;;) {
-          for (int r = 0; r < 4; ++r) launch_score_round<TK>(Kc, y, o, n, lam, cst, score_part, nblk, sc, st);
-          rounds += 4;
-          if (rounds >= 64 || read(&sc->n_active_sel) == 0) break;
+      // One attempt runs every step of the stage without host synchronisation. A step whose slots did not all
+      // converge within the launched passes selects nothing and flags the stage, which is then rerun from its
+      // saved start state with more passes (64 passes always suffice: the update stops every slot by then).
+      SPSVM_HIP(hipMemcpyAsync(o_stage, o, n * 8, hipMemcpyDeviceToDevice, st));
+      for (int attempt = 0;; ++attempt) {
+        const int rounds = attempt == 0 ? 4 : (attempt == 1 ? 12 : 64);
+        if (attempt > 0) {
+          SPSVM_HIP(hipMemcpyAsync(o, o_stage, n * 8, hipMemcpyDeviceToDevice, st));
+          int32_t* mh = (int32_t*)((char*)pin.p + 8192);
+          *mh = m;
+          SPSVM_HIP(hipMemcpyAsync(m_dev, mh, 4, hipMemcpyHostToDevice, st));
+          stats.stage_redos += 1;
         }
-        stats.score_passes += rounds;
-        launch_select_append<TK>(cst, hash, stage_hash, q, Kc, n, o, KXJ, p.ldk, J, beta, m_dev, sel, st);
+        SPSVM_HIP(hipMemsetAsync(incomplete, 0, 4, st));
+        for (int q = 0; q < cs; ++q) {
+          const int32_t* cq = cand_table + (size_t)q * kCandSlots;
+          int ncand = 0;
+          for (int c = 0; c < kCandSlots; ++c) ncand += table[(size_t)q * kCandSlots + c] >= 0;
+          prof.timed(kProfKblock, 2.0 * n * ncand * d,
+                     [&] { launch_kblock<TX, TK>(X, n, d, xnorm, cq, kCandSlots, Kc, kCandSlots, gamma, st); });
+          launch_score_init(cq, o, hash, stage_hash, q, cst, sc, st);
+          for (int r = 0; r < rounds; ++r) {
+            prof.timed(kProfScore, (double)n * (opt.kappa * sizeof(TK) + 12.0),
+                       [&] { launch_score_pass<TK>(Kc, y, o, n, cst, score_part, nblk, st); });
+            launch_score_update(cst, score_part, nblk, lam, st);
+          }
+          stats.score_passes += rounds;
+          launch_select_append<TK>(cst, hash, stage_hash, q, Kc, n, o, KXJ, p.ldk, J, beta, m_dev, sel, incomplete, st);
+        }
+        if (read(incomplete) == 0 || rounds >= 64) break;
       }
       t += cs;
       const int m_new = read(m_dev);
@@ -408,7 +555,8 @@ struct Impl {
     SPSVM_HIP(hipMemcpyAsync(J, Jh, m * 8, hipMemcpyHostToDevice, st));
     SPSVM_HIP(hipMemcpyAsync(J32, j32.data(), m * 4, hipMemcpyHostToDevice, st));
     const auto t0 = clk::now();
-    launch_kblock<TX, TK>(X, n, d, xnorm, J32, (int)m, KXJ, p.ldk, gamma, st);
+    prof.timed(kProfKblock, 2.0 * n * m * d,
+               [&] { launch_kblock<TX, TK>(X, n, d, xnorm, J32, (int)m, KXJ, p.ldk, gamma, st); });
     update_basis(0, (int)m);
     SPSVM_HIP(hipMemsetAsync(beta, 0, m * 8, st));
     sync();
@@ -426,6 +574,19 @@ struct Impl {
     final_eval(m, &F, &s);
     stats.n_sv = s.n_sv;
     stats.grad_norm = std::sqrt(s.gnorm2);
+    sync();
+    stats.kblock_launches = prof.count[kProfKblock];
+    stats.kblock_seconds = prof.seconds[kProfKblock];
+    stats.kblock_flops = prof.work[kProfKblock];
+    stats.syrk_launches = prof.count[kProfSyrk];
+    stats.syrk_seconds = prof.seconds[kProfSyrk];
+    stats.syrk_flops = prof.work[kProfSyrk];
+    stats.score_launches = prof.count[kProfScore];
+    stats.score_seconds = prof.seconds[kProfScore];
+    stats.score_bytes = prof.work[kProfScore];
+    stats.chol_calls = prof.count[kProfChol];
+    stats.chol_seconds = prof.seconds[kProfChol];
+    stats.chol_flops = prof.work[kProfChol];
     auto* md = new spsvm_model();
     try {
       md->m = m;

@@ -36,7 +36,7 @@ struct Plan {
   // offsets into the workspace
   size_t xnorm, hash, KXJ, Kc, o, delta, act0, act1, I, cblk_cnt, cblk_sum, cblk_flips, J, J32, beta, dvec, g, z,
       H, Linv, syrk_part, grad_part, cand_state, sel, ls, scalars, score_part, ls_part, cand_table, stage_hash, m_dev,
-      flags, XJ64, xjnorm, KJJ, vJ, wJ, iota;
+      flags, XJ64, xjnorm, KJJ, vJ, wJ, iota, ticket, incomplete, o_stage, Hf, F_in, F_out, fcnt_in, fcnt_out;
 };
 
 Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection);

@@ -80,6 +80,22 @@ def test_greedy_f32_ragged_matches_oracle_at_gpu_basis():
     assert _decision_err(dg, do) <= 1e-4
 
 
+@pytest.mark.parametrize("refactor_frac", [0.0, 0.05])
+def test_newton_matrix_reuse_and_updates_keep_parity(refactor_frac):
+    """Refactorising at every change of the violator set (0.0) or reusing the factor until 5% of it changed
+    must both reach the oracle's optimum at the GPU's basis."""
+    X, y = datagen.make_blobs(6000, 10, seed=31, dtype=np.float32)
+    C, gamma, m = 4.0, 0.1, 300
+    Xg, yg = _dev(X, y)
+    model = lib.train(Xg, yg, C, gamma, m, seed=2, refactor_frac=refactor_frac)
+    J, beta, F = model.get()
+    st = model.stats()
+    assert st["incremental_factorizations"] > 0
+    b_or, F_or, _ = osp.solve_fixed_J(X, y, C, gamma, J)
+    Fo = osp.objective_at(X, y, C, gamma, J, beta)
+    assert (Fo - F_or) / F_or <= 1e-6
+
+
 def test_training_is_deterministic():
     X, y = datagen.make_blobs(4000, 12, seed=21, dtype=np.float32)
     Xg, yg = _dev(X, y)
