@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=12)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison runs")
     return ap.parse_args()
 
 
@@ -89,7 +90,7 @@ def main():
     dt = torch.float64 if args.precision == "f64" else torch.float32
     Xg = torch.tensor(p.X, dtype=dt, device="cuda")
     yg = torch.tensor(p.y, dtype=torch.float32, device="cuda")
-    ws = torch.empty(lib.workspace_bytes(n, d, p.J_max, precision=args.precision), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(lib.workspace_bytes(n, d, p.J_max, dtype=dt, precision=args.precision), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     common = dict(precision=args.precision, workspace=ws, stream=stream)
 
@@ -143,6 +144,19 @@ def main():
                                                         "seconds_newton")},
     }
 
+    # the same runs with split-BF16 distances (SPSVM_MIXED), for the "mixed vs FP32" part of the metric
+    mixed_models = []
+    if not args.no_mixed and args.precision == "f32":
+        mcommon = dict(common, precision="mixed")
+        lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=1000, **mcommon)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for k in range(args.steps):
+            mixed_models.append(lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=k, **mcommon))
+        torch.cuda.synchronize()
+        per_mixed = (time.perf_counter() - t3) / args.steps
+        out["mixed"] = {"value": round(per_mixed, 6), "unit": "s", "ratio_fp32_over_mixed": round(per_run / per_mixed, 4)}
+
     J, beta, F = models[0].get()
     if not args.no_parity or not args.no_cpu_baseline:
         from oracle import spsvm as osp
@@ -160,6 +174,12 @@ def main():
         rel = (Fo - F_or) / F_or
         out["parity"] = {"objective_rel": rel, "objective_ok": bool(rel <= 1e-6), "decision_max_rel": derr,
                          "decision_ok": bool(derr <= 1e-4), "F_gpu": Fo, "F_oracle": F_or, "m": int(len(J))}
+        if mixed_models:
+            Jm, bm, _ = mixed_models[0].get()
+            _, F_orm, _ = osp.solve_fixed_J(p.X, p.y, p.C, p.gamma, Jm) if not np.array_equal(Jm, J) else (None, F_or, None)
+            Fm = osp.objective_at(p.X, p.y, p.C, p.gamma, Jm, bm)
+            out["mixed"]["objective_rel"] = (Fm - F_orm) / F_orm
+            out["mixed"]["objective_ok"] = bool((Fm - F_orm) / F_orm <= 1e-6)
     else:
         newton_oracle_s = None
 

@@ -112,11 +112,13 @@ typedef struct {
 /* Fills *opt with the defaults listed above. */
 void spsvm_options_default(spsvm_options* opt);
 
-/* Bytes of device workspace spsvm_train needs for n rows, d features and up to J_max basis vectors
- * with these options (NULL = defaults). The sizes of the kernel block n x J_max and the
- * candidate block n x 64 dominate. */
-spsvm_status spsvm_train_workspace_bytes(int64_t n, int64_t d, int64_t J_max, const spsvm_options* opt,
-                                         size_t* bytes);
+/* Bytes of device workspace spsvm_train needs for n rows, d features of type xdt and up to J_max basis
+ * vectors with these options (NULL = defaults). The kernel block n x J_max and the candidate block n x 64
+ * dominate. When d is not a multiple of 4 (FP32) or 2 (FP64) the workspace also holds a copy of X with
+ * padded rows. The figure assumes X starts on a 16-byte boundary (otherwise training needs the padded
+ * copy too and reports SPSVM_E_WORKSPACE). */
+spsvm_status spsvm_train_workspace_bytes(int64_t n, int64_t d, int64_t J_max, spsvm_dtype xdt,
+                                         const spsvm_options* opt, size_t* bytes);
 
 /* Greedy SP-SVM training (section 4, Eq. 4): grows J to J_max rows and returns J and beta.
  *  X:   device, n x d, element type xdt, finite values.
@@ -133,8 +135,8 @@ spsvm_status spsvm_train(const void* X, spsvm_dtype xdt, const float* y, int64_t
                          double gamma, int64_t J_max, const spsvm_options* opt, void* workspace,
                          size_t ws_bytes, void* stream, spsvm_model** out);
 
-/* Bytes of device workspace spsvm_train_fixed_basis needs (m basis vectors). */
-spsvm_status spsvm_fixed_workspace_bytes(int64_t n, int64_t d, int64_t m, const spsvm_options* opt,
+/* Bytes of device workspace spsvm_train_fixed_basis needs (m basis vectors); as above. */
+spsvm_status spsvm_fixed_workspace_bytes(int64_t n, int64_t d, int64_t m, spsvm_dtype xdt, const spsvm_options* opt,
                                          size_t* bytes);
 
 /* Newton re-optimisation of Eq. 4 on a given basis (no selection): computes the kernel block
@@ -145,6 +147,23 @@ spsvm_status spsvm_train_fixed_basis(const void* X, spsvm_dtype xdt, const float
                                      double C, double gamma, const int64_t* J, int64_t m,
                                      const spsvm_options* opt, void* workspace, size_t ws_bytes, void* stream,
                                      spsvm_model** out);
+
+/* Bytes of device workspace spsvm_train_batch needs (m shared basis vectors); as above. */
+spsvm_status spsvm_batch_workspace_bytes(int64_t n, int64_t d, int64_t m, spsvm_dtype xdt, const spsvm_options* opt,
+                                         size_t* bytes);
+
+/* P independent Newton re-optimisations of Eq. 4 that share X and one basis J (e.g. one-vs-rest classes
+ * crossed with a (C, gamma) grid). Problem p has labels Y + p n, C[p] and gamma[p]. The squared distances
+ * between all rows and the basis rows are computed once; the kernel block exp(-gamma D) once per distinct
+ * gamma; each problem then runs the Newton solve from beta = 0. Model p equals what
+ * spsvm_train_fixed_basis returns for problem p (same kernels, same arithmetic).
+ *  Y: device, P x n labels (+1 / -1). C, gamma: host, P values each, finite and > 0.
+ *  J: host, m row indices, rows pairwise distinct in value. out: host array of P model pointers; on
+ *  failure every entry is NULL. Other arguments as for spsvm_train. */
+spsvm_status spsvm_train_batch(const void* X, spsvm_dtype xdt, int64_t n, int64_t d, int64_t P, const float* Y,
+                               const double* C, const double* gamma, const int64_t* J, int64_t m,
+                               const spsvm_options* opt, void* workspace, size_t ws_bytes, void* stream,
+                               spsvm_model** out);
 
 /* Reads a model. Any output pointer may be NULL.
  *  m: number of basis vectors. J_idx: host, capacity >= m, receives the training-row indices of J in
@@ -159,7 +178,9 @@ spsvm_status spsvm_model_stats(const spsvm_model* model, spsvm_stats* stats);
 /* Decision values out[i] = sum_k beta_k exp(-gamma ||xt_i - x_{J_k}||^2) (the classifier of Eq. 4
  * without bias), evaluated in the model's precision with FP64 accumulation.
  *  Xt: device, n_t x d, element type xdt. out: device, n_t doubles. The n_t x m kernel block is never
- *  stored. The model keeps its own copy of X_J, so the training X need not be alive. */
+ *  stored. The model keeps its own copy of X_J, so the training X need not be alive. When d is not a
+ *  multiple of 4 (FP32) or 2 (FP64), or Xt is not 16-byte aligned, a padded copy of Xt is allocated for
+ *  the call and freed before it returns. */
 spsvm_status spsvm_predict(const spsvm_model* model, const void* Xt, spsvm_dtype xdt, int64_t n_t, double* out,
                            void* stream);
 

@@ -17,12 +17,17 @@ extern "C" {
  *   out[i * ldo + c] = exp(-gamma ||x_i - x_{idx[c]}||^2),  0 <= i < n, 0 <= c < ncols,
  * with squared distances |x_i|^2 + |x_j|^2 - 2 x_i . x_j clamped at 0, dot products on MFMA.
  *  X: device n x d (xdt). idx: device, ncols int32 row indices in [0, n) (a negative index leaves that
- *  column untouched). precision: SPSVM_F64 (out is double) or SPSVM_F32 (out is float).
- *  out: device, n rows of leading dimension ldo >= ncols. workspace: device, >= n * 8 bytes, receives
- *  the row norms. */
+ *  column untouched). precision: SPSVM_F64 (out is double), SPSVM_F32 (out is float, FP32 products) or
+ *  SPSVM_MIXED (out is float, split-BF16 products hi.hi' + hi.lo' + lo.hi' accumulated in FP32).
+ *  out: device, n rows of leading dimension ldo >= ncols. workspace: device, 256-byte aligned, at least
+ *  spsvm_rbf_block_workspace_bytes(n, d, xdt) bytes (row norms, and a padded copy of X when d is not a
+ *  multiple of 4 for FP32 / 2 for FP64 or X is not 16-byte aligned). */
 spsvm_status spsvm_rbf_block(const void* X, spsvm_dtype xdt, int64_t n, int64_t d, const int32_t* idx, int64_t ncols,
                              spsvm_precision precision, double gamma, void* out, int64_t ldo, void* workspace,
                              size_t ws_bytes, void* stream);
+
+/* Bytes of device workspace spsvm_rbf_block needs. */
+spsvm_status spsvm_rbf_block_workspace_bytes(int64_t n, int64_t d, spsvm_dtype xdt, size_t* bytes);
 
 /* Bytes of device workspace spsvm_newton_solve needs for an m x m system. */
 spsvm_status spsvm_newton_solve_workspace_bytes(int64_t m, size_t* bytes);

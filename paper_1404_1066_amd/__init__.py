@@ -11,6 +11,7 @@ from .binding import (  # noqa: F401
     options,
     train,
     train_fixed_basis,
+    train_batch,
     rbf_block,
     newton_solve,
     candidate_draw,

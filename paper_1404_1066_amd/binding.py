@@ -26,6 +26,8 @@ EXPORTED = (
     "spsvm_fixed_workspace_bytes",
     "spsvm_train",
     "spsvm_train_fixed_basis",
+    "spsvm_batch_workspace_bytes",
+    "spsvm_train_batch",
     "spsvm_model_get",
     "spsvm_model_stats",
     "spsvm_predict",
@@ -33,6 +35,7 @@ EXPORTED = (
     "spsvm_status_string",
     "spsvm_last_error",
     "spsvm_rbf_block",
+    "spsvm_rbf_block_workspace_bytes",
     "spsvm_newton_solve_workspace_bytes",
     "spsvm_newton_solve",
     "spsvm_candidate_draw",
@@ -109,11 +112,15 @@ def load(path: str = LIB_PATH):
     P, I64, D, VP = ctypes.POINTER, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
     lib.spsvm_options_default.argtypes = [P(Options)]
     lib.spsvm_options_default.restype = None
-    lib.spsvm_train_workspace_bytes.argtypes = [I64, I64, I64, P(Options), P(ctypes.c_size_t)]
-    lib.spsvm_fixed_workspace_bytes.argtypes = [I64, I64, I64, P(Options), P(ctypes.c_size_t)]
+    lib.spsvm_train_workspace_bytes.argtypes = [I64, I64, I64, ctypes.c_int, P(Options), P(ctypes.c_size_t)]
+    lib.spsvm_fixed_workspace_bytes.argtypes = [I64, I64, I64, ctypes.c_int, P(Options), P(ctypes.c_size_t)]
+    lib.spsvm_rbf_block_workspace_bytes.argtypes = [I64, I64, ctypes.c_int, P(ctypes.c_size_t)]
     lib.spsvm_train.argtypes = [VP, ctypes.c_int, VP, I64, I64, D, D, I64, P(Options), VP, ctypes.c_size_t, VP, P(VP)]
     lib.spsvm_train_fixed_basis.argtypes = [VP, ctypes.c_int, VP, I64, I64, D, D, P(I64), I64, P(Options), VP,
                                             ctypes.c_size_t, VP, P(VP)]
+    lib.spsvm_batch_workspace_bytes.argtypes = [I64, I64, I64, ctypes.c_int, P(Options), P(ctypes.c_size_t)]
+    lib.spsvm_train_batch.argtypes = [VP, ctypes.c_int, I64, I64, I64, VP, P(D), P(D), P(I64), I64, P(Options), VP,
+                                      ctypes.c_size_t, VP, P(VP)]
     lib.spsvm_model_get.argtypes = [VP, P(I64), P(I64), P(D), P(D)]
     lib.spsvm_model_stats.argtypes = [VP, P(Stats)]
     lib.spsvm_predict.argtypes = [VP, VP, ctypes.c_int, I64, VP, VP]
@@ -128,9 +135,9 @@ def load(path: str = LIB_PATH):
     lib.spsvm_newton_solve_workspace_bytes.argtypes = [I64, P(ctypes.c_size_t)]
     lib.spsvm_newton_solve.argtypes = [VP, I64, I64, VP, VP, VP, ctypes.c_size_t, VP]
     lib.spsvm_candidate_draw.argtypes = [ctypes.c_uint64, I64, I64, ctypes.c_int32, P(ctypes.c_int32)]
-    for name in ("spsvm_candidate_draw", "spsvm_rbf_block", "spsvm_newton_solve_workspace_bytes", "spsvm_newton_solve",
+    for name in ("spsvm_candidate_draw", "spsvm_rbf_block", "spsvm_rbf_block_workspace_bytes", "spsvm_newton_solve_workspace_bytes", "spsvm_newton_solve",
                  "spsvm_train_workspace_bytes", "spsvm_fixed_workspace_bytes", "spsvm_train",
-                 "spsvm_train_fixed_basis", "spsvm_model_get", "spsvm_model_stats", "spsvm_predict"):
+                 "spsvm_train_fixed_basis", "spsvm_batch_workspace_bytes", "spsvm_train_batch", "spsvm_model_get", "spsvm_model_stats", "spsvm_predict"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -222,11 +229,14 @@ class Model:
         return out
 
 
-def workspace_bytes(n: int, d: int, J_max: int, fixed: bool = False, **opts) -> int:
+def workspace_bytes(n: int, d: int, J_max: int, fixed: bool = False, dtype=torch.float32, batch: bool = False,
+                    **opts) -> int:
     o = options(**opts)
     b = ctypes.c_size_t()
-    fn = load().spsvm_fixed_workspace_bytes if fixed else load().spsvm_train_workspace_bytes
-    _check(fn(n, d, J_max, ctypes.byref(o), ctypes.byref(b)))
+    fn = (load().spsvm_batch_workspace_bytes if batch else
+          load().spsvm_fixed_workspace_bytes if fixed else load().spsvm_train_workspace_bytes)
+    dt = SPSVM_DT_F64 if dtype == torch.float64 else SPSVM_DT_F32
+    _check(fn(n, d, J_max, dt, ctypes.byref(o), ctypes.byref(b)))
     return b.value
 
 
@@ -249,7 +259,7 @@ def train(X: torch.Tensor, y: torch.Tensor, C: float, gamma: float, J_max: int, 
         raise TypeError("y must be float32")
     n, d = X.shape
     o = options(**opts)
-    ws, nbytes = _workspace(workspace_bytes(n, d, J_max, **opts), X.device, workspace)
+    ws, nbytes = _workspace(workspace_bytes(n, d, J_max, dtype=X.dtype, **opts), X.device, workspace)
     out = ctypes.c_void_p()
     _check(load().spsvm_train(ctypes.c_void_p(X.data_ptr()), _dtype_code(X), ctypes.c_void_p(y.data_ptr()), n, d,
                               float(C), float(gamma), int(J_max), ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()),
@@ -269,7 +279,7 @@ def train_fixed_basis(X: torch.Tensor, y: torch.Tensor, C: float, gamma: float, 
     n, d = X.shape
     Jh = np.ascontiguousarray(np.asarray(J, dtype=np.int64))
     o = options(**opts)
-    ws, nbytes = _workspace(workspace_bytes(n, d, Jh.size, fixed=True, **opts), X.device, workspace)
+    ws, nbytes = _workspace(workspace_bytes(n, d, Jh.size, fixed=True, dtype=X.dtype, **opts), X.device, workspace)
     out = ctypes.c_void_p()
     _check(load().spsvm_train_fixed_basis(ctypes.c_void_p(X.data_ptr()), _dtype_code(X), ctypes.c_void_p(y.data_ptr()),
                                           n, d, float(C), float(gamma),
@@ -292,7 +302,9 @@ def rbf_block(X: torch.Tensor, idx: torch.Tensor, gamma: float, precision: str =
     if out is None:
         out = torch.empty((n, ncols), dtype=dt, device=X.device)
     _need_gpu(out, "out")
-    ws = torch.empty(max(n, 1) * 8, dtype=torch.uint8, device=X.device)
+    b = ctypes.c_size_t()
+    _check(load().spsvm_rbf_block_workspace_bytes(n, d, _dtype_code(X), ctypes.byref(b)))
+    ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=X.device)
     _check(load().spsvm_rbf_block(ctypes.c_void_p(X.data_ptr()), _dtype_code(X), n, d, ctypes.c_void_p(idx.data_ptr()),
                                   ncols, PRECISIONS[precision], float(gamma), ctypes.c_void_p(out.data_ptr()),
                                   out.stride(0), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
@@ -322,3 +334,28 @@ def candidate_draw(seed: int, t: int, n: int, kappa: int = 59):
     out = (ctypes.c_int32 * 64)()
     _check(load().spsvm_candidate_draw(seed, t, n, kappa, out))
     return [v for v in out if v >= 0]
+
+
+def train_batch(X: torch.Tensor, Y: torch.Tensor, C, gamma, J: Sequence[int], workspace=None, stream=None,
+                **opts):
+    """P Newton re-optimisations sharing X and the basis J: problem p has labels Y[p], C[p], gamma[p]."""
+    import numpy as np
+
+    _need_gpu(X, "X")
+    _need_gpu(Y, "Y")
+    if Y.dtype != torch.float32 or Y.dim() != 2 or Y.shape[1] != X.shape[0]:
+        raise TypeError("Y must be a P x n float32 tensor")
+    n, d = X.shape
+    P = Y.shape[0]
+    Ch = np.ascontiguousarray(np.asarray(C, dtype=np.float64).reshape(P))
+    gh = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(P))
+    Jh = np.ascontiguousarray(np.asarray(J, dtype=np.int64))
+    o = options(**opts)
+    ws, nbytes = _workspace(workspace_bytes(n, d, Jh.size, batch=True, dtype=X.dtype, **opts), X.device, workspace)
+    outs = (ctypes.c_void_p * P)()
+    _check(load().spsvm_train_batch(ctypes.c_void_p(X.data_ptr()), _dtype_code(X), n, d, P,
+                                    ctypes.c_void_p(Y.data_ptr()), Ch.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    gh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    Jh.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), Jh.size, ctypes.byref(o),
+                                    ctypes.c_void_p(ws.data_ptr()), nbytes, ctypes.c_void_p(_stream_ptr(stream)), outs))
+    return [Model(outs[p]) for p in range(P)]

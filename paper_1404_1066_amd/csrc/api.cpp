@@ -4,6 +4,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "trainer.h"
@@ -49,8 +50,8 @@ spsvm_options resolve(const spsvm_options* opt) {
   if (o.newton_max_iter < 1) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "newton_max_iter must be >= 1");
   if (!(o.refactor_frac >= 0.0) || !std::isfinite(o.refactor_frac))
     throw spsvm::Failure(SPSVM_E_INVALID_ARG, "refactor_frac must be finite and >= 0");
-  if (o.precision != SPSVM_F64 && o.precision != SPSVM_F32)
-    throw spsvm::Failure(SPSVM_E_INVALID_ARG, "precision must be SPSVM_F64 or SPSVM_F32");
+  if (o.precision != SPSVM_F64 && o.precision != SPSVM_F32 && o.precision != SPSVM_MIXED)
+    throw spsvm::Failure(SPSVM_E_INVALID_ARG, "precision must be SPSVM_F64, SPSVM_F32 or SPSVM_MIXED");
   return o;
 }
 
@@ -88,19 +89,23 @@ void spsvm_options_default(spsvm_options* o) {
   o->refactor_frac = 0.002;
 }
 
-spsvm_status spsvm_train_workspace_bytes(int64_t n, int64_t d, int64_t J_max, const spsvm_options* opt, size_t* bytes) {
+spsvm_status spsvm_train_workspace_bytes(int64_t n, int64_t d, int64_t J_max, spsvm_dtype xdt,
+                                         const spsvm_options* opt, size_t* bytes) {
   return guarded([&] {
     if (!bytes) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bytes must not be NULL");
     if (n < 1 || d < 1 || J_max < 1 || J_max > n) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad sizes");
-    *bytes = spsvm::make_plan(n, d, J_max, resolve(opt), true).bytes;
+    if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
+    *bytes = spsvm::make_plan(n, d, J_max, resolve(opt), true, xdt == SPSVM_DT_F64, true).bytes;
   });
 }
 
-spsvm_status spsvm_fixed_workspace_bytes(int64_t n, int64_t d, int64_t m, const spsvm_options* opt, size_t* bytes) {
+spsvm_status spsvm_fixed_workspace_bytes(int64_t n, int64_t d, int64_t m, spsvm_dtype xdt, const spsvm_options* opt,
+                                         size_t* bytes) {
   return guarded([&] {
     if (!bytes) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bytes must not be NULL");
     if (n < 1 || d < 1 || m < 1 || m > n) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad sizes");
-    *bytes = spsvm::make_plan(n, d, m, resolve(opt), false).bytes;
+    if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
+    *bytes = spsvm::make_plan(n, d, m, resolve(opt), false, xdt == SPSVM_DT_F64, true).bytes;
   });
 }
 
@@ -127,6 +132,33 @@ spsvm_status spsvm_train_fixed_basis(const void* X, spsvm_dtype xdt, const float
     const spsvm_options o = resolve(opt);
     check_problem(X, xdt, y, n, d, C, gamma, m);
     *out = spsvm::run_train(X, xdt == SPSVM_DT_F64, y, n, d, C, gamma, m, o, workspace, ws_bytes, as_stream(stream), J);
+  });
+}
+
+spsvm_status spsvm_batch_workspace_bytes(int64_t n, int64_t d, int64_t m, spsvm_dtype xdt, const spsvm_options* opt,
+                                         size_t* bytes) {
+  return guarded([&] {
+    if (!bytes) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bytes must not be NULL");
+    if (n < 1 || d < 1 || m < 1 || m > n) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad sizes");
+    if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
+    *bytes = spsvm::make_plan(n, d, m, resolve(opt), false, xdt == SPSVM_DT_F64, true, true).bytes;
+  });
+}
+
+spsvm_status spsvm_train_batch(const void* X, spsvm_dtype xdt, int64_t n, int64_t d, int64_t P, const float* Y,
+                               const double* C, const double* gamma, const int64_t* J, int64_t m,
+                               const spsvm_options* opt, void* workspace, size_t ws_bytes, void* stream,
+                               spsvm_model** out) {
+  if (out && P > 0)
+    for (int64_t p = 0; p < P; ++p) out[p] = nullptr;
+  return guarded([&] {
+    using spsvm::Failure;
+    if (!out || !C || !gamma || !J) throw Failure(SPSVM_E_INVALID_ARG, "out, C, gamma and J must be host arrays");
+    if (P < 1 || P > (1 << 20)) throw Failure(SPSVM_E_INVALID_ARG, "P must lie in [1, 2^20]");
+    const spsvm_options o = resolve(opt);
+    for (int64_t p = 0; p < P; ++p) check_problem(X, xdt, Y, n, d, C[p], gamma[p], m);
+    spsvm::run_train_batch(X, xdt == SPSVM_DT_F64, n, d, P, Y, C, gamma, J, m, o, workspace, ws_bytes,
+                           as_stream(stream), out);
   });
 }
 
@@ -184,6 +216,36 @@ const char* spsvm_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" {
 
+}  // extern "C"
+
+static size_t rbf_ws(int64_t n, int64_t d, bool xd) {
+  const int64_t xe = xd ? 8 : 4, ld = spsvm::round_up(d, 16 / xe);
+  return (size_t)spsvm::round_up(n * 8, 256) + (size_t)n * ld * xe;
+}
+
+template <typename TX, typename TK>
+static void rbf_typed(const TX* X, int64_t n, int64_t d, const int32_t* idx, int64_t ncols, double gamma, TK* out,
+                      int64_t ldo, char* ws, hipStream_t st, bool split = false) {
+  TK* nrm = (TK*)ws;
+  const int64_t ld = spsvm::padded_ld<TX>(d);
+  const TX* A = X;
+  if (ld != d || ((uintptr_t)X & 15u)) {
+    TX* Xp = (TX*)(ws + spsvm::round_up(n * 8, 256));
+    spsvm::launch_pad_rows<TX>(X, n, d, Xp, ld, st);
+    A = Xp;
+  }
+  spsvm::launch_row_norms<TX, TK>(X, n, d, d, nrm, st);
+  if constexpr (std::is_same<TK, float>::value) {
+    if (split) {
+      spsvm::launch_kblock_split<TX>(A, ld, n, d, nrm, idx, (int)ncols, out, ldo, gamma, st);
+      return;
+    }
+  }
+  spsvm::launch_kblock<TX, TK>(A, ld, n, d, nrm, idx, (int)ncols, out, ldo, gamma, st);
+}
+
+extern "C" {
+
 spsvm_status spsvm_rbf_block(const void* X, spsvm_dtype xdt, int64_t n, int64_t d, const int32_t* idx, int64_t ncols,
                              spsvm_precision precision, double gamma, void* out, int64_t ldo, void* workspace,
                              size_t ws_bytes, void* stream) {
@@ -193,31 +255,35 @@ spsvm_status spsvm_rbf_block(const void* X, spsvm_dtype xdt, int64_t n, int64_t 
     if (n < 0 || d < 1 || ncols < 0 || ncols > 0x7fffffff || ldo < ncols)
       throw Failure(SPSVM_E_INVALID_ARG, "bad sizes");
     if (!(gamma > 0.0) || !std::isfinite(gamma)) throw Failure(SPSVM_E_INVALID_ARG, "gamma must be finite and > 0");
-    if (precision != SPSVM_F64 && precision != SPSVM_F32) throw Failure(SPSVM_E_INVALID_ARG, "bad precision");
-    if (!workspace || ((uintptr_t)workspace & 255u) || ws_bytes < (size_t)n * 8)
-      throw Failure(SPSVM_E_WORKSPACE, "workspace must be 256-byte aligned with >= n * 8 bytes");
-    hipStream_t st = as_stream(stream);
+    if (precision != SPSVM_F64 && precision != SPSVM_F32 && precision != SPSVM_MIXED)
+      throw Failure(SPSVM_E_INVALID_ARG, "bad precision");
+    if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
     const bool xd = xdt == SPSVM_DT_F64;
+    if (!workspace || ((uintptr_t)workspace & 255u) || ws_bytes < rbf_ws(n, d, xd))
+      throw Failure(SPSVM_E_WORKSPACE, "workspace must be 256-byte aligned with >= spsvm_rbf_block_workspace_bytes");
+    hipStream_t st = as_stream(stream);
+    char* w = (char*)workspace;
     if (precision == SPSVM_F64) {
-      double* nrm = (double*)workspace;
-      if (xd) {
-        spsvm::launch_row_norms<double, double>((const double*)X, n, d, nrm, st);
-        spsvm::launch_kblock<double, double>((const double*)X, n, d, nrm, idx, (int)ncols, (double*)out, ldo, gamma, st);
-      } else {
-        spsvm::launch_row_norms<float, double>((const float*)X, n, d, nrm, st);
-        spsvm::launch_kblock<float, double>((const float*)X, n, d, nrm, idx, (int)ncols, (double*)out, ldo, gamma, st);
-      }
+      if (xd)
+        rbf_typed<double, double>((const double*)X, n, d, idx, ncols, gamma, (double*)out, ldo, w, st);
+      else
+        rbf_typed<float, double>((const float*)X, n, d, idx, ncols, gamma, (double*)out, ldo, w, st);
     } else {
-      float* nrm = (float*)workspace;
-      if (xd) {
-        spsvm::launch_row_norms<double, float>((const double*)X, n, d, nrm, st);
-        spsvm::launch_kblock<double, float>((const double*)X, n, d, nrm, idx, (int)ncols, (float*)out, ldo, gamma, st);
-      } else {
-        spsvm::launch_row_norms<float, float>((const float*)X, n, d, nrm, st);
-        spsvm::launch_kblock<float, float>((const float*)X, n, d, nrm, idx, (int)ncols, (float*)out, ldo, gamma, st);
-      }
+      const bool split = precision == SPSVM_MIXED;
+      if (xd)
+        rbf_typed<double, float>((const double*)X, n, d, idx, ncols, gamma, (float*)out, ldo, w, st, split);
+      else
+        rbf_typed<float, float>((const float*)X, n, d, idx, ncols, gamma, (float*)out, ldo, w, st, split);
     }
     SPSVM_HIP(hipStreamSynchronize(st));
+  });
+}
+
+spsvm_status spsvm_rbf_block_workspace_bytes(int64_t n, int64_t d, spsvm_dtype xdt, size_t* bytes) {
+  return guarded([&] {
+    if (!bytes || n < 0 || d < 1 || (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64))
+      throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad arguments");
+    *bytes = rbf_ws(n, d, xdt == SPSVM_DT_F64);
   });
 }
 

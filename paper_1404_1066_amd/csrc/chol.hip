@@ -16,78 +16,52 @@ namespace spsvm {
 constexpr int NB = kCholNB;
 constexpr int NB_LD = NB + 1;
 
-// Factor the 64 x 64 diagonal block in LDS and write L_kk and its inverse. Thread t owns column t & 63 and
-// rows (t >> 6) + 4 r, so every step is one parallel sweep followed by one barrier:
-//  factor step j:  A[i][l] -= A[i][j] A[l][j] / A[j][j]  for j < l <= i (column j itself is scaled at the end);
-//  inverse step p: X[i][c] -= L[i][p] X[p][c] / L[p][p]   for i > p      (rows of X are scaled at the end).
-__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ H, int64_t ldh, int m, int k0,
-                                                    double* __restrict__ Linv, NewtonScalars* sc) {
+// Factor the 64 x 64 diagonal block in LDS and write L_kk and its inverse, with a single wave: lane l owns
+// column l. A wave executes its LDS operations in order, so the steps need no barrier, only a compiler
+// scheduling fence (wave_barrier) so that loads are not moved above the previous step's stores.
+//  factor step j:  A[i][l] -= A[i][j] A[l][j] / A[j][j]  for l > j, i >= l (column j is scaled at the end);
+//  inverse:        lane c runs forward substitution for column c of L^{-1} (no cross-lane dependence).
+__global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ H, int64_t ldh, int m, int k0,
+                                                   double* __restrict__ Linv, NewtonScalars* sc) {
   __shared__ double A[NB][NB_LD];
   __shared__ double X[NB][NB_LD];
-  __shared__ double dg[NB];
   const int nb = m - k0 < NB ? m - k0 : NB;
-  const int tid = threadIdx.x, col = tid & 63, r0 = tid >> 6;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e / NB, c = e % NB;
-    A[r][c] = (r < nb && c <= r) ? H[(int64_t)(k0 + r) * ldh + k0 + c] : (r == c ? 1.0 : 0.0);
-    X[r][c] = (r == c) ? 1.0 : 0.0;
-  }
+  const int l = threadIdx.x;
+  for (int r = 0; r < NB; ++r)
+    A[r][l] = (r < nb && l <= r) ? H[(int64_t)(k0 + r) * ldh + k0 + l] : (r == l ? 1.0 : 0.0);
   __syncthreads();
   bool bad = false;
   for (int j = 0; j < NB; ++j) {
     const double piv = A[j][j];
-    if (tid == 0) bad |= !(piv > 0.0) || !(piv < __builtin_huge_val());
-    const double rp = (piv > 0.0 && piv < __builtin_huge_val()) ? 1.0 / piv : 0.0;
-    if (col > j) {
-      // all LDS reads of the step first, then the writes (keeps the reads pipelined)
-      double aij[16], aic[16];
-      const double alj = A[col][j] * rp;
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        aij[q] = A[r0 + 4 * q][j];
-        aic[q] = A[r0 + 4 * q][col];
-      }
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (r0 + 4 * q >= col) A[r0 + 4 * q][col] = aic[q] - aij[q] * alj;
+    const bool ok = piv > 0.0 && piv < __builtin_huge_val();
+    bad |= !ok;
+    if (l > j) {
+      const double alj = ok ? A[l][j] / piv : 0.0;
+      for (int i = l; i < NB; ++i) A[i][l] -= A[i][j] * alj;
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
   }
-  if (tid < NB) {
-    const double p = A[tid][tid];
-    dg[tid] = (p > 0.0 && p < __builtin_huge_val()) ? sqrt(p) : 1.0;
+  const double p = A[l][l];
+  const double dl = (p > 0.0 && p < __builtin_huge_val()) ? sqrt(p) : 1.0;
+  const double rdl = 1.0 / dl;
+  for (int i = l + 1; i < NB; ++i) A[i][l] *= rdl;
+  A[l][l] = dl;
+  __builtin_amdgcn_wave_barrier();
+  __syncthreads();
+  // column l of L^{-1}: x_i = (e_l[i] - sum_{p < i} L[i][p] x_p) / L[i][i] for i >= l
+  for (int i = 0; i < NB; ++i) X[i][l] = 0.0;
+  for (int i = l; i < NB; ++i) {
+    double t = (i == l) ? 1.0 : 0.0;
+    for (int q = l; q < i; ++q) t -= A[i][q] * X[q][l];
+    X[i][l] = t / A[i][i];
   }
   __syncthreads();
-  // L[i][c] = A[i][c] / sqrt(A[c][c]) below the diagonal, sqrt(A[c][c]) on it
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int i = r0 + 4 * q;
-    if (i > col) A[i][col] /= dg[col];
-  }
-  __syncthreads();
-  if (tid < NB) A[tid][tid] = dg[tid];
-  __syncthreads();
-  // inverse of the lower-triangular L: column-oriented forward substitution on X = I
-  for (int p = 0; p < NB; ++p) {
-    const double xp = X[p][col] / A[p][p];
-    double aip[16], xic[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      aip[q] = A[r0 + 4 * q][p];
-      xic[q] = X[r0 + 4 * q][col];
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (r0 + 4 * q > p) X[r0 + 4 * q][col] = xic[q] - aip[q] * xp;
-    __syncthreads();
-  }
   double* Lo = Linv + (int64_t)(k0 / NB) * NB * NB;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e / NB, c = e % NB;
-    Lo[e] = (c <= r) ? X[r][c] / A[r][r] : 0.0;
-    if (r < nb && c <= r) H[(int64_t)(k0 + r) * ldh + k0 + c] = A[r][c];
+  for (int r = 0; r < NB; ++r) {
+    Lo[r * NB + l] = X[r][l];
+    if (r < nb && l <= r) H[(int64_t)(k0 + r) * ldh + k0 + l] = A[r][l];
   }
-  if (tid == 0 && bad) sc->fail = 1;
+  if (bad && l == 0) sc->fail = 1;
 }
 
 // Rows r >= k0 + 64: L[r, panel] = H[r, panel] Linv^T, a 64 x 64 x 64 product per workgroup on FP64 MFMA.
@@ -197,7 +171,7 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ H, int
 
 void launch_cholesky(double* H, int64_t ldh, int m, double* Linv, NewtonScalars* sc, hipStream_t s) {
   for (int k0 = 0; k0 < m; k0 += NB) {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, H, ldh, m, k0, Linv, sc);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, H, ldh, m, k0, Linv, sc);
     SPSVM_LAUNCHED();
     const int rest = m - k0 - NB;
     if (rest <= 0) break;

@@ -11,12 +11,12 @@ namespace spsvm {
 // ------------------------------------------------------------------------------------------ row norms
 // One wave per row; squares summed in FP64 from the values the GEMM sees (cast to TK first).
 template <typename TX, typename TK>
-__global__ __launch_bounds__(256) void k_row_norms(const TX* __restrict__ X, int64_t n, int64_t d,
+__global__ __launch_bounds__(256) void k_row_norms(const TX* __restrict__ X, int64_t n, int64_t d, int64_t ldx,
                                                    TK* __restrict__ out) {
   const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (row >= n) return;
-  const TX* x = X + row * d;
+  const TX* x = X + row * ldx;
   double s = 0.0;
   for (int64_t t = lane; t < d; t += kWave) {
     const double v = (double)(TK)x[t];
@@ -27,9 +27,9 @@ __global__ __launch_bounds__(256) void k_row_norms(const TX* __restrict__ X, int
 }
 
 template <typename TX, typename TK>
-void launch_row_norms(const TX* X, int64_t n, int64_t d, TK* out, hipStream_t st) {
+void launch_row_norms(const TX* X, int64_t n, int64_t d, int64_t ldx, TK* out, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((k_row_norms<TX, TK>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, X, n, d, out);
+  hipLaunchKernelGGL((k_row_norms<TX, TK>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, X, n, d, ldx, out);
   SPSVM_LAUNCHED();
 }
 
@@ -104,6 +104,22 @@ __device__ __forceinline__ double gamma_scale<double>(double g) { return g; }
 // read; A and B use the same k assignment, so the sum runs over every k exactly once.
 constexpr int KB_BM = 128, KB_BN = 64, KB_BK = 32, KB_PAD = 4, KB_LD = KB_BK + KB_PAD;
 
+// Operand rows are read with 16-byte vector loads: every row of A and B starts at a multiple of lda / ldb
+// elements with lda, ldb multiples of 16 / sizeof(element) (the caller pads the feature matrix when needed),
+// and elements past d in a row are ignored.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = floatx4;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  using type = double __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2;
+};
+
 template <typename TA, typename TB, typename TK>
 struct KTile {
   using M = Mfma<TK>;
@@ -118,40 +134,53 @@ struct KTile {
 
   // acc += A[r0 .. r0+128) . B[rows of this column tile]^T over all d features. The next chunk's global
   // loads are issued into registers before the current chunk's MFMAs, so they overlap.
-  __device__ __forceinline__ void run(const TA* __restrict__ A, int64_t nA, int64_t r0, const TB* __restrict__ B,
-                                      const int32_t* __restrict__ bidx, int64_t c0, int ncols, int64_t d,
-                                      TK (*As)[KB_LD], TK (*Bs)[KB_LD]) {
+  __device__ __forceinline__ void run(const TA* __restrict__ A, int64_t lda, int64_t nA, int64_t r0,
+                                      const TB* __restrict__ B, int64_t ldb, const int32_t* __restrict__ bidx,
+                                      int64_t c0, int ncols, int64_t d, TK (*As)[KB_LD], TK (*Bs)[KB_LD]) {
+    constexpr int VA = Vec16<TA>::n, VB = Vec16<TB>::n;
+    constexpr int NA = KB_BM * KB_BK / VA / 256, NB = KB_BN * KB_BK / VB / 256;  // vector loads per thread
+    constexpr int PA = KB_BK / VA, PB = KB_BK / VB;                              // vectors per row chunk
+    using VTA = typename Vec16<TA>::type;
+    using VTB = typename Vec16<TB>::type;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int g = lane >> 4, i16 = lane & 15;
-    const int kk_a = tid & 31;  // every element this thread stages sits in column kk_a of the chunk
-    int64_t brow[8];
+    const int ka = (tid % PA) * VA, kb = (tid % PB) * VB;  // first k of this thread's vectors in a chunk
+    const TA* arow[NA];
+    const TB* brow[NB];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int c = (tid + e * 256) >> 5;
-      const int64_t col = c0 + c;
-      brow[e] = col < ncols ? (bidx ? (int64_t)bidx[col] : col) : -1;
+    for (int e = 0; e < NA; ++e) {
+      const int64_t row = r0 + (tid + e * 256) / PA;
+      arow[e] = row < nA ? A + row * lda : nullptr;
     }
-    const TA* arow[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int64_t row = r0 + ((tid + e * 256) >> 5);
-      arow[e] = row < nA ? A + row * d : nullptr;
+    for (int e = 0; e < NB; ++e) {
+      const int64_t col = c0 + (tid + e * 256) / PB;
+      const int64_t src = col < ncols ? (bidx ? (int64_t)bidx[col] : col) : -1;
+      brow[e] = src >= 0 ? B + src * ldb : nullptr;
     }
-    TK ra[16], rb[8];
+    VTA ra[NA];
+    VTB rb[NB];
     auto fetch = [&](int64_t k0) {
-      const bool kin = k0 + kk_a < d;
 #pragma unroll
-      for (int e = 0; e < 16; ++e) ra[e] = (arow[e] && kin) ? (TK)arow[e][k0 + kk_a] : (TK)0;
+      for (int e = 0; e < NA; ++e) ra[e] = (arow[e] && k0 + ka < d) ? *(const VTA*)(arow[e] + k0 + ka) : VTA{};
 #pragma unroll
-      for (int e = 0; e < 8; ++e) rb[e] = (brow[e] >= 0 && kin) ? (TK)B[brow[e] * d + k0 + kk_a] : (TK)0;
+      for (int e = 0; e < NB; ++e) rb[e] = (brow[e] && k0 + kb < d) ? *(const VTB*)(brow[e] + k0 + kb) : VTB{};
     };
     fetch(0);
     for (int64_t k0 = 0; k0 < d; k0 += KB_BK) {
       __syncthreads();
 #pragma unroll
-      for (int e = 0; e < 16; ++e) As[(tid + e * 256) >> 5][kk_a] = ra[e];
+      for (int e = 0; e < NA; ++e) {
+        const int r = (tid + e * 256) / PA;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) Bs[(tid + e * 256) >> 5][kk_a] = rb[e];
+        for (int v = 0; v < VA; ++v) As[r][ka + v] = (k0 + ka + v < d) ? (TK)ra[e][v] : (TK)0;
+      }
+#pragma unroll
+      for (int e = 0; e < NB; ++e) {
+        const int r = (tid + e * 256) / PB;
+#pragma unroll
+        for (int v = 0; v < VB; ++v) Bs[r][kb + v] = (k0 + kb + v < d) ? (TK)rb[e][v] : (TK)0;
+      }
       __syncthreads();
       if (k0 + KB_BK < d) fetch(k0 + KB_BK);
 #pragma unroll
@@ -173,8 +202,9 @@ struct KTile {
 };
 
 // STORE: out[row * ldo + c] for the column tile blockIdx.y.
+// gamma > 0: out = exp(-gamma d2); gamma == 0: out = d2 (the squared distance itself, clamped at 0).
 template <typename TX, typename TK>
-__global__ __launch_bounds__(256) void k_kblock_store(const TX* __restrict__ X, int64_t n, int64_t d,
+__global__ __launch_bounds__(256) void k_kblock_store(const TX* __restrict__ X, int64_t ldx, int64_t n, int64_t d,
                                                       const TK* __restrict__ xnorm, const int32_t* __restrict__ cidx,
                                                       int ncols, TK* __restrict__ out, int64_t ldo, double gamma) {
   using M = Mfma<TK>;
@@ -183,7 +213,7 @@ __global__ __launch_bounds__(256) void k_kblock_store(const TX* __restrict__ X, 
   const int64_t r0 = (int64_t)blockIdx.x * KB_BM, c0 = (int64_t)blockIdx.y * KB_BN;
   KTile<TX, TX, TK> t;
   t.zero();
-  t.run(X, n, r0, X, cidx, c0, ncols, d, As, Bs);
+  t.run(X, ldx, n, r0, X, ldx, cidx, c0, ncols, d, As, Bs);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const TK gs = gamma_scale<TK>(gamma);
 #pragma unroll
@@ -200,26 +230,162 @@ __global__ __launch_bounds__(256) void k_kblock_store(const TX* __restrict__ X, 
         const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
         if (row < n) {
           const TK d2 = xnorm[row] + zn - (TK)2 * t.acc[i][j][r];
-          out[row * ldo + col] = rbf_from_d2(d2, gs);
+          out[row * ldo + col] = gamma > 0.0 ? rbf_from_d2(d2, gs) : (d2 > (TK)0 ? d2 : (TK)0);
         }
       }
   }
 }
 
 template <typename TX, typename TK>
-void launch_kblock(const TX* X, int64_t n, int64_t d, const TK* xnorm, const int32_t* cidx, int ncols, TK* out,
-                   int64_t ldo, double gamma, hipStream_t st) {
+void launch_kblock(const TX* X, int64_t ldx, int64_t n, int64_t d, const TK* xnorm, const int32_t* cidx, int ncols,
+                   TK* out, int64_t ldo, double gamma, hipStream_t st) {
   if (n <= 0 || ncols <= 0) return;
+  if (ldx % Vec16<TX>::n != 0 || ((uintptr_t)X & 15u))
+    throw Failure(1, "kernel block: rows must start on 16-byte boundaries");
   dim3 grid((unsigned)ceil_div(n, KB_BM), (unsigned)ceil_div(ncols, KB_BN));
-  hipLaunchKernelGGL((k_kblock_store<TX, TK>), grid, dim3(256), 0, st, X, n, d, xnorm, cidx, ncols, out, ldo, gamma);
+  hipLaunchKernelGGL((k_kblock_store<TX, TK>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out, ldo,
+                     gamma);
+  SPSVM_LAUNCHED();
+}
+
+// ---------------------------------------------------------------------- split-BF16 kernel block (MIXED)
+// Every operand value is split as x = hi + lo with hi = bf16(x) and lo = bf16(x - hi) (round to nearest
+// even), and x . z is taken as hi.hi' + hi.lo' + lo.hi' on the BF16 MFMA (16x16x32, FP32 accumulation); the
+// dropped lo.lo' term is below 2^-16 |x||z|. Lane l of a 16x16x32 MFMA supplies A[l % 16][8 (l / 16) .. +7]
+// and B[8 (l / 16) .. +7][l % 16] (measured on gfx950); the output layout is that of the FP32 16x16 MFMA.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne_bits(float x) {
+  const unsigned int b = __float_as_uint(x);
+  return (unsigned short)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_float(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+constexpr int SB_BK = 32, SB_LD = SB_BK + 8;  // bf16 elements per LDS row (16-byte aligned rows)
+
+template <typename TX>
+__global__ __launch_bounds__(256) void k_kblock_split(const TX* __restrict__ X, int64_t ldx, int64_t n, int64_t d,
+                                                      const float* __restrict__ xnorm,
+                                                      const int32_t* __restrict__ cidx, int ncols,
+                                                      float* __restrict__ out, int64_t ldo, double gamma) {
+  __shared__ __attribute__((aligned(16))) unsigned short Ah[KB_BM][SB_LD], Al[KB_BM][SB_LD];
+  __shared__ __attribute__((aligned(16))) unsigned short Bh[KB_BN][SB_LD], Bl[KB_BN][SB_LD];
+  constexpr int V = Vec16<TX>::n;
+  constexpr int NA = KB_BM * SB_BK / V / 256, NB = KB_BN * SB_BK / V / 256, P = SB_BK / V;
+  using VT = typename Vec16<TX>::type;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, i16 = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * KB_BM, c0 = (int64_t)blockIdx.y * KB_BN;
+  const int kq = (tid % P) * V;
+  const TX* arow[NA];
+  const TX* brow[NB];
+#pragma unroll
+  for (int e = 0; e < NA; ++e) {
+    const int64_t row = r0 + (tid + e * 256) / P;
+    arow[e] = row < n ? X + row * ldx : nullptr;
+  }
+#pragma unroll
+  for (int e = 0; e < NB; ++e) {
+    const int64_t col = c0 + (tid + e * 256) / P;
+    const int64_t src = col < ncols ? (cidx ? (int64_t)cidx[col] : col) : -1;
+    brow[e] = src >= 0 ? X + src * ldx : nullptr;
+  }
+  floatx4 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0, 0, 0, 0};
+  VT ra[NA], rb[NB];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < NA; ++e) ra[e] = (arow[e] && k0 + kq < d) ? *(const VT*)(arow[e] + k0 + kq) : VT{};
+#pragma unroll
+    for (int e = 0; e < NB; ++e) rb[e] = (brow[e] && k0 + kq < d) ? *(const VT*)(brow[e] + k0 + kq) : VT{};
+  };
+  auto split_store = [&](const VT& v, int64_t k0, unsigned short* hi, unsigned short* lo) {
+#pragma unroll
+    for (int t = 0; t < V; ++t) {
+      const bool in = k0 + kq + t < d;
+      const float xv = in ? (float)v[t] : 0.0f;
+      const unsigned short h = bf16_rne_bits(xv);
+      const double rest = in ? (double)v[t] - (double)bf16_bits_to_float(h) : 0.0;
+      hi[t] = h;
+      lo[t] = bf16_rne_bits((float)rest);
+    }
+  };
+  fetch(0);
+  for (int64_t k0 = 0; k0 < d; k0 += SB_BK) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+      const int r = (tid + e * 256) / P;
+      split_store(ra[e], k0, &Ah[r][kq], &Al[r][kq]);
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int r = (tid + e * 256) / P;
+      split_store(rb[e], k0, &Bh[r][kq], &Bl[r][kq]);
+    }
+    __syncthreads();
+    if (k0 + SB_BK < d) fetch(k0 + SB_BK);
+    bf16x8 ah[2], al[2], bh[4], bl[4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      ah[i] = *(const bf16x8*)&Ah[w * 32 + i * 16 + i16][8 * g];
+      al[i] = *(const bf16x8*)&Al[w * 32 + i * 16 + i16][8 * g];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bh[j] = *(const bf16x8*)&Bh[j * 16 + i16][8 * g];
+      bl[j] = *(const bf16x8*)&Bl[j * 16 + i16][8 * g];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+  }
+  const float gs = (float)(gamma * 1.4426950408889634);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t col = c0 + j * 16 + i16;
+    if (col >= ncols) continue;
+    const int64_t zi = cidx ? (int64_t)cidx[col] : col;
+    if (zi < 0) continue;
+    const float zn = xnorm[zi];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + w * 32 + i * 16 + (lane >> 4) * 4 + r;
+        if (row < n) {
+          const float d2 = xnorm[row] + zn - 2.0f * acc[i][j][r];
+          out[row * ldo + col] = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
+        }
+      }
+  }
+}
+
+template <typename TX>
+void launch_kblock_split(const TX* X, int64_t ldx, int64_t n, int64_t d, const float* xnorm, const int32_t* cidx,
+                         int ncols, float* out, int64_t ldo, double gamma, hipStream_t st) {
+  if (n <= 0 || ncols <= 0) return;
+  if (ldx % Vec16<TX>::n != 0 || ((uintptr_t)X & 15u))
+    throw Failure(1, "kernel block: rows must start on 16-byte boundaries");
+  dim3 grid((unsigned)ceil_div(n, KB_BM), (unsigned)ceil_div(ncols, KB_BN));
+  hipLaunchKernelGGL((k_kblock_split<TX>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out, ldo, gamma);
   SPSVM_LAUNCHED();
 }
 
 // PREDICT: out[row] = sum_c beta[c] exp(-gamma d2(row, c)) over all m basis rows Z (m x d, type TK),
 // with FP64 accumulation; row norms of Xt are computed in the kernel.
 template <typename TX, typename TK>
-__global__ __launch_bounds__(256) void k_kblock_predict(const TX* __restrict__ Xt, int64_t n, int64_t d,
-                                                        const TK* __restrict__ Z, const TK* __restrict__ znorm, int m,
+__global__ __launch_bounds__(256) void k_kblock_predict(const TX* __restrict__ Xt, int64_t ldxt, int64_t n, int64_t d,
+                                                        const TK* __restrict__ Z, int64_t ldz,
+                                                        const TK* __restrict__ znorm, int m,
                                                         const double* __restrict__ beta, double* __restrict__ out,
                                                         double gamma) {
   using M = Mfma<TK>;
@@ -233,7 +399,7 @@ __global__ __launch_bounds__(256) void k_kblock_predict(const TX* __restrict__ X
     double s = 0.0;
     if (row < n)
       for (int64_t k = lane; k < d; k += 64) {
-        const double v = (double)(TK)Xt[row * d + k];
+        const double v = (double)(TK)Xt[row * ldxt + k];
         s += v * v;
       }
     s = wave_sum(s);
@@ -245,7 +411,7 @@ __global__ __launch_bounds__(256) void k_kblock_predict(const TX* __restrict__ X
   for (int64_t c0 = 0; c0 < m; c0 += KB_BN) {
     KTile<TX, TK, TK> t;
     t.zero();
-    t.run(Xt, n, r0, Z, nullptr, c0, m, d, As, Bs);
+    t.run(Xt, ldxt, n, r0, Z, ldz, nullptr, c0, m, d, As, Bs);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t col = c0 + j * 16 + (lane & 15);
@@ -274,29 +440,73 @@ __global__ __launch_bounds__(256) void k_kblock_predict(const TX* __restrict__ X
 }
 
 template <typename TX, typename TK>
-void launch_predict(const TX* Xt, int64_t n, int64_t d, const TK* Z, const TK* znorm, int m, const double* beta,
-                    double* out, double gamma, hipStream_t st) {
+void launch_predict(const TX* Xt, int64_t ldxt, int64_t n, int64_t d, const TK* Z, int64_t ldz, const TK* znorm, int m,
+                    const double* beta, double* out, double gamma, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((k_kblock_predict<TX, TK>), dim3((unsigned)ceil_div(n, KB_BM)), dim3(256), 0, st, Xt, n, d, Z,
-                     znorm, m, beta, out, gamma);
+  if (ldxt % Vec16<TX>::n != 0 || ((uintptr_t)Xt & 15u) || ldz % Vec16<TK>::n != 0 || ((uintptr_t)Z & 15u))
+    throw Failure(1, "predict: rows must start on 16-byte boundaries");
+  hipLaunchKernelGGL((k_kblock_predict<TX, TK>), dim3((unsigned)ceil_div(n, KB_BM)), dim3(256), 0, st, Xt, ldxt, n, d,
+                     Z, ldz, znorm, m, beta, out, gamma);
+  SPSVM_LAUNCHED();
+}
+
+// ------------------------------------------------------------------------------- K = exp(-gamma D)
+// Applies the RBF map to a block of squared distances (rows of ncols values, leading dimension ld), with the
+// same arithmetic as the fused epilogue of the kernel-block GEMM.
+template <typename TK>
+__global__ __launch_bounds__(256) void k_rbf_from_dist(const TK* __restrict__ D, int64_t rows, int ncols, int64_t ld,
+                                                       TK* __restrict__ K, double gamma) {
+  const TK gs = gamma_scale<TK>(gamma);
+  const int64_t total = rows * ncols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / ncols, c = e - r * ncols;
+    K[r * ld + c] = rbf_from_d2(D[r * ld + c], gs);
+  }
+}
+
+template <typename TK>
+void launch_rbf_from_dist(const TK* D, int64_t rows, int ncols, int64_t ld, TK* K, double gamma, hipStream_t st) {
+  if (rows <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL((k_rbf_from_dist<TK>), dim3((unsigned)std::min<int64_t>(ceil_div(rows * ncols, 256), 65536)),
+                     dim3(256), 0, st, D, rows, ncols, ld, K, gamma);
+  SPSVM_LAUNCHED();
+}
+
+// ------------------------------------------------------------------------------------- padded copies
+// out (n x ldo) = X (n x d) with zero padding, so that every row starts on a 16-byte boundary.
+template <typename TX>
+__global__ void k_pad_rows(const TX* __restrict__ X, int64_t n, int64_t d, TX* __restrict__ out, int64_t ldo) {
+  const int64_t total = n * ldo;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / ldo, c = e - r * ldo;
+    out[e] = c < d ? X[r * d + c] : (TX)0;
+  }
+}
+
+template <typename TX>
+void launch_pad_rows(const TX* X, int64_t n, int64_t d, TX* out, int64_t ldo, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_pad_rows<TX>), dim3((unsigned)std::min<int64_t>(ceil_div(n * ldo, 256), 65536)), dim3(256), 0,
+                     st, X, n, d, out, ldo);
   SPSVM_LAUNCHED();
 }
 
 // ---------------------------------------------------------------------------------- gather rows X_J
+// out[k, :] = X[idx[k], :] converted to TK, rows of out with stride ldo (the padding is zeroed).
 template <typename TX, typename TK>
 __global__ void k_gather_rows(const TX* __restrict__ X, int64_t d, const int64_t* __restrict__ idx, int64_t m,
-                              TK* __restrict__ out) {
+                              TK* __restrict__ out, int64_t ldo) {
   const int64_t k = blockIdx.y;
   const int64_t src = idx[k];
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < d; t += (int64_t)gridDim.x * blockDim.x)
-    out[k * d + t] = (TK)X[src * d + t];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ldo; t += (int64_t)gridDim.x * blockDim.x)
+    out[k * ldo + t] = t < d ? (TK)X[src * d + t] : (TK)0;
 }
 
 template <typename TX, typename TK>
-void launch_gather_rows(const TX* X, int64_t d, const int64_t* idx, int64_t m, TK* out, hipStream_t st) {
+void launch_gather_rows(const TX* X, int64_t d, const int64_t* idx, int64_t m, TK* out, int64_t ldo, hipStream_t st) {
   if (m <= 0) return;
-  hipLaunchKernelGGL((k_gather_rows<TX, TK>), dim3((unsigned)std::min<int64_t>(ceil_div(d, 256), 64), (unsigned)m),
-                     dim3(256), 0, st, X, d, idx, m, out);
+  hipLaunchKernelGGL((k_gather_rows<TX, TK>), dim3((unsigned)std::min<int64_t>(ceil_div(ldo, 256), 64), (unsigned)m),
+                     dim3(256), 0, st, X, d, idx, m, out, ldo);
   SPSVM_LAUNCHED();
 }
 
@@ -338,12 +548,12 @@ void launch_check_inputs(const TX* X, int64_t total, const float* y, int64_t n, 
 
 // ------------------------------------------------------------------------------------ instantiations
 #define SPSVM_INST(TX, TK)                                                                                    \
-  template void launch_row_norms<TX, TK>(const TX*, int64_t, int64_t, TK*, hipStream_t);                      \
-  template void launch_kblock<TX, TK>(const TX*, int64_t, int64_t, const TK*, const int32_t*, int, TK*, int64_t, \
-                                      double, hipStream_t);                                                   \
-  template void launch_predict<TX, TK>(const TX*, int64_t, int64_t, const TK*, const TK*, int, const double*,   \
-                                       double*, double, hipStream_t);                                         \
-  template void launch_gather_rows<TX, TK>(const TX*, int64_t, const int64_t*, int64_t, TK*, hipStream_t);
+  template void launch_row_norms<TX, TK>(const TX*, int64_t, int64_t, int64_t, TK*, hipStream_t);             \
+  template void launch_kblock<TX, TK>(const TX*, int64_t, int64_t, int64_t, const TK*, const int32_t*, int, TK*, \
+                                      int64_t, double, hipStream_t);                                          \
+  template void launch_predict<TX, TK>(const TX*, int64_t, int64_t, int64_t, const TK*, int64_t, const TK*, int,  \
+                                       const double*, double*, double, hipStream_t);                          \
+  template void launch_gather_rows<TX, TK>(const TX*, int64_t, const int64_t*, int64_t, TK*, int64_t, hipStream_t);
 SPSVM_INST(float, float)
 SPSVM_INST(float, double)
 SPSVM_INST(double, float)
@@ -351,6 +561,14 @@ SPSVM_INST(double, double)
 #undef SPSVM_INST
 template void launch_row_hash<float>(const float*, int64_t, int64_t, uint64_t*, hipStream_t);
 template void launch_row_hash<double>(const double*, int64_t, int64_t, uint64_t*, hipStream_t);
+template void launch_kblock_split<float>(const float*, int64_t, int64_t, int64_t, const float*, const int32_t*, int,
+                                         float*, int64_t, double, hipStream_t);
+template void launch_kblock_split<double>(const double*, int64_t, int64_t, int64_t, const float*, const int32_t*, int,
+                                          float*, int64_t, double, hipStream_t);
+template void launch_rbf_from_dist<float>(const float*, int64_t, int, int64_t, float*, double, hipStream_t);
+template void launch_rbf_from_dist<double>(const double*, int64_t, int, int64_t, double*, double, hipStream_t);
+template void launch_pad_rows<float>(const float*, int64_t, int64_t, float*, int64_t, hipStream_t);
+template void launch_pad_rows<double>(const double*, int64_t, int64_t, double*, int64_t, hipStream_t);
 template void launch_check_inputs<float>(const float*, int64_t, const float*, int64_t, int32_t*, hipStream_t);
 template void launch_check_inputs<double>(const double*, int64_t, const float*, int64_t, int32_t*, hipStream_t);
 

@@ -54,19 +54,34 @@ struct NewtonScalars {
 
 // ----------------------------------------------------------------------------------------- kblock.hip
 template <typename TX, typename TK>
-void launch_row_norms(const TX* X, int64_t n, int64_t d, TK* out, hipStream_t st);
+void launch_row_norms(const TX* X, int64_t n, int64_t d, int64_t ldx, TK* out, hipStream_t st);
 template <typename TX>
 void launch_row_hash(const TX* X, int64_t n, int64_t d, uint64_t* out, hipStream_t st);
+// X rows start at multiples of ldx elements; ldx * sizeof(TX) and X must be 16-byte aligned.
+// gamma > 0 writes exp(-gamma d2); gamma == 0 writes the squared distances d2.
 template <typename TX, typename TK>
-void launch_kblock(const TX* X, int64_t n, int64_t d, const TK* xnorm, const int32_t* cidx, int ncols, TK* out,
-                   int64_t ldo, double gamma, hipStream_t st);
+void launch_kblock(const TX* X, int64_t ldx, int64_t n, int64_t d, const TK* xnorm, const int32_t* cidx, int ncols,
+                   TK* out, int64_t ldo, double gamma, hipStream_t st);
 template <typename TX, typename TK>
-void launch_predict(const TX* Xt, int64_t n, int64_t d, const TK* Z, const TK* znorm, int m, const double* beta,
-                    double* out, double gamma, hipStream_t st);
+void launch_predict(const TX* Xt, int64_t ldxt, int64_t n, int64_t d, const TK* Z, int64_t ldz, const TK* znorm, int m,
+                    const double* beta, double* out, double gamma, hipStream_t st);
+// Same block with split-BF16 products (x = hi + lo; x.z ~ hi.hi' + hi.lo' + lo.hi'), FP32 results.
+template <typename TX>
+void launch_kblock_split(const TX* X, int64_t ldx, int64_t n, int64_t d, const float* xnorm, const int32_t* cidx,
+                         int ncols, float* out, int64_t ldo, double gamma, hipStream_t st);
+template <typename TK>
+void launch_rbf_from_dist(const TK* D, int64_t rows, int ncols, int64_t ld, TK* K, double gamma, hipStream_t st);
+template <typename TX>
+void launch_pad_rows(const TX* X, int64_t n, int64_t d, TX* out, int64_t ldo, hipStream_t st);
+// Row stride (elements) that makes every row start on a 16-byte boundary.
+template <typename TX>
+inline int64_t padded_ld(int64_t d) {
+  return round_up(d, 16 / (int64_t)sizeof(TX));
+}
 template <typename TX>
 void launch_check_inputs(const TX* X, int64_t total, const float* y, int64_t n, int32_t* flags, hipStream_t st);
 template <typename TX, typename TK>
-void launch_gather_rows(const TX* X, int64_t d, const int64_t* idx, int64_t m, TK* out, hipStream_t st);
+void launch_gather_rows(const TX* X, int64_t d, const int64_t* idx, int64_t m, TK* out, int64_t ldo, hipStream_t st);
 void launch_iota(int32_t* out, int64_t m, hipStream_t st);
 
 // ----------------------------------------------------------------------------------------- select.hip

@@ -68,6 +68,12 @@ __device__ __forceinline__ int advance_slot(CandState& s, double P, double Q, do
   int still = 0;
   if (!done) {
     const double r = (P - lam * s.oc) / (lam + Q);
+    // A Newton step below 1e-10 of |s| changes the score only in the second order of the step (the
+    // derivative is already ~0 there), i.e. far below FP64 rounding of the score: stop at s.
+    if (s.newton && fabs(r - s.s) <= 1e-10 * fabs(s.s)) done = true;
+  }
+  if (!done) {
+    const double r = (P - lam * s.oc) / (lam + Q);
     double nx;
     int nw;
     if (bracket_next(s.s, g, r, s.lo, s.hi, nx, nw) && s.passes < kMaxPasses) {
@@ -236,6 +242,9 @@ __global__ void k_select(const CandState* __restrict__ st, const uint64_t* __res
                          int32_t* __restrict__ m_dev, Selection* __restrict__ sel, int32_t* __restrict__ incomplete) {
   const int c = threadIdx.x;
   const CandState s = st[c];
+  int mp = s.passes;
+  for (int off = 32; off > 0; off >>= 1) mp = max(mp, __shfl_xor(mp, off, kWave));
+  if (c == 0) atomicMax(&incomplete[1], mp);  // largest number of passes any slot needed in this stage
   const int pending = __any(s.status == 0);  // a slot still being scored: this step must be redone
   const bool ok = !pending && s.status == 1 && s.idx >= 0 && !(s.score != s.score);
   double best = ok ? s.score : -__builtin_huge_val();

@@ -9,6 +9,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 
 #include "launch.h"
 
@@ -52,8 +53,13 @@ int64_t stage_size(int64_t J, int64_t J_max, double growth, int64_t cap) {
 }
 
 // ------------------------------------------------------------------------------------------ workspace
-Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection) {
+Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection, bool x_double,
+               bool x_aligned, bool batch) {
   Plan p;
+  const int64_t xe = x_double ? 8 : 4;
+  p.ldx = round_up(d, 16 / xe);
+  p.pad_x = p.ldx != d || !x_aligned;
+  p.ldj = padded_ld<double>(d);
   p.n = n;
   p.d = d;
   p.J_max = J_max;
@@ -101,20 +107,22 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.stage_hash = take(cap * 8);
   p.m_dev = take(4);
   p.flags = take(8);
-  p.XJ64 = take((size_t)J_max * d * 8);
+  p.XJ64 = take((size_t)J_max * p.ldj * 8);
   p.xjnorm = take(J_max * 8);
   p.KJJ = take((size_t)J_max * p.ldh * 8);
   p.vJ = take(J_max * 8);
   p.wJ = take(J_max * 8);
   p.iota = take(J_max * 4);
-  p.ticket = take(4);
-  p.incomplete = take(4);
+  p.incomplete = take(8);
   p.o_stage = take(with_selection ? n * 8 : 0);
   p.Hf = take((size_t)J_max * p.ldh * 8);
   p.F_in = take(n * 4);
   p.F_out = take(n * 4);
   p.fcnt_in = take(nb_c * 4);
   p.fcnt_out = take(nb_c * 4);
+  p.Xp = take(p.pad_x ? (size_t)n * p.ldx * xe : 0);
+  p.D = take(batch ? (size_t)n * p.ldk * tk : 0);
+  p.DJJ = take(batch ? (size_t)J_max * p.ldh * 8 : 0);
   p.bytes = off;
   return p;
 }
@@ -199,7 +207,8 @@ enum { kProfKblock = 0, kProfSyrk = 1, kProfScore = 2, kProfChol = 3 };
 
 template <typename TX, typename TK>
 struct Impl {
-  const TX* X;
+  const TX* X;   // caller's n x d matrix
+  const TX* Xk;  // the matrix the kernel-block GEMMs read: X itself or its padded copy (row stride p.ldx)
   const float* y;
   int64_t n, d, J_max;
   double C, gamma, lam;
@@ -218,7 +227,6 @@ struct Impl {
   int32_t *iota, *incomplete, *F_in, *F_out, *fcnt_in, *fcnt_out;
   bool hb_valid = false;  // H (unfactored) holds lambda K_JJ + K_I^T K_I for the first m_fact basis vectors and
   int m_fact = 0;         // the violator status in act_fact
-  unsigned int* ticket;
   uint8_t *act_fact, *act_cur;
   int32_t *I, *cblk_cnt, *cblk_flips, *cand_table, *m_dev, *flags, *J32;
   int64_t* J;
@@ -239,6 +247,7 @@ struct Impl {
         base((char*)ws), pin(kPinnedScalars + (size_t)o_.chunk_cap * kCandSlots * 4) {
     prof.st = s;
     prof.mask = o_.profile;
+    Xk = p.pad_x ? at<TX>(p.Xp) : X;
     xnorm = at<TK>(p.xnorm);
     KXJ = at<TK>(p.KXJ);
     Kc = at<TK>(p.Kc);
@@ -277,7 +286,6 @@ struct Impl {
     vJ = at<double>(p.vJ);
     wJ = at<double>(p.wJ);
     iota = at<int32_t>(p.iota);
-    ticket = at<unsigned int>(p.ticket);
     incomplete = at<int32_t>(p.incomplete);
     o_stage = at<double>(p.o_stage);
     Hf = at<double>(p.Hf);
@@ -287,12 +295,23 @@ struct Impl {
     fcnt_out = at<int32_t>(p.fcnt_out);
   }
 
+  // The n x N kernel block in the training precision (split-BF16 products in MIXED mode).
+  void kblock(const int32_t* cols, int ncols, TK* out, int64_t ldo) {
+    if constexpr (std::is_same<TK, float>::value) {
+      if (opt.precision == SPSVM_MIXED) {
+        launch_kblock_split<TX>(Xk, p.ldx, n, d, xnorm, cols, ncols, out, ldo, gamma, st);
+        return;
+      }
+    }
+    launch_kblock<TX, TK>(Xk, p.ldx, n, d, xnorm, cols, ncols, out, ldo, gamma, st);
+  }
+
   // Basis rows m0..m1 of J gathered into XJ64 (FP64), then the FP64 kernel matrix K_JJ of the first m1 rows.
   void update_basis(int m0, int m1) {
     if (m1 <= m0) return;
-    launch_gather_rows<TX, double>(X, d, J + m0, m1 - m0, XJ64 + (size_t)m0 * d, st);
-    launch_row_norms<double, double>(XJ64 + (size_t)m0 * d, m1 - m0, d, xjnorm + m0, st);
-    launch_kblock<double, double>(XJ64, m1, d, xjnorm, iota, m1, KJJ, p.ldh, gamma, st);
+    launch_gather_rows<TX, double>(X, d, J + m0, m1 - m0, XJ64 + (size_t)m0 * p.ldj, p.ldj, st);
+    launch_row_norms<double, double>(XJ64 + (size_t)m0 * p.ldj, m1 - m0, d, p.ldj, xjnorm + m0, st);
+    launch_kblock<double, double>(XJ64, p.ldj, m1, d, xjnorm, iota, m1, KJJ, p.ldh, gamma, st);
   }
 
   void sync() {
@@ -313,9 +332,10 @@ struct Impl {
   void prepare() {
     SPSVM_HIP(hipMemsetAsync(flags, 0, 8, st));
     launch_iota(iota, J_max, st);
+    if (p.pad_x) launch_pad_rows<TX>(X, n, d, at<TX>(p.Xp), p.ldx, st);
     launch_check_inputs<TX>(X, n * d, y, n, flags, st);
     launch_row_hash<TX>(X, n, d, hash, st);
-    launch_row_norms<TX, TK>(X, n, d, xnorm, st);
+    launch_row_norms<TX, TK>(X, n, d, d, xnorm, st);
     hash_host.resize(n);
     SPSVM_HIP(hipMemcpyAsync(hash_host.data(), hash, n * 8, hipMemcpyDeviceToHost, st));
     SPSVM_HIP(hipMemcpyAsync(pin.p, flags, 8, hipMemcpyDeviceToHost, st));
@@ -330,6 +350,21 @@ struct Impl {
     if (J_max > distinct)
       throw Failure(SPSVM_E_INVALID_ARG, "J_max (" + std::to_string(J_max) + ") exceeds the number of distinct rows (" +
                                              std::to_string(distinct) + ")");
+  }
+
+  // prepare() for a batch: the label check covers all P label vectors (ny values).
+  void prepare_batch(const float* Y, int64_t ny) {
+    const float* keep = y;
+    y = nullptr;
+    prepare();
+    y = keep;
+    SPSVM_HIP(hipMemsetAsync(flags, 0, 8, st));
+    launch_check_inputs<TX>(X, 0, Y, ny, flags, st);
+    SPSVM_HIP(hipMemcpyAsync(pin.p, flags, 8, hipMemcpyDeviceToHost, st));
+    sync();
+    int32_t f[2];
+    std::memcpy(f, pin.p, 8);
+    if (f[1]) throw Failure(SPSVM_E_INVALID_ARG, "labels must be exactly +1 or -1");
   }
 
   // ------------------------------------------------------------------------------------ Newton at fixed J
@@ -476,8 +511,8 @@ struct Impl {
     std::vector<int32_t> table((size_t)opt.chunk_cap * kCandSlots);
     SPSVM_HIP(hipMemsetAsync(o, 0, n * 8, st));
     SPSVM_HIP(hipMemsetAsync(m_dev, 0, 4, st));
-    SPSVM_HIP(hipMemsetAsync(ticket, 0, 4, st));
     const int nblk = score_blocks(n);
+    int first_rounds = 4;
     while (m < J_max) {
       const auto t0 = clk::now();
       const int cs = (int)stage_size(m, J_max, opt.growth, opt.chunk_cap);
@@ -490,7 +525,8 @@ struct Impl {
       // saved start state with more passes (64 passes always suffice: the update stops every slot by then).
       SPSVM_HIP(hipMemcpyAsync(o_stage, o, n * 8, hipMemcpyDeviceToDevice, st));
       for (int attempt = 0;; ++attempt) {
-        const int rounds = attempt == 0 ? 4 : (attempt == 1 ? 12 : 64);
+        // passes launched per step: one more than the most any step of the previous stage needed
+        const int rounds = attempt == 0 ? first_rounds : (attempt == 1 ? std::max(2 * first_rounds, 12) : 64);
         if (attempt > 0) {
           SPSVM_HIP(hipMemcpyAsync(o, o_stage, n * 8, hipMemcpyDeviceToDevice, st));
           int32_t* mh = (int32_t*)((char*)pin.p + 8192);
@@ -498,13 +534,13 @@ struct Impl {
           SPSVM_HIP(hipMemcpyAsync(m_dev, mh, 4, hipMemcpyHostToDevice, st));
           stats.stage_redos += 1;
         }
-        SPSVM_HIP(hipMemsetAsync(incomplete, 0, 4, st));
+        SPSVM_HIP(hipMemsetAsync(incomplete, 0, 8, st));
         for (int q = 0; q < cs; ++q) {
           const int32_t* cq = cand_table + (size_t)q * kCandSlots;
           int ncand = 0;
           for (int c = 0; c < kCandSlots; ++c) ncand += table[(size_t)q * kCandSlots + c] >= 0;
           prof.timed(kProfKblock, 2.0 * n * ncand * d,
-                     [&] { launch_kblock<TX, TK>(X, n, d, xnorm, cq, kCandSlots, Kc, kCandSlots, gamma, st); });
+                     [&] { kblock(cq, kCandSlots, Kc, kCandSlots); });
           launch_score_init(cq, o, hash, stage_hash, q, cst, sc, st);
           for (int r = 0; r < rounds; ++r) {
             prof.timed(kProfScore, (double)n * (opt.kappa * sizeof(TK) + 12.0),
@@ -514,7 +550,12 @@ struct Impl {
           stats.score_passes += rounds;
           launch_select_append<TK>(cst, hash, stage_hash, q, Kc, n, o, KXJ, p.ldk, J, beta, m_dev, sel, incomplete, st);
         }
-        if (read(incomplete) == 0 || rounds >= 64) break;
+        int32_t flags2[2];
+        SPSVM_HIP(hipMemcpyAsync(pin.p, incomplete, 8, hipMemcpyDeviceToHost, st));
+        sync();
+        std::memcpy(flags2, pin.p, 8);
+        first_rounds = std::min(64, std::max(3, flags2[1] + 1));
+        if (flags2[0] == 0 || rounds >= 64) break;
       }
       t += cs;
       const int m_new = read(m_dev);
@@ -556,7 +597,7 @@ struct Impl {
     SPSVM_HIP(hipMemcpyAsync(J32, j32.data(), m * 4, hipMemcpyHostToDevice, st));
     const auto t0 = clk::now();
     prof.timed(kProfKblock, 2.0 * n * m * d,
-               [&] { launch_kblock<TX, TK>(X, n, d, xnorm, J32, (int)m, KXJ, p.ldk, gamma, st); });
+               [&] { kblock(J32, (int)m, KXJ, p.ldk); });
     update_basis(0, (int)m);
     SPSVM_HIP(hipMemsetAsync(beta, 0, m * 8, st));
     sync();
@@ -566,6 +607,64 @@ struct Impl {
     stats.stages = 1;
     stats.seconds_newton += secs(t1, clk::now());
     return (int)m;
+  }
+
+  // ------------------------------------------------------------------------- batched problems, shared J
+  // The squared distances D(X, X_J) (n x m) and D_JJ (FP64) are computed once; for each distinct gamma the
+  // kernel block K = exp(-gamma D) and K_JJ are formed once, then each problem with that gamma runs the
+  // Newton re-optimisation from beta = 0 with its own labels and C.
+  void batch(int64_t P, const float* Y, const double* Cs, const double* gs, const int64_t* Jh, int64_t m,
+             spsvm_model** outs) {
+    std::vector<uint64_t> hs(m);
+    for (int64_t k = 0; k < m; ++k) {
+      if (Jh[k] < 0 || Jh[k] >= n) throw Failure(SPSVM_E_INVALID_ARG, "basis index out of range");
+      hs[k] = hash_host[Jh[k]];
+    }
+    std::sort(hs.begin(), hs.end());
+    if (std::unique(hs.begin(), hs.end()) != hs.end())
+      throw Failure(SPSVM_E_INVALID_ARG, "basis rows must be pairwise distinct in value");
+    std::vector<int32_t> j32(Jh, Jh + m);
+    SPSVM_HIP(hipMemcpyAsync(J, Jh, m * 8, hipMemcpyHostToDevice, st));
+    SPSVM_HIP(hipMemcpyAsync(J32, j32.data(), m * 4, hipMemcpyHostToDevice, st));
+    TK* D = at<TK>(p.D);
+    double* DJJ = at<double>(p.DJJ);
+    const auto t0 = clk::now();
+    // distances once: n x m block (training precision) and the basis block in FP64
+    {
+      const double keep = gamma;
+      gamma = 0.0;
+      prof.timed(kProfKblock, 2.0 * n * m * d, [&] { kblock(J32, (int)m, D, p.ldk); });
+      gamma = keep;
+    }
+    launch_gather_rows<TX, double>(X, d, J, m, XJ64, p.ldj, st);
+    launch_row_norms<double, double>(XJ64, m, d, p.ldj, xjnorm, st);
+    launch_kblock<double, double>(XJ64, p.ldj, m, d, xjnorm, iota, (int)m, DJJ, p.ldh, 0.0, st);
+    sync();
+    const double dist_s = secs(t0, clk::now());
+    std::vector<char> done(P, 0);
+    for (int64_t a = 0; a < P; ++a) {
+      if (done[a]) continue;
+      const double g = gs[a];
+      launch_rbf_from_dist<TK>(D, n, (int)m, p.ldk, KXJ, g, st);
+      launch_rbf_from_dist<double>(DJJ, m, (int)m, p.ldh, KJJ, g, st);
+      for (int64_t q = a; q < P; ++q) {
+        if (done[q] || gs[q] != g) continue;
+        done[q] = 1;
+        const auto t1 = clk::now();
+        stats = spsvm_stats{};
+        y = Y + q * n;
+        C = Cs[q];
+        lam = 1.0 / C;
+        gamma = g;
+        hb_valid = false;
+        SPSVM_HIP(hipMemsetAsync(beta, 0, m * 8, st));
+        newton((int)m);
+        stats.stages = 1;
+        stats.seconds_select = dist_s / P;  // share of the distance block
+        stats.seconds_newton = secs(t1, clk::now());
+        outs[q] = build_model((int)m);
+      }
+    }
   }
 
   spsvm_model* build_model(int m) {
@@ -601,11 +700,12 @@ struct Impl {
       if (m > 0) {
         SPSVM_HIP(hipMemcpyAsync(md->J.data(), J, m * 8, hipMemcpyDeviceToHost, st));
         SPSVM_HIP(hipMemcpyAsync(md->beta.data(), beta, m * 8, hipMemcpyDeviceToHost, st));
-        SPSVM_HIP(hipMalloc(&md->XJ, (size_t)m * d * sizeof(TK)));
+        md->ldz = padded_ld<TK>(d);
+        SPSVM_HIP(hipMalloc(&md->XJ, (size_t)m * md->ldz * sizeof(TK)));
         SPSVM_HIP(hipMalloc(&md->XJnorm, (size_t)m * sizeof(TK)));
         SPSVM_HIP(hipMalloc(&md->beta_dev, (size_t)m * 8));
-        launch_gather_rows<TX, TK>(X, d, J, m, (TK*)md->XJ, st);
-        launch_row_norms<TK, TK>((const TK*)md->XJ, m, d, (TK*)md->XJnorm, st);
+        launch_gather_rows<TX, TK>(X, d, J, m, (TK*)md->XJ, md->ldz, st);
+        launch_row_norms<TK, TK>((const TK*)md->XJ, m, d, md->ldz, (TK*)md->XJnorm, st);
         SPSVM_HIP(hipMemcpyAsync(md->beta_dev, beta, m * 8, hipMemcpyDeviceToDevice, st));
         sync();
       }
@@ -631,7 +731,7 @@ spsvm_model* train_typed(const TX* X, const float* y, int64_t n, int64_t d, doub
 spsvm_model* run_train(const void* X, bool x_double, const float* y, int64_t n, int64_t d, double C, double gamma,
                        int64_t J_max, const spsvm_options& opt, void* ws, size_t ws_bytes, hipStream_t stream,
                        const int64_t* J_fixed) {
-  const Plan plan = make_plan(n, d, J_max, opt, J_fixed == nullptr);
+  const Plan plan = make_plan(n, d, J_max, opt, J_fixed == nullptr, x_double, ((uintptr_t)X & 15u) == 0);
   if (!ws || ((uintptr_t)ws & 255u)) throw Failure(SPSVM_E_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
   if (ws_bytes < plan.bytes)
     throw Failure(SPSVM_E_WORKSPACE, "workspace too small: need " + std::to_string(plan.bytes) + " bytes, got " +
@@ -644,25 +744,82 @@ spsvm_model* run_train(const void* X, bool x_double, const float* y, int64_t n, 
                    : train_typed<float, float>((const float*)X, y, n, d, C, gamma, J_max, opt, ws, plan, stream, J_fixed);
 }
 
+template <typename TX, typename TK>
+static void predict_typed(const spsvm_model* md, const TX* Xt, int64_t n_t, double* out, hipStream_t st) {
+  const int64_t d = md->d, ld = padded_ld<TX>(d);
+  const TX* A = Xt;
+  void* tmp = nullptr;
+  if (ld != d || ((uintptr_t)Xt & 15u)) {  // rows must start on 16-byte boundaries: use a padded copy
+    SPSVM_HIP(hipMalloc(&tmp, (size_t)n_t * ld * sizeof(TX)));
+    launch_pad_rows<TX>(Xt, n_t, d, (TX*)tmp, ld, st);
+    A = (const TX*)tmp;
+  }
+  try {
+    launch_predict<TX, TK>(A, ld, n_t, d, (const TK*)md->XJ, md->ldz, (const TK*)md->XJnorm, (int)md->m, md->beta_dev,
+                           out, md->gamma, st);
+    SPSVM_HIP(hipStreamSynchronize(st));
+  } catch (...) {
+    if (tmp) (void)hipFree(tmp);
+    throw;
+  }
+  if (tmp) SPSVM_HIP(hipFree(tmp));
+}
+
+template <typename TX, typename TK>
+static void batch_typed(const TX* X, int64_t n, int64_t d, int64_t P, const float* Y, const double* C,
+                        const double* gamma, const int64_t* J, int64_t m, const spsvm_options& opt, void* ws,
+                        const Plan& plan, hipStream_t st, spsvm_model** out) {
+  Impl<TX, TK> im(X, Y, n, d, C[0], gamma[0], m, opt, ws, st, plan);
+  im.prepare_batch(Y, n * P);
+  try {
+    im.batch(P, Y, C, gamma, J, m, out);
+  } catch (...) {
+    for (int64_t p = 0; p < P; ++p) {
+      delete out[p];
+      out[p] = nullptr;
+    }
+    throw;
+  }
+}
+
+void run_train_batch(const void* X, bool x_double, int64_t n, int64_t d, int64_t P, const float* Y, const double* C,
+                     const double* gamma, const int64_t* J, int64_t m, const spsvm_options& opt, void* ws,
+                     size_t ws_bytes, hipStream_t stream, spsvm_model** out) {
+  const Plan plan = make_plan(n, d, m, opt, false, x_double, ((uintptr_t)X & 15u) == 0, true);
+  if (!ws || ((uintptr_t)ws & 255u)) throw Failure(SPSVM_E_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
+  if (ws_bytes < plan.bytes)
+    throw Failure(SPSVM_E_WORKSPACE, "workspace too small: need " + std::to_string(plan.bytes) + " bytes, got " +
+                                         std::to_string(ws_bytes));
+  for (int64_t p = 0; p < P; ++p) out[p] = nullptr;
+  const bool tk_double = opt.precision == SPSVM_F64;
+  if (x_double) {
+    if (tk_double)
+      batch_typed<double, double>((const double*)X, n, d, P, Y, C, gamma, J, m, opt, ws, plan, stream, out);
+    else
+      batch_typed<double, float>((const double*)X, n, d, P, Y, C, gamma, J, m, opt, ws, plan, stream, out);
+  } else {
+    if (tk_double)
+      batch_typed<float, double>((const float*)X, n, d, P, Y, C, gamma, J, m, opt, ws, plan, stream, out);
+    else
+      batch_typed<float, float>((const float*)X, n, d, P, Y, C, gamma, J, m, opt, ws, plan, stream, out);
+  }
+}
+
 void run_predict(const spsvm_model* md, const void* Xt, bool x_double, int64_t n_t, double* out, hipStream_t st) {
   if (md->m == 0) {
     SPSVM_HIP(hipMemsetAsync(out, 0, n_t * 8, st));
+    SPSVM_HIP(hipStreamSynchronize(st));
   } else if (md->tk_double) {
     if (x_double)
-      launch_predict<double, double>((const double*)Xt, n_t, md->d, (const double*)md->XJ, (const double*)md->XJnorm,
-                                     (int)md->m, md->beta_dev, out, md->gamma, st);
+      predict_typed<double, double>(md, (const double*)Xt, n_t, out, st);
     else
-      launch_predict<float, double>((const float*)Xt, n_t, md->d, (const double*)md->XJ, (const double*)md->XJnorm,
-                                    (int)md->m, md->beta_dev, out, md->gamma, st);
+      predict_typed<float, double>(md, (const float*)Xt, n_t, out, st);
   } else {
     if (x_double)
-      launch_predict<double, float>((const double*)Xt, n_t, md->d, (const float*)md->XJ, (const float*)md->XJnorm,
-                                    (int)md->m, md->beta_dev, out, md->gamma, st);
+      predict_typed<double, float>(md, (const double*)Xt, n_t, out, st);
     else
-      launch_predict<float, float>((const float*)Xt, n_t, md->d, (const float*)md->XJ, (const float*)md->XJnorm,
-                                   (int)md->m, md->beta_dev, out, md->gamma, st);
+      predict_typed<float, float>(md, (const float*)Xt, n_t, out, st);
   }
-  SPSVM_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace spsvm

@@ -9,7 +9,7 @@
 #include "common.h"
 
 struct spsvm_model {
-  int64_t m = 0, d = 0;
+  int64_t m = 0, d = 0, ldz = 0;  // ldz: row stride of the basis copy XJ
   int tk_double = 0;  // kernel values / basis copy in FP64 (else FP32)
   double C = 1.0, gamma = 1.0, objective = 0.0;
   std::vector<int64_t> J;
@@ -30,21 +30,29 @@ void draw_step(uint64_t seed, int64_t t, int64_t n, int kappa, const std::vector
 int64_t stage_size(int64_t J, int64_t J_max, double growth, int64_t cap);
 
 struct Plan {
-  int64_t n = 0, d = 0, J_max = 0, ldk = 0, ldh = 0;
+  int64_t n = 0, d = 0, J_max = 0, ldk = 0, ldh = 0, ldx = 0, ldj = 0;
+  bool pad_x = false;  // X is copied with a padded row stride (rows on 16-byte boundaries)
   bool tk_double = false;
   size_t bytes = 0;
   // offsets into the workspace
   size_t xnorm, hash, KXJ, Kc, o, delta, act0, act1, I, cblk_cnt, cblk_sum, cblk_flips, J, J32, beta, dvec, g, z,
       H, Linv, syrk_part, grad_part, cand_state, sel, ls, scalars, score_part, ls_part, cand_table, stage_hash, m_dev,
-      flags, XJ64, xjnorm, KJJ, vJ, wJ, iota, ticket, incomplete, o_stage, Hf, F_in, F_out, fcnt_in, fcnt_out;
+      flags, XJ64, xjnorm, KJJ, vJ, wJ, iota, incomplete, o_stage, Hf, F_in, F_out, fcnt_in, fcnt_out, Xp, D, DJJ;
 };
 
-Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection);
+Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection,
+               bool x_double, bool x_aligned, bool batch = false);
 
 // Runs training; returns a new model (caller owns) or throws Failure.
 spsvm_model* run_train(const void* X, bool x_double, const float* y, int64_t n, int64_t d, double C, double gamma,
                        int64_t J_max, const spsvm_options& opt, void* ws, size_t ws_bytes, hipStream_t stream,
                        const int64_t* J_fixed /*nullptr = greedy selection*/);
+
+// P Newton re-optimisations on one shared basis J (m rows): problem p has labels Y + p n, C[p], gamma[p].
+// out receives P models.
+void run_train_batch(const void* X, bool x_double, int64_t n, int64_t d, int64_t P, const float* Y, const double* C,
+                     const double* gamma, const int64_t* J, int64_t m, const spsvm_options& opt, void* ws,
+                     size_t ws_bytes, hipStream_t stream, spsvm_model** out);
 
 void run_predict(const spsvm_model* model, const void* Xt, bool x_double, int64_t n_t, double* out,
                  hipStream_t stream);

@@ -40,6 +40,21 @@ def test_rbf_block_f32_within_rounding_bound(n, d, nc):
     assert np.all(np.abs(K - want) <= bound)
 
 
+@pytest.mark.parametrize("n,d,nc", [(1037, 70, 59), (300, 123, 64), (129, 5, 3), (4100, 54, 70)])
+def test_rbf_block_mixed_within_split_bound(n, d, nc):
+    """Split-BF16 products: x = hi + lo with |x - hi - lo| <= 2^-17 |x| and the dropped lo.lo' <= 2^-16 |x||z|
+    per term, so |d2 error| <= about 2^-13 (|x|^2 + |z|^2)."""
+    X, idx, gamma, K, want = _kblock_case(n, d, nc, "mixed", np.float32, n * 13 + d)
+    nx = (X * X).sum(1)
+    bound = 2.0 ** -13 * gamma * (nx[:, None] + nx[idx][None, :]) * want + 4 * EPS32
+    assert np.all(np.abs(K - want) <= bound)
+
+
+def test_rbf_block_mixed_exact_on_binary_rows():
+    X, idx, gamma, K, want = _kblock_case(2000, 123, 64, "mixed", np.float32, 6, binary=True)
+    assert np.max(np.abs(K - want) / want) <= 4 * EPS32
+
+
 def test_rbf_block_binary_rows_exact_distances():
     X, idx, gamma, K, want = _kblock_case(2000, 123, 64, "f32", np.float32, 5, binary=True)
     assert np.max(np.abs(K - want) / want) <= 4 * EPS32

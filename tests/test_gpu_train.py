@@ -96,6 +96,45 @@ def test_newton_matrix_reuse_and_updates_keep_parity(refactor_frac):
     assert (Fo - F_or) / F_or <= 1e-6
 
 
+@pytest.mark.parametrize("prec", ["mixed", "f32"])
+def test_onehot_mixed_precision_reaches_oracle_objective(prec):
+    """Split-BF16 kernel block (mixed) on data shaped like the one-hot workload: the FP64 objective of the
+    GPU's beta is within 1e-6 of the oracle's optimum at the GPU's basis."""
+    p = datagen.make_config("onehot-500k", n=20000, J_max=300)
+    Xg, yg = _dev(p.X, p.y)
+    model = lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=1, precision=prec)
+    J, beta, F = model.get()
+    b_or, F_or, _ = osp.solve_fixed_J(p.X, p.y, p.C, p.gamma, J)
+    Fo = osp.objective_at(p.X, p.y, p.C, p.gamma, J, beta)
+    print(prec, "objective rel", (Fo - F_or) / F_or)
+    assert (Fo - F_or) / F_or <= 1e-6
+    rows = np.arange(0, 20000, 7)
+    dg = model.predict(Xg[torch.tensor(rows, device="cuda")]).cpu().numpy()
+    do = oracle.predict(p.X[J], b_or, p.gamma, p.X[rows])
+    assert _decision_err(dg, do) <= 1e-4
+
+
+def test_batch_equals_fixed_basis_and_oracle():
+    """Batched one-vs-rest x (C, gamma) problems on one shared basis: each model equals the single-problem
+    fixed-basis solve bitwise (same kernels), and reaches the oracle's optimum."""
+    p = datagen.make_config("mnist-60k", n=3000, J_max=150)
+    sel = [0, 5, 18, 23, 37, 42]  # classes 0-2, several (C, gamma) pairs
+    Xg = torch.tensor(p.X, device="cuda")
+    Yg = torch.tensor(p.Y[sel], dtype=torch.float32, device="cuda").contiguous()
+    models = lib.train_batch(Xg, Yg, p.C[sel], p.gamma[sel], p.J)
+    assert len(models) == len(sel)
+    for q, s_ in enumerate(sel):
+        Jb, bb, Fb = models[q].get()
+        assert Jb.tolist() == p.J.tolist()
+        single = lib.train_fixed_basis(Xg, Yg[q].contiguous(), p.C[s_], p.gamma[s_], p.J)
+        J1, b1, F1 = single.get()
+        assert np.array_equal(bb, b1) and Fb == F1
+        if q < 2:
+            b_or, F_or, _ = osp.solve_fixed_J(p.X, p.Y[s_], p.C[s_], p.gamma[s_], p.J)
+            Fo = osp.objective_at(p.X, p.Y[s_], p.C[s_], p.gamma[s_], p.J, bb)
+            assert (Fo - F_or) / F_or <= 1e-6
+
+
 def test_training_is_deterministic():
     X, y = datagen.make_blobs(4000, 12, seed=21, dtype=np.float32)
     Xg, yg = _dev(X, y)
