@@ -16,52 +16,149 @@ namespace spsvm {
 constexpr int NB = kCholNB;
 constexpr int NB_LD = NB + 1;
 
-// Factor the 64 x 64 diagonal block in LDS and write L_kk and its inverse, with a single wave: lane l owns
-// column l. A wave executes its LDS operations in order, so the steps need no barrier, only a compiler
-// scheduling fence (wave_barrier) so that loads are not moved above the previous step's stores.
-//  factor step j:  A[i][l] -= A[i][j] A[l][j] / A[j][j]  for l > j, i >= l (column j is scaled at the end);
-//  inverse:        lane c runs forward substitution for column c of L^{-1} (no cross-lane dependence).
-__global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ H, int64_t ldh, int m, int k0,
-                                                   double* __restrict__ Linv, NewtonScalars* sc) {
+// Factor the 64 x 64 diagonal block in LDS and write L_kk and its inverse. The block is itself processed in
+// four 16-wide column blocks: wave 0 factors the 16 x 16 diagonal sub-block and inverts it (no barriers
+// inside one wave), then all threads solve the sub-panel below it and update the trailing sub-matrix. The
+// inverse of the 64 x 64 factor is assembled from the 16 x 16 inverses by block forward substitution:
+// X_bb = D_b^{-1}, X_bc = -D_b^{-1} sum_{k=c}^{b-1} L_bk X_kc.
+constexpr int SB = 16;
+
+__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ H, int64_t ldh, int m, int k0,
+                                                    double* __restrict__ Linv, NewtonScalars* sc) {
   __shared__ double A[NB][NB_LD];
   __shared__ double X[NB][NB_LD];
+  __shared__ int bad;
   const int nb = m - k0 < NB ? m - k0 : NB;
-  const int l = threadIdx.x;
-  for (int r = 0; r < NB; ++r)
-    A[r][l] = (r < nb && l <= r) ? H[(int64_t)(k0 + r) * ldh + k0 + l] : (r == l ? 1.0 : 0.0);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    A[r][c] = (r < nb && c <= r) ? H[(int64_t)(k0 + r) * ldh + k0 + c] : (r == c ? 1.0 : 0.0);
+    X[r][c] = 0.0;
+  }
   __syncthreads();
-  bool bad = false;
-  for (int j = 0; j < NB; ++j) {
-    const double piv = A[j][j];
-    const bool ok = piv > 0.0 && piv < __builtin_huge_val();
-    bad |= !ok;
-    if (l > j) {
-      const double alj = ok ? A[l][j] / piv : 0.0;
-      for (int i = l; i < NB; ++i) A[i][l] -= A[i][j] * alj;
+  for (int kb = 0; kb < NB / SB; ++kb) {
+    const int c0 = kb * SB;
+    if (w == 0) {
+      // Unblocked factorisation and inversion of the 16 x 16 diagonal sub-block in registers: lane l < 16
+      // holds column l (a[i] = A[c0 + i][c0 + l]); column j is broadcast with wave shuffles.
+      double a[SB], x[SB];
+#pragma unroll
+      for (int i = 0; i < SB; ++i) a[i] = lane < SB ? A[c0 + i][c0 + lane] : 0.0;
+      bool badl = false;
+#pragma unroll
+      for (int j = 0; j < SB; ++j) {
+        double pc[SB];
+#pragma unroll
+        for (int i = 0; i < SB; ++i) pc[i] = __shfl(a[i], j, kWave);
+        const double piv = pc[j];
+        const bool ok = piv > 0.0 && piv < __builtin_huge_val();
+        badl |= !ok;
+        double alj = 0.0;
+#pragma unroll
+        for (int i = 0; i < SB; ++i) alj = (lane == i) ? pc[i] : alj;
+        alj = ok ? alj / piv : 0.0;
+#pragma unroll
+        for (int i = 0; i < SB; ++i)
+          if (lane > j && lane < SB && i >= lane) a[i] -= pc[i] * alj;
+      }
+      double dg = 1.0;
+#pragma unroll
+      for (int i = 0; i < SB; ++i) dg = (lane == i) ? a[i] : dg;
+      dg = (dg > 0.0 && dg < __builtin_huge_val()) ? sqrt(dg) : 1.0;
+      const double rdg = 1.0 / dg;
+#pragma unroll
+      for (int i = 0; i < SB; ++i) a[i] = (i == lane) ? dg : (i > lane ? a[i] * rdg : a[i]);
+      // column lane of the inverse: x_i = (e_lane[i] - sum_{q < i} L[i][q] x_q) / L[i][i]
+#pragma unroll
+      for (int i = 0; i < SB; ++i) {
+        double t = (lane == i) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < i; ++q) t -= __shfl(a[i], q, kWave) * x[q];
+        const double lii = __shfl(a[i], i, kWave);
+        x[i] = (i >= lane) ? t / lii : 0.0;
+      }
+      if (lane < SB) {
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+          if (i >= lane) A[c0 + i][c0 + lane] = a[i];
+          X[c0 + i][c0 + lane] = x[i];
+        }
+      }
+      if (lane == 0 && badl) bad = 1;
     }
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
+    const int rest = NB - c0 - SB;  // rows below this sub-block
+    if (rest > 0) {
+      // sub-panel: L[r][c0 + c] = sum_q A[r][c0 + q] Dinv[c][q] for rows r >= c0 + 16 (results kept in
+      // registers until every thread has read its row)
+      double v[3];
+      int cnt = 0;
+      for (int e = tid; e < rest * SB; e += 256) {
+        const int r = c0 + SB + e / SB, c = e % SB;
+        double t = 0.0;
+        for (int q = 0; q <= c; ++q) t += A[r][c0 + q] * X[c0 + c][c0 + q];
+        v[cnt++] = t;
+      }
+      __syncthreads();
+      cnt = 0;
+      for (int e = tid; e < rest * SB; e += 256) {
+        const int r = c0 + SB + e / SB, c = e % SB;
+        A[r][c0 + c] = v[cnt++];
+      }
+      __syncthreads();
+      // trailing update of the lower part of rows/columns >= c0 + 16
+      for (int e = tid; e < rest * rest; e += 256) {
+        const int r = c0 + SB + e / rest, c2 = c0 + SB + e % rest;
+        if (c2 > r) continue;
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < SB; ++q) t += A[r][c0 + q] * A[c2][c0 + q];
+        A[r][c2] -= t;
+      }
+      __syncthreads();
+    }
   }
-  const double p = A[l][l];
-  const double dl = (p > 0.0 && p < __builtin_huge_val()) ? sqrt(p) : 1.0;
-  const double rdl = 1.0 / dl;
-  for (int i = l + 1; i < NB; ++i) A[i][l] *= rdl;
-  A[l][l] = dl;
-  __builtin_amdgcn_wave_barrier();
-  __syncthreads();
-  // column l of L^{-1}: x_i = (e_l[i] - sum_{p < i} L[i][p] x_p) / L[i][i] for i >= l
-  for (int i = 0; i < NB; ++i) X[i][l] = 0.0;
-  for (int i = l; i < NB; ++i) {
-    double t = (i == l) ? 1.0 : 0.0;
-    for (int q = l; q < i; ++q) t -= A[i][q] * X[q][l];
-    X[i][l] = t / A[i][i];
+  // off-diagonal 16 x 16 blocks of the inverse, one block row b at a time: X_bc = -D_b^{-1} T_bc with
+  // T_bc = sum_{k=c}^{b-1} L_bk X_kc
+  for (int b = 1; b < NB / SB; ++b) {
+    double v[3];
+    int cnt = 0;
+    for (int e = tid; e < b * SB * SB; e += 256) {  // T for all c < b: rows of block b, columns < 16 b
+      const int i = e / (b * SB), col = e % (b * SB), c = col / SB;
+      double t = 0.0;
+      for (int q = c * SB; q < b * SB; ++q) t += A[b * SB + i][q] * X[q][col];
+      v[cnt++] = t;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int e = tid; e < b * SB * SB; e += 256) {
+      const int i = e / (b * SB), col = e % (b * SB);
+      X[b * SB + i][col] = v[cnt++];  // T stored in place of X_bc until it is multiplied below
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int e = tid; e < b * SB * SB; e += 256) {
+      const int i = e / (b * SB), col = e % (b * SB);
+      double t = 0.0;
+      for (int q = 0; q <= i; ++q) t -= X[b * SB + i][b * SB + q] * X[b * SB + q][col];
+      v[cnt++] = t;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int e = tid; e < b * SB * SB; e += 256) {
+      const int i = e / (b * SB), col = e % (b * SB);
+      X[b * SB + i][col] = v[cnt++];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   double* Lo = Linv + (int64_t)(k0 / NB) * NB * NB;
-  for (int r = 0; r < NB; ++r) {
-    Lo[r * NB + l] = X[r][l];
-    if (r < nb && l <= r) H[(int64_t)(k0 + r) * ldh + k0 + l] = A[r][l];
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    Lo[e] = (c <= r) ? X[r][c] : 0.0;
+    if (r < nb && c <= r) H[(int64_t)(k0 + r) * ldh + k0 + c] = A[r][c];
   }
-  if (bad && l == 0) sc->fail = 1;
+  if (tid == 0 && bad) sc->fail = 1;
 }
 
 // Rows r >= k0 + 64: L[r, panel] = H[r, panel] Linv^T, a 64 x 64 x 64 product per workgroup on FP64 MFMA.
@@ -171,7 +268,7 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ H, int
 
 void launch_cholesky(double* H, int64_t ldh, int m, double* Linv, NewtonScalars* sc, hipStream_t s) {
   for (int k0 = 0; k0 < m; k0 += NB) {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, H, ldh, m, k0, Linv, sc);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, H, ldh, m, k0, Linv, sc);
     SPSVM_LAUNCHED();
     const int rest = m - k0 - NB;
     if (rest <= 0) break;
