@@ -10,6 +10,7 @@
 namespace spsvm {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex2 __attribute__((ext_vector_type(2)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;

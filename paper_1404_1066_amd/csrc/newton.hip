@@ -218,12 +218,15 @@ void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv
 
 // ------------------------------------------------------------------------------------------------ SYRK
 // Partial H tiles over a range of violator rows: P[split][tile] = sum_{r in split} K[I_r, T_r]^T K[I_r, T_c]
-// for the lower tiles (T_r >= T_c) of 128 x 128. Each workgroup (4 waves, 2 x 2, each 64 x 64 = 4 x 4 MFMA
-// blocks) stages 16 gathered rows at a time in LDS in their natural layout; in an MFMA step lane group g
-// supplies row kk + g, so no transpose is needed. The next rows are loaded into registers during the MFMAs.
-// The products run on FP64 MFMA: a product of two FP32 values is exact in FP64, so the Gram part of H is
-// accumulated to FP64 accuracy and stays positive semi-definite even for nearly dependent basis columns.
-constexpr int SY_T = 128, SY_BK = 16, SY_LD = SY_T + 4;
+// for the lower tiles (T_r >= T_c) of 128 x 128. Each workgroup has 4 waves (2 x 2), each owning a 64 x 64
+// block (4 x 4 MFMA blocks); the strictly upper block of a diagonal tile is never read and its wave exits.
+// Operands go straight from global memory into MFMA registers, no LDS and no barriers: in an MFMA step lane
+// (g, i) supplies gathered row g of the step and the four consecutive columns 4i..4i+3 of its 64-column
+// stripe (one 16-byte load), so MFMA block i holds the columns congruent to i mod 4 and the output is
+// permuted back when written. The next 16 rows are loaded while the current 16 are multiplied. The products
+// run on FP64 MFMA: a product of two FP32 values is exact in FP64, so the Gram part of H is accumulated to
+// FP64 accuracy and stays positive semi-definite even for nearly dependent basis columns.
+constexpr int SY_T = 128;
 
 __device__ __forceinline__ void tile_of(int t, int& tr, int& tc) {
   int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -233,22 +236,41 @@ __device__ __forceinline__ void tile_of(int t, int& tr, int& tc) {
   tc = t - r * (r + 1) / 2;
 }
 
+// Four consecutive values of a row, cnt of them valid (cnt = 4: one vector load; the rest are zero).
+__device__ __forceinline__ void load4(const float* p, int cnt, float (&v)[4]) {
+  if (cnt >= 4) {
+    const floatx4 t = *reinterpret_cast<const floatx4*>(p);
+    v[0] = t[0], v[1] = t[1], v[2] = t[2], v[3] = t[3];
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = e < cnt ? p[e] : 0.0f;
+  }
+}
+__device__ __forceinline__ void load4(const double* p, int cnt, double (&v)[4]) {
+  if (cnt >= 4) {
+    const doublex2 a = *reinterpret_cast<const doublex2*>(p), b = *reinterpret_cast<const doublex2*>(p + 2);
+    v[0] = a[0], v[1] = a[1], v[2] = b[0], v[3] = b[1];
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = e < cnt ? p[e] : 0.0;
+  }
+}
+
+// K: n x ldk row-major with ldk a multiple of 4 (16-byte aligned rows for FP32).
 template <typename TK>
 __global__ __launch_bounds__(256) void k_syrk(const TK* __restrict__ K, int64_t ldk, int m,
                                               const int32_t* __restrict__ I, int n_sv, int rows_per_split, int ntiles,
                                               int tile_base, double* __restrict__ partial) {
-  __shared__ __attribute__((aligned(16))) double At[SY_BK][SY_LD];
-  __shared__ __attribute__((aligned(16))) double Bt[SY_BK][SY_LD];
   int tr, tc;
   tile_of(tile_base + blockIdx.x, tr, tc);
-  const bool diag = tr == tc;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, i16 = lane & 15;
+  const int wr = w >> 1, wc = w & 1;
+  if (tr == tc && wr < wc) return;  // wave-uniform
+  const bool same = tr == tc && wr == wc;
   const int lo = blockIdx.y * rows_per_split;
   const int hi = lo + rows_per_split < n_sv ? lo + rows_per_split : n_sv;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, i16 = lane & 15;
-  const int wr = w >> 1, wc = w & 1;
-  const int cc = tid & 127, rr0 = tid >> 7;  // this thread stages column cc of rows rr0, rr0 + 2, ...
-  const int ca = tr * SY_T + cc, cb = tc * SY_T + cc;
-  const bool a_in = ca < m, b_in = !diag && cb < m;
+  const int ca = tr * SY_T + wr * 64 + 4 * i16, cb = tc * SY_T + wc * 64 + 4 * i16;
+  const int cnt_a = min(max(m - ca, 0), 4), cnt_b = min(max(m - cb, 0), 4);
   doublex4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -256,64 +278,66 @@ __global__ __launch_bounds__(256) void k_syrk(const TK* __restrict__ K, int64_t 
     for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0, 0, 0, 0};
   // Software pipeline: the row indices of chunk c + 2 and the values of chunk c + 1 are in flight while
   // chunk c is multiplied, so no load waits on a just-loaded index.
-  double va[8], vb[8];
-  int32_t ix[8];
+  int32_t ix[4];
+  TK xa[4][4], xb[4][4];
   auto fetch_idx = [&](int r0) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int rrow = r0 + rr0 + 2 * e;
-      ix[e] = rrow < hi ? I[rrow] : -1;
+    for (int s = 0; s < 4; ++s) {
+      const int r = r0 + 4 * s + g;
+      ix[s] = r < hi ? I[r] : -1;
     }
   };
   auto fetch_val = [&]() {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t row = ix[e];
-      va[e] = (row >= 0 && a_in) ? (double)K[row * ldk + ca] : 0.0;
-      vb[e] = (row >= 0 && b_in) ? (double)K[row * ldk + cb] : 0.0;
+    for (int s = 0; s < 4; ++s) {
+      const TK* row = K + (int64_t)(ix[s] < 0 ? 0 : ix[s]) * ldk;
+      load4(row + ca, ix[s] < 0 ? 0 : cnt_a, xa[s]);
+      if (!same) load4(row + cb, ix[s] < 0 ? 0 : cnt_b, xb[s]);
     }
   };
   if (lo < hi) {
     fetch_idx(lo);
     fetch_val();
-    fetch_idx(lo + SY_BK);
+    fetch_idx(lo + 16);
   }
-  for (int r0 = lo; r0 < hi; r0 += SY_BK) {
-    __syncthreads();
+  for (int r0 = lo; r0 < hi; r0 += 16) {
+    TK va[4][4], vb[4][4];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      At[rr0 + 2 * e][cc] = va[e];
-      Bt[rr0 + 2 * e][cc] = vb[e];
-    }
-    __syncthreads();
-    if (r0 + SY_BK < hi) {
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        va[s][e] = xa[s][e];
+        vb[s][e] = same ? xa[s][e] : xb[s][e];
+      }
+    if (r0 + 16 < hi) {
       fetch_val();
-      fetch_idx(r0 + 2 * SY_BK);
+      fetch_idx(r0 + 32);
     }
-    double(*Bp)[SY_LD] = diag ? At : Bt;
 #pragma unroll
-    for (int kk = 0; kk < SY_BK; kk += 4) {
+    for (int s = 0; s < 4; ++s) {
       double av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = At[kk + g][wr * 64 + i * 16 + i16];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bp[kk + g][wc * 64 + j * 16 + i16];
+      for (int e = 0; e < 4; ++e) {
+        av[e] = (double)va[s][e];
+        bv[e] = (double)vb[s][e];
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
   }
+  // FP64 MFMA output: acc[i][j][r] is row g + 4r of block (i, j), column i16, i.e. tile entry
+  // (wr*64 + 4*(g + 4r) + i, wc*64 + 4*i16 + j).
   double* out = partial + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * (SY_T * SY_T);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int orow = wr * 64 + i * 16 + (lane >> 4) + 4 * r, ocol = wc * 64 + j * 16 + i16;
-        out[orow * SY_T + ocol] = acc[i][j][r];
-      }
+    for (int r = 0; r < 4; ++r) {
+      double* o = out + (wr * 64 + 4 * (g + 4 * r) + i) * SY_T + wc * 64 + 4 * i16;
+      *reinterpret_cast<doublex2*>(o) = doublex2{acc[i][0][r], acc[i][1][r]};
+      *reinterpret_cast<doublex2*>(o + 2) = doublex2{acc[i][2][r], acc[i][3][r]};
+    }
 }
 
 int syrk_tiles(int m) {
@@ -321,20 +345,30 @@ int syrk_tiles(int m) {
   return t * (t + 1) / 2;
 }
 
-// Row splits per tile: enough workgroups to cover the chip about four times (memory-level parallelism for the
-// gathered rows), at least 256 rows per split, at most 256 splits.
+// Row splits per tile. Two workgroups fit on a CU (the accumulators take 128 AGPRs), so a launch runs in
+// rounds of 512 workgroups; the split count minimises rounds x (rows per split + start-up) plus the cost of
+// reducing the split partials, with at most kSyrkMaxPartials partial tiles and at least 64 rows per split.
+constexpr int kSyrkSlots = 512, kSyrkMaxPartials = 8192;
+
+static int syrk_max_splits(int nt) { return std::max(1, std::min(256, kSyrkMaxPartials / std::max(nt, 1))); }
+
 int syrk_splits(int nt, int n_sv) {
-  int s = (int)ceil_div(1024, std::max(nt, 1));
-  s = std::min<int>(s, (int)std::max<int64_t>(1, ceil_div(n_sv, 256)));
-  return std::max(1, std::min(s, 256));
+  const int smax = std::min<int>(syrk_max_splits(nt), (int)std::max<int64_t>(1, ceil_div(n_sv, 64)));
+  int best = 1;
+  double best_cost = 0.0;
+  for (int s = 1; s <= smax; ++s) {
+    const double rounds = (double)ceil_div((int64_t)nt * s, kSyrkSlots);
+    const double cost = rounds * ((double)ceil_div(n_sv, s) + 32.0) + 0.1 * s * nt;
+    if (s == 1 || cost < best_cost) best = s, best_cost = cost;
+  }
+  return best;
 }
 
 size_t syrk_partial_doubles(int m_max) {
   size_t best = 0;
   for (int t = 1; t <= ceil_div(std::max(m_max, 1), SY_T); ++t) {
     const int nt = t * (t + 1) / 2;
-    const int s = std::max(1, std::min<int>((int)ceil_div(1024, nt), 256));
-    best = std::max(best, (size_t)s * nt * SY_T * SY_T);
+    best = std::max(best, (size_t)syrk_max_splits(nt) * nt * SY_T * SY_T);
   }
   return best;
 }
