@@ -237,7 +237,7 @@ static void rbf_typed(const TX* X, int64_t n, int64_t d, const int32_t* idx, int
   spsvm::launch_row_norms<TX, TK>(X, n, d, d, nrm, st);
   if constexpr (std::is_same<TK, float>::value) {
     if (split) {
-      spsvm::launch_kblock_split<TX>(A, ld, n, d, nrm, idx, (int)ncols, out, ldo, gamma, st);
+      spsvm::launch_kblock_split<TX>(A, ld, n, d, nrm, idx, (int)ncols, out, ldo, gamma, false, st);
       return;
     }
   }

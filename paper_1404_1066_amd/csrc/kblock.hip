@@ -264,7 +264,9 @@ __device__ __forceinline__ float bf16_bits_to_float(unsigned short h) { return _
 
 constexpr int SB_BK = 32, SB_LD = SB_BK + 8;  // bf16 elements per LDS row (16-byte aligned rows)
 
-template <typename TX>
+// SPLIT = false: every operand value is exactly a BF16 number, so lo = 0 and the two correction products
+// are exact zeros; only hi.hi' is issued (the same result bit for bit).
+template <typename TX, bool SPLIT>
 __global__ __launch_bounds__(256) void k_kblock_split(const TX* __restrict__ X, int64_t ldx, int64_t n, int64_t d,
                                                       const float* __restrict__ xnorm,
                                                       const int32_t* __restrict__ cidx, int ncols,
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(256) void k_kblock_split(const TX* __restrict__ X, 
       const unsigned short h = bf16_rne_bits(xv);
       const double rest = in ? (double)v[t] - (double)bf16_bits_to_float(h) : 0.0;
       hi[t] = h;
-      lo[t] = bf16_rne_bits((float)rest);
+      if (SPLIT) lo[t] = bf16_rne_bits((float)rest);
     }
   };
   fetch(0);
@@ -332,19 +334,21 @@ __global__ __launch_bounds__(256) void k_kblock_split(const TX* __restrict__ X, 
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       ah[i] = *(const bf16x8*)&Ah[w * 32 + i * 16 + i16][8 * g];
-      al[i] = *(const bf16x8*)&Al[w * 32 + i * 16 + i16][8 * g];
+      if (SPLIT) al[i] = *(const bf16x8*)&Al[w * 32 + i * 16 + i16][8 * g];
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       bh[j] = *(const bf16x8*)&Bh[j * 16 + i16][8 * g];
-      bl[j] = *(const bf16x8*)&Bl[j * 16 + i16][8 * g];
+      if (SPLIT) bl[j] = *(const bf16x8*)&Bl[j * 16 + i16][8 * g];
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        if (SPLIT) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        }
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
       }
   }
@@ -371,12 +375,17 @@ __global__ __launch_bounds__(256) void k_kblock_split(const TX* __restrict__ X, 
 
 template <typename TX>
 void launch_kblock_split(const TX* X, int64_t ldx, int64_t n, int64_t d, const float* xnorm, const int32_t* cidx,
-                         int ncols, float* out, int64_t ldo, double gamma, hipStream_t st) {
+                         int ncols, float* out, int64_t ldo, double gamma, bool bf16_exact, hipStream_t st) {
   if (n <= 0 || ncols <= 0) return;
   if (ldx % Vec16<TX>::n != 0 || ((uintptr_t)X & 15u))
     throw Failure(1, "kernel block: rows must start on 16-byte boundaries");
   dim3 grid((unsigned)ceil_div(n, KB_BM), (unsigned)ceil_div(ncols, KB_BN));
-  hipLaunchKernelGGL((k_kblock_split<TX>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out, ldo, gamma);
+  if (bf16_exact)
+    hipLaunchKernelGGL((k_kblock_split<TX, false>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out,
+                       ldo, gamma);
+  else
+    hipLaunchKernelGGL((k_kblock_split<TX, true>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out,
+                       ldo, gamma);
   SPSVM_LAUNCHED();
 }
 
@@ -522,21 +531,24 @@ void launch_iota(int32_t* out, int64_t m, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------------------------- input checks
-// flags[0] |= some X value is NaN or infinite; flags[1] |= some label is not exactly +1 or -1.
+// flags[0] |= some X value is NaN or infinite; flags[1] |= some label is not exactly +1 or -1;
+// flags[2] |= some X value is not exactly a BF16 number (then the split-BF16 lo parts are not all zero).
 template <typename TX>
 __global__ __launch_bounds__(256) void k_check_inputs(const TX* __restrict__ X, int64_t total, const float* __restrict__ y,
                                                       int64_t n, int32_t* __restrict__ flags) {
-  int bad_x = 0, bad_y = 0;
+  int bad_x = 0, bad_y = 0, inexact = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
     const double v = (double)X[i];
     bad_x |= !(v - v == 0.0);
+    inexact |= (double)bf16_bits_to_float(bf16_rne_bits((float)v)) != v;
   }
   if (y)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
       bad_y |= !(y[i] == 1.0f || y[i] == -1.0f);
   if (__any(bad_x) && (threadIdx.x & 63) == 0) atomicOr(&flags[0], 1);
   if (__any(bad_y) && (threadIdx.x & 63) == 0) atomicOr(&flags[1], 1);
+  if (__any(inexact) && (threadIdx.x & 63) == 0) atomicOr(&flags[2], 1);
 }
 
 template <typename TX>
@@ -562,9 +574,9 @@ SPSVM_INST(double, double)
 template void launch_row_hash<float>(const float*, int64_t, int64_t, uint64_t*, hipStream_t);
 template void launch_row_hash<double>(const double*, int64_t, int64_t, uint64_t*, hipStream_t);
 template void launch_kblock_split<float>(const float*, int64_t, int64_t, int64_t, const float*, const int32_t*, int,
-                                         float*, int64_t, double, hipStream_t);
+                                         float*, int64_t, double, bool, hipStream_t);
 template void launch_kblock_split<double>(const double*, int64_t, int64_t, int64_t, const float*, const int32_t*, int,
-                                          float*, int64_t, double, hipStream_t);
+                                          float*, int64_t, double, bool, hipStream_t);
 template void launch_rbf_from_dist<float>(const float*, int64_t, int, int64_t, float*, double, hipStream_t);
 template void launch_rbf_from_dist<double>(const double*, int64_t, int, int64_t, double*, double, hipStream_t);
 template void launch_pad_rows<float>(const float*, int64_t, int64_t, float*, int64_t, hipStream_t);

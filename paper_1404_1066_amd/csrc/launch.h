@@ -66,9 +66,10 @@ template <typename TX, typename TK>
 void launch_predict(const TX* Xt, int64_t ldxt, int64_t n, int64_t d, const TK* Z, int64_t ldz, const TK* znorm, int m,
                     const double* beta, double* out, double gamma, hipStream_t st);
 // Same block with split-BF16 products (x = hi + lo; x.z ~ hi.hi' + hi.lo' + lo.hi'), FP32 results.
+// bf16_exact: every X value is a BF16 number (lo = 0), so only hi.hi' is issued (identical result).
 template <typename TX>
 void launch_kblock_split(const TX* X, int64_t ldx, int64_t n, int64_t d, const float* xnorm, const int32_t* cidx,
-                         int ncols, float* out, int64_t ldo, double gamma, hipStream_t st);
+                         int ncols, float* out, int64_t ldo, double gamma, bool bf16_exact, hipStream_t st);
 template <typename TK>
 void launch_rbf_from_dist(const TK* D, int64_t rows, int ncols, int64_t ld, TK* K, double gamma, hipStream_t st);
 template <typename TX>

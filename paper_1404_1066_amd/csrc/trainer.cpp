@@ -106,7 +106,7 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.cand_table = take((size_t)cap * kCandSlots * 4);
   p.stage_hash = take(cap * 8);
   p.m_dev = take(4);
-  p.flags = take(8);
+  p.flags = take(16);
   p.XJ64 = take((size_t)J_max * p.ldj * 8);
   p.xjnorm = take(J_max * 8);
   p.KJJ = take((size_t)J_max * p.ldh * 8);
@@ -225,6 +225,7 @@ struct Impl {
   double *o, *delta, *beta, *dvec, *g, *z, *H, *Linv, *syrk_part, *grad_part, *score_part, *ls_part, *cblk_sum;
   double *XJ64, *xjnorm, *KJJ, *vJ, *wJ, *o_stage, *Hf;
   int32_t *iota, *incomplete, *F_in, *F_out, *fcnt_in, *fcnt_out;
+  bool bf16_exact = false;  // every X value is exactly a BF16 number (split-BF16 lo parts are all zero)
   bool hb_valid = false;  // H (unfactored) holds lambda K_JJ + K_I^T K_I for the first m_fact basis vectors and
   int m_fact = 0;         // the violator status in act_fact
   uint8_t *act_fact, *act_cur;
@@ -299,7 +300,7 @@ struct Impl {
   void kblock(const int32_t* cols, int ncols, TK* out, int64_t ldo) {
     if constexpr (std::is_same<TK, float>::value) {
       if (opt.precision == SPSVM_MIXED) {
-        launch_kblock_split<TX>(Xk, p.ldx, n, d, xnorm, cols, ncols, out, ldo, gamma, st);
+        launch_kblock_split<TX>(Xk, p.ldx, n, d, xnorm, cols, ncols, out, ldo, gamma, bf16_exact, st);
         return;
       }
     }
@@ -330,7 +331,7 @@ struct Impl {
 
   // ---------------------------------------------------------------------------------------- preparation
   void prepare() {
-    SPSVM_HIP(hipMemsetAsync(flags, 0, 8, st));
+    SPSVM_HIP(hipMemsetAsync(flags, 0, 12, st));
     launch_iota(iota, J_max, st);
     if (p.pad_x) launch_pad_rows<TX>(X, n, d, at<TX>(p.Xp), p.ldx, st);
     launch_check_inputs<TX>(X, n * d, y, n, flags, st);
@@ -338,11 +339,12 @@ struct Impl {
     launch_row_norms<TX, TK>(X, n, d, d, xnorm, st);
     hash_host.resize(n);
     SPSVM_HIP(hipMemcpyAsync(hash_host.data(), hash, n * 8, hipMemcpyDeviceToHost, st));
-    SPSVM_HIP(hipMemcpyAsync(pin.p, flags, 8, hipMemcpyDeviceToHost, st));
+    SPSVM_HIP(hipMemcpyAsync(pin.p, flags, 12, hipMemcpyDeviceToHost, st));
     sync();
-    int32_t f[2];
-    std::memcpy(f, pin.p, 8);
+    int32_t f[3];
+    std::memcpy(f, pin.p, 12);
     if (f[0]) throw Failure(SPSVM_E_INVALID_ARG, "X holds NaN or Inf");
+    bf16_exact = f[2] == 0;
     if (f[1]) throw Failure(SPSVM_E_INVALID_ARG, "labels must be exactly +1 or -1");
     std::vector<uint64_t> hs = hash_host;
     std::sort(hs.begin(), hs.end());

@@ -114,6 +114,17 @@ def test_onehot_mixed_precision_reaches_oracle_objective(prec):
     assert _decision_err(dg, do) <= 1e-4
 
 
+def test_mixed_on_bf16_exact_data_equals_fp32_bitwise():
+    """0/1 features are exact in BF16, so the split's lo parts vanish and the mixed kernel block issues only
+    hi.hi'; its integer dot products equal the FP32 path's, so the whole training run must agree bit for bit."""
+    p = datagen.make_config("binary-100k", n=12000, J_max=200)
+    Xg, yg = _dev(p.X, p.y)
+    runs = [lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=4, precision=prec).get() for prec in ("f32", "mixed")]
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert runs[0][2] == runs[1][2]
+
+
 def test_batch_equals_fixed_basis_and_oracle():
     """Batched one-vs-rest x (C, gamma) problems on one shared basis: each model equals the single-problem
     fixed-basis solve bitwise (same kernels), and reaches the oracle's optimum."""
