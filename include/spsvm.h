@@ -148,9 +148,10 @@ spsvm_status spsvm_train_fixed_basis(const void* X, spsvm_dtype xdt, const float
                                      const spsvm_options* opt, void* workspace, size_t ws_bytes, void* stream,
                                      spsvm_model** out);
 
-/* Bytes of device workspace spsvm_train_batch needs (m shared basis vectors); as above. */
-spsvm_status spsvm_batch_workspace_bytes(int64_t n, int64_t d, int64_t m, spsvm_dtype xdt, const spsvm_options* opt,
-                                         size_t* bytes);
+/* Bytes of device workspace spsvm_train_batch needs for P problems on m shared basis vectors. The
+ * workspace holds the Newton state of min(P, 64) problems, which are solved in lockstep; as above. */
+spsvm_status spsvm_batch_workspace_bytes(int64_t n, int64_t d, int64_t P, int64_t m, spsvm_dtype xdt,
+                                         const spsvm_options* opt, size_t* bytes);
 
 /* P independent Newton re-optimisations of Eq. 4 that share X and one basis J (e.g. one-vs-rest classes
  * crossed with a (C, gamma) grid). Problem p has labels Y + p n, C[p] and gamma[p]. The squared distances

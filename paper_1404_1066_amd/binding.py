@@ -118,7 +118,7 @@ def load(path: str = LIB_PATH):
     lib.spsvm_train.argtypes = [VP, ctypes.c_int, VP, I64, I64, D, D, I64, P(Options), VP, ctypes.c_size_t, VP, P(VP)]
     lib.spsvm_train_fixed_basis.argtypes = [VP, ctypes.c_int, VP, I64, I64, D, D, P(I64), I64, P(Options), VP,
                                             ctypes.c_size_t, VP, P(VP)]
-    lib.spsvm_batch_workspace_bytes.argtypes = [I64, I64, I64, ctypes.c_int, P(Options), P(ctypes.c_size_t)]
+    lib.spsvm_batch_workspace_bytes.argtypes = [I64, I64, I64, I64, ctypes.c_int, P(Options), P(ctypes.c_size_t)]
     lib.spsvm_train_batch.argtypes = [VP, ctypes.c_int, I64, I64, I64, VP, P(D), P(D), P(I64), I64, P(Options), VP,
                                       ctypes.c_size_t, VP, P(VP)]
     lib.spsvm_model_get.argtypes = [VP, P(I64), P(I64), P(D), P(D)]
@@ -230,13 +230,17 @@ class Model:
 
 
 def workspace_bytes(n: int, d: int, J_max: int, fixed: bool = False, dtype=torch.float32, batch: bool = False,
-                    **opts) -> int:
+                    problems: int = 1, **opts) -> int:
+    """Workspace bytes for train (default), train_fixed_basis (fixed=True) or train_batch (batch=True, with
+    `problems` problems on J_max shared basis vectors)."""
     o = options(**opts)
     b = ctypes.c_size_t()
-    fn = (load().spsvm_batch_workspace_bytes if batch else
-          load().spsvm_fixed_workspace_bytes if fixed else load().spsvm_train_workspace_bytes)
     dt = SPSVM_DT_F64 if dtype == torch.float64 else SPSVM_DT_F32
-    _check(fn(n, d, J_max, dt, ctypes.byref(o), ctypes.byref(b)))
+    if batch:
+        _check(load().spsvm_batch_workspace_bytes(n, d, problems, J_max, dt, ctypes.byref(o), ctypes.byref(b)))
+    else:
+        fn = load().spsvm_fixed_workspace_bytes if fixed else load().spsvm_train_workspace_bytes
+        _check(fn(n, d, J_max, dt, ctypes.byref(o), ctypes.byref(b)))
     return b.value
 
 
@@ -351,7 +355,7 @@ def train_batch(X: torch.Tensor, Y: torch.Tensor, C, gamma, J: Sequence[int], wo
     gh = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(P))
     Jh = np.ascontiguousarray(np.asarray(J, dtype=np.int64))
     o = options(**opts)
-    ws, nbytes = _workspace(workspace_bytes(n, d, Jh.size, batch=True, dtype=X.dtype, **opts), X.device, workspace)
+    ws, nbytes = _workspace(workspace_bytes(n, d, Jh.size, batch=True, problems=P, dtype=X.dtype, **opts), X.device, workspace)
     outs = (ctypes.c_void_p * P)()
     _check(load().spsvm_train_batch(ctypes.c_void_p(X.data_ptr()), _dtype_code(X), n, d, P,
                                     ctypes.c_void_p(Y.data_ptr()), Ch.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),

@@ -135,13 +135,13 @@ spsvm_status spsvm_train_fixed_basis(const void* X, spsvm_dtype xdt, const float
   });
 }
 
-spsvm_status spsvm_batch_workspace_bytes(int64_t n, int64_t d, int64_t m, spsvm_dtype xdt, const spsvm_options* opt,
-                                         size_t* bytes) {
+spsvm_status spsvm_batch_workspace_bytes(int64_t n, int64_t d, int64_t P, int64_t m, spsvm_dtype xdt,
+                                         const spsvm_options* opt, size_t* bytes) {
   return guarded([&] {
     if (!bytes) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bytes must not be NULL");
-    if (n < 1 || d < 1 || m < 1 || m > n) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad sizes");
+    if (n < 1 || d < 1 || m < 1 || m > n || P < 1) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad sizes");
     if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
-    *bytes = spsvm::make_plan(n, d, m, resolve(opt), false, xdt == SPSVM_DT_F64, true, true).bytes;
+    *bytes = spsvm::make_plan(n, d, m, resolve(opt), false, xdt == SPSVM_DT_F64, true, true, P).bytes;
   });
 }
 

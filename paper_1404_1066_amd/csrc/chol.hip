@@ -23,8 +23,11 @@ constexpr int NB_LD = NB + 1;
 // X_bb = D_b^{-1}, X_bc = -D_b^{-1} sum_{k=c}^{b-1} L_bk X_kc.
 constexpr int SB = 16;
 
-__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ H, int64_t ldh, int m, int k0,
-                                                    double* __restrict__ Linv, NewtonScalars* sc) {
+// Grid z = slot of the batch.
+__global__ __launch_bounds__(256) void k_potrf_diag(const CholBatch bt, int64_t ldh, int m, int k0) {
+  double* __restrict__ H = bt.H[blockIdx.z];
+  double* __restrict__ Linv = bt.Linv[blockIdx.z];
+  NewtonScalars* sc = bt.sc[blockIdx.z];
   __shared__ double A[NB][NB_LD];
   __shared__ double X[NB][NB_LD];
   __shared__ int bad;
@@ -164,8 +167,9 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ H, int6
 // Rows r >= k0 + 64: L[r, panel] = H[r, panel] Linv^T, a 64 x 64 x 64 product per workgroup on FP64 MFMA.
 constexpr int TU_LD = NB + 4;
 
-__global__ __launch_bounds__(256) void k_trsm_panel(double* __restrict__ H, int64_t ldh, int m, int k0,
-                                                    const double* __restrict__ Linv) {
+__global__ __launch_bounds__(256) void k_trsm_panel(const CholBatch bt, int64_t ldh, int m, int k0) {
+  double* __restrict__ H = bt.H[blockIdx.z];
+  const double* __restrict__ Linv = bt.Linv[blockIdx.z];
   __shared__ __attribute__((aligned(32))) double Bm[NB][TU_LD];
   __shared__ __attribute__((aligned(32))) double Li[NB][TU_LD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, i16 = lane & 15;
@@ -219,7 +223,8 @@ __device__ __forceinline__ void tri_tile(int t, int& tr, int& tc) {
   tc = t - r * (r + 1) / 2;
 }
 
-__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ H, int64_t ldh, int m, int k0) {
+__global__ __launch_bounds__(256) void k_chol_update(const CholBatch bt, int64_t ldh, int m, int k0) {
+  double* __restrict__ H = bt.H[blockIdx.z];
   __shared__ __attribute__((aligned(32))) double Pa[NB][TU_LD];
   __shared__ __attribute__((aligned(32))) double Pb[NB][TU_LD];
   int tr, tc;
@@ -266,26 +271,42 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ H, int
       }
 }
 
-void launch_cholesky(double* H, int64_t ldh, int m, double* Linv, NewtonScalars* sc, hipStream_t s) {
+// All slots share m and ldh; each panel step is one launch per kernel for the whole batch.
+void launch_cholesky_batch(const CholBatch& b, int64_t ldh, int m, hipStream_t s) {
+  if (b.count <= 0 || m <= 0) return;
+  if (b.count > kMaxBatch) throw Failure(1, "Cholesky batch: too many slots");
+  const unsigned nz = (unsigned)b.count;
   for (int k0 = 0; k0 < m; k0 += NB) {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, H, ldh, m, k0, Linv, sc);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, nz), dim3(256), 0, s, b, ldh, m, k0);
     SPSVM_LAUNCHED();
     const int rest = m - k0 - NB;
     if (rest <= 0) break;
     const int nblk = (int)ceil_div(rest, NB);
-    hipLaunchKernelGGL(k_trsm_panel, dim3(nblk), dim3(256), 0, s, H, ldh, m, k0, Linv);
+    hipLaunchKernelGGL(k_trsm_panel, dim3(nblk, 1, nz), dim3(256), 0, s, b, ldh, m, k0);
     SPSVM_LAUNCHED();
-    hipLaunchKernelGGL(k_chol_update, dim3(nblk * (nblk + 1) / 2), dim3(256), 0, s, H, ldh, m, k0);
+    hipLaunchKernelGGL(k_chol_update, dim3(nblk * (nblk + 1) / 2, 1, nz), dim3(256), 0, s, b, ldh, m, k0);
     SPSVM_LAUNCHED();
   }
+}
+
+void launch_cholesky(double* H, int64_t ldh, int m, double* Linv, NewtonScalars* sc, hipStream_t s) {
+  CholBatch b{};
+  b.H[0] = H;
+  b.Linv[0] = Linv;
+  b.sc[0] = sc;
+  b.count = 1;
+  launch_cholesky_batch(b, ldh, m, s);
 }
 
 // ----------------------------------------------------------------------------------- triangular solves
 // One workgroup of 1024 threads. Forward: z_b = Linv_b (g_b - L[b, <b] z_<b); backward:
 // x_b = Linv_b^T (z_b - L[>b, b]^T x_>b); the result is negated (x = -H^{-1} g).
-__global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ L, int64_t ldh, int m,
-                                                     const double* __restrict__ Linv, const double* __restrict__ g,
-                                                     double* __restrict__ x, double* __restrict__ z) {
+__global__ __launch_bounds__(1024) void k_chol_solve(const SolveBatch bt, int64_t ldh, int m) {
+  const double* __restrict__ L = bt.L[blockIdx.z];
+  const double* __restrict__ Linv = bt.Linv[blockIdx.z];
+  const double* __restrict__ g = bt.g[blockIdx.z];
+  double* __restrict__ x = bt.x[blockIdx.z];
+  double* __restrict__ z = bt.work[blockIdx.z];
   __shared__ double part[16][NB];
   __shared__ double rhs[NB];
   const int tid = threadIdx.x;
@@ -339,10 +360,23 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
   for (int k = tid; k < m; k += 1024) x[k] = -x[k];
 }
 
+void launch_chol_solve_batch(const SolveBatch& b, int64_t ldh, int m, hipStream_t s) {
+  if (b.count <= 0 || m <= 0) return;
+  if (b.count > kMaxBatch) throw Failure(1, "solve batch: too many slots");
+  hipLaunchKernelGGL(k_chol_solve, dim3(1, 1, (unsigned)b.count), dim3(1024), 0, s, b, ldh, m);
+  SPSVM_LAUNCHED();
+}
+
 void launch_chol_solve(const double* L, int64_t ldh, int m, const double* Linv, const double* g, double* x,
                        double* work, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, s, L, ldh, m, Linv, g, x, work);
-  SPSVM_LAUNCHED();
+  SolveBatch b{};
+  b.L[0] = L;
+  b.Linv[0] = Linv;
+  b.g[0] = g;
+  b.x[0] = x;
+  b.work[0] = work;
+  b.count = 1;
+  launch_chol_solve_batch(b, ldh, m, s);
 }
 
 }  // namespace spsvm

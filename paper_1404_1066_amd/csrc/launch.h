@@ -113,15 +113,41 @@ void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv
                      const double* v, const double* beta, double lam, double* partial, int nchunk, double* g,
                      NewtonScalars* sc, hipStream_t s);
 int gradient_chunks(int m, int n_sv);
-// SYRK partials over the rows I[0..n_rows) for the lower 128 x 128 tiles tile_lo..tile_hi-1 (tiles numbered
-// row by row: tile t = tr (tr + 1) / 2 + tc).
+// Batched launches: up to kMaxBatch independent problems (slots) per launch, one grid z-index per slot; the
+// per-slot operands travel by value in the kernel arguments.
+constexpr int kMaxBatch = 32;
+
+// SYRK partials over the rows rows[0..n_rows) for the lower 128 x 128 tiles tile_lo..tile_hi-1 (tiles numbered
+// row by row: tile t = tr (tr + 1) / 2 + tc), split into nsplit row ranges.
+template <typename TK>
+struct SyrkBatch {
+  const TK* K[kMaxBatch];
+  const int32_t* rows[kMaxBatch];
+  double* partial[kMaxBatch];
+  int n_rows[kMaxBatch], nsplit[kMaxBatch], tile_lo[kMaxBatch], tile_hi[kMaxBatch];
+  int count;
+};
+template <typename TK>
+void launch_syrk_batch(const SyrkBatch<TK>& b, int64_t ldk, int m, hipStream_t s);
 template <typename TK>
 void launch_syrk(const TK* K, int64_t ldk, int m, const int32_t* I, int n_rows, int tile_lo, int tile_hi, int nsplit,
                  double* partial, hipStream_t s);
 // mode 0: H = lambda K_JJ + partials; +1: H += partials; -1: H -= partials (same tile range as the SYRK).
+struct ReduceBatch {
+  const double* KJJ[kMaxBatch];
+  const double* partial[kMaxBatch];
+  double* H[kMaxBatch];
+  double lam[kMaxBatch];
+  int nsplit[kMaxBatch], tile_lo[kMaxBatch], tile_hi[kMaxBatch], mode[kMaxBatch];
+  int count;
+};
+void launch_syrk_reduce_batch(const ReduceBatch& b, int m, int64_t ldh, hipStream_t s);
 void launch_syrk_reduce(const double* KJJ, int m, double lam, const double* partial, int nsplit, int tile_lo,
                         int tile_hi, int mode, double* H, int64_t ldh, hipStream_t s);
 void launch_add_diag(double* H, int64_t ldh, int m, double v, hipStream_t s);
+// Lower triangle: H = lam * KJJ + G (all m x m, leading dimension ldh).
+void launch_scaled_sum_lower(double* H, const double* KJJ, const double* G, double lam, int m, int64_t ldh,
+                             hipStream_t s);
 void launch_flip_lists(const uint8_t* act_new, const uint8_t* act_old, int64_t n, int32_t* cnt_in, int32_t* cnt_out,
                        int32_t* F_in, int32_t* F_out, NewtonScalars* sc, hipStream_t s);
 void launch_trace(const double* H, int64_t ldh, int m, NewtonScalars* sc, hipStream_t s);
@@ -129,7 +155,11 @@ int syrk_tiles(int m);
 int syrk_tile_rows(int m);
 int syrk_tile_size();
 int syrk_splits(int ntiles, int n_rows);
+// Split count of one problem in a batched Newton solve (at most kSyrkBatchSplits).
+int syrk_splits_batch(int ntiles, int n_rows);
+constexpr int kSyrkBatchSplits = 2;
 size_t syrk_partial_doubles(int m_max);
+size_t syrk_partial_doubles_batch(int m_max);
 void launch_c1c2(const double* beta, const double* dvec, const double* w, int m, LineState* ls, hipStream_t s);
 void launch_ls_round(const double* o, const double* delta, const float* y, int64_t n, double lam, LineState* ls,
                      double* partial, int nblk, hipStream_t s);
@@ -142,8 +172,24 @@ constexpr int kCholNB = 64;
 // In-place lower Cholesky of H (m x m, leading dimension ldh); Linv receives the inverses of the diagonal
 // blocks (ceil(m/64) blocks of 64 x 64). Sets sc->fail on a non-positive or non-finite pivot.
 void launch_cholesky(double* H, int64_t ldh, int m, double* Linv, NewtonScalars* sc, hipStream_t s);
+struct CholBatch {
+  double* H[kMaxBatch];
+  double* Linv[kMaxBatch];
+  NewtonScalars* sc[kMaxBatch];
+  int count;
+};
+void launch_cholesky_batch(const CholBatch& b, int64_t ldh, int m, hipStream_t s);
 // x = -L^{-T} L^{-1} g using the factor and the diagonal-block inverses.
 void launch_chol_solve(const double* L, int64_t ldh, int m, const double* Linv, const double* g, double* x,
                        double* work, hipStream_t s);
+struct SolveBatch {
+  const double* L[kMaxBatch];
+  const double* Linv[kMaxBatch];
+  const double* g[kMaxBatch];
+  double* x[kMaxBatch];
+  double* work[kMaxBatch];
+  int count;
+};
+void launch_chol_solve_batch(const SolveBatch& b, int64_t ldh, int m, hipStream_t s);
 
 }  // namespace spsvm

@@ -256,13 +256,19 @@ __device__ __forceinline__ void load4(const double* p, int cnt, double (&v)[4]) 
   }
 }
 
-// K: n x ldk row-major with ldk a multiple of 4 (16-byte aligned rows for FP32).
+// K: n x ldk row-major with ldk a multiple of 4 (16-byte aligned rows for FP32). Grid: x = tile, y = split,
+// z = slot; workgroups beyond a slot's tile range or split count exit at once.
 template <typename TK>
-__global__ __launch_bounds__(256) void k_syrk(const TK* __restrict__ K, int64_t ldk, int m,
-                                              const int32_t* __restrict__ I, int n_sv, int rows_per_split, int ntiles,
-                                              int tile_base, double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_syrk(const SyrkBatch<TK> b, int64_t ldk, int m) {
+  const int q = blockIdx.z;
+  const int ntiles = b.tile_hi[q] - b.tile_lo[q], nsplit = b.nsplit[q], n_sv = b.n_rows[q];
+  if ((int)blockIdx.x >= ntiles || (int)blockIdx.y >= nsplit) return;
+  const TK* __restrict__ K = b.K[q];
+  const int32_t* __restrict__ I = b.rows[q];
+  double* __restrict__ partial = b.partial[q];
+  const int rows_per_split = n_sv > nsplit ? (n_sv + nsplit - 1) / nsplit : 1;
   int tr, tc;
-  tile_of(tile_base + blockIdx.x, tr, tc);
+  tile_of(b.tile_lo[q] + blockIdx.x, tr, tc);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, i16 = lane & 15;
   const int wr = w >> 1, wc = w & 1;
   if (tr == tc && wr < wc) return;  // wave-uniform
@@ -364,6 +370,15 @@ int syrk_splits(int nt, int n_sv) {
   return best;
 }
 
+// In a batch the other problems fill the chip, so a problem's rows are split at most in two, and only when it
+// has few tiles. The choice depends on the problem alone, so a problem's result does not depend on which
+// other problems share its batch.
+int syrk_splits_batch(int nt, int n_sv) { return (nt < 128 && n_sv >= 128) ? kSyrkBatchSplits : 1; }
+
+size_t syrk_partial_doubles_batch(int m_max) {
+  return (size_t)kSyrkBatchSplits * syrk_tiles(std::max(m_max, 1)) * SY_T * SY_T;
+}
+
 size_t syrk_partial_doubles(int m_max) {
   size_t best = 0;
   for (int t = 1; t <= ceil_div(std::max(m_max, 1), SY_T); ++t) {
@@ -377,44 +392,100 @@ int syrk_tile_rows(int m) { return (int)ceil_div(m, SY_T); }
 int syrk_tile_size() { return SY_T; }
 
 template <typename TK>
+void launch_syrk_batch(const SyrkBatch<TK>& b, int64_t ldk, int m, hipStream_t s) {
+  int nt = 0, ns = 0;
+  for (int q = 0; q < b.count; ++q) {
+    if (b.nsplit[q] < 1 || b.tile_lo[q] < 0 || b.tile_hi[q] > syrk_tiles(m) || b.n_rows[q] < 0)
+      throw Failure(1, "SYRK batch: invalid slot descriptor");
+    nt = std::max(nt, b.tile_hi[q] - b.tile_lo[q]);
+    ns = std::max(ns, b.nsplit[q]);
+  }
+  if (b.count <= 0 || b.count > kMaxBatch || nt <= 0) return;
+  hipLaunchKernelGGL((k_syrk<TK>), dim3(nt, ns, b.count), dim3(256), 0, s, b, ldk, m);
+  SPSVM_LAUNCHED();
+}
+
+template <typename TK>
 void launch_syrk(const TK* K, int64_t ldk, int m, const int32_t* I, int n_rows, int tile_lo, int tile_hi, int nsplit,
                  double* partial, hipStream_t s) {
-  const int nt = tile_hi - tile_lo;
-  if (nt <= 0) return;
-  const int rows = (int)std::max<int64_t>(1, ceil_div(n_rows, nsplit));
-  hipLaunchKernelGGL((k_syrk<TK>), dim3(nt, nsplit), dim3(256), 0, s, K, ldk, m, I, n_rows, rows, nt, tile_lo,
-                     partial);
-  SPSVM_LAUNCHED();
+  SyrkBatch<TK> b{};
+  b.K[0] = K;
+  b.rows[0] = I;
+  b.partial[0] = partial;
+  b.n_rows[0] = n_rows;
+  b.nsplit[0] = nsplit;
+  b.tile_lo[0] = tile_lo;
+  b.tile_hi[0] = tile_hi;
+  b.count = 1;
+  launch_syrk_batch(b, ldk, m, s);
 }
 
 // For the tiles tile_lo.. of the lower triangle: mode 0 sets H = lambda K_JJ + sum of the split partials,
 // mode +1 adds the partial sums to H, mode -1 subtracts them (rows that joined or left the violator set).
 // K_JJ is the FP64 kernel matrix of the basis rows (row-major, leading dimension ldh).
-__global__ __launch_bounds__(256) void k_syrk_reduce(const double* __restrict__ KJJ, int m, double lam,
-                                                     const double* __restrict__ partial, int nsplit, int ntiles,
-                                                     int tile_lo, int mode, double* __restrict__ H, int64_t ldh) {
+__global__ __launch_bounds__(256) void k_syrk_reduce(const ReduceBatch b, int m, int64_t ldh) {
+  const int q = blockIdx.z;
+  const int ntiles = b.tile_hi[q] - b.tile_lo[q], nsplit = b.nsplit[q], mode = b.mode[q];
+  if ((int)blockIdx.x >= ntiles) return;
   int tr, tc;
-  tile_of(tile_lo + blockIdx.x, tr, tc);
+  tile_of(b.tile_lo[q] + blockIdx.x, tr, tc);
   const int idx = blockIdx.y * 256 + threadIdx.x, r = idx / SY_T, c = idx % SY_T;
   const int gr = tr * SY_T + r, gc = tc * SY_T + c;
   if (gr >= m || gc >= m || gc > gr) return;
+  const double* __restrict__ partial = b.partial[q];
   double s = 0.0;
   for (int p = 0; p < nsplit; ++p) s += partial[((int64_t)p * ntiles + blockIdx.x) * (SY_T * SY_T) + idx];
-  double* h = H + (int64_t)gr * ldh + gc;
+  double* h = b.H[q] + (int64_t)gr * ldh + gc;
   if (mode == 0)
-    *h = lam * KJJ[(int64_t)gr * ldh + gc] + s;
+    *h = b.lam[q] * b.KJJ[q][(int64_t)gr * ldh + gc] + s;
   else if (mode > 0)
     *h += s;
   else
     *h -= s;
 }
 
+void launch_syrk_reduce_batch(const ReduceBatch& b, int m, int64_t ldh, hipStream_t s) {
+  int nt = 0;
+  for (int q = 0; q < b.count; ++q) {
+    if (b.nsplit[q] < 1 || b.tile_lo[q] < 0 || b.tile_hi[q] > syrk_tiles(m))
+      throw Failure(1, "SYRK reduce batch: invalid slot descriptor");
+    nt = std::max(nt, b.tile_hi[q] - b.tile_lo[q]);
+  }
+  if (b.count <= 0 || b.count > kMaxBatch || nt <= 0) return;
+  hipLaunchKernelGGL(k_syrk_reduce, dim3(nt, SY_T * SY_T / 256, b.count), dim3(256), 0, s, b, m, ldh);
+  SPSVM_LAUNCHED();
+}
+
 void launch_syrk_reduce(const double* KJJ, int m, double lam, const double* partial, int nsplit, int tile_lo,
                         int tile_hi, int mode, double* H, int64_t ldh, hipStream_t s) {
-  const int nt = tile_hi - tile_lo;
-  if (nt <= 0) return;
-  hipLaunchKernelGGL(k_syrk_reduce, dim3(nt, SY_T * SY_T / 256), dim3(256), 0, s, KJJ, m, lam, partial, nsplit, nt,
-                     tile_lo, mode, H, ldh);
+  ReduceBatch b{};
+  b.KJJ[0] = KJJ;
+  b.partial[0] = partial;
+  b.H[0] = H;
+  b.lam[0] = lam;
+  b.nsplit[0] = nsplit;
+  b.tile_lo[0] = tile_lo;
+  b.tile_hi[0] = tile_hi;
+  b.mode[0] = mode;
+  b.count = 1;
+  launch_syrk_reduce_batch(b, m, ldh, s);
+}
+
+__global__ __launch_bounds__(256) void k_scaled_sum_lower(double* __restrict__ H, const double* __restrict__ KJJ,
+                                                          const double* __restrict__ G, double lam, int m,
+                                                          int64_t ldh) {
+  const int r = blockIdx.y;
+  for (int c = blockIdx.x * 256 + threadIdx.x; c <= r && c < m; c += gridDim.x * 256) {
+    const int64_t e = (int64_t)r * ldh + c;
+    H[e] = lam * KJJ[e] + G[e];
+  }
+}
+
+void launch_scaled_sum_lower(double* H, const double* KJJ, const double* G, double lam, int m, int64_t ldh,
+                             hipStream_t s) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_scaled_sum_lower, dim3((unsigned)ceil_div(m, 256), (unsigned)m), dim3(256), 0, s, H, KJJ, G,
+                     lam, m, ldh);
   SPSVM_LAUNCHED();
 }
 
@@ -743,6 +814,8 @@ template void launch_gradient<float>(const float*, int64_t, int, const int32_t*,
 template void launch_gradient<double>(const double*, int64_t, int, const int32_t*, int, const double*, const float*,
                                       const double*, const double*, double, double*, int, double*, NewtonScalars*,
                                       hipStream_t);
+template void launch_syrk_batch<float>(const SyrkBatch<float>&, int64_t, int, hipStream_t);
+template void launch_syrk_batch<double>(const SyrkBatch<double>&, int64_t, int, hipStream_t);
 template void launch_syrk<float>(const float*, int64_t, int, const int32_t*, int, int, int, int, double*, hipStream_t);
 template void launch_syrk<double>(const double*, int64_t, int, const int32_t*, int, int, int, int, double*,
                                   hipStream_t);

@@ -54,7 +54,7 @@ int64_t stage_size(int64_t J, int64_t J_max, double growth, int64_t cap) {
 
 // ------------------------------------------------------------------------------------------ workspace
 Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection, bool x_double,
-               bool x_aligned, bool batch) {
+               bool x_aligned, bool batch, int64_t problems) {
   Plan p;
   const int64_t xe = x_double ? 8 : 4;
   p.ldx = round_up(d, 16 / xe);
@@ -64,6 +64,8 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.d = d;
   p.J_max = J_max;
   p.tk_double = opt.precision == SPSVM_F64;
+  p.batch = batch;
+  p.slots = batch ? (int)std::max<int64_t>(1, std::min<int64_t>(problems, kBatchSlots)) : 1;
   p.ldk = round_up(J_max, 4);
   p.ldh = round_up(J_max, 4);
   const size_t tk = p.tk_double ? 8 : 4;
@@ -79,30 +81,13 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.hash = take(n * 8);
   p.KXJ = take((size_t)n * p.ldk * tk);
   p.Kc = take(with_selection ? (size_t)n * kCandSlots * tk : 0);
-  p.o = take(n * 8);
-  p.delta = take(n * 8);
-  p.act0 = take(n);
-  p.act1 = take(n);
-  p.I = take(n * 4);
-  p.cblk_cnt = take(nb_c * 4);
-  p.cblk_sum = take(nb_c * 8);
-  p.cblk_flips = take(nb_c * 4);
   p.J = take(J_max * 8);
   p.J32 = take(J_max * 4);
-  p.beta = take(J_max * 8);
-  p.dvec = take(J_max * 8);
-  p.g = take(J_max * 8);
-  p.z = take(J_max * 8);
-  p.H = take((size_t)J_max * p.ldh * 8);
-  p.Linv = take((size_t)ceil_div(J_max, kCholNB) * kCholNB * kCholNB * 8);
-  p.syrk_part = take(syrk_partial_doubles((int)J_max) * 8);
-  p.grad_part = take((size_t)1024 * 256 * 8);
   p.cand_state = take(kCandSlots * sizeof(CandState));
   p.sel = take(sizeof(Selection));
-  p.ls = take(sizeof(LineState));
-  p.scalars = take(sizeof(NewtonScalars));
+  p.ls = take(p.slots * sizeof(LineState));
+  p.scalars = take(p.slots * sizeof(NewtonScalars));
   p.score_part = take((size_t)nb_s * kCandSlots * 4 * 8);
-  p.ls_part = take((size_t)nb_s * 6 * 8);
   p.cand_table = take((size_t)cap * kCandSlots * 4);
   p.stage_hash = take(cap * 8);
   p.m_dev = take(4);
@@ -110,19 +95,49 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.XJ64 = take((size_t)J_max * p.ldj * 8);
   p.xjnorm = take(J_max * 8);
   p.KJJ = take((size_t)J_max * p.ldh * 8);
-  p.vJ = take(J_max * 8);
-  p.wJ = take(J_max * 8);
   p.iota = take(J_max * 4);
   p.incomplete = take(8);
   p.o_stage = take(with_selection ? n * 8 : 0);
-  p.Hf = take((size_t)J_max * p.ldh * 8);
-  p.F_in = take(n * 4);
-  p.F_out = take(n * 4);
-  p.fcnt_in = take(nb_c * 4);
-  p.fcnt_out = take(nb_c * 4);
   p.Xp = take(p.pad_x ? (size_t)n * p.ldx * xe : 0);
   p.D = take(batch ? (size_t)n * p.ldk * tk : 0);
   p.DJJ = take(batch ? (size_t)J_max * p.ldh * 8 : 0);
+  p.G = take(batch ? (size_t)J_max * p.ldh * 8 : 0);
+  // one problem's Newton state
+  {
+    size_t so = 0;
+    auto st = [&](size_t bytes) {
+      const size_t at = so;
+      so += (size_t)round_up((int64_t)std::max<size_t>(bytes, 1), 256);
+      return at;
+    };
+    SlotPlan& q = p.slot;
+    q.o = st(n * 8);
+    q.delta = st(n * 8);
+    q.act0 = st(n);
+    q.act1 = st(n);
+    q.I = st(n * 4);
+    q.cblk_cnt = st(nb_c * 4);
+    q.cblk_sum = st(nb_c * 8);
+    q.cblk_flips = st(nb_c * 4);
+    q.beta = st(J_max * 8);
+    q.dvec = st(J_max * 8);
+    q.g = st(J_max * 8);
+    q.z = st(J_max * 8);
+    q.H = st((size_t)J_max * p.ldh * 8);
+    q.Hf = st((size_t)J_max * p.ldh * 8);
+    q.Linv = st((size_t)ceil_div(J_max, kCholNB) * kCholNB * kCholNB * 8);
+    q.syrk_part = st((batch ? syrk_partial_doubles_batch((int)J_max) : syrk_partial_doubles((int)J_max)) * 8);
+    q.grad_part = st((size_t)1024 * 256 * 8);
+    q.ls_part = st((size_t)nb_s * 6 * 8);
+    q.vJ = st(J_max * 8);
+    q.wJ = st(J_max * 8);
+    q.F_in = st(n * 4);
+    q.F_out = st(n * 4);
+    q.fcnt_in = st(nb_c * 4);
+    q.fcnt_out = st(nb_c * 4);
+    q.bytes = so;
+  }
+  p.slots_at = take((size_t)p.slots * p.slot.bytes);
   p.bytes = off;
   return p;
 }
@@ -226,8 +241,6 @@ struct Impl {
   double *XJ64, *xjnorm, *KJJ, *vJ, *wJ, *o_stage, *Hf;
   int32_t *iota, *incomplete, *F_in, *F_out, *fcnt_in, *fcnt_out;
   bool bf16_exact = false;  // every X value is exactly a BF16 number (split-BF16 lo parts are all zero)
-  bool hb_valid = false;  // H (unfactored) holds lambda K_JJ + K_I^T K_I for the first m_fact basis vectors and
-  int m_fact = 0;         // the violator status in act_fact
   uint8_t *act_fact, *act_cur;
   int32_t *I, *cblk_cnt, *cblk_flips, *cand_table, *m_dev, *flags, *J32;
   int64_t* J;
@@ -237,6 +250,32 @@ struct Impl {
   NewtonScalars* sc;
   std::vector<uint64_t> hash_host;
 
+  // One problem's Newton state. A training run uses slot 0 (its buffers are also the members above); a batch
+  // runs up to kBatchSlots problems in lockstep, one per slot.
+  struct Slot {
+    const float* y = nullptr;
+    double C = 1.0, lam = 1.0;
+    const TK* K = nullptr;         // n x ldk kernel block of the basis
+    const double* KJJ = nullptr;   // FP64 kernel matrix of the basis (ldh)
+    double *o, *delta, *beta, *dvec, *g, *z, *H, *Hf, *Linv, *syrk_part, *grad_part, *ls_part, *cblk_sum, *vJ, *wJ;
+    uint8_t *act_fact, *act_cur;
+    int32_t *I, *cblk_cnt, *cblk_flips, *F_in, *F_out, *fcnt_in, *fcnt_out;
+    NewtonScalars* sc;
+    LineState* ls;
+    spsvm_stats* stats = nullptr;  // counters this slot's solves add to
+    spsvm_stats own{};
+    bool hb_valid = false;  // H (unfactored) holds lambda K_JJ + K_I^T K_I for the first m_fact basis vectors and
+    int m_fact = 0;         // the violator status in act_fact
+    // the current solve
+    bool fact_valid = false;
+    double g0 = 0.0, f = 0.0;
+    int it = 0, tr0 = 0, n_in = 0, n_out = 0;
+    NewtonScalars s{};
+    LineState L{};
+  };
+  std::vector<Slot> slots;
+  Pinned pin_slots;
+
   template <typename T>
   T* at(size_t off) {
     return reinterpret_cast<T*>(base + off);
@@ -245,7 +284,8 @@ struct Impl {
   Impl(const TX* X_, const float* y_, int64_t n_, int64_t d_, double C_, double g_, int64_t Jm, const spsvm_options& o_,
        void* ws, hipStream_t s, const Plan& plan)
       : X(X_), y(y_), n(n_), d(d_), J_max(Jm), C(C_), gamma(g_), lam(1.0 / C_), opt(o_), st(s), p(plan),
-        base((char*)ws), pin(kPinnedScalars + (size_t)o_.chunk_cap * kCandSlots * 4) {
+        base((char*)ws), pin(kPinnedScalars + (size_t)o_.chunk_cap * kCandSlots * 4),
+        pin_slots((size_t)plan.slots * (sizeof(NewtonScalars) + sizeof(LineState))) {
     prof.st = s;
     prof.mask = o_.profile;
     Xk = p.pad_x ? at<TX>(p.Xp) : X;
@@ -254,24 +294,7 @@ struct Impl {
     Kc = at<TK>(p.Kc);
     hash = at<uint64_t>(p.hash);
     stage_hash = at<uint64_t>(p.stage_hash);
-    o = at<double>(p.o);
-    delta = at<double>(p.delta);
-    beta = at<double>(p.beta);
-    dvec = at<double>(p.dvec);
-    g = at<double>(p.g);
-    z = at<double>(p.z);
-    H = at<double>(p.H);
-    Linv = at<double>(p.Linv);
-    syrk_part = at<double>(p.syrk_part);
-    grad_part = at<double>(p.grad_part);
     score_part = at<double>(p.score_part);
-    ls_part = at<double>(p.ls_part);
-    cblk_sum = at<double>(p.cblk_sum);
-    act_fact = at<uint8_t>(p.act0);
-    act_cur = at<uint8_t>(p.act1);
-    I = at<int32_t>(p.I);
-    cblk_cnt = at<int32_t>(p.cblk_cnt);
-    cblk_flips = at<int32_t>(p.cblk_flips);
     cand_table = at<int32_t>(p.cand_table);
     m_dev = at<int32_t>(p.m_dev);
     flags = at<int32_t>(p.flags);
@@ -279,21 +302,77 @@ struct Impl {
     J = at<int64_t>(p.J);
     cst = at<CandState>(p.cand_state);
     sel = at<Selection>(p.sel);
-    ls = at<LineState>(p.ls);
-    sc = at<NewtonScalars>(p.scalars);
     XJ64 = at<double>(p.XJ64);
     xjnorm = at<double>(p.xjnorm);
     KJJ = at<double>(p.KJJ);
-    vJ = at<double>(p.vJ);
-    wJ = at<double>(p.wJ);
     iota = at<int32_t>(p.iota);
     incomplete = at<int32_t>(p.incomplete);
     o_stage = at<double>(p.o_stage);
-    Hf = at<double>(p.Hf);
-    F_in = at<int32_t>(p.F_in);
-    F_out = at<int32_t>(p.F_out);
-    fcnt_in = at<int32_t>(p.fcnt_in);
-    fcnt_out = at<int32_t>(p.fcnt_out);
+    slots.resize(p.slots);
+    for (int q = 0; q < p.slots; ++q) {
+      Slot& S = slots[q];
+      char* b = base + p.slots_at + (size_t)q * p.slot.bytes;
+      const SlotPlan& sp = p.slot;
+      S.o = (double*)(b + sp.o);
+      S.delta = (double*)(b + sp.delta);
+      S.beta = (double*)(b + sp.beta);
+      S.dvec = (double*)(b + sp.dvec);
+      S.g = (double*)(b + sp.g);
+      S.z = (double*)(b + sp.z);
+      S.H = (double*)(b + sp.H);
+      S.Hf = (double*)(b + sp.Hf);
+      S.Linv = (double*)(b + sp.Linv);
+      S.syrk_part = (double*)(b + sp.syrk_part);
+      S.grad_part = (double*)(b + sp.grad_part);
+      S.ls_part = (double*)(b + sp.ls_part);
+      S.cblk_sum = (double*)(b + sp.cblk_sum);
+      S.vJ = (double*)(b + sp.vJ);
+      S.wJ = (double*)(b + sp.wJ);
+      S.act_fact = (uint8_t*)(b + sp.act0);
+      S.act_cur = (uint8_t*)(b + sp.act1);
+      S.I = (int32_t*)(b + sp.I);
+      S.cblk_cnt = (int32_t*)(b + sp.cblk_cnt);
+      S.cblk_flips = (int32_t*)(b + sp.cblk_flips);
+      S.F_in = (int32_t*)(b + sp.F_in);
+      S.F_out = (int32_t*)(b + sp.F_out);
+      S.fcnt_in = (int32_t*)(b + sp.fcnt_in);
+      S.fcnt_out = (int32_t*)(b + sp.fcnt_out);
+      S.sc = at<NewtonScalars>(p.scalars) + q;
+      S.ls = at<LineState>(p.ls) + q;
+      S.stats = p.batch ? &S.own : &stats;
+    }
+    Slot& s0 = slots[0];
+    s0.y = y;
+    s0.C = C;
+    s0.lam = lam;
+    s0.K = KXJ;
+    s0.KJJ = KJJ;
+    o = s0.o;
+    delta = s0.delta;
+    beta = s0.beta;
+    dvec = s0.dvec;
+    g = s0.g;
+    z = s0.z;
+    H = s0.H;
+    Hf = s0.Hf;
+    Linv = s0.Linv;
+    syrk_part = s0.syrk_part;
+    grad_part = s0.grad_part;
+    ls_part = s0.ls_part;
+    cblk_sum = s0.cblk_sum;
+    vJ = s0.vJ;
+    wJ = s0.wJ;
+    act_fact = s0.act_fact;
+    act_cur = s0.act_cur;
+    I = s0.I;
+    cblk_cnt = s0.cblk_cnt;
+    cblk_flips = s0.cblk_flips;
+    F_in = s0.F_in;
+    F_out = s0.F_out;
+    fcnt_in = s0.fcnt_in;
+    fcnt_out = s0.fcnt_out;
+    sc = s0.sc;
+    ls = s0.ls;
   }
 
   // The n x N kernel block in the training precision (split-BF16 products in MIXED mode).
@@ -369,140 +448,281 @@ struct Impl {
     if (f[1]) throw Failure(SPSVM_E_INVALID_ARG, "labels must be exactly +1 or -1");
   }
 
-  // ------------------------------------------------------------------------------------ Newton at fixed J
-  // Returns the number of iterations.
-  int newton(int m) {
-    if (m <= 0) return 0;
-    launch_gemv<TK>(KXJ, p.ldk, n, m, beta, o, st);
-    bool fact_valid = false;
-    double g0 = 0.0;
-    int it = 0;
-    for (; it < opt.newton_max_iter; ++it) {
-      launch_compact(o, y, n, hb_valid ? act_fact : nullptr, act_cur, I, cblk_cnt, cblk_sum, cblk_flips, sc, st);
-      NewtonScalars s = read(sc);
-      const int nchunk = gradient_chunks(m, s.n_sv);
-      launch_gemv<double>(KJJ, p.ldh, m, m, beta, vJ, st);
-      launch_gradient<TK>(KXJ, p.ldk, m, I, s.n_sv, o, y, vJ, beta, lam, grad_part, nchunk, g, sc, st);
-      s = read(sc);
-      const double gn = std::sqrt(s.gnorm2);
-      const double f = 0.5 * lam * s.beta_oJ + 0.5 * s.sum_a2;
-      if (!std::isfinite(f) || !std::isfinite(gn))
-        throw Failure(SPSVM_E_NO_CONVERGENCE, "non-finite objective or gradient in Newton (m=" + std::to_string(m) + ")");
-      if (it == 0) g0 = gn;
-      if (opt.log_level >= 2)
-        std::fprintf(stderr, "[spsvm]   newton it=%d m=%d f=%.15e |g|=%.3e n_sv=%d flips=%d\n", it, m, f, gn, s.n_sv,
-                     s.flips);
-      if (gn <= opt.newton_tol * std::max(1.0, g0)) break;
-      if (!fact_valid || s.flips > opt.refactor_frac * std::max(1, s.n_sv)) {
-        factorize(m, s.n_sv);
-        fact_valid = true;
-        std::swap(act_fact, act_cur);
-      }
-      launch_chol_solve(Hf, p.ldh, m, Linv, g, dvec, z, st);
-      launch_gemv<TK>(KXJ, p.ldk, n, m, dvec, delta, st);
-      launch_gemv<double>(KJJ, p.ldh, m, m, dvec, wJ, st);
-      launch_c1c2(beta, dvec, wJ, m, ls, st);
-      const int nblk = score_blocks(n);
-      LineState L;
-      int rounds = 0;
-      for (;;) {
-        for (int r = 0; r < 3; ++r) launch_ls_round(o, delta, y, n, lam, ls, ls_part, nblk, st);
-        rounds += 3;
-        L = read(ls);
-        if (L.status != 0 || rounds >= 66) break;
-      }
-      stats.ls_passes += L.passes;
-      launch_apply_step(ls, beta, dvec, m, o, delta, n, st);
-      if (L.t == 0.0) {
-        ++it;
-        break;
-      }
-      if (L.dec <= opt.newton_ftol * f) {
-        ++it;
-        break;
-      }
-    }
-    if (it >= opt.newton_max_iter) stats.iter_cap_hits += 1;
-    stats.newton_iters += it;
-    return it;
+  // Reads every slot's NewtonScalars (or LineState) back in one copy.
+  void read_slots() {
+    const size_t b = slots.size() * sizeof(NewtonScalars);
+    SPSVM_HIP(hipMemcpyAsync(pin_slots.p, slots[0].sc, b, hipMemcpyDeviceToHost, st));
+    sync();
+    for (size_t q = 0; q < slots.size(); ++q) std::memcpy(&slots[q].s, (char*)pin_slots.p + q * sizeof(NewtonScalars), sizeof(NewtonScalars));
+  }
+  void read_slot_lines() {
+    const size_t b = slots.size() * sizeof(LineState);
+    SPSVM_HIP(hipMemcpyAsync(pin_slots.p, slots[0].ls, b, hipMemcpyDeviceToHost, st));
+    sync();
+    for (size_t q = 0; q < slots.size(); ++q) std::memcpy(&slots[q].L, (char*)pin_slots.p + q * sizeof(LineState), sizeof(LineState));
   }
 
-  // Forms H = lambda K_JJ + K_I^T K_I for the current basis (m) and violator status (act_cur), then factors a
-  // copy. Tile rows of H that already existed at the last factorisation are updated with the rows that joined
-  // or left the violator set (exact FP64 products, so the update loses nothing); the remaining tile rows are
-  // recomputed over all violators. A full recomputation is chosen when it is cheaper.
-  void factorize(int m, int n_sv) {
+  // ------------------------------------------------------------------------------------ Newton at fixed J
+  // Newton re-optimisation of beta at a fixed basis of m vectors, for the given slots in lockstep: each phase
+  // is launched for every unfinished slot before the host reads their scalars back in one copy, and the SYRK,
+  // Cholesky and triangular solves of all slots are batched launches. Every slot takes exactly the decisions
+  // and kernel calls of a solve on its own. Returns the iterations of the first slot.
+  int newton(int m) { return newton_slots(m, {0}); }
+
+  int newton_slots(int m, const std::vector<int>& ids) {
+    if (m <= 0 || ids.empty()) return 0;
+    std::vector<int> act;
+    for (int q : ids) {
+      Slot& S = slots[q];
+      launch_gemv<TK>(S.K, p.ldk, n, m, S.beta, S.o, st);
+      S.fact_valid = false;
+      S.g0 = 0.0;
+      S.it = 0;
+      act.push_back(q);
+    }
+    auto finish = [&](Slot& S) {
+      if (S.it >= opt.newton_max_iter) S.stats->iter_cap_hits += 1;
+      S.stats->newton_iters += S.it;
+    };
+    const int first = ids[0];
+    int first_its = 0;
+    while (!act.empty()) {
+      for (int q : act) {
+        Slot& S = slots[q];
+        launch_compact(S.o, S.y, n, S.hb_valid ? S.act_fact : nullptr, S.act_cur, S.I, S.cblk_cnt, S.cblk_sum,
+                       S.cblk_flips, S.sc, st);
+      }
+      read_slots();
+      for (int q : act) {
+        Slot& S = slots[q];
+        const int nchunk = gradient_chunks(m, S.s.n_sv);
+        launch_gemv<double>(S.KJJ, p.ldh, m, m, S.beta, S.vJ, st);
+        launch_gradient<TK>(S.K, p.ldk, m, S.I, S.s.n_sv, S.o, S.y, S.vJ, S.beta, S.lam, S.grad_part, nchunk, S.g,
+                            S.sc, st);
+      }
+      read_slots();
+      std::vector<int> go, refac;
+      for (int q : act) {
+        Slot& S = slots[q];
+        const double gn = std::sqrt(S.s.gnorm2);
+        S.f = 0.5 * S.lam * S.s.beta_oJ + 0.5 * S.s.sum_a2;
+        if (!std::isfinite(S.f) || !std::isfinite(gn))
+          throw Failure(SPSVM_E_NO_CONVERGENCE, "non-finite objective or gradient in Newton (m=" + std::to_string(m) + ")");
+        if (S.it == 0) S.g0 = gn;
+        if (opt.log_level >= 2)
+          std::fprintf(stderr, "[spsvm]   newton slot=%d it=%d m=%d f=%.15e |g|=%.3e n_sv=%d flips=%d\n", q, S.it, m,
+                       S.f, gn, S.s.n_sv, S.s.flips);
+        if (gn <= opt.newton_tol * std::max(1.0, S.g0)) {
+          finish(S);
+          if (q == first) first_its = S.it;
+          continue;
+        }
+        go.push_back(q);
+        if (!S.fact_valid || S.s.flips > opt.refactor_frac * std::max(1, S.s.n_sv)) refac.push_back(q);
+      }
+      if (go.empty()) break;
+      factorize_slots(m, refac);
+      for (int q : refac) {
+        Slot& S = slots[q];
+        S.fact_valid = true;
+        std::swap(S.act_fact, S.act_cur);
+      }
+      for (size_t a = 0; a < go.size(); a += kMaxBatch) {
+        SolveBatch sb{};
+        for (size_t k = a; k < go.size() && k < a + kMaxBatch; ++k) {
+          const Slot& S = slots[go[k]];
+          const int c = sb.count++;
+          sb.L[c] = S.Hf;
+          sb.Linv[c] = S.Linv;
+          sb.g[c] = S.g;
+          sb.x[c] = S.dvec;
+          sb.work[c] = S.z;
+        }
+        launch_chol_solve_batch(sb, p.ldh, m, st);
+      }
+      for (int q : go) {
+        Slot& S = slots[q];
+        launch_gemv<TK>(S.K, p.ldk, n, m, S.dvec, S.delta, st);
+        launch_gemv<double>(S.KJJ, p.ldh, m, m, S.dvec, S.wJ, st);
+        launch_c1c2(S.beta, S.dvec, S.wJ, m, S.ls, st);
+      }
+      const int nblk = score_blocks(n);
+      std::vector<int> lsq = go;
+      int rounds = 0;
+      while (!lsq.empty()) {
+        for (int q : lsq) {
+          Slot& S = slots[q];
+          for (int r = 0; r < 3; ++r) launch_ls_round(S.o, S.delta, S.y, n, S.lam, S.ls, S.ls_part, nblk, st);
+        }
+        rounds += 3;
+        read_slot_lines();
+        std::vector<int> keep;
+        for (int q : lsq)
+          if (slots[q].L.status == 0 && rounds < 66) keep.push_back(q);
+        lsq.swap(keep);
+      }
+      act.clear();
+      for (int q : go) {
+        Slot& S = slots[q];
+        S.stats->ls_passes += S.L.passes;
+        launch_apply_step(S.ls, S.beta, S.dvec, m, S.o, S.delta, n, st);
+        S.it += 1;
+        if (S.L.t == 0.0 || S.L.dec <= opt.newton_ftol * S.f || S.it >= opt.newton_max_iter) {
+          finish(S);
+          if (q == first) first_its = S.it;
+        } else {
+          act.push_back(q);
+        }
+      }
+    }
+    return first_its;
+  }
+
+  // For the given slots: forms H = lambda K_JJ + K_I^T K_I for the current basis (m) and violator status
+  // (act_cur), then factors a copy. Tile rows of H that already existed at the slot's last factorisation are
+  // updated with the rows that joined or left the violator set (exact FP64 products, so the update loses
+  // nothing); the remaining tile rows are recomputed over all violators. A full recomputation is chosen when it
+  // is cheaper.
+  void factorize(int m) { factorize_slots(m, {0}); }
+
+  void factorize_slots(int m, const std::vector<int>& ids) {
+    if (ids.empty()) return;
     const int B = syrk_tile_size();
     const int T = syrk_tile_rows(m), ntile = T * (T + 1) / 2;
-    int tr0 = 0, n_in = 0, n_out = 0;
-    if (hb_valid) {
-      launch_flip_lists(act_cur, act_fact, n, fcnt_in, fcnt_out, F_in, F_out, sc, st);
-      const NewtonScalars s = read(sc);
-      n_in = s.n_in;
-      n_out = s.n_out;
-      const int t0 = m_fact / B;
-      const double r0 = (double)t0 * B;
-      const double cost_inc = (double)(n_in + n_out) * r0 * r0 + (double)n_sv * ((double)m * m - r0 * r0);
-      const double cost_full = (double)n_sv * m * m;
-      if (cost_inc < 0.8 * cost_full) tr0 = t0;
-    }
-    const int t_old = tr0 * (tr0 + 1) / 2;
-    const double r0 = (double)tr0 * B;
-    auto syrk_part = [&](const int32_t* rows, int nrows, int lo, int hi, int mode, double work) {
-      if (nrows <= 0 || hi <= lo) return;
-      const int ns = syrk_splits(hi - lo, nrows);
-      prof.timed(kProfSyrk, work, [&] { launch_syrk<TK>(KXJ, p.ldk, m, rows, nrows, lo, hi, ns, this->syrk_part, st); });
-      launch_syrk_reduce(KJJ, m, lam, this->syrk_part, ns, lo, hi, mode, H, p.ldh, st);
-    };
-    if (tr0 > 0) {
-      syrk_part(F_in, n_in, 0, t_old, +1, (double)n_in * r0 * (r0 + 1.0));
-      syrk_part(F_out, n_out, 0, t_old, -1, (double)n_out * r0 * (r0 + 1.0));
-      stats.incremental_factorizations += 1;
-    }
-    if (t_old < ntile) {
-      if (n_sv > 0) {
-        syrk_part(I, n_sv, t_old, ntile, 0, (double)n_sv * ((double)m * (m + 1.0) - r0 * (r0 + 1.0)));
-      } else {  // no violators: H = lambda K_JJ on the recomputed tiles
-        launch_syrk<TK>(KXJ, p.ldk, m, I, 0, t_old, ntile, 1, this->syrk_part, st);
-        launch_syrk_reduce(KJJ, m, lam, this->syrk_part, 1, t_old, ntile, 0, H, p.ldh, st);
+    bool any = false;
+    for (int q : ids) {
+      Slot& S = slots[q];
+      if (S.hb_valid) {
+        launch_flip_lists(S.act_cur, S.act_fact, n, S.fcnt_in, S.fcnt_out, S.F_in, S.F_out, S.sc, st);
+        any = true;
       }
     }
-    hb_valid = true;
-    m_fact = m;
-    // factor a copy of H (H itself is kept for the next update)
-    SPSVM_HIP(hipMemcpyAsync(Hf, H, (size_t)m * p.ldh * 8, hipMemcpyDeviceToDevice, st));
-    SPSVM_HIP(hipMemsetAsync(&sc->fail, 0, 4, st));
-    prof.timed(kProfChol, (double)m * m * m / 3.0, [&] { launch_cholesky(Hf, p.ldh, m, Linv, sc, st); });
-    stats.factorizations += 1;
-    if (read(&sc->fail) == 0) return;
-    // jitter retries: H + mu * mean(diag H) * I
-    launch_trace(H, p.ldh, m, sc, st);
-    const double mean_diag = read(&sc->trace) / m;
-    for (double mu : {1e-14, 1e-12, 1e-10, 1e-8}) {
-      SPSVM_HIP(hipMemcpyAsync(Hf, H, (size_t)m * p.ldh * 8, hipMemcpyDeviceToDevice, st));
-      launch_add_diag(Hf, p.ldh, m, mu * mean_diag, st);
-      SPSVM_HIP(hipMemsetAsync(&sc->fail, 0, 4, st));
-      launch_cholesky(Hf, p.ldh, m, Linv, sc, st);
-      stats.factorizations += 1;
-      if (read(&sc->fail) == 0) return;
+    if (any) read_slots();
+    for (int q : ids) {
+      Slot& S = slots[q];
+      S.tr0 = 0;
+      S.n_in = S.n_out = 0;
+      if (!S.hb_valid) continue;
+      S.n_in = S.s.n_in;
+      S.n_out = S.s.n_out;
+      // tile rows of H that are complete: all of them when the basis has not grown since, else those below
+      // the last factorisation's partial tile row
+      const int t0 = S.m_fact == m ? T : S.m_fact / B;
+      const double r0 = std::min<double>((double)t0 * B, m);
+      const double cost_inc = (double)(S.n_in + S.n_out) * r0 * r0 + (double)S.s.n_sv * ((double)m * m - r0 * r0);
+      const double cost_full = (double)S.s.n_sv * m * m;
+      if (cost_inc < 0.8 * cost_full) S.tr0 = t0;
     }
-    throw Failure(SPSVM_E_NOT_PD, "Newton matrix not positive definite after jitter retries (m=" + std::to_string(m) + ")");
+    // The three row sets (joined, left, recomputed tiles) run as batched SYRK launches, each followed by its
+    // reduction into H (a slot's partial buffer is reused by the next set).
+    for (int kind : {+1, -1, 0}) {
+      std::vector<int> use;
+      for (int q : ids) {
+        const Slot& S = slots[q];
+        const int t_old = S.tr0 * (S.tr0 + 1) / 2;
+        if (kind != 0 && (S.tr0 == 0 || (kind > 0 ? S.n_in : S.n_out) <= 0)) continue;
+        if (kind == 0 && t_old >= ntile) continue;
+        use.push_back(q);
+      }
+      for (size_t a = 0; a < use.size(); a += kMaxBatch) {
+        SyrkBatch<TK> sb{};
+        ReduceBatch rb{};
+        double work = 0.0;
+        const int cnt = (int)std::min<size_t>(kMaxBatch, use.size() - a);
+        for (int k = 0; k < cnt; ++k) {
+          Slot& S = slots[use[a + k]];
+          const int t_old = S.tr0 * (S.tr0 + 1) / 2;
+          const double r0 = std::min<double>((double)S.tr0 * B, m);
+          const int32_t* rows = kind > 0 ? S.F_in : (kind < 0 ? S.F_out : S.I);
+          const int nrows = kind > 0 ? S.n_in : (kind < 0 ? S.n_out : S.s.n_sv);
+          const int lo = kind == 0 ? t_old : 0, hi = kind == 0 ? ntile : t_old;
+          const int ns = nrows <= 0 ? 1 : (p.batch ? syrk_splits_batch(hi - lo, nrows) : syrk_splits(hi - lo, nrows));
+          sb.K[k] = S.K;
+          sb.rows[k] = rows;
+          sb.partial[k] = S.syrk_part;
+          sb.n_rows[k] = std::max(nrows, 0);
+          sb.nsplit[k] = ns;
+          sb.tile_lo[k] = lo;
+          sb.tile_hi[k] = hi;
+          rb.KJJ[k] = S.KJJ;
+          rb.partial[k] = S.syrk_part;
+          rb.H[k] = S.H;
+          rb.lam[k] = S.lam;
+          rb.nsplit[k] = ns;
+          rb.tile_lo[k] = lo;
+          rb.tile_hi[k] = hi;
+          rb.mode[k] = kind;
+          work += kind == 0 ? (double)nrows * ((double)m * (m + 1.0) - r0 * (r0 + 1.0)) : (double)nrows * r0 * (r0 + 1.0);
+        }
+        sb.count = rb.count = cnt;
+        if (work > 0.0)
+          prof.timed(kProfSyrk, work, [&] { launch_syrk_batch<TK>(sb, p.ldk, m, st); });
+        else
+          launch_syrk_batch<TK>(sb, p.ldk, m, st);
+        launch_syrk_reduce_batch(rb, m, p.ldh, st);
+      }
+    }
+    for (int q : ids) {
+      Slot& S = slots[q];
+      if (S.tr0 > 0) S.stats->incremental_factorizations += 1;
+      S.hb_valid = true;
+      S.m_fact = m;
+      // factor a copy of H (H itself is kept for the next update)
+      SPSVM_HIP(hipMemcpyAsync(S.Hf, S.H, (size_t)m * p.ldh * 8, hipMemcpyDeviceToDevice, st));
+      SPSVM_HIP(hipMemsetAsync(&S.sc->fail, 0, 4, st));
+      S.stats->factorizations += 1;
+    }
+    for (size_t a = 0; a < ids.size(); a += kMaxBatch) {
+      CholBatch cb{};
+      for (size_t k = a; k < ids.size() && k < a + kMaxBatch; ++k) {
+        const Slot& S = slots[ids[k]];
+        const int c = cb.count++;
+        cb.H[c] = S.Hf;
+        cb.Linv[c] = S.Linv;
+        cb.sc[c] = S.sc;
+      }
+      prof.timed(kProfChol, cb.count * (double)m * m * m / 3.0, [&] { launch_cholesky_batch(cb, p.ldh, m, st); });
+    }
+    read_slots();
+    for (int q : ids) {
+      Slot& S = slots[q];
+      if (S.s.fail == 0) continue;
+      // jitter retries: H + mu * mean(diag H) * I
+      launch_trace(S.H, p.ldh, m, S.sc, st);
+      const double mean_diag = read(&S.sc->trace) / m;
+      bool ok = false;
+      for (double mu : {1e-14, 1e-12, 1e-10, 1e-8}) {
+        SPSVM_HIP(hipMemcpyAsync(S.Hf, S.H, (size_t)m * p.ldh * 8, hipMemcpyDeviceToDevice, st));
+        launch_add_diag(S.Hf, p.ldh, m, mu * mean_diag, st);
+        SPSVM_HIP(hipMemsetAsync(&S.sc->fail, 0, 4, st));
+        launch_cholesky(S.Hf, p.ldh, m, S.Linv, S.sc, st);
+        S.stats->factorizations += 1;
+        if (read(&S.sc->fail) == 0) {
+          ok = true;
+          break;
+        }
+      }
+      if (!ok)
+        throw Failure(SPSVM_E_NOT_PD,
+                      "Newton matrix not positive definite after jitter retries (m=" + std::to_string(m) + ")");
+    }
   }
 
-  // Objective and residual statistics at the current beta (o is recomputed).
-  void final_eval(int m, double* F, NewtonScalars* out) {
+  // Objective and residual statistics at the slot's current beta (o is recomputed).
+  void final_eval(Slot& S, int m, double* F, NewtonScalars* out) {
     if (m == 0) {
-      *F = C * 0.5 * (double)n;
+      *F = S.C * 0.5 * (double)n;
       return;
     }
-    launch_gemv<TK>(KXJ, p.ldk, n, m, beta, o, st);
-    launch_compact(o, y, n, nullptr, act_cur, I, cblk_cnt, cblk_sum, cblk_flips, sc, st);
-    NewtonScalars s = read(sc);
-    launch_gemv<double>(KJJ, p.ldh, m, m, beta, vJ, st);
-    launch_gradient<TK>(KXJ, p.ldk, m, I, s.n_sv, o, y, vJ, beta, lam, grad_part, gradient_chunks(m, s.n_sv), g, sc, st);
-    s = read(sc);
+    launch_gemv<TK>(S.K, p.ldk, n, m, S.beta, S.o, st);
+    launch_compact(S.o, S.y, n, nullptr, S.act_cur, S.I, S.cblk_cnt, S.cblk_sum, S.cblk_flips, S.sc, st);
+    NewtonScalars s = read(S.sc);
+    launch_gemv<double>(S.KJJ, p.ldh, m, m, S.beta, S.vJ, st);
+    launch_gradient<TK>(S.K, p.ldk, m, S.I, s.n_sv, S.o, S.y, S.vJ, S.beta, S.lam, S.grad_part,
+                        gradient_chunks(m, s.n_sv), S.g, S.sc, st);
+    s = read(S.sc);
     *out = s;
-    *F = C * (0.5 * lam * s.beta_oJ + 0.5 * s.sum_a2);
+    *F = S.C * (0.5 * S.lam * s.beta_oJ + 0.5 * s.sum_a2);
   }
 
   // ------------------------------------------------------------------------------------ greedy training
@@ -643,36 +863,73 @@ struct Impl {
     launch_kblock<double, double>(XJ64, p.ldj, m, d, xjnorm, iota, (int)m, DJJ, p.ldh, 0.0, st);
     sync();
     const double dist_s = secs(t0, clk::now());
+    // Problems with the same gamma share the kernel block; they run in lockstep, up to one per slot.
     std::vector<char> done(P, 0);
+    const int Q = (int)slots.size();
     for (int64_t a = 0; a < P; ++a) {
       if (done[a]) continue;
       const double g = gs[a];
       launch_rbf_from_dist<TK>(D, n, (int)m, p.ldk, KXJ, g, st);
       launch_rbf_from_dist<double>(DJJ, m, (int)m, p.ldh, KJJ, g, st);
-      for (int64_t q = a; q < P; ++q) {
-        if (done[q] || gs[q] != g) continue;
-        done[q] = 1;
+      gamma = g;
+      std::vector<int64_t> group;
+      for (int64_t q = a; q < P; ++q)
+        if (!done[q] && gs[q] == g) {
+          done[q] = 1;
+          group.push_back(q);
+        }
+      // At beta = 0 every row is a violator, so every problem of the group starts from H = lambda K_JJ + K^T K
+      // with the same K^T K (labels do not enter it): it is formed once over all n rows.
+      double* G = at<double>(p.G);
+      {
+        Slot& S0 = slots[0];
+        const int T = syrk_tile_rows((int)m), ntile = T * (T + 1) / 2;
+        launch_iota(S0.I, n, st);
+        const int ns = syrk_splits_batch(ntile, (int)n);
+        prof.timed(kProfSyrk, (double)n * m * (m + 1.0),
+                   [&] { launch_syrk<TK>(KXJ, p.ldk, (int)m, S0.I, (int)n, 0, ntile, ns, S0.syrk_part, st); });
+        launch_syrk_reduce(KJJ, (int)m, 0.0, S0.syrk_part, ns, 0, ntile, 0, G, p.ldh, st);
+      }
+      for (size_t c0 = 0; c0 < group.size(); c0 += Q) {
         const auto t1 = clk::now();
-        stats = spsvm_stats{};
-        y = Y + q * n;
-        C = Cs[q];
-        lam = 1.0 / C;
-        gamma = g;
-        hb_valid = false;
-        SPSVM_HIP(hipMemsetAsync(beta, 0, m * 8, st));
-        newton((int)m);
-        stats.stages = 1;
-        stats.seconds_select = dist_s / P;  // share of the distance block
-        stats.seconds_newton = secs(t1, clk::now());
-        outs[q] = build_model((int)m);
+        std::vector<int> ids;
+        for (size_t k = c0; k < group.size() && k < c0 + Q; ++k) {
+          const int64_t q = group[k];
+          Slot& S = slots[ids.size()];
+          S.own = spsvm_stats{};
+          S.y = Y + q * n;
+          S.C = Cs[q];
+          S.lam = 1.0 / Cs[q];
+          S.K = KXJ;
+          S.KJJ = KJJ;
+          launch_scaled_sum_lower(S.H, KJJ, G, S.lam, (int)m, p.ldh, st);
+          SPSVM_HIP(hipMemsetAsync(S.act_fact, 1, n, st));  // every row a violator, as at beta = 0
+          S.hb_valid = true;
+          S.m_fact = (int)m;
+          SPSVM_HIP(hipMemsetAsync(S.beta, 0, m * 8, st));
+          ids.push_back((int)ids.size());
+        }
+        newton_slots((int)m, ids);
+        sync();
+        const double share = secs(t1, clk::now()) / ids.size();
+        for (size_t k = 0; k < ids.size(); ++k) {
+          Slot& S = slots[ids[k]];
+          S.own.stages = 1;
+          S.own.seconds_select = dist_s / P;  // share of the distance block
+          S.own.seconds_newton = share;       // share of the lockstep solve
+          outs[group[c0 + k]] = build_model(S, (int)m);
+        }
       }
     }
   }
 
-  spsvm_model* build_model(int m) {
+  spsvm_model* build_model(int m) { return build_model(slots[0], m); }
+
+  spsvm_model* build_model(Slot& S, int m) {
     double F = 0.0;
     NewtonScalars s{};
-    final_eval(m, &F, &s);
+    final_eval(S, m, &F, &s);
+    spsvm_stats& stats = *S.stats;
     stats.n_sv = s.n_sv;
     stats.grad_norm = std::sqrt(s.gnorm2);
     sync();
@@ -693,7 +950,7 @@ struct Impl {
       md->m = m;
       md->d = d;
       md->tk_double = std::is_same<TK, double>::value;
-      md->C = C;
+      md->C = S.C;
       md->gamma = gamma;
       md->objective = F;
       md->stats = stats;
@@ -701,14 +958,14 @@ struct Impl {
       md->beta.resize(m);
       if (m > 0) {
         SPSVM_HIP(hipMemcpyAsync(md->J.data(), J, m * 8, hipMemcpyDeviceToHost, st));
-        SPSVM_HIP(hipMemcpyAsync(md->beta.data(), beta, m * 8, hipMemcpyDeviceToHost, st));
+        SPSVM_HIP(hipMemcpyAsync(md->beta.data(), S.beta, m * 8, hipMemcpyDeviceToHost, st));
         md->ldz = padded_ld<TK>(d);
         SPSVM_HIP(hipMalloc(&md->XJ, (size_t)m * md->ldz * sizeof(TK)));
         SPSVM_HIP(hipMalloc(&md->XJnorm, (size_t)m * sizeof(TK)));
         SPSVM_HIP(hipMalloc(&md->beta_dev, (size_t)m * 8));
         launch_gather_rows<TX, TK>(X, d, J, m, (TK*)md->XJ, md->ldz, st);
         launch_row_norms<TK, TK>((const TK*)md->XJ, m, d, md->ldz, (TK*)md->XJnorm, st);
-        SPSVM_HIP(hipMemcpyAsync(md->beta_dev, beta, m * 8, hipMemcpyDeviceToDevice, st));
+        SPSVM_HIP(hipMemcpyAsync(md->beta_dev, S.beta, m * 8, hipMemcpyDeviceToDevice, st));
         sync();
       }
     } catch (...) {
@@ -787,7 +1044,7 @@ static void batch_typed(const TX* X, int64_t n, int64_t d, int64_t P, const floa
 void run_train_batch(const void* X, bool x_double, int64_t n, int64_t d, int64_t P, const float* Y, const double* C,
                      const double* gamma, const int64_t* J, int64_t m, const spsvm_options& opt, void* ws,
                      size_t ws_bytes, hipStream_t stream, spsvm_model** out) {
-  const Plan plan = make_plan(n, d, m, opt, false, x_double, ((uintptr_t)X & 15u) == 0, true);
+  const Plan plan = make_plan(n, d, m, opt, false, x_double, ((uintptr_t)X & 15u) == 0, true, P);
   if (!ws || ((uintptr_t)ws & 255u)) throw Failure(SPSVM_E_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
   if (ws_bytes < plan.bytes)
     throw Failure(SPSVM_E_WORKSPACE, "workspace too small: need " + std::to_string(plan.bytes) + " bytes, got " +

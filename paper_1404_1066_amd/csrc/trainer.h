@@ -29,19 +29,33 @@ void draw_step(uint64_t seed, int64_t t, int64_t n, int kappa, const std::vector
                const std::vector<uint64_t>& blocked_sorted, int32_t* out64);
 int64_t stage_size(int64_t J, int64_t J_max, double growth, int64_t cap);
 
+// Offsets of one problem's Newton state inside its slot region of the workspace.
+struct SlotPlan {
+  size_t o, delta, act0, act1, I, cblk_cnt, cblk_sum, cblk_flips, beta, dvec, g, z, H, Hf, Linv, syrk_part,
+      grad_part, ls_part, vJ, wJ, F_in, F_out, fcnt_in, fcnt_out;
+  size_t bytes;
+};
+
+// Problems whose Newton solves run in lockstep in a batch (one slot each).
+constexpr int kBatchSlots = 64;
+
 struct Plan {
   int64_t n = 0, d = 0, J_max = 0, ldk = 0, ldh = 0, ldx = 0, ldj = 0;
   bool pad_x = false;  // X is copied with a padded row stride (rows on 16-byte boundaries)
   bool tk_double = false;
+  bool batch = false;
   size_t bytes = 0;
-  // offsets into the workspace
-  size_t xnorm, hash, KXJ, Kc, o, delta, act0, act1, I, cblk_cnt, cblk_sum, cblk_flips, J, J32, beta, dvec, g, z,
-      H, Linv, syrk_part, grad_part, cand_state, sel, ls, scalars, score_part, ls_part, cand_table, stage_hash, m_dev,
-      flags, XJ64, xjnorm, KJJ, vJ, wJ, iota, incomplete, o_stage, Hf, F_in, F_out, fcnt_in, fcnt_out, Xp, D, DJJ;
+  // offsets into the workspace (shared by all slots)
+  size_t xnorm, hash, KXJ, Kc, J, J32, cand_state, sel, ls, scalars, score_part, cand_table, stage_hash, m_dev, flags,
+      XJ64, xjnorm, KJJ, iota, incomplete, o_stage, Xp, D, DJJ, G;
+  // per-problem regions: slot q starts at slots_at + q * slot.bytes; ls and scalars hold one entry per slot
+  SlotPlan slot;
+  size_t slots_at = 0;
+  int slots = 1;
 };
 
 Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection,
-               bool x_double, bool x_aligned, bool batch = false);
+               bool x_double, bool x_aligned, bool batch = false, int64_t problems = 1);
 
 // Runs training; returns a new model (caller owns) or throws Failure.
 spsvm_model* run_train(const void* X, bool x_double, const float* y, int64_t n, int64_t d, double C, double gamma,
