@@ -5,7 +5,9 @@ every row of the hot path) on a fixed synthetic workload already resident in HBM
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload binary-100k] [--precision f32]
 
-The default workload is the 100 000 x 123 binary one (|J| = 1000, C = 1, gamma = 0.05). The dominant kernel
+The default workload is the 100 000 x 123 binary one (|J| = 1000, C = 1, gamma = 0.05). With
+--workload mnist-60k a step is instead one batched call: 160 one-vs-rest x (C, gamma) Newton solves on a shared
+basis of 2000 rows of a 60 000 x 784 matrix. The dominant kernel
 (largest GPU time among kernel block, SYRK, score passes, Cholesky, found on the first warm-up run) is timed
 with HIP events on the training stream during the timed steps, for the roofline entry. Parity of the first
 timed run is checked against the FP64 oracle (objective at the GPU's basis, sampled decision values), and the
@@ -47,7 +49,21 @@ def parse():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=12)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison runs")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy a 256 MiB device buffer 3 times (a plain copy kernel of known size, to calibrate "
+                         "hardware byte counters)")
     return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 256 MiB
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def roofline_entry(stats, bit, precision):
@@ -71,12 +87,90 @@ def roofline_entry(stats, bit, precision):
             "work_per_launch": work / max(launches, 1)}
 
 
+def run_batch(args):
+    """The batched workload: 160 one-vs-rest x (C, gamma) Newton solves on one shared basis; one step is one
+    spsvm_train_batch call over all of them."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1404_1066_amd as lib
+
+    p = datagen.make_config(args.workload)
+    n, d = p.X.shape
+    P, m = p.Y.shape[0], len(p.J)
+    dt = torch.float64 if args.precision == "f64" else torch.float32
+    Xg = torch.tensor(p.X, dtype=dt, device="cuda")
+    Yg = torch.tensor(p.Y, dtype=torch.float32, device="cuda")
+    ws = torch.empty(lib.workspace_bytes(n, d, m, batch=True, problems=P, dtype=dt, precision=args.precision),
+                     dtype=torch.uint8, device="cuda")
+    common = dict(precision=args.precision, workspace=ws, stream=torch.cuda.current_stream())
+    warm = None
+    for w in range(max(args.warmup, 1)):
+        ms = lib.train_batch(Xg, Yg, p.C, p.gamma, p.J, profile=15 if w == 0 else 0, **common)
+        if w == 0:
+            warm = ms[-1].stats()  # kernel timings cover the whole batch
+    dominant = max(CATS, key=lambda b: warm[f"{CATS[b][0]}_seconds"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    runs = []
+    for k in range(args.steps):
+        runs.append(lib.train_batch(Xg, Yg, p.C, p.gamma, p.J, profile=dominant | 1, **common))
+    torch.cuda.synchronize()
+    per_run = (time.perf_counter() - t1) / args.steps
+    agg = {}
+    for key in warm:
+        agg[key] = sum(r[-1].stats()[key] for r in runs)
+    out = {
+        "metric": METRIC,
+        "value": round(per_run, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * per_run, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "d": d, "problems": P, "m": m,
+                   "C": sorted(set(float(c) for c in p.C)), "gamma": sorted(set(float(g) for g in p.gamma)),
+                   "precision": args.precision},
+        "roofline": roofline_entry(agg, dominant, args.precision),
+        "kblock": roofline_entry(agg, 1, args.precision),
+        "kernels_warmup": {CATS[b][0]: roofline_entry(warm, b, args.precision) for b in CATS},
+    }
+    from oracle import spsvm as osp
+
+    if not args.no_parity:
+        par = []
+        for q in (0, P - 1):
+            _, beta, _ = runs[0][q].get()
+            tq = time.perf_counter()
+            b_or, F_or, _ = osp.solve_fixed_J(p.X, p.Y[q], p.C[q], p.gamma[q], p.J)
+            oracle_s = time.perf_counter() - tq
+            Fo = osp.objective_at(p.X, p.Y[q], p.C[q], p.gamma[q], p.J, beta)
+            par.append({"problem": q, "objective_rel": (Fo - F_or) / F_or, "objective_ok": bool((Fo - F_or) / F_or <= 1e-6)})
+        out["parity"] = par
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = {
+                "value": round(oracle_s * P, 3), "unit": "s", "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+                "sample": f"FP64 oracle fixed-basis Newton solve of problem {P - 1} ({oracle_s:.2f} s), times {P} problems"}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+    if args.workload == "mnist-60k":
+        run_batch(args)
+        return
     import numpy as np
     import torch
 
