@@ -66,6 +66,28 @@ def copy_probe():
     del a, b
 
 
+KERNEL_OF = {"kblock": "k_kblock_store", "syrk": "k_syrk", "score": "k_score_pass", "chol": "k_potrf_diag"}
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed byte-counter summary of this workload, or None when
+    there is none or the kernel's source file changed after the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{KERNEL_OF.get(kernel, kernel)}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            rec = json.loads(fh.read().strip().splitlines()[-1])
+        with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != rec["source_sha256"]:
+                return None
+        return rec["bytes_per_dispatch"]
+    except (OSError, ValueError, KeyError, TypeError):
+        return None
+
+
 def roofline_entry(stats, bit, precision):
     pre, unit, bound = CATS[bit]
     sec = stats[f"{pre}_seconds"]
@@ -141,6 +163,8 @@ def run_batch(args):
         "kblock": roofline_entry(agg, 1, args.precision),
         "kernels_warmup": {CATS[b][0]: roofline_entry(warm, b, args.precision) for b in CATS},
     }
+    if out["roofline"] is not None:
+        out["roofline"]["traffic"] = measured_traffic(args.workload, out["roofline"]["kernel"])
     from oracle import spsvm as osp
 
     if not args.no_parity:
@@ -214,6 +238,8 @@ def main():
     for key in stats[0]:
         agg[key] = sum(s[key] for s in stats)
     roof = roofline_entry(agg, dominant, args.precision)
+    if roof is not None:
+        roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
     kblock_timed = roofline_entry(agg, 1, args.precision)
     others = {CATS[b][0]: roofline_entry(warm_stats, b, args.precision) for b in CATS}
 

@@ -83,7 +83,8 @@ typedef struct {
   int64_t additions;        /* basis vectors added by greedy selection */
   int64_t newton_iters;     /* Newton iterations over all stages */
   int64_t factorizations;   /* Cholesky factorisations of the Newton matrix (incl. jitter retries) */
-  int64_t score_passes;     /* O(n) passes spent on candidate scoring */
+  int64_t score_passes;     /* O(n) scoring passes launched (a pass whose slots are all settled exits at once) */
+  int64_t score_passes_active; /* launched scoring passes in which some slot was still being scored */
   int64_t ls_passes;        /* O(n) passes spent in exact line searches */
   int64_t iter_cap_hits;    /* re-optimisations stopped by newton_max_iter */
   int64_t stage_redos;      /* selection stages rerun with more scoring passes */
@@ -103,7 +104,7 @@ typedef struct {
   double syrk_flops;        /* n_sv m (m + 1) per launch (lower triangle, multiply-add = 2) */
   int64_t score_launches;   /* candidate-score passes over the n rows */
   double score_seconds;
-  double score_bytes;       /* n (kappa sizeof(K) + 12) per pass: candidate columns, o (FP64), y (FP32) */
+  double score_bytes;       /* n (kappa sizeof(K) + 12) per active pass: candidate columns, o (FP64), y (FP32) */
   int64_t chol_calls;       /* Cholesky factorisations (all panel kernels of one factorisation) */
   double chol_seconds;
   double chol_flops;        /* m^3 / 3 per factorisation */

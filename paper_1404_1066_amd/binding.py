@@ -72,6 +72,7 @@ class Stats(ctypes.Structure):
         ("newton_iters", ctypes.c_int64),
         ("factorizations", ctypes.c_int64),
         ("score_passes", ctypes.c_int64),
+        ("score_passes_active", ctypes.c_int64),
         ("ls_passes", ctypes.c_int64),
         ("iter_cap_hits", ctypes.c_int64),
         ("stage_redos", ctypes.c_int64),

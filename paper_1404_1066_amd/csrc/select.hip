@@ -244,7 +244,10 @@ __global__ void k_select(const CandState* __restrict__ st, const uint64_t* __res
   const CandState s = st[c];
   int mp = s.passes;
   for (int off = 32; off > 0; off >>= 1) mp = max(mp, __shfl_xor(mp, off, kWave));
-  if (c == 0) atomicMax(&incomplete[1], mp);  // largest number of passes any slot needed in this stage
+  if (c == 0) {
+    atomicMax(&incomplete[1], mp);  // largest number of passes any slot needed in this stage
+    atomicAdd(&incomplete[2], mp);  // passes of this step that did work
+  }
   const int pending = __any(s.status == 0);  // a slot still being scored: this step must be redone
   const bool ok = !pending && s.status == 1 && s.idx >= 0 && !(s.score != s.score);
   double best = ok ? s.score : -__builtin_huge_val();

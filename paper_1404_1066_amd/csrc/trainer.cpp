@@ -96,7 +96,7 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.xjnorm = take(J_max * 8);
   p.KJJ = take((size_t)J_max * p.ldh * 8);
   p.iota = take(J_max * 4);
-  p.incomplete = take(8);
+  p.incomplete = take(16);
   p.o_stage = take(with_selection ? n * 8 : 0);
   p.Xp = take(p.pad_x ? (size_t)n * p.ldx * xe : 0);
   p.D = take(batch ? (size_t)n * p.ldk * tk : 0);
@@ -756,7 +756,7 @@ struct Impl {
           SPSVM_HIP(hipMemcpyAsync(m_dev, mh, 4, hipMemcpyHostToDevice, st));
           stats.stage_redos += 1;
         }
-        SPSVM_HIP(hipMemsetAsync(incomplete, 0, 8, st));
+        SPSVM_HIP(hipMemsetAsync(incomplete, 0, 12, st));
         for (int q = 0; q < cs; ++q) {
           const int32_t* cq = cand_table + (size_t)q * kCandSlots;
           int ncand = 0;
@@ -772,10 +772,11 @@ struct Impl {
           stats.score_passes += rounds;
           launch_select_append<TK>(cst, hash, stage_hash, q, Kc, n, o, KXJ, p.ldk, J, beta, m_dev, sel, incomplete, st);
         }
-        int32_t flags2[2];
-        SPSVM_HIP(hipMemcpyAsync(pin.p, incomplete, 8, hipMemcpyDeviceToHost, st));
+        int32_t flags2[3];
+        SPSVM_HIP(hipMemcpyAsync(pin.p, incomplete, 12, hipMemcpyDeviceToHost, st));
         sync();
-        std::memcpy(flags2, pin.p, 8);
+        std::memcpy(flags2, pin.p, 12);
+        stats.score_passes_active += flags2[2];
         first_rounds = std::min(64, std::max(3, flags2[1] + 1));
         if (flags2[0] == 0 || rounds >= 64) break;
       }
@@ -941,7 +942,9 @@ struct Impl {
     stats.syrk_flops = prof.work[kProfSyrk];
     stats.score_launches = prof.count[kProfScore];
     stats.score_seconds = prof.seconds[kProfScore];
-    stats.score_bytes = prof.work[kProfScore];
+    stats.score_bytes = prof.count[kProfScore] > 0
+                            ? (double)stats.score_passes_active * (double)n * (opt.kappa * sizeof(TK) + 12.0)
+                            : 0.0;
     stats.chol_calls = prof.count[kProfChol];
     stats.chol_seconds = prof.seconds[kProfChol];
     stats.chol_flops = prof.work[kProfChol];
