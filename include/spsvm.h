@@ -83,7 +83,8 @@ typedef struct {
   int64_t additions;        /* basis vectors added by greedy selection */
   int64_t newton_iters;     /* Newton iterations over all stages */
   int64_t factorizations;   /* Cholesky factorisations of the Newton matrix (incl. jitter retries) */
-  int64_t score_passes;     /* O(n) scoring passes launched (a pass whose slots are all settled exits at once) */
+  int64_t score_passes;     /* O(n) scoring passes launched after the first, which the candidate block computes
+                               (a pass whose slots are all settled exits at once) */
   int64_t score_passes_active; /* launched scoring passes in which some slot was still being scored */
   int64_t ls_passes;        /* O(n) passes spent in exact line searches */
   int64_t iter_cap_hits;    /* re-optimisations stopped by newton_max_iter */

@@ -201,12 +201,56 @@ struct KTile {
   }
 };
 
+// Fused first scoring pass (see Score0): lane-local sums over this lane's 8 rows of each of its 4 columns,
+// then over the four lane groups (xor shuffles) and the four waves (LDS, in wave order).
+struct Score0Acc {
+  double P[4] = {0, 0, 0, 0}, Q[4] = {0, 0, 0, 0};
+  __device__ __forceinline__ void add(int j, double a, float yv, double kv) {
+    if (a > 0.0) {
+      const double b = (double)yv * kv;
+      P[j] += a * b;
+      Q[j] += b * b;
+    }
+  }
+  // partial record of this tile for every column of the block (64 columns)
+  __device__ __forceinline__ void finish(double* __restrict__ partial, int64_t tile, double (*red)[64][2]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      P[j] += __shfl_xor(P[j], 16, kWave);
+      Q[j] += __shfl_xor(Q[j], 16, kWave);
+      P[j] += __shfl_xor(P[j], 32, kWave);
+      Q[j] += __shfl_xor(Q[j], 32, kWave);
+      if (lane < 16) {
+        red[w][j * 16 + lane][0] = P[j];
+        red[w][j * 16 + lane][1] = Q[j];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int c = threadIdx.x;
+      double p = 0.0, q = 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        p += red[v][c][0];
+        q += red[v][c][1];
+      }
+      double* out = partial + (tile * 64 + c) * 4;
+      out[0] = p;
+      out[1] = q;
+      out[2] = 0.0;
+      out[3] = 0.0;
+    }
+  }
+};
+
 // STORE: out[row * ldo + c] for the column tile blockIdx.y.
 // gamma > 0: out = exp(-gamma d2); gamma == 0: out = d2 (the squared distance itself, clamped at 0).
 template <typename TX, typename TK>
 __global__ __launch_bounds__(256) void k_kblock_store(const TX* __restrict__ X, int64_t ldx, int64_t n, int64_t d,
                                                       const TK* __restrict__ xnorm, const int32_t* __restrict__ cidx,
-                                                      int ncols, TK* __restrict__ out, int64_t ldo, double gamma) {
+                                                      int ncols, TK* __restrict__ out, int64_t ldo, double gamma,
+                                                      const Score0 s0) {
   using M = Mfma<TK>;
   __shared__ __attribute__((aligned(32))) TK As[KB_BM][KB_LD];
   __shared__ __attribute__((aligned(32))) TK Bs[KB_BN][KB_LD];
@@ -216,6 +260,20 @@ __global__ __launch_bounds__(256) void k_kblock_store(const TX* __restrict__ X, 
   t.run(X, ldx, n, r0, X, ldx, cidx, c0, ncols, d, As, Bs);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const TK gs = gamma_scale<TK>(gamma);
+  const bool fused = s0.partial != nullptr;
+  double ga[2][4];  // a_i of this lane's rows (fused pass)
+  float gy[2][4];
+  if (fused) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
+        gy[i][r] = row < n ? s0.y[row] : 0.0f;
+        ga[i][r] = row < n ? margin_gap(gy[i][r], s0.o[row]) : 0.0;
+      }
+  }
+  Score0Acc sa;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int64_t col = c0 + j * 16 + (lane & 15);
@@ -230,21 +288,28 @@ __global__ __launch_bounds__(256) void k_kblock_store(const TX* __restrict__ X, 
         const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
         if (row < n) {
           const TK d2 = xnorm[row] + zn - (TK)2 * t.acc[i][j][r];
-          out[row * ldo + col] = gamma > 0.0 ? rbf_from_d2(d2, gs) : (d2 > (TK)0 ? d2 : (TK)0);
+          const TK kv = gamma > 0.0 ? rbf_from_d2(d2, gs) : (d2 > (TK)0 ? d2 : (TK)0);
+          out[row * ldo + col] = kv;
+          if (fused) sa.add(j, ga[i][r], gy[i][r], (double)kv);
         }
       }
+  }
+  if (fused) {
+    __shared__ double red[4][64][2];
+    sa.finish(s0.partial, blockIdx.x, red);
   }
 }
 
 template <typename TX, typename TK>
 void launch_kblock(const TX* X, int64_t ldx, int64_t n, int64_t d, const TK* xnorm, const int32_t* cidx, int ncols,
-                   TK* out, int64_t ldo, double gamma, hipStream_t st) {
+                   TK* out, int64_t ldo, double gamma, hipStream_t st, const Score0& s0) {
   if (n <= 0 || ncols <= 0) return;
   if (ldx % Vec16<TX>::n != 0 || ((uintptr_t)X & 15u))
     throw Failure(1, "kernel block: rows must start on 16-byte boundaries");
+  if (s0.partial && ncols > KB_BN) throw Failure(1, "kernel block: the fused scoring pass takes one column tile");
   dim3 grid((unsigned)ceil_div(n, KB_BM), (unsigned)ceil_div(ncols, KB_BN));
   hipLaunchKernelGGL((k_kblock_store<TX, TK>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out, ldo,
-                     gamma);
+                     gamma, s0);
   SPSVM_LAUNCHED();
 }
 
@@ -270,7 +335,8 @@ template <typename TX, bool SPLIT>
 __global__ __launch_bounds__(256) void k_kblock_split(const TX* __restrict__ X, int64_t ldx, int64_t n, int64_t d,
                                                       const float* __restrict__ xnorm,
                                                       const int32_t* __restrict__ cidx, int ncols,
-                                                      float* __restrict__ out, int64_t ldo, double gamma) {
+                                                      float* __restrict__ out, int64_t ldo, double gamma,
+                                                      const Score0 s0) {
   __shared__ __attribute__((aligned(16))) unsigned short Ah[KB_BM][SB_LD], Al[KB_BM][SB_LD];
   __shared__ __attribute__((aligned(16))) unsigned short Bh[KB_BN][SB_LD], Bl[KB_BN][SB_LD];
   constexpr int V = Vec16<TX>::n;
@@ -353,6 +419,20 @@ __global__ __launch_bounds__(256) void k_kblock_split(const TX* __restrict__ X, 
       }
   }
   const float gs = (float)(gamma * 1.4426950408889634);
+  const bool fused = s0.partial != nullptr;
+  double ga[2][4];
+  float gy[2][4];
+  if (fused) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + w * 32 + i * 16 + (lane >> 4) * 4 + r;
+        gy[i][r] = row < n ? s0.y[row] : 0.0f;
+        ga[i][r] = row < n ? margin_gap(gy[i][r], s0.o[row]) : 0.0;
+      }
+  }
+  Score0Acc sa;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int64_t col = c0 + j * 16 + i16;
@@ -367,25 +447,33 @@ __global__ __launch_bounds__(256) void k_kblock_split(const TX* __restrict__ X, 
         const int64_t row = r0 + w * 32 + i * 16 + (lane >> 4) * 4 + r;
         if (row < n) {
           const float d2 = xnorm[row] + zn - 2.0f * acc[i][j][r];
-          out[row * ldo + col] = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
+          const float kv = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
+          out[row * ldo + col] = kv;
+          if (fused) sa.add(j, ga[i][r], gy[i][r], (double)kv);
         }
       }
+  }
+  if (fused) {
+    __shared__ double red[4][64][2];
+    sa.finish(s0.partial, blockIdx.x, red);
   }
 }
 
 template <typename TX>
 void launch_kblock_split(const TX* X, int64_t ldx, int64_t n, int64_t d, const float* xnorm, const int32_t* cidx,
-                         int ncols, float* out, int64_t ldo, double gamma, bool bf16_exact, hipStream_t st) {
+                         int ncols, float* out, int64_t ldo, double gamma, bool bf16_exact, hipStream_t st,
+                         const Score0& s0) {
   if (n <= 0 || ncols <= 0) return;
   if (ldx % Vec16<TX>::n != 0 || ((uintptr_t)X & 15u))
     throw Failure(1, "kernel block: rows must start on 16-byte boundaries");
+  if (s0.partial && ncols > KB_BN) throw Failure(1, "kernel block: the fused scoring pass takes one column tile");
   dim3 grid((unsigned)ceil_div(n, KB_BM), (unsigned)ceil_div(ncols, KB_BN));
   if (bf16_exact)
     hipLaunchKernelGGL((k_kblock_split<TX, false>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out,
-                       ldo, gamma);
+                       ldo, gamma, s0);
   else
     hipLaunchKernelGGL((k_kblock_split<TX, true>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out,
-                       ldo, gamma);
+                       ldo, gamma, s0);
   SPSVM_LAUNCHED();
 }
 
@@ -562,7 +650,7 @@ void launch_check_inputs(const TX* X, int64_t total, const float* y, int64_t n, 
 #define SPSVM_INST(TX, TK)                                                                                    \
   template void launch_row_norms<TX, TK>(const TX*, int64_t, int64_t, int64_t, TK*, hipStream_t);             \
   template void launch_kblock<TX, TK>(const TX*, int64_t, int64_t, int64_t, const TK*, const int32_t*, int, TK*, \
-                                      int64_t, double, hipStream_t);                                          \
+                                      int64_t, double, hipStream_t, const Score0&);                                          \
   template void launch_predict<TX, TK>(const TX*, int64_t, int64_t, int64_t, const TK*, int64_t, const TK*, int,  \
                                        const double*, double*, double, hipStream_t);                          \
   template void launch_gather_rows<TX, TK>(const TX*, int64_t, const int64_t*, int64_t, TK*, int64_t, hipStream_t);
@@ -574,9 +662,9 @@ SPSVM_INST(double, double)
 template void launch_row_hash<float>(const float*, int64_t, int64_t, uint64_t*, hipStream_t);
 template void launch_row_hash<double>(const double*, int64_t, int64_t, uint64_t*, hipStream_t);
 template void launch_kblock_split<float>(const float*, int64_t, int64_t, int64_t, const float*, const int32_t*, int,
-                                         float*, int64_t, double, bool, hipStream_t);
+                                         float*, int64_t, double, bool, hipStream_t, const Score0&);
 template void launch_kblock_split<double>(const double*, int64_t, int64_t, int64_t, const float*, const int32_t*, int,
-                                          float*, int64_t, double, bool, hipStream_t);
+                                          float*, int64_t, double, bool, hipStream_t, const Score0&);
 template void launch_rbf_from_dist<float>(const float*, int64_t, int, int64_t, float*, double, hipStream_t);
 template void launch_rbf_from_dist<double>(const double*, int64_t, int, int64_t, double*, double, hipStream_t);
 template void launch_pad_rows<float>(const float*, int64_t, int64_t, float*, int64_t, hipStream_t);

@@ -57,11 +57,21 @@ template <typename TX, typename TK>
 void launch_row_norms(const TX* X, int64_t n, int64_t d, int64_t ldx, TK* out, hipStream_t st);
 template <typename TX>
 void launch_row_hash(const TX* X, int64_t n, int64_t d, uint64_t* out, hipStream_t st);
+// First scoring pass (at s = 0) fused into the candidate block: for every 128-row tile t and column c the
+// epilogue writes partial[(t * 64 + c) * 4 + {0, 1, 2, 3}] = {P, Q, 0, 0}, the sums of a_i b_i and b_i^2 over
+// the rows of the tile with a_i = 1 - y_i o_i > 0 (b_i = y_i k_ic), in the layout of a scoring pass.
+struct Score0 {
+  const float* y = nullptr;
+  const double* o = nullptr;
+  double* partial = nullptr;  // nullptr: no fused pass
+};
+constexpr int kKblockRows = 128;  // rows per kernel-block tile (the fused pass writes one record per tile)
+
 // X rows start at multiples of ldx elements; ldx * sizeof(TX) and X must be 16-byte aligned.
 // gamma > 0 writes exp(-gamma d2); gamma == 0 writes the squared distances d2.
 template <typename TX, typename TK>
 void launch_kblock(const TX* X, int64_t ldx, int64_t n, int64_t d, const TK* xnorm, const int32_t* cidx, int ncols,
-                   TK* out, int64_t ldo, double gamma, hipStream_t st);
+                   TK* out, int64_t ldo, double gamma, hipStream_t st, const Score0& s0 = Score0{});
 template <typename TX, typename TK>
 void launch_predict(const TX* Xt, int64_t ldxt, int64_t n, int64_t d, const TK* Z, int64_t ldz, const TK* znorm, int m,
                     const double* beta, double* out, double gamma, hipStream_t st);
@@ -69,7 +79,8 @@ void launch_predict(const TX* Xt, int64_t ldxt, int64_t n, int64_t d, const TK* 
 // bf16_exact: every X value is a BF16 number (lo = 0), so only hi.hi' is issued (identical result).
 template <typename TX>
 void launch_kblock_split(const TX* X, int64_t ldx, int64_t n, int64_t d, const float* xnorm, const int32_t* cidx,
-                         int ncols, float* out, int64_t ldo, double gamma, bool bf16_exact, hipStream_t st);
+                         int ncols, float* out, int64_t ldo, double gamma, bool bf16_exact, hipStream_t st,
+                         const Score0& s0 = Score0{});
 template <typename TK>
 void launch_rbf_from_dist(const TK* D, int64_t rows, int ncols, int64_t ld, TK* K, double gamma, hipStream_t st);
 template <typename TX>

@@ -37,8 +37,6 @@ void launch_gemv(const TK* K, int64_t ldk, int64_t n, int m, const double* x, do
 // ------------------------------------------------------------------------------------------ compaction
 constexpr int kCompactRows = 4096;  // rows per block: 16 chunks of 256
 
-// a_i = 1 - y_i o_i with explicit rounding (no contraction), so every kernel draws the same I.
-__device__ __forceinline__ double margin_gap(float y, double o) { return __dadd_rn(1.0, -__dmul_rn((double)y, o)); }
 
 __global__ __launch_bounds__(256) void k_compact_count(const double* __restrict__ o, const float* __restrict__ y,
                                                        int64_t n, const uint8_t* __restrict__ act_ref,

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_score_pass(const TK* __restrict__ Kc, c
     int64_t i = lo + q;
     for (; i + 4 < hi; i += 8) {
       const double y0 = (double)y[i], y1 = (double)y[i + 4];
-      const double a0 = 1.0 - y0 * o[i], a1 = 1.0 - y1 * o[i + 4];
+      const double a0 = margin_gap(y[i], o[i]), a1 = margin_gap(y[i + 4], o[i + 4]);
       const double b0 = y0 * (double)Kc[i * kCandSlots + c], b1 = y1 * (double)Kc[(i + 4) * kCandSlots + c];
       const double e0 = a0 - s * b0, e1 = a1 - s * b1;
       if (e0 > 0.0) {
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_score_pass(const TK* __restrict__ Kc, c
     }
     for (; i < hi; i += 4) {
       const double yi = (double)y[i];
-      const double a = 1.0 - yi * o[i];
+      const double a = margin_gap(y[i], o[i]);
       const double b = yi * (double)Kc[i * kCandSlots + c];
       const double e = a - s * b;
       if (e > 0.0) {
@@ -246,7 +246,8 @@ __global__ void k_select(const CandState* __restrict__ st, const uint64_t* __res
   for (int off = 32; off > 0; off >>= 1) mp = max(mp, __shfl_xor(mp, off, kWave));
   if (c == 0) {
     atomicMax(&incomplete[1], mp);  // largest number of passes any slot needed in this stage
-    atomicAdd(&incomplete[2], mp);  // passes of this step that did work
+    atomicAdd(&incomplete[2], mp > 0 ? mp - 1 : 0);  // launched passes of this step that did work (the first
+                                                     // pass is fused into the candidate block)
   }
   const int pending = __any(s.status == 0);  // a slot still being scored: this step must be redone
   const bool ok = !pending && s.status == 1 && s.idx >= 0 && !(s.score != s.score);

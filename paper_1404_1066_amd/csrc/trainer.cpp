@@ -87,7 +87,7 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.sel = take(sizeof(Selection));
   p.ls = take(p.slots * sizeof(LineState));
   p.scalars = take(p.slots * sizeof(NewtonScalars));
-  p.score_part = take((size_t)nb_s * kCandSlots * 4 * 8);
+  p.score_part = take((size_t)std::max<int64_t>(nb_s, ceil_div(n, kKblockRows)) * kCandSlots * 4 * 8);
   p.cand_table = take((size_t)cap * kCandSlots * 4);
   p.stage_hash = take(cap * 8);
   p.m_dev = take(4);
@@ -376,14 +376,14 @@ struct Impl {
   }
 
   // The n x N kernel block in the training precision (split-BF16 products in MIXED mode).
-  void kblock(const int32_t* cols, int ncols, TK* out, int64_t ldo) {
+  void kblock(const int32_t* cols, int ncols, TK* out, int64_t ldo, const Score0& s0 = Score0{}) {
     if constexpr (std::is_same<TK, float>::value) {
       if (opt.precision == SPSVM_MIXED) {
-        launch_kblock_split<TX>(Xk, p.ldx, n, d, xnorm, cols, ncols, out, ldo, gamma, bf16_exact, st);
+        launch_kblock_split<TX>(Xk, p.ldx, n, d, xnorm, cols, ncols, out, ldo, gamma, bf16_exact, st, s0);
         return;
       }
     }
-    launch_kblock<TX, TK>(Xk, p.ldx, n, d, xnorm, cols, ncols, out, ldo, gamma, st);
+    launch_kblock<TX, TK>(Xk, p.ldx, n, d, xnorm, cols, ncols, out, ldo, gamma, st, s0);
   }
 
   // Basis rows m0..m1 of J gathered into XJ64 (FP64), then the FP64 kernel matrix K_JJ of the first m1 rows.
@@ -761,15 +761,21 @@ struct Impl {
           const int32_t* cq = cand_table + (size_t)q * kCandSlots;
           int ncand = 0;
           for (int c = 0; c < kCandSlots; ++c) ncand += table[(size_t)q * kCandSlots + c] >= 0;
+          // the candidate block also yields the first scoring pass (at s = 0)
+          Score0 s0;
+          s0.y = y;
+          s0.o = o;
+          s0.partial = score_part;
           prof.timed(kProfKblock, 2.0 * n * ncand * d,
-                     [&] { kblock(cq, kCandSlots, Kc, kCandSlots); });
+                     [&] { kblock(cq, kCandSlots, Kc, kCandSlots, s0); });
           launch_score_init(cq, o, hash, stage_hash, q, cst, sc, st);
-          for (int r = 0; r < rounds; ++r) {
+          launch_score_update(cst, score_part, (int)ceil_div(n, kKblockRows), lam, st);
+          for (int r = 1; r < rounds; ++r) {
             prof.timed(kProfScore, (double)n * (opt.kappa * sizeof(TK) + 12.0),
                        [&] { launch_score_pass<TK>(Kc, y, o, n, cst, score_part, nblk, st); });
             launch_score_update(cst, score_part, nblk, lam, st);
           }
-          stats.score_passes += rounds;
+          stats.score_passes += rounds - 1;
           launch_select_append<TK>(cst, hash, stage_hash, q, Kc, n, o, KXJ, p.ldk, J, beta, m_dev, sel, incomplete, st);
         }
         int32_t flags2[3];
