@@ -30,14 +30,25 @@ __global__ __launch_bounds__(256) void k_potrf_diag(const CholBatch bt, int64_t 
   NewtonScalars* sc = bt.sc[blockIdx.z];
   __shared__ double A[NB][NB_LD];
   __shared__ double X[NB][NB_LD];
+  __shared__ double Rd[SB];
   __shared__ int bad;
   const int nb = m - k0 < NB ? m - k0 : NB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid == 0) bad = 0;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    A[r][c] = (r < nb && c <= r) ? H[(int64_t)(k0 + r) * ldh + k0 + c] : (r == c ? 1.0 : 0.0);
-    X[r][c] = 0.0;
+  {
+    // all 16 loads of this thread in flight before the LDS stores
+    double v[NB * NB / 256];
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+      const int e = tid + q * 256, r = e >> 6, c = e & 63;
+      v[q] = (r < nb && c <= r) ? H[(int64_t)(k0 + r) * ldh + k0 + c] : (r == c ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+      const int e = tid + q * 256, r = e >> 6, c = e & 63;
+      A[r][c] = v[q];
+      X[r][c] = 0.0;
+    }
   }
   __syncthreads();
   for (int kb = 0; kb < NB / SB; ++kb) {
@@ -60,7 +71,8 @@ __global__ __launch_bounds__(256) void k_potrf_diag(const CholBatch bt, int64_t 
         double alj = 0.0;
 #pragma unroll
         for (int i = 0; i < SB; ++i) alj = (lane == i) ? pc[i] : alj;
-        alj = ok ? alj / piv : 0.0;
+        const double rpiv = ok ? 1.0 / piv : 0.0;  // one reciprocal per column, shared by the lanes
+        alj *= rpiv;
 #pragma unroll
         for (int i = 0; i < SB; ++i)
           if (lane > j && lane < SB && i >= lane) a[i] -= pc[i] * alj;
@@ -72,21 +84,25 @@ __global__ __launch_bounds__(256) void k_potrf_diag(const CholBatch bt, int64_t 
       const double rdg = 1.0 / dg;
 #pragma unroll
       for (int i = 0; i < SB; ++i) a[i] = (i == lane) ? dg : (i > lane ? a[i] * rdg : a[i]);
-      // column lane of the inverse: x_i = (e_lane[i] - sum_{q < i} L[i][q] x_q) / L[i][i]
+      // L's column `lane` goes to LDS; then column lane of the inverse, x_i = (e_lane[i] - sum_{q < i} L[i][q]
+      // x_q) / L[i][i], with L read back at addresses common to the wave (LDS broadcasts; one wave, in order)
+      if (lane < SB) {
+#pragma unroll
+        for (int i = 0; i < SB; ++i)
+          if (i >= lane) A[c0 + i][c0 + lane] = a[i];
+        Rd[lane] = rdg;
+      }
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int i = 0; i < SB; ++i) {
         double t = (lane == i) ? 1.0 : 0.0;
 #pragma unroll
-        for (int q = 0; q < i; ++q) t -= __shfl(a[i], q, kWave) * x[q];
-        const double lii = __shfl(a[i], i, kWave);
-        x[i] = (i >= lane) ? t / lii : 0.0;
+        for (int q = 0; q < i; ++q) t -= A[c0 + i][c0 + q] * x[q];
+        x[i] = (i >= lane) ? t * Rd[i] : 0.0;
       }
       if (lane < SB) {
 #pragma unroll
-        for (int i = 0; i < SB; ++i) {
-          if (i >= lane) A[c0 + i][c0 + lane] = a[i];
-          X[c0 + i][c0 + lane] = x[i];
-        }
+        for (int i = 0; i < SB; ++i) X[c0 + i][c0 + lane] = x[i];
       }
       if (lane == 0 && badl) bad = 1;
     }
