@@ -128,6 +128,16 @@ int gradient_chunks(int m, int n_sv);
 // per-slot operands travel by value in the kernel arguments.
 constexpr int kMaxBatch = 32;
 
+// out_q = K x_q for up to kMaxBatch vectors x_q (m FP64 values each, 32-byte aligned) with one read of K
+// (n x m, leading dimension ldk a multiple of 4, rows 16-byte aligned). FP64 MFMA, exact products.
+struct GemvBatch {
+  const double* x[kMaxBatch];
+  double* out[kMaxBatch];
+  int count;
+};
+template <typename TK>
+void launch_gemv_batch(const TK* K, int64_t ldk, int64_t n, int m, const GemvBatch& b, hipStream_t s);
+
 // SYRK partials over the rows rows[0..n_rows) for the lower 128 x 128 tiles tile_lo..tile_hi-1 (tiles numbered
 // row by row: tile t = tr (tr + 1) / 2 + tc), split into nsplit row ranges.
 template <typename TK>

@@ -497,6 +497,78 @@ void launch_add_diag(double* H, int64_t ldh, int m, double v, hipStream_t s) {
   SPSVM_LAUNCHED();
 }
 
+// ------------------------------------------------------------------------------------- batched GEMV
+// One wave per 64 rows of K (four 16-row MFMA tiles) and NCB x 16 vectors. In an MFMA step lane (g, i) supplies
+// K[row i][k] and x_{slot i}[k] for k = k0 + 4g + t (t = 0..3 over four steps), so one 16-byte load per row
+// feeds four steps; acc[i][j][r] ends as out_{slot 16j + i16}[row 16i + g + 4r].
+template <typename TK, int NCB>
+__global__ __launch_bounds__(64) void k_gemv_batch(const TK* __restrict__ K, int64_t ldk, int64_t n, int m,
+                                                   const GemvBatch b) {
+  const int lane = threadIdx.x, g = lane >> 4, i16 = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const TK* krow[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t row = r0 + i * 16 + i16;
+    krow[i] = row < n ? K + row * ldk : nullptr;
+  }
+  const double* xs[NCB];
+#pragma unroll
+  for (int j = 0; j < NCB; ++j) {
+    const int q = j * 16 + i16;
+    xs[j] = q < b.count ? b.x[q] : nullptr;
+  }
+  doublex4 acc[4][NCB];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) acc[i][j] = doublex4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < m; k0 += 16) {
+    const int kb = k0 + 4 * g;
+    const int cnt = min(max(m - kb, 0), 4);
+    TK kv[4][4];
+    double xv[NCB][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) load4(krow[i] ? krow[i] + kb : K, krow[i] ? cnt : 0, kv[i]);
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) load4(xs[j] ? xs[j] + kb : b.x[0], xs[j] ? cnt : 0, xv[j]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NCB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)kv[i][t], xv[j][t], acc[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < NCB; ++j) {
+    const int q = j * 16 + i16;
+    if (q >= b.count) continue;
+    double* out = b.out[q];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + i * 16 + g + 4 * r;
+        if (row < n) out[row] = acc[i][j][r];
+      }
+  }
+}
+
+template <typename TK>
+void launch_gemv_batch(const TK* K, int64_t ldk, int64_t n, int m, const GemvBatch& b, hipStream_t s) {
+  if (n <= 0 || b.count <= 0) return;
+  if (b.count > kMaxBatch || (ldk & 3) || ((uintptr_t)K & 15u)) throw Failure(1, "GEMV batch: bad arguments");
+  for (int q = 0; q < b.count; ++q)
+    if ((uintptr_t)b.x[q] & 31u) throw Failure(1, "GEMV batch: vectors must be 32-byte aligned");
+  const dim3 grid((unsigned)ceil_div(n, 64));
+  if (b.count <= 16)
+    hipLaunchKernelGGL((k_gemv_batch<TK, 1>), grid, dim3(64), 0, s, K, ldk, n, m, b);
+  else
+    hipLaunchKernelGGL((k_gemv_batch<TK, 2>), grid, dim3(64), 0, s, K, ldk, n, m, b);
+  SPSVM_LAUNCHED();
+}
+
 // --------------------------------------------------------------------------------------- flipped rows
 // Lists of rows whose violator status differs between act_new and act_old: joined (new 1, old 0) and left
 // (new 0, old 1), each in ascending order. Same block scheme as the violator compaction.
@@ -812,6 +884,8 @@ template void launch_gradient<float>(const float*, int64_t, int, const int32_t*,
 template void launch_gradient<double>(const double*, int64_t, int, const int32_t*, int, const double*, const float*,
                                       const double*, const double*, double, double*, int, double*, NewtonScalars*,
                                       hipStream_t);
+template void launch_gemv_batch<float>(const float*, int64_t, int64_t, int, const GemvBatch&, hipStream_t);
+template void launch_gemv_batch<double>(const double*, int64_t, int64_t, int, const GemvBatch&, hipStream_t);
 template void launch_syrk_batch<float>(const SyrkBatch<float>&, int64_t, int, hipStream_t);
 template void launch_syrk_batch<double>(const SyrkBatch<double>&, int64_t, int, hipStream_t);
 template void launch_syrk<float>(const float*, int64_t, int, const int32_t*, int, int, int, int, double*, hipStream_t);

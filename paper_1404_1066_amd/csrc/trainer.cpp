@@ -469,12 +469,33 @@ struct Impl {
   // and kernel calls of a solve on its own. Returns the iterations of the first slot.
   int newton(int m) { return newton_slots(m, {0}); }
 
+  // out = K x (the slot's n x m kernel block) for the given slots; in a batch one MFMA launch serves up to
+  // kMaxBatch slots with a single read of the shared block.
+  void gemv_slots(int m, const std::vector<int>& ids, double* Slot::*x, double* Slot::*out) {
+    if (!p.batch) {
+      for (int q : ids) launch_gemv<TK>(slots[q].K, p.ldk, n, m, slots[q].*x, slots[q].*out, st);
+      return;
+    }
+    for (size_t a = 0; a < ids.size(); a += kMaxBatch) {
+      GemvBatch gb{};
+      const TK* K = slots[ids[a]].K;
+      for (size_t k = a; k < ids.size() && k < a + kMaxBatch; ++k) {
+        const Slot& S = slots[ids[k]];
+        if (S.K != K) throw Failure(SPSVM_E_INVALID_ARG, "batched GEMV: slots must share the kernel block");
+        gb.x[gb.count] = S.*x;
+        gb.out[gb.count] = S.*out;
+        gb.count++;
+      }
+      launch_gemv_batch<TK>(K, p.ldk, n, m, gb, st);
+    }
+  }
+
   int newton_slots(int m, const std::vector<int>& ids) {
     if (m <= 0 || ids.empty()) return 0;
     std::vector<int> act;
+    gemv_slots(m, ids, &Slot::beta, &Slot::o);
     for (int q : ids) {
       Slot& S = slots[q];
-      launch_gemv<TK>(S.K, p.ldk, n, m, S.beta, S.o, st);
       S.fact_valid = false;
       S.g0 = 0.0;
       S.it = 0;
@@ -540,9 +561,9 @@ struct Impl {
         }
         launch_chol_solve_batch(sb, p.ldh, m, st);
       }
+      gemv_slots(m, go, &Slot::dvec, &Slot::delta);
       for (int q : go) {
         Slot& S = slots[q];
-        launch_gemv<TK>(S.K, p.ldk, n, m, S.dvec, S.delta, st);
         launch_gemv<double>(S.KJJ, p.ldh, m, m, S.dvec, S.wJ, st);
         launch_c1c2(S.beta, S.dvec, S.wJ, m, S.ls, st);
       }
@@ -708,13 +729,13 @@ struct Impl {
     }
   }
 
-  // Objective and residual statistics at the slot's current beta (o is recomputed).
-  void final_eval(Slot& S, int m, double* F, NewtonScalars* out) {
+  // Objective and residual statistics at the slot's current beta (o is recomputed unless the caller just did).
+  void final_eval(Slot& S, int m, double* F, NewtonScalars* out, bool o_fresh = false) {
     if (m == 0) {
       *F = S.C * 0.5 * (double)n;
       return;
     }
-    launch_gemv<TK>(S.K, p.ldk, n, m, S.beta, S.o, st);
+    if (!o_fresh) launch_gemv<TK>(S.K, p.ldk, n, m, S.beta, S.o, st);
     launch_compact(S.o, S.y, n, nullptr, S.act_cur, S.I, S.cblk_cnt, S.cblk_sum, S.cblk_flips, S.sc, st);
     NewtonScalars s = read(S.sc);
     launch_gemv<double>(S.KJJ, p.ldh, m, m, S.beta, S.vJ, st);
@@ -917,6 +938,7 @@ struct Impl {
           ids.push_back((int)ids.size());
         }
         newton_slots((int)m, ids);
+        gemv_slots((int)m, ids, &Slot::beta, &Slot::o);  // o at the final beta, for the models' statistics
         sync();
         const double share = secs(t1, clk::now()) / ids.size();
         for (size_t k = 0; k < ids.size(); ++k) {
@@ -924,7 +946,7 @@ struct Impl {
           S.own.stages = 1;
           S.own.seconds_select = dist_s / P;  // share of the distance block
           S.own.seconds_newton = share;       // share of the lockstep solve
-          outs[group[c0 + k]] = build_model(S, (int)m);
+          outs[group[c0 + k]] = build_model(S, (int)m, true);
         }
       }
     }
@@ -932,10 +954,10 @@ struct Impl {
 
   spsvm_model* build_model(int m) { return build_model(slots[0], m); }
 
-  spsvm_model* build_model(Slot& S, int m) {
+  spsvm_model* build_model(Slot& S, int m, bool o_fresh = false) {
     double F = 0.0;
     NewtonScalars s{};
-    final_eval(S, m, &F, &s);
+    final_eval(S, m, &F, &s, o_fresh);
     spsvm_stats& stats = *S.stats;
     stats.n_sv = s.n_sv;
     stats.grad_norm = std::sqrt(s.gnorm2);
