@@ -138,6 +138,24 @@ struct GemvBatch {
 template <typename TK>
 void launch_gemv_batch(const TK* K, int64_t ldk, int64_t n, int m, const GemvBatch& b, hipStream_t s);
 
+// Gradients of up to kMaxBatch problems sharing K, in dense form: for each slot the chunk partials
+// partial[c * m + j] = sum_{i in chunk c, a_i > 0} K[i][j] (o_i - y_i) (a_i = 1 - y_i o_i), one read of K for
+// all slots; then, per slot, g = lambda v + sum of the partials and the norms (as the single-problem gradient).
+struct GradBatch {
+  const double* o[kMaxBatch];
+  const float* y[kMaxBatch];
+  double* partial[kMaxBatch];
+  const double* v[kMaxBatch];
+  const double* beta[kMaxBatch];
+  double* g[kMaxBatch];
+  NewtonScalars* sc[kMaxBatch];
+  double lam[kMaxBatch];
+  int count;
+};
+int gradient_chunks_dense(int64_t n, int m);
+template <typename TK>
+void launch_gradient_batch(const TK* K, int64_t ldk, int64_t n, int m, const GradBatch& b, hipStream_t s);
+
 // SYRK partials over the rows rows[0..n_rows) for the lower 128 x 128 tiles tile_lo..tile_hi-1 (tiles numbered
 // row by row: tile t = tr (tr + 1) / 2 + tc), split into nsplit row ranges.
 template <typename TK>

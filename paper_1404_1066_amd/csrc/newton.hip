@@ -569,6 +569,153 @@ void launch_gemv_batch(const TK* K, int64_t ldk, int64_t n, int m, const GemvBat
   SPSVM_LAUNCHED();
 }
 
+// --------------------------------------------------------------------------------- batched gradient
+// Dense K^T r for NCB x 16 slots: one wave per 64 columns of K and chunk of rows. In an MFMA step lane (g, i)
+// supplies K[row][16 jt + i] and r_{slot i}[row] for row = i0 + 4g + t (t = 0..3 over four steps), with
+// r = o - y on violators and 0 elsewhere; acc[jt][c][r] ends as the partial of column 16 jt + g + 4r for slot
+// 16 c + i.
+template <typename TK, int NCB>
+__global__ __launch_bounds__(64) void k_grad_batch(const TK* __restrict__ K, int64_t ldk, int64_t n, int m,
+                                                   int64_t rows_per_chunk, const GradBatch b) {
+  const int lane = threadIdx.x, g = lane >> 4, i16 = lane & 15;
+  const int j0 = blockIdx.x * 64;
+  const int64_t lo = (int64_t)blockIdx.y * rows_per_chunk;
+  const int64_t hi = lo + rows_per_chunk < n ? lo + rows_per_chunk : n;
+  const double* os[NCB];
+  const float* ys[NCB];
+#pragma unroll
+  for (int c = 0; c < NCB; ++c) {
+    const int q = c * 16 + i16;
+    os[c] = q < b.count ? b.o[q] : nullptr;
+    ys[c] = q < b.count ? b.y[q] : nullptr;
+  }
+  doublex4 acc[4][NCB];
+#pragma unroll
+  for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) acc[jt][c] = doublex4{0, 0, 0, 0};
+  for (int64_t i0 = lo; i0 < hi; i0 += 16) {
+    const int64_t ib = i0 + 4 * g;
+    const int64_t cnt = hi - ib;
+    double rv[NCB][4];
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) {
+      double ov[4];
+      load4(os[c] && cnt > 0 ? os[c] + ib : b.o[0], os[c] ? (int)min<int64_t>(max<int64_t>(cnt, 0), 4) : 0, ov);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bool in = os[c] && t < cnt;
+        const float yv = in ? ys[c][ib + t] : 0.0f;
+        rv[c][t] = (in && margin_gap(yv, ov[t]) > 0.0) ? ov[t] - (double)yv : 0.0;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const TK* krow = K + (ib + t < hi ? ib + t : lo) * ldk;
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt) {
+        const int col = j0 + jt * 16 + i16;
+        const double kv = (t < cnt && col < m) ? (double)krow[col] : 0.0;
+#pragma unroll
+        for (int c = 0; c < NCB; ++c)
+          acc[jt][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv, rv[c][t], acc[jt][c], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCB; ++c) {
+    const int q = c * 16 + i16;
+    if (q >= b.count) continue;
+    double* part = b.partial[q] + (int64_t)blockIdx.y * m;
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = j0 + jt * 16 + g + 4 * r;
+        if (j < m) part[j] = acc[jt][c][r];
+      }
+  }
+}
+
+// Row chunks of the dense gradient: at least 512 rows each, and the partials fit the gradient buffer
+// (nchunk * m + 2 * ceil(m / 64) <= 1024 * 256 doubles).
+int gradient_chunks_dense(int64_t n, int m) {
+  const int64_t room = (1024 * 256 - 2 * ceil_div(std::max(m, 1), 64)) / std::max(m, 1);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(room, ceil_div(n, 512)));
+}
+
+// Per slot: g = lambda v + sum of the chunk partials, then |g|^2 and beta . v (grid z = slot).
+__global__ __launch_bounds__(1024) void k_grad_reduce_batch(int m, int nchunk, const GradBatch b) {
+  const int q = blockIdx.z;
+  __shared__ double red[16][64];
+  const int c = threadIdx.x & 63, j = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + c;
+  const double* partial = b.partial[q];
+  double a = 0.0;
+  if (k < m)
+    for (int p = j; p < nchunk; p += 16) a += partial[(int64_t)p * m + k];
+  red[j][c] = a;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double gn = 0.0, bo = 0.0;
+    if (k < m) {
+      double s = 0.0;
+      for (int p = 0; p < 16; ++p) s += red[p][c];
+      s += b.lam[q] * b.v[q][k];
+      b.g[q][k] = s;
+      gn = s * s;
+      bo = b.beta[q][k] * b.v[q][k];
+    }
+    gn = wave_sum(gn);
+    bo = wave_sum(bo);
+    if (threadIdx.x == 0) {
+      double* blk = b.partial[q] + (int64_t)nchunk * m;
+      blk[2 * blockIdx.x] = gn;
+      blk[2 * blockIdx.x + 1] = bo;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_grad_norms_batch(int m, int nchunk, int nblk, const GradBatch b) {
+  const int q = blockIdx.z;
+  const double* blk = b.partial[q] + (int64_t)nchunk * m;
+  double gn = 0.0, bo = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 64) {
+    gn += blk[2 * i];
+    bo += blk[2 * i + 1];
+  }
+  gn = wave_sum(gn);
+  bo = wave_sum(bo);
+  if (threadIdx.x == 0) {
+    b.sc[q]->gnorm2 = gn;
+    b.sc[q]->beta_oJ = bo;
+  }
+}
+
+template <typename TK>
+void launch_gradient_batch(const TK* K, int64_t ldk, int64_t n, int m, const GradBatch& b, hipStream_t s) {
+  if (b.count <= 0 || m <= 0) return;
+  if (b.count > kMaxBatch) throw Failure(1, "gradient batch: too many slots");
+  for (int q = 0; q < b.count; ++q)
+    if ((uintptr_t)b.o[q] & 31u) throw Failure(1, "gradient batch: o must be 32-byte aligned");
+  const int nchunk = gradient_chunks_dense(n, m);
+  // chunks start on multiples of 16 rows, so each lane group's four o values are one aligned vector load
+  const int64_t rows = round_up(ceil_div(std::max<int64_t>(n, 1), nchunk), 16);
+  const dim3 grid((unsigned)ceil_div(m, 64), (unsigned)nchunk);
+  if (n > 0) {
+    if (b.count <= 16)
+      hipLaunchKernelGGL((k_grad_batch<TK, 1>), grid, dim3(64), 0, s, K, ldk, n, m, rows, b);
+    else
+      hipLaunchKernelGGL((k_grad_batch<TK, 2>), grid, dim3(64), 0, s, K, ldk, n, m, rows, b);
+    SPSVM_LAUNCHED();
+  }
+  const int nb = (int)ceil_div(m, 64);
+  hipLaunchKernelGGL(k_grad_reduce_batch, dim3(nb, 1, b.count), dim3(1024), 0, s, m, n > 0 ? nchunk : 0, b);
+  SPSVM_LAUNCHED();
+  hipLaunchKernelGGL(k_grad_norms_batch, dim3(1, 1, b.count), dim3(64), 0, s, m, n > 0 ? nchunk : 0, nb, b);
+  SPSVM_LAUNCHED();
+}
+
 // --------------------------------------------------------------------------------------- flipped rows
 // Lists of rows whose violator status differs between act_new and act_old: joined (new 1, old 0) and left
 // (new 0, old 1), each in ascending order. Same block scheme as the violator compaction.
@@ -884,6 +1031,8 @@ template void launch_gradient<float>(const float*, int64_t, int, const int32_t*,
 template void launch_gradient<double>(const double*, int64_t, int, const int32_t*, int, const double*, const float*,
                                       const double*, const double*, double, double*, int, double*, NewtonScalars*,
                                       hipStream_t);
+template void launch_gradient_batch<float>(const float*, int64_t, int64_t, int, const GradBatch&, hipStream_t);
+template void launch_gradient_batch<double>(const double*, int64_t, int64_t, int, const GradBatch&, hipStream_t);
 template void launch_gemv_batch<float>(const float*, int64_t, int64_t, int, const GemvBatch&, hipStream_t);
 template void launch_gemv_batch<double>(const double*, int64_t, int64_t, int, const GemvBatch&, hipStream_t);
 template void launch_syrk_batch<float>(const SyrkBatch<float>&, int64_t, int, hipStream_t);

@@ -490,6 +490,58 @@ struct Impl {
     }
   }
 
+  // out = K_JJ x (FP64, m x m) for the given slots, batched like gemv_slots.
+  void gemv_kjj_slots(int m, const std::vector<int>& ids, double* Slot::*x, double* Slot::*out) {
+    if (!p.batch) {
+      for (int q : ids) launch_gemv<double>(slots[q].KJJ, p.ldh, m, m, slots[q].*x, slots[q].*out, st);
+      return;
+    }
+    for (size_t a = 0; a < ids.size(); a += kMaxBatch) {
+      GemvBatch gb{};
+      const double* KJJ = slots[ids[a]].KJJ;
+      for (size_t k = a; k < ids.size() && k < a + kMaxBatch; ++k) {
+        const Slot& S = slots[ids[k]];
+        if (S.KJJ != KJJ) throw Failure(SPSVM_E_INVALID_ARG, "batched GEMV: slots must share K_JJ");
+        gb.x[gb.count] = S.*x;
+        gb.out[gb.count] = S.*out;
+        gb.count++;
+      }
+      launch_gemv_batch<double>(KJJ, p.ldh, m, m, gb, st);
+    }
+  }
+
+  // Gradient, |g|^2 and beta . K_JJ beta for the given slots (their violator sets are compacted and their
+  // n_sv read back). A batch takes the dense form, one read of K for up to kMaxBatch slots.
+  void gradient_slots(int m, const std::vector<int>& ids) {
+    gemv_kjj_slots(m, ids, &Slot::beta, &Slot::vJ);
+    if (!p.batch) {
+      for (int q : ids) {
+        Slot& S = slots[q];
+        launch_gradient<TK>(S.K, p.ldk, m, S.I, S.s.n_sv, S.o, S.y, S.vJ, S.beta, S.lam, S.grad_part,
+                            gradient_chunks(m, S.s.n_sv), S.g, S.sc, st);
+      }
+      return;
+    }
+    for (size_t a = 0; a < ids.size(); a += kMaxBatch) {
+      GradBatch gb{};
+      const TK* K = slots[ids[a]].K;
+      for (size_t k = a; k < ids.size() && k < a + kMaxBatch; ++k) {
+        const Slot& S = slots[ids[k]];
+        if (S.K != K) throw Failure(SPSVM_E_INVALID_ARG, "batched gradient: slots must share the kernel block");
+        const int c = gb.count++;
+        gb.o[c] = S.o;
+        gb.y[c] = S.y;
+        gb.partial[c] = S.grad_part;
+        gb.v[c] = S.vJ;
+        gb.beta[c] = S.beta;
+        gb.g[c] = S.g;
+        gb.sc[c] = S.sc;
+        gb.lam[c] = S.lam;
+      }
+      launch_gradient_batch<TK>(K, p.ldk, n, m, gb, st);
+    }
+  }
+
   int newton_slots(int m, const std::vector<int>& ids) {
     if (m <= 0 || ids.empty()) return 0;
     std::vector<int> act;
@@ -514,13 +566,7 @@ struct Impl {
                        S.cblk_flips, S.sc, st);
       }
       read_slots();
-      for (int q : act) {
-        Slot& S = slots[q];
-        const int nchunk = gradient_chunks(m, S.s.n_sv);
-        launch_gemv<double>(S.KJJ, p.ldh, m, m, S.beta, S.vJ, st);
-        launch_gradient<TK>(S.K, p.ldk, m, S.I, S.s.n_sv, S.o, S.y, S.vJ, S.beta, S.lam, S.grad_part, nchunk, S.g,
-                            S.sc, st);
-      }
+      gradient_slots(m, act);
       read_slots();
       std::vector<int> go, refac;
       for (int q : act) {
@@ -562,11 +608,8 @@ struct Impl {
         launch_chol_solve_batch(sb, p.ldh, m, st);
       }
       gemv_slots(m, go, &Slot::dvec, &Slot::delta);
-      for (int q : go) {
-        Slot& S = slots[q];
-        launch_gemv<double>(S.KJJ, p.ldh, m, m, S.dvec, S.wJ, st);
-        launch_c1c2(S.beta, S.dvec, S.wJ, m, S.ls, st);
-      }
+      gemv_kjj_slots(m, go, &Slot::dvec, &Slot::wJ);
+      for (int q : go) launch_c1c2(slots[q].beta, slots[q].dvec, slots[q].wJ, m, slots[q].ls, st);
       const int nblk = score_blocks(n);
       std::vector<int> lsq = go;
       int rounds = 0;
@@ -738,9 +781,8 @@ struct Impl {
     if (!o_fresh) launch_gemv<TK>(S.K, p.ldk, n, m, S.beta, S.o, st);
     launch_compact(S.o, S.y, n, nullptr, S.act_cur, S.I, S.cblk_cnt, S.cblk_sum, S.cblk_flips, S.sc, st);
     NewtonScalars s = read(S.sc);
-    launch_gemv<double>(S.KJJ, p.ldh, m, m, S.beta, S.vJ, st);
-    launch_gradient<TK>(S.K, p.ldk, m, S.I, s.n_sv, S.o, S.y, S.vJ, S.beta, S.lam, S.grad_part,
-                        gradient_chunks(m, s.n_sv), S.g, S.sc, st);
+    S.s = s;
+    gradient_slots(m, {(int)(&S - slots.data())});
     s = read(S.sc);
     *out = s;
     *F = S.C * (0.5 * S.lam * s.beta_oJ + 0.5 * s.sum_a2);
