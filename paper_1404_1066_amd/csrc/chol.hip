@@ -239,50 +239,61 @@ __device__ __forceinline__ void tri_tile(int t, int& tr, int& tc) {
   tc = t - r * (r + 1) / 2;
 }
 
+// Operands come straight from global memory (no LDS, no barrier): wave (wr, wc) owns a 32 x 32 block and lane
+// group g takes the panel columns k0 + 16 g .. k0 + 16 g + 15, so in MFMA step s the four lane groups supply
+// four distinct columns and every column enters the sum once; each lane loads its rows' 16 values as four
+// 32-byte vectors. The strictly upper block of a diagonal tile is skipped.
 __global__ __launch_bounds__(256) void k_chol_update(const CholBatch bt, int64_t ldh, int m, int k0) {
   double* __restrict__ H = bt.H[blockIdx.z];
-  __shared__ __attribute__((aligned(32))) double Pa[NB][TU_LD];
-  __shared__ __attribute__((aligned(32))) double Pb[NB][TU_LD];
   int tr, tc;
   tri_tile(blockIdx.x, tr, tc);
   const int base = k0 + NB;
-  const int ra = base + tr * NB, rb = base + tc * NB;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, i16 = lane & 15;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e / NB, c = e % NB;
-    Pa[r][c] = (ra + r < m) ? H[(int64_t)(ra + r) * ldh + k0 + c] : 0.0;
-    Pb[r][c] = (rb + r < m) ? H[(int64_t)(rb + r) * ldh + k0 + c] : 0.0;
-  }
-  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, i16 = lane & 15;
   const int wr = w >> 1, wc = w & 1;
+  if (tr == tc && wr < wc) return;  // wave-uniform
+  const int ra = base + tr * NB + wr * 32, rb = base + tc * NB + wc * 32;
+  double av[2][16], bv[2][16];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int row = ra + i * 16 + i16;
+    const double* p = H + (int64_t)(row < m ? row : k0) * ldh + k0 + 16 * g;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const doublex4 v = row < m ? *(const doublex4*)(p + 4 * h) : doublex4{0, 0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) av[i][4 * h + e] = v[e];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int row = rb + j * 16 + i16;
+    const double* p = H + (int64_t)(row < m ? row : k0) * ldh + k0 + 16 * g;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const doublex4 v = row < m ? *(const doublex4*)(p + 4 * h) : doublex4{0, 0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bv[j][4 * h + e] = v[e];
+    }
+  }
   doublex4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0, 0, 0, 0};
 #pragma unroll
-  for (int kk = 0; kk < NB; kk += 16) {
-    doublex4 av[2], bv[2];
+  for (int st = 0; st < 16; ++st)
 #pragma unroll
-    for (int i = 0; i < 2; ++i) av[i] = *(const doublex4*)&Pa[wr * 32 + i * 16 + i16][kk + 4 * g];
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) bv[j] = *(const doublex4*)&Pb[wc * 32 + j * 16 + i16][kk + 4 * g];
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
-  }
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][st], bv[j][st], acc[i][j], 0, 0, 0);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gr = ra + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
-        const int gc = rb + wc * 32 + j * 16 + i16;
+        const int gr = ra + i * 16 + g + 4 * r;
+        const int gc = rb + j * 16 + i16;
         if (gr < m && gc < m && gc <= gr) H[(int64_t)gr * ldh + gc] -= acc[i][j][r];
       }
 }

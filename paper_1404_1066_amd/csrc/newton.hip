@@ -498,17 +498,18 @@ void launch_add_diag(double* H, int64_t ldh, int m, double v, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------------------------- batched GEMV
-// One wave per 64 rows of K (four 16-row MFMA tiles) and NCB x 16 vectors. In an MFMA step lane (g, i) supplies
-// K[row i][k] and x_{slot i}[k] for k = k0 + 4g + t (t = 0..3 over four steps), so one 16-byte load per row
-// feeds four steps; acc[i][j][r] ends as out_{slot 16j + i16}[row 16i + g + 4r].
-template <typename TK, int NCB>
+// One wave per RT x 16 rows of K (RT 16-row MFMA tiles) and NCB x 16 vectors. In an MFMA step lane (g, i)
+// supplies K[row i][k] and x_{slot i}[k] for k = k0 + 4g + t (t = 0..3 over four steps), so one 16-byte load per
+// row feeds four steps; acc[i][j][r] ends as out_{slot 16j + i16}[row 16i + g + 4r]. The next 16 k are loaded
+// while the current ones are multiplied.
+template <typename TK, int RT, int NCB>
 __global__ __launch_bounds__(64) void k_gemv_batch(const TK* __restrict__ K, int64_t ldk, int64_t n, int m,
                                                    const GemvBatch b) {
   const int lane = threadIdx.x, g = lane >> 4, i16 = lane & 15;
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
-  const TK* krow[4];
+  const int64_t r0 = (int64_t)blockIdx.x * (RT * 16);
+  const TK* krow[RT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < RT; ++i) {
     const int64_t row = r0 + i * 16 + i16;
     krow[i] = row < n ? K + row * ldk : nullptr;
   }
@@ -518,27 +519,39 @@ __global__ __launch_bounds__(64) void k_gemv_batch(const TK* __restrict__ K, int
     const int q = j * 16 + i16;
     xs[j] = q < b.count ? b.x[q] : nullptr;
   }
-  doublex4 acc[4][NCB];
+  doublex4 acc[RT][NCB];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < NCB; ++j) acc[i][j] = doublex4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < m; k0 += 16) {
+  TK kv[RT][4];
+  double xv[NCB][4];
+  auto fetch = [&](int k0) {
     const int kb = k0 + 4 * g;
     const int cnt = min(max(m - kb, 0), 4);
-    TK kv[4][4];
-    double xv[NCB][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) load4(krow[i] ? krow[i] + kb : K, krow[i] ? cnt : 0, kv[i]);
+    for (int i = 0; i < RT; ++i) load4(krow[i] ? krow[i] + kb : K, krow[i] ? cnt : 0, kv[i]);
 #pragma unroll
     for (int j = 0; j < NCB; ++j) load4(xs[j] ? xs[j] + kb : b.x[0], xs[j] ? cnt : 0, xv[j]);
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < m; k0 += 16) {
+    double a[RT][4], c[NCB][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+      for (int i = 0; i < RT; ++i) a[i][t] = (double)kv[i][t];
+#pragma unroll
+      for (int j = 0; j < NCB; ++j) c[j][t] = xv[j][t];
+    }
+    if (k0 + 16 < m) fetch(k0 + 16);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < RT; ++i)
 #pragma unroll
         for (int j = 0; j < NCB; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)kv[i][t], xv[j][t], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][t], c[j][t], acc[i][j], 0, 0, 0);
   }
 #pragma unroll
   for (int j = 0; j < NCB; ++j) {
@@ -546,7 +559,7 @@ __global__ __launch_bounds__(64) void k_gemv_batch(const TK* __restrict__ K, int
     if (q >= b.count) continue;
     double* out = b.out[q];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = r0 + i * 16 + g + 4 * r;
@@ -561,11 +574,20 @@ void launch_gemv_batch(const TK* K, int64_t ldk, int64_t n, int m, const GemvBat
   if (b.count > kMaxBatch || (ldk & 3) || ((uintptr_t)K & 15u)) throw Failure(1, "GEMV batch: bad arguments");
   for (int q = 0; q < b.count; ++q)
     if ((uintptr_t)b.x[q] & 31u) throw Failure(1, "GEMV batch: vectors must be 32-byte aligned");
-  const dim3 grid((unsigned)ceil_div(n, 64));
-  if (b.count <= 16)
-    hipLaunchKernelGGL((k_gemv_batch<TK, 1>), grid, dim3(64), 0, s, K, ldk, n, m, b);
-  else
-    hipLaunchKernelGGL((k_gemv_batch<TK, 2>), grid, dim3(64), 0, s, K, ldk, n, m, b);
+  // 32-row waves fill the chip for tall blocks; 16-row waves for short ones (K_JJ)
+  if (n >= 16384) {
+    const dim3 grid((unsigned)ceil_div(n, 32));
+    if (b.count <= 16)
+      hipLaunchKernelGGL((k_gemv_batch<TK, 2, 1>), grid, dim3(64), 0, s, K, ldk, n, m, b);
+    else
+      hipLaunchKernelGGL((k_gemv_batch<TK, 2, 2>), grid, dim3(64), 0, s, K, ldk, n, m, b);
+  } else {
+    const dim3 grid((unsigned)ceil_div(n, 16));
+    if (b.count <= 16)
+      hipLaunchKernelGGL((k_gemv_batch<TK, 1, 1>), grid, dim3(64), 0, s, K, ldk, n, m, b);
+    else
+      hipLaunchKernelGGL((k_gemv_batch<TK, 1, 2>), grid, dim3(64), 0, s, K, ldk, n, m, b);
+  }
   SPSVM_LAUNCHED();
 }
 
@@ -594,20 +616,19 @@ __global__ __launch_bounds__(64) void k_grad_batch(const TK* __restrict__ K, int
   for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
     for (int c = 0; c < NCB; ++c) acc[jt][c] = doublex4{0, 0, 0, 0};
-  for (int64_t i0 = lo; i0 < hi; i0 += 16) {
+  // operands of 16 rows: K values and o, y of this lane group's four rows; the next block is loaded while the
+  // current one is multiplied
+  TK kx[4][4];
+  double ox[NCB][4];
+  float yx[NCB][4];
+  auto fetch = [&](int64_t i0) {
     const int64_t ib = i0 + 4 * g;
     const int64_t cnt = hi - ib;
-    double rv[NCB][4];
 #pragma unroll
     for (int c = 0; c < NCB; ++c) {
-      double ov[4];
-      load4(os[c] && cnt > 0 ? os[c] + ib : b.o[0], os[c] ? (int)min<int64_t>(max<int64_t>(cnt, 0), 4) : 0, ov);
+      load4(os[c] && cnt > 0 ? os[c] + ib : b.o[0], os[c] ? (int)min<int64_t>(max<int64_t>(cnt, 0), 4) : 0, ox[c]);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const bool in = os[c] && t < cnt;
-        const float yv = in ? ys[c][ib + t] : 0.0f;
-        rv[c][t] = (in && margin_gap(yv, ov[t]) > 0.0) ? ov[t] - (double)yv : 0.0;
-      }
+      for (int t = 0; t < 4; ++t) yx[c][t] = (os[c] && t < cnt) ? ys[c][ib + t] : 0.0f;
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -615,12 +636,33 @@ __global__ __launch_bounds__(64) void k_grad_batch(const TK* __restrict__ K, int
 #pragma unroll
       for (int jt = 0; jt < 4; ++jt) {
         const int col = j0 + jt * 16 + i16;
-        const double kv = (t < cnt && col < m) ? (double)krow[col] : 0.0;
-#pragma unroll
-        for (int c = 0; c < NCB; ++c)
-          acc[jt][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv, rv[c][t], acc[jt][c], 0, 0, 0);
+        kx[t][jt] = (t < cnt && col < m) ? krow[col] : (TK)0;
       }
     }
+  };
+  if (lo < hi) fetch(lo);
+  for (int64_t i0 = lo; i0 < hi; i0 += 16) {
+    const int64_t cnt = hi - (i0 + 4 * g);
+    double rv[NCB][4], kv[4][4];
+#pragma unroll
+    for (int c = 0; c < NCB; ++c)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bool in = os[c] && t < cnt;
+        rv[c][t] = (in && margin_gap(yx[c][t], ox[c][t]) > 0.0) ? ox[c][t] - (double)yx[c][t] : 0.0;
+      }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt) kv[t][jt] = (double)kx[t][jt];
+    if (i0 + 16 < hi) fetch(i0 + 16);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c)
+          acc[jt][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[t][jt], rv[c][t], acc[jt][c], 0, 0, 0);
   }
 #pragma unroll
   for (int c = 0; c < NCB; ++c) {
