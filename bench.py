@@ -208,7 +208,9 @@ def main():
     dt = torch.float64 if args.precision == "f64" else torch.float32
     Xg = torch.tensor(p.X, dtype=dt, device="cuda")
     yg = torch.tensor(p.y, dtype=torch.float32, device="cuda")
-    ws = torch.empty(lib.workspace_bytes(n, d, p.J_max, dtype=dt, precision=args.precision), dtype=torch.uint8, device="cuda")
+    # sized for the mixed-precision runs too (they also hold the split-BF16 copies of X)
+    ws_prec = "mixed" if (args.precision == "f32" and not args.no_mixed) else args.precision
+    ws = torch.empty(lib.workspace_bytes(n, d, p.J_max, dtype=dt, precision=ws_prec), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     common = dict(precision=args.precision, workspace=ws, stream=stream)
 

@@ -220,7 +220,8 @@ extern "C" {
 
 static size_t rbf_ws(int64_t n, int64_t d, bool xd) {
   const int64_t xe = xd ? 8 : 4, ld = spsvm::round_up(d, 16 / xe);
-  return (size_t)spsvm::round_up(n * 8, 256) + (size_t)n * ld * xe;
+  const size_t split = (size_t)spsvm::round_up(n * spsvm::split_ld(d) * 2, 256);  // one BF16 copy
+  return (size_t)spsvm::round_up(n * 8, 256) + (size_t)spsvm::round_up(n * ld * xe, 256) + 2 * split;
 }
 
 template <typename TX, typename TK>
@@ -237,7 +238,12 @@ static void rbf_typed(const TX* X, int64_t n, int64_t d, const int32_t* idx, int
   spsvm::launch_row_norms<TX, TK>(X, n, d, d, nrm, st);
   if constexpr (std::is_same<TK, float>::value) {
     if (split) {
-      spsvm::launch_kblock_split<TX>(A, ld, n, d, nrm, idx, (int)ncols, out, ldo, gamma, false, st);
+      const int64_t ldb = spsvm::split_ld(d);
+      unsigned short* hi = (unsigned short*)(ws + spsvm::round_up(n * 8, 256) +
+                                             spsvm::round_up(n * spsvm::padded_ld<TX>(d) * (int64_t)sizeof(TX), 256));
+      unsigned short* lo = hi + spsvm::round_up(n * ldb * 2, 256) / 2;
+      spsvm::launch_split_bf16<TX>(X, n, d, d, hi, lo, ldb, st);
+      spsvm::launch_kblock_bf16(hi, lo, ldb, n, nrm, idx, (int)ncols, out, ldo, gamma, st);
       return;
     }
   }

@@ -329,73 +329,89 @@ __device__ __forceinline__ float bf16_bits_to_float(unsigned short h) { return _
 
 constexpr int SB_BK = 32, SB_LD = SB_BK + 8;  // bf16 elements per LDS row (16-byte aligned rows)
 
-// SPLIT = false: every operand value is exactly a BF16 number, so lo = 0 and the two correction products
-// are exact zeros; only hi.hi' is issued (the same result bit for bit).
-template <typename TX, bool SPLIT>
-__global__ __launch_bounds__(256) void k_kblock_split(const TX* __restrict__ X, int64_t ldx, int64_t n, int64_t d,
-                                                      const float* __restrict__ xnorm,
-                                                      const int32_t* __restrict__ cidx, int ncols,
-                                                      float* __restrict__ out, int64_t ldo, double gamma,
-                                                      const Score0 s0) {
-  __shared__ __attribute__((aligned(16))) unsigned short Ah[KB_BM][SB_LD], Al[KB_BM][SB_LD];
-  __shared__ __attribute__((aligned(16))) unsigned short Bh[KB_BN][SB_LD], Bl[KB_BN][SB_LD];
-  constexpr int V = Vec16<TX>::n;
-  constexpr int NA = KB_BM * SB_BK / V / 256, NB = KB_BN * SB_BK / V / 256, P = SB_BK / V;
-  using VT = typename Vec16<TX>::type;
+// The split copies: hi and lo, n x ldb each (ldb = d rounded up to 32, zero padded), computed once per run.
+int64_t split_ld(int64_t d) { return round_up(d, SB_BK); }
+
+template <typename TX>
+__global__ __launch_bounds__(256) void k_split_bf16(const TX* __restrict__ X, int64_t n, int64_t d, int64_t ldx,
+                                                    unsigned short* __restrict__ hi, unsigned short* __restrict__ lo,
+                                                    int64_t ldb) {
+  const int64_t total = n * ldb;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / ldb, k = e - i * ldb;
+    const double v = k < d ? (double)X[i * ldx + k] : 0.0;
+    const unsigned short h = bf16_rne_bits((float)v);
+    hi[e] = h;
+    if (lo) lo[e] = bf16_rne_bits((float)(v - (double)bf16_bits_to_float(h)));
+  }
+}
+
+template <typename TX>
+void launch_split_bf16(const TX* X, int64_t n, int64_t d, int64_t ldx, unsigned short* hi, unsigned short* lo,
+                       int64_t ldb, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n * ldb, 256), 65536));
+  hipLaunchKernelGGL((k_split_bf16<TX>), dim3((unsigned)blocks), dim3(256), 0, st, X, n, d, ldx, hi, lo, ldb);
+  SPSVM_LAUNCHED();
+}
+
+// Split-BF16 block from the split copies: tiles of 128 rows x 64 columns, 4 waves of 32 x 64, the k loop in
+// chunks of 32 staged through LDS by 16-byte copies (no conversion in the loop); the next chunk is loaded
+// into registers while the current one is multiplied. SPLIT = false: every value is exactly a BF16 number,
+// so lo = 0 and the correction products are exact zeros; only hi.hi' is issued (the same result bit for bit).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __restrict__ hi,
+                                                     const unsigned short* __restrict__ lo, int64_t ldb, int64_t n,
+                                                     const float* __restrict__ xnorm,
+                                                     const int32_t* __restrict__ cidx, int ncols,
+                                                     float* __restrict__ out, int64_t ldo, double gamma,
+                                                     const Score0 s0) {
+  __shared__ __attribute__((aligned(16))) unsigned short Ah[KB_BM][SB_LD], Bh[KB_BN][SB_LD];
+  __shared__ __attribute__((aligned(16))) unsigned short Al[SPLIT ? KB_BM : 1][SB_LD], Bl[SPLIT ? KB_BN : 1][SB_LD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, i16 = lane & 15;
   const int64_t r0 = (int64_t)blockIdx.x * KB_BM, c0 = (int64_t)blockIdx.y * KB_BN;
-  const int kq = (tid % P) * V;
-  const TX* arow[NA];
-  const TX* brow[NB];
+  const int part = tid & 3;  // which 8 of the chunk's 32 k this thread stages
+  int64_t aoff[2], boff;
 #pragma unroll
-  for (int e = 0; e < NA; ++e) {
-    const int64_t row = r0 + (tid + e * 256) / P;
-    arow[e] = row < n ? X + row * ldx : nullptr;
+  for (int q = 0; q < 2; ++q) {
+    const int64_t row = r0 + ((tid + 256 * q) >> 2);
+    aoff[q] = row < n ? row * ldb + 8 * part : -1;
   }
-#pragma unroll
-  for (int e = 0; e < NB; ++e) {
-    const int64_t col = c0 + (tid + e * 256) / P;
+  {
+    const int64_t col = c0 + (tid >> 2);
     const int64_t src = col < ncols ? (cidx ? (int64_t)cidx[col] : col) : -1;
-    brow[e] = src >= 0 ? X + src * ldx : nullptr;
+    boff = src >= 0 ? src * ldb + 8 * part : -1;
   }
   floatx4 acc[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0, 0, 0, 0};
-  VT ra[NA], rb[NB];
+  u32x4 rah[2], ral[2], rbh, rbl;
   auto fetch = [&](int64_t k0) {
 #pragma unroll
-    for (int e = 0; e < NA; ++e) ra[e] = (arow[e] && k0 + kq < d) ? *(const VT*)(arow[e] + k0 + kq) : VT{};
-#pragma unroll
-    for (int e = 0; e < NB; ++e) rb[e] = (brow[e] && k0 + kq < d) ? *(const VT*)(brow[e] + k0 + kq) : VT{};
-  };
-  auto split_store = [&](const VT& v, int64_t k0, unsigned short* hi, unsigned short* lo) {
-#pragma unroll
-    for (int t = 0; t < V; ++t) {
-      const bool in = k0 + kq + t < d;
-      const float xv = in ? (float)v[t] : 0.0f;
-      const unsigned short h = bf16_rne_bits(xv);
-      const double rest = in ? (double)v[t] - (double)bf16_bits_to_float(h) : 0.0;
-      hi[t] = h;
-      if (SPLIT) lo[t] = bf16_rne_bits((float)rest);
+    for (int q = 0; q < 2; ++q) {
+      rah[q] = aoff[q] >= 0 ? *(const u32x4*)(hi + aoff[q] + k0) : u32x4{0, 0, 0, 0};
+      if (SPLIT) ral[q] = aoff[q] >= 0 ? *(const u32x4*)(lo + aoff[q] + k0) : u32x4{0, 0, 0, 0};
     }
+    rbh = boff >= 0 ? *(const u32x4*)(hi + boff + k0) : u32x4{0, 0, 0, 0};
+    if (SPLIT) rbl = boff >= 0 ? *(const u32x4*)(lo + boff + k0) : u32x4{0, 0, 0, 0};
   };
   fetch(0);
-  for (int64_t k0 = 0; k0 < d; k0 += SB_BK) {
+  for (int64_t k0 = 0; k0 < ldb; k0 += SB_BK) {
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < NA; ++e) {
-      const int r = (tid + e * 256) / P;
-      split_store(ra[e], k0, &Ah[r][kq], &Al[r][kq]);
+    for (int q = 0; q < 2; ++q) {
+      const int r = (tid + 256 * q) >> 2;
+      *(u32x4*)&Ah[r][8 * part] = rah[q];
+      if (SPLIT) *(u32x4*)&Al[r][8 * part] = ral[q];
     }
-#pragma unroll
-    for (int e = 0; e < NB; ++e) {
-      const int r = (tid + e * 256) / P;
-      split_store(rb[e], k0, &Bh[r][kq], &Bl[r][kq]);
-    }
+    *(u32x4*)&Bh[tid >> 2][8 * part] = rbh;
+    if (SPLIT) *(u32x4*)&Bl[tid >> 2][8 * part] = rbl;
     __syncthreads();
-    if (k0 + SB_BK < d) fetch(k0 + SB_BK);
+    if (k0 + SB_BK < ldb) fetch(k0 + SB_BK);
     bf16x8 ah[2], al[2], bh[4], bl[4];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -459,21 +475,20 @@ __global__ __launch_bounds__(256) void k_kblock_split(const TX* __restrict__ X, 
   }
 }
 
-template <typename TX>
-void launch_kblock_split(const TX* X, int64_t ldx, int64_t n, int64_t d, const float* xnorm, const int32_t* cidx,
-                         int ncols, float* out, int64_t ldo, double gamma, bool bf16_exact, hipStream_t st,
-                         const Score0& s0) {
+void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int64_t ldb, int64_t n,
+                        const float* xnorm, const int32_t* cidx, int ncols, float* out, int64_t ldo, double gamma,
+                        hipStream_t st, const Score0& s0) {
   if (n <= 0 || ncols <= 0) return;
-  if (ldx % Vec16<TX>::n != 0 || ((uintptr_t)X & 15u))
-    throw Failure(1, "kernel block: rows must start on 16-byte boundaries");
+  if (ldb % SB_BK != 0 || ((uintptr_t)hi & 15u) || ((uintptr_t)lo & 15u))
+    throw Failure(1, "kernel block: split copies must be 16-byte aligned with ldb a multiple of 32");
   if (s0.partial && ncols > KB_BN) throw Failure(1, "kernel block: the fused scoring pass takes one column tile");
   dim3 grid((unsigned)ceil_div(n, KB_BM), (unsigned)ceil_div(ncols, KB_BN));
-  if (bf16_exact)
-    hipLaunchKernelGGL((k_kblock_split<TX, false>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out,
-                       ldo, gamma, s0);
+  if (lo)
+    hipLaunchKernelGGL(k_kblock_bf16<true>, grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out, ldo,
+                       gamma, s0);
   else
-    hipLaunchKernelGGL((k_kblock_split<TX, true>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out,
-                       ldo, gamma, s0);
+    hipLaunchKernelGGL(k_kblock_bf16<false>, grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out, ldo,
+                       gamma, s0);
   SPSVM_LAUNCHED();
 }
 
@@ -661,10 +676,10 @@ SPSVM_INST(double, double)
 #undef SPSVM_INST
 template void launch_row_hash<float>(const float*, int64_t, int64_t, uint64_t*, hipStream_t);
 template void launch_row_hash<double>(const double*, int64_t, int64_t, uint64_t*, hipStream_t);
-template void launch_kblock_split<float>(const float*, int64_t, int64_t, int64_t, const float*, const int32_t*, int,
-                                         float*, int64_t, double, bool, hipStream_t, const Score0&);
-template void launch_kblock_split<double>(const double*, int64_t, int64_t, int64_t, const float*, const int32_t*, int,
-                                          float*, int64_t, double, bool, hipStream_t, const Score0&);
+template void launch_split_bf16<float>(const float*, int64_t, int64_t, int64_t, unsigned short*, unsigned short*,
+                                       int64_t, hipStream_t);
+template void launch_split_bf16<double>(const double*, int64_t, int64_t, int64_t, unsigned short*, unsigned short*,
+                                        int64_t, hipStream_t);
 template void launch_rbf_from_dist<float>(const float*, int64_t, int, int64_t, float*, double, hipStream_t);
 template void launch_rbf_from_dist<double>(const double*, int64_t, int, int64_t, double*, double, hipStream_t);
 template void launch_pad_rows<float>(const float*, int64_t, int64_t, float*, int64_t, hipStream_t);

@@ -75,12 +75,18 @@ void launch_kblock(const TX* X, int64_t ldx, int64_t n, int64_t d, const TK* xno
 template <typename TX, typename TK>
 void launch_predict(const TX* Xt, int64_t ldxt, int64_t n, int64_t d, const TK* Z, int64_t ldz, const TK* znorm, int m,
                     const double* beta, double* out, double gamma, hipStream_t st);
-// Same block with split-BF16 products (x = hi + lo; x.z ~ hi.hi' + hi.lo' + lo.hi'), FP32 results.
-// bf16_exact: every X value is a BF16 number (lo = 0), so only hi.hi' is issued (identical result).
+// Split-BF16 copies of X for the mixed kernel block: hi = bf16(x), lo = bf16(x - hi) (round to nearest even),
+// n x ldb each with ldb = split_ld(d) (d rounded up to 32, zero padded); lo may be null (not needed).
+int64_t split_ld(int64_t d);
 template <typename TX>
-void launch_kblock_split(const TX* X, int64_t ldx, int64_t n, int64_t d, const float* xnorm, const int32_t* cidx,
-                         int ncols, float* out, int64_t ldo, double gamma, bool bf16_exact, hipStream_t st,
-                         const Score0& s0 = Score0{});
+void launch_split_bf16(const TX* X, int64_t n, int64_t d, int64_t ldx, unsigned short* hi, unsigned short* lo,
+                       int64_t ldb, hipStream_t st);
+// The kernel block with split-BF16 products x.z ~ hi.hi' + hi.lo' + lo.hi' from the split copies, FP32 results
+// (same output and fused pass as launch_kblock). lo = nullptr: every X value is a BF16 number (lo = 0), so only
+// hi.hi' is issued (identical result).
+void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int64_t ldb, int64_t n,
+                        const float* xnorm, const int32_t* cidx, int ncols, float* out, int64_t ldo, double gamma,
+                        hipStream_t st, const Score0& s0 = Score0{});
 template <typename TK>
 void launch_rbf_from_dist(const TK* D, int64_t rows, int ncols, int64_t ld, TK* K, double gamma, hipStream_t st);
 template <typename TX>

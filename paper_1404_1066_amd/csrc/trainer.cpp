@@ -102,6 +102,10 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.D = take(batch ? (size_t)n * p.ldk * tk : 0);
   p.DJJ = take(batch ? (size_t)J_max * p.ldh * 8 : 0);
   p.G = take(batch ? (size_t)J_max * p.ldh * 8 : 0);
+  const bool mixed = opt.precision == SPSVM_MIXED;
+  p.ldb = split_ld(d);
+  p.Xhi = take(mixed ? (size_t)n * p.ldb * 2 : 0);
+  p.Xlo = take(mixed ? (size_t)n * p.ldb * 2 : 0);
   // one problem's Newton state
   {
     size_t so = 0;
@@ -379,7 +383,8 @@ struct Impl {
   void kblock(const int32_t* cols, int ncols, TK* out, int64_t ldo, const Score0& s0 = Score0{}) {
     if constexpr (std::is_same<TK, float>::value) {
       if (opt.precision == SPSVM_MIXED) {
-        launch_kblock_split<TX>(Xk, p.ldx, n, d, xnorm, cols, ncols, out, ldo, gamma, bf16_exact, st, s0);
+        launch_kblock_bf16(at<unsigned short>(p.Xhi), bf16_exact ? nullptr : at<unsigned short>(p.Xlo), p.ldb, n,
+                           xnorm, cols, ncols, out, ldo, gamma, st, s0);
         return;
       }
     }
@@ -424,6 +429,9 @@ struct Impl {
     std::memcpy(f, pin.p, 12);
     if (f[0]) throw Failure(SPSVM_E_INVALID_ARG, "X holds NaN or Inf");
     bf16_exact = f[2] == 0;
+    if (opt.precision == SPSVM_MIXED)
+      launch_split_bf16<TX>(X, n, d, d, at<unsigned short>(p.Xhi), bf16_exact ? nullptr : at<unsigned short>(p.Xlo),
+                            p.ldb, st);
     if (f[1]) throw Failure(SPSVM_E_INVALID_ARG, "labels must be exactly +1 or -1");
     std::vector<uint64_t> hs = hash_host;
     std::sort(hs.begin(), hs.end());
