@@ -43,6 +43,33 @@ def test_blobs_full_pipeline_identical_basis_f64():
     assert _decision_err(dg, do) <= 1e-4
 
 
+def test_wide_rows_identical_basis_f64():
+    """Rows of 300 features (several k chunks per tile, a ragged last chunk): the FP64 path must pick the
+    oracle's basis, step for step."""
+    X, y = datagen.make_blobs(2500, 300, seed=21)
+    C, gamma, m = 1.0, 1.0 / 300, 60
+    ref = oracle.train(X, y, C, gamma, m, seed=5)
+    Xg, yg = _dev(X, y)
+    model = lib.train(Xg, yg, C, gamma, m, seed=5, precision="f64")
+    J, beta, F = model.get()
+    assert J.tolist() == ref.J.tolist()
+    Fo = osp.objective_at(X, y, C, gamma, J, beta)
+    assert abs(Fo - ref.F) <= 1e-6 * ref.F
+
+
+@pytest.mark.parametrize("prec", ["f32", "mixed"])
+def test_wide_rows_f32_mixed_reach_oracle_objective(prec):
+    X, y = datagen.make_blobs(3001, 333, seed=22, dtype=np.float32)
+    C, gamma, m = 2.0, 1.0 / 333, 90
+    Xg, yg = _dev(X, y)
+    model = lib.train(Xg, yg, C, gamma, m, seed=6, precision=prec)
+    J, beta, F = model.get()
+    assert len(set(J.tolist())) == m
+    b_or, F_or, _ = osp.solve_fixed_J(X, y, C, gamma, J)
+    Fo = osp.objective_at(X, y, C, gamma, J, beta)
+    assert (Fo - F_or) / F_or <= 1e-6
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_fixed_basis_ragged_matches_oracle(prec):
     X, y = datagen.make_blobs(5003, 37, seed=11, dtype=np.float32 if prec == "f32" else np.float64)
