@@ -104,6 +104,22 @@ __device__ __forceinline__ double gamma_scale<double>(double g) { return g; }
 // read; A and B use the same k assignment, so the sum runs over every k exactly once.
 constexpr int KB_BM = 128, KB_BN = 64, KB_BK = 32, KB_PAD = 4, KB_LD = KB_BK + KB_PAD;
 
+// XCD-aware tile order. Workgroups are dealt to the 8 XCDs round robin (workgroup L runs on XCD L % 8), each
+// XCD with its own L2. The launch is one-dimensional over ceil(R / 8) * 8 * C workgroups for R row tiles and C
+// column tiles; workgroup L takes row tile 8 ((L / 8) / C) + L % 8 and column tile (L / 8) % C, so the C
+// column tiles of a row tile run back to back on one XCD and read its rows of X from that XCD's L2.
+constexpr int kXcds = 8;
+struct TileOf {
+  int64_t r, c;
+};
+__device__ __forceinline__ TileOf xcd_tile(int64_t ctiles) {
+  const int64_t L = blockIdx.x, q = L / kXcds;
+  return TileOf{(q / ctiles) * kXcds + L % kXcds, q % ctiles};
+}
+inline unsigned xcd_grid(int64_t rtiles, int64_t ctiles) {
+  return (unsigned)(round_up(rtiles, kXcds) * ctiles);
+}
+
 // Operand rows are read with 16-byte vector loads: every row of A and B starts at a multiple of lda / ldb
 // elements with lda, ldb multiples of 16 / sizeof(element) (the caller pads the feature matrix when needed),
 // and elements past d in a row are ignored.
@@ -212,8 +228,10 @@ struct Score0Acc {
       Q[j] += b * b;
     }
   }
-  // partial record of this tile for every column of the block (64 columns)
-  __device__ __forceinline__ void finish(double* __restrict__ partial, int64_t tile, double (*red)[64][2]) {
+  // partial records for every column of the block (64 columns): waves w * wpr .. w * wpr + wpr - 1 (each
+  // covering 128 / wpr rows) form record rec0 + w; records at or past nrec are not written
+  __device__ __forceinline__ void finish(double* __restrict__ partial, int64_t rec0, int64_t nrec, int wpr,
+                                         double (*red)[64][2]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -227,15 +245,14 @@ struct Score0Acc {
       }
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
-      const int c = threadIdx.x;
+    const int grp = threadIdx.x >> 6, c = threadIdx.x & 63;
+    if (grp < 4 / wpr && rec0 + grp < nrec) {
       double p = 0.0, q = 0.0;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        p += red[v][c][0];
-        q += red[v][c][1];
+      for (int v = 0; v < wpr; ++v) {
+        p += red[grp * wpr + v][c][0];
+        q += red[grp * wpr + v][c][1];
       }
-      double* out = partial + (tile * 64 + c) * 4;
+      double* out = partial + ((rec0 + grp) * 64 + c) * 4;
       out[0] = p;
       out[1] = q;
       out[2] = 0.0;
@@ -244,7 +261,7 @@ struct Score0Acc {
   }
 };
 
-// STORE: out[row * ldo + c] for the column tile blockIdx.y.
+// STORE: out[row * ldo + c] for the tile of xcd_tile().
 // gamma > 0: out = exp(-gamma d2); gamma == 0: out = d2 (the squared distance itself, clamped at 0).
 template <typename TX, typename TK>
 __global__ __launch_bounds__(256) void k_kblock_store(const TX* __restrict__ X, int64_t ldx, int64_t n, int64_t d,
@@ -254,13 +271,15 @@ __global__ __launch_bounds__(256) void k_kblock_store(const TX* __restrict__ X, 
   using M = Mfma<TK>;
   __shared__ __attribute__((aligned(32))) TK As[KB_BM][KB_LD];
   __shared__ __attribute__((aligned(32))) TK Bs[KB_BN][KB_LD];
-  const int64_t r0 = (int64_t)blockIdx.x * KB_BM, c0 = (int64_t)blockIdx.y * KB_BN;
+  const TileOf tile = xcd_tile(ceil_div_dev(ncols, KB_BN));
+  const int64_t r0 = tile.r * KB_BM, c0 = tile.c * KB_BN;
+  if (r0 >= n) return;  // padding of the row-tile count to a multiple of 8
   KTile<TX, TX, TK> t;
   t.zero();
   t.run(X, ldx, n, r0, X, ldx, cidx, c0, ncols, d, As, Bs);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const TK gs = gamma_scale<TK>(gamma);
-  const bool fused = s0.partial != nullptr;
+  const bool fused = s0.partial != nullptr;  // (one column tile: checked at launch)
   double ga[2][4];  // a_i of this lane's rows (fused pass)
   float gy[2][4];
   if (fused) {
@@ -296,7 +315,7 @@ __global__ __launch_bounds__(256) void k_kblock_store(const TX* __restrict__ X, 
   }
   if (fused) {
     __shared__ double red[4][64][2];
-    sa.finish(s0.partial, blockIdx.x, red);
+    sa.finish(s0.partial, tile.r, tile.r + 1, 4, red);
   }
 }
 
@@ -307,7 +326,7 @@ void launch_kblock(const TX* X, int64_t ldx, int64_t n, int64_t d, const TK* xno
   if (ldx % Vec16<TX>::n != 0 || ((uintptr_t)X & 15u))
     throw Failure(1, "kernel block: rows must start on 16-byte boundaries");
   if (s0.partial && ncols > KB_BN) throw Failure(1, "kernel block: the fused scoring pass takes one column tile");
-  dim3 grid((unsigned)ceil_div(n, KB_BM), (unsigned)ceil_div(ncols, KB_BN));
+  const dim3 grid(xcd_grid(ceil_div(n, KB_BM), ceil_div(ncols, KB_BN)));
   hipLaunchKernelGGL((k_kblock_store<TX, TK>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out, ldo,
                      gamma, s0);
   SPSVM_LAUNCHED();
@@ -361,21 +380,24 @@ void launch_split_bf16(const TX* X, int64_t n, int64_t d, int64_t ldx, unsigned 
 // so lo = 0 and the correction products are exact zeros; only hi.hi' is issued (the same result bit for bit).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <bool SPLIT>
+template <bool SPLIT, int RTW>
 __global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __restrict__ hi,
                                                      const unsigned short* __restrict__ lo, int64_t ldb, int64_t n,
                                                      const float* __restrict__ xnorm,
                                                      const int32_t* __restrict__ cidx, int ncols,
                                                      float* __restrict__ out, int64_t ldo, double gamma,
                                                      const Score0 s0) {
-  __shared__ __attribute__((aligned(16))) unsigned short Ah[KB_BM][SB_LD], Bh[KB_BN][SB_LD];
-  __shared__ __attribute__((aligned(16))) unsigned short Al[SPLIT ? KB_BM : 1][SB_LD], Bl[SPLIT ? KB_BN : 1][SB_LD];
+  constexpr int BM = 64 * RTW;  // rows per workgroup: 4 waves of RTW 16-row tiles
+  __shared__ __attribute__((aligned(16))) unsigned short Ah[BM][SB_LD], Bh[KB_BN][SB_LD];
+  __shared__ __attribute__((aligned(16))) unsigned short Al[SPLIT ? BM : 1][SB_LD], Bl[SPLIT ? KB_BN : 1][SB_LD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, i16 = lane & 15;
-  const int64_t r0 = (int64_t)blockIdx.x * KB_BM, c0 = (int64_t)blockIdx.y * KB_BN;
+  const TileOf tile = xcd_tile(ceil_div_dev(ncols, KB_BN));
+  const int64_t r0 = tile.r * BM, c0 = tile.c * KB_BN;
+  if (r0 >= n) return;  // padding of the row-tile count to a multiple of 8
   const int part = tid & 3;  // which 8 of the chunk's 32 k this thread stages
-  int64_t aoff[2], boff;
+  int64_t aoff[RTW], boff;
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < RTW; ++q) {
     const int64_t row = r0 + ((tid + 256 * q) >> 2);
     aoff[q] = row < n ? row * ldb + 8 * part : -1;
   }
@@ -384,15 +406,15 @@ __global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __res
     const int64_t src = col < ncols ? (cidx ? (int64_t)cidx[col] : col) : -1;
     boff = src >= 0 ? src * ldb + 8 * part : -1;
   }
-  floatx4 acc[2][4];
+  floatx4 acc[RTW][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < RTW; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0, 0, 0, 0};
-  u32x4 rah[2], ral[2], rbh, rbl;
+  u32x4 rah[RTW], ral[RTW], rbh, rbl;
   auto fetch = [&](int64_t k0) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < RTW; ++q) {
       rah[q] = aoff[q] >= 0 ? *(const u32x4*)(hi + aoff[q] + k0) : u32x4{0, 0, 0, 0};
       if (SPLIT) ral[q] = aoff[q] >= 0 ? *(const u32x4*)(lo + aoff[q] + k0) : u32x4{0, 0, 0, 0};
     }
@@ -403,7 +425,7 @@ __global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __res
   for (int64_t k0 = 0; k0 < ldb; k0 += SB_BK) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < RTW; ++q) {
       const int r = (tid + 256 * q) >> 2;
       *(u32x4*)&Ah[r][8 * part] = rah[q];
       if (SPLIT) *(u32x4*)&Al[r][8 * part] = ral[q];
@@ -412,11 +434,11 @@ __global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __res
     if (SPLIT) *(u32x4*)&Bl[tid >> 2][8 * part] = rbl;
     __syncthreads();
     if (k0 + SB_BK < ldb) fetch(k0 + SB_BK);
-    bf16x8 ah[2], al[2], bh[4], bl[4];
+    bf16x8 ah[RTW], al[RTW], bh[4], bl[4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      ah[i] = *(const bf16x8*)&Ah[w * 32 + i * 16 + i16][8 * g];
-      if (SPLIT) al[i] = *(const bf16x8*)&Al[w * 32 + i * 16 + i16][8 * g];
+    for (int i = 0; i < RTW; ++i) {
+      ah[i] = *(const bf16x8*)&Ah[w * 16 * RTW + i * 16 + i16][8 * g];
+      if (SPLIT) al[i] = *(const bf16x8*)&Al[w * 16 * RTW + i * 16 + i16][8 * g];
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -424,7 +446,7 @@ __global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __res
       if (SPLIT) bl[j] = *(const bf16x8*)&Bl[j * 16 + i16][8 * g];
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < RTW; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (SPLIT) {
@@ -436,14 +458,14 @@ __global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __res
   }
   const float gs = (float)(gamma * 1.4426950408889634);
   const bool fused = s0.partial != nullptr;
-  double ga[2][4];
-  float gy[2][4];
+  double ga[RTW][4];
+  float gy[RTW][4];
   if (fused) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < RTW; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + w * 32 + i * 16 + (lane >> 4) * 4 + r;
+        const int64_t row = r0 + w * 16 * RTW + i * 16 + (lane >> 4) * 4 + r;
         gy[i][r] = row < n ? s0.y[row] : 0.0f;
         ga[i][r] = row < n ? margin_gap(gy[i][r], s0.o[row]) : 0.0;
       }
@@ -457,10 +479,10 @@ __global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __res
     if (zi < 0) continue;
     const float zn = xnorm[zi];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < RTW; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + w * 32 + i * 16 + (lane >> 4) * 4 + r;
+        const int64_t row = r0 + w * 16 * RTW + i * 16 + (lane >> 4) * 4 + r;
         if (row < n) {
           const float d2 = xnorm[row] + zn - 2.0f * acc[i][j][r];
           const float kv = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
@@ -471,9 +493,14 @@ __global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __res
   }
   if (fused) {
     __shared__ double red[4][64][2];
-    sa.finish(s0.partial, blockIdx.x, red);
+    // one record per 128 rows: RTW = 2 -> all four waves, RTW = 4 -> two pairs of waves
+    sa.finish(s0.partial, tile.r * (BM / kKblockRows), ceil_div_dev(n, kKblockRows), 4 * 128 / BM, red);
   }
 }
+
+// Tiles of 256 rows (each wave 64 x 64: more MFMAs per LDS fragment) once the matrix has enough of them to
+// fill the chip; 128 rows below that.
+constexpr int64_t kWideRows = 65536;
 
 void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int64_t ldb, int64_t n,
                         const float* xnorm, const int32_t* cidx, int ncols, float* out, int64_t ldo, double gamma,
@@ -482,13 +509,23 @@ void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int6
   if (ldb % SB_BK != 0 || ((uintptr_t)hi & 15u) || ((uintptr_t)lo & 15u))
     throw Failure(1, "kernel block: split copies must be 16-byte aligned with ldb a multiple of 32");
   if (s0.partial && ncols > KB_BN) throw Failure(1, "kernel block: the fused scoring pass takes one column tile");
-  dim3 grid((unsigned)ceil_div(n, KB_BM), (unsigned)ceil_div(ncols, KB_BN));
-  if (lo)
-    hipLaunchKernelGGL(k_kblock_bf16<true>, grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out, ldo,
-                       gamma, s0);
-  else
-    hipLaunchKernelGGL(k_kblock_bf16<false>, grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out, ldo,
-                       gamma, s0);
+  const bool wide = n >= kWideRows;
+  const dim3 grid(xcd_grid(ceil_div(n, wide ? 256 : 128), ceil_div(ncols, KB_BN)));
+  if (wide) {
+    if (lo)
+      hipLaunchKernelGGL((k_kblock_bf16<true, 4>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
+                         ldo, gamma, s0);
+    else
+      hipLaunchKernelGGL((k_kblock_bf16<false, 4>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
+                         ldo, gamma, s0);
+  } else {
+    if (lo)
+      hipLaunchKernelGGL((k_kblock_bf16<true, 2>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
+                         ldo, gamma, s0);
+    else
+      hipLaunchKernelGGL((k_kblock_bf16<false, 2>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
+                         ldo, gamma, s0);
+  }
   SPSVM_LAUNCHED();
 }
 

@@ -40,7 +40,8 @@ def test_rbf_block_f32_within_rounding_bound(n, d, nc):
     assert np.all(np.abs(K - want) <= bound)
 
 
-@pytest.mark.parametrize("n,d,nc", [(1037, 70, 59), (300, 123, 64), (129, 5, 3), (4100, 54, 70)])
+@pytest.mark.parametrize("n,d,nc", [(1037, 70, 59), (300, 123, 64), (129, 5, 3), (4100, 54, 70), (70001, 54, 70),
+                                    (66000, 300, 64)])
 def test_rbf_block_mixed_within_split_bound(n, d, nc):
     """Split-BF16 products: x = hi + lo with |x - hi - lo| <= 2^-17 |x| and the dropped lo.lo' <= 2^-16 |x||z|
     per term, so |d2 error| <= about 2^-13 (|x|^2 + |z|^2)."""

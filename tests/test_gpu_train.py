@@ -141,6 +141,18 @@ def test_onehot_mixed_precision_reaches_oracle_objective(prec):
     assert _decision_err(dg, do) <= 1e-4
 
 
+def test_mixed_wide_tiles_reach_oracle_objective():
+    """Mixed precision at n >= 65536 (the split-BF16 block then uses 256-row tiles, and the fused first scoring
+    pass writes two 128-row records per tile)."""
+    p = datagen.make_config("onehot-500k", n=70001, J_max=150)
+    Xg, yg = _dev(p.X, p.y)
+    model = lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=2, precision="mixed")
+    J, beta, F = model.get()
+    b_or, F_or, _ = osp.solve_fixed_J(p.X, p.y, p.C, p.gamma, J)
+    Fo = osp.objective_at(p.X, p.y, p.C, p.gamma, J, beta)
+    assert (Fo - F_or) / F_or <= 1e-6
+
+
 def test_mixed_on_bf16_exact_data_equals_fp32_bitwise():
     """0/1 features are exact in BF16, so the split's lo parts vanish and the mixed kernel block issues only
     hi.hi'; its integer dot products equal the FP32 path's, so the whole training run must agree bit for bit."""
