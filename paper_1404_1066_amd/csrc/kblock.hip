@@ -279,7 +279,7 @@ __global__ __launch_bounds__(256) void k_kblock_store(const TX* __restrict__ X, 
   t.run(X, ldx, n, r0, X, ldx, cidx, c0, ncols, d, As, Bs);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const TK gs = gamma_scale<TK>(gamma);
-  const bool fused = s0.partial != nullptr;  // (one column tile: checked at launch)
+  const bool fused = s0.partial != nullptr && tile.c == 0;  // the first 64 columns only
   double ga[2][4];  // a_i of this lane's rows (fused pass)
   float gy[2][4];
   if (fused) {
@@ -325,7 +325,6 @@ void launch_kblock(const TX* X, int64_t ldx, int64_t n, int64_t d, const TK* xno
   if (n <= 0 || ncols <= 0) return;
   if (ldx % Vec16<TX>::n != 0 || ((uintptr_t)X & 15u))
     throw Failure(1, "kernel block: rows must start on 16-byte boundaries");
-  if (s0.partial && ncols > KB_BN) throw Failure(1, "kernel block: the fused scoring pass takes one column tile");
   const dim3 grid(xcd_grid(ceil_div(n, KB_BM), ceil_div(ncols, KB_BN)));
   hipLaunchKernelGGL((k_kblock_store<TX, TK>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out, ldo,
                      gamma, s0);
@@ -457,7 +456,7 @@ __global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __res
       }
   }
   const float gs = (float)(gamma * 1.4426950408889634);
-  const bool fused = s0.partial != nullptr;
+  const bool fused = s0.partial != nullptr && tile.c == 0;  // the first 64 columns only
   double ga[RTW][4];
   float gy[RTW][4];
   if (fused) {
@@ -508,7 +507,6 @@ void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int6
   if (n <= 0 || ncols <= 0) return;
   if (ldb % SB_BK != 0 || ((uintptr_t)hi & 15u) || ((uintptr_t)lo & 15u))
     throw Failure(1, "kernel block: split copies must be 16-byte aligned with ldb a multiple of 32");
-  if (s0.partial && ncols > KB_BN) throw Failure(1, "kernel block: the fused scoring pass takes one column tile");
   const bool wide = n >= kWideRows;
   const dim3 grid(xcd_grid(ceil_div(n, wide ? 256 : 128), ceil_div(ncols, KB_BN)));
   if (wide) {

@@ -57,9 +57,10 @@ template <typename TX, typename TK>
 void launch_row_norms(const TX* X, int64_t n, int64_t d, int64_t ldx, TK* out, hipStream_t st);
 template <typename TX>
 void launch_row_hash(const TX* X, int64_t n, int64_t d, uint64_t* out, hipStream_t st);
-// First scoring pass (at s = 0) fused into the candidate block: for every 128-row tile t and column c the
-// epilogue writes partial[(t * 64 + c) * 4 + {0, 1, 2, 3}] = {P, Q, 0, 0}, the sums of a_i b_i and b_i^2 over
-// the rows of the tile with a_i = 1 - y_i o_i > 0 (b_i = y_i k_ic), in the layout of a scoring pass.
+// First scoring pass (at s = 0) fused into the candidate block: for every 128-row tile t and column c of the
+// first 64 columns the epilogue writes partial[(t * 64 + c) * 4 + {0, 1, 2, 3}] = {P, Q, 0, 0}, the sums of
+// a_i b_i and b_i^2 over the rows of the tile with a_i = 1 - y_i o_i > 0 (b_i = y_i k_ic), in the layout of a
+// scoring pass.
 struct Score0 {
   const float* y = nullptr;
   const double* o = nullptr;
@@ -109,13 +110,14 @@ void launch_score_init(const int32_t* cand, const double* o, const uint64_t* has
 // One scoring pass over the n rows for all active slots (partial sums per workgroup), then one workgroup per
 // slot reduces them and advances the slot. Both kernels return at once when every slot is settled.
 template <typename TK>
-void launch_score_pass(const TK* Kc, const float* y, const double* o, int64_t n, const CandState* st,
+void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, const CandState* st,
                        double* partial, int nblk, hipStream_t s);
 void launch_score_update(CandState* st, const double* partial, int nblk, double lam, hipStream_t s);
 template <typename TK>
+// Kc: the step's candidate columns (leading dimension ldc); fused0: its first scoring pass came with the block.
 void launch_select_append(const CandState* st, const uint64_t* hash, uint64_t* stage_hash, int q, const TK* Kc,
-                          int64_t n, double* o, TK* KXJ, int64_t ldk, int64_t* J, double* beta, int32_t* m_dev,
-                          Selection* sel, int32_t* incomplete, hipStream_t s);
+                          int64_t ldc, int64_t n, double* o, TK* KXJ, int64_t ldk, int64_t* J, double* beta,
+                          int32_t* m_dev, Selection* sel, int32_t* incomplete, int fused0, hipStream_t s);
 int score_blocks(int64_t n);
 
 // ----------------------------------------------------------------------------------------- newton.hip

@@ -96,7 +96,7 @@ __device__ __forceinline__ int advance_slot(CandState& s, double P, double Q, do
 // ... of its workgroup's range, two rows per iteration with separate accumulators; the four waves' sums are
 // added in wave order and written as this workgroup's partial record {P, Q, V, flips} per slot.
 template <typename TK>
-__global__ __launch_bounds__(256) void k_score_pass(const TK* __restrict__ Kc, const float* __restrict__ y,
+__global__ __launch_bounds__(256) void k_score_pass(const TK* __restrict__ Kc, int64_t ldc, const float* __restrict__ y,
                                                     const double* __restrict__ o, int64_t n, int64_t rows_per_blk,
                                                     const CandState* __restrict__ st, double* __restrict__ partial) {
   __shared__ double sh[4][4][kCandSlots];
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void k_score_pass(const TK* __restrict__ Kc, c
     for (; i + 4 < hi; i += 8) {
       const double y0 = (double)y[i], y1 = (double)y[i + 4];
       const double a0 = margin_gap(y[i], o[i]), a1 = margin_gap(y[i + 4], o[i + 4]);
-      const double b0 = y0 * (double)Kc[i * kCandSlots + c], b1 = y1 * (double)Kc[(i + 4) * kCandSlots + c];
+      const double b0 = y0 * (double)Kc[i * ldc + c], b1 = y1 * (double)Kc[(i + 4) * ldc + c];
       const double e0 = a0 - s * b0, e1 = a1 - s * b1;
       if (e0 > 0.0) {
         P += a0 * b0;
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_score_pass(const TK* __restrict__ Kc, c
     for (; i < hi; i += 4) {
       const double yi = (double)y[i];
       const double a = margin_gap(y[i], o[i]);
-      const double b = yi * (double)Kc[i * kCandSlots + c];
+      const double b = yi * (double)Kc[i * ldc + c];
       const double e = a - s * b;
       if (e > 0.0) {
         P += a * b;
@@ -223,10 +223,10 @@ int score_blocks(int64_t n) {
 }
 
 template <typename TK>
-void launch_score_pass(const TK* Kc, const float* y, const double* o, int64_t n, const CandState* st,
+void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, const CandState* st,
                        double* partial, int nblk, hipStream_t s) {
   const int64_t rows = round_up(ceil_div(n, nblk), 4);
-  hipLaunchKernelGGL((k_score_pass<TK>), dim3(nblk), dim3(256), 0, s, Kc, y, o, n, rows, st, partial);
+  hipLaunchKernelGGL((k_score_pass<TK>), dim3(nblk), dim3(256), 0, s, Kc, ldc, y, o, n, rows, st, partial);
   SPSVM_LAUNCHED();
 }
 
@@ -239,15 +239,16 @@ void launch_score_update(CandState* st, const double* partial, int nblk, double 
 // then append the winner to J and beta.
 __global__ void k_select(const CandState* __restrict__ st, const uint64_t* __restrict__ hash,
                          uint64_t* __restrict__ stage_hash, int q, int64_t* __restrict__ J, double* __restrict__ beta,
-                         int32_t* __restrict__ m_dev, Selection* __restrict__ sel, int32_t* __restrict__ incomplete) {
+                         int32_t* __restrict__ m_dev, Selection* __restrict__ sel, int32_t* __restrict__ incomplete,
+                         int fused0) {
   const int c = threadIdx.x;
   const CandState s = st[c];
   int mp = s.passes;
   for (int off = 32; off > 0; off >>= 1) mp = max(mp, __shfl_xor(mp, off, kWave));
   if (c == 0) {
     atomicMax(&incomplete[1], mp);  // largest number of passes any slot needed in this stage
-    atomicAdd(&incomplete[2], mp > 0 ? mp - 1 : 0);  // launched passes of this step that did work (the first
-                                                     // pass is fused into the candidate block)
+    atomicAdd(&incomplete[2], mp > fused0 ? mp - fused0 : 0);  // launched passes of this step that did work
+                                                                // (fused0: the first pass came with the block)
   }
   const int pending = __any(s.status == 0);  // a slot still being scored: this step must be redone
   const bool ok = !pending && s.status == 1 && s.idx >= 0 && !(s.score != s.score);
@@ -286,12 +287,13 @@ __global__ void k_select(const CandState* __restrict__ st, const uint64_t* __res
 
 // o += s * k_winner; K_XJ[:, pos] = k_winner.
 template <typename TK>
-__global__ __launch_bounds__(256) void k_append(const Selection* __restrict__ sel, const TK* __restrict__ Kc, int64_t n,
+__global__ __launch_bounds__(256) void k_append(const Selection* __restrict__ sel, const TK* __restrict__ Kc, int64_t ldc,
+                                                int64_t n,
                                                 double* __restrict__ o, TK* __restrict__ KXJ, int64_t ldk) {
   const Selection s = *sel;
   if (!s.valid) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const TK k = Kc[i * kCandSlots + s.slot];
+    const TK k = Kc[i * ldc + s.slot];
     o[i] += s.s * (double)k;
     KXJ[i * ldk + s.pos] = k;
   }
@@ -299,25 +301,25 @@ __global__ __launch_bounds__(256) void k_append(const Selection* __restrict__ se
 
 template <typename TK>
 void launch_select_append(const CandState* st, const uint64_t* hash, uint64_t* stage_hash, int q, const TK* Kc,
-                          int64_t n, double* o, TK* KXJ, int64_t ldk, int64_t* J, double* beta, int32_t* m_dev,
-                          Selection* sel, int32_t* incomplete, hipStream_t s) {
+                          int64_t ldc, int64_t n, double* o, TK* KXJ, int64_t ldk, int64_t* J, double* beta,
+                          int32_t* m_dev, Selection* sel, int32_t* incomplete, int fused0, hipStream_t s) {
   hipLaunchKernelGGL(k_select, dim3(1), dim3(kCandSlots), 0, s, st, hash, stage_hash, q, J, beta, m_dev, sel,
-                     incomplete);
+                     incomplete, fused0);
   SPSVM_LAUNCHED();
   const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), 2048);
-  hipLaunchKernelGGL((k_append<TK>), dim3((unsigned)blocks), dim3(256), 0, s, sel, Kc, n, o, KXJ, ldk);
+  hipLaunchKernelGGL((k_append<TK>), dim3((unsigned)blocks), dim3(256), 0, s, sel, Kc, ldc, n, o, KXJ, ldk);
   SPSVM_LAUNCHED();
 }
 
-template void launch_score_pass<float>(const float*, const float*, const double*, int64_t, const CandState*, double*,
-                                       int, hipStream_t);
-template void launch_score_pass<double>(const double*, const float*, const double*, int64_t, const CandState*,
-                                        double*, int, hipStream_t);
+template void launch_score_pass<float>(const float*, int64_t, const float*, const double*, int64_t, const CandState*,
+                                       double*, int, hipStream_t);
+template void launch_score_pass<double>(const double*, int64_t, const float*, const double*, int64_t,
+                                        const CandState*, double*, int, hipStream_t);
 template void launch_select_append<float>(const CandState*, const uint64_t*, uint64_t*, int, const float*, int64_t,
-                                          double*, float*, int64_t, int64_t*, double*, int32_t*, Selection*, int32_t*,
-                                          hipStream_t);
+                                          int64_t, double*, float*, int64_t, int64_t*, double*, int32_t*, Selection*,
+                                          int32_t*, int, hipStream_t);
 template void launch_select_append<double>(const CandState*, const uint64_t*, uint64_t*, int, const double*, int64_t,
-                                           double*, double*, int64_t, int64_t*, double*, int32_t*, Selection*,
-                                           int32_t*, hipStream_t);
+                                           int64_t, double*, double*, int64_t, int64_t*, double*, int32_t*,
+                                           Selection*, int32_t*, int, hipStream_t);
 
 }  // namespace spsvm

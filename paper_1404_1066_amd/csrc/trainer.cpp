@@ -47,6 +47,13 @@ void draw_step(uint64_t seed, int64_t t, int64_t n, int kappa, const std::vector
   }
 }
 
+// Steps whose candidate columns come from one kernel-block launch. For wide rows the block is bound by reading
+// X (d values per row for 64 columns); the column tiles of several steps of a stage (all drawn at its start)
+// then share each row slab of X through L2. The first scoring pass is launched for all but the first step.
+int cand_group(int64_t d, int64_t chunk_cap) {
+  return (int)std::min<int64_t>(d >= 256 ? 8 : 1, std::max<int64_t>(chunk_cap, 1));
+}
+
 int64_t stage_size(int64_t J, int64_t J_max, double growth, int64_t cap) {
   const int64_t g = (int64_t)std::floor(growth * (double)J);
   return std::min<int64_t>(J_max - J, std::max<int64_t>(1, std::min<int64_t>(cap, g)));
@@ -80,7 +87,7 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.xnorm = take(n * tk);
   p.hash = take(n * 8);
   p.KXJ = take((size_t)n * p.ldk * tk);
-  p.Kc = take(with_selection ? (size_t)n * kCandSlots * tk : 0);
+  p.Kc = take(with_selection ? (size_t)n * kCandSlots * cand_group(d, opt.chunk_cap) * tk : 0);
   p.J = take(J_max * 8);
   p.J32 = take(J_max * 4);
   p.cand_state = take(kCandSlots * sizeof(CandState));
@@ -828,26 +835,40 @@ struct Impl {
           stats.stage_redos += 1;
         }
         SPSVM_HIP(hipMemsetAsync(incomplete, 0, 12, st));
-        for (int q = 0; q < cs; ++q) {
-          const int32_t* cq = cand_table + (size_t)q * kCandSlots;
+        const int G = cand_group(d, opt.chunk_cap);
+        for (int q0 = 0; q0 < cs; q0 += G) {
+          const int gsz = std::min(G, cs - q0);  // steps sharing this kernel-block launch
+          const int64_t ldc = (int64_t)kCandSlots * gsz;
           int ncand = 0;
-          for (int c = 0; c < kCandSlots; ++c) ncand += table[(size_t)q * kCandSlots + c] >= 0;
-          // the candidate block also yields the first scoring pass (at s = 0)
+          for (int c = 0; c < kCandSlots * gsz; ++c) ncand += table[(size_t)q0 * kCandSlots + c] >= 0;
+          // the candidate block also yields the first scoring pass (at s = 0) of its first step
           Score0 s0;
           s0.y = y;
           s0.o = o;
           s0.partial = score_part;
           prof.timed(kProfKblock, 2.0 * n * ncand * d,
-                     [&] { kblock(cq, kCandSlots, Kc, kCandSlots, s0); });
-          launch_score_init(cq, o, hash, stage_hash, q, cst, sc, st);
-          launch_score_update(cst, score_part, (int)ceil_div(n, kKblockRows), lam, st);
-          for (int r = 1; r < rounds; ++r) {
-            prof.timed(kProfScore, (double)n * (opt.kappa * sizeof(TK) + 12.0),
-                       [&] { launch_score_pass<TK>(Kc, y, o, n, cst, score_part, nblk, st); });
-            launch_score_update(cst, score_part, nblk, lam, st);
+                     [&] { kblock(cand_table + (size_t)q0 * kCandSlots, (int)ldc, Kc, ldc, s0); });
+          for (int j = 0; j < gsz; ++j) {
+            const int q = q0 + j;
+            const int32_t* cq = cand_table + (size_t)q * kCandSlots;
+            const TK* Kq = Kc + (size_t)j * kCandSlots;
+            launch_score_init(cq, o, hash, stage_hash, q, cst, sc, st);
+            if (j == 0) {
+              launch_score_update(cst, score_part, (int)ceil_div(n, kKblockRows), lam, st);
+            } else {
+              prof.timed(kProfScore, (double)n * (opt.kappa * sizeof(TK) + 12.0),
+                         [&] { launch_score_pass<TK>(Kq, ldc, y, o, n, cst, score_part, nblk, st); });
+              launch_score_update(cst, score_part, nblk, lam, st);
+            }
+            for (int r = 1; r < rounds; ++r) {
+              prof.timed(kProfScore, (double)n * (opt.kappa * sizeof(TK) + 12.0),
+                         [&] { launch_score_pass<TK>(Kq, ldc, y, o, n, cst, score_part, nblk, st); });
+              launch_score_update(cst, score_part, nblk, lam, st);
+            }
+            stats.score_passes += rounds - (j == 0 ? 1 : 0);
+            launch_select_append<TK>(cst, hash, stage_hash, q, Kq, ldc, n, o, KXJ, p.ldk, J, beta, m_dev, sel,
+                                     incomplete, j == 0 ? 1 : 0, st);
           }
-          stats.score_passes += rounds - 1;
-          launch_select_append<TK>(cst, hash, stage_hash, q, Kc, n, o, KXJ, p.ldk, J, beta, m_dev, sel, incomplete, st);
         }
         int32_t flags2[3];
         SPSVM_HIP(hipMemcpyAsync(pin.p, incomplete, 12, hipMemcpyDeviceToHost, st));
