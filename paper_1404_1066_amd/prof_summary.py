@@ -24,10 +24,10 @@ def kernels(db, cmd, runs, title):
     tot = sum(r[2] for r in rows)
     out = [f"# {title}", "", "Command (from the repository root, one MI355X):", "", f"    {cmd}", "",
            f"rocprofv3 kernel-trace statistics over {runs} runs in the process. Total kernel time "
-           f"{tot / 1e6:.1f} ms ({tot / 1e6 / runs:.1f} ms per run).", "",
+           f"{tot / 1e3:.1f} ms ({tot / 1e3 / runs:.1f} ms per run).", "",
            "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
-    for name, calls, total, avg, pct in rows[:30]:
-        out.append(f"| `{name.split('(')[0].replace('void ', '')}` | {calls} | {total / 1e6:.2f} | {avg / 1e3:.2f} "
+    for name, calls, total, avg, pct in rows[:30]:  # the summary table holds microseconds
+        out.append(f"| `{name.split('(')[0].replace('void ', '')}` | {calls} | {total / 1e3:.2f} | {avg:.2f} "
                    f"| {pct:.1f} |")
     return "\n".join(out)
 
