@@ -59,7 +59,7 @@ def traffic(fdb, wdb, cmd, title, kernel, source):
     rec = None
     for _, k, c, a, b in sorted(rows, reverse=True)[:20]:
         out.append(f"| `{k}` | {c} | {a:.1f} | {b:.1f} | {(a * sf + b * sw) * 1024:.4g} |")
-        if k.endswith(kernel) or k.split("<")[0].endswith(kernel):
+        if rec is None and (k.endswith(kernel) or k.split("<")[0].endswith(kernel)):  # the largest variant
             with open(source, "rb") as fh:
                 sha = hashlib.sha256(fh.read()).hexdigest()
             rec = {"kernel": k, "bytes_per_dispatch": (a * sf + b * sw) * 1024, "fetch_kib": a, "write_kib": b,
