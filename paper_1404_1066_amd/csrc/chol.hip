@@ -387,11 +387,107 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const SolveBatch bt, int64_
   for (int k = tid; k < m; k += 1024) x[k] = -x[k];
 }
 
+// Large m: one launch per 64-row block step, the remaining blocks updated in parallel (right-looking).
+// Forward, step b: every workgroup forms z_b = Linv_b r_b (r: right-hand side, held in x); the one for
+// block b stores z_b, the others update their own block r_rb -= L[rb, b] z_b. Backward, step b: every
+// workgroup forms x_b = Linv_b^T z_b; the one for block b stores -x_b, the others update z_rb -= L[b, rb]^T x_b.
+// Right-hand side blocks are read only in their own step and written only by their own workgroup.
+__global__ __launch_bounds__(64) void k_solve_copy(const SolveBatch bt, int m) {
+  const double* g = bt.g[blockIdx.z];
+  double* x = bt.x[blockIdx.z];
+  for (int k = blockIdx.x * 64 + threadIdx.x; k < m; k += gridDim.x * 64) x[k] = g[k];
+}
+
+__global__ __launch_bounds__(256) void k_trsv_fwd(const SolveBatch bt, int64_t ldh, int m, int b) {
+  const int rb = b + blockIdx.x;
+  const int b0 = b * NB, r0 = rb * NB;
+  if (r0 >= m) return;
+  const double* __restrict__ L = bt.L[blockIdx.z];
+  const double* __restrict__ Lo = bt.Linv[blockIdx.z] + (int64_t)b * NB * NB;
+  double* __restrict__ r = bt.x[blockIdx.z];
+  double* __restrict__ z = bt.work[blockIdx.z];
+  __shared__ double zb[NB];
+  __shared__ double rhs[NB];
+  const int t = threadIdx.x;
+  if (t < NB) rhs[t] = b0 + t < m ? r[b0 + t] : 0.0;
+  __syncthreads();
+  if (t < NB) {
+    double a = 0.0;
+    const double* row = Lo + (int64_t)t * NB;
+    for (int p = 0; p <= t; ++p) a += row[p] * rhs[p];
+    zb[t] = a;
+  }
+  __syncthreads();
+  if (rb == b) {
+    if (t < NB && b0 + t < m) z[b0 + t] = zb[t];
+    return;
+  }
+  // rows r0 + i, four threads per row, sixteen columns each
+  const int i = t >> 2, q = t & 3;
+  double a = 0.0;
+  if (r0 + i < m) {
+    const double* row = L + (int64_t)(r0 + i) * ldh + b0;
+#pragma unroll
+    for (int p = q * 16; p < q * 16 + 16; ++p) a += (b0 + p < m ? row[p] : 0.0) * zb[p];
+  }
+  a += __shfl_xor(a, 1, kWave);
+  a += __shfl_xor(a, 2, kWave);
+  if (q == 0 && r0 + i < m) r[r0 + i] -= a;
+}
+
+__global__ __launch_bounds__(256) void k_trsv_bwd(const SolveBatch bt, int64_t ldh, int m, int b) {
+  const int rb = blockIdx.x;  // 0 .. b
+  const int b0 = b * NB, r0 = rb * NB;
+  const double* __restrict__ L = bt.L[blockIdx.z];
+  const double* __restrict__ Lo = bt.Linv[blockIdx.z] + (int64_t)b * NB * NB;
+  double* __restrict__ z = bt.work[blockIdx.z];
+  double* __restrict__ x = bt.x[blockIdx.z];
+  __shared__ double xb[NB];
+  __shared__ double rhs[NB];
+  __shared__ double part[4][NB];
+  const int t = threadIdx.x;
+  if (t < NB) rhs[t] = b0 + t < m ? z[b0 + t] : 0.0;
+  __syncthreads();
+  if (t < NB) {
+    double a = 0.0;
+    for (int p = t; p < NB; ++p) a += Lo[(int64_t)p * NB + t] * rhs[p];
+    xb[t] = a;
+  }
+  __syncthreads();
+  if (rb == b) {
+    if (t < NB && b0 + t < m) x[b0 + t] = -xb[t];
+    return;
+  }
+  // columns r0 + j of L's rows b0 + i: thread (q, j) sums rows i = q, q + 4, ...
+  const int j = t & 63, q = t >> 6;
+  double a = 0.0;
+  for (int i = q; i < NB; i += 4)
+    if (b0 + i < m) a += L[(int64_t)(b0 + i) * ldh + r0 + j] * xb[i];
+  part[q][j] = a;
+  __syncthreads();
+  if (t < NB) z[r0 + t] -= part[0][t] + part[1][t] + part[2][t] + part[3][t];
+}
+
 void launch_chol_solve_batch(const SolveBatch& b, int64_t ldh, int m, hipStream_t s) {
   if (b.count <= 0 || m <= 0) return;
   if (b.count > kMaxBatch) throw Failure(1, "solve batch: too many slots");
-  hipLaunchKernelGGL(k_chol_solve, dim3(1, 1, (unsigned)b.count), dim3(1024), 0, s, b, ldh, m);
+  const unsigned nz = (unsigned)b.count;
+  if (m <= 1024) {  // one workgroup per problem: fewer launches than block steps
+    hipLaunchKernelGGL(k_chol_solve, dim3(1, 1, nz), dim3(1024), 0, s, b, ldh, m);
+    SPSVM_LAUNCHED();
+    return;
+  }
+  const int nb = (int)ceil_div(m, NB);
+  hipLaunchKernelGGL(k_solve_copy, dim3((unsigned)std::min<int64_t>(ceil_div(m, 64), 64), 1, nz), dim3(64), 0, s, b, m);
   SPSVM_LAUNCHED();
+  for (int k = 0; k < nb; ++k) {
+    hipLaunchKernelGGL(k_trsv_fwd, dim3((unsigned)(nb - k), 1, nz), dim3(256), 0, s, b, ldh, m, k);
+    SPSVM_LAUNCHED();
+  }
+  for (int k = nb - 1; k >= 0; --k) {
+    hipLaunchKernelGGL(k_trsv_bwd, dim3((unsigned)(k + 1), 1, nz), dim3(256), 0, s, b, ldh, m, k);
+    SPSVM_LAUNCHED();
+  }
 }
 
 void launch_chol_solve(const double* L, int64_t ldh, int m, const double* Linv, const double* g, double* x,

@@ -71,7 +71,7 @@ def test_rbf_block_negative_index_leaves_column():
     assert np.all(np.isnan(o[:, 1])) and np.all(np.isfinite(o[:, [0, 2]]))
 
 
-@pytest.mark.parametrize("m", [1, 5, 63, 64, 65, 130, 500, 1000])
+@pytest.mark.parametrize("m", [1, 5, 63, 64, 65, 130, 500, 1000, 1025, 1100, 2000])
 def test_newton_solve_matches_numpy(m):
     r = np.random.default_rng(m)
     A = r.standard_normal((m, m + 7))
