@@ -298,6 +298,61 @@ __global__ __launch_bounds__(256) void k_chol_update(const CholBatch bt, int64_t
       }
 }
 
+// The same update with 128 x 128 tiles for large trailing matrices: each wave owns a 64 x 64 block (4 x 4
+// MFMA tiles), half the loads per MFMA of the 64 x 64 tiles. The panel's 64 columns are taken in quarters of
+// 16 (lane group g: columns 4 g .. 4 g + 3 of the quarter, one 32-byte load per row).
+__global__ __launch_bounds__(256) void k_chol_update128(const CholBatch bt, int64_t ldh, int m, int k0) {
+  double* __restrict__ H = bt.H[blockIdx.z];
+  int tr, tc;
+  tri_tile(blockIdx.x, tr, tc);
+  const int base = k0 + NB;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, i16 = lane & 15;
+  const int wr = w >> 1, wc = w & 1;
+  if (tr == tc && wr < wc) return;  // wave-uniform
+  const int ra = base + tr * 128 + wr * 64, rb = base + tc * 128 + wc * 64;
+  if (ra >= m || rb >= m) return;
+  doublex4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0, 0, 0, 0};
+  for (int qt = 0; qt < 4; ++qt) {  // quarters of the panel: lane group g takes columns 16 qt + 4 g .. + 3
+    double av[4][4], bv[4][4];
+    const int kc = k0 + 16 * qt + 4 * g;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = ra + i * 16 + i16;
+      const doublex4 v = row < m ? *(const doublex4*)(H + (int64_t)row * ldh + kc) : doublex4{0, 0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) av[i][e] = v[e];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = rb + j * 16 + i16;
+      const doublex4 v = row < m ? *(const doublex4*)(H + (int64_t)row * ldh + kc) : doublex4{0, 0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bv[j][e] = v[e];
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][st], bv[j][st], acc[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = ra + i * 16 + g + 4 * r;
+        const int gc = rb + j * 16 + i16;
+        if (gr < m && gc < m && gc <= gr) H[(int64_t)gr * ldh + gc] -= acc[i][j][r];
+      }
+}
+
 // All slots share m and ldh; each panel step is one launch per kernel for the whole batch.
 void launch_cholesky_batch(const CholBatch& b, int64_t ldh, int m, hipStream_t s) {
   if (b.count <= 0 || m <= 0) return;
@@ -311,7 +366,12 @@ void launch_cholesky_batch(const CholBatch& b, int64_t ldh, int m, hipStream_t s
     const int nblk = (int)ceil_div(rest, NB);
     hipLaunchKernelGGL(k_trsm_panel, dim3(nblk, 1, nz), dim3(256), 0, s, b, ldh, m, k0);
     SPSVM_LAUNCHED();
-    hipLaunchKernelGGL(k_chol_update, dim3(nblk * (nblk + 1) / 2, 1, nz), dim3(256), 0, s, b, ldh, m, k0);
+    if (rest >= 512 && nz >= 4) {  // many problems: the larger tiles; one problem: more, smaller workgroups
+      const int nb2 = (int)ceil_div(rest, 128);
+      hipLaunchKernelGGL(k_chol_update128, dim3(nb2 * (nb2 + 1) / 2, 1, nz), dim3(256), 0, s, b, ldh, m, k0);
+    } else {
+      hipLaunchKernelGGL(k_chol_update, dim3(nblk * (nblk + 1) / 2, 1, nz), dim3(256), 0, s, b, ldh, m, k0);
+    }
     SPSVM_LAUNCHED();
   }
 }
