@@ -190,6 +190,21 @@ def test_batch_equals_fixed_basis_and_oracle():
         assert np.array_equal(sub[k].get()[1], models[q].get()[1]) and sub[k].get()[2] == models[q].get()[2]
 
 
+def test_batch_large_basis_matches_oracle():
+    """Six problems on a shared basis of 700 rows: the batched Cholesky then uses its 128 x 128 trailing-update
+    tiles and the batched triangular solves; each model reaches the oracle's optimum."""
+    p = datagen.make_config("mnist-60k", n=3000, J_max=700)
+    sel = [1, 5, 9, 13, 17, 21]  # one gamma: a lockstep group of six
+    Xg = torch.tensor(p.X, device="cuda")
+    Yg = torch.tensor(p.Y[sel], dtype=torch.float32, device="cuda").contiguous()
+    models = lib.train_batch(Xg, Yg, p.C[sel], p.gamma[sel], p.J)
+    for q, s_ in enumerate(sel[:3]):
+        _, bb, _ = models[q].get()
+        b_or, F_or, _ = osp.solve_fixed_J(p.X, p.Y[s_], p.C[s_], p.gamma[s_], p.J)
+        Fo = osp.objective_at(p.X, p.Y[s_], p.C[s_], p.gamma[s_], p.J, bb)
+        assert (Fo - F_or) / F_or <= 1e-6
+
+
 def test_batch_more_problems_than_slots():
     """70 problems (more than the 64 lockstep slots): the second round of slots solves the rest; every model
     reaches the oracle's optimum at the shared basis and matches the same problem solved in a small batch."""
