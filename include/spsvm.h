@@ -67,9 +67,11 @@ typedef struct {
   int32_t newton_max_iter; /* Newton iterations per re-optimisation, >= 1; default 50 */
   spsvm_precision precision; /* default SPSVM_F32 */
   int32_t log_level;       /* 0 silent; 1 one line per stage on stderr; 2 one line per Newton iteration */
-  int32_t profile;         /* bit mask of kernels to time with HIP events on the call's stream (results in
+  int32_t profile;         /* bits 0-3: kernels to time with HIP events on the call's stream (results in
                               spsvm_stats): 1 kernel block, 2 Newton-matrix SYRK, 4 candidate-score passes,
-                              8 Cholesky factorisations; 0 (default) records nothing */
+                              8 Cholesky factorisations; 0 (default) records nothing. Bits 8-15: k, time only
+                              every k-th launch of a kernel (0 or 1: every launch); each timed launch is
+                              bracketed by two events, which delay the stream a few microseconds */
   double refactor_frac;    /* the Newton matrix is re-formed and re-factorised when more than this fraction of
                               the violator set changed since the last factorisation (else the last factor is
                               reused; the exact line search keeps every step a descent step); default 0.002 */
@@ -95,18 +97,19 @@ typedef struct {
   double grad_norm;         /* ||grad f|| at the returned solution (f = F / C) */
   double seconds_select;    /* wall time in greedy selection */
   double seconds_newton;    /* wall time in Newton re-optimisation */
-  /* Per-kernel GPU time (HIP events) and algorithmic work, for the kernels selected by
-   * spsvm_options.profile; zero otherwise. */
-  int64_t kblock_launches;  /* kernel-block GEMMs (candidate blocks and basis blocks) */
+  /* Per-kernel GPU time (HIP events) and algorithmic work of the timed launches of the kernels selected by
+   * spsvm_options.profile (every k-th launch with a stride k); zero otherwise. */
+  int64_t kblock_launches;  /* timed kernel-block GEMMs (candidate blocks and basis blocks) */
   double kblock_seconds;
   double kblock_flops;      /* 2 n N d per launch, N = columns computed */
-  int64_t syrk_launches;    /* Newton-matrix SYRKs */
+  int64_t syrk_launches;    /* timed Newton-matrix SYRKs */
   double syrk_seconds;
   double syrk_flops;        /* n_sv m (m + 1) per launch (lower triangle, multiply-add = 2) */
-  int64_t score_launches;   /* candidate-score passes over the n rows */
+  int64_t score_launches;   /* timed candidate-score passes over the n rows */
   double score_seconds;
-  double score_bytes;       /* n (kappa sizeof(K) + 12) per active pass: candidate columns, o (FP64), y (FP32) */
-  int64_t chol_calls;       /* Cholesky factorisations (all panel kernels of one factorisation) */
+  double score_bytes;       /* n (kappa sizeof(K) + 12) per timed pass, scaled by the fraction of launched passes
+                               that were active: candidate columns, o (FP64), y (FP32) */
+  int64_t chol_calls;       /* timed Cholesky factorisations (all panel kernels of one factorisation) */
   double chol_seconds;
   double chol_flops;        /* m^3 / 3 per factorisation */
 } spsvm_stats;

@@ -173,6 +173,8 @@ static double secs(clk::time_point a, clk::time_point b) { return std::chrono::d
 struct Profiler {
   hipStream_t st = nullptr;
   int mask = 0;
+  int stride = 1;  // time every stride-th launch of a category
+  int64_t seen[4] = {0, 0, 0, 0};
   struct Pending {
     hipEvent_t a, b;
     int cat;
@@ -195,7 +197,7 @@ struct Profiler {
   }
   template <class F>
   void timed(int cat, double w, F&& launch) {
-    if (!(mask & (1 << cat))) {
+    if (!(mask & (1 << cat)) || (seen[cat]++ % stride) != 0) {
       launch();
       return;
     }
@@ -298,7 +300,8 @@ struct Impl {
         base((char*)ws), pin(kPinnedScalars + (size_t)o_.chunk_cap * kCandSlots * 4),
         pin_slots((size_t)plan.slots * (sizeof(NewtonScalars) + sizeof(LineState))) {
     prof.st = s;
-    prof.mask = o_.profile;
+    prof.mask = o_.profile & 0xF;
+    prof.stride = std::max(1, (o_.profile >> 8) & 0xFF);
     Xk = p.pad_x ? at<TX>(p.Xp) : X;
     xnorm = at<TK>(p.xnorm);
     KXJ = at<TK>(p.KXJ);
@@ -1041,9 +1044,9 @@ struct Impl {
     stats.syrk_flops = prof.work[kProfSyrk];
     stats.score_launches = prof.count[kProfScore];
     stats.score_seconds = prof.seconds[kProfScore];
-    stats.score_bytes = prof.count[kProfScore] > 0
-                            ? (double)stats.score_passes_active * (double)n * (opt.kappa * sizeof(TK) + 12.0)
-                            : 0.0;
+    stats.score_bytes = stats.score_passes > 0 ? prof.work[kProfScore] * (double)stats.score_passes_active /
+                                                     (double)stats.score_passes
+                                               : 0.0;
     stats.chol_calls = prof.count[kProfChol];
     stats.chol_seconds = prof.seconds[kProfChol];
     stats.chol_flops = prof.work[kProfChol];
