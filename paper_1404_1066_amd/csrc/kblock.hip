@@ -497,9 +497,157 @@ __global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __res
   }
 }
 
+// Split-BF16 block in 256 x 256 tiles for blocks with many columns (grouped candidate steps, a whole basis):
+// 8 waves in a 4 x 2 grid, each 64 rows x 128 columns (4 x 8 MFMA tiles). Every A fragment read from LDS feeds
+// 8 tiles and every B fragment 4, and each staged byte feeds twice the products of a 256 x 64 tile; two waves
+// share each SIMD. Two LDS stages of one 32-wide k chunk each (unpadded 64-byte rows): chunk t is multiplied
+// from one stage while chunk t + 1 goes from registers into the other, so each chunk costs one barrier.
+// 16-byte LDS accesses are served 8 lanes at a time over 32 four-byte banks; the 16-byte part p of row r is
+// kept at position p ^ ((r >> 1) & 3), which makes both the staging writes (two rows per 8 lanes) and the
+// fragment reads (8 rows at one part) conflict-free. The k chunks, the order of the three products inside a
+// chunk and the epilogue are those of k_kblock_bf16, so both give the same bits.
+template <bool SPLIT>
+__global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* __restrict__ hi,
+                                                          const unsigned short* __restrict__ lo, int64_t ldb,
+                                                          int64_t n, const float* __restrict__ xnorm,
+                                                          const int32_t* __restrict__ cidx, int ncols,
+                                                          float* __restrict__ out, int64_t ldo, double gamma,
+                                                          const Score0 s0) {
+  constexpr int BM = 256, BN = 256;
+  __shared__ __attribute__((aligned(16))) unsigned short Ah[2][BM][SB_BK], Bh[2][BN][SB_BK];
+  __shared__ __attribute__((aligned(16))) unsigned short Al[2][SPLIT ? BM : 1][SB_BK], Bl[2][SPLIT ? BN : 1][SB_BK];
+  auto phys = [](int row, int p) { return p ^ ((row >> 1) & 3); };
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w & 3, wc = w >> 2, g = lane >> 4,
+            i16 = lane & 15;
+  const TileOf tile = xcd_tile(ceil_div_dev(ncols, BN));
+  const int64_t r0 = tile.r * BM, c0 = tile.c * BN;
+  if (r0 >= n) return;  // padding of the row-tile count to a multiple of 8
+  const int part = tid & 3;  // which 8 of the chunk's 32 k this thread stages
+  int64_t aoff[2], boff[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int rr = (tid + 512 * q) >> 2;
+    const int64_t row = r0 + rr, col = c0 + rr;
+    aoff[q] = row < n ? row * ldb + 8 * part : -1;
+    const int64_t src = col < ncols ? (cidx ? (int64_t)cidx[col] : col) : -1;
+    boff[q] = src >= 0 ? src * ldb + 8 * part : -1;
+  }
+  floatx4 acc[4][8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = floatx4{0, 0, 0, 0};
+  u32x4 rah[2], ral[2], rbh[2], rbl[2];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      rah[q] = aoff[q] >= 0 ? *(const u32x4*)(hi + aoff[q] + k0) : u32x4{0, 0, 0, 0};
+      rbh[q] = boff[q] >= 0 ? *(const u32x4*)(hi + boff[q] + k0) : u32x4{0, 0, 0, 0};
+      if (SPLIT) {
+        ral[q] = aoff[q] >= 0 ? *(const u32x4*)(lo + aoff[q] + k0) : u32x4{0, 0, 0, 0};
+        rbl[q] = boff[q] >= 0 ? *(const u32x4*)(lo + boff[q] + k0) : u32x4{0, 0, 0, 0};
+      }
+    }
+  };
+  auto store = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int rr = (tid + 512 * q) >> 2, pp = 8 * phys(rr, part);
+      *(u32x4*)&Ah[b][rr][pp] = rah[q];
+      *(u32x4*)&Bh[b][rr][pp] = rbh[q];
+      if (SPLIT) {
+        *(u32x4*)&Al[b][rr][pp] = ral[q];
+        *(u32x4*)&Bl[b][rr][pp] = rbl[q];
+      }
+    }
+  };
+  auto compute = [&](int b) {
+    bf16x8 ah[4], al[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ra = wr * 64 + i * 16 + i16, pa = 8 * phys(ra, g);
+      ah[i] = *(const bf16x8*)&Ah[b][ra][pa];
+      if (SPLIT) al[i] = *(const bf16x8*)&Al[b][ra][pa];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int rb = wc * 128 + j * 16 + i16, pb = 8 * phys(rb, g);
+      const bf16x8 bh = *(const bf16x8*)&Bh[b][rb][pb];
+      bf16x8 bl;
+      if (SPLIT) bl = *(const bf16x8*)&Bl[b][rb][pb];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (SPLIT) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+        }
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+  const int nk = (int)(ldb / SB_BK);
+  fetch(0);
+  store(0);
+  if (nk > 1) fetch(SB_BK);
+  __syncthreads();
+  for (int t = 0; t < nk; ++t) {
+    compute(t & 1);
+    // the other stage was last read for chunk t - 1, which every wave finished before the previous barrier
+    if (t + 1 < nk) {
+      store((t + 1) & 1);
+      if (t + 2 < nk) fetch((int64_t)(t + 2) * SB_BK);
+    }
+    __syncthreads();
+  }
+  const float gs = (float)(gamma * 1.4426950408889634);
+  // the fused first scoring pass covers the block's first 64 columns: column wave 0, fragments 0..3
+  const bool fused = s0.partial != nullptr && tile.c == 0;
+  const bool mine = fused && wc == 0;
+  double ga[4][4];
+  float gy[4][4];
+  if (mine) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + wr * 64 + i * 16 + g * 4 + r;
+        gy[i][r] = row < n ? s0.y[row] : 0.0f;
+        ga[i][r] = row < n ? margin_gap(gy[i][r], s0.o[row]) : 0.0;
+      }
+  }
+  Score0Acc sa;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int64_t col = c0 + wc * 128 + j * 16 + i16;
+    if (col >= ncols) continue;
+    const int64_t zi = cidx ? (int64_t)cidx[col] : col;
+    if (zi < 0) continue;
+    const float zn = xnorm[zi];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + wr * 64 + i * 16 + g * 4 + r;
+        if (row < n) {
+          const float d2 = xnorm[row] + zn - 2.0f * acc[i][j][r];
+          const float kv = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
+          out[row * ldo + col] = kv;
+          if (mine && j < 4) sa.add(j, ga[i][r], gy[i][r], (double)kv);
+        }
+      }
+  }
+  if (fused) {
+    // waves 0..3 hold the first 128 columns (rows 64 wr ..); two waves per 128-row record
+    __shared__ double red[8][64][2];
+    sa.finish(s0.partial, tile.r * (BM / kKblockRows), ceil_div_dev(n, kKblockRows), 2, red);
+  }
+}
+
 // Tiles of 256 rows (each wave 64 x 64: more MFMAs per LDS fragment) once the matrix has enough of them to
 // fill the chip; 128 rows below that.
 constexpr int64_t kWideRows = 65536;
+// 256 x 256 tiles from this many columns on (and enough tiles to fill the chip)
+constexpr int64_t kWideCols = 192;
 
 void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int64_t ldb, int64_t n,
                         const float* xnorm, const int32_t* cidx, int ncols, float* out, int64_t ldo, double gamma,
@@ -507,6 +655,17 @@ void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int6
   if (n <= 0 || ncols <= 0) return;
   if (ldb % SB_BK != 0 || ((uintptr_t)hi & 15u) || ((uintptr_t)lo & 15u))
     throw Failure(1, "kernel block: split copies must be 16-byte aligned with ldb a multiple of 32");
+  if (ncols >= kWideCols && ceil_div(n, 256) * ceil_div(ncols, 256) >= 256) {
+    const dim3 grid(xcd_grid(ceil_div(n, 256), ceil_div(ncols, 256)));
+    if (lo)
+      hipLaunchKernelGGL((k_kblock_bf16_wide<true>), grid, dim3(512), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
+                         ldo, gamma, s0);
+    else
+      hipLaunchKernelGGL((k_kblock_bf16_wide<false>), grid, dim3(512), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols,
+                         out, ldo, gamma, s0);
+    SPSVM_LAUNCHED();
+    return;
+  }
   const bool wide = n >= kWideRows;
   const dim3 grid(xcd_grid(ceil_div(n, wide ? 256 : 128), ceil_div(ncols, KB_BN)));
   if (wide) {

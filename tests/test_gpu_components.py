@@ -51,6 +51,27 @@ def test_rbf_block_mixed_within_split_bound(n, d, nc):
     assert np.all(np.abs(K - want) <= bound)
 
 
+@pytest.mark.parametrize("n,d,nc,binary", [(70001, 300, 260, False), (66000, 54, 512, False),
+                                           (66000, 123, 256, True)])
+def test_rbf_block_mixed_wide_tiles(n, d, nc, binary):
+    """Blocks of 192 or more columns (with at least 256 tiles) take 256 x 256 tiles. Against the oracle: the split
+    bound (exact on binary rows). Against 64-column slices of the same block, which take the 64-column tiles: the
+    same products are summed in the same order, so the bits agree."""
+    X, idx, gamma, K, want = _kblock_case(n, d, nc, "mixed", np.float32, n * 17 + d, binary=binary)
+    if binary:
+        # exact distances; the FP32 exponent argument gamma log2(e) d2 carries a relative rounding of ~1 eps,
+        # which moves K by |ln K| eps relative, and exp2 adds a few ulps
+        assert np.all(np.abs(K - want) <= (2.0 * -np.log(want) + 4.0) * EPS32 * want)
+    else:
+        nx = (X * X).sum(1)
+        bound = 2.0 ** -13 * gamma * (nx[:, None] + nx[idx][None, :]) * want + 4 * EPS32
+        assert np.all(np.abs(K - want) <= bound)
+    Xg = torch.tensor(X, dtype=torch.float32, device="cuda")
+    for c in range(0, nc, 64):
+        part = lib.rbf_block(Xg, torch.tensor(idx[c:c + 64], device="cuda"), gamma, "mixed").cpu().numpy()
+        assert np.array_equal(part.astype(np.float64), K[:, c:c + 64])
+
+
 def test_rbf_block_mixed_exact_on_binary_rows():
     X, idx, gamma, K, want = _kblock_case(2000, 123, 64, "mixed", np.float32, 6, binary=True)
     assert np.max(np.abs(K - want) / want) <= 4 * EPS32

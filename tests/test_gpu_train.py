@@ -153,6 +153,28 @@ def test_mixed_wide_tiles_reach_oracle_objective():
     assert (Fo - F_or) / F_or <= 1e-6
 
 
+@pytest.mark.parametrize("binary", [False, True])
+def test_mixed_grouped_wide_tiles_reach_oracle_objective(binary):
+    """300 features: candidate steps share kernel-block launches (up to 8 steps, 512 columns), which the
+    split-BF16 block runs in 256 x 256 tiles with the fused first scoring pass in its first 64 columns."""
+    n, d = 40000, 300
+    if binary:
+        r = np.random.default_rng(31)
+        X = (r.random((n, d)) < 0.05).astype(np.float32)
+        s = X @ r.standard_normal(d) + 0.3 * r.standard_normal(n)
+        y = np.where(s > np.median(s), 1.0, -1.0).astype(np.float32)
+    else:
+        X, y = datagen.make_blobs(n, d, seed=23, dtype=np.float32)
+    C, gamma, m = 1.0, 1.0 / d, 120
+    Xg, yg = _dev(X, y)
+    model = lib.train(Xg, yg, C, gamma, m, seed=7, precision="mixed")
+    J, beta, F = model.get()
+    assert len(set(J.tolist())) == m
+    b_or, F_or, _ = osp.solve_fixed_J(X, y, C, gamma, J)
+    Fo = osp.objective_at(X, y, C, gamma, J, beta)
+    assert (Fo - F_or) / F_or <= 1e-6
+
+
 def test_mixed_on_bf16_exact_data_equals_fp32_bitwise():
     """0/1 features are exact in BF16, so the split's lo parts vanish and the mixed kernel block issues only
     hi.hi'; its integer dot products equal the FP32 path's, so the whole training run must agree bit for bit."""
