@@ -17,6 +17,9 @@
 
 namespace spsvm {
 
+constexpr int kMaxStageHash = 256;
+constexpr int kScoreWaves = 8;  // waves per scoring workgroup  // stage winners staged in LDS by the score init (the default stage cap)
+
 __device__ __forceinline__ bool hash_in(uint64_t h, const uint64_t* __restrict__ list, int cnt) {
   for (int q = 0; q < cnt; ++q)
     if (list[q] == h) return true;
@@ -28,7 +31,12 @@ __global__ void k_score_init(const int32_t* __restrict__ cand, const double* __r
                              const uint64_t* __restrict__ hash, const uint64_t* __restrict__ stage_hash, int n_stage,
                              CandState* __restrict__ st, NewtonScalars* sc) {
   __shared__ int red[1];
+  __shared__ uint64_t sh[kMaxStageHash];
   const int c = threadIdx.x;
+  // hashes of this stage's earlier winners, staged in LDS (every slot scans all of them)
+  const int ns = n_stage < kMaxStageHash ? n_stage : kMaxStageHash;
+  for (int q = c; q < ns; q += kCandSlots) sh[q] = stage_hash[q];
+  __syncthreads();
   CandState s;
   s.idx = cand[c];
   s.s = 0.0;
@@ -39,7 +47,7 @@ __global__ void k_score_init(const int32_t* __restrict__ cand, const double* __r
   s.score = -__builtin_huge_val();
   s.newton = 0;
   s.passes = 0;
-  if (s.idx < 0 || hash_in(hash[s.idx], stage_hash, n_stage)) {
+  if (s.idx < 0 || hash_in(hash[s.idx], sh, ns) || (n_stage > ns && hash_in(hash[s.idx], stage_hash + ns, n_stage - ns))) {
     s.status = 2;
   } else {
     s.status = 0;
@@ -92,14 +100,17 @@ __device__ __forceinline__ int advance_slot(CandState& s, double P, double Q, do
   return still;
 }
 
-// One pass over the rows for every active slot. Thread (wave q, lane c) handles slot c on rows lo + q, lo + q + 4,
-// ... of its workgroup's range, two rows per iteration with separate accumulators; the four waves' sums are
-// added in wave order and written as this workgroup's partial record {P, Q, V, flips} per slot.
+// One pass over the rows for every active slot. Thread (wave q, lane c) handles slot c on rows lo + q,
+// lo + q + kScoreWaves, ... of its workgroup's range, eight rows per iteration into two sets of sums; the waves'
+// sums are added in wave order and written as this workgroup's partial record {P, Q, V, flips} per slot.
 template <typename TK>
-__global__ __launch_bounds__(256) void k_score_pass(const TK* __restrict__ Kc, int64_t ldc, const float* __restrict__ y,
-                                                    const double* __restrict__ o, int64_t n, int64_t rows_per_blk,
-                                                    const CandState* __restrict__ st, double* __restrict__ partial) {
-  __shared__ double sh[4][4][kCandSlots];
+__global__ __launch_bounds__(64 * kScoreWaves) void k_score_pass(const TK* __restrict__ Kc, int64_t ldc,
+                                                                  const float* __restrict__ y,
+                                                                  const double* __restrict__ o, int64_t n,
+                                                                  int64_t rows_per_blk,
+                                                                  const CandState* __restrict__ st,
+                                                                  double* __restrict__ partial) {
+  __shared__ double sh[kScoreWaves][4][kCandSlots];
   const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int status = st[c].status;
   if (!__any(status == 0)) return;  // every slot is settled (same answer in every wave and workgroup)
@@ -112,28 +123,42 @@ __global__ __launch_bounds__(256) void k_score_pass(const TK* __restrict__ Kc, i
     double P2 = 0.0, Q2 = 0.0, V2 = 0.0;
     int fl = 0, fl2 = 0;
     int64_t i = lo + q;
-    for (; i + 4 < hi; i += 8) {
-      const double y0 = (double)y[i], y1 = (double)y[i + 4];
-      const double a0 = margin_gap(y[i], o[i]), a1 = margin_gap(y[i + 4], o[i + 4]);
-      const double b0 = y0 * (double)Kc[i * ldc + c], b1 = y1 * (double)Kc[(i + 4) * ldc + c];
-      const double e0 = a0 - s * b0, e1 = a1 - s * b1;
-      if (e0 > 0.0) {
-        P += a0 * b0;
-        Q += b0 * b0;
+    // eight rows per iteration: their loads are issued together, so each wave keeps eight rows in flight;
+    // even rows go to the first set of sums, odd rows to the second
+    constexpr int U = 8;
+    for (; i + kScoreWaves * (U - 1) < hi; i += kScoreWaves * U) {
+      float yv[U];
+      double ov[U], kv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        yv[u] = y[i + kScoreWaves * u];
+        ov[u] = o[i + kScoreWaves * u];
+        kv[u] = (double)Kc[(i + kScoreWaves * u) * ldc + c];
       }
-      if (e1 > 0.0) {
-        P2 += a1 * b1;
-        Q2 += b1 * b1;
-      }
-      const double u0 = fmax(a0, 0.0), w0 = fmax(e0, 0.0), u1 = fmax(a1, 0.0), w1 = fmax(e1, 0.0);
-      V += (w0 - u0) * (w0 + u0);
-      V2 += (w1 - u1) * (w1 + u1);
-      if (chk) {
-        fl += ((e0 > 0.0) != (a0 - sp * b0 > 0.0)) ? 1 : 0;
-        fl2 += ((e1 > 0.0) != (a1 - sp * b1 > 0.0)) ? 1 : 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double a = margin_gap(yv[u], ov[u]);
+        const double b = (double)yv[u] * kv[u];
+        const double e = a - s * b;
+        const double ua = fmax(a, 0.0), we = fmax(e, 0.0);
+        const int flip = chk && ((e > 0.0) != (a - sp * b > 0.0)) ? 1 : 0;
+        // selects rather than branches (adding an exact zero leaves a sum unchanged), so that no control flow
+        // keeps the compiler from issuing the eight rows' loads together
+        const double pa = e > 0.0 ? a * b : 0.0, qa = e > 0.0 ? b * b : 0.0;
+        if (u & 1) {
+          P2 += pa;
+          Q2 += qa;
+          V2 += (we - ua) * (we + ua);
+          fl2 += flip;
+        } else {
+          P += pa;
+          Q += qa;
+          V += (we - ua) * (we + ua);
+          fl += flip;
+        }
       }
     }
-    for (; i < hi; i += 4) {
+    for (; i < hi; i += kScoreWaves) {
       const double yi = (double)y[i];
       const double a = margin_gap(y[i], o[i]);
       const double b = yi * (double)Kc[i * ldc + c];
@@ -159,7 +184,12 @@ __global__ __launch_bounds__(256) void k_score_pass(const TK* __restrict__ Kc, i
   if (q == 0) {
     double* out = partial + ((int64_t)blockIdx.x * kCandSlots + c) * 4;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[k] = sh[0][k][c] + sh[1][k][c] + sh[2][k][c] + sh[3][k][c];
+    for (int k = 0; k < 4; ++k) {
+      double t = sh[0][k][c];
+#pragma unroll
+      for (int v = 1; v < kScoreWaves; ++v) t += sh[v][k][c];
+      out[k] = t;
+    }
   }
 }
 
@@ -167,27 +197,29 @@ __global__ __launch_bounds__(256) void k_score_pass(const TK* __restrict__ Kc, i
 // tree, then advance the slot.
 __global__ __launch_bounds__(256) void k_score_update(CandState* __restrict__ st, const double* __restrict__ partial,
                                                       int nblk, double lam) {
-  __shared__ double red[4][256];
+  __shared__ double red[4][4];
   const int c = blockIdx.x;
   if (st[c].status != 0) return;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblk; b += 256) {
-    const double* p = partial + ((int64_t)b * kCandSlots + c) * 4;
+    const doublex4 p = *(const doublex4*)(partial + ((int64_t)b * kCandSlots + c) * 4);
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] += p[k];
   }
+  // fixed order: xor butterflies inside each wave, then the four waves in order
+  const int w = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = v[k];
+  for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[w][k] = v[k];
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-#pragma unroll
-      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
+    double t[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
     CandState cs = st[c];
-    advance_slot(cs, red[0][0], red[1][0], red[2][0], red[3][0], lam);
+    advance_slot(cs, t[0], t[1], t[2], t[3], lam);
     st[c] = cs;
   }
 }
@@ -225,8 +257,8 @@ int score_blocks(int64_t n) {
 template <typename TK>
 void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, const CandState* st,
                        double* partial, int nblk, hipStream_t s) {
-  const int64_t rows = round_up(ceil_div(n, nblk), 4);
-  hipLaunchKernelGGL((k_score_pass<TK>), dim3(nblk), dim3(256), 0, s, Kc, ldc, y, o, n, rows, st, partial);
+  const int64_t rows = round_up(ceil_div(n, nblk), kScoreWaves);
+  hipLaunchKernelGGL((k_score_pass<TK>), dim3(nblk), dim3(64 * kScoreWaves), 0, s, Kc, ldc, y, o, n, rows, st, partial);
   SPSVM_LAUNCHED();
 }
 
