@@ -77,8 +77,11 @@ __device__ __forceinline__ int block_sum_int(int v, int* scratch) {
 // a_i = 1 - y_i o_i with explicit rounding (no contraction), so every kernel draws the same violator set.
 __device__ __forceinline__ double margin_gap(float y, double o) { return __dadd_rn(1.0, -__dmul_rn((double)y, o)); }
 
-// exp(-g * d2) where g2 = g * log2(e) was folded in on the host: FP32 uses the hardware 2^x.
-__device__ __forceinline__ float rbf_from_d2(float d2, float g2) { return exp2f(-g2 * fmaxf(d2, 0.0f)); }
+// exp(-g * d2) where g2 = g * log2(e) was folded in on the host: FP32 uses the hardware 2^x instruction as is
+// (no rescaling of arguments below -126, so values under 2^-126 may come out as zero).
+__device__ __forceinline__ float rbf_from_d2(float d2, float g2) {
+  return __builtin_amdgcn_exp2f(-g2 * fmaxf(d2, 0.0f));
+}
 __device__ __forceinline__ double rbf_from_d2(double d2, double g) { return exp(-g * fmax(d2, 0.0)); }
 
 }  // namespace spsvm

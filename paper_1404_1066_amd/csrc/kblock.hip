@@ -3,6 +3,8 @@
 // as an MFMA GEMM (x_i . z_c) with the exp fused into the epilogue (RBF kernel of section 2; the block
 // K(X, X_J) and the candidate columns of section 4, "Sparse primal optimization"). A predict variant
 // multiplies by beta and reduces over the basis in the epilogue, so the n_t x m block is never stored.
+#include <type_traits>
+
 #include "common.h"
 #include "launch.h"
 
@@ -185,17 +187,27 @@ struct KTile {
     fetch(0);
     for (int64_t k0 = 0; k0 < d; k0 += KB_BK) {
       __syncthreads();
+      // whole vectors: a row's elements past d are zero (the rows are padded with zeros, or d is a multiple of
+      // the vector width), and vectors that start past d were fetched as zeros
 #pragma unroll
       for (int e = 0; e < NA; ++e) {
         const int r = (tid + e * 256) / PA;
+        if constexpr (std::is_same<TA, TK>::value) {
+          *(VTA*)&As[r][ka] = ra[e];
+        } else {
 #pragma unroll
-        for (int v = 0; v < VA; ++v) As[r][ka + v] = (k0 + ka + v < d) ? (TK)ra[e][v] : (TK)0;
+          for (int v = 0; v < VA; ++v) As[r][ka + v] = (TK)ra[e][v];
+        }
       }
 #pragma unroll
       for (int e = 0; e < NB; ++e) {
         const int r = (tid + e * 256) / PB;
+        if constexpr (std::is_same<TB, TK>::value) {
+          *(VTB*)&Bs[r][kb] = rb[e];
+        } else {
 #pragma unroll
-        for (int v = 0; v < VB; ++v) Bs[r][kb + v] = (k0 + kb + v < d) ? (TK)rb[e][v] : (TK)0;
+          for (int v = 0; v < VB; ++v) Bs[r][kb + v] = (TK)rb[e][v];
+        }
       }
       __syncthreads();
       if (k0 + KB_BK < d) fetch(k0 + KB_BK);
@@ -261,10 +273,15 @@ struct Score0Acc {
   }
 };
 
+// Waves per SIMD the FP32 block is compiled for: four (at most 128 registers) keeps four workgroups of the
+// launch on each CU; the other type combinations take what their registers allow.
+template <typename TX, typename TK>
+constexpr int kStoreWaves = (std::is_same<TX, float>::value && std::is_same<TK, float>::value) ? 4 : 1;
+
 // STORE: out[row * ldo + c] for the tile of xcd_tile().
 // gamma > 0: out = exp(-gamma d2); gamma == 0: out = d2 (the squared distance itself, clamped at 0).
 template <typename TX, typename TK>
-__global__ __launch_bounds__(256) void k_kblock_store(const TX* __restrict__ X, int64_t ldx, int64_t n, int64_t d,
+__global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(const TX* __restrict__ X, int64_t ldx, int64_t n, int64_t d,
                                                       const TK* __restrict__ xnorm, const int32_t* __restrict__ cidx,
                                                       int ncols, TK* __restrict__ out, int64_t ldo, double gamma,
                                                       const Score0 s0) {
@@ -288,30 +305,81 @@ __global__ __launch_bounds__(256) void k_kblock_store(const TX* __restrict__ X, 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
-        gy[i][r] = row < n ? s0.y[row] : 0.0f;
-        ga[i][r] = row < n ? margin_gap(gy[i][r], s0.o[row]) : 0.0;
+        const int64_t rc = row < n ? row : n - 1;  // clamped: unconditional loads, no branches between them
+        const float yv = s0.y[rc];
+        const double ov = s0.o[rc];
+        gy[i][r] = row < n ? yv : 0.0f;
+        ga[i][r] = row < n ? margin_gap(yv, ov) : 0.0;
       }
   }
-  Score0Acc sa;
+  // every norm this lane needs, loaded before the first store (a load issued after a store waits for it)
+  TK xr[2][4], zn[4];
+  bool zok[4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
+      xr[i][r] = xnorm[row < n ? row : n - 1];  // rows past n are computed but never used
+    }
+  int64_t zis[4];  // source rows of this lane's columns: all index loads first, then all norm loads
+  if (cidx) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = c0 + j * 16 + (lane & 15);
+      zis[j] = cidx[col < ncols ? col : ncols - 1];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) zis[j] = c0 + j * 16 + (lane & 15);
+  }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int64_t col = c0 + j * 16 + (lane & 15);
-    if (col >= ncols) continue;
-    const int64_t zi = cidx ? (int64_t)cidx[col] : col;
-    if (zi < 0) continue;  // empty candidate slot
-    const TK zn = xnorm[zi];
+    const int64_t zi = col < ncols ? zis[j] : -1;
+    zok[j] = zi >= 0;  // false: past the block or an empty candidate slot
+    zn[j] = xnorm[zok[j] ? zi : 0];
+  }
+  Score0Acc sa;
+  // Per 16-row group i: all values, then their stores (every load was issued above, so no store waits on one).
+  // The uniform choices (exp or plain distance, fused pass or not) are taken once, outside the element loops;
+  // rows past n have a_i = 0 and add nothing to the fused sums.
+  auto group = [&](int i, auto rbf_tag, auto fused_tag) {
+    constexpr bool RBF = decltype(rbf_tag)::value, FUSED = decltype(fused_tag)::value;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 4; ++j) {
+      if (!zok[j]) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
-        if (row < n) {
-          const TK d2 = xnorm[row] + zn - (TK)2 * t.acc[i][j][r];
-          const TK kv = gamma > 0.0 ? rbf_from_d2(d2, gs) : (d2 > (TK)0 ? d2 : (TK)0);
-          out[row * ldo + col] = kv;
-          if (fused) sa.add(j, ga[i][r], gy[i][r], (double)kv);
-        }
+        const TK d2 = xr[i][r] + zn[j] - (TK)2 * t.acc[i][j][r];
+        const TK kv = RBF ? rbf_from_d2(d2, gs) : (d2 > (TK)0 ? d2 : (TK)0);
+        t.acc[i][j][r] = kv;
+        if (FUSED) sa.add(j, ga[i][r], gy[i][r], (double)kv);
       }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
+      if (row >= n) continue;
+      TK* orow = out + row * ldo + c0 + (lane & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (zok[j]) orow[j * 16] = t.acc[i][j][r];
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (gamma > 0.0) {
+      if (fused)
+        group(i, std::true_type{}, std::true_type{});
+      else
+        group(i, std::true_type{}, std::false_type{});
+    } else {
+      if (fused)
+        group(i, std::false_type{}, std::true_type{});
+      else
+        group(i, std::false_type{}, std::false_type{});
+    }
   }
   if (fused) {
     __shared__ double red[4][64][2];
@@ -465,31 +533,67 @@ __global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __res
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = r0 + w * 16 * RTW + i * 16 + (lane >> 4) * 4 + r;
-        gy[i][r] = row < n ? s0.y[row] : 0.0f;
-        ga[i][r] = row < n ? margin_gap(gy[i][r], s0.o[row]) : 0.0;
+        const int64_t rc = row < n ? row : n - 1;  // clamped: unconditional loads, no branches between them
+        const float yv = s0.y[rc];
+        const double ov = s0.o[rc];
+        gy[i][r] = row < n ? yv : 0.0f;
+        ga[i][r] = row < n ? margin_gap(yv, ov) : 0.0;
       }
+  }
+  // every norm this lane needs, loaded before the first store (a load issued after a store waits for it)
+  float xr[RTW][4], zn[4];
+  bool zok[4];
+#pragma unroll
+  for (int i = 0; i < RTW; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + w * 16 * RTW + i * 16 + (lane >> 4) * 4 + r;
+      xr[i][r] = xnorm[row < n ? row : n - 1];  // rows past n are computed but never used
+    }
+  int64_t zis[4];  // source rows of this lane's columns: all index loads first, then all norm loads
+  if (cidx) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = c0 + j * 16 + i16;
+      zis[j] = cidx[col < ncols ? col : ncols - 1];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) zis[j] = c0 + j * 16 + i16;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t col = c0 + j * 16 + i16;
+    const int64_t zi = col < ncols ? zis[j] : -1;
+    zok[j] = zi >= 0;
+    zn[j] = xnorm[zok[j] ? zi : 0];
   }
   Score0Acc sa;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int64_t col = c0 + j * 16 + i16;
-    if (col >= ncols) continue;
-    const int64_t zi = cidx ? (int64_t)cidx[col] : col;
-    if (zi < 0) continue;
-    const float zn = xnorm[zi];
+    if (!zok[j]) continue;
 #pragma unroll
     for (int i = 0; i < RTW; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + w * 16 * RTW + i * 16 + (lane >> 4) * 4 + r;
-        if (row < n) {
-          const float d2 = xnorm[row] + zn - 2.0f * acc[i][j][r];
-          const float kv = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
-          out[row * ldo + col] = kv;
-          if (fused) sa.add(j, ga[i][r], gy[i][r], (double)kv);
-        }
+        const float d2 = xr[i][r] + zn[j] - 2.0f * acc[i][j][r];
+        const float kv = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
+        acc[i][j][r] = kv;
+        if (fused) sa.add(j, ga[i][r], gy[i][r], (double)kv);  // rows past n have a_i = 0: they add nothing
       }
   }
+  // all values first, then the stores, so that no load is waited for between two stores; one address per row
+#pragma unroll
+  for (int i = 0; i < RTW; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + w * 16 * RTW + i * 16 + (lane >> 4) * 4 + r;
+      if (row >= n) continue;
+      float* orow = out + row * ldo + c0 + i16;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (zok[j]) orow[j * 16] = acc[i][j][r];
+    }
   if (fused) {
     __shared__ double red[4][64][2];
     // one record per 128 rows: RTW = 2 -> all four waves, RTW = 4 -> two pairs of waves
@@ -611,31 +715,67 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = r0 + wr * 64 + i * 16 + g * 4 + r;
-        gy[i][r] = row < n ? s0.y[row] : 0.0f;
-        ga[i][r] = row < n ? margin_gap(gy[i][r], s0.o[row]) : 0.0;
+        const int64_t rc = row < n ? row : n - 1;  // clamped: unconditional loads, no branches between them
+        const float yv = s0.y[rc];
+        const double ov = s0.o[rc];
+        gy[i][r] = row < n ? yv : 0.0f;
+        ga[i][r] = row < n ? margin_gap(yv, ov) : 0.0;
       }
+  }
+  // every norm this lane needs, loaded before the first store (a load issued after a store waits for it)
+  float xr[4][4], zn[8];
+  bool zok[8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + wr * 64 + i * 16 + g * 4 + r;
+      xr[i][r] = xnorm[row < n ? row : n - 1];  // rows past n are computed but never used
+    }
+  int64_t zis[8];  // source rows of this lane's columns: all index loads first, then all norm loads
+  if (cidx) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t col = c0 + wc * 128 + j * 16 + i16;
+      zis[j] = cidx[col < ncols ? col : ncols - 1];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) zis[j] = c0 + wc * 128 + j * 16 + i16;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int64_t col = c0 + wc * 128 + j * 16 + i16;
+    const int64_t zi = col < ncols ? zis[j] : -1;
+    zok[j] = zi >= 0;
+    zn[j] = xnorm[zok[j] ? zi : 0];
   }
   Score0Acc sa;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int64_t col = c0 + wc * 128 + j * 16 + i16;
-    if (col >= ncols) continue;
-    const int64_t zi = cidx ? (int64_t)cidx[col] : col;
-    if (zi < 0) continue;
-    const float zn = xnorm[zi];
+    if (!zok[j]) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + wr * 64 + i * 16 + g * 4 + r;
-        if (row < n) {
-          const float d2 = xnorm[row] + zn - 2.0f * acc[i][j][r];
-          const float kv = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
-          out[row * ldo + col] = kv;
-          if (mine && j < 4) sa.add(j, ga[i][r], gy[i][r], (double)kv);
-        }
+        const float d2 = xr[i][r] + zn[j] - 2.0f * acc[i][j][r];
+        const float kv = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
+        acc[i][j][r] = kv;
+        if (mine && j < 4) sa.add(j, ga[i][r], gy[i][r], (double)kv);  // rows past n have a_i = 0
       }
   }
+  // all values first, then the stores, so that no load is waited for between two stores; one address per row
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + wr * 64 + i * 16 + g * 4 + r;
+      if (row >= n) continue;
+      float* orow = out + row * ldo + c0 + wc * 128 + i16;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (zok[j]) orow[j * 16] = acc[i][j][r];
+    }
   if (fused) {
     // waves 0..3 hold the first 128 columns (rows 64 wr ..); two waves per 128-row record
     __shared__ double red[8][64][2];
