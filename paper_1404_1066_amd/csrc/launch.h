@@ -133,8 +133,9 @@ void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv
                      NewtonScalars* sc, hipStream_t s);
 int gradient_chunks(int m, int n_sv);
 // Batched launches: up to kMaxBatch independent problems (slots) per launch, one grid z-index per slot; the
-// per-slot operands travel by value in the kernel arguments.
-constexpr int kMaxBatch = 32;
+// per-slot operands travel by value in the kernel arguments. 48 covers the 40 problems of one kernel width in
+// a one-vs-rest x C sweep with a single launch per step, and keeps the largest argument block near 3 KB.
+constexpr int kMaxBatch = 48;
 
 // out_q = K x_q for up to kMaxBatch vectors x_q (m FP64 values each, 32-byte aligned) with one read of K
 // (n x m, leading dimension ldk a multiple of 4, rows 16-byte aligned). FP64 MFMA, exact products.

@@ -579,14 +579,18 @@ void launch_gemv_batch(const TK* K, int64_t ldk, int64_t n, int m, const GemvBat
     const dim3 grid((unsigned)ceil_div(n, 32));
     if (b.count <= 16)
       hipLaunchKernelGGL((k_gemv_batch<TK, 2, 1>), grid, dim3(64), 0, s, K, ldk, n, m, b);
-    else
+    else if (b.count <= 32)
       hipLaunchKernelGGL((k_gemv_batch<TK, 2, 2>), grid, dim3(64), 0, s, K, ldk, n, m, b);
+    else
+      hipLaunchKernelGGL((k_gemv_batch<TK, 2, 3>), grid, dim3(64), 0, s, K, ldk, n, m, b);
   } else {
     const dim3 grid((unsigned)ceil_div(n, 16));
     if (b.count <= 16)
       hipLaunchKernelGGL((k_gemv_batch<TK, 1, 1>), grid, dim3(64), 0, s, K, ldk, n, m, b);
-    else
+    else if (b.count <= 32)
       hipLaunchKernelGGL((k_gemv_batch<TK, 1, 2>), grid, dim3(64), 0, s, K, ldk, n, m, b);
+    else
+      hipLaunchKernelGGL((k_gemv_batch<TK, 1, 3>), grid, dim3(64), 0, s, K, ldk, n, m, b);
   }
   SPSVM_LAUNCHED();
 }
@@ -747,8 +751,10 @@ void launch_gradient_batch(const TK* K, int64_t ldk, int64_t n, int m, const Gra
   if (n > 0) {
     if (b.count <= 16)
       hipLaunchKernelGGL((k_grad_batch<TK, 1>), grid, dim3(64), 0, s, K, ldk, n, m, rows, b);
-    else
+    else if (b.count <= 32)
       hipLaunchKernelGGL((k_grad_batch<TK, 2>), grid, dim3(64), 0, s, K, ldk, n, m, rows, b);
+    else
+      hipLaunchKernelGGL((k_grad_batch<TK, 3>), grid, dim3(64), 0, s, K, ldk, n, m, rows, b);
     SPSVM_LAUNCHED();
   }
   const int nb = (int)ceil_div(m, 64);
