@@ -448,7 +448,7 @@ void launch_split_bf16(const TX* X, int64_t n, int64_t d, int64_t ldx, unsigned 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <bool SPLIT, int RTW>
-__global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __restrict__ hi,
+__global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const unsigned short* __restrict__ hi,
                                                      const unsigned short* __restrict__ lo, int64_t ldb, int64_t n,
                                                      const float* __restrict__ xnorm,
                                                      const int32_t* __restrict__ cidx, int ncols,
@@ -569,22 +569,21 @@ __global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __res
     zn[j] = xnorm[zok[j] ? zi : 0];
   }
   Score0Acc sa;
+  // Per 16-row group i: all values, then their stores (every load was issued above, so no store waits on one);
+  // rows past n have a_i = 0 and add nothing to the fused sums.
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    if (!zok[j]) continue;
+  for (int i = 0; i < RTW; ++i) {
 #pragma unroll
-    for (int i = 0; i < RTW; ++i)
+    for (int j = 0; j < 4; ++j) {
+      if (!zok[j]) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float d2 = xr[i][r] + zn[j] - 2.0f * acc[i][j][r];
         const float kv = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
         acc[i][j][r] = kv;
-        if (fused) sa.add(j, ga[i][r], gy[i][r], (double)kv);  // rows past n have a_i = 0: they add nothing
+        if (fused) sa.add(j, ga[i][r], gy[i][r], (double)kv);
       }
-  }
-  // all values first, then the stores, so that no load is waited for between two stores; one address per row
-#pragma unroll
-  for (int i = 0; i < RTW; ++i)
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = r0 + w * 16 * RTW + i * 16 + (lane >> 4) * 4 + r;
@@ -594,6 +593,7 @@ __global__ __launch_bounds__(256) void k_kblock_bf16(const unsigned short* __res
       for (int j = 0; j < 4; ++j)
         if (zok[j]) orow[j * 16] = acc[i][j][r];
     }
+  }
   if (fused) {
     __shared__ double red[4][64][2];
     // one record per 128 rows: RTW = 2 -> all four waves, RTW = 4 -> two pairs of waves
@@ -751,22 +751,21 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
     zn[j] = xnorm[zok[j] ? zi : 0];
   }
   Score0Acc sa;
+  // Per 16-row group i: all values, then their stores (every load was issued above, so no store waits on one);
+  // rows past n have a_i = 0 and add nothing to the fused sums.
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    if (!zok[j]) continue;
+  for (int i = 0; i < 4; ++i) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 8; ++j) {
+      if (!zok[j]) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float d2 = xr[i][r] + zn[j] - 2.0f * acc[i][j][r];
         const float kv = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
         acc[i][j][r] = kv;
-        if (mine && j < 4) sa.add(j, ga[i][r], gy[i][r], (double)kv);  // rows past n have a_i = 0
+        if (mine && j < 4) sa.add(j, ga[i][r], gy[i][r], (double)kv);
       }
-  }
-  // all values first, then the stores, so that no load is waited for between two stores; one address per row
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = r0 + wr * 64 + i * 16 + g * 4 + r;
@@ -776,6 +775,7 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
       for (int j = 0; j < 8; ++j)
         if (zok[j]) orow[j * 16] = acc[i][j][r];
     }
+  }
   if (fused) {
     // waves 0..3 hold the first 128 columns (rows 64 wr ..); two waves per 128-row record
     __shared__ double red[8][64][2];
@@ -784,7 +784,7 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
 }
 
 // Tiles of 256 rows (each wave 64 x 64: more MFMAs per LDS fragment) once the matrix has enough of them to
-// fill the chip; 128 rows below that.
+// fill the chip and rows are long enough for the k loop to dominate; 128 rows otherwise.
 constexpr int64_t kWideRows = 65536;
 // 256 x 256 tiles from this many columns on (and enough tiles to fill the chip)
 constexpr int64_t kWideCols = 192;
@@ -806,7 +806,7 @@ void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int6
     SPSVM_LAUNCHED();
     return;
   }
-  const bool wide = n >= kWideRows;
+  const bool wide = n >= kWideRows && ldb >= 256;  // short rows: the 128-row tiles keep more waves resident
   const dim3 grid(xcd_grid(ceil_div(n, wide ? 256 : 128), ceil_div(ncols, KB_BN)));
   if (wide) {
     if (lo)

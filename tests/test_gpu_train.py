@@ -141,15 +141,22 @@ def test_onehot_mixed_precision_reaches_oracle_objective(prec):
     assert _decision_err(dg, do) <= 1e-4
 
 
-def test_mixed_wide_tiles_reach_oracle_objective():
-    """Mixed precision at n >= 65536 (the split-BF16 block then uses 256-row tiles, and the fused first scoring
-    pass writes two 128-row records per tile)."""
-    p = datagen.make_config("onehot-500k", n=70001, J_max=150)
-    Xg, yg = _dev(p.X, p.y)
-    model = lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=2, precision="mixed")
+@pytest.mark.parametrize("d", [54, 300])
+def test_mixed_tall_blocks_reach_oracle_objective(d):
+    """Mixed precision at n >= 65536: short rows (d = 54) keep the 128-row tiles; long rows (d = 300) take
+    256-row tiles for single candidate steps, whose fused first scoring pass writes two 128-row records per tile
+    (later stages group steps into 256 x 256 tiles)."""
+    if d == 54:
+        p = datagen.make_config("onehot-500k", n=70001, J_max=150)
+        X, y, C, gamma, m = p.X, p.y, p.C, p.gamma, p.J_max
+    else:
+        X, y = datagen.make_blobs(70001, d, seed=24, dtype=np.float32)
+        C, gamma, m = 1.0, 1.0 / d, 60
+    Xg, yg = _dev(X, y)
+    model = lib.train(Xg, yg, C, gamma, m, seed=2, precision="mixed")
     J, beta, F = model.get()
-    b_or, F_or, _ = osp.solve_fixed_J(p.X, p.y, p.C, p.gamma, J)
-    Fo = osp.objective_at(p.X, p.y, p.C, p.gamma, J, beta)
+    b_or, F_or, _ = osp.solve_fixed_J(X, y, C, gamma, J)
+    Fo = osp.objective_at(X, y, C, gamma, J, beta)
     assert (Fo - F_or) / F_or <= 1e-6
 
 
