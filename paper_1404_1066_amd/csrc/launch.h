@@ -113,8 +113,10 @@ template <typename TK>
 void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, const CandState* st,
                        double* partial, int nblk, hipStream_t s);
 void launch_score_update(CandState* st, const double* partial, int nblk, double lam, hipStream_t s);
+// Argmax of the scored slots and its append (one launch). Kc: the step's candidate columns (leading dimension
+// ldc); fused0: its first scoring pass came with the block; m_dev: two ints, step q reads the basis size at
+// m_dev[q & 1] and writes the next at m_dev[(q + 1) & 1].
 template <typename TK>
-// Kc: the step's candidate columns (leading dimension ldc); fused0: its first scoring pass came with the block.
 void launch_select_append(const CandState* st, const uint64_t* hash, uint64_t* stage_hash, int q, const TK* Kc,
                           int64_t ldc, int64_t n, double* o, TK* KXJ, int64_t ldk, int64_t* J, double* beta,
                           int32_t* m_dev, Selection* sel, int32_t* incomplete, int fused0, hipStream_t s);

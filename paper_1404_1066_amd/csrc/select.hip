@@ -267,67 +267,77 @@ void launch_score_update(CandState* st, const double* partial, int nblk, double 
   SPSVM_LAUNCHED();
 }
 
-// Argmax over the scored slots (strictly larger score wins, equal scores go to the lower training row),
-// then append the winner to J and beta.
-__global__ void k_select(const CandState* __restrict__ st, const uint64_t* __restrict__ hash,
-                         uint64_t* __restrict__ stage_hash, int q, int64_t* __restrict__ J, double* __restrict__ beta,
-                         int32_t* __restrict__ m_dev, Selection* __restrict__ sel, int32_t* __restrict__ incomplete,
-                         int fused0) {
-  const int c = threadIdx.x;
-  const CandState s = st[c];
-  int mp = s.passes;
-  for (int off = 32; off > 0; off >>= 1) mp = max(mp, __shfl_xor(mp, off, kWave));
-  if (c == 0) {
-    atomicMax(&incomplete[1], mp);  // largest number of passes any slot needed in this stage
-    atomicAdd(&incomplete[2], mp > fused0 ? mp - fused0 : 0);  // launched passes of this step that did work
-                                                                // (fused0: the first pass came with the block)
-  }
-  const int pending = __any(s.status == 0);  // a slot still being scored: this step must be redone
-  const bool ok = !pending && s.status == 1 && s.idx >= 0 && !(s.score != s.score);
-  double best = ok ? s.score : -__builtin_huge_val();
-  int bidx = ok ? s.idx : 0x7fffffff;
-  int bslot = c;
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ob = __shfl_xor(best, off, kWave);
-    const int oi = __shfl_xor(bidx, off, kWave);
-    const int os = __shfl_xor(bslot, off, kWave);
-    if (ob > best || (ob == best && oi < bidx)) {
-      best = ob;
-      bidx = oi;
-      bslot = os;
-    }
-  }
-  if (c == 0) {
-    if (pending) *incomplete = 1;
-    Selection r;
-    r.valid = bidx != 0x7fffffff;
-    r.slot = bslot;
-    r.idx = bidx;
-    r.score = best;
-    r.s = 0.0;
-    r.pos = *m_dev;
-    if (r.valid) {
-      r.s = st[bslot].s;
-      J[r.pos] = bidx;
-      beta[r.pos] = r.s;
-      stage_hash[q] = hash[bidx];
-      *m_dev = r.pos + 1;
-    }
-    *sel = r;
-  }
-}
-
-// o += s * k_winner; K_XJ[:, pos] = k_winner.
+// Argmax over the scored slots (strictly larger score wins, equal scores go to the lower training row), then
+// the append: o += s * k_winner and K_XJ[:, pos] = k_winner over all rows. Every workgroup takes the same
+// argmax from the slot states; workgroup 0 alone records it (J, beta, the stage hash, the pass counters and
+// the next basis size). The basis size is double-buffered by step parity: step q reads m_dev[q & 1] and
+// writes m_dev[(q + 1) & 1], so no workgroup reads a value another one has already advanced.
 template <typename TK>
-__global__ __launch_bounds__(256) void k_append(const Selection* __restrict__ sel, const TK* __restrict__ Kc, int64_t ldc,
-                                                int64_t n,
-                                                double* __restrict__ o, TK* __restrict__ KXJ, int64_t ldk) {
-  const Selection s = *sel;
-  if (!s.valid) return;
+__global__ __launch_bounds__(256) void k_select_append(const CandState* __restrict__ st,
+                                                       const uint64_t* __restrict__ hash,
+                                                       uint64_t* __restrict__ stage_hash, int q,
+                                                       int64_t* __restrict__ J, double* __restrict__ beta,
+                                                       int32_t* __restrict__ m_dev, Selection* __restrict__ sel,
+                                                       int32_t* __restrict__ incomplete, int fused0,
+                                                       const TK* __restrict__ Kc, int64_t ldc, int64_t n,
+                                                       double* __restrict__ o, TK* __restrict__ KXJ, int64_t ldk) {
+  __shared__ Selection choice;
+  if (threadIdx.x < kWave) {
+    const int c = threadIdx.x;
+    const CandState s = st[c];
+    const int pending = __any(s.status == 0);  // a slot still being scored: this step must be redone
+    const bool ok = !pending && s.status == 1 && s.idx >= 0 && !(s.score != s.score);
+    double best = ok ? s.score : -__builtin_huge_val();
+    int bidx = ok ? s.idx : 0x7fffffff;
+    int bslot = c;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, kWave);
+      const int oi = __shfl_xor(bidx, off, kWave);
+      const int os = __shfl_xor(bslot, off, kWave);
+      if (ob > best || (ob == best && oi < bidx)) {
+        best = ob;
+        bidx = oi;
+        bslot = os;
+      }
+    }
+    const double s_best = __shfl(s.s, bslot, kWave);
+    if (c == 0) {
+      Selection r;
+      r.valid = bidx != 0x7fffffff;
+      r.slot = bslot;
+      r.idx = bidx;
+      r.score = best;
+      r.s = r.valid ? s_best : 0.0;
+      r.pos = m_dev[q & 1];
+      choice = r;
+      if (blockIdx.x == 0) {
+        if (pending) *incomplete = 1;
+        if (r.valid) {
+          J[r.pos] = bidx;
+          beta[r.pos] = r.s;
+          stage_hash[q] = hash[bidx];
+        }
+        m_dev[(q + 1) & 1] = r.pos + (r.valid ? 1 : 0);
+        *sel = r;
+      }
+    }
+    if (blockIdx.x == 0) {
+      int mp = s.passes;
+      for (int off = 32; off > 0; off >>= 1) mp = max(mp, __shfl_xor(mp, off, kWave));
+      if (c == 0) {
+        atomicMax(&incomplete[1], mp);  // largest number of passes any slot needed in this stage
+        atomicAdd(&incomplete[2], mp > fused0 ? mp - fused0 : 0);  // launched passes of this step that did
+                                                                    // work (fused0: the first came with the block)
+      }
+    }
+  }
+  __syncthreads();
+  const Selection r = choice;
+  if (!r.valid) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const TK k = Kc[i * ldc + s.slot];
-    o[i] += s.s * (double)k;
-    KXJ[i * ldk + s.pos] = k;
+    const TK k = Kc[i * ldc + r.slot];
+    o[i] += r.s * (double)k;
+    KXJ[i * ldk + r.pos] = k;
   }
 }
 
@@ -335,11 +345,9 @@ template <typename TK>
 void launch_select_append(const CandState* st, const uint64_t* hash, uint64_t* stage_hash, int q, const TK* Kc,
                           int64_t ldc, int64_t n, double* o, TK* KXJ, int64_t ldk, int64_t* J, double* beta,
                           int32_t* m_dev, Selection* sel, int32_t* incomplete, int fused0, hipStream_t s) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(kCandSlots), 0, s, st, hash, stage_hash, q, J, beta, m_dev, sel,
-                     incomplete, fused0);
-  SPSVM_LAUNCHED();
-  const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), 2048);
-  hipLaunchKernelGGL((k_append<TK>), dim3((unsigned)blocks), dim3(256), 0, s, sel, Kc, ldc, n, o, KXJ, ldk);
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 2048));
+  hipLaunchKernelGGL((k_select_append<TK>), dim3((unsigned)blocks), dim3(256), 0, s, st, hash, stage_hash, q, J, beta,
+                     m_dev, sel, incomplete, fused0, Kc, ldc, n, o, KXJ, ldk);
   SPSVM_LAUNCHED();
 }
 

@@ -97,7 +97,7 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.score_part = take((size_t)std::max<int64_t>(nb_s, ceil_div(n, kKblockRows)) * kCandSlots * 4 * 8);
   p.cand_table = take((size_t)cap * kCandSlots * 4);
   p.stage_hash = take(cap * 8);
-  p.m_dev = take(4);
+  p.m_dev = take(8);  // basis size, double-buffered by step parity
   p.flags = take(16);
   p.XJ64 = take((size_t)J_max * p.ldj * 8);
   p.xjnorm = take(J_max * 8);
@@ -813,7 +813,7 @@ struct Impl {
     std::vector<uint64_t> blocked;  // sorted hashes of J's rows
     std::vector<int32_t> table((size_t)opt.chunk_cap * kCandSlots);
     SPSVM_HIP(hipMemsetAsync(o, 0, n * 8, st));
-    SPSVM_HIP(hipMemsetAsync(m_dev, 0, 4, st));
+    SPSVM_HIP(hipMemsetAsync(m_dev, 0, 8, st));
     const int nblk = score_blocks(n);
     int first_rounds = 4;
     while (m < J_max) {
@@ -830,11 +830,14 @@ struct Impl {
       for (int attempt = 0;; ++attempt) {
         // passes launched per step: one more than the most any step of the previous stage needed
         const int rounds = attempt == 0 ? first_rounds : (attempt == 1 ? std::max(2 * first_rounds, 12) : 64);
-        if (attempt > 0) {
-          SPSVM_HIP(hipMemcpyAsync(o, o_stage, n * 8, hipMemcpyDeviceToDevice, st));
+        {
+          // the stage's steps read the basis size at m_dev[q & 1] and leave the next one at m_dev[(q + 1) & 1]
           int32_t* mh = (int32_t*)((char*)pin.p + 8192);
           *mh = m;
           SPSVM_HIP(hipMemcpyAsync(m_dev, mh, 4, hipMemcpyHostToDevice, st));
+        }
+        if (attempt > 0) {
+          SPSVM_HIP(hipMemcpyAsync(o, o_stage, n * 8, hipMemcpyDeviceToDevice, st));
           stats.stage_redos += 1;
         }
         SPSVM_HIP(hipMemsetAsync(incomplete, 0, 12, st));
@@ -882,7 +885,7 @@ struct Impl {
         if (flags2[0] == 0 || rounds >= 64) break;
       }
       t += cs;
-      const int m_new = read(m_dev);
+      const int m_new = read(m_dev + (cs & 1));
       stats.additions += m_new - m;
       if (m_new > m) {
         std::vector<int64_t> jn(m_new - m);
