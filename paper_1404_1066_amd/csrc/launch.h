@@ -113,6 +113,11 @@ template <typename TK>
 void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, const CandState* st,
                        double* partial, int nblk, hipStream_t s);
 void launch_score_update(CandState* st, const double* partial, int nblk, double lam, hipStream_t s);
+// launch_score_init followed by launch_score_update on the nblk records of a first pass that came with the
+// kernel block, as one launch.
+void launch_score_init_update(const int32_t* cand, const double* o, const uint64_t* hash, const uint64_t* stage_hash,
+                              int n_stage, CandState* st, const double* partial, int nblk, double lam,
+                              hipStream_t s);
 // Argmax of the scored slots and its append (one launch). Kc: the step's candidate columns (leading dimension
 // ldc); fused0: its first scoring pass came with the block; m_dev: two ints, step q reads the basis size at
 // m_dev[q & 1] and writes the next at m_dev[(q + 1) & 1].

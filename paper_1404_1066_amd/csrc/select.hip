@@ -267,6 +267,77 @@ void launch_score_update(CandState* st, const double* partial, int nblk, double 
   SPSVM_LAUNCHED();
 }
 
+// Slot set-up and the update after a first pass that came with the kernel block, in one launch: workgroup c
+// sets slot c up as the initialisation kernel does (its 256 threads scan the stage's earlier winners at once),
+// then reduces the slot's partial records and advances it as the update kernel does.
+__global__ __launch_bounds__(256) void k_score_init_update(const int32_t* __restrict__ cand,
+                                                           const double* __restrict__ o,
+                                                           const uint64_t* __restrict__ hash,
+                                                           const uint64_t* __restrict__ stage_hash, int n_stage,
+                                                           CandState* __restrict__ st,
+                                                           const double* __restrict__ partial, int nblk,
+                                                           double lam) {
+  __shared__ double red[4][4];
+  __shared__ int taken;
+  const int c = blockIdx.x;
+  const int idx = cand[c];
+  if (threadIdx.x == 0) taken = 0;
+  __syncthreads();
+  if (idx >= 0) {
+    const uint64_t h = hash[idx];
+    for (int q = threadIdx.x; q < n_stage; q += 256)
+      if (stage_hash[q] == h) taken = 1;
+  }
+  __syncthreads();
+  CandState s;
+  s.idx = idx;
+  s.s = 0.0;
+  s.s_prev = 0.0;
+  s.lo = -__builtin_huge_val();
+  s.hi = __builtin_huge_val();
+  s.oc = 0.0;
+  s.score = -__builtin_huge_val();
+  s.newton = 0;
+  s.passes = 0;
+  if (idx < 0 || taken) {
+    s.status = 2;
+    if (threadIdx.x == 0) st[c] = s;
+    return;
+  }
+  s.status = 0;
+  s.oc = o[idx];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+    const doublex4 p = *(const doublex4*)(partial + ((int64_t)b * kCandSlots + c) * 4);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] += p[k];
+  }
+  // the update kernel's order: xor butterflies inside each wave, then the four waves in order
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[w][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+    advance_slot(s, t[0], t[1], t[2], t[3], lam);
+    st[c] = s;
+  }
+}
+
+void launch_score_init_update(const int32_t* cand, const double* o, const uint64_t* hash, const uint64_t* stage_hash,
+                              int n_stage, CandState* st, const double* partial, int nblk, double lam,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_score_init_update, dim3(kCandSlots), dim3(256), 0, s, cand, o, hash, stage_hash, n_stage, st,
+                     partial, nblk, lam);
+  SPSVM_LAUNCHED();
+}
+
+
 // Argmax over the scored slots (strictly larger score wins, equal scores go to the lower training row), then
 // the append: o += s * k_winner and K_XJ[:, pos] = k_winner over all rows. Every workgroup takes the same
 // argmax from the slot states; workgroup 0 alone records it (J, beta, the stage hash, the pass counters and

@@ -858,10 +858,11 @@ struct Impl {
             const int q = q0 + j;
             const int32_t* cq = cand_table + (size_t)q * kCandSlots;
             const TK* Kq = Kc + (size_t)j * kCandSlots;
-            launch_score_init(cq, o, hash, stage_hash, q, cst, sc, st);
             if (j == 0) {
-              launch_score_update(cst, score_part, (int)ceil_div(n, kKblockRows), lam, st);
+              launch_score_init_update(cq, o, hash, stage_hash, q, cst, score_part, (int)ceil_div(n, kKblockRows),
+                                       lam, st);
             } else {
+              launch_score_init(cq, o, hash, stage_hash, q, cst, sc, st);
               prof.timed(kProfScore, (double)n * (opt.kappa * sizeof(TK) + 12.0),
                          [&] { launch_score_pass<TK>(Kq, ldc, y, o, n, cst, score_part, nblk, st); });
               launch_score_update(cst, score_part, nblk, lam, st);
