@@ -134,6 +134,8 @@ void launch_compact(const double* o, const float* y, int64_t n, const uint8_t* a
                     int32_t* I, int32_t* blk_count, double* blk_sum, int32_t* blk_flips, NewtonScalars* sc,
                     hipStream_t s);
 int compact_blocks(int64_t n);
+// Workgroups of a line-search pass over n rows (partial records per workgroup).
+int ls_blocks(int64_t n);
 template <typename TK>
 void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv, const double* o, const float* y,
                      const double* v, const double* beta, double lam, double* partial, int nchunk, double* g,

@@ -112,6 +112,7 @@ __global__ __launch_bounds__(256) void k_compact_write(const double* __restrict_
 }
 
 int compact_blocks(int64_t n) { return (int)std::max<int64_t>(1, ceil_div(n, kCompactRows)); }
+int ls_blocks(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(n, 128))); }
 
 void launch_compact(const double* o, const float* y, int64_t n, const uint8_t* act_ref, uint8_t* act_out, int32_t* I,
                     int32_t* blk_count, double* blk_sum, int32_t* blk_flips, NewtonScalars* sc, hipStream_t s) {

@@ -249,9 +249,12 @@ __device__ __forceinline__ bool bracket_next(double x, double g, double r, doubl
   return nx > lo && nx < hi;
 }
 
+// 128 rows per workgroup up to 1024 workgroups; past that up to 2048 (more rows in flight for long passes;
+// for short ones the cost of reducing more partial records outweighs it).
 int score_blocks(int64_t n) {
-  int64_t b = ceil_div(n, 128);
-  return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+  const int64_t b = ceil_div(n, 128);
+  if (b <= 1024) return (int)(b < 1 ? 1 : b);
+  return (int)std::min<int64_t>(2048, ceil_div(n, 64));
 }
 
 template <typename TK>

@@ -139,7 +139,7 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
     q.Linv = st((size_t)ceil_div(J_max, kCholNB) * kCholNB * kCholNB * 8);
     q.syrk_part = st((batch ? syrk_partial_doubles_batch((int)J_max) : syrk_partial_doubles((int)J_max)) * 8);
     q.grad_part = st((size_t)1024 * 256 * 8);
-    q.ls_part = st((size_t)nb_s * 6 * 8);
+    q.ls_part = st((size_t)ls_blocks(n) * 6 * 8);
     q.vJ = st(J_max * 8);
     q.wJ = st(J_max * 8);
     q.F_in = st(n * 4);
@@ -628,7 +628,7 @@ struct Impl {
       gemv_slots(m, go, &Slot::dvec, &Slot::delta);
       gemv_kjj_slots(m, go, &Slot::dvec, &Slot::wJ);
       for (int q : go) launch_c1c2(slots[q].beta, slots[q].dvec, slots[q].wJ, m, slots[q].ls, st);
-      const int nblk = score_blocks(n);
+      const int nblk = ls_blocks(n);
       std::vector<int> lsq = go;
       int rounds = 0;
       while (!lsq.empty()) {
