@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_potrf_diag(const CholBatch bt, int64_t 
   __shared__ double Rd[SB];
   __shared__ int bad;
   const int nb = m - k0 < NB ? m - k0 : NB;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, i16 = lane & 15;
   if (tid == 0) bad = 0;
   {
     // all 16 loads of this thread in flight before the LDS stores
@@ -107,67 +107,76 @@ __global__ __launch_bounds__(256) void k_potrf_diag(const CholBatch bt, int64_t 
       if (lane == 0 && badl) bad = 1;
     }
     __syncthreads();
-    const int rest = NB - c0 - SB;  // rows below this sub-block
-    if (rest > 0) {
-      // sub-panel: L[r][c0 + c] = sum_q A[r][c0 + q] Dinv[c][q] for rows r >= c0 + 16 (results kept in
-      // registers until every thread has read its row)
-      double v[3];
-      int cnt = 0;
-      for (int e = tid; e < rest * SB; e += 256) {
-        const int r = c0 + SB + e / SB, c = e % SB;
-        double t = 0.0;
-        for (int q = 0; q <= c; ++q) t += A[r][c0 + q] * X[c0 + c][c0 + q];
-        v[cnt++] = t;
-      }
-      __syncthreads();
-      cnt = 0;
-      for (int e = tid; e < rest * SB; e += 256) {
-        const int r = c0 + SB + e / SB, c = e % SB;
-        A[r][c0 + c] = v[cnt++];
-      }
-      __syncthreads();
-      // trailing update of the lower part of rows/columns >= c0 + 16
-      for (int e = tid; e < rest * rest; e += 256) {
-        const int r = c0 + SB + e / rest, c2 = c0 + SB + e % rest;
-        if (c2 > r) continue;
-        double t = 0.0;
+    const int nr = NB / SB - 1 - kb;  // 16-row blocks below this sub-block
+    if (nr > 0) {
+      // sub-panel on FP64 MFMA, one wave per 16-row block i: L_ik = A_ik D_k^{-T}. In a step lane (g, i16)
+      // supplies P[i16][4g + s] and Q[i16][4g + s]; acc[r] ends as (P Q^T)[g + 4r][i16]. Results stay in
+      // registers until every wave has read its block.
+      doublex4 pacc = {0.0, 0.0, 0.0, 0.0};
+      const int ib = kb + 1 + w;
+      if (w < nr) {
 #pragma unroll
-        for (int q = 0; q < SB; ++q) t += A[r][c0 + q] * A[c2][c0 + q];
-        A[r][c2] -= t;
+        for (int s2 = 0; s2 < 4; ++s2)
+          pacc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ib * SB + i16][c0 + 4 * g + s2],
+                                                      X[c0 + i16][c0 + 4 * g + s2], pacc, 0, 0, 0);
+      }
+      __syncthreads();
+      if (w < nr) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) A[ib * SB + g + 4 * r][c0 + i16] = pacc[r];
+      }
+      __syncthreads();
+      // trailing blocks A_ij -= L_ik L_jk^T for kb < j <= i, round robin over the waves (they write columns
+      // right of the sub-panel, which is only read). Diagonal blocks are updated whole; their upper halves
+      // are never read.
+      const int npairs = nr * (nr + 1) / 2;
+      for (int p = w; p < npairs; p += 4) {
+        int ii = 0, jj = p;
+        while (jj > ii) {
+          jj -= ii + 1;
+          ++ii;
+        }
+        const int bi = kb + 1 + ii, bj = kb + 1 + jj;
+        doublex4 t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2)
+          t = __builtin_amdgcn_mfma_f64_16x16x4f64(A[bi * SB + i16][c0 + 4 * g + s2],
+                                                   A[bj * SB + i16][c0 + 4 * g + s2], t, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) A[bi * SB + g + 4 * r][bj * SB + i16] -= t[r];
       }
       __syncthreads();
     }
   }
-  // off-diagonal 16 x 16 blocks of the inverse, one block row b at a time: X_bc = -D_b^{-1} T_bc with
-  // T_bc = sum_{k=c}^{b-1} L_bk X_kc
+  // off-diagonal 16 x 16 blocks of the inverse, one block row b at a time, wave c for block column c:
+  // T_bc = sum_{k=c}^{b-1} L_bk X_kc (written in place of X_bc, which nobody reads yet), then
+  // X_bc = -D_b^{-1} T_bc. For a product P Q lane (g, i16) supplies P[i16][4g + s] and Q[4g + s][i16].
   for (int b = 1; b < NB / SB; ++b) {
-    double v[3];
-    int cnt = 0;
-    for (int e = tid; e < b * SB * SB; e += 256) {  // T for all c < b: rows of block b, columns < 16 b
-      const int i = e / (b * SB), col = e % (b * SB), c = col / SB;
-      double t = 0.0;
-      for (int q = c * SB; q < b * SB; ++q) t += A[b * SB + i][q] * X[q][col];
-      v[cnt++] = t;
+    if (w < b) {
+      const int c = w;
+      doublex4 t = {0.0, 0.0, 0.0, 0.0};
+      for (int k = c; k < b; ++k) {
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2)
+          t = __builtin_amdgcn_mfma_f64_16x16x4f64(A[b * SB + i16][k * SB + 4 * g + s2],
+                                                   X[k * SB + 4 * g + s2][c * SB + i16], t, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) X[b * SB + g + 4 * r][c * SB + i16] = t[r];
     }
     __syncthreads();
-    cnt = 0;
-    for (int e = tid; e < b * SB * SB; e += 256) {
-      const int i = e / (b * SB), col = e % (b * SB);
-      X[b * SB + i][col] = v[cnt++];  // T stored in place of X_bc until it is multiplied below
+    doublex4 u = {0.0, 0.0, 0.0, 0.0};
+    if (w < b) {
+      const int c = w;
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2)
+        u = __builtin_amdgcn_mfma_f64_16x16x4f64(X[b * SB + i16][b * SB + 4 * g + s2],
+                                                 X[b * SB + 4 * g + s2][c * SB + i16], u, 0, 0, 0);
     }
     __syncthreads();
-    cnt = 0;
-    for (int e = tid; e < b * SB * SB; e += 256) {
-      const int i = e / (b * SB), col = e % (b * SB);
-      double t = 0.0;
-      for (int q = 0; q <= i; ++q) t -= X[b * SB + i][b * SB + q] * X[b * SB + q][col];
-      v[cnt++] = t;
-    }
-    __syncthreads();
-    cnt = 0;
-    for (int e = tid; e < b * SB * SB; e += 256) {
-      const int i = e / (b * SB), col = e % (b * SB);
-      X[b * SB + i][col] = v[cnt++];
+    if (w < b) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) X[b * SB + g + 4 * r][w * SB + i16] = -u[r];
     }
     __syncthreads();
   }
