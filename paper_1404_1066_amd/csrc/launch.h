@@ -217,11 +217,27 @@ int syrk_splits_batch(int ntiles, int n_rows);
 constexpr int kSyrkBatchSplits = 2;
 size_t syrk_partial_doubles(int m_max);
 size_t syrk_partial_doubles_batch(int m_max);
-void launch_c1c2(const double* beta, const double* dvec, const double* w, int m, LineState* ls, hipStream_t s);
-void launch_ls_round(const double* o, const double* delta, const float* y, int64_t n, double lam, LineState* ls,
-                     double* partial, int nblk, hipStream_t s);
-void launch_apply_step(const LineState* ls, double* beta, const double* dvec, int m, double* o, const double* delta,
-                       int64_t n, hipStream_t s);
+// Exact line search of up to kMaxBatch problems per launch (grid dimension = slot): per slot the margins o, the
+// step delta = K_XJ d, the labels, the line state, the pass partials (ls_blocks(n) x 6 doubles), lambda, and for
+// the set-up and the step: beta, d and w = K_JJ d (the step updates beta and o in place).
+struct LsBatch {
+  double* o[kMaxBatch];
+  const double* delta[kMaxBatch];
+  const float* y[kMaxBatch];
+  LineState* ls[kMaxBatch];
+  double* partial[kMaxBatch];
+  double lam[kMaxBatch];
+  double* beta[kMaxBatch];
+  const double* dvec[kMaxBatch];
+  const double* w[kMaxBatch];
+  int count;
+};
+// c1 = beta . w, c2 = d . w and a fresh line state.
+void launch_c1c2_batch(const LsBatch& b, int m, hipStream_t s);
+// One pass over the rows and one update of the line state.
+void launch_ls_round_batch(const LsBatch& b, int64_t n, int nblk, hipStream_t s);
+// beta += t d, o += t delta with the final step t.
+void launch_apply_step_batch(const LsBatch& b, int m, int64_t n, hipStream_t s);
 void launch_scale(double* v, int m, double a, hipStream_t s);
 
 // ------------------------------------------------------------------------------------------- chol.hip

@@ -867,8 +867,13 @@ void launch_trace(const double* H, int64_t ldh, int m, NewtonScalars* sc, hipStr
 // ---------------------------------------------------------------------------------------- line search
 // phi(t) = f(beta + t d) = const + lambda (t c1 + t^2 c2 / 2) + 1/2 sum max(0, a_i - t b_i)^2,
 // a_i = 1 - y_i o_i, b_i = y_i delta_i, delta = K_XJ d, c1 = beta^T K_JJ d, c2 = d^T K_JJ d (from w = K_JJ d).
-__global__ __launch_bounds__(256) void k_c1c2(const double* __restrict__ beta, const double* __restrict__ dvec,
-                                              const double* __restrict__ w, int m, LineState* ls) {
+// Grid x = slot of the batch.
+__global__ __launch_bounds__(256) void k_c1c2(const LsBatch bt, int m) {
+  const int q = blockIdx.x;
+  const double* __restrict__ beta = bt.beta[q];
+  const double* __restrict__ dvec = bt.dvec[q];
+  const double* __restrict__ w = bt.w[q];
+  LineState* ls = bt.ls[q];
   __shared__ double rd[4];
   double a = 0.0, b = 0.0;
   for (int k = threadIdx.x; k < m; k += 256) {
@@ -894,16 +899,23 @@ __global__ __launch_bounds__(256) void k_c1c2(const double* __restrict__ beta, c
   }
 }
 
-void launch_c1c2(const double* beta, const double* dvec, const double* w, int m, LineState* ls, hipStream_t s) {
-  hipLaunchKernelGGL(k_c1c2, dim3(1), dim3(256), 0, s, beta, dvec, w, m, ls);
+void launch_c1c2_batch(const LsBatch& b, int m, hipStream_t s) {
+  if (b.count <= 0) return;
+  if (b.count > kMaxBatch) throw Failure(1, "line-search batch: too many slots");
+  hipLaunchKernelGGL(k_c1c2, dim3(b.count), dim3(256), 0, s, b, m);
   SPSVM_LAUNCHED();
 }
 
 // Pass 0 evaluates t = 0 and t = 1 (slots A and B); later passes evaluate t (slot B) with flips against t_prev.
 // Partial record per block: {P_A, Q_A, P_B, Q_B, V_B, flips}.
-__global__ __launch_bounds__(256) void k_ls_pass(const double* __restrict__ o, const double* __restrict__ delta,
-                                                 const float* __restrict__ y, int64_t n, int64_t rows_per_blk,
-                                                 const LineState* __restrict__ ls, double* __restrict__ partial) {
+// Grid y = slot of the batch.
+__global__ __launch_bounds__(256) void k_ls_pass(const LsBatch bt, int64_t n, int64_t rows_per_blk) {
+  const int q = blockIdx.y;
+  const double* __restrict__ o = bt.o[q];
+  const double* __restrict__ delta = bt.delta[q];
+  const float* __restrict__ y = bt.y[q];
+  const LineState* __restrict__ ls = bt.ls[q];
+  double* __restrict__ partial = bt.partial[q];
   __shared__ double rd[4];
   if (ls->status != 0) return;
   const bool first = ls->passes == 0;
@@ -936,8 +948,12 @@ __global__ __launch_bounds__(256) void k_ls_pass(const double* __restrict__ o, c
   }
 }
 
-__global__ __launch_bounds__(256) void k_ls_update(LineState* ls, const double* __restrict__ partial, int nblk,
-                                                   double lam) {
+// Grid x = slot of the batch.
+__global__ __launch_bounds__(256) void k_ls_update(const LsBatch bt, int nblk) {
+  const int q = blockIdx.x;
+  LineState* ls = bt.ls[q];
+  const double* __restrict__ partial = bt.partial[q];
+  const double lam = bt.lam[q];
   __shared__ double red[6][256];
   if (ls->status != 0) return;
   {
@@ -1036,29 +1052,35 @@ __global__ __launch_bounds__(256) void k_ls_update(LineState* ls, const double* 
   *ls = s;
 }
 
-void launch_ls_round(const double* o, const double* delta, const float* y, int64_t n, double lam, LineState* ls,
-                     double* partial, int nblk, hipStream_t s) {
+void launch_ls_round_batch(const LsBatch& b, int64_t n, int nblk, hipStream_t s) {
+  if (b.count <= 0) return;
+  if (b.count > kMaxBatch) throw Failure(1, "line-search batch: too many slots");
   const int64_t rows = ceil_div(n, nblk);
-  hipLaunchKernelGGL(k_ls_pass, dim3(nblk), dim3(256), 0, s, o, delta, y, n, rows, ls, partial);
+  hipLaunchKernelGGL(k_ls_pass, dim3(nblk, b.count), dim3(256), 0, s, b, n, rows);
   SPSVM_LAUNCHED();
-  hipLaunchKernelGGL(k_ls_update, dim3(1), dim3(256), 0, s, ls, partial, nblk, lam);
+  hipLaunchKernelGGL(k_ls_update, dim3(b.count), dim3(256), 0, s, b, nblk);
   SPSVM_LAUNCHED();
 }
 
-__global__ __launch_bounds__(256) void k_apply_step(const LineState* __restrict__ ls, double* __restrict__ beta,
-                                                    const double* __restrict__ dvec, int m, double* __restrict__ o,
-                                                    const double* __restrict__ delta, int64_t n) {
-  const double t = ls->t;
+// Grid y = slot of the batch.
+__global__ __launch_bounds__(256) void k_apply_step(const LsBatch bt, int m, int64_t n) {
+  const int q = blockIdx.y;
+  double* __restrict__ beta = bt.beta[q];
+  const double* __restrict__ dvec = bt.dvec[q];
+  double* __restrict__ o = bt.o[q];
+  const double* __restrict__ delta = bt.delta[q];
+  const double t = bt.ls[q]->t;
   if (t == 0.0) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) o[i] += t * delta[i];
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += stride) beta[k] += t * dvec[k];
 }
 
-void launch_apply_step(const LineState* ls, double* beta, const double* dvec, int m, double* o, const double* delta,
-                       int64_t n, hipStream_t s) {
+void launch_apply_step_batch(const LsBatch& b, int m, int64_t n, hipStream_t s) {
+  if (b.count <= 0) return;
+  if (b.count > kMaxBatch) throw Failure(1, "line-search batch: too many slots");
   const int64_t blocks = std::min<int64_t>(ceil_div(std::max<int64_t>(n, m), 256), 2048);
-  hipLaunchKernelGGL(k_apply_step, dim3((unsigned)blocks), dim3(256), 0, s, ls, beta, dvec, m, o, delta, n);
+  hipLaunchKernelGGL(k_apply_step, dim3((unsigned)blocks, b.count), dim3(256), 0, s, b, m, n);
   SPSVM_LAUNCHED();
 }
 

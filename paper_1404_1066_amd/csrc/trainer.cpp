@@ -627,14 +627,32 @@ struct Impl {
       }
       gemv_slots(m, go, &Slot::dvec, &Slot::delta);
       gemv_kjj_slots(m, go, &Slot::dvec, &Slot::wJ);
-      for (int q : go) launch_c1c2(slots[q].beta, slots[q].dvec, slots[q].wJ, m, slots[q].ls, st);
+      // line search: all unfinished slots in each launch (up to kMaxBatch)
+      auto ls_batch = [&](const std::vector<int>& ids, size_t a) {
+        LsBatch b{};
+        for (size_t k = a; k < ids.size() && k < a + kMaxBatch; ++k) {
+          Slot& S = slots[ids[k]];
+          const int c = b.count++;
+          b.o[c] = S.o;
+          b.delta[c] = S.delta;
+          b.y[c] = S.y;
+          b.ls[c] = S.ls;
+          b.partial[c] = S.ls_part;
+          b.lam[c] = S.lam;
+          b.beta[c] = S.beta;
+          b.dvec[c] = S.dvec;
+          b.w[c] = S.wJ;
+        }
+        return b;
+      };
+      for (size_t a = 0; a < go.size(); a += kMaxBatch) launch_c1c2_batch(ls_batch(go, a), m, st);
       const int nblk = ls_blocks(n);
       std::vector<int> lsq = go;
       int rounds = 0;
       while (!lsq.empty()) {
-        for (int q : lsq) {
-          Slot& S = slots[q];
-          for (int r = 0; r < 3; ++r) launch_ls_round(S.o, S.delta, S.y, n, S.lam, S.ls, S.ls_part, nblk, st);
+        for (size_t a = 0; a < lsq.size(); a += kMaxBatch) {
+          const LsBatch b = ls_batch(lsq, a);
+          for (int r = 0; r < 3; ++r) launch_ls_round_batch(b, n, nblk, st);
         }
         rounds += 3;
         read_slot_lines();
@@ -643,11 +661,11 @@ struct Impl {
           if (slots[q].L.status == 0 && rounds < 66) keep.push_back(q);
         lsq.swap(keep);
       }
+      for (size_t a = 0; a < go.size(); a += kMaxBatch) launch_apply_step_batch(ls_batch(go, a), m, n, st);
       act.clear();
       for (int q : go) {
         Slot& S = slots[q];
         S.stats->ls_passes += S.L.passes;
-        launch_apply_step(S.ls, S.beta, S.dvec, m, S.o, S.delta, n, st);
         S.it += 1;
         if (S.L.t == 0.0 || S.L.dec <= opt.newton_ftol * S.f || S.it >= opt.newton_max_iter) {
           finish(S);
