@@ -18,6 +18,11 @@ struct CandState {
 };
 constexpr int kCandSlots = 64;
 
+// Batched launches: up to kMaxBatch independent problems (slots) per launch, one grid z-index per slot; the
+// per-slot operands travel by value in the kernel arguments. 48 covers the 40 problems of one kernel width in
+// a one-vs-rest x C sweep with a single launch per step, and keeps the largest argument block near 3 KB.
+constexpr int kMaxBatch = 48;
+
 // Result of a selection step.
 struct Selection {
   double s;       // coefficient of the new basis vector
@@ -133,6 +138,20 @@ void launch_gemv(const TK* K, int64_t ldk, int64_t n, int m, const double* x, do
 void launch_compact(const double* o, const float* y, int64_t n, const uint8_t* act_ref, uint8_t* act_out,
                     int32_t* I, int32_t* blk_count, double* blk_sum, int32_t* blk_flips, NewtonScalars* sc,
                     hipStream_t s);
+// The same for up to kMaxBatch problems per launch (grid y = slot), one entry per problem.
+struct CompactBatch {
+  const double* o[kMaxBatch];
+  const float* y[kMaxBatch];
+  const uint8_t* act_ref[kMaxBatch];
+  uint8_t* act_out[kMaxBatch];
+  int32_t* I[kMaxBatch];
+  int32_t* cnt[kMaxBatch];
+  double* bsum[kMaxBatch];
+  int32_t* bflips[kMaxBatch];
+  NewtonScalars* sc[kMaxBatch];
+  int count;
+};
+void launch_compact_batch(const CompactBatch& b, int64_t n, hipStream_t s);
 int compact_blocks(int64_t n);
 // Workgroups of a line-search pass over n rows (partial records per workgroup).
 int ls_blocks(int64_t n);
@@ -141,10 +160,6 @@ void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv
                      const double* v, const double* beta, double lam, double* partial, int nchunk, double* g,
                      NewtonScalars* sc, hipStream_t s);
 int gradient_chunks(int m, int n_sv);
-// Batched launches: up to kMaxBatch independent problems (slots) per launch, one grid z-index per slot; the
-// per-slot operands travel by value in the kernel arguments. 48 covers the 40 problems of one kernel width in
-// a one-vs-rest x C sweep with a single launch per step, and keeps the largest argument block near 3 KB.
-constexpr int kMaxBatch = 48;
 
 // out_q = K x_q for up to kMaxBatch vectors x_q (m FP64 values each, 32-byte aligned) with one read of K
 // (n x m, leading dimension ldk a multiple of 4, rows 16-byte aligned). FP64 MFMA, exact products.
@@ -205,8 +220,20 @@ void launch_add_diag(double* H, int64_t ldh, int m, double v, hipStream_t s);
 // Lower triangle: H = lam * KJJ + G (all m x m, leading dimension ldh).
 void launch_scaled_sum_lower(double* H, const double* KJJ, const double* G, double lam, int m, int64_t ldh,
                              hipStream_t s);
-void launch_flip_lists(const uint8_t* act_new, const uint8_t* act_old, int64_t n, int32_t* cnt_in, int32_t* cnt_out,
-                       int32_t* F_in, int32_t* F_out, NewtonScalars* sc, hipStream_t s);
+// Rows that joined (act_new and not act_old) and left the violator set, listed in ascending order, for up to
+// kMaxBatch problems per launch; per-workgroup counts in cnt_in / cnt_out (compact_blocks(n) each), totals in
+// the scalars (n_in, n_out).
+struct FlipBatch {
+  const uint8_t* act_new[kMaxBatch];
+  const uint8_t* act_old[kMaxBatch];
+  int32_t* cnt_in[kMaxBatch];
+  int32_t* cnt_out[kMaxBatch];
+  int32_t* F_in[kMaxBatch];
+  int32_t* F_out[kMaxBatch];
+  NewtonScalars* sc[kMaxBatch];
+  int count;
+};
+void launch_flip_lists_batch(const FlipBatch& b, int64_t n, hipStream_t s);
 void launch_trace(const double* H, int64_t ldh, int m, NewtonScalars* sc, hipStream_t s);
 int syrk_tiles(int m);
 int syrk_tile_rows(int m);

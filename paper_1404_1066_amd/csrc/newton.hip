@@ -38,10 +38,15 @@ void launch_gemv(const TK* K, int64_t ldk, int64_t n, int m, const double* x, do
 constexpr int kCompactRows = 4096;  // rows per block: 16 chunks of 256
 
 
-__global__ __launch_bounds__(256) void k_compact_count(const double* __restrict__ o, const float* __restrict__ y,
-                                                       int64_t n, const uint8_t* __restrict__ act_ref,
-                                                       int32_t* __restrict__ cnt, double* __restrict__ bsum,
-                                                       int32_t* __restrict__ bflips) {
+// Grid y = slot of the batch.
+__global__ __launch_bounds__(256) void k_compact_count(const CompactBatch bt, int64_t n) {
+  const int q = blockIdx.y;
+  const double* __restrict__ o = bt.o[q];
+  const float* __restrict__ y = bt.y[q];
+  const uint8_t* __restrict__ act_ref = bt.act_ref[q];
+  int32_t* __restrict__ cnt = bt.cnt[q];
+  double* __restrict__ bsum = bt.bsum[q];
+  int32_t* __restrict__ bflips = bt.bflips[q];
   __shared__ double rd[4];
   __shared__ int ri[4];
   const int64_t lo = (int64_t)blockIdx.x * kCompactRows;
@@ -67,12 +72,17 @@ __global__ __launch_bounds__(256) void k_compact_count(const double* __restrict_
   }
 }
 
-__global__ __launch_bounds__(256) void k_compact_write(const double* __restrict__ o, const float* __restrict__ y,
-                                                       int64_t n, const int32_t* __restrict__ cnt,
-                                                       const double* __restrict__ bsum,
-                                                       const int32_t* __restrict__ bflips, int nblk,
-                                                       uint8_t* __restrict__ act_out, int32_t* __restrict__ I,
-                                                       NewtonScalars* sc) {
+// Grid y = slot of the batch.
+__global__ __launch_bounds__(256) void k_compact_write(const CompactBatch bt, int64_t n, int nblk) {
+  const int q = blockIdx.y;
+  const double* __restrict__ o = bt.o[q];
+  const float* __restrict__ y = bt.y[q];
+  const int32_t* __restrict__ cnt = bt.cnt[q];
+  const double* __restrict__ bsum = bt.bsum[q];
+  const int32_t* __restrict__ bflips = bt.bflips[q];
+  uint8_t* __restrict__ act_out = bt.act_out[q];
+  int32_t* __restrict__ I = bt.I[q];
+  NewtonScalars* sc = bt.sc[q];
   __shared__ int ri[4];
   __shared__ int wc[4];
   int part = 0;
@@ -114,14 +124,30 @@ __global__ __launch_bounds__(256) void k_compact_write(const double* __restrict_
 int compact_blocks(int64_t n) { return (int)std::max<int64_t>(1, ceil_div(n, kCompactRows)); }
 int ls_blocks(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(n, 128))); }
 
+void launch_compact_batch(const CompactBatch& b, int64_t n, hipStream_t s) {
+  if (b.count <= 0) return;
+  if (b.count > kMaxBatch) throw Failure(1, "compaction batch: too many slots");
+  const int nblk = compact_blocks(n);
+  hipLaunchKernelGGL(k_compact_count, dim3(nblk, b.count), dim3(256), 0, s, b, n);
+  SPSVM_LAUNCHED();
+  hipLaunchKernelGGL(k_compact_write, dim3(nblk, b.count), dim3(256), 0, s, b, n, nblk);
+  SPSVM_LAUNCHED();
+}
+
 void launch_compact(const double* o, const float* y, int64_t n, const uint8_t* act_ref, uint8_t* act_out, int32_t* I,
                     int32_t* blk_count, double* blk_sum, int32_t* blk_flips, NewtonScalars* sc, hipStream_t s) {
-  const int nblk = compact_blocks(n);
-  hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(256), 0, s, o, y, n, act_ref, blk_count, blk_sum, blk_flips);
-  SPSVM_LAUNCHED();
-  hipLaunchKernelGGL(k_compact_write, dim3(nblk), dim3(256), 0, s, o, y, n, blk_count, blk_sum, blk_flips, nblk,
-                     act_out, I, sc);
-  SPSVM_LAUNCHED();
+  CompactBatch b{};
+  b.o[0] = o;
+  b.y[0] = y;
+  b.act_ref[0] = act_ref;
+  b.act_out[0] = act_out;
+  b.I[0] = I;
+  b.cnt[0] = blk_count;
+  b.bsum[0] = blk_sum;
+  b.bflips[0] = blk_flips;
+  b.sc[0] = sc;
+  b.count = 1;
+  launch_compact_batch(b, n, s);
 }
 
 // -------------------------------------------------------------------------------------------- gradient
@@ -768,9 +794,13 @@ void launch_gradient_batch(const TK* K, int64_t ldk, int64_t n, int m, const Gra
 // --------------------------------------------------------------------------------------- flipped rows
 // Lists of rows whose violator status differs between act_new and act_old: joined (new 1, old 0) and left
 // (new 0, old 1), each in ascending order. Same block scheme as the violator compaction.
-__global__ __launch_bounds__(256) void k_flip_count(const uint8_t* __restrict__ act_new,
-                                                    const uint8_t* __restrict__ act_old, int64_t n,
-                                                    int32_t* __restrict__ cnt_in, int32_t* __restrict__ cnt_out) {
+// Grid y = slot of the batch.
+__global__ __launch_bounds__(256) void k_flip_count(const FlipBatch bt, int64_t n) {
+  const int q = blockIdx.y;
+  const uint8_t* __restrict__ act_new = bt.act_new[q];
+  const uint8_t* __restrict__ act_old = bt.act_old[q];
+  int32_t* __restrict__ cnt_in = bt.cnt_in[q];
+  int32_t* __restrict__ cnt_out = bt.cnt_out[q];
   __shared__ int ri[4];
   const int64_t lo = (int64_t)blockIdx.x * kCompactRows;
   int a = 0, b = 0;
@@ -789,12 +819,16 @@ __global__ __launch_bounds__(256) void k_flip_count(const uint8_t* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(256) void k_flip_write(const uint8_t* __restrict__ act_new,
-                                                    const uint8_t* __restrict__ act_old, int64_t n,
-                                                    const int32_t* __restrict__ cnt_in,
-                                                    const int32_t* __restrict__ cnt_out, int nblk,
-                                                    int32_t* __restrict__ F_in, int32_t* __restrict__ F_out,
-                                                    NewtonScalars* sc) {
+// Grid y = slot of the batch.
+__global__ __launch_bounds__(256) void k_flip_write(const FlipBatch bt, int64_t n, int nblk) {
+  const int q = blockIdx.y;
+  const uint8_t* __restrict__ act_new = bt.act_new[q];
+  const uint8_t* __restrict__ act_old = bt.act_old[q];
+  const int32_t* __restrict__ cnt_in = bt.cnt_in[q];
+  const int32_t* __restrict__ cnt_out = bt.cnt_out[q];
+  int32_t* __restrict__ F_in = bt.F_in[q];
+  int32_t* __restrict__ F_out = bt.F_out[q];
+  NewtonScalars* sc = bt.sc[q];
   __shared__ int ri[4];
   __shared__ int wc[2][4];
   int pa = 0, pb = 0;
@@ -841,13 +875,13 @@ __global__ __launch_bounds__(256) void k_flip_write(const uint8_t* __restrict__ 
   }
 }
 
-void launch_flip_lists(const uint8_t* act_new, const uint8_t* act_old, int64_t n, int32_t* cnt_in, int32_t* cnt_out,
-                       int32_t* F_in, int32_t* F_out, NewtonScalars* sc, hipStream_t s) {
+void launch_flip_lists_batch(const FlipBatch& b, int64_t n, hipStream_t s) {
+  if (b.count <= 0) return;
+  if (b.count > kMaxBatch) throw Failure(1, "flip-list batch: too many slots");
   const int nblk = compact_blocks(n);
-  hipLaunchKernelGGL(k_flip_count, dim3(nblk), dim3(256), 0, s, act_new, act_old, n, cnt_in, cnt_out);
+  hipLaunchKernelGGL(k_flip_count, dim3(nblk, b.count), dim3(256), 0, s, b, n);
   SPSVM_LAUNCHED();
-  hipLaunchKernelGGL(k_flip_write, dim3(nblk), dim3(256), 0, s, act_new, act_old, n, cnt_in, cnt_out, nblk, F_in,
-                     F_out, sc);
+  hipLaunchKernelGGL(k_flip_write, dim3(nblk, b.count), dim3(256), 0, s, b, n, nblk);
   SPSVM_LAUNCHED();
 }
 

@@ -578,10 +578,22 @@ struct Impl {
     const int first = ids[0];
     int first_its = 0;
     while (!act.empty()) {
-      for (int q : act) {
-        Slot& S = slots[q];
-        launch_compact(S.o, S.y, n, S.hb_valid ? S.act_fact : nullptr, S.act_cur, S.I, S.cblk_cnt, S.cblk_sum,
-                       S.cblk_flips, S.sc, st);
+      for (size_t a = 0; a < act.size(); a += kMaxBatch) {
+        CompactBatch cb{};
+        for (size_t k = a; k < act.size() && k < a + kMaxBatch; ++k) {
+          Slot& S = slots[act[k]];
+          const int c = cb.count++;
+          cb.o[c] = S.o;
+          cb.y[c] = S.y;
+          cb.act_ref[c] = S.hb_valid ? S.act_fact : nullptr;
+          cb.act_out[c] = S.act_cur;
+          cb.I[c] = S.I;
+          cb.cnt[c] = S.cblk_cnt;
+          cb.bsum[c] = S.cblk_sum;
+          cb.bflips[c] = S.cblk_flips;
+          cb.sc[c] = S.sc;
+        }
+        launch_compact_batch(cb, n, st);
       }
       read_slots();
       gradient_slots(m, act);
@@ -689,15 +701,25 @@ struct Impl {
     if (ids.empty()) return;
     const int B = syrk_tile_size();
     const int T = syrk_tile_rows(m), ntile = T * (T + 1) / 2;
-    bool any = false;
-    for (int q : ids) {
-      Slot& S = slots[q];
-      if (S.hb_valid) {
-        launch_flip_lists(S.act_cur, S.act_fact, n, S.fcnt_in, S.fcnt_out, S.F_in, S.F_out, S.sc, st);
-        any = true;
+    std::vector<int> fl;
+    for (int q : ids)
+      if (slots[q].hb_valid) fl.push_back(q);
+    for (size_t a = 0; a < fl.size(); a += kMaxBatch) {
+      FlipBatch fb{};
+      for (size_t k = a; k < fl.size() && k < a + kMaxBatch; ++k) {
+        Slot& S = slots[fl[k]];
+        const int c = fb.count++;
+        fb.act_new[c] = S.act_cur;
+        fb.act_old[c] = S.act_fact;
+        fb.cnt_in[c] = S.fcnt_in;
+        fb.cnt_out[c] = S.fcnt_out;
+        fb.F_in[c] = S.F_in;
+        fb.F_out[c] = S.F_out;
+        fb.sc[c] = S.sc;
       }
+      launch_flip_lists_batch(fb, n, st);
     }
-    if (any) read_slots();
+    if (!fl.empty()) read_slots();
     for (int q : ids) {
       Slot& S = slots[q];
       S.tr0 = 0;
