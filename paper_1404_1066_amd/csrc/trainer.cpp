@@ -51,7 +51,7 @@ void draw_step(uint64_t seed, int64_t t, int64_t n, int kappa, const std::vector
 // X (d values per row for 64 columns); the column tiles of several steps of a stage (all drawn at its start)
 // then share each row slab of X through L2. The first scoring pass is launched for all but the first step.
 int cand_group(int64_t d, int64_t chunk_cap) {
-  return (int)std::min<int64_t>(d >= 256 ? 8 : 1, std::max<int64_t>(chunk_cap, 1));
+  return (int)std::min<int64_t>(d >= 256 ? 16 : 1, std::max<int64_t>(chunk_cap, 1));
 }
 
 int64_t stage_size(int64_t J, int64_t J_max, double growth, int64_t cap) {
