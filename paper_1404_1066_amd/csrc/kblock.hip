@@ -241,7 +241,8 @@ struct Score0Acc {
     }
   }
   // partial records for every column of the block (64 columns): waves w * wpr .. w * wpr + wpr - 1 (each
-  // covering 128 / wpr rows) form record rec0 + w; records at or past nrec are not written
+  // covering 128 / wpr rows) form record rec0 + w; records at or past nrec are not written. Records are kept
+  // slot-major (all nrec records of a column together), so the per-slot reduction reads them contiguously.
   __device__ __forceinline__ void finish(double* __restrict__ partial, int64_t rec0, int64_t nrec, int wpr,
                                          double (*red)[64][2]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -264,7 +265,7 @@ struct Score0Acc {
         p += red[grp * wpr + v][c][0];
         q += red[grp * wpr + v][c][1];
       }
-      double* out = partial + ((rec0 + grp) * 64 + c) * 4;
+      double* out = partial + ((int64_t)c * nrec + rec0 + grp) * 4;  // slot-major: [slot][record][4]
       out[0] = p;
       out[1] = q;
       out[2] = 0.0;
@@ -383,7 +384,7 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
   }
   if (fused) {
     __shared__ double red[4][64][2];
-    sa.finish(s0.partial, tile.r, tile.r + 1, 4, red);
+    sa.finish(s0.partial, tile.r, ceil_div_dev(n, kKblockRows), 4, red);
   }
 }
 

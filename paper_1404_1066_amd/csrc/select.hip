@@ -182,7 +182,7 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score_pass(const TK* __res
   sh[q][3][c] = F;
   __syncthreads();
   if (q == 0) {
-    double* out = partial + ((int64_t)blockIdx.x * kCandSlots + c) * 4;
+    double* out = partial + ((int64_t)c * gridDim.x + blockIdx.x) * 4;  // slot-major: [slot][record][4]
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       double t = sh[0][k][c];
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_score_update(CandState* __restrict__ st
   if (st[c].status != 0) return;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblk; b += 256) {
-    const doublex4 p = *(const doublex4*)(partial + ((int64_t)b * kCandSlots + c) * 4);
+    const doublex4 p = *(const doublex4*)(partial + ((int64_t)c * nblk + b) * 4);
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] += p[k];
   }
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256) void k_score_init_update(const int32_t* __rest
   s.oc = o[idx];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblk; b += 256) {
-    const doublex4 p = *(const doublex4*)(partial + ((int64_t)b * kCandSlots + c) * 4);
+    const doublex4 p = *(const doublex4*)(partial + ((int64_t)c * nblk + b) * 4);
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] += p[k];
   }
