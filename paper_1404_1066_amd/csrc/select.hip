@@ -100,51 +100,66 @@ __device__ __forceinline__ int advance_slot(CandState& s, double P, double Q, do
   return still;
 }
 
-// One pass over the rows for every active slot. Thread (wave q, lane c) handles slot c on rows lo + q,
-// lo + q + kScoreWaves, ... of its workgroup's range, eight rows per iteration into two sets of sums; the waves'
-// sums are added in wave order and written as this workgroup's partial record {P, Q, V, flips} per slot.
+// One pass over the rows for the slots still being scored (na of the 64). The live slots are packed onto the
+// lanes: with R = 64 / na rows per wave step, lane r * na + a (r < R) takes live slot a on rows
+// lo + q R + r + m kScoreWaves R of its workgroup's range (wave q), so late passes with few live slots touch
+// each row once per live slot instead of once per lane. Eight steps per iteration have their loads issued
+// together, even steps summed apart from odd ones. The per-lane sums are added over the waves, then over r, in
+// a fixed order, and written as this workgroup's record {P, Q, V, flips} of each live slot.
 template <typename TK>
-__global__ __launch_bounds__(64 * kScoreWaves) void k_score_pass(const TK* __restrict__ Kc, int64_t ldc,
+__global__ __launch_bounds__(64 * kScoreWaves, 6) void k_score_pass(const TK* __restrict__ Kc, int64_t ldc,
                                                                   const float* __restrict__ y,
                                                                   const double* __restrict__ o, int64_t n,
                                                                   int64_t rows_per_blk,
                                                                   const CandState* __restrict__ st,
                                                                   double* __restrict__ partial) {
   __shared__ double sh[kScoreWaves][4][kCandSlots];
-  const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int status = st[c].status;
-  if (!__any(status == 0)) return;  // every slot is settled (same answer in every wave and workgroup)
+  __shared__ double red[4][kCandSlots];
+  __shared__ int act[kCandSlots];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const bool live = st[lane].status == 0;
+  const unsigned long long mask = __ballot(live);
+  const int na = __popcll(mask);
+  if (na == 0) return;  // every slot is settled (same answer in every wave and workgroup)
+  if (q == 0 && live) act[__popcll(mask & ((1ull << lane) - 1ull))] = lane;
+  __syncthreads();
+  const int R = kCandSlots / na, r = lane / na, a = lane - r * na;
   double P = 0.0, Q = 0.0, V = 0.0, F = 0.0;
-  if (status == 0) {
+  if (r < R) {
+    const int c = act[a];
     const double s = st[c].s, sp = st[c].s_prev;
     const bool chk = st[c].passes > 0;
     const int64_t lo = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t hi = lo + rows_per_blk < n ? lo + rows_per_blk : n;
+    const int64_t step = (int64_t)kScoreWaves * R;
     double P2 = 0.0, Q2 = 0.0, V2 = 0.0;
     int fl = 0, fl2 = 0;
-    int64_t i = lo + q;
-    // eight rows per iteration: their loads are issued together, so each wave keeps eight rows in flight;
-    // even rows go to the first set of sums, odd rows to the second
+    int64_t i = lo + q * R + r;
     constexpr int U = 8;
-    for (; i + kScoreWaves * (U - 1) < hi; i += kScoreWaves * U) {
+    const int st32 = (int)step, kst32 = (int)(step * ldc);  // 32-bit offsets inside an iteration
+    for (; i + step * (U - 1) < hi; i += step * U) {
       float yv[U];
-      double ov[U], kv[U];
+      double ov[U];
+      TK kv[U];  // converted where used: a conversion here would wait for the load
+      const float* yp = y + i;
+      const double* op = o + i;
+      const TK* kp = Kc + i * ldc + c;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        yv[u] = y[i + kScoreWaves * u];
-        ov[u] = o[i + kScoreWaves * u];
-        kv[u] = (double)Kc[(i + kScoreWaves * u) * ldc + c];
+        yv[u] = yp[st32 * u];
+        ov[u] = op[st32 * u];
+        kv[u] = kp[kst32 * u];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const double a = margin_gap(yv[u], ov[u]);
-        const double b = (double)yv[u] * kv[u];
-        const double e = a - s * b;
-        const double ua = fmax(a, 0.0), we = fmax(e, 0.0);
-        const int flip = chk && ((e > 0.0) != (a - sp * b > 0.0)) ? 1 : 0;
+        const double av = margin_gap(yv[u], ov[u]);
+        const double b = (double)yv[u] * (double)kv[u];
+        const double e = av - s * b;
+        const double ua = fmax(av, 0.0), we = fmax(e, 0.0);
+        const int flip = chk && ((e > 0.0) != (av - sp * b > 0.0)) ? 1 : 0;
         // selects rather than branches (adding an exact zero leaves a sum unchanged), so that no control flow
         // keeps the compiler from issuing the eight rows' loads together
-        const double pa = e > 0.0 ? a * b : 0.0, qa = e > 0.0 ? b * b : 0.0;
+        const double pa = e > 0.0 ? av * b : 0.0, qa = e > 0.0 ? b * b : 0.0;
         if (u & 1) {
           P2 += pa;
           Q2 += qa;
@@ -158,37 +173,43 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score_pass(const TK* __res
         }
       }
     }
-    for (; i < hi; i += kScoreWaves) {
+    for (; i < hi; i += step) {
       const double yi = (double)y[i];
-      const double a = margin_gap(y[i], o[i]);
+      const double av = margin_gap(y[i], o[i]);
       const double b = yi * (double)Kc[i * ldc + c];
-      const double e = a - s * b;
+      const double e = av - s * b;
       if (e > 0.0) {
-        P += a * b;
+        P += av * b;
         Q += b * b;
       }
-      const double u = fmax(a, 0.0), w = fmax(e, 0.0);
+      const double u = fmax(av, 0.0), w = fmax(e, 0.0);
       V += (w - u) * (w + u);
-      if (chk) fl += ((e > 0.0) != (a - sp * b > 0.0)) ? 1 : 0;
+      if (chk) fl += ((e > 0.0) != (av - sp * b > 0.0)) ? 1 : 0;
     }
     P += P2;
     Q += Q2;
     V += V2;
     F = (double)(fl + fl2);
   }
-  sh[q][0][c] = P;
-  sh[q][1][c] = Q;
-  sh[q][2][c] = V;
-  sh[q][3][c] = F;
+  sh[q][0][lane] = P;
+  sh[q][1][lane] = Q;
+  sh[q][2][lane] = V;
+  sh[q][3][lane] = F;
   __syncthreads();
-  if (q == 0) {
-    double* out = partial + ((int64_t)c * gridDim.x + blockIdx.x) * 4;  // slot-major: [slot][record][4]
+  if (threadIdx.x < 4 * kCandSlots) {  // over the waves, per lane and component
+    const int l = threadIdx.x & 63, k = threadIdx.x >> 6;
+    double t = sh[0][k][l];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      double t = sh[0][k][c];
-#pragma unroll
-      for (int v = 1; v < kScoreWaves; ++v) t += sh[v][k][c];
-      out[k] = t;
+    for (int v = 1; v < kScoreWaves; ++v) t += sh[v][k][l];
+    red[k][l] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4 * kCandSlots) {  // over r, per live slot and component
+    const int aa = threadIdx.x & 63, k = threadIdx.x >> 6;
+    if (aa < na) {
+      double t = red[k][aa];
+      for (int rr = 1; rr < R; ++rr) t += red[k][rr * na + aa];
+      partial[((int64_t)act[aa] * gridDim.x + blockIdx.x) * 4 + k] = t;  // slot-major: [slot][record][4]
     }
   }
 }
