@@ -88,6 +88,7 @@ typedef struct {
   int64_t score_passes;     /* O(n) scoring passes launched after the first, which the candidate block computes
                                (a pass whose slots are all settled exits at once) */
   int64_t score_passes_active; /* launched scoring passes in which some slot was still being scored */
+  int64_t score_slot_passes;   /* sum over those passes of the slots still being scored */
   int64_t ls_passes;        /* O(n) passes spent in exact line searches */
   int64_t iter_cap_hits;    /* re-optimisations stopped by newton_max_iter */
   int64_t stage_redos;      /* selection stages rerun with more scoring passes */
@@ -107,8 +108,9 @@ typedef struct {
   double syrk_flops;        /* n_sv m (m + 1) per launch (lower triangle, multiply-add = 2) */
   int64_t score_launches;   /* timed candidate-score passes over the n rows */
   double score_seconds;
-  double score_bytes;       /* n (kappa sizeof(K) + 12) per timed pass, scaled by the fraction of launched passes
-                               that were active: candidate columns, o (FP64), y (FP32) */
+  double score_bytes;       /* bytes the timed passes had to read: their share (timed / launched) of
+                               n (12 score_passes_active + sizeof(K) score_slot_passes), i.e. o (FP64) and y (FP32)
+                               in every active pass and one candidate column per slot still being scored */
   int64_t chol_calls;       /* timed Cholesky factorisations (all panel kernels of one factorisation) */
   double chol_seconds;
   double chol_flops;        /* m^3 / 3 per factorisation */

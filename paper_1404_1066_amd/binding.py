@@ -73,6 +73,7 @@ class Stats(ctypes.Structure):
         ("factorizations", ctypes.c_int64),
         ("score_passes", ctypes.c_int64),
         ("score_passes_active", ctypes.c_int64),
+        ("score_slot_passes", ctypes.c_int64),
         ("ls_passes", ctypes.c_int64),
         ("iter_cap_hits", ctypes.c_int64),
         ("stage_redos", ctypes.c_int64),

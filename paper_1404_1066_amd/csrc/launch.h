@@ -117,7 +117,8 @@ void launch_score_init(const int32_t* cand, const double* o, const uint64_t* has
 template <typename TK>
 void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, const CandState* st,
                        double* partial, int nblk, hipStream_t s);
-void launch_score_update(CandState* st, const double* partial, int nblk, double lam, hipStream_t s);
+// live (may be null): incremented once per slot that the pass scored (for the byte count of the passes).
+void launch_score_update(CandState* st, const double* partial, int nblk, double lam, int32_t* live, hipStream_t s);
 // launch_score_init followed by launch_score_update on the nblk records of a first pass that came with the
 // kernel block, as one launch.
 void launch_score_init_update(const int32_t* cand, const double* o, const uint64_t* hash, const uint64_t* stage_hash,

@@ -217,10 +217,11 @@ __global__ __launch_bounds__(64 * kScoreWaves, 6) void k_score_pass(const TK* __
 // One workgroup per slot: reduce the slot's partial records over the workgroups of the pass with a fixed
 // tree, then advance the slot.
 __global__ __launch_bounds__(256) void k_score_update(CandState* __restrict__ st, const double* __restrict__ partial,
-                                                      int nblk, double lam) {
+                                                      int nblk, double lam, int32_t* __restrict__ live) {
   __shared__ double red[4][4];
   const int c = blockIdx.x;
   if (st[c].status != 0) return;
+  if (threadIdx.x == 0 && live) atomicAdd(live, 1);  // slot-passes: this slot was read by the pass
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblk; b += 256) {
     const doublex4 p = *(const doublex4*)(partial + ((int64_t)c * nblk + b) * 4);
@@ -286,8 +287,8 @@ void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* 
   SPSVM_LAUNCHED();
 }
 
-void launch_score_update(CandState* st, const double* partial, int nblk, double lam, hipStream_t s) {
-  hipLaunchKernelGGL(k_score_update, dim3(kCandSlots), dim3(256), 0, s, st, partial, nblk, lam);
+void launch_score_update(CandState* st, const double* partial, int nblk, double lam, int32_t* live, hipStream_t s) {
+  hipLaunchKernelGGL(k_score_update, dim3(kCandSlots), dim3(256), 0, s, st, partial, nblk, lam, live);
   SPSVM_LAUNCHED();
 }
 

@@ -880,7 +880,7 @@ struct Impl {
           SPSVM_HIP(hipMemcpyAsync(o, o_stage, n * 8, hipMemcpyDeviceToDevice, st));
           stats.stage_redos += 1;
         }
-        SPSVM_HIP(hipMemsetAsync(incomplete, 0, 12, st));
+        SPSVM_HIP(hipMemsetAsync(incomplete, 0, 16, st));
         const int G = cand_group(d, opt.chunk_cap);
         for (int q0 = 0; q0 < cs; q0 += G) {
           const int gsz = std::min(G, cs - q0);  // steps sharing this kernel-block launch
@@ -905,23 +905,24 @@ struct Impl {
               launch_score_init(cq, o, hash, stage_hash, q, cst, sc, st);
               prof.timed(kProfScore, (double)n * (opt.kappa * sizeof(TK) + 12.0),
                          [&] { launch_score_pass<TK>(Kq, ldc, y, o, n, cst, score_part, nblk, st); });
-              launch_score_update(cst, score_part, nblk, lam, st);
+              launch_score_update(cst, score_part, nblk, lam, incomplete + 3, st);
             }
             for (int r = 1; r < rounds; ++r) {
               prof.timed(kProfScore, (double)n * (opt.kappa * sizeof(TK) + 12.0),
                          [&] { launch_score_pass<TK>(Kq, ldc, y, o, n, cst, score_part, nblk, st); });
-              launch_score_update(cst, score_part, nblk, lam, st);
+              launch_score_update(cst, score_part, nblk, lam, incomplete + 3, st);
             }
             stats.score_passes += rounds - (j == 0 ? 1 : 0);
             launch_select_append<TK>(cst, hash, stage_hash, q, Kq, ldc, n, o, KXJ, p.ldk, J, beta, m_dev, sel,
                                      incomplete, j == 0 ? 1 : 0, st);
           }
         }
-        int32_t flags2[3];
-        SPSVM_HIP(hipMemcpyAsync(pin.p, incomplete, 12, hipMemcpyDeviceToHost, st));
+        int32_t flags2[4];
+        SPSVM_HIP(hipMemcpyAsync(pin.p, incomplete, 16, hipMemcpyDeviceToHost, st));
         sync();
-        std::memcpy(flags2, pin.p, 12);
+        std::memcpy(flags2, pin.p, 16);
         stats.score_passes_active += flags2[2];
+        stats.score_slot_passes += flags2[3];
         first_rounds = std::min(64, std::max(3, flags2[1] + 1));
         if (flags2[0] == 0 || rounds >= 64) break;
       }
@@ -1088,9 +1089,12 @@ struct Impl {
     stats.syrk_flops = prof.work[kProfSyrk];
     stats.score_launches = prof.count[kProfScore];
     stats.score_seconds = prof.seconds[kProfScore];
-    stats.score_bytes = stats.score_passes > 0 ? prof.work[kProfScore] * (double)stats.score_passes_active /
-                                                     (double)stats.score_passes
-                                               : 0.0;
+    // the timed passes' share of what all launched passes read: y and o (12 bytes per row) in every pass that
+    // did work, and one candidate column per slot still being scored
+    stats.score_bytes = stats.score_passes > 0
+                            ? (double)prof.count[kProfScore] / (double)stats.score_passes * (double)n *
+                                  (12.0 * (double)stats.score_passes_active + (double)sizeof(TK) * (double)stats.score_slot_passes)
+                            : 0.0;
     stats.chol_calls = prof.count[kProfChol];
     stats.chol_seconds = prof.seconds[kProfChol];
     stats.chol_flops = prof.work[kProfChol];
