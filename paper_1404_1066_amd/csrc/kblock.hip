@@ -285,7 +285,7 @@ template <typename TX, typename TK>
 __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(const TX* __restrict__ X, int64_t ldx, int64_t n, int64_t d,
                                                       const TK* __restrict__ xnorm, const int32_t* __restrict__ cidx,
                                                       int ncols, TK* __restrict__ out, int64_t ldo, double gamma,
-                                                      const Score0 s0) {
+                                                      const Score0 s0, int cm) {
   using M = Mfma<TK>;
   __shared__ __attribute__((aligned(32))) TK As[KB_BM][KB_LD];
   __shared__ __attribute__((aligned(32))) TK Bs[KB_BN][KB_LD];
@@ -358,14 +358,34 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
         if (FUSED) sa.add(j, ga[i][r], gy[i][r], (double)kv);
       }
     }
+    if (cm) {  // column-major out (column stride ldo)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
-      if (row >= n) continue;
-      TK* orow = out + row * ldo + c0 + (lane & 15);
+      for (int j = 0; j < 4; ++j) {
+        if (!zok[j]) continue;
+        TK* ocol = out + (c0 + j * 16 + (lane & 15)) * ldo;
+        const int64_t rb = r0 + w * 32 + i * 16 + M::row(lane, 0);
+        if constexpr (std::is_same<TK, float>::value) {  // rows rb .. rb + 3: one 16-byte store
+          if (rb + 3 < n) {
+            *(floatx4*)(ocol + rb) = t.acc[i][j];
+            continue;
+          }
+        }
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (zok[j]) orow[j * 16] = t.acc[i][j][r];
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
+          if (row < n) ocol[row] = t.acc[i][j][r];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
+        if (row >= n) continue;
+        TK* orow = out + row * ldo + c0 + (lane & 15);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (zok[j]) orow[j * 16] = t.acc[i][j][r];
+      }
     }
   };
 #pragma unroll
@@ -390,13 +410,15 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
 
 template <typename TX, typename TK>
 void launch_kblock(const TX* X, int64_t ldx, int64_t n, int64_t d, const TK* xnorm, const int32_t* cidx, int ncols,
-                   TK* out, int64_t ldo, double gamma, hipStream_t st, const Score0& s0) {
+                   TK* out, int64_t ldo, double gamma, hipStream_t st, const Score0& s0, bool colmajor) {
   if (n <= 0 || ncols <= 0) return;
   if (ldx % Vec16<TX>::n != 0 || ((uintptr_t)X & 15u))
     throw Failure(1, "kernel block: rows must start on 16-byte boundaries");
   const dim3 grid(xcd_grid(ceil_div(n, KB_BM), ceil_div(ncols, KB_BN)));
+  if (colmajor && (ldo % 4 != 0 || ((uintptr_t)out & 15u)))
+    throw Failure(1, "kernel block: column-major out needs 16-byte aligned columns");
   hipLaunchKernelGGL((k_kblock_store<TX, TK>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out, ldo,
-                     gamma, s0);
+                     gamma, s0, colmajor ? 1 : 0);
   SPSVM_LAUNCHED();
 }
 
@@ -454,7 +476,7 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
                                                      const float* __restrict__ xnorm,
                                                      const int32_t* __restrict__ cidx, int ncols,
                                                      float* __restrict__ out, int64_t ldo, double gamma,
-                                                     const Score0 s0) {
+                                                     const Score0 s0, int cm) {
   constexpr int BM = 64 * RTW;  // rows per workgroup: 4 waves of RTW 16-row tiles
   __shared__ __attribute__((aligned(16))) unsigned short Ah[BM][SB_LD], Bh[KB_BN][SB_LD];
   __shared__ __attribute__((aligned(16))) unsigned short Al[SPLIT ? BM : 1][SB_LD], Bl[SPLIT ? KB_BN : 1][SB_LD];
@@ -585,14 +607,30 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
         if (fused) sa.add(j, ga[i][r], gy[i][r], (double)kv);
       }
     }
+    if (cm) {  // column-major out (column stride ldo): rows rb .. rb + 3 of a column in one 16-byte store
+      const int64_t rb = r0 + w * 16 * RTW + i * 16 + (lane >> 4) * 4;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + w * 16 * RTW + i * 16 + (lane >> 4) * 4 + r;
-      if (row >= n) continue;
-      float* orow = out + row * ldo + c0 + i16;
+      for (int j = 0; j < 4; ++j) {
+        if (!zok[j]) continue;
+        float* ocol = out + (c0 + j * 16 + i16) * ldo;
+        if (rb + 3 < n) {
+          *(floatx4*)(ocol + rb) = acc[i][j];
+        } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (zok[j]) orow[j * 16] = acc[i][j][r];
+          for (int r = 0; r < 4; ++r)
+            if (rb + r < n) ocol[rb + r] = acc[i][j][r];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + w * 16 * RTW + i * 16 + (lane >> 4) * 4 + r;
+        if (row >= n) continue;
+        float* orow = out + row * ldo + c0 + i16;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (zok[j]) orow[j * 16] = acc[i][j][r];
+      }
     }
   }
   if (fused) {
@@ -617,7 +655,7 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
                                                           int64_t n, const float* __restrict__ xnorm,
                                                           const int32_t* __restrict__ cidx, int ncols,
                                                           float* __restrict__ out, int64_t ldo, double gamma,
-                                                          const Score0 s0) {
+                                                          const Score0 s0, int cm) {
   constexpr int BM = 256, BN = 256;
   __shared__ __attribute__((aligned(16))) unsigned short Ah[2][BM][SB_BK], Bh[2][BN][SB_BK];
   __shared__ __attribute__((aligned(16))) unsigned short Al[2][SPLIT ? BM : 1][SB_BK], Bl[2][SPLIT ? BN : 1][SB_BK];
@@ -767,14 +805,30 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
         if (mine && j < 4) sa.add(j, ga[i][r], gy[i][r], (double)kv);
       }
     }
+    if (cm) {  // column-major out (column stride ldo): rows rb .. rb + 3 of a column in one 16-byte store
+      const int64_t rb = r0 + wr * 64 + i * 16 + g * 4;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + wr * 64 + i * 16 + g * 4 + r;
-      if (row >= n) continue;
-      float* orow = out + row * ldo + c0 + wc * 128 + i16;
+      for (int j = 0; j < 8; ++j) {
+        if (!zok[j]) continue;
+        float* ocol = out + (c0 + wc * 128 + j * 16 + i16) * ldo;
+        if (rb + 3 < n) {
+          *(floatx4*)(ocol + rb) = acc[i][j];
+        } else {
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (zok[j]) orow[j * 16] = acc[i][j][r];
+          for (int r = 0; r < 4; ++r)
+            if (rb + r < n) ocol[rb + r] = acc[i][j][r];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + wr * 64 + i * 16 + g * 4 + r;
+        if (row >= n) continue;
+        float* orow = out + row * ldo + c0 + wc * 128 + i16;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (zok[j]) orow[j * 16] = acc[i][j][r];
+      }
     }
   }
   if (fused) {
@@ -792,18 +846,21 @@ constexpr int64_t kWideCols = 192;
 
 void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int64_t ldb, int64_t n,
                         const float* xnorm, const int32_t* cidx, int ncols, float* out, int64_t ldo, double gamma,
-                        hipStream_t st, const Score0& s0) {
+                        hipStream_t st, const Score0& s0, bool colmajor) {
   if (n <= 0 || ncols <= 0) return;
+  if (colmajor && (ldo % 4 != 0 || ((uintptr_t)out & 15u)))
+    throw Failure(1, "kernel block: column-major out needs 16-byte aligned columns");
+  const int cm = colmajor ? 1 : 0;
   if (ldb % SB_BK != 0 || ((uintptr_t)hi & 15u) || ((uintptr_t)lo & 15u))
     throw Failure(1, "kernel block: split copies must be 16-byte aligned with ldb a multiple of 32");
   if (ncols >= kWideCols && ceil_div(n, 256) * ceil_div(ncols, 256) >= 256) {
     const dim3 grid(xcd_grid(ceil_div(n, 256), ceil_div(ncols, 256)));
     if (lo)
       hipLaunchKernelGGL((k_kblock_bf16_wide<true>), grid, dim3(512), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
-                         ldo, gamma, s0);
+                         ldo, gamma, s0, cm);
     else
       hipLaunchKernelGGL((k_kblock_bf16_wide<false>), grid, dim3(512), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols,
-                         out, ldo, gamma, s0);
+                         out, ldo, gamma, s0, cm);
     SPSVM_LAUNCHED();
     return;
   }
@@ -812,17 +869,17 @@ void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int6
   if (wide) {
     if (lo)
       hipLaunchKernelGGL((k_kblock_bf16<true, 4>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
-                         ldo, gamma, s0);
+                         ldo, gamma, s0, cm);
     else
       hipLaunchKernelGGL((k_kblock_bf16<false, 4>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
-                         ldo, gamma, s0);
+                         ldo, gamma, s0, cm);
   } else {
     if (lo)
       hipLaunchKernelGGL((k_kblock_bf16<true, 2>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
-                         ldo, gamma, s0);
+                         ldo, gamma, s0, cm);
     else
       hipLaunchKernelGGL((k_kblock_bf16<false, 2>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
-                         ldo, gamma, s0);
+                         ldo, gamma, s0, cm);
   }
   SPSVM_LAUNCHED();
 }
@@ -1000,7 +1057,7 @@ void launch_check_inputs(const TX* X, int64_t total, const float* y, int64_t n, 
 #define SPSVM_INST(TX, TK)                                                                                    \
   template void launch_row_norms<TX, TK>(const TX*, int64_t, int64_t, int64_t, TK*, hipStream_t);             \
   template void launch_kblock<TX, TK>(const TX*, int64_t, int64_t, int64_t, const TK*, const int32_t*, int, TK*, \
-                                      int64_t, double, hipStream_t, const Score0&);                                          \
+                                      int64_t, double, hipStream_t, const Score0&, bool);                                    \
   template void launch_predict<TX, TK>(const TX*, int64_t, int64_t, int64_t, const TK*, int64_t, const TK*, int,  \
                                        const double*, double*, double, hipStream_t);                          \
   template void launch_gather_rows<TX, TK>(const TX*, int64_t, const int64_t*, int64_t, TK*, int64_t, hipStream_t);

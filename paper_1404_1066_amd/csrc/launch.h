@@ -76,8 +76,10 @@ constexpr int kKblockRows = 128;  // rows per kernel-block tile (the fused pass 
 // X rows start at multiples of ldx elements; ldx * sizeof(TX) and X must be 16-byte aligned.
 // gamma > 0 writes exp(-gamma d2); gamma == 0 writes the squared distances d2.
 template <typename TX, typename TK>
+// colmajor: out[c * ldo + i] (columns 16-byte aligned, ldo a multiple of 4) instead of out[i * ldo + c].
 void launch_kblock(const TX* X, int64_t ldx, int64_t n, int64_t d, const TK* xnorm, const int32_t* cidx, int ncols,
-                   TK* out, int64_t ldo, double gamma, hipStream_t st, const Score0& s0 = Score0{});
+                   TK* out, int64_t ldo, double gamma, hipStream_t st, const Score0& s0 = Score0{},
+                   bool colmajor = false);
 template <typename TX, typename TK>
 void launch_predict(const TX* Xt, int64_t ldxt, int64_t n, int64_t d, const TK* Z, int64_t ldz, const TK* znorm, int m,
                     const double* beta, double* out, double gamma, hipStream_t st);
@@ -92,7 +94,7 @@ void launch_split_bf16(const TX* X, int64_t n, int64_t d, int64_t ldx, unsigned 
 // hi.hi' is issued (identical result).
 void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int64_t ldb, int64_t n,
                         const float* xnorm, const int32_t* cidx, int ncols, float* out, int64_t ldo, double gamma,
-                        hipStream_t st, const Score0& s0 = Score0{});
+                        hipStream_t st, const Score0& s0 = Score0{}, bool colmajor = false);
 template <typename TK>
 void launch_rbf_from_dist(const TK* D, int64_t rows, int ncols, int64_t ld, TK* K, double gamma, hipStream_t st);
 template <typename TX>
@@ -112,7 +114,8 @@ void launch_iota(int32_t* out, int64_t m, hipStream_t st);
 // Score slots for step `step` of the candidate table (kCandSlots indices per step, -1 = empty).
 void launch_score_init(const int32_t* cand, const double* o, const uint64_t* hash, const uint64_t* stage_hash,
                        int n_stage, CandState* st, NewtonScalars* sc, hipStream_t s);
-// One scoring pass over the n rows for all active slots (partial sums per workgroup), then one workgroup per
+// One scoring pass over the n rows for all active slots (candidate block Kc column-major, column stride ldc;
+// partial sums per workgroup), then one workgroup per
 // slot reduces them and advances the slot. Both kernels return at once when every slot is settled.
 template <typename TK>
 void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, const CandState* st,
@@ -124,8 +127,8 @@ void launch_score_update(CandState* st, const double* partial, int nblk, double 
 void launch_score_init_update(const int32_t* cand, const double* o, const uint64_t* hash, const uint64_t* stage_hash,
                               int n_stage, CandState* st, const double* partial, int nblk, double lam,
                               hipStream_t s);
-// Argmax of the scored slots and its append (one launch). Kc: the step's candidate columns (leading dimension
-// ldc); fused0: its first scoring pass came with the block; m_dev: two ints, step q reads the basis size at
+// Argmax of the scored slots and its append (one launch). Kc: the step's candidate columns, column-major
+// (column stride ldc); fused0: its first scoring pass came with the block; m_dev: two ints, step q reads the basis size at
 // m_dev[q & 1] and writes the next at m_dev[(q + 1) & 1].
 template <typename TK>
 void launch_select_append(const CandState* st, const uint64_t* hash, uint64_t* stage_hash, int q, const TK* Kc,

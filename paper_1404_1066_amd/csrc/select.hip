@@ -100,12 +100,12 @@ __device__ __forceinline__ int advance_slot(CandState& s, double P, double Q, do
   return still;
 }
 
-// One pass over the rows for the slots still being scored (na of the 64). The live slots are packed onto the
-// lanes: with R = 64 / na rows per wave step, lane r * na + a (r < R) takes live slot a on rows
-// lo + q R + r + m kScoreWaves R of its workgroup's range (wave q), so late passes with few live slots touch
-// each row once per live slot instead of once per lane. Eight steps per iteration have their loads issued
-// together, even steps summed apart from odd ones. The per-lane sums are added over the waves, then over r, in
-// a fixed order, and written as this workgroup's record {P, Q, V, flips} of each live slot.
+// One pass over the rows for the slots still being scored (na of the 64). The candidate block is column-major
+// (column stride ldc), so a live slot's values are one contiguous column. The live slots are packed onto the
+// lanes: with R = 64 / na, lane r * na + a (r < R) of wave q takes live slot a on the chunks of 8 consecutive rows
+// starting at lo + 8 (q R + r) + m 8 kScoreWaves R of its workgroup's range; a pass thus reads one column per
+// live slot. The per-lane sums are added over the waves, then over r, in a fixed order, and written as this
+// workgroup's record {P, Q, V, flips} of each live slot.
 template <typename TK>
 __global__ __launch_bounds__(64 * kScoreWaves, 6) void k_score_pass(const TK* __restrict__ Kc, int64_t ldc,
                                                                   const float* __restrict__ y,
@@ -127,65 +127,48 @@ __global__ __launch_bounds__(64 * kScoreWaves, 6) void k_score_pass(const TK* __
   double P = 0.0, Q = 0.0, V = 0.0, F = 0.0;
   if (r < R) {
     const int c = act[a];
+    const TK* __restrict__ kc = Kc + (int64_t)c * ldc;  // the slot's candidate column
     const double s = st[c].s, sp = st[c].s_prev;
     const bool chk = st[c].passes > 0;
     const int64_t lo = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t hi = lo + rows_per_blk < n ? lo + rows_per_blk : n;
-    const int64_t step = (int64_t)kScoreWaves * R;
+    constexpr int U = 8;
+    const int64_t step = (int64_t)kScoreWaves * R * U;
     double P2 = 0.0, Q2 = 0.0, V2 = 0.0;
     int fl = 0, fl2 = 0;
-    int64_t i = lo + q * R + r;
-    constexpr int U = 8;
-    const int st32 = (int)step, kst32 = (int)(step * ldc);  // 32-bit offsets inside an iteration
-    for (; i + step * (U - 1) < hi; i += step * U) {
+    auto one = [&](double av, double b, double& Pa, double& Qa, double& Va, int& fa) {
+      const double e = av - s * b;
+      const double ua = fmax(av, 0.0), we = fmax(e, 0.0);
+      // selects rather than branches (adding an exact zero leaves a sum unchanged), so that no control flow
+      // keeps the compiler from issuing a chunk's loads together
+      Pa += e > 0.0 ? av * b : 0.0;
+      Qa += e > 0.0 ? b * b : 0.0;
+      Va += (we - ua) * (we + ua);
+      fa += chk && ((e > 0.0) != (av - sp * b > 0.0)) ? 1 : 0;
+    };
+    // chunks of U consecutive rows per lane (contiguous loads from the column), even rows summed apart from odd
+    int64_t i = lo + (int64_t)(q * R + r) * U;
+    for (; i + U - 1 < hi; i += step) {
       float yv[U];
       double ov[U];
       TK kv[U];  // converted where used: a conversion here would wait for the load
-      const float* yp = y + i;
-      const double* op = o + i;
-      const TK* kp = Kc + i * ldc + c;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        yv[u] = yp[st32 * u];
-        ov[u] = op[st32 * u];
-        kv[u] = kp[kst32 * u];
+        yv[u] = y[i + u];
+        ov[u] = o[i + u];
+        kv[u] = kc[i + u];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const double av = margin_gap(yv[u], ov[u]);
         const double b = (double)yv[u] * (double)kv[u];
-        const double e = av - s * b;
-        const double ua = fmax(av, 0.0), we = fmax(e, 0.0);
-        const int flip = chk && ((e > 0.0) != (av - sp * b > 0.0)) ? 1 : 0;
-        // selects rather than branches (adding an exact zero leaves a sum unchanged), so that no control flow
-        // keeps the compiler from issuing the eight rows' loads together
-        const double pa = e > 0.0 ? av * b : 0.0, qa = e > 0.0 ? b * b : 0.0;
-        if (u & 1) {
-          P2 += pa;
-          Q2 += qa;
-          V2 += (we - ua) * (we + ua);
-          fl2 += flip;
-        } else {
-          P += pa;
-          Q += qa;
-          V += (we - ua) * (we + ua);
-          fl += flip;
-        }
+        if (u & 1)
+          one(av, b, P2, Q2, V2, fl2);
+        else
+          one(av, b, P, Q, V, fl);
       }
     }
-    for (; i < hi; i += step) {
-      const double yi = (double)y[i];
-      const double av = margin_gap(y[i], o[i]);
-      const double b = yi * (double)Kc[i * ldc + c];
-      const double e = av - s * b;
-      if (e > 0.0) {
-        P += av * b;
-        Q += b * b;
-      }
-      const double u = fmax(av, 0.0), w = fmax(e, 0.0);
-      V += (w - u) * (w + u);
-      if (chk) fl += ((e > 0.0) != (av - sp * b > 0.0)) ? 1 : 0;
-    }
+    for (; i < hi; ++i) one(margin_gap(y[i], o[i]), (double)y[i] * (double)kc[i], P, Q, V, fl);  // partial chunk
     P += P2;
     Q += Q2;
     V += V2;
@@ -431,7 +414,7 @@ __global__ __launch_bounds__(256) void k_select_append(const CandState* __restri
   const Selection r = choice;
   if (!r.valid) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const TK k = Kc[i * ldc + r.slot];
+    const TK k = Kc[(int64_t)r.slot * ldc + i];  // column-major candidate block
     o[i] += r.s * (double)k;
     KXJ[i * ldk + r.pos] = k;
   }

@@ -87,7 +87,7 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.xnorm = take(n * tk);
   p.hash = take(n * 8);
   p.KXJ = take((size_t)n * p.ldk * tk);
-  p.Kc = take(with_selection ? (size_t)n * kCandSlots * cand_group(d, opt.chunk_cap) * tk : 0);
+  p.Kc = take(with_selection ? (size_t)round_up(n, 4) * kCandSlots * cand_group(d, opt.chunk_cap) * tk : 0);
   p.J = take(J_max * 8);
   p.J32 = take(J_max * 4);
   p.cand_state = take(kCandSlots * sizeof(CandState));
@@ -390,15 +390,16 @@ struct Impl {
   }
 
   // The n x N kernel block in the training precision (split-BF16 products in MIXED mode).
-  void kblock(const int32_t* cols, int ncols, TK* out, int64_t ldo, const Score0& s0 = Score0{}) {
+  void kblock(const int32_t* cols, int ncols, TK* out, int64_t ldo, const Score0& s0 = Score0{},
+              bool colmajor = false) {
     if constexpr (std::is_same<TK, float>::value) {
       if (opt.precision == SPSVM_MIXED) {
         launch_kblock_bf16(at<unsigned short>(p.Xhi), bf16_exact ? nullptr : at<unsigned short>(p.Xlo), p.ldb, n,
-                           xnorm, cols, ncols, out, ldo, gamma, st, s0);
+                           xnorm, cols, ncols, out, ldo, gamma, st, s0, colmajor);
         return;
       }
     }
-    launch_kblock<TX, TK>(Xk, p.ldx, n, d, xnorm, cols, ncols, out, ldo, gamma, st, s0);
+    launch_kblock<TX, TK>(Xk, p.ldx, n, d, xnorm, cols, ncols, out, ldo, gamma, st, s0, colmajor);
   }
 
   // Basis rows m0..m1 of J gathered into XJ64 (FP64), then the FP64 kernel matrix K_JJ of the first m1 rows.
@@ -884,7 +885,7 @@ struct Impl {
         const int G = cand_group(d, opt.chunk_cap);
         for (int q0 = 0; q0 < cs; q0 += G) {
           const int gsz = std::min(G, cs - q0);  // steps sharing this kernel-block launch
-          const int64_t ldc = (int64_t)kCandSlots * gsz;
+          const int64_t ldc = round_up(n, 4);     // candidate columns, column-major (one contiguous column each)
           int ncand = 0;
           for (int c = 0; c < kCandSlots * gsz; ++c) ncand += table[(size_t)q0 * kCandSlots + c] >= 0;
           // the candidate block also yields the first scoring pass (at s = 0) of its first step
@@ -893,11 +894,11 @@ struct Impl {
           s0.o = o;
           s0.partial = score_part;
           prof.timed(kProfKblock, 2.0 * n * ncand * d,
-                     [&] { kblock(cand_table + (size_t)q0 * kCandSlots, (int)ldc, Kc, ldc, s0); });
+                     [&] { kblock(cand_table + (size_t)q0 * kCandSlots, kCandSlots * gsz, Kc, ldc, s0, true); });
           for (int j = 0; j < gsz; ++j) {
             const int q = q0 + j;
             const int32_t* cq = cand_table + (size_t)q * kCandSlots;
-            const TK* Kq = Kc + (size_t)j * kCandSlots;
+            const TK* Kq = Kc + (size_t)j * kCandSlots * ldc;
             if (j == 0) {
               launch_score_init_update(cq, o, hash, stage_hash, q, cst, score_part, (int)ceil_div(n, kKblockRows),
                                        lam, st);
