@@ -274,6 +274,38 @@ struct Score0Acc {
   }
 };
 
+// Column-major store of a BM-row x 64-column FP32 tile through LDS, tr[column][row] (rows padded by 4 floats).
+// After a barrier that ends the k loop's use of the LDS operand tiles (which tr may alias), each wave puts its
+// 4-row pieces at their place (row, column) as it finishes them; flush() then has every eight consecutive lanes
+// write one 128-byte run (32 rows) of one column, so each store instruction fills whole lines. Columns past
+// ncols and empty candidate slots are skipped.
+template <int BM>
+struct ColStage {
+  static_assert(BM % 32 == 0 && (BM * 64 / 4) % 256 == 0, "whole 32-row runs, whole passes of 256 threads");
+  float (*tr)[BM + 4];
+  __device__ __forceinline__ void put(int col, int row, const floatx4& v) const { *(floatx4*)&tr[col][row] = v; }
+  __device__ __forceinline__ void flush(float* __restrict__ out, int64_t ldo, int64_t n, int64_t r0, int64_t c0,
+                                        int ncols, const int32_t* __restrict__ cidx) const {
+    __syncthreads();
+    const int sub = threadIdx.x & 7;
+#pragma unroll
+    for (int s = 0; s < BM / 16; ++s) {
+      const int run = s * 32 + (threadIdx.x >> 3), cc = run & 63, rr = (run >> 6) * 32 + sub * 4;
+      const int64_t col = c0 + cc, row = r0 + rr;
+      if (col >= ncols || row >= n || (cidx && cidx[col] < 0)) continue;
+      const floatx4 x = *(const floatx4*)&tr[cc][rr];
+      float* o = out + col * ldo + row;
+      if (row + 3 < n) {
+        *(floatx4*)o = x;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (row + r < n) o[r] = x[r];
+      }
+    }
+  }
+};
+
 // Waves per SIMD the FP32 block is compiled for: four (at most 128 registers) keeps four workgroups of the
 // launch on each CU; the other type combinations take what their registers allow.
 template <typename TX, typename TK>
@@ -287,8 +319,11 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
                                                       int ncols, TK* __restrict__ out, int64_t ldo, double gamma,
                                                       const Score0 s0, int cm) {
   using M = Mfma<TK>;
-  __shared__ __attribute__((aligned(32))) TK As[KB_BM][KB_LD];
-  __shared__ __attribute__((aligned(32))) TK Bs[KB_BN][KB_LD];
+  // operand tiles during the k loop; afterwards (column-major out) the tile's values as [column][row]
+  constexpr int kOps = (KB_BM + KB_BN) * KB_LD * (int)sizeof(TK), kTr = KB_BN * (KB_BM + 4) * 4;
+  __shared__ __attribute__((aligned(32))) char smem[kOps > kTr ? kOps : kTr];
+  TK(*As)[KB_LD] = reinterpret_cast<TK(*)[KB_LD]>(smem);
+  TK(*Bs)[KB_LD] = reinterpret_cast<TK(*)[KB_LD]>(smem + KB_BM * KB_LD * sizeof(TK));
   const TileOf tile = xcd_tile(ceil_div_dev(ncols, KB_BN));
   const int64_t r0 = tile.r * KB_BM, c0 = tile.c * KB_BN;
   if (r0 >= n) return;  // padding of the row-tile count to a multiple of 8
@@ -342,6 +377,8 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
     zn[j] = xnorm[zok[j] ? zi : 0];
   }
   Score0Acc sa;
+  const ColStage<KB_BM> stage{reinterpret_cast<float(*)[KB_BM + 4]>(smem)};
+  if (std::is_same<TK, float>::value && cm) __syncthreads();  // the operand tiles are free for the staging
   // Per 16-row group i: all values, then their stores (every load was issued above, so no store waits on one).
   // The uniform choices (exp or plain distance, fused pass or not) are taken once, outside the element loops;
   // rows past n have a_i = 0 and add nothing to the fused sums.
@@ -358,23 +395,21 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
         if (FUSED) sa.add(j, ga[i][r], gy[i][r], (double)kv);
       }
     }
-    if (cm) {  // column-major out (column stride ldo)
+    if (cm) {
+      if constexpr (!std::is_same<TK, float>::value) {  // FP64: direct column-major stores
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (!zok[j]) continue;
-        TK* ocol = out + (c0 + j * 16 + (lane & 15)) * ldo;
-        const int64_t rb = r0 + w * 32 + i * 16 + M::row(lane, 0);
-        if constexpr (std::is_same<TK, float>::value) {  // rows rb .. rb + 3: one 16-byte store
-          if (rb + 3 < n) {
-            *(floatx4*)(ocol + rb) = t.acc[i][j];
-            continue;
+        for (int j = 0; j < 4; ++j) {
+          if (!zok[j]) continue;
+          TK* ocol = out + (c0 + j * 16 + (lane & 15)) * ldo;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
+            if (row < n) ocol[row] = t.acc[i][j][r];
           }
         }
+      } else {  // FP32: staged through LDS, each column then written in whole 128-byte runs
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
-          if (row < n) ocol[row] = t.acc[i][j][r];
-        }
+        for (int j = 0; j < 4; ++j) stage.put(j * 16 + (lane & 15), w * 32 + i * 16 + M::row(lane, 0), t.acc[i][j]);
       }
     } else {
 #pragma unroll
@@ -401,6 +436,9 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
       else
         group(i, std::false_type{}, std::false_type{});
     }
+  }
+  if constexpr (std::is_same<TK, float>::value) {
+    if (cm) stage.flush(out, ldo, n, r0, c0, ncols, cidx);
   }
   if (fused) {
     __shared__ double red[4][64][2];
@@ -478,8 +516,15 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
                                                      float* __restrict__ out, int64_t ldo, double gamma,
                                                      const Score0 s0, int cm) {
   constexpr int BM = 64 * RTW;  // rows per workgroup: 4 waves of RTW 16-row tiles
-  __shared__ __attribute__((aligned(16))) unsigned short Ah[BM][SB_LD], Bh[KB_BN][SB_LD];
-  __shared__ __attribute__((aligned(16))) unsigned short Al[SPLIT ? BM : 1][SB_LD], Bl[SPLIT ? KB_BN : 1][SB_LD];
+  // operand tiles during the k loop; afterwards (column-major out) the tile's values as [column][row]
+  constexpr int kA = BM * SB_LD * 2, kB = KB_BN * SB_LD * 2, kOps = SPLIT ? 2 * (kA + kB) : kA + kB,
+                kTr = KB_BN * (BM + 4) * 4;
+  __shared__ __attribute__((aligned(16))) char smem[kOps > kTr ? kOps : kTr];
+  typedef unsigned short Row[SB_LD];
+  Row* Ah = reinterpret_cast<Row*>(smem);
+  Row* Bh = reinterpret_cast<Row*>(smem + kA);
+  Row* Al = reinterpret_cast<Row*>(smem + kA + kB);             // SPLIT only
+  Row* Bl = reinterpret_cast<Row*>(smem + (SPLIT ? 2 * kA : kA) + kB);  // SPLIT only
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, i16 = lane & 15;
   const TileOf tile = xcd_tile(ceil_div_dev(ncols, KB_BN));
   const int64_t r0 = tile.r * BM, c0 = tile.c * KB_BN;
@@ -592,6 +637,8 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
     zn[j] = xnorm[zok[j] ? zi : 0];
   }
   Score0Acc sa;
+  const ColStage<BM> stage{reinterpret_cast<float(*)[BM + 4]>(smem)};
+  if (cm) __syncthreads();  // the operand tiles are free for the staging
   // Per 16-row group i: all values, then their stores (every load was issued above, so no store waits on one);
   // rows past n have a_i = 0 and add nothing to the fused sums.
 #pragma unroll
@@ -607,20 +654,9 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
         if (fused) sa.add(j, ga[i][r], gy[i][r], (double)kv);
       }
     }
-    if (cm) {  // column-major out (column stride ldo): rows rb .. rb + 3 of a column in one 16-byte store
-      const int64_t rb = r0 + w * 16 * RTW + i * 16 + (lane >> 4) * 4;
+    if (cm) {  // column-major: staged through LDS, each column then written in whole 128-byte runs
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (!zok[j]) continue;
-        float* ocol = out + (c0 + j * 16 + i16) * ldo;
-        if (rb + 3 < n) {
-          *(floatx4*)(ocol + rb) = acc[i][j];
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (rb + r < n) ocol[rb + r] = acc[i][j][r];
-        }
-      }
+      for (int j = 0; j < 4; ++j) stage.put(j * 16 + i16, w * 16 * RTW + i * 16 + g * 4, acc[i][j]);
     } else {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -633,6 +669,7 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
       }
     }
   }
+  if (cm) stage.flush(out, ldo, n, r0, c0, ncols, cidx);
   if (fused) {
     __shared__ double red[4][64][2];
     // one record per 128 rows: RTW = 2 -> all four waves, RTW = 4 -> two pairs of waves
