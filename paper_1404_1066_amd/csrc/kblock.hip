@@ -276,31 +276,103 @@ struct Score0Acc {
 
 // Column-major store of a BM-row x 64-column FP32 tile through LDS, tr[column][row] (rows padded by 4 floats).
 // After a barrier that ends the k loop's use of the LDS operand tiles (which tr may alias), each wave puts its
-// 4-row pieces at their place (row, column) as it finishes them; flush() then has every eight consecutive lanes
-// write one 128-byte run (32 rows) of one column, so each store instruction fills whole lines. Columns past
-// ncols and empty candidate slots are skipped.
+// 4-row pieces at their place (row, column) as it finishes them. flush() then gives the eight consecutive lanes
+// of group cb = t / 8 the whole of columns cb and cb + 32: lane t % 8 holds rows 32 q + 4 (t % 8) .. + 3 of
+// both, and each store instruction writes 128-byte runs (32 rows) of eight columns, so whole lines. Columns
+// past ncols and empty candidate slots are skipped.
+// Fused first scoring pass (see Score0; the first 64 columns only): the lanes of a group sum a_i b_i and
+// b_i^2 over their rows of each of their two columns, one record per 128 rows, then over the group (xor
+// shuffles); records at or past nrec are not written, empty columns get zero records.
 template <int BM>
 struct ColStage {
-  static_assert(BM % 32 == 0 && (BM * 64 / 4) % 256 == 0, "whole 32-row runs, whole passes of 256 threads");
+  static_assert(BM % 128 == 0 && BM <= 256, "whole fused records, at most 8 row quads per lane");
   float (*tr)[BM + 4];
   __device__ __forceinline__ void put(int col, int row, const floatx4& v) const { *(floatx4*)&tr[col][row] = v; }
   __device__ __forceinline__ void flush(float* __restrict__ out, int64_t ldo, int64_t n, int64_t r0, int64_t c0,
-                                        int ncols, const int32_t* __restrict__ cidx) const {
+                                        int ncols, const int32_t* __restrict__ cidx, const Score0& s0, bool fused,
+                                        int64_t rec0, int64_t nrec) const {
+    constexpr int NQ = BM / 32, NR = BM / 128;  // row quads per lane, fused records per column
+    const int sub = threadIdx.x & 7, cb = threadIdx.x >> 3;
+    bool ok[2];  // loads first: a load issued after a store waits for it
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t col = c0 + cb + 32 * h;
+      ok[h] = col < ncols && (!cidx || cidx[col] >= 0);
+    }
+    double ga[NQ][4];
+    float gy[NQ][4];
+    if (fused) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = r0 + 32 * q + 4 * sub + r;
+          const int64_t rc = row < n ? row : n - 1;  // clamped: unconditional loads
+          const float yv = s0.y[rc];
+          const double ov = s0.o[rc];
+          gy[q][r] = yv;
+          ga[q][r] = row < n ? margin_gap(yv, ov) : 0.0;  // rows past n add nothing
+        }
+    }
     __syncthreads();
-    const int sub = threadIdx.x & 7;
+    floatx4 x[2][NQ];
 #pragma unroll
-    for (int s = 0; s < BM / 16; ++s) {
-      const int run = s * 32 + (threadIdx.x >> 3), cc = run & 63, rr = (run >> 6) * 32 + sub * 4;
-      const int64_t col = c0 + cc, row = r0 + rr;
-      if (col >= ncols || row >= n || (cidx && cidx[col] < 0)) continue;
-      const floatx4 x = *(const floatx4*)&tr[cc][rr];
-      float* o = out + col * ldo + row;
-      if (row + 3 < n) {
-        *(floatx4*)o = x;
-      } else {
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (row + r < n) o[r] = x[r];
+      for (int q = 0; q < NQ; ++q) x[h][q] = *(const floatx4*)&tr[cb + 32 * h][32 * q + 4 * sub];
+    if (fused) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double P[NR], Q[NR];
+#pragma unroll
+        for (int e = 0; e < NR; ++e) P[e] = Q[e] = 0.0;
+        if (ok[h]) {
+#pragma unroll
+          for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const double av = ga[q][r];
+              if (av > 0.0) {
+                const double bv = (double)gy[q][r] * (double)x[h][q][r];
+                P[q / 4] += av * bv;
+                Q[q / 4] += bv * bv;
+              }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < NR; ++e)
+#pragma unroll
+          for (int m = 1; m < 8; m <<= 1) {
+            P[e] += __shfl_xor(P[e], m, kWave);
+            Q[e] += __shfl_xor(Q[e], m, kWave);
+          }
+        if (sub == 0) {
+#pragma unroll
+          for (int e = 0; e < NR; ++e) {
+            if (rec0 + e >= nrec) continue;
+            double* rec = s0.partial + ((int64_t)(cb + 32 * h) * nrec + rec0 + e) * 4;  // [slot][record][4]
+            rec[0] = P[e];
+            rec[1] = Q[e];
+            rec[2] = 0.0;
+            rec[3] = 0.0;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!ok[h]) continue;
+      float* ocol = out + (c0 + cb + 32 * h) * ldo;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int64_t row = r0 + 32 * q + 4 * sub;
+        if (row + 3 < n) {
+          *(floatx4*)(ocol + row) = x[h][q];
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (row + r < n) ocol[row + r] = x[h][q][r];
+        }
       }
     }
   }
@@ -333,9 +405,12 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const TK gs = gamma_scale<TK>(gamma);
   const bool fused = s0.partial != nullptr && tile.c == 0;  // the first 64 columns only
-  double ga[2][4];  // a_i of this lane's rows (fused pass)
+  // FP32 values: column-major out and the fused pass go through LDS (ColStage); FP64: both from registers
+  constexpr bool kStaged = std::is_same<TK, float>::value;
+  const bool rfused = !kStaged && fused;
+  double ga[2][4];  // a_i of this lane's rows (fused pass from registers)
   float gy[2][4];
-  if (fused) {
+  if (rfused) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -378,7 +453,7 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
   }
   Score0Acc sa;
   const ColStage<KB_BM> stage{reinterpret_cast<float(*)[KB_BM + 4]>(smem)};
-  if (std::is_same<TK, float>::value && cm) __syncthreads();  // the operand tiles are free for the staging
+  if (kStaged && cm) __syncthreads();  // the operand tiles are free for the staging
   // Per 16-row group i: all values, then their stores (every load was issued above, so no store waits on one).
   // The uniform choices (exp or plain distance, fused pass or not) are taken once, outside the element loops;
   // rows past n have a_i = 0 and add nothing to the fused sums.
@@ -426,21 +501,21 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     if (gamma > 0.0) {
-      if (fused)
+      if (rfused)
         group(i, std::true_type{}, std::true_type{});
       else
         group(i, std::true_type{}, std::false_type{});
     } else {
-      if (fused)
+      if (rfused)
         group(i, std::false_type{}, std::true_type{});
       else
         group(i, std::false_type{}, std::false_type{});
     }
   }
-  if constexpr (std::is_same<TK, float>::value) {
-    if (cm) stage.flush(out, ldo, n, r0, c0, ncols, cidx);
+  if constexpr (kStaged) {
+    if (cm) stage.flush(out, ldo, n, r0, c0, ncols, cidx, s0, fused, tile.r, ceil_div_dev(n, kKblockRows));
   }
-  if (fused) {
+  if (rfused) {
     __shared__ double red[4][64][2];
     sa.finish(s0.partial, tile.r, ceil_div_dev(n, kKblockRows), 4, red);
   }
@@ -455,6 +530,7 @@ void launch_kblock(const TX* X, int64_t ldx, int64_t n, int64_t d, const TK* xno
   const dim3 grid(xcd_grid(ceil_div(n, KB_BM), ceil_div(ncols, KB_BN)));
   if (colmajor && (ldo % 4 != 0 || ((uintptr_t)out & 15u)))
     throw Failure(1, "kernel block: column-major out needs 16-byte aligned columns");
+  if (s0.partial && !colmajor) throw Failure(1, "kernel block: the fused scoring pass needs column-major out");
   hipLaunchKernelGGL((k_kblock_store<TX, TK>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out, ldo,
                      gamma, s0, colmajor ? 1 : 0);
   SPSVM_LAUNCHED();
@@ -592,22 +668,7 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
       }
   }
   const float gs = (float)(gamma * 1.4426950408889634);
-  const bool fused = s0.partial != nullptr && tile.c == 0;  // the first 64 columns only
-  double ga[RTW][4];
-  float gy[RTW][4];
-  if (fused) {
-#pragma unroll
-    for (int i = 0; i < RTW; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + w * 16 * RTW + i * 16 + (lane >> 4) * 4 + r;
-        const int64_t rc = row < n ? row : n - 1;  // clamped: unconditional loads, no branches between them
-        const float yv = s0.y[rc];
-        const double ov = s0.o[rc];
-        gy[i][r] = row < n ? yv : 0.0f;
-        ga[i][r] = row < n ? margin_gap(yv, ov) : 0.0;
-      }
-  }
+  const bool fused = s0.partial != nullptr && tile.c == 0;  // the first 64 columns only (column-major out)
   // every norm this lane needs, loaded before the first store (a load issued after a store waits for it)
   float xr[RTW][4], zn[4];
   bool zok[4];
@@ -636,11 +697,9 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
     zok[j] = zi >= 0;
     zn[j] = xnorm[zok[j] ? zi : 0];
   }
-  Score0Acc sa;
   const ColStage<BM> stage{reinterpret_cast<float(*)[BM + 4]>(smem)};
   if (cm) __syncthreads();  // the operand tiles are free for the staging
-  // Per 16-row group i: all values, then their stores (every load was issued above, so no store waits on one);
-  // rows past n have a_i = 0 and add nothing to the fused sums.
+  // Per 16-row group i: all values, then their stores (every load was issued above, so no store waits on one).
 #pragma unroll
   for (int i = 0; i < RTW; ++i) {
 #pragma unroll
@@ -651,7 +710,6 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
         const float d2 = xr[i][r] + zn[j] - 2.0f * acc[i][j][r];
         const float kv = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
         acc[i][j][r] = kv;
-        if (fused) sa.add(j, ga[i][r], gy[i][r], (double)kv);
       }
     }
     if (cm) {  // column-major: staged through LDS, each column then written in whole 128-byte runs
@@ -669,12 +727,8 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
       }
     }
   }
-  if (cm) stage.flush(out, ldo, n, r0, c0, ncols, cidx);
-  if (fused) {
-    __shared__ double red[4][64][2];
-    // one record per 128 rows: RTW = 2 -> all four waves, RTW = 4 -> two pairs of waves
-    sa.finish(s0.partial, tile.r * (BM / kKblockRows), ceil_div_dev(n, kKblockRows), 4 * 128 / BM, red);
-  }
+  if (cm)
+    stage.flush(out, ldo, n, r0, c0, ncols, cidx, s0, fused, tile.r * (BM / kKblockRows), ceil_div_dev(n, kKblockRows));
 }
 
 // Split-BF16 block in 256 x 256 tiles for blocks with many columns (grouped candidate steps, a whole basis):
@@ -887,6 +941,7 @@ void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int6
   if (n <= 0 || ncols <= 0) return;
   if (colmajor && (ldo % 4 != 0 || ((uintptr_t)out & 15u)))
     throw Failure(1, "kernel block: column-major out needs 16-byte aligned columns");
+  if (s0.partial && !colmajor) throw Failure(1, "kernel block: the fused scoring pass needs column-major out");
   const int cm = colmajor ? 1 : 0;
   if (ldb % SB_BK != 0 || ((uintptr_t)hi & 15u) || ((uintptr_t)lo & 15u))
     throw Failure(1, "kernel block: split copies must be 16-byte aligned with ldb a multiple of 32");
