@@ -274,19 +274,32 @@ struct Score0Acc {
   }
 };
 
-// Column-major store of a BM-row x 64-column FP32 tile through LDS, tr[column][row] (rows padded by 4 floats).
-// After a barrier that ends the k loop's use of the LDS operand tiles (which tr may alias), each wave puts its
-// 4-row pieces at their place (row, column) as it finishes them. flush() then gives the eight consecutive lanes
-// of group cb = t / 8 the whole of columns cb and cb + 32: lane t % 8 holds rows 32 q + 4 (t % 8) .. + 3 of
-// both, and each store instruction writes 128-byte runs (32 rows) of eight columns, so whole lines. Columns
-// past ncols and empty candidate slots are skipped.
-// Fused first scoring pass (see Score0; the first 64 columns only): the lanes of a group sum a_i b_i and
-// b_i^2 over their rows of each of their two columns, one record per 128 rows, then over the group (xor
+// Column-major store of a BM-row x NC-column FP32 tile (NC = NT / 4 for NT threads) through LDS, tr[column][row]
+// (rows padded by 4 floats, so the 16-byte accesses of 8 lanes cover all 32 banks). After a barrier that ends
+// the k loop's use of the LDS operand tiles (which tr may alias), each wave puts its 4-row pieces at their place
+// (row, column). flush() then gives the eight consecutive lanes of group cb = t / 8 the whole of columns cb and
+// cb + NC / 2: lane t % 8 holds rows 32 q + 4 (t % 8) .. + 3 of both, and each store instruction writes
+// 128-byte runs (32 rows) of eight columns, so whole lines. Columns past ncols and empty candidate slots are
+// skipped.
+// Fused first scoring pass (see Score0; the tile's columns 0 .. 63 when it holds the first 64 columns): rows()
+// puts a_i and y_i of the tile's rows in LDS (a_i = 0 past n) before that barrier; the lanes of a group sum
+// a_i b_i and b_i^2 over their rows of each such column, one record per 128 rows, then over the group (xor
 // shuffles); records at or past nrec are not written, empty columns get zero records.
-template <int BM>
+template <int BM, int NT = 256>
 struct ColStage {
-  static_assert(BM % 128 == 0 && BM <= 256, "whole fused records, at most 8 row quads per lane");
+  static_assert(BM % 128 == 0 && BM <= NT, "whole fused records, one row per thread in rows()");
+  static constexpr int NC = NT / 4, HC = NC / 2;  // staged columns; column offset of a group's second column
   float (*tr)[BM + 4];
+  double* ga;  // [BM] in LDS
+  float* gy;   // [BM] in LDS
+  __device__ __forceinline__ void rows(const Score0& s0, int64_t r0, int64_t n) const {
+    if (threadIdx.x < BM) {
+      const int64_t row = r0 + threadIdx.x, rc = row < n ? row : n - 1;
+      const float yv = s0.y[rc];
+      ga[threadIdx.x] = row < n ? margin_gap(yv, s0.o[rc]) : 0.0;
+      gy[threadIdx.x] = yv;
+    }
+  }
   __device__ __forceinline__ void put(int col, int row, const floatx4& v) const { *(floatx4*)&tr[col][row] = v; }
   __device__ __forceinline__ void flush(float* __restrict__ out, int64_t ldo, int64_t n, int64_t r0, int64_t c0,
                                         int ncols, const int32_t* __restrict__ cidx, const Score0& s0, bool fused,
@@ -296,49 +309,43 @@ struct ColStage {
     bool ok[2];  // loads first: a load issued after a store waits for it
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int64_t col = c0 + cb + 32 * h;
+      const int64_t col = c0 + cb + HC * h;
       ok[h] = col < ncols && (!cidx || cidx[col] >= 0);
     }
-    double ga[NQ][4];
-    float gy[NQ][4];
-    if (fused) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t row = r0 + 32 * q + 4 * sub + r;
-          const int64_t rc = row < n ? row : n - 1;  // clamped: unconditional loads
-          const float yv = s0.y[rc];
-          const double ov = s0.o[rc];
-          gy[q][r] = yv;
-          ga[q][r] = row < n ? margin_gap(yv, ov) : 0.0;  // rows past n add nothing
-        }
-    }
     __syncthreads();
-    floatx4 x[2][NQ];
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < 2; ++h) {
+      const bool f = fused && HC * h < 64;  // slots 0 .. 63 only (uniform)
+      double P[NR], Q[NR];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) x[h][q] = *(const floatx4*)&tr[cb + 32 * h][32 * q + 4 * sub];
-    if (fused) {
+      for (int e = 0; e < NR; ++e) P[e] = Q[e] = 0.0;
+      float* ocol = out + (c0 + cb + HC * h) * ldo;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        double P[NR], Q[NR];
+      for (int q = 0; q < NQ; ++q) {
+        const int rr = 32 * q + 4 * sub;
+        const floatx4 x = *(const floatx4*)&tr[cb + HC * h][rr];
+        if (!ok[h]) continue;
+        if (f) {
 #pragma unroll
-        for (int e = 0; e < NR; ++e) P[e] = Q[e] = 0.0;
-        if (ok[h]) {
-#pragma unroll
-          for (int q = 0; q < NQ; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const double av = ga[q][r];
-              if (av > 0.0) {
-                const double bv = (double)gy[q][r] * (double)x[h][q][r];
-                P[q / 4] += av * bv;
-                Q[q / 4] += bv * bv;
-              }
+          for (int r = 0; r < 4; ++r) {
+            const double av = ga[rr + r];
+            if (av > 0.0) {
+              const double bv = (double)gy[rr + r] * (double)x[r];
+              P[q / 4] += av * bv;
+              Q[q / 4] += bv * bv;
             }
+          }
         }
+        const int64_t row = r0 + rr;
+        if (row + 3 < n) {
+          *(floatx4*)(ocol + row) = x;
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (row + r < n) ocol[row + r] = x[r];
+        }
+      }
+      if (f) {
 #pragma unroll
         for (int e = 0; e < NR; ++e)
 #pragma unroll
@@ -350,28 +357,12 @@ struct ColStage {
 #pragma unroll
           for (int e = 0; e < NR; ++e) {
             if (rec0 + e >= nrec) continue;
-            double* rec = s0.partial + ((int64_t)(cb + 32 * h) * nrec + rec0 + e) * 4;  // [slot][record][4]
+            double* rec = s0.partial + ((int64_t)(cb + HC * h) * nrec + rec0 + e) * 4;  // [slot][record][4]
             rec[0] = P[e];
             rec[1] = Q[e];
             rec[2] = 0.0;
             rec[3] = 0.0;
           }
-        }
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (!ok[h]) continue;
-      float* ocol = out + (c0 + cb + 32 * h) * ldo;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int64_t row = r0 + 32 * q + 4 * sub;
-        if (row + 3 < n) {
-          *(floatx4*)(ocol + row) = x[h][q];
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (row + r < n) ocol[row + r] = x[h][q][r];
         }
       }
     }
@@ -452,8 +443,13 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
     zn[j] = xnorm[zok[j] ? zi : 0];
   }
   Score0Acc sa;
-  const ColStage<KB_BM> stage{reinterpret_cast<float(*)[KB_BM + 4]>(smem)};
-  if (kStaged && cm) __syncthreads();  // the operand tiles are free for the staging
+  __shared__ double sga[kStaged ? KB_BM : 1];
+  __shared__ float sgy[kStaged ? KB_BM : 1];
+  const ColStage<KB_BM> stage{reinterpret_cast<float(*)[KB_BM + 4]>(smem), sga, sgy};
+  if (kStaged && cm) {
+    if (fused) stage.rows(s0, r0, n);
+    __syncthreads();  // the operand tiles are free for the staging
+  }
   // Per 16-row group i: all values, then their stores (every load was issued above, so no store waits on one).
   // The uniform choices (exp or plain distance, fused pass or not) are taken once, outside the element loops;
   // rows past n have a_i = 0 and add nothing to the fused sums.
@@ -697,8 +693,13 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
     zok[j] = zi >= 0;
     zn[j] = xnorm[zok[j] ? zi : 0];
   }
-  const ColStage<BM> stage{reinterpret_cast<float(*)[BM + 4]>(smem)};
-  if (cm) __syncthreads();  // the operand tiles are free for the staging
+  __shared__ double sga[BM];
+  __shared__ float sgy[BM];
+  const ColStage<BM> stage{reinterpret_cast<float(*)[BM + 4]>(smem), sga, sgy};
+  if (cm) {
+    if (fused) stage.rows(s0, r0, n);
+    __syncthreads();  // the operand tiles are free for the staging
+  }
   // Per 16-row group i: all values, then their stores (every load was issued above, so no store waits on one).
 #pragma unroll
   for (int i = 0; i < RTW; ++i) {
@@ -748,8 +749,16 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
                                                           float* __restrict__ out, int64_t ldo, double gamma,
                                                           const Score0 s0, int cm) {
   constexpr int BM = 256, BN = 256;
-  __shared__ __attribute__((aligned(16))) unsigned short Ah[2][BM][SB_BK], Bh[2][BN][SB_BK];
-  __shared__ __attribute__((aligned(16))) unsigned short Al[2][SPLIT ? BM : 1][SB_BK], Bl[2][SPLIT ? BN : 1][SB_BK];
+  // two stages of the operand chunks during the k loop; afterwards (column-major out) 128 columns of the tile
+  // at a time as [column][row]
+  typedef unsigned short Stage[BM][SB_BK];
+  static_assert(BM == BN, "one stage type for both operands");
+  constexpr int kOps = (SPLIT ? 8 : 4) * (int)sizeof(Stage), kTr = 128 * (BM + 4) * 4;
+  __shared__ __attribute__((aligned(16))) char smem[kOps > kTr ? kOps : kTr];
+  Stage* Ah = reinterpret_cast<Stage*>(smem);
+  Stage* Bh = Ah + 2;
+  Stage* Al = Ah + 4;  // SPLIT only
+  Stage* Bl = Ah + 6;  // SPLIT only
   auto phys = [](int row, int p) { return p ^ ((row >> 1) & 3); };
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w & 3, wc = w >> 2, g = lane >> 4,
             i16 = lane & 15;
@@ -834,24 +843,8 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
     __syncthreads();
   }
   const float gs = (float)(gamma * 1.4426950408889634);
-  // the fused first scoring pass covers the block's first 64 columns: column wave 0, fragments 0..3
+  // the fused first scoring pass covers the block's first 64 columns (column-major out)
   const bool fused = s0.partial != nullptr && tile.c == 0;
-  const bool mine = fused && wc == 0;
-  double ga[4][4];
-  float gy[4][4];
-  if (mine) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + wr * 64 + i * 16 + g * 4 + r;
-        const int64_t rc = row < n ? row : n - 1;  // clamped: unconditional loads, no branches between them
-        const float yv = s0.y[rc];
-        const double ov = s0.o[rc];
-        gy[i][r] = row < n ? yv : 0.0f;
-        ga[i][r] = row < n ? margin_gap(yv, ov) : 0.0;
-      }
-  }
   // every norm this lane needs, loaded before the first store (a load issued after a store waits for it)
   float xr[4][4], zn[8];
   bool zok[8];
@@ -880,9 +873,7 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
     zok[j] = zi >= 0;
     zn[j] = xnorm[zok[j] ? zi : 0];
   }
-  Score0Acc sa;
-  // Per 16-row group i: all values, then their stores (every load was issued above, so no store waits on one);
-  // rows past n have a_i = 0 and add nothing to the fused sums.
+  // Per 16-row group i: all values, then (row-major out) their stores; every load was issued above.
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -891,26 +882,10 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float d2 = xr[i][r] + zn[j] - 2.0f * acc[i][j][r];
-        const float kv = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
-        acc[i][j][r] = kv;
-        if (mine && j < 4) sa.add(j, ga[i][r], gy[i][r], (double)kv);
+        acc[i][j][r] = gamma > 0.0 ? rbf_from_d2(d2, gs) : fmaxf(d2, 0.0f);
       }
     }
-    if (cm) {  // column-major out (column stride ldo): rows rb .. rb + 3 of a column in one 16-byte store
-      const int64_t rb = r0 + wr * 64 + i * 16 + g * 4;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        if (!zok[j]) continue;
-        float* ocol = out + (c0 + wc * 128 + j * 16 + i16) * ldo;
-        if (rb + 3 < n) {
-          *(floatx4*)(ocol + rb) = acc[i][j];
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (rb + r < n) ocol[rb + r] = acc[i][j][r];
-        }
-      }
-    } else {
+    if (!cm) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = r0 + wr * 64 + i * 16 + g * 4 + r;
@@ -922,10 +897,23 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
       }
     }
   }
-  if (fused) {
-    // waves 0..3 hold the first 128 columns (rows 64 wr ..); two waves per 128-row record
-    __shared__ double red[8][64][2];
-    sa.finish(s0.partial, tile.r * (BM / kKblockRows), ceil_div_dev(n, kKblockRows), 2, red);
+  if (cm) {  // through LDS, 128 columns (one column half of the waves) at a time
+    __shared__ double sga[BM];
+    __shared__ float sgy[BM];
+    const ColStage<BM, 512> stage{reinterpret_cast<float(*)[BM + 4]>(smem), sga, sgy};
+    if (fused) stage.rows(s0, r0, n);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      __syncthreads();  // h = 0: the operand stages are dead; h = 1: the first half has been read back
+      if (wc == h) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) stage.put(j * 16 + i16, wr * 64 + i * 16 + g * 4, acc[i][j]);
+      }
+      stage.flush(out, ldo, n, r0, c0 + 128 * h, ncols, cidx, s0, fused && h == 0, tile.r * (BM / kKblockRows),
+                  ceil_div_dev(n, kKblockRows));
+    }
   }
 }
 
