@@ -65,7 +65,8 @@ void launch_row_hash(const TX* X, int64_t n, int64_t d, uint64_t* out, hipStream
 // First scoring pass (at s = 0) fused into the candidate block: for every 128-row tile t (of T = ceil(n / 128))
 // and column c of the first 64 columns the epilogue writes partial[(c * T + t) * 4 + {0, 1, 2, 3}] =
 // {P, Q, 0, 0}, the sums of a_i b_i and b_i^2 over the rows of the tile with a_i = 1 - y_i o_i > 0
-// (b_i = y_i k_ic), in the slot-major layout of a scoring pass.
+// (b_i = y_i k_ic), in the slot-major layout of a scoring pass. Only with column-major out (the launchers
+// reject it otherwise).
 struct Score0 {
   const float* y = nullptr;
   const double* o = nullptr;

@@ -254,13 +254,28 @@ __device__ __forceinline__ bool bracket_next(double x, double g, double r, doubl
   return nx > lo && nx < hi;
 }
 
-// 128 rows per workgroup up to 1024 workgroups; past that up to 2048 (more rows in flight for long passes;
-// for short ones the cost of reducing more partial records outweighs it).
-int score_blocks(int64_t n) {
-  const int64_t b = ceil_div(n, 128);
-  if (b <= 1024) return (int)(b < 1 ? 1 : b);
-  return (int)std::min<int64_t>(2048, ceil_div(n, 64));
+// Workgroups of the scoring pass that the device holds at once (CUs x resident workgroups per CU of the
+// heavier instance); 256 x 3 on MI355X, also the value taken when no device can be queried.
+static int score_resident() {
+  static const int v = [] {
+    int dev = 0, cus = 0, pf = 0, pd = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&pf, k_score_pass<float>, 64 * kScoreWaves, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&pd, k_score_pass<double>, 64 * kScoreWaves, 0) != hipSuccess ||
+        cus <= 0 || std::min(pf, pd) <= 0) {
+      (void)hipGetLastError();  // leave no error behind for the next launch check
+      return 768;
+    }
+    return cus * std::min(pf, pd);
+  }();
+  return v;
 }
+
+// 128 rows per workgroup, but no more workgroups than the device holds at once: a pass is then one round of
+// workgroups (a second, nearly empty round costs about as much as the first), and longer passes give each
+// workgroup more rows.
+int score_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 128), score_resident())); }
 
 template <typename TK>
 void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, const CandState* st,
