@@ -22,7 +22,19 @@ __global__ __launch_bounds__(256) void k_gemv(const TK* __restrict__ K, int64_t 
   if (row >= n) return;
   const TK* k = K + row * ldk;
   double s = 0.0;
-  for (int j = lane; j < m; j += kWave) s += (double)k[j] * x[j];
+  int j = lane;
+  for (; j + 3 * kWave < m; j += 4 * kWave) {  // four loads in flight, summed in the same order
+    TK kv[4];
+    double xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      kv[u] = k[j + u * kWave];
+      xv[u] = x[j + u * kWave];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += (double)kv[u] * xv[u];
+  }
+  for (; j < m; j += kWave) s += (double)k[j] * x[j];
   s = wave_sum(s);
   if (lane == 0) out[row] = s;
 }
@@ -161,7 +173,24 @@ __global__ __launch_bounds__(256) void k_grad_partial(const TK* __restrict__ K, 
   const int hi = lo + rows_per_chunk < n_sv ? lo + rows_per_chunk : n_sv;
   if (k >= m) return;
   double acc = 0.0;
-  for (int r = lo; r < hi; ++r) {
+  int r = lo;
+  for (; r + 8 <= hi; r += 8) {  // eight rows' loads in flight, summed in row order
+    int64_t iv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) iv[u] = I[r + u];
+    TK kv[8];
+    double ov[8];
+    float yv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      kv[u] = K[iv[u] * ldk + k];
+      ov[u] = o[iv[u]];
+      yv[u] = y[iv[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += (double)kv[u] * (ov[u] - (double)yv[u]);
+  }
+  for (; r < hi; ++r) {
     const int64_t i = I[r];
     acc += (double)K[i * ldk + k] * (o[i] - (double)y[i]);
   }
