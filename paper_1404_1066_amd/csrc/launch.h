@@ -11,12 +11,19 @@ struct CandState {
   double s, s_prev, lo, hi;  // evaluation point, previous point, bracket of the root of psi'
   double oc;                 // o at the candidate's row
   double score;              // exact decrease of f when done
+  double phi_lo, g_lo;       // psi - psi(0) and psi' at lo (when lo is finite)
+  double phi_hi, g_hi;       // the same at hi
+  double lb, ub;             // bounds on the score: best decrease seen so far; largest decrease still possible
   int32_t idx;               // training row, -1 for an empty slot
-  int32_t status;            // 0 active, 1 done, 2 skipped
+  int32_t status;            // 0 active, 1 done, 2 skipped, 3 dropped (cannot win: ub below another slot's lb)
   int32_t newton;            // s is the Newton root of the previous point's segment
   int32_t passes;
 };
 constexpr int kCandSlots = 64;
+// The slot states are followed by kCandSlots int32 drop flags (a pass marks the slots it dropped, the update
+// that follows it retires them).
+constexpr size_t kCandStateBytes = kCandSlots * sizeof(CandState) + kCandSlots * sizeof(int32_t);
+__host__ __device__ inline int32_t* cand_drop_flags(CandState* st) { return reinterpret_cast<int32_t*>(st + kCandSlots); }
 
 // Batched launches: up to kMaxBatch independent problems (slots) per launch, one grid z-index per slot; the
 // per-slot operands travel by value in the kernel arguments. 48 covers the 40 problems of one kernel width in
@@ -119,7 +126,7 @@ void launch_score_init(const int32_t* cand, const double* o, const uint64_t* has
 // partial sums per workgroup), then one workgroup per
 // slot reduces them and advances the slot. Both kernels return at once when every slot is settled.
 template <typename TK>
-void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, const CandState* st,
+void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, CandState* st,
                        double* partial, int nblk, hipStream_t s);
 // live (may be null): incremented once per slot that the pass scored (for the byte count of the passes).
 void launch_score_update(CandState* st, const double* partial, int nblk, double lam, int32_t* live, hipStream_t s);

@@ -26,6 +26,61 @@ __device__ __forceinline__ bool hash_in(uint64_t h, const uint64_t* __restrict__
   return false;
 }
 
+__device__ __forceinline__ void clear_bounds(CandState& s) {
+  s.phi_lo = s.g_lo = s.phi_hi = s.g_hi = 0.0;
+  s.lb = 0.0;  // psi(0) - psi(0)
+  s.ub = __builtin_huge_val();
+}
+
+// Largest decrease psi(0) - min psi still possible given what the passes have seen. psi'' >= lambda everywhere
+// (the regulariser's curvature; the loss terms only add to it), so at an evaluated point x
+//   psi(z) - psi(0) >= T_x(z) = phi_x + g_x (z - x) + lambda/2 (z - x)^2
+// for all z, and the minimiser lies in the bracket [lo, hi]. The minimum of max(T_lo, T_hi) over the bracket is
+// attained at a bracket end, at the unconstrained minimiser of T_lo or T_hi, or where the two cross; the bound
+// is minus the smallest of max(T_lo, T_hi) over those points (exact in real arithmetic, no iteration).
+__device__ __forceinline__ double score_upper(const CandState& s, double lam) {
+  const bool hl = s.lo > -__builtin_huge_val(), hh = s.hi < __builtin_huge_val();
+  if (!hl && !hh) return __builtin_huge_val();
+  auto L = [&](double z) {
+    double v = -__builtin_huge_val();
+    if (hl) {
+      const double u = z - s.lo;
+      v = fmax(v, s.phi_lo + s.g_lo * u + 0.5 * lam * u * u);
+    }
+    if (hh) {
+      const double u = z - s.hi;
+      v = fmax(v, s.phi_hi + s.g_hi * u + 0.5 * lam * u * u);
+    }
+    return v;
+  };
+  double m = __builtin_huge_val();
+  if (hl) {
+    m = fmin(m, L(s.lo));
+    const double z = s.lo - s.g_lo / lam;
+    if (!hh || z <= s.hi) m = fmin(m, L(z));
+  }
+  if (hh) {
+    m = fmin(m, L(s.hi));
+    const double z = s.hi - s.g_hi / lam;
+    if (!hl || z >= s.lo) m = fmin(m, L(z));
+  }
+  if (hl && hh) {  // T_lo - T_hi is linear in u = z - lo: zero at u = -c0 / c1
+    const double h = s.hi - s.lo;
+    const double c0 = s.phi_lo - s.phi_hi + s.g_hi * h - 0.5 * lam * h * h;
+    const double c1 = s.g_lo - s.g_hi + lam * h;
+    if (c1 != 0.0) {
+      const double u = -c0 / c1;
+      if (u >= 0.0 && u <= h) m = fmin(m, L(s.lo + u));
+    }
+  }
+  return -m;
+}
+
+// A slot is dropped when even its largest possible decrease is below the best decrease another slot has already
+// reached: it cannot win the argmax. The relative margin keeps rounding in the sums (far below it) from ever
+// dropping a slot whose computed final score could reach the winner's.
+constexpr double kDropMargin = 1e-7;
+
 // 64 threads: one per slot.
 __global__ void k_score_init(const int32_t* __restrict__ cand, const double* __restrict__ o,
                              const uint64_t* __restrict__ hash, const uint64_t* __restrict__ stage_hash, int n_stage,
@@ -47,6 +102,7 @@ __global__ void k_score_init(const int32_t* __restrict__ cand, const double* __r
   s.score = -__builtin_huge_val();
   s.newton = 0;
   s.passes = 0;
+  clear_bounds(s);
   if (s.idx < 0 || hash_in(hash[s.idx], sh, ns) || (n_stage > ns && hash_in(hash[s.idx], stage_hash + ns, n_stage - ns))) {
     s.status = 2;
   } else {
@@ -72,6 +128,8 @@ constexpr int kMaxPasses = 64;
 __device__ __forceinline__ int advance_slot(CandState& s, double P, double Q, double V, double F, double lam) {
   s.passes += 1;
   const double g = lam * (s.oc + s.s) - (P - s.s * Q);
+  const double phi = lam * (s.s * s.oc + 0.5 * s.s * s.s) + 0.5 * V;  // psi(s) - psi(0)
+  s.lb = fmax(s.lb, -phi);
   bool done = (s.newton && F == 0.0) || g == 0.0;
   int still = 0;
   if (!done) {
@@ -84,10 +142,18 @@ __device__ __forceinline__ int advance_slot(CandState& s, double P, double Q, do
     const double r = (P - lam * s.oc) / (lam + Q);
     double nx;
     int nw;
+    if (g < 0.0) {  // the bracket end bracket_next moves to s
+      s.phi_lo = phi;
+      s.g_lo = g;
+    } else {
+      s.phi_hi = phi;
+      s.g_hi = g;
+    }
     if (bracket_next(s.s, g, r, s.lo, s.hi, nx, nw) && s.passes < kMaxPasses) {
       s.s_prev = s.s;
       s.s = nx;
       s.newton = nw;
+      s.ub = fmax(score_upper(s, lam), s.lb);
       still = 1;
     } else {
       done = true;  // bracket exhausted or pass cap: keep the current point
@@ -95,7 +161,8 @@ __device__ __forceinline__ int advance_slot(CandState& s, double P, double Q, do
   }
   if (done) {
     s.status = 1;
-    s.score = -(lam * (s.s * s.oc + 0.5 * s.s * s.s) + 0.5 * V);
+    s.score = -phi;
+    s.lb = s.ub = s.score;
   }
   return still;
 }
@@ -112,12 +179,21 @@ __global__ __launch_bounds__(64 * kScoreWaves, 6) void k_score_pass(const TK* __
                                                                   const double* __restrict__ o, int64_t n,
                                                                   int64_t rows_per_blk,
                                                                   const CandState* __restrict__ st,
+                                                                  int32_t* __restrict__ drop,
                                                                   double* __restrict__ partial) {
   __shared__ double sh[kScoreWaves][4][kCandSlots];
   __shared__ double red[4][kCandSlots];
   __shared__ int act[kCandSlots];
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const bool live = st[lane].status == 0;
+  // Lane = slot. Slots that cannot win any more (their upper bound below the best lower bound of all slots)
+  // are dropped before the pass; every wave takes the same decision from the same states, workgroup 0 records
+  // it for the update that follows.
+  const int status = st[lane].status;
+  double best = status == 1 ? st[lane].score : (status == 0 ? st[lane].lb : -__builtin_huge_val());
+  for (int off = 32; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off, kWave));
+  const bool dropped = status == 0 && st[lane].ub < best - kDropMargin * fabs(best);
+  if (blockIdx.x == 0 && q == 0) drop[lane] = dropped ? 1 : 0;
+  const bool live = status == 0 && !dropped;
   const unsigned long long mask = __ballot(live);
   const int na = __popcll(mask);
   if (na == 0) return;  // every slot is settled (same answer in every wave and workgroup)
@@ -204,6 +280,11 @@ __global__ __launch_bounds__(256) void k_score_update(CandState* __restrict__ st
   __shared__ double red[4][4];
   const int c = blockIdx.x;
   if (st[c].status != 0) return;
+  if (cand_drop_flags(st)[c]) {  // dropped by the pass: not read, retired without a score
+    __syncthreads();  // every thread has read the status before it changes
+    if (threadIdx.x == 0) st[c].status = 3;
+    return;
+  }
   if (threadIdx.x == 0 && live) atomicAdd(live, 1);  // slot-passes: this slot was read by the pass
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblk; b += 256) {
@@ -278,10 +359,11 @@ static int score_resident() {
 int score_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 128), score_resident())); }
 
 template <typename TK>
-void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, const CandState* st,
+void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, CandState* st,
                        double* partial, int nblk, hipStream_t s) {
   const int64_t rows = round_up(ceil_div(n, nblk), kScoreWaves);
-  hipLaunchKernelGGL((k_score_pass<TK>), dim3(nblk), dim3(64 * kScoreWaves), 0, s, Kc, ldc, y, o, n, rows, st, partial);
+  hipLaunchKernelGGL((k_score_pass<TK>), dim3(nblk), dim3(64 * kScoreWaves), 0, s, Kc, ldc, y, o, n, rows, st,
+                     cand_drop_flags(st), partial);
   SPSVM_LAUNCHED();
 }
 
@@ -322,6 +404,7 @@ __global__ __launch_bounds__(256) void k_score_init_update(const int32_t* __rest
   s.score = -__builtin_huge_val();
   s.newton = 0;
   s.passes = 0;
+  clear_bounds(s);
   if (idx < 0 || taken) {
     s.status = 2;
     if (threadIdx.x == 0) st[c] = s;
@@ -445,10 +528,10 @@ void launch_select_append(const CandState* st, const uint64_t* hash, uint64_t* s
   SPSVM_LAUNCHED();
 }
 
-template void launch_score_pass<float>(const float*, int64_t, const float*, const double*, int64_t, const CandState*,
+template void launch_score_pass<float>(const float*, int64_t, const float*, const double*, int64_t, CandState*,
                                        double*, int, hipStream_t);
-template void launch_score_pass<double>(const double*, int64_t, const float*, const double*, int64_t,
-                                        const CandState*, double*, int, hipStream_t);
+template void launch_score_pass<double>(const double*, int64_t, const float*, const double*, int64_t, CandState*,
+                                        double*, int, hipStream_t);
 template void launch_select_append<float>(const CandState*, const uint64_t*, uint64_t*, int, const float*, int64_t,
                                           int64_t, double*, float*, int64_t, int64_t*, double*, int32_t*, Selection*,
                                           int32_t*, int, hipStream_t);

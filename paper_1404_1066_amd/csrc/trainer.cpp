@@ -90,7 +90,7 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.Kc = take(with_selection ? (size_t)round_up(n, 4) * kCandSlots * cand_group(d, opt.chunk_cap) * tk : 0);
   p.J = take(J_max * 8);
   p.J32 = take(J_max * 4);
-  p.cand_state = take(kCandSlots * sizeof(CandState));
+  p.cand_state = take(kCandStateBytes);
   p.sel = take(sizeof(Selection));
   p.ls = take(p.slots * sizeof(LineState));
   p.scalars = take(p.slots * sizeof(NewtonScalars));
