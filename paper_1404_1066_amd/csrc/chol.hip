@@ -402,18 +402,21 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const SolveBatch bt, int64_
   const double* __restrict__ Linv = bt.Linv[blockIdx.z];
   const double* __restrict__ g = bt.g[blockIdx.z];
   double* __restrict__ x = bt.x[blockIdx.z];
-  double* __restrict__ z = bt.work[blockIdx.z];
   __shared__ double part[16][NB];
   __shared__ double rhs[NB];
+  __shared__ double zs[1024], xs[1024];  // z = L^-1 g and x = L^-T z stay in LDS (m <= 1024 here)
   const int tid = threadIdx.x;
   const int nblk = (int)((m + NB - 1) / NB);
-  // forward
+  // forward; the inner sums keep their order (unrolled so that several rows' loads are in flight)
   for (int b = 0; b < nblk; ++b) {
     const int b0 = b * NB;
     const int r = tid >> 4, p0 = tid & 15;
     double s = 0.0;
-    if (b0 + r < m)
-      for (int p = p0; p < b0; p += 16) s += L[(int64_t)(b0 + r) * ldh + p] * z[p];
+    if (b0 + r < m) {
+      const double* __restrict__ Lr = L + (int64_t)(b0 + r) * ldh;
+#pragma unroll 8
+      for (int p = p0; p < b0; p += 16) s += Lr[p] * zs[p];
+    }
     part[p0][r] = s;
     __syncthreads();
     if (tid < NB) {
@@ -423,10 +426,11 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const SolveBatch bt, int64_
     }
     __syncthreads();
     if (tid < NB && b0 + tid < m) {
-      const double* Lo = Linv + (int64_t)b * NB * NB + (int64_t)tid * NB;
+      const double* __restrict__ Lo = Linv + (int64_t)b * NB * NB + (int64_t)tid * NB;
       double t = 0.0;
+#pragma unroll 8
       for (int p = 0; p <= tid; ++p) t += Lo[p] * rhs[p];
-      z[b0 + tid] = t;
+      zs[b0 + tid] = t;
     }
     __syncthreads();
   }
@@ -435,25 +439,28 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const SolveBatch bt, int64_
     const int b0 = b * NB;
     const int c = tid & 63, p0 = tid >> 6;
     double s = 0.0;
-    if (b0 + c < m)
-      for (int i = b0 + NB + p0; i < m; i += 16) s += L[(int64_t)i * ldh + b0 + c] * x[i];
+    if (b0 + c < m) {
+#pragma unroll 8
+      for (int i = b0 + NB + p0; i < m; i += 16) s += L[(int64_t)i * ldh + b0 + c] * xs[i];
+    }
     part[p0][c] = s;
     __syncthreads();
     if (tid < NB) {
       double t = 0.0;
       for (int q = 0; q < 16; ++q) t += part[q][tid];
-      rhs[tid] = (b0 + tid < m) ? z[b0 + tid] - t : 0.0;
+      rhs[tid] = (b0 + tid < m) ? zs[b0 + tid] - t : 0.0;
     }
     __syncthreads();
     if (tid < NB && b0 + tid < m) {
-      const double* Lo = Linv + (int64_t)b * NB * NB;
+      const double* __restrict__ Lo = Linv + (int64_t)b * NB * NB;
       double t = 0.0;
+#pragma unroll 8
       for (int p = tid; p < NB; ++p) t += Lo[(int64_t)p * NB + tid] * rhs[p];
-      x[b0 + tid] = t;
+      xs[b0 + tid] = t;
     }
     __syncthreads();
   }
-  for (int k = tid; k < m; k += 1024) x[k] = -x[k];
+  for (int k = tid; k < m; k += 1024) x[k] = -xs[k];
 }
 
 // Large m: one launch per 64-row block step, the remaining blocks updated in parallel (right-looking).

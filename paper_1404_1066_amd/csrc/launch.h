@@ -168,7 +168,7 @@ int compact_blocks(int64_t n);
 // Workgroups of a line-search pass over n rows (partial records per workgroup).
 int ls_blocks(int64_t n);
 template <typename TK>
-void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv, const double* o, const float* y,
+void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, const double* o, const float* y,
                      const double* v, const double* beta, double lam, double* partial, int nchunk, double* g,
                      NewtonScalars* sc, hipStream_t s);
 int gradient_chunks(int m, int n_sv);

@@ -165,9 +165,14 @@ void launch_compact(const double* o, const float* y, int64_t n, const uint8_t* a
 // -------------------------------------------------------------------------------------------- gradient
 template <typename TK>
 __global__ __launch_bounds__(256) void k_grad_partial(const TK* __restrict__ K, int64_t ldk, int m,
-                                                      const int32_t* __restrict__ I, int n_sv, int rows_per_chunk,
+                                                      const int32_t* __restrict__ I,
+                                                      const NewtonScalars* __restrict__ sc,
                                                       const double* __restrict__ o, const float* __restrict__ y,
                                                       double* __restrict__ partial) {
+  // |I| as the compaction left it on the device (no host read-back between compaction and gradient); the
+  // gridDim.y chunks split it evenly
+  const int n_sv = sc->n_sv;
+  const int rows_per_chunk = n_sv > (int)gridDim.y ? (n_sv + (int)gridDim.y - 1) / (int)gridDim.y : 1;
   const int k = blockIdx.x * 256 + threadIdx.x;
   const int lo = blockIdx.y * rows_per_chunk;
   const int hi = lo + rows_per_chunk < n_sv ? lo + rows_per_chunk : n_sv;
@@ -255,12 +260,11 @@ int gradient_chunks(int m, int n_sv) {
 }
 
 template <typename TK>
-void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, int n_sv, const double* o, const float* y,
+void launch_gradient(const TK* K, int64_t ldk, int m, const int32_t* I, const double* o, const float* y,
                      const double* v, const double* beta, double lam, double* partial, int nchunk, double* g,
                      NewtonScalars* sc, hipStream_t s) {
-  const int rows = (int)std::max<int64_t>(1, ceil_div(n_sv, nchunk));
   hipLaunchKernelGGL((k_grad_partial<TK>), dim3((unsigned)ceil_div(m, 256), nchunk), dim3(256), 0, s, K, ldk, m, I,
-                     n_sv, rows, o, y, partial);
+                     sc, o, y, partial);
   SPSVM_LAUNCHED();
   const int nb = (int)ceil_div(m, 64);
   double* blk = partial + (int64_t)nchunk * m;  // the partial buffer holds 1024 * 256 doubles; see gradient_chunks
@@ -1159,10 +1163,10 @@ void launch_scale(double* v, int m, double a, hipStream_t s) {
 // ------------------------------------------------------------------------------------ instantiations
 template void launch_gemv<float>(const float*, int64_t, int64_t, int, const double*, double*, hipStream_t);
 template void launch_gemv<double>(const double*, int64_t, int64_t, int, const double*, double*, hipStream_t);
-template void launch_gradient<float>(const float*, int64_t, int, const int32_t*, int, const double*, const float*,
+template void launch_gradient<float>(const float*, int64_t, int, const int32_t*, const double*, const float*,
                                      const double*, const double*, double, double*, int, double*, NewtonScalars*,
                                      hipStream_t);
-template void launch_gradient<double>(const double*, int64_t, int, const int32_t*, int, const double*, const float*,
+template void launch_gradient<double>(const double*, int64_t, int, const int32_t*, const double*, const float*,
                                       const double*, const double*, double, double*, int, double*, NewtonScalars*,
                                       hipStream_t);
 template void launch_gradient_batch<float>(const float*, int64_t, int64_t, int, const GradBatch&, hipStream_t);

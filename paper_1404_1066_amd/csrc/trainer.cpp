@@ -529,15 +529,15 @@ struct Impl {
     }
   }
 
-  // Gradient, |g|^2 and beta . K_JJ beta for the given slots (their violator sets are compacted and their
-  // n_sv read back). A batch takes the dense form, one read of K for up to kMaxBatch slots.
+  // Gradient, |g|^2 and beta . K_JJ beta for the given slots (their violator sets compacted on the device). A
+  // batch takes the dense form, one read of K for up to kMaxBatch slots.
   void gradient_slots(int m, const std::vector<int>& ids) {
     gemv_kjj_slots(m, ids, &Slot::beta, &Slot::vJ);
     if (!p.batch) {
       for (int q : ids) {
         Slot& S = slots[q];
-        launch_gradient<TK>(S.K, p.ldk, m, S.I, S.s.n_sv, S.o, S.y, S.vJ, S.beta, S.lam, S.grad_part,
-                            gradient_chunks(m, S.s.n_sv), S.g, S.sc, st);
+        launch_gradient<TK>(S.K, p.ldk, m, S.I, S.o, S.y, S.vJ, S.beta, S.lam, S.grad_part,
+                            gradient_chunks(m, (int)n), S.g, S.sc, st);
       }
       return;
     }
@@ -596,8 +596,7 @@ struct Impl {
         }
         launch_compact_batch(cb, n, st);
       }
-      read_slots();
-      gradient_slots(m, act);
+      gradient_slots(m, act);  // takes |I| from the device
       read_slots();
       std::vector<int> go, refac;
       for (int q : act) {
