@@ -331,3 +331,30 @@ def test_binary_100k_full_size_f32():
     dg = model.predict(Xg[torch.tensor(rows, device="cuda")]).cpu().numpy()
     do = oracle.predict(p.X[J], b_or, p.gamma, p.X[rows])
     assert _decision_err(dg, do) <= 1e-4
+
+
+@pytest.mark.slow
+def test_mnist_60k_full_batch_f32():
+    """The batched workload at its full size, as the benchmark's batched mode runs it: 160 one-vs-rest x
+    (C, gamma) problems on 60000 x 784 rows with a shared basis of 2000 rows, one call. The oracle re-solves
+    three of them (the first, a large-C one and the last) at that basis and checks their objectives; decision
+    values of one model are checked on 1000 sampled rows."""
+    p = datagen.make_config("mnist-60k")
+    P = p.Y.shape[0]
+    Xg = torch.tensor(p.X, dtype=torch.float32, device="cuda")
+    Yg = torch.tensor(p.Y, dtype=torch.float32, device="cuda")
+    models = lib.train_batch(Xg, Yg, p.C, p.gamma, p.J)
+    assert len(models) == P
+    big_c = int(np.flatnonzero(p.C == p.C.max())[0])
+    for q in (0, big_c, P - 1):
+        Jq, bq, Fq = models[q].get()
+        assert Jq.tolist() == p.J.tolist()
+        b_or, F_or, _ = osp.solve_fixed_J(p.X, p.Y[q], p.C[q], p.gamma[q], p.J)
+        Fo = osp.objective_at(p.X, p.Y[q], p.C[q], p.gamma[q], p.J, bq)
+        print("problem", q, "C", p.C[q], "gamma", p.gamma[q], "F_gpu", Fo, "F_oracle", F_or, "rel", (Fo - F_or) / F_or)
+        assert (Fo - F_or) / F_or <= 1e-6
+    rows = np.random.default_rng(1).choice(p.X.shape[0], 1000, replace=False)
+    _, bq, _ = models[P - 1].get()
+    dg = models[P - 1].predict(Xg[torch.tensor(rows, device="cuda")]).cpu().numpy()
+    do = oracle.predict(p.X[p.J], bq, p.gamma[P - 1], p.X[rows])
+    assert _decision_err(dg, do) <= 1e-4
