@@ -21,9 +21,16 @@ struct CandState {
 };
 constexpr int kCandSlots = 64;
 // The slot states are followed by kCandSlots int32 drop flags (a pass marks the slots it dropped, the update
-// that follows it retires them).
-constexpr size_t kCandStateBytes = kCandSlots * sizeof(CandState) + kCandSlots * sizeof(int32_t);
+// that follows it retires them), kCandSlots int32 window counts and, per slot, kWinCap window rows (a_i, b_i):
+// the rows whose violator status changes inside the window around the slot's point of the pass.
+constexpr int kWinCap = 64;
+constexpr size_t kCandStateBytes = kCandSlots * sizeof(CandState) + 2 * kCandSlots * sizeof(int32_t) +
+                                   (size_t)kCandSlots * kWinCap * 2 * sizeof(double);
 __host__ __device__ inline int32_t* cand_drop_flags(CandState* st) { return reinterpret_cast<int32_t*>(st + kCandSlots); }
+__host__ __device__ inline int32_t* cand_win_count(CandState* st) { return cand_drop_flags(st) + kCandSlots; }
+__host__ __device__ inline double* cand_win_rows(CandState* st) {
+  return reinterpret_cast<double*>(cand_win_count(st) + kCandSlots);
+}
 
 // Batched launches: up to kMaxBatch independent problems (slots) per launch, one grid z-index per slot; the
 // per-slot operands travel by value in the kernel arguments. 48 covers the 40 problems of one kernel width in

@@ -11,7 +11,10 @@
 // the value sum V, and the number of rows whose activity differs from the previous point. The update then
 // takes the Newton root of the current linear piece, (P - lambda o_c) / (lambda + Q), inside a bracket of the
 // root (bisection when it falls outside). When a Newton root has the same active set as the point it came
-// from, psi' is linear between them and the root is exact.
+// from, psi' is linear between them and the root is exact. A pass also lists, per slot, the rows whose
+// activity changes inside a window of |s| / 256 around its point s (usually none or a handful); when the root
+// lies in that window the update finds it exactly by walking those rows' breakpoints in order, without the
+// pass that would otherwise confirm it.
 #include "common.h"
 #include "launch.h"
 
@@ -110,6 +113,7 @@ __global__ void k_score_init(const int32_t* __restrict__ cand, const double* __r
     s.oc = o[s.idx];
   }
   st[c] = s;
+  cand_win_count(st)[c] = 0;
   const int na = block_sum_int(s.status == 0 ? 1 : 0, red);
   if (c == 0) sc->n_active_sel = na;
 }
@@ -120,17 +124,86 @@ void launch_score_init(const int32_t* cand, const double* o, const uint64_t* has
   SPSVM_LAUNCHED();
 }
 
+// a_i - z b_i with one rounding; every kernel that classifies rows as active (> 0) uses this form, so the
+// pass sums, the flip counts and the window lists agree row by row.
+__device__ __forceinline__ double gap_at(double a, double b, double z) { return __fma_rn(-z, b, a); }
+
+constexpr double kWinFrac = 1.0 / 256.0;  // window half-width relative to |s|
+
+struct WinRoot {
+  bool found;
+  double r, phi;  // root and psi(r) - psi(0)
+};
+
+// Exact root of psi' inside the window [s - w, s + w], from the sums at s (P, Q over the rows active at s, V)
+// and the cnt window rows sorted by breakpoint along the direction of descent (ra, rb). Segment k has the rows
+// of the first k breakpoints toggled; its linear root is accepted when it lies in the window and every window
+// row is active there exactly as segment k assumes (then no other row changes either: each row's activity is
+// monotone in z, and rows off the list keep theirs over the window). psi(r) is continued from psi(s) with the
+// exact change of each row's term.
+__device__ WinRoot window_root(const CandState& st, double P, double Q, double V, double lam, const double* ra,
+                               const double* rb, int cnt, double w) {
+  WinRoot out{false, 0.0, 0.0};
+  const double s = st.s, zl = s - w, zh = s + w;
+  double Pc = P, Qc = Q;
+  for (int k = 0; k <= cnt; ++k) {
+    const double r = (Pc - lam * st.oc) / (lam + Qc);
+    if (r >= zl && r <= zh) {
+      bool ok = true;
+      for (int j = 0; j < cnt && ok; ++j) {
+        const bool flips = (gap_at(ra[j], rb[j], s) > 0.0) != (gap_at(ra[j], rb[j], r) > 0.0);
+        ok = flips == (j < k);
+      }
+      if (ok) {
+        // rows active at both points: the sums at s without the rows that went inactive
+        double Pb = P, Qb = Q, dv = 0.0;
+        for (int j = 0; j < k; ++j) {
+          const double es = gap_at(ra[j], rb[j], s), er = gap_at(ra[j], rb[j], r);
+          if (es > 0.0) {
+            Pb -= ra[j] * rb[j];
+            Qb -= rb[j] * rb[j];
+            dv -= es * es;
+          } else {
+            dv += er * er;
+          }
+        }
+        dv += (s - r) * (2.0 * Pb - (s + r) * Qb);
+        out.found = true;
+        out.r = r;
+        out.phi = lam * (r * st.oc + 0.5 * r * r) + 0.5 * (V + dv);
+        return out;
+      }
+    }
+    if (k < cnt) {
+      if (gap_at(ra[k], rb[k], s) > 0.0) {
+        Pc -= ra[k] * rb[k];
+        Qc -= rb[k] * rb[k];
+      } else {
+        Pc += ra[k] * rb[k];
+        Qc += rb[k] * rb[k];
+      }
+    }
+  }
+  return out;
+}
+
 // Advance one slot after a pass (sums P, Q, V and the flip count F at the slot's current point s).
 __device__ __forceinline__ bool bracket_next(double x, double g, double r, double& lo, double& hi, double& nx,
                                              int& newton);
 constexpr int kMaxPasses = 64;
 
-__device__ __forceinline__ int advance_slot(CandState& s, double P, double Q, double V, double F, double lam) {
+__device__ __forceinline__ int advance_slot(CandState& s, double P, double Q, double V, double F, double lam,
+                                            const WinRoot* wr = nullptr) {
   s.passes += 1;
   const double g = lam * (s.oc + s.s) - (P - s.s * Q);
-  const double phi = lam * (s.s * s.oc + 0.5 * s.s * s.s) + 0.5 * V;  // psi(s) - psi(0)
+  double phi = lam * (s.s * s.oc + 0.5 * s.s * s.s) + 0.5 * V;  // psi(s) - psi(0)
   s.lb = fmax(s.lb, -phi);
   bool done = (s.newton && F == 0.0) || g == 0.0;
+  if (!done && wr && wr->found) {  // exact root inside the window of this pass
+    s.s = wr->r;
+    phi = wr->phi;
+    done = true;
+  }
   int still = 0;
   if (!done) {
     const double r = (P - lam * s.oc) / (lam + Q);
@@ -180,6 +253,8 @@ __global__ __launch_bounds__(64 * kScoreWaves, 6) void k_score_pass(const TK* __
                                                                   int64_t rows_per_blk,
                                                                   const CandState* __restrict__ st,
                                                                   int32_t* __restrict__ drop,
+                                                                  int32_t* __restrict__ wcnt,
+                                                                  double* __restrict__ wrows,
                                                                   double* __restrict__ partial) {
   __shared__ double sh[kScoreWaves][4][kCandSlots];
   __shared__ double red[4][kCandSlots];
@@ -206,6 +281,14 @@ __global__ __launch_bounds__(64 * kScoreWaves, 6) void k_score_pass(const TK* __
     const TK* __restrict__ kc = Kc + (int64_t)c * ldc;  // the slot's candidate column
     const double s = st[c].s, sp = st[c].s_prev;
     const bool chk = st[c].passes > 0;
+    // A row's activity changes inside [s - w, s + w] only if |a_i - s b_i| <= w |b_i| (exactly; the gap is one
+    // correctly rounded fma, so its sign is exact, and s -+ w and the product add relative errors near 2^-52):
+    // the test below with a 1e-4 relative margin lists every such row, and possibly a few more, which the
+    // walk classifies exactly.
+    const double wt = 1.0001 * kWinFrac * fabs(s);
+    const bool win = wt > 0.0;
+    int32_t* __restrict__ cnt = wcnt + c;
+    double* __restrict__ rows = wrows + (int64_t)c * kWinCap * 2;
     const int64_t lo = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t hi = lo + rows_per_blk < n ? lo + rows_per_blk : n;
     constexpr int U = 8;
@@ -213,14 +296,23 @@ __global__ __launch_bounds__(64 * kScoreWaves, 6) void k_score_pass(const TK* __
     double P2 = 0.0, Q2 = 0.0, V2 = 0.0;
     int fl = 0, fl2 = 0;
     auto one = [&](double av, double b, double& Pa, double& Qa, double& Va, int& fa) {
-      const double e = av - s * b;
+      const double e = gap_at(av, b, s);
       const double ua = fmax(av, 0.0), we = fmax(e, 0.0);
       // selects rather than branches (adding an exact zero leaves a sum unchanged), so that no control flow
       // keeps the compiler from issuing a chunk's loads together
       Pa += e > 0.0 ? av * b : 0.0;
       Qa += e > 0.0 ? b * b : 0.0;
       Va += (we - ua) * (we + ua);
-      fa += chk && ((e > 0.0) != (av - sp * b > 0.0)) ? 1 : 0;
+      fa += chk && ((e > 0.0) != (gap_at(av, b, sp) > 0.0)) ? 1 : 0;
+      // rows whose activity changes inside the window (rare): appended to the slot's list while it has room
+      if (win && fabs(e) <= wt * fabs(b) &&
+          __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < kWinCap) {
+        const int k = atomicAdd(cnt, 1);
+        if (k < kWinCap) {
+          rows[2 * k] = av;
+          rows[2 * k + 1] = b;
+        }
+      }
     };
     // chunks of U consecutive rows per lane (contiguous loads from the column), even rows summed apart from odd
     int64_t i = lo + (int64_t)(q * R + r) * U;
@@ -285,6 +377,7 @@ __global__ __launch_bounds__(256) void k_score_update(CandState* __restrict__ st
     if (threadIdx.x == 0) st[c].status = 3;
     return;
   }
+  __shared__ double wa[kWinCap], wb[kWinCap];
   if (threadIdx.x == 0 && live) atomicAdd(live, 1);  // slot-passes: this slot was read by the pass
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblk; b += 256) {
@@ -300,13 +393,51 @@ __global__ __launch_bounds__(256) void k_score_update(CandState* __restrict__ st
 #pragma unroll
     for (int k = 0; k < 4; ++k) red[w][k] = v[k];
   __syncthreads();
-  if (threadIdx.x == 0) {
+  // wave 0: the window rows sorted by breakpoint along the descent direction (rank sort over the lanes; equal
+  // keys ordered by value, so the order never depends on the order the pass appended them), then lane 0 walks
+  // them and advances the slot
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
     double t[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) t[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
     CandState cs = st[c];
-    advance_slot(cs, t[0], t[1], t[2], t[3], lam);
-    st[c] = cs;
+    int32_t* cntp = cand_win_count(st) + c;
+    const int cnt = *cntp;
+    const double w = kWinFrac * fabs(cs.s);
+    const bool usable = w > 0.0 && cnt <= kWinCap;
+    const bool any = cnt > 0;
+    WinRoot wr{false, 0.0, 0.0};
+    if (usable) {
+      const double g = lam * (cs.oc + cs.s) - (t[0] - cs.s * t[1]);
+      const double dir = g < 0.0 ? 1.0 : -1.0;
+      const bool real = lane < cnt;
+      const double* rows = cand_win_rows(st) + (int64_t)c * kWinCap * 2;
+      const double a = real ? rows[2 * lane] : 0.0, b = real ? rows[2 * lane + 1] : 0.0;
+      double key = real ? dir * (a / b - cs.s) : 0.0;
+      if (!(key >= 0.0)) key = __builtin_huge_val();  // breakpoints behind s are never crossed
+      int rank = 0;
+      for (int j = 0; any && j < cnt; ++j) {  // only real entries can come before a real one
+        const bool rj = __shfl((int)real, j, kWave) != 0;
+        const double kj = __shfl(key, j, kWave), aj = __shfl(a, j, kWave), bj = __shfl(b, j, kWave);
+        const bool before = (rj && !real) ||
+                            (rj == real && (kj < key || (kj == key && (aj < a || (aj == a && (bj < b || (bj == b && j < lane)))))));
+        rank += before ? 1 : 0;
+      }
+      if (real) {
+        wa[rank] = a;
+        wb[rank] = b;
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      if (lane == 0 && cs.status == 0) wr = window_root(cs, t[0], t[1], t[2], lam, wa, wb, cnt, w);
+    }
+    if (lane == 0) {
+      advance_slot(cs, t[0], t[1], t[2], t[3], lam, &wr);
+      st[c] = cs;
+      *cntp = 0;  // the next pass lists the window of the slot's next point
+    }
   }
 }
 
@@ -363,7 +494,7 @@ void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* 
                        double* partial, int nblk, hipStream_t s) {
   const int64_t rows = round_up(ceil_div(n, nblk), kScoreWaves);
   hipLaunchKernelGGL((k_score_pass<TK>), dim3(nblk), dim3(64 * kScoreWaves), 0, s, Kc, ldc, y, o, n, rows, st,
-                     cand_drop_flags(st), partial);
+                     cand_drop_flags(st), cand_win_count(st), cand_win_rows(st), partial);
   SPSVM_LAUNCHED();
 }
 
@@ -386,7 +517,10 @@ __global__ __launch_bounds__(256) void k_score_init_update(const int32_t* __rest
   __shared__ int taken;
   const int c = blockIdx.x;
   const int idx = cand[c];
-  if (threadIdx.x == 0) taken = 0;
+  if (threadIdx.x == 0) {
+    taken = 0;
+    cand_win_count(st)[c] = 0;  // no window list for the first pass, which came with the kernel block
+  }
   __syncthreads();
   if (idx >= 0) {
     const uint64_t h = hash[idx];
