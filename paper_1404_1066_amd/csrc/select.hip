@@ -247,7 +247,7 @@ __device__ __forceinline__ int advance_slot(CandState& s, double P, double Q, do
 // live slot. The per-lane sums are added over the waves, then over r, in a fixed order, and written as this
 // workgroup's record {P, Q, V, flips} of each live slot.
 template <typename TK>
-__global__ __launch_bounds__(64 * kScoreWaves, 6) void k_score_pass(const TK* __restrict__ Kc, int64_t ldc,
+__global__ __launch_bounds__(64 * kScoreWaves, 5) void k_score_pass(const TK* __restrict__ Kc, int64_t ldc,
                                                                   const float* __restrict__ y,
                                                                   const double* __restrict__ o, int64_t n,
                                                                   int64_t rows_per_blk,
