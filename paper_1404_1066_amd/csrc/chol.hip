@@ -24,6 +24,15 @@ constexpr int NB_LD = NB + 1;
 constexpr int SB = 16;
 
 // Grid z = slot of the batch.
+// Value of v in lane l of the wave (l the same for every lane, a constant once the loops are unrolled): two
+// v_readlane reads of the halves instead of a 64-bit shuffle through the LDS crossbar.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __global__ __launch_bounds__(256) void k_potrf_diag(const CholBatch bt, int64_t ldh, int m, int k0) {
   double* __restrict__ H = bt.H[blockIdx.z];
   double* __restrict__ Linv = bt.Linv[blockIdx.z];
@@ -55,7 +64,7 @@ __global__ __launch_bounds__(256) void k_potrf_diag(const CholBatch bt, int64_t 
     const int c0 = kb * SB;
     if (w == 0) {
       // Unblocked factorisation and inversion of the 16 x 16 diagonal sub-block in registers: lane l < 16
-      // holds column l (a[i] = A[c0 + i][c0 + l]); column j is broadcast with wave shuffles.
+      // holds column l (a[i] = A[c0 + i][c0 + l]); column j is broadcast with lane reads.
       double a[SB], x[SB];
 #pragma unroll
       for (int i = 0; i < SB; ++i) a[i] = lane < SB ? A[c0 + i][c0 + lane] : 0.0;
@@ -64,7 +73,7 @@ __global__ __launch_bounds__(256) void k_potrf_diag(const CholBatch bt, int64_t 
       for (int j = 0; j < SB; ++j) {
         double pc[SB];
 #pragma unroll
-        for (int i = 0; i < SB; ++i) pc[i] = __shfl(a[i], j, kWave);
+        for (int i = 0; i < SB; ++i) pc[i] = lane_value(a[i], j);
         const double piv = pc[j];
         const bool ok = piv > 0.0 && piv < __builtin_huge_val();
         badl |= !ok;
