@@ -467,7 +467,8 @@ __device__ __forceinline__ bool bracket_next(double x, double g, double r, doubl
 }
 
 // Workgroups of the scoring pass that the device holds at once (CUs x resident workgroups per CU of the
-// heavier instance); 256 x 3 on MI355X, also the value taken when no device can be queried.
+// heavier instance); 256 x 2 on MI355X (five waves per SIMD: two 8-wave workgroups per CU), also the value
+// taken when no device can be queried.
 static int score_resident() {
   static const int v = [] {
     int dev = 0, cus = 0, pf = 0, pd = 0;
@@ -477,7 +478,7 @@ static int score_resident() {
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&pd, k_score_pass<double>, 64 * kScoreWaves, 0) != hipSuccess ||
         cus <= 0 || std::min(pf, pd) <= 0) {
       (void)hipGetLastError();  // leave no error behind for the next launch check
-      return 768;
+      return 512;
     }
     return cus * std::min(pf, pd);
   }();
