@@ -193,8 +193,10 @@ class Model:
         self._ptr = ctypes.c_void_p(ptr)
 
     def __del__(self):
-        if getattr(self, "_ptr", None) is not None and self._ptr.value:
-            load().spsvm_model_free(self._ptr)
+        ptr = getattr(self, "_ptr", None)
+        # at interpreter exit the module's globals may already be gone; the process frees the memory then
+        if ptr is not None and ptr.value and _lib is not None:
+            _lib.spsvm_model_free(ptr)
             self._ptr = ctypes.c_void_p(None)
 
     @property

@@ -584,6 +584,10 @@ void launch_score_init_update(const int32_t* cand, const double* o, const uint64
 // argmax from the slot states; workgroup 0 alone records it (J, beta, the stage hash, the pass counters and
 // the next basis size). The basis size is double-buffered by step parity: step q reads m_dev[q & 1] and
 // writes m_dev[(q + 1) & 1], so no workgroup reads a value another one has already advanced.
+// A step whose slots did not all settle within the launched passes selects nothing, sets incomplete[0] and
+// records its index in incomplete[4]; every later step of the same launch sequence then selects nothing
+// either (incomplete[0] is already set when it starts), so o, J and the basis size stay as they were after the
+// last complete step and the stage can be resumed from the recorded step.
 template <typename TK>
 __global__ __launch_bounds__(256) void k_select_append(const CandState* __restrict__ st,
                                                        const uint64_t* __restrict__ hash,
@@ -597,8 +601,11 @@ __global__ __launch_bounds__(256) void k_select_append(const CandState* __restri
   if (threadIdx.x < kWave) {
     const int c = threadIdx.x;
     const CandState s = st[c];
+    // an earlier step of this sequence did not settle (read before this step's own flag can be set; a workgroup
+    // that sees this step's flag instead is in a step that selects nothing anyway)
+    const bool after_fail = incomplete[0] != 0;
     const int pending = __any(s.status == 0);  // a slot still being scored: this step must be redone
-    const bool ok = !pending && s.status == 1 && s.idx >= 0 && !(s.score != s.score);
+    const bool ok = !pending && !after_fail && s.status == 1 && s.idx >= 0 && !(s.score != s.score);
     double best = ok ? s.score : -__builtin_huge_val();
     int bidx = ok ? s.idx : 0x7fffffff;
     int bslot = c;
@@ -623,7 +630,10 @@ __global__ __launch_bounds__(256) void k_select_append(const CandState* __restri
       r.pos = m_dev[q & 1];
       choice = r;
       if (blockIdx.x == 0) {
-        if (pending) *incomplete = 1;
+        if (pending && !after_fail) {
+          incomplete[0] = 1;
+          incomplete[4] = q;  // the first step to redo
+        }
         if (r.valid) {
           J[r.pos] = bidx;
           beta[r.pos] = r.s;

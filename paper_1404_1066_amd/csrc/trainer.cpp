@@ -103,8 +103,7 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.xjnorm = take(J_max * 8);
   p.KJJ = take((size_t)J_max * p.ldh * 8);
   p.iota = take(J_max * 4);
-  p.incomplete = take(16);
-  p.o_stage = take(with_selection ? n * 8 : 0);
+  p.incomplete = take(32);  // [0] a step did not settle, [1] most passes needed, [2] working passes, [3] slot-passes, [4] first step to redo
   p.Xp = take(p.pad_x ? (size_t)n * p.ldx * xe : 0);
   p.D = take(batch ? (size_t)n * p.ldk * tk : 0);
   p.DJJ = take(batch ? (size_t)J_max * p.ldh * 8 : 0);
@@ -251,7 +250,7 @@ struct Impl {
   TK *xnorm, *KXJ, *Kc;
   uint64_t *hash, *stage_hash;
   double *o, *delta, *beta, *dvec, *g, *z, *H, *Linv, *syrk_part, *grad_part, *score_part, *ls_part, *cblk_sum;
-  double *XJ64, *xjnorm, *KJJ, *vJ, *wJ, *o_stage, *Hf;
+  double *XJ64, *xjnorm, *KJJ, *vJ, *wJ, *Hf;
   int32_t *iota, *incomplete, *F_in, *F_out, *fcnt_in, *fcnt_out;
   bool bf16_exact = false;  // every X value is exactly a BF16 number (split-BF16 lo parts are all zero)
   uint8_t *act_fact, *act_cur;
@@ -321,7 +320,6 @@ struct Impl {
     KJJ = at<double>(p.KJJ);
     iota = at<int32_t>(p.iota);
     incomplete = at<int32_t>(p.incomplete);
-    o_stage = at<double>(p.o_stage);
     slots.resize(p.slots);
     for (int q = 0; q < p.slots; ++q) {
       Slot& S = slots[q];
@@ -863,26 +861,26 @@ struct Impl {
       int32_t* tp = (int32_t*)((char*)pin.p + kPinnedScalars);
       std::memcpy(tp, table.data(), (size_t)cs * kCandSlots * 4);
       SPSVM_HIP(hipMemcpyAsync(cand_table, tp, (size_t)cs * kCandSlots * 4, hipMemcpyHostToDevice, st));
-      // One attempt runs every step of the stage without host synchronisation. A step whose slots did not all
-      // converge within the launched passes selects nothing and flags the stage, which is then rerun from its
-      // saved start state with more passes (64 passes always suffice: the update stops every slot by then).
-      SPSVM_HIP(hipMemcpyAsync(o_stage, o, n * 8, hipMemcpyDeviceToDevice, st));
+      // One attempt runs the steps of the stage without host synchronisation. A step whose slots did not all
+      // converge within the launched passes selects nothing, and so does every later step of the attempt; the
+      // stage then resumes from that step (o, J and the basis size are as the last complete step left them)
+      // with more passes (64 passes always suffice: the update stops every slot by then).
+      const int G = cand_group(d, opt.chunk_cap);
+      int qstart = 0, m_q = m;  // first step of the attempt and the basis size it starts from
       for (int attempt = 0;; ++attempt) {
-        // passes launched per step: one more than the most any step of the previous stage needed
-        const int rounds = attempt == 0 ? first_rounds : (attempt == 1 ? std::max(2 * first_rounds, 12) : 64);
+        const int rounds = attempt == 0   ? first_rounds
+                           : attempt == 1 ? std::min(64, first_rounds + 2)
+                           : attempt == 2 ? std::min(64, std::max(12, 2 * first_rounds + 4))
+                                          : 64;
         {
           // the stage's steps read the basis size at m_dev[q & 1] and leave the next one at m_dev[(q + 1) & 1]
           int32_t* mh = (int32_t*)((char*)pin.p + 8192);
-          *mh = m;
-          SPSVM_HIP(hipMemcpyAsync(m_dev, mh, 4, hipMemcpyHostToDevice, st));
+          *mh = m_q;
+          SPSVM_HIP(hipMemcpyAsync(m_dev + (qstart & 1), mh, 4, hipMemcpyHostToDevice, st));
         }
-        if (attempt > 0) {
-          SPSVM_HIP(hipMemcpyAsync(o, o_stage, n * 8, hipMemcpyDeviceToDevice, st));
-          stats.stage_redos += 1;
-        }
-        SPSVM_HIP(hipMemsetAsync(incomplete, 0, 16, st));
-        const int G = cand_group(d, opt.chunk_cap);
-        for (int q0 = 0; q0 < cs; q0 += G) {
+        if (attempt > 0) stats.stage_redos += 1;
+        SPSVM_HIP(hipMemsetAsync(incomplete, 0, 32, st));
+        for (int q0 = qstart; q0 < cs; q0 += G) {
           const int gsz = std::min(G, cs - q0);  // steps sharing this kernel-block launch
           const int64_t ldc = round_up(n, 4);     // candidate columns, column-major (one contiguous column each)
           int ncand = 0;
@@ -917,14 +915,20 @@ struct Impl {
                                      incomplete, j == 0 ? 1 : 0, st);
           }
         }
-        int32_t flags2[4];
-        SPSVM_HIP(hipMemcpyAsync(pin.p, incomplete, 16, hipMemcpyDeviceToHost, st));
+        int32_t flags2[8];
+        SPSVM_HIP(hipMemcpyAsync(pin.p, incomplete, 32, hipMemcpyDeviceToHost, st));
         sync();
-        std::memcpy(flags2, pin.p, 16);
+        std::memcpy(flags2, pin.p, 32);
         stats.score_passes_active += flags2[2];
         stats.score_slot_passes += flags2[3];
-        first_rounds = std::min(64, std::max(3, flags2[1] + 1));
+        // passes for the next stage: as many as the most any step needed, plus one in reserve unless every step
+        // of this attempt needed exactly that many (one kernel-block launch per step, so each step's count is
+        // its own: a uniform stage predicts the next one well, and a miss only resumes from the step concerned)
+        const bool uniform = G == 1 && flags2[0] == 0 && flags2[2] == (cs - qstart) * (flags2[1] - 1);
+        first_rounds = std::min(64, std::max(2, flags2[1] + (uniform ? 0 : 1)));
         if (flags2[0] == 0 || rounds >= 64) break;
+        qstart = flags2[4];
+        m_q = read(m_dev + (cs & 1));  // the steps after the incomplete one left the size unchanged
       }
       t += cs;
       const int m_new = read(m_dev + (cs & 1));

@@ -47,7 +47,7 @@ struct Plan {
   size_t bytes = 0;
   // offsets into the workspace (shared by all slots)
   size_t xnorm, hash, KXJ, Kc, J, J32, cand_state, sel, ls, scalars, score_part, cand_table, stage_hash, m_dev, flags,
-      XJ64, xjnorm, KJJ, iota, incomplete, o_stage, Xp, D, DJJ, G, Xhi, Xlo;
+      XJ64, xjnorm, KJJ, iota, incomplete, Xp, D, DJJ, G, Xhi, Xlo;
   int64_t ldb = 0;  // row stride of the split-BF16 copies (MIXED)
   // per-problem regions: slot q starts at slots_at + q * slot.bytes; ls and scalars hold one entry per slot
   SlotPlan slot;
