@@ -404,6 +404,9 @@ void launch_cholesky(double* H, int64_t ldh, int m, double* Linv, NewtonScalars*
 }
 
 // ----------------------------------------------------------------------------------- triangular solves
+// Largest m solved by one workgroup per problem: z and x (16 m bytes of LDS) plus the partial sums fit in 64 KB.
+constexpr int kSolveOneMax = 3328;
+
 // One workgroup of 1024 threads. Forward: z_b = Linv_b (g_b - L[b, <b] z_<b); backward:
 // x_b = Linv_b^T (z_b - L[>b, b]^T x_>b); the result is negated (x = -H^{-1} g).
 __global__ __launch_bounds__(1024) void k_chol_solve(const SolveBatch bt, int64_t ldh, int m) {
@@ -413,7 +416,9 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const SolveBatch bt, int64_
   double* __restrict__ x = bt.x[blockIdx.z];
   __shared__ double part[16][NB];
   __shared__ double rhs[NB];
-  __shared__ double zs[1024], xs[1024];  // z = L^-1 g and x = L^-T z stay in LDS (m <= 1024 here)
+  extern __shared__ double zx[];  // z = L^-1 g and x = L^-T z stay in LDS: 2 m doubles (m <= kSolveOneMax)
+  double* zs = zx;
+  double* xs = zx + m;
   const int tid = threadIdx.x;
   const int nblk = (int)((m + NB - 1) / NB);
   // forward; the inner sums keep their order (unrolled so that several rows' loads are in flight)
@@ -472,7 +477,7 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const SolveBatch bt, int64_
   for (int k = tid; k < m; k += 1024) x[k] = -xs[k];
 }
 
-// Large m: one launch per 64-row block step, the remaining blocks updated in parallel (right-looking).
+// m > kSolveOneMax: one launch per 64-row block step, the remaining blocks updated in parallel (right-looking).
 // Forward, step b: every workgroup forms z_b = Linv_b r_b (r: right-hand side, held in x); the one for
 // block b stores z_b, the others update their own block r_rb -= L[rb, b] z_b. Backward, step b: every
 // workgroup forms x_b = Linv_b^T z_b; the one for block b stores -x_b, the others update z_rb -= L[b, rb]^T x_b.
@@ -557,8 +562,8 @@ void launch_chol_solve_batch(const SolveBatch& b, int64_t ldh, int m, hipStream_
   if (b.count <= 0 || m <= 0) return;
   if (b.count > kMaxBatch) throw Failure(1, "solve batch: too many slots");
   const unsigned nz = (unsigned)b.count;
-  if (m <= 1024) {  // one workgroup per problem: fewer launches than block steps
-    hipLaunchKernelGGL(k_chol_solve, dim3(1, 1, nz), dim3(1024), 0, s, b, ldh, m);
+  if (m <= kSolveOneMax) {  // one workgroup per problem: no launch per block step
+    hipLaunchKernelGGL(k_chol_solve, dim3(1, 1, nz), dim3(1024), (size_t)2 * m * sizeof(double), s, b, ldh, m);
     SPSVM_LAUNCHED();
     return;
   }
