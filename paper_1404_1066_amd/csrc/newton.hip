@@ -213,8 +213,10 @@ __global__ __launch_bounds__(1024) void k_grad_reduce(int m, const double* __res
   const int c = threadIdx.x & 63, j = threadIdx.x >> 6;
   const int k = blockIdx.x * 64 + c;
   double a = 0.0;
-  if (k < m)
-    for (int q = j; q < nchunk; q += 16) a += partial[(int64_t)q * m + k];
+  if (k < m) {
+#pragma unroll 8
+    for (int q = j; q < nchunk; q += 16) a += partial[(int64_t)q * m + k];  // in order; loads issued ahead
+  }
   red[j][c] = a;
   __syncthreads();
   if (threadIdx.x < 64) {
@@ -492,7 +494,8 @@ __global__ __launch_bounds__(256) void k_syrk_reduce(const ReduceBatch b, int m,
   if (gr >= m || gc >= m || gc > gr) return;
   const double* __restrict__ partial = b.partial[q];
   double s = 0.0;
-  for (int p = 0; p < nsplit; ++p) s += partial[((int64_t)p * ntiles + blockIdx.x) * (SY_T * SY_T) + idx];
+#pragma unroll 8
+  for (int p = 0; p < nsplit; ++p) s += partial[((int64_t)p * ntiles + blockIdx.x) * (SY_T * SY_T) + idx];  // in order
   double* h = b.H[q] + (int64_t)gr * ldh + gc;
   if (mode == 0)
     *h = b.lam[q] * b.KJJ[q][(int64_t)gr * ldh + gc] + s;
