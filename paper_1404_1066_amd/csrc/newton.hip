@@ -762,7 +762,8 @@ __global__ __launch_bounds__(1024) void k_grad_reduce_batch(int m, int nchunk, c
   const double* partial = b.partial[q];
   double a = 0.0;
   if (k < m)
-    for (int p = j; p < nchunk; p += 16) a += partial[(int64_t)p * m + k];
+#pragma unroll 8
+    for (int p = j; p < nchunk; p += 16) a += partial[(int64_t)p * m + k];  // in order; loads issued ahead
   red[j][c] = a;
   __syncthreads();
   if (threadIdx.x < 64) {
@@ -1028,6 +1029,7 @@ __global__ __launch_bounds__(256) void k_ls_update(const LsBatch bt, int nblk) {
   if (ls->status != 0) return;
   {
     double a[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll 4
     for (int b = threadIdx.x; b < nblk; b += 256)
       for (int k = 0; k < 6; ++k) a[k] += partial[(int64_t)b * 6 + k];
     for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = a[k];

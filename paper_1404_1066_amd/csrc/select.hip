@@ -380,7 +380,8 @@ __global__ __launch_bounds__(256) void k_score_update(CandState* __restrict__ st
   __shared__ double wa[kWinCap], wb[kWinCap];
   if (threadIdx.x == 0 && live) atomicAdd(live, 1);  // slot-passes: this slot was read by the pass
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nblk; b += 256) {
+#pragma unroll 4
+  for (int b = threadIdx.x; b < nblk; b += 256) {  // in order; several records in flight
     const doublex4 p = *(const doublex4*)(partial + ((int64_t)c * nblk + b) * 4);
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] += p[k];
@@ -548,7 +549,8 @@ __global__ __launch_bounds__(256) void k_score_init_update(const int32_t* __rest
   s.status = 0;
   s.oc = o[idx];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nblk; b += 256) {
+#pragma unroll 4
+  for (int b = threadIdx.x; b < nblk; b += 256) {  // in order; several records in flight
     const doublex4 p = *(const doublex4*)(partial + ((int64_t)c * nblk + b) * 4);
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] += p[k];
