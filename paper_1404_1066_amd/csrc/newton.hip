@@ -47,7 +47,7 @@ void launch_gemv(const TK* K, int64_t ldk, int64_t n, int m, const double* x, do
 }
 
 // ------------------------------------------------------------------------------------------ compaction
-constexpr int kCompactRows = 4096;  // rows per block: 16 chunks of 256
+constexpr int kCompactRows = 1024;  // rows per block: 4 chunks of 256 (about 100 workgroups at n = 100000)
 
 
 // Grid y = slot of the batch.
@@ -62,12 +62,20 @@ __global__ __launch_bounds__(256) void k_compact_count(const CompactBatch bt, in
   __shared__ double rd[4];
   __shared__ int ri[4];
   const int64_t lo = (int64_t)blockIdx.x * kCompactRows;
+  constexpr int NJ = kCompactRows / 256;
   int c = 0, fl = 0;
   double s = 0.0;
-  for (int j = 0; j < kCompactRows / 256; ++j) {
+  double av[NJ];  // every row's loads first (the rows of a block are few, so latency decides), then in order
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int64_t i = lo + j * 256 + threadIdx.x;
+    av[j] = i < n ? margin_gap(y[i], o[i]) : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
     const int64_t i = lo + j * 256 + threadIdx.x;
     if (i < n) {
-      const double a = margin_gap(y[i], o[i]);
+      const double a = av[j];
       const int v = a > 0.0;
       c += v;
       if (v) s += a * a;
@@ -102,13 +110,18 @@ __global__ __launch_bounds__(256) void k_compact_write(const CompactBatch bt, in
   int offset = block_sum_int(part, ri);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t lo = (int64_t)blockIdx.x * kCompactRows;
-  for (int j = 0; j < kCompactRows / 256; ++j) {
+  constexpr int NJ = kCompactRows / 256;
+  bool vr[NJ];  // every row classified first (all loads in flight), then the ranks chunk by chunk
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
     const int64_t i = lo + j * 256 + threadIdx.x;
-    int v = 0;
-    if (i < n) {
-      v = margin_gap(y[i], o[i]) > 0.0;
-      act_out[i] = (uint8_t)v;
-    }
+    vr[j] = i < n && margin_gap(y[i], o[i]) > 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int64_t i = lo + j * 256 + threadIdx.x;
+    const int v = vr[j] ? 1 : 0;
+    if (i < n) act_out[i] = (uint8_t)v;
     const unsigned long long mask = __ballot(v);
     const int rank = __popcll(mask & ((1ull << lane) - 1ull));
     if (lane == 0) wc[w] = __popcll(mask);
@@ -122,7 +135,8 @@ __global__ __launch_bounds__(256) void k_compact_write(const CompactBatch bt, in
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     int tot = 0, fl = 0;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) {
+#pragma unroll 8
+    for (int b = 0; b < nblk; ++b) {  // in order; several blocks' values in flight
       tot += cnt[b];
       fl += bflips[b];
       s += bsum[b];
