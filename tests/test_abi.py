@@ -118,3 +118,13 @@ def test_host_candidate_draw_matches_oracle_generator():
         assert a == b
     total = [lib.candidate_draw(3, t, 100) for t in range(200)]
     assert all(len(c) == 59 and len(set(c)) == 59 for c in total)
+
+
+def test_host_candidate_draw_stream_start_matches_hand_worked_values():
+    """The library's sampler against the first indices worked by hand from the published generator outputs."""
+    path = os.path.join(ROOT, "tests", "golden", "candidate_stream_start.txt")
+    lines = [ln for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    for ln in lines:
+        seed, t, n, idx = [p.strip() for p in ln.split(";")]
+        want = [int(v) for v in idx.split(",")]
+        assert lib.candidate_draw(int(seed, 0), int(t), int(n))[:len(want)] == want

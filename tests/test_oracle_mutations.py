@@ -88,3 +88,60 @@ def test_score_without_regulariser_changes_selection(monkeypatch):
 
     monkeypatch.setattr(osp, "score_candidate", wrong)
     assert pins.selection_bruteforce_mismatches() > 0
+
+
+def _jitter_fails():
+    try:
+        return pins.jitter_error() > 1e-11
+    except osp.NotPositiveDefinite:  # the planted schedule gave up where the right one succeeds
+        return True
+
+
+def test_jitter_without_diagonal_scale_is_caught(monkeypatch):
+    def wrong(H):
+        try:
+            return np.linalg.cholesky(H)
+        except np.linalg.LinAlgError:
+            pass
+        for mu in osp.JITTER:  # mu alone, not mu * mean(diag H)
+            try:
+                return np.linalg.cholesky(H + mu * np.eye(H.shape[0]))
+            except np.linalg.LinAlgError:
+                continue
+        raise osp.NotPositiveDefinite("H")
+
+    monkeypatch.setattr(osp, "cholesky_jitter", wrong)
+    assert _jitter_fails()
+
+
+def test_jitter_schedule_out_of_order_is_caught(monkeypatch):
+    monkeypatch.setattr(osp, "JITTER", (1e-14, 1e-12, 1e-8, 1e-10))
+    assert _jitter_fails()
+
+
+def test_stream_started_at_step_instead_of_next_is_caught(monkeypatch):
+    monkeypatch.setattr(orng, "step_state", lambda seed, t: (seed ^ ((t * orng.GOLDEN) & orng.MASK64)) & orng.MASK64)
+    assert pins.stream_start_mismatches() > 0
+
+
+def test_stream_seed_added_instead_of_xored_is_caught(monkeypatch):
+    monkeypatch.setattr(orng, "step_state", lambda seed, t: (seed + (t + 1) * orng.GOLDEN) & orng.MASK64)
+    assert pins.stream_start_mismatches() > 0
+
+
+def _replay_fails():
+    try:
+        return pins.stage_replay()[0] > 0
+    except osp.NotPositiveDefinite:  # a duplicate entered the basis and made H singular
+        return True
+
+
+def test_draw_ignoring_the_stage_start_basis_is_caught(monkeypatch):
+    real = osp.draw_candidates
+    monkeypatch.setattr(osp, "draw_candidates", lambda seed, t, n, kappa, blocked: real(seed, t, n, kappa, lambda i: False))
+    assert _replay_fails()
+
+
+def test_duplicates_of_winners_not_blocked_is_caught(monkeypatch):
+    monkeypatch.setattr(osp, "duplicate_groups", lambda X: np.arange(np.asarray(X).shape[0]))
+    assert _replay_fails()

@@ -81,6 +81,22 @@ def test_candidate_draw_rules():
     assert c2 == [3]
 
 
+def stream_start_mismatches():
+    """First candidate indices of an addition step against the values worked by hand from the published
+    generator outputs (golden file): pins where a step's stream starts (seed XOR (t + 1) GOLDEN)."""
+    bad = 0
+    for ln in _golden_lines("candidate_stream_start.txt"):
+        seed, t, n, idx = [p.strip() for p in ln.split(";")]
+        want = [int(v) for v in idx.split(",")]
+        got = orng.draw_candidates(int(seed, 0), int(t), int(n), len(want), lambda i: False)
+        bad += int(got != want)
+    return bad
+
+
+def test_candidate_stream_start():
+    assert stream_start_mismatches() == 0
+
+
 def test_candidate_index_is_high_bits_scaled():
     # index = floor(hi32(z) * n / 2^32): check against exact rational arithmetic on the published stream
     z = orng.splitmix64_stream(0, 1)[0]
@@ -402,9 +418,115 @@ def test_argument_validation():
         osp.train(Xn, y, 1.0, 0.5, 5)
 
 
-def test_cholesky_jitter_schedule():
-    H = np.array([[1.0, 1.0], [1.0, 1.0]])  # PSD, singular: first retry with mu = 1e-14 fails?
-    L = osp.cholesky_jitter(H)
-    assert np.allclose(L @ L.T, H, atol=1e-7)
+def _indefinite(lam_min, seed=0):
+    """H = Q diag(120, 80, 40, 20, 10, lam_min) Q^T with a random orthogonal Q: mean diagonal (270 + lam_min) / 6,
+    about 45, and one eigenvalue lam_min < 0 far above the rounding of the entries (~1e-14)."""
+    r = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(r.standard_normal((6, 6)))
+    H = (Q * np.array([120.0, 80.0, 40.0, 20.0, 10.0, lam_min])) @ Q.T
+    return 0.5 * (H + H.T)
+
+
+def jitter_error():
+    """The retry adds mu * mean(diag H) to the diagonal, mu = 1e-14, 1e-12, 1e-10, 1e-8 in turn. With the smallest
+    eigenvalue -1e-9 and mean diagonal ~45 the shifts are 4.5e-13, 4.5e-11 (still indefinite) and 4.5e-9 (PD), so
+    the factor must reproduce H + 1e-10 mean(diag H) I; with -1e-7 only the last shift (4.5e-7) succeeds. Returns
+    the largest deviation of L L^T from those matrices, relative to the largest entry of H."""
+    worst = 0.0
+    for lam_min, mu in ((-1e-9, 1e-10), (-1e-7, 1e-8)):
+        H = _indefinite(lam_min)
+        with pytest.raises(np.linalg.LinAlgError):
+            np.linalg.cholesky(H)  # the retry path is taken
+        L = osp.cholesky_jitter(H)
+        want = H + mu * (np.trace(H) / 6) * np.eye(6)
+        worst = max(worst, float(np.max(np.abs(L @ L.T - want)) / np.max(np.abs(H))))
+    return worst
+
+
+def test_cholesky_jitter_scale_and_order():
+    assert jitter_error() < 1e-13
+
+
+def test_cholesky_jitter_gives_up():
+    with pytest.raises(osp.NotPositiveDefinite):
+        osp.cholesky_jitter(_indefinite(-1e-5))  # the largest shift, 4.5e-7, leaves it indefinite
     with pytest.raises(osp.NotPositiveDefinite):
         osp.cholesky_jitter(np.array([[1.0, 0.0], [0.0, -1.0]]))
+    H = np.array([[4.0, 2.0], [2.0, 3.0]])  # PD: no jitter at all
+    assert np.array_equal(osp.cholesky_jitter(H), np.linalg.cholesky(H))
+
+
+# ----------------------------------------------------------------------------- stages of several additions
+def _dup_groups(X):
+    """Row groups by exact equality of the feature vectors, computed here rather than by the oracle."""
+    seen, out = {}, np.empty(X.shape[0], dtype=np.int64)
+    for i, row in enumerate(map(tuple, np.asarray(X, dtype=np.float64))):
+        out[i] = seen.setdefault(row, len(seen))
+    return out
+
+
+def stage_replay(n=45, J_max=14, kappa=12, growth=1.0, draw_seed=4, data_seed=710):
+    """Brute-force replay of the oracle's greedy growth over stages that add several vectors (growth 1 gives
+    stages of 1, 1, 2, 4, 6 additions). Every row has two exact duplicates. Per stage: candidates are drawn with
+    J as it stood at the stage start blocked (members and their duplicates); a drawn row whose duplicate group
+    won earlier in the same stage is skipped; each remaining candidate is appended and the full objective is
+    minimised over its coefficient by golden section, the lowest value winning (lower row on ties); Newton
+    after the stage. Returns (mismatching additions, additions made in stages of 2 or more, same-stage
+    duplicates skipped)."""
+    r = np.random.default_rng(data_seed)
+    base = r.standard_normal((n // 3, 3))
+    X = np.concatenate([base, base, base])
+    y = np.where(X[:, 0] + 0.4 * r.standard_normal(n) > 0, 1.0, -1.0)
+    C, gamma = 2.0, 0.5
+    lam = 1 / C
+    res = osp.train(X, y, C, gamma, J_max=J_max, seed=draw_seed, kappa=kappa, growth=growth)
+    grp = _dup_groups(X)
+    J, beta, t = [], np.zeros(0), 0
+    multi = skipped = mism = 0
+    while len(J) < J_max:
+        cs = min(J_max - len(J), max(1, int(math.floor(growth * len(J)))))
+        frozen = {grp[j] for j in J}
+        for q in range(cs):
+            cands = orng.draw_candidates(draw_seed, t + q, n, kappa, lambda i: grp[i] in frozen)
+            best = None
+            for c in cands:
+                if grp[c] in {grp[j] for j in J}:
+                    assert grp[c] not in frozen
+                    skipped += 1
+                    continue
+                Jc = J + [c]
+                K = oracle.rbf_block(X, X[Jc], gamma)
+
+                def f(s):
+                    return osp.objective(K, K[Jc], y, np.append(beta, s), lam)
+
+                R = 1.0
+                while f(R) < f(R / 2) or f(-R) < f(-R / 2):
+                    R *= 2
+                grid = np.linspace(-R, R, 4001)
+                k = int(np.argmin([f(v) for v in grid]))
+                s = _golden_section(f, grid[max(k - 1, 0)], grid[min(k + 1, 4000)])
+                val = f(s)
+                if best is None or val < best[0] - 1e-12 or (abs(val - best[0]) <= 1e-12 and c < best[1]):
+                    best = (val, c, s)
+            # exact duplicates give identical columns, and their scores differ only by rounding of o (the
+            # oracle's products may round identical rows differently): the pick must be the same group, and
+            # the replay goes on with the oracle's row
+            k = len(J)
+            if k >= len(res.J) or grp[res.J[k]] != grp[best[1]]:
+                mism += 1
+                J.append(best[1])
+            else:
+                J.append(int(res.J[k]))
+            beta = np.append(beta, best[2])
+            multi += int(cs >= 2)
+        K = oracle.rbf_block(X, X[J], gamma)
+        beta, _ = osp.newton_solve(K, K[J], y, lam, beta)
+        t += cs
+    return mism + abs(len(J) - len(res.J)), multi, skipped
+
+
+def test_multi_addition_stages_match_bruteforce_replay():
+    mism, multi, skipped = stage_replay()
+    assert multi >= 8 and skipped >= 1  # the stage-level rules are exercised
+    assert mism == 0
