@@ -3,15 +3,19 @@
 One step = one complete greedy SP-SVM training run (basis selection + Newton re-optimisation to |J| = J_max,
 every row of the hot path) on a fixed synthetic workload already resident in HBM. Prints ONE JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload binary-100k] [--precision f32]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dense-2m] [--precision mixed]
 
-The default workload is the 100 000 x 123 binary one (|J| = 1000, C = 1, gamma = 0.05). With
---workload mnist-60k a step is instead one batched call: 160 one-vs-rest x (C, gamma) Newton solves on a shared
-basis of 2000 rows of a 60 000 x 784 matrix. The dominant kernel
-(largest GPU time among kernel block, SYRK, score passes, Cholesky, found on the first warm-up run) is timed
-with HIP events on the training stream during the timed steps, for the roofline entry. Parity of the first
-timed run is checked against the FP64 oracle (objective at the GPU's basis, sampled decision values), and the
-oracle itself is timed on a bounded sample of the same workload (the CPU baseline).
+The default workload is the largest single-GPU one, dense-2m (2 000 000 x 2000 i.i.d. N(0, 1) FP32 rows,
+|J| = 4000, C = 1, gamma = 1/2000), timed in mixed precision (split-BF16 distances); the FP32 path is timed on
+the same workload with the same kernel-block timing for the "mixed vs FP32" part of the metric (--compare-steps
+runs). The kernel block is timed with HIP events on the training stream during the timed steps (every launch on
+rows of 256+ features) for the roofline entry: algorithmic flops 2 n N d and issued MFMA flops, each over the
+launches' time. Other workloads: binary-100k, onehot-500k, blobs-2k; with --workload mnist-60k a step is one
+batched call (160 one-vs-rest x (C, gamma) Newton solves on a shared basis of 2000 rows of 60 000 x 784 rows).
+Parity: where the oracle can re-solve at the GPU's basis within the run (up to 4e8 kernel values) it does;
+beyond that the returned model's decisions are checked on sampled rows and the objective parity at this row
+shape is a GPU test. The CPU baseline is the oracle timed on a bounded sample of the same workload, plus its full
+pipeline on the 2000-row blob workload on all cores and on one thread.
 """
 
 import argparse
@@ -27,6 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "train sec to oracle objective (rel 1e-6), mixed vs FP32; K-block TFLOP/s"
 PEAKS = {  # MI355X published dense peaks
     "hbm_GBps": 8000.0,
+    "bf16_mfma_TFLOPs": 2500.0,
     "fp64_mfma_TFLOPs": 78.6,
     "fp32_mfma_TFLOPs": 157.3,
 }
@@ -46,12 +51,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="binary-100k")
-    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--workload", default="dense-2m")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "f32", "f64"])
+    ap.add_argument("--compare-steps", type=int, default=2,
+                    help="timed runs of the other precision (f32 when the headline is mixed); 0 skips them")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c0-baseline", action="store_true", help="skip the full oracle pipeline on blobs-2k")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=12)
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison runs")
+    ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times (a plain copy kernel of known size, to calibrate "
                          "hardware byte counters)")
@@ -69,7 +76,8 @@ def copy_probe():
     del a, b
 
 
-KERNEL_OF = {"kblock": "k_kblock_store", "syrk": "k_syrk", "score": "k_score_pass", "chol": "k_potrf_diag"}
+KERNEL_OF = {"kblock": "k_kblock_store", "syrk": "k_syrk", "score": "k_score_pass", "chol": "k_potrf_diag",
+             "k_kblock_bf16_wide": "k_kblock_bf16_wide", "k_kblock_store": "k_kblock_store"}
 
 
 def measured_traffic(workload, kernel):
@@ -178,13 +186,111 @@ def run_batch(args):
             b_or, F_or, _ = osp.solve_fixed_J(p.X, p.Y[q], p.C[q], p.gamma[q], p.J)
             oracle_s = time.perf_counter() - tq
             Fo = osp.objective_at(p.X, p.Y[q], p.C[q], p.gamma[q], p.J, beta)
-            par.append({"problem": q, "objective_rel": (Fo - F_or) / F_or, "objective_ok": bool((Fo - F_or) / F_or <= 1e-6)})
+            par.append({"problem": q, "objective_rel": (Fo - F_or) / F_or, "objective_ok": bool(abs(Fo - F_or) / F_or <= 1e-6)})
         out["parity"] = par
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = {
                 "value": round(oracle_s * P, 3), "unit": "s", "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
                 "sample": f"FP64 oracle fixed-basis Newton solve of problem {P - 1} ({oracle_s:.2f} s), times {P} problems"}
     print(json.dumps(out))
+
+
+def _kblock_entry(stats, precision, split, d):
+    """Roofline of the kernel block over the timed launches: algorithmic flops 2 n N d (N candidate columns drawn)
+    and the MFMA flops the launches issued (whole tiles; three products per multiply-add with the split
+    correction), each over the launches' HIP-event time."""
+    e = roofline_entry(stats, 1, precision)
+    if e is None:
+        return None
+    sec = stats["kblock_seconds"]
+    peak = PEAKS["bf16_mfma_TFLOPs"] if precision == "mixed" else e["peak"]
+    e["peak"] = peak
+    e["frac"] = round(e["achieved"] / peak, 4)
+    e["issued_tflops"] = round(stats["kblock_mfma_flops"] / sec / 1e12, 3)
+    e["issued_frac"] = round(e["issued_tflops"] / peak, 4)
+    e["issued_per_launch"] = stats["kblock_mfma_flops"] / max(stats["kblock_launches"], 1)
+    e["split_products"] = 3 if split else 1
+    # candidate steps are grouped (up to 16 per launch, 256 x 256 split-BF16 tiles) on rows of 256+ features
+    e["kernel_name"] = (("k_kblock_bf16_wide" if d >= 256 else "k_kblock_bf16") if precision == "mixed" else
+                        "k_kblock_store")
+    return e
+
+
+def _timed_runs(lib, Xg, yg, p, steps, precision, common, profile):
+    import torch
+
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    models = [lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=k, precision=precision, profile=profile, **common)
+              for k in range(steps)]
+    torch.cuda.synchronize()
+    per_run = (time.perf_counter() - t1) / max(steps, 1)
+    stats = [m.stats() for m in models]
+    agg = {key: sum(s[key] for s in stats) for key in stats[0]} if stats else {}
+    return per_run, models, stats, agg
+
+
+def _oracle_cpu_baseline(p, gpu_stats, sample_steps):
+    """The FP64 oracle on the host cores, on a bounded sample of the same workload: its greedy training on the
+    first (at most 100 000) rows, timed for 1 and for 1 + sample_steps addition steps; the difference is the cost
+    of sample_steps steps (59 candidate columns and exact scores each, a short Newton solve in between), which is
+    scaled linearly to all rows and to the GPU run's additions. A lower bound on a full oracle run: scoring sorts
+    (n log n), and the Newton re-optimisations on the grown basis are not counted."""
+    from oracle import spsvm as osp
+
+    cores = len(os.sched_getaffinity(0))
+    n, d = p.X.shape
+    rows = min(n, 100000)
+    Xs, ys = p.X[:rows], p.y[:rows]
+    jm = min(p.J_max, rows)
+    t = time.perf_counter()
+    osp.train(Xs, ys, p.C, p.gamma, jm, seed=0, max_steps=1)
+    t1 = time.perf_counter() - t
+    t = time.perf_counter()
+    osp.train(Xs, ys, p.C, p.gamma, jm, seed=0, max_steps=1 + sample_steps)
+    t2 = time.perf_counter() - t
+    per_step = max(t2 - t1, 1e-9) / sample_steps
+    steps_full = int(gpu_stats["additions"])
+    return {"value": round(per_step * (n / rows) * steps_full, 3), "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 oracle greedy training on the first {rows} of the {n} x {d} rows: {sample_steps} addition "
+                       f"steps take {t2 - t1:.2f} s ({t1:.2f} s for set-up and the first step, {t2:.2f} s for "
+                       f"{1 + sample_steps}), i.e. {per_step:.3f} s per step, scaled by {n / rows:g} (rows) and "
+                       f"{steps_full} (the GPU run's additions); Newton re-optimisations on the grown basis not "
+                       f"counted, so a lower bound on a full oracle run")}
+
+
+def _oracle_c0_pipeline():
+    """Measured full oracle pipeline on the 2000-row blob workload (|J| = 100), on all host cores and on one
+    thread, beside the GPU's FP64 run of the same problem."""
+    import torch
+
+    import datagen
+    import paper_1404_1066_amd as lib
+    from oracle import spsvm as osp
+
+    p = datagen.make_config("blobs-2k")
+    out = {"workload": "blobs-2k", "n": 2000, "d": 16, "J_max": 100}
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # noqa: BLE001
+        threadpool_limits = None
+    for label, threads in (("all_cores", len(os.sched_getaffinity(0))), ("single_thread", 1)):
+        ctx = threadpool_limits(threads) if threadpool_limits else None
+        t = time.perf_counter()
+        ref = osp.train(p.X, p.y, p.C, p.gamma, p.J_max, seed=0)
+        out[f"oracle_{label}_s"] = round(time.perf_counter() - t, 3)
+        if ctx is not None:
+            ctx.unregister()
+    Xg = torch.tensor(p.X, device="cuda")
+    yg = torch.tensor(p.y, dtype=torch.float32, device="cuda")
+    lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=0, precision="f64")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    m = lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=0, precision="f64")
+    torch.cuda.synchronize()
+    out["gpu_f64_s"] = round(time.perf_counter() - t, 4)
+    out["identical_basis"] = bool(m.get()[0].tolist() == ref.J.tolist())
+    return out
 
 
 def main():
@@ -205,50 +311,44 @@ def main():
     import paper_1404_1066_amd as lib
 
     t0 = time.time()
-    p = datagen.make_config(args.workload)
+    if args.workload == "dense-2m":  # 16 GB of FP32 rows: blocks generated in parallel (same values)
+        X = np.empty((2000000, 2000), dtype=np.float32)
+        X, y = datagen.make_large_dense(out=X, threads=min(16, len(os.sched_getaffinity(0))))
+        p = datagen.Problem("dense-2m", X, y, C=1.0, gamma=1.0 / 2000, J_max=4000)
+    else:
+        p = datagen.make_config(args.workload)
     gen_s = time.time() - t0
     n, d = p.X.shape
-    dt = torch.float64 if args.precision == "f64" else torch.float32
-    Xg = torch.tensor(p.X, dtype=dt, device="cuda")
+    prec = args.precision
+    other = None if args.compare_steps <= 0 or prec == "f64" else ("f32" if prec == "mixed" else "mixed")
+    dt = torch.float64 if p.X.dtype == np.float64 else torch.float32
+    Xg = torch.from_numpy(p.X).to("cuda", dtype=dt)
     yg = torch.tensor(p.y, dtype=torch.float32, device="cuda")
-    # sized for the mixed-precision runs too (they also hold the split-BF16 copies of X)
-    ws_prec = "mixed" if (args.precision == "f32" and not args.no_mixed) else args.precision
-    ws = torch.empty(lib.workspace_bytes(n, d, p.J_max, dtype=dt, precision=ws_prec), dtype=torch.uint8, device="cuda")
+    ws_bytes = max(lib.workspace_bytes(n, d, p.J_max, dtype=dt, precision=q) for q in (prec, other) if q)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
-    common = dict(precision=args.precision, workspace=ws, stream=stream)
+    common = dict(workspace=ws, stream=stream)
+    # the kernel block is timed on every launch when launches are long (wide rows), every 8th otherwise
+    stride = (1 if d >= 256 else 8) << 8
+    print(f"[bench] {args.workload}: n={n} d={d} |J|={p.J_max} generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
 
     # warm-up; the first one is profiled on every kernel class to find the dominant kernel
-    dominant, warm_stats = 2, None
+    warm_stats = None
     for w in range(max(args.warmup, 1)):
-        m = lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=1000 + w, profile=15 if w == 0 else 0, **common)
+        m = lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=1000 + w, precision=prec, profile=15 if w == 0 else 0,
+                      **common)
         if w == 0:
             warm_stats = m.stats()
-            dominant = max(CATS, key=lambda b: warm_stats[f"{CATS[b][0]}_seconds"])
         del m
-    torch.cuda.synchronize()
-
-    models, stats = [], []
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for k in range(args.steps):  # the kernel block is timed too (the metric's K-block TFLOP/s); every 8th launch
-        models.append(lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=k, profile=(dominant | 1) | PROFILE_STRIDE,
-                                **common))
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    per_run = (t2 - t1) / args.steps
-    for m in models:
-        stats.append(m.stats())
-
-    # roofline of the dominant kernel over the timed region (sum of the timed runs' event timings)
-    agg = {}
-    for key in stats[0]:
-        agg[key] = sum(s[key] for s in stats)
-    roof = roofline_entry(agg, dominant, args.precision)
+        print(f"[bench] warm-up {w + 1} done", file=sys.stderr, flush=True)
+    per_run, models, stats, agg = _timed_runs(lib, Xg, yg, p, args.steps, prec, common, 1 | stride)
+    print(f"[bench] {args.steps} timed {prec} runs: {per_run:.4f} s each", file=sys.stderr, flush=True)
+    # split correction issued unless every value is a BF16 number (checked on the first rows, as a label only; the
+    # issued flops themselves come from the library)
+    split = prec == "mixed" and not (p.X.dtype == np.float32 and not np.any(p.X[:4096].view(np.uint32) & 0xFFFF))
+    roof = _kblock_entry(agg, prec, split, d)
     if roof is not None:
-        roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
-    kblock_timed = roofline_entry(agg, 1, args.precision)
-    others = {CATS[b][0]: roofline_entry(warm_stats, b, args.precision) for b in CATS}
-
+        roof["traffic"] = measured_traffic(args.workload, roof["kernel_name"])
     out = {
         "metric": METRIC,
         "value": round(per_run, 6),
@@ -260,84 +360,66 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        "dtype": {"mixed": "split-bf16 MFMA products, f32 K, f64 Newton", "f32": "f32 K, f64 Newton",
+                  "f64": "f64"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d, "J_max": p.J_max, "C": p.C, "gamma": p.gamma,
-                   "kappa": 59, "precision": args.precision, "seeds": list(range(args.steps))},
+                   "kappa": 59, "precision": prec, "seeds": list(range(args.steps))},
         "roofline": roof,
-        "kblock_tflops": kblock_timed["achieved"] if kblock_timed else None,
-        "kblock": kblock_timed,
-        "kernels_warmup": others,
-        "train_stats_seed0": {k: stats[0][k] for k in ("stages", "newton_iters", "factorizations", "score_passes",
-                                                        "ls_passes", "n_sv", "grad_norm", "seconds_select",
-                                                        "seconds_newton")},
+        "kernels_warmup": {CATS[b][0]: (_kblock_entry(warm_stats, prec, split, d) if b == 1 else
+                                        roofline_entry(warm_stats, b, prec)) for b in CATS},
+        "train_stats_seed0": {k: stats[0][k] for k in ("stages", "additions", "newton_iters", "factorizations",
+                                                        "score_passes", "ls_passes", "n_sv", "grad_norm",
+                                                        "seconds_select", "seconds_newton", "jitter_retries")},
     }
-
-    # the same runs with split-BF16 distances (SPSVM_MIXED), for the "mixed vs FP32" part of the metric
-    mixed_models = []
-    if not args.no_mixed and args.precision == "f32":
-        mcommon = dict(common, precision="mixed")
-        lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=1000, **mcommon)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        for k in range(args.steps):
-            mixed_models.append(lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=k, **mcommon))
-        torch.cuda.synchronize()
-        per_mixed = (time.perf_counter() - t3) / args.steps
-        out["mixed"] = {"value": round(per_mixed, 6), "unit": "s", "ratio_fp32_over_mixed": round(per_run / per_mixed, 4)}
+    if other:
+        per_o, models_o, stats_o, agg_o = _timed_runs(lib, Xg, yg, p, args.compare_steps, other, common, 1 | stride)
+        print(f"[bench] {args.compare_steps} timed {other} runs: {per_o:.4f} s each", file=sys.stderr, flush=True)
+        key = "fp32_over_mixed" if prec == "mixed" else "fp32_over_mixed_inv"
+        out[other] = {"value": round(per_o, 6), "unit": "s", "steps": args.compare_steps,
+                      "seeds": list(range(args.compare_steps)),
+                      "profile": "same HIP-event timing of the kernel block as the headline runs",
+                      "kblock": _kblock_entry(agg_o, other, split, d),
+                      "ratio_" + key: round(per_o / per_run if prec == "mixed" else per_run / per_o, 4)}
 
     J, beta, F = models[0].get()
-    if not args.no_parity or not args.no_cpu_baseline:
-        from oracle import spsvm as osp
-        import oracle
+    from oracle import spsvm as osp
+    import oracle
 
     if not args.no_parity:
-        tq = time.perf_counter()
-        b_or, F_or, info = osp.solve_fixed_J(p.X, p.y, p.C, p.gamma, J)
-        newton_oracle_s = time.perf_counter() - tq
-        Fo = osp.objective_at(p.X, p.y, p.C, p.gamma, J, beta)
-        rows = np.random.default_rng(0).choice(n, 2000, replace=False)
-        dg = models[0].predict(Xg[torch.tensor(rows, device="cuda")]).cpu().numpy()
-        do = oracle.predict(p.X[J], b_or, p.gamma, p.X[rows])
-        derr = float(np.max(np.abs(dg - do) / np.maximum(1.0, np.abs(do))))
-        rel = (Fo - F_or) / F_or
-        out["parity"] = {"objective_rel": rel, "objective_ok": bool(rel <= 1e-6), "decision_max_rel": derr,
-                         "decision_ok": bool(derr <= 1e-4), "F_gpu": Fo, "F_oracle": F_or, "m": int(len(J))}
-        if mixed_models:
-            Jm, bm, _ = mixed_models[0].get()
-            _, F_orm, _ = osp.solve_fixed_J(p.X, p.y, p.C, p.gamma, Jm) if not np.array_equal(Jm, J) else (None, F_or, None)
-            Fm = osp.objective_at(p.X, p.y, p.C, p.gamma, Jm, bm)
-            out["mixed"]["objective_rel"] = (Fm - F_orm) / F_orm
-            out["mixed"]["objective_ok"] = bool((Fm - F_orm) / F_orm <= 1e-6)
-    else:
-        newton_oracle_s = None
+        if n * p.J_max <= 100000 * 1000 * 4:  # the oracle re-solves at the GPU's basis within a few minutes
+            tq = time.perf_counter()
+            b_or, F_or, info = osp.solve_fixed_J(p.X, p.y, p.C, p.gamma, J)
+            newton_oracle_s = time.perf_counter() - tq
+            Fo = osp.objective_at(p.X, p.y, p.C, p.gamma, J, beta)
+            rows = np.random.default_rng(0).choice(n, 2000, replace=False)
+            dg = models[0].predict(Xg[torch.tensor(rows, device="cuda")]).cpu().numpy()
+            do = oracle.predict(p.X[J], b_or, p.gamma, p.X[rows])
+            derr = float(np.max(np.abs(dg - do) / np.maximum(1.0, np.abs(do))))
+            rel = (Fo - F_or) / F_or
+            out["parity"] = {"kind": "oracle re-solve at the GPU's basis", "objective_rel": rel,
+                             "objective_ok": bool(abs(rel) <= 1e-6), "decision_max_rel": derr,
+                             "decision_ok": bool(derr <= 1e-4), "F_gpu": Fo, "F_oracle": F_or, "m": int(len(J)),
+                             "oracle_newton_s": round(newton_oracle_s, 3)}
+        else:
+            # at this size the oracle cannot re-solve within the run; it checks the returned model's decision
+            # values on sampled rows (its kernel evaluated in FP64 at the GPU's J and beta)
+            rows = np.random.default_rng(0).choice(n, 500, replace=False)
+            dg = models[0].predict(Xg[torch.tensor(rows, device="cuda")]).cpu().numpy()
+            do = oracle.predict(p.X[J], beta, p.gamma, p.X[rows])
+            derr = float(np.max(np.abs(dg - do) / np.maximum(1.0, np.abs(do))))
+            out["parity"] = {
+                "kind": "sampled: the GPU model's decisions on 500 rows against the oracle's FP64 kernel at the same "
+                        "(J, beta); objective parity at this size is in tests/test_gpu_train.py::"
+                        "test_dense_2m_rows_full_basis_reach_oracle_objective (same rows at n = 100000, |J| = 4000)",
+                "decision_max_rel": derr, "decision_ok": bool(derr <= 1e-4), "m": int(len(J)),
+                "gpu_grad_norm": stats[0]["grad_norm"], "F_gpu_self": F}
 
     if not args.no_cpu_baseline:
-        cores = len(os.sched_getaffinity(0))
-        try:
-            from threadpoolctl import threadpool_limits
-            ctx = threadpool_limits(cores)
-        except Exception:  # noqa: BLE001
-            ctx = None
-        os.environ.setdefault("OMP_NUM_THREADS", str(cores))
-        S = args.cpu_sample_steps
-        tq = time.perf_counter()
-        osp.train(p.X, p.y, p.C, p.gamma, p.J_max, seed=0, max_steps=S)
-        sample_s = time.perf_counter() - tq
-        steps_full = int(stats[0]["additions"])
-        est = sample_s / S * steps_full + (newton_oracle_s or 0.0)
-        out["cpu_baseline"] = {
-            "value": round(est, 3),
-            "unit": "s",
-            "cores": cores,
-            "kind": "oracle",
-            "sample": (f"FP64 oracle greedy training, first {S} addition steps on the full {n} x {d} data "
-                       f"({sample_s:.2f} s, scaled to {steps_full} steps) plus one oracle Newton re-solve at "
-                       f"the GPU's final basis ({newton_oracle_s:.2f} s); a lower bound on the full oracle run"
-                       if newton_oracle_s is not None else f"first {S} addition steps scaled to {steps_full}"),
-        }
-        if ctx is not None:
-            ctx.unregister() if hasattr(ctx, "unregister") else None
+        out["cpu_baseline"] = _oracle_cpu_baseline(p, stats[0], args.cpu_sample_steps)
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+        if not args.no_c0_baseline:
+            out["cpu_baseline"]["c0_full_pipeline"] = _oracle_c0_pipeline()
     print(json.dumps(out))
 
 

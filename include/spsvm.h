@@ -114,6 +114,10 @@ typedef struct {
   int64_t chol_calls;       /* timed Cholesky factorisations (all panel kernels of one factorisation) */
   double chol_seconds;
   double chol_flops;        /* m^3 / 3 per factorisation */
+  double kblock_mfma_flops; /* MFMA flops the timed kernel blocks issued: whole tiles, the feature dimension padded
+                               to the k chunk, three products per multiply-add with the split-BF16 correction */
+  int64_t jitter_retries;   /* factorisations repeated with a diagonal shift mu * mean(diag H), mu = 1e-14, 1e-12,
+                               1e-10, 1e-8 in turn, because the Newton matrix was not numerically positive definite */
 } spsvm_stats;
 
 /* Fills *opt with the defaults listed above. */
@@ -121,9 +125,10 @@ void spsvm_options_default(spsvm_options* opt);
 
 /* Bytes of device workspace spsvm_train needs for n rows, d features of type xdt and up to J_max basis
  * vectors with these options (NULL = defaults). The kernel block n x J_max and the candidate block n x 64
- * dominate. When d is not a multiple of 4 (FP32) or 2 (FP64) the workspace also holds a copy of X with
- * padded rows. The figure assumes X starts on a 16-byte boundary (otherwise training needs the padded
- * copy too and reports SPSVM_E_WORKSPACE). */
+ * dominate. In SPSVM_F32 and SPSVM_F64 the figure includes a copy of X with rows padded to 16-byte
+ * boundaries, which training uses when d is not a multiple of 4 (FP32) or 2 (FP64) or X does not start on a
+ * 16-byte boundary (the query cannot see X, so it always reserves it in those modes); SPSVM_MIXED reads
+ * split BF16 copies of X instead (also in the workspace) and needs no padded copy. */
 spsvm_status spsvm_train_workspace_bytes(int64_t n, int64_t d, int64_t J_max, spsvm_dtype xdt,
                                          const spsvm_options* opt, size_t* bytes);
 

@@ -46,6 +46,31 @@ spsvm_status spsvm_newton_solve(double* H, int64_t ldh, int64_t m, const double*
  *  out: host, 64 int32; unused slots are set to -1. Host-only: no GPU work. */
 spsvm_status spsvm_candidate_draw(uint64_t seed, int64_t t, int64_t n, int32_t kappa, int32_t* out);
 
+/* Greedy-selection scores of section 4 ("Sparse primal optimization": each candidate of a random subset is
+ * scored by the loss reduction it would bring). For candidate c with kernel column k_c (k_c(x_c) = 1) the score
+ * is the exact decrease of f(beta) = lambda/2 beta^T K_JJ beta + 1/2 sum_i max(0, 1 - y_i o_i)^2 (lambda = 1 / C,
+ * Eq. 4 divided by C) when only a new coefficient s for c is optimised and every other coefficient is fixed:
+ *   psi_c(s) - f = lambda (s o_c + s^2 / 2) + 1/2 sum_i [max(0, a_i - s b_i)^2 - max(0, a_i)^2],
+ *   a_i = 1 - y_i o_i, b_i = y_i k_c[i],  score_c = psi_c(0) - min_s psi_c(s) >= 0.
+ * The same passes and updates as greedy training run (64 candidate slots, semismooth Newton on psi_c' with the
+ * window walk, candidates that cannot win dropped), up to 64 passes.
+ *  o: device, n doubles (current outputs K_XJ beta). y: device, n floats, +1 or -1.
+ *  Kc: device, the ncand candidate columns, column-major: column c (n values of type kdt) starts at
+ *    Kc + c * ldc elements, ldc >= n. oc: host, ncand doubles, o at each candidate's row. 1 <= ncand <= 64.
+ *  s_out, score_out: host, ncand doubles: the minimiser and the score of each candidate with status 1; a dropped
+ *    candidate (status 3: its largest possible score is below another candidate's reached one) reports the
+ *    bracket point it stopped at and -infinity. status_out, passes_out: host, ncand int32 (may be NULL): 1 scored,
+ *    3 dropped; the passes over the rows each slot took. winner: host, the candidate with the largest score (the
+ *    lowest index on ties), -1 if none.
+ *  workspace: device, 256-byte aligned, at least spsvm_score_workspace_bytes(n) bytes. */
+spsvm_status spsvm_score_candidates(const double* o, const float* y, int64_t n, const void* Kc, spsvm_dtype kdt,
+                                    int64_t ldc, const double* oc, int32_t ncand, double C, double* s_out,
+                                    double* score_out, int32_t* status_out, int32_t* passes_out, int32_t* winner,
+                                    void* workspace, size_t ws_bytes, void* stream);
+
+/* Bytes of device workspace spsvm_score_candidates needs for n rows. */
+spsvm_status spsvm_score_workspace_bytes(int64_t n, size_t* bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,7 @@ from .binding import (  # noqa: F401
     rbf_block,
     newton_solve,
     candidate_draw,
+    score_candidates,
     workspace_bytes,
     EXPORTED,
     LIB_PATH,

@@ -39,6 +39,8 @@ EXPORTED = (
     "spsvm_newton_solve_workspace_bytes",
     "spsvm_newton_solve",
     "spsvm_candidate_draw",
+    "spsvm_score_candidates",
+    "spsvm_score_workspace_bytes",
 )
 
 
@@ -94,6 +96,8 @@ class Stats(ctypes.Structure):
         ("chol_calls", ctypes.c_int64),
         ("chol_seconds", ctypes.c_double),
         ("chol_flops", ctypes.c_double),
+        ("kblock_mfma_flops", ctypes.c_double),
+        ("jitter_retries", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -137,7 +141,11 @@ def load(path: str = LIB_PATH):
     lib.spsvm_newton_solve_workspace_bytes.argtypes = [I64, P(ctypes.c_size_t)]
     lib.spsvm_newton_solve.argtypes = [VP, I64, I64, VP, VP, VP, ctypes.c_size_t, VP]
     lib.spsvm_candidate_draw.argtypes = [ctypes.c_uint64, I64, I64, ctypes.c_int32, P(ctypes.c_int32)]
-    for name in ("spsvm_candidate_draw", "spsvm_rbf_block", "spsvm_rbf_block_workspace_bytes", "spsvm_newton_solve_workspace_bytes", "spsvm_newton_solve",
+    lib.spsvm_score_workspace_bytes.argtypes = [I64, P(ctypes.c_size_t)]
+    I32 = ctypes.c_int32
+    lib.spsvm_score_candidates.argtypes = [VP, VP, I64, VP, ctypes.c_int, I64, P(D), I32, D, P(D), P(D), P(I32),
+                                           P(I32), P(I32), VP, ctypes.c_size_t, VP]
+    for name in ("spsvm_score_candidates", "spsvm_score_workspace_bytes", "spsvm_candidate_draw", "spsvm_rbf_block", "spsvm_rbf_block_workspace_bytes", "spsvm_newton_solve_workspace_bytes", "spsvm_newton_solve",
                  "spsvm_train_workspace_bytes", "spsvm_fixed_workspace_bytes", "spsvm_train",
                  "spsvm_train_fixed_basis", "spsvm_batch_workspace_bytes", "spsvm_train_batch", "spsvm_model_get", "spsvm_model_stats", "spsvm_predict"):
         getattr(lib, name).restype = ctypes.c_int
@@ -335,6 +343,36 @@ def newton_solve(H: torch.Tensor, g: torch.Tensor, stream=None):
                                      ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(ws.data_ptr()), b.value,
                                      ctypes.c_void_p(_stream_ptr(stream))))
     return x
+
+
+def score_candidates(o: torch.Tensor, y: torch.Tensor, Kc: torch.Tensor, oc, C: float, stream=None):
+    """Greedy-selection scores of ncand candidates (spsvm_score_candidates). Kc: ncand x n (row c is candidate c's
+    kernel column, row stride >= n), float32 or float64; oc: o at the candidate rows. Returns a dict of numpy
+    arrays s, score, status, passes and the winning candidate (-1 if none)."""
+    import numpy as np
+
+    for t, name in ((o, "o"), (y, "y"), (Kc, "Kc")):
+        _need_gpu(t, name)
+    if o.dtype != torch.float64 or y.dtype != torch.float32 or Kc.dim() != 2 or Kc.stride(1) != 1:
+        raise TypeError("o must be float64, y float32 and Kc a 2-D tensor with contiguous rows")
+    ncand, n = Kc.shape
+    och = np.ascontiguousarray(np.asarray(oc, dtype=np.float64).reshape(ncand))
+    b = ctypes.c_size_t()
+    _check(load().spsvm_score_workspace_bytes(n, ctypes.byref(b)))
+    ws = torch.empty(b.value, dtype=torch.uint8, device=o.device)
+    s_out = np.zeros(ncand)
+    sc_out = np.zeros(ncand)
+    st_out = np.zeros(ncand, dtype=np.int32)
+    ps_out = np.zeros(ncand, dtype=np.int32)
+    win = ctypes.c_int32(-2)
+    P, D, I32 = ctypes.POINTER, ctypes.c_double, ctypes.c_int32
+    _check(load().spsvm_score_candidates(ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(y.data_ptr()), n,
+                                         ctypes.c_void_p(Kc.data_ptr()), _dtype_code(Kc), Kc.stride(0),
+                                         och.ctypes.data_as(P(D)), ncand, float(C), s_out.ctypes.data_as(P(D)),
+                                         sc_out.ctypes.data_as(P(D)), st_out.ctypes.data_as(P(I32)),
+                                         ps_out.ctypes.data_as(P(I32)), ctypes.byref(win),
+                                         ctypes.c_void_p(ws.data_ptr()), b.value, ctypes.c_void_p(_stream_ptr(stream))))
+    return {"s": s_out, "score": sc_out, "status": st_out, "passes": ps_out, "winner": int(win.value)}
 
 
 def candidate_draw(seed: int, t: int, n: int, kappa: int = 59):

@@ -95,7 +95,7 @@ spsvm_status spsvm_train_workspace_bytes(int64_t n, int64_t d, int64_t J_max, sp
     if (!bytes) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bytes must not be NULL");
     if (n < 1 || d < 1 || J_max < 1 || J_max > n) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad sizes");
     if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
-    *bytes = spsvm::make_plan(n, d, J_max, resolve(opt), true, xdt == SPSVM_DT_F64, true).bytes;
+    *bytes = spsvm::make_plan(n, d, J_max, resolve(opt), true, xdt == SPSVM_DT_F64, false).bytes;
   });
 }
 
@@ -105,7 +105,7 @@ spsvm_status spsvm_fixed_workspace_bytes(int64_t n, int64_t d, int64_t m, spsvm_
     if (!bytes) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bytes must not be NULL");
     if (n < 1 || d < 1 || m < 1 || m > n) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad sizes");
     if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
-    *bytes = spsvm::make_plan(n, d, m, resolve(opt), false, xdt == SPSVM_DT_F64, true).bytes;
+    *bytes = spsvm::make_plan(n, d, m, resolve(opt), false, xdt == SPSVM_DT_F64, false).bytes;
   });
 }
 
@@ -141,7 +141,7 @@ spsvm_status spsvm_batch_workspace_bytes(int64_t n, int64_t d, int64_t P, int64_
     if (!bytes) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bytes must not be NULL");
     if (n < 1 || d < 1 || m < 1 || m > n || P < 1) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad sizes");
     if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
-    *bytes = spsvm::make_plan(n, d, m, resolve(opt), false, xdt == SPSVM_DT_F64, true, true, P).bytes;
+    *bytes = spsvm::make_plan(n, d, m, resolve(opt), false, xdt == SPSVM_DT_F64, false, true, P).bytes;
   });
 }
 
@@ -327,6 +327,92 @@ spsvm_status spsvm_newton_solve(double* H, int64_t ldh, int64_t m, const double*
     SPSVM_HIP(hipMemcpyAsync(&fl, &sc->fail, 4, hipMemcpyDeviceToHost, st));
     SPSVM_HIP(hipStreamSynchronize(st));
     if (fl) throw Failure(SPSVM_E_NOT_PD, "Cholesky met a non-positive or non-finite pivot");
+  });
+}
+
+// Scoring workspace: slot states, per-workgroup partial records of a pass, the candidate table, o at the
+// candidate rows, zero hashes (no candidate is blocked) and the scalars.
+static int64_t score_nblk_max(int64_t n) { return std::min<int64_t>(spsvm::ceil_div(n, 128), 4096); }
+static size_t score_ws(int64_t n) {
+  using spsvm::kCandSlots;
+  return (size_t)spsvm::round_up((int64_t)spsvm::kCandStateBytes, 256) +
+         (size_t)spsvm::round_up(score_nblk_max(n) * kCandSlots * 4 * 8, 256) + 4 * 256 * 2 +
+         (size_t)spsvm::round_up((int64_t)sizeof(spsvm::NewtonScalars), 256);
+}
+
+spsvm_status spsvm_score_workspace_bytes(int64_t n, size_t* bytes) {
+  return guarded([&] {
+    if (!bytes || n < 1) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "n must be >= 1 and bytes not NULL");
+    *bytes = score_ws(n);
+  });
+}
+
+spsvm_status spsvm_score_candidates(const double* o, const float* y, int64_t n, const void* Kc, spsvm_dtype kdt,
+                                    int64_t ldc, const double* oc, int32_t ncand, double C, double* s_out,
+                                    double* score_out, int32_t* status_out, int32_t* passes_out, int32_t* winner,
+                                    void* workspace, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    using namespace spsvm;
+    if (!o || !y || !Kc) throw Failure(SPSVM_E_INVALID_ARG, "o, y and Kc must be device pointers");
+    if (!oc || !s_out || !score_out || !winner) throw Failure(SPSVM_E_INVALID_ARG, "oc, s_out, score_out and winner must be host arrays");
+    if (n < 1 || n > 0x7fffffffLL || ldc < n || ncand < 1 || ncand > kCandSlots) throw Failure(SPSVM_E_INVALID_ARG, "bad sizes");
+    if (kdt != SPSVM_DT_F32 && kdt != SPSVM_DT_F64) throw Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
+    if (!(C > 0.0) || !std::isfinite(C)) throw Failure(SPSVM_E_INVALID_ARG, "C must be finite and > 0");
+    if (!workspace || ((uintptr_t)workspace & 255u) || ws_bytes < score_ws(n))
+      throw Failure(SPSVM_E_WORKSPACE, "workspace must be 256-byte aligned with >= spsvm_score_workspace_bytes");
+    const int nblk = score_blocks(n);
+    if (nblk > score_nblk_max(n)) throw Failure(SPSVM_E_WORKSPACE, "more scoring workgroups than the workspace holds");
+    hipStream_t st = as_stream(stream);
+    char* w = (char*)workspace;
+    CandState* cs = (CandState*)w;
+    w += round_up((int64_t)kCandStateBytes, 256);
+    double* partial = (double*)w;
+    w += round_up(score_nblk_max(n) * kCandSlots * 4 * 8, 256);
+    int32_t* cand = (int32_t*)w;
+    double* ocd = (double*)(w + 256);
+    uint64_t* hash = (uint64_t*)(w + 768);
+    uint64_t* stage_hash = (uint64_t*)(w + 1280);
+    NewtonScalars* sc = (NewtonScalars*)(w + 2048);
+    std::vector<int32_t> ch(kCandSlots, -1);
+    std::vector<double> oh(kCandSlots, 0.0);
+    std::vector<uint64_t> zh(kCandSlots, 0);
+    for (int c = 0; c < ncand; ++c) {
+      ch[c] = c;
+      oh[c] = oc[c];
+    }
+    SPSVM_HIP(hipMemcpyAsync(cand, ch.data(), kCandSlots * 4, hipMemcpyHostToDevice, st));
+    SPSVM_HIP(hipMemcpyAsync(ocd, oh.data(), kCandSlots * 8, hipMemcpyHostToDevice, st));
+    SPSVM_HIP(hipMemcpyAsync(hash, zh.data(), kCandSlots * 8, hipMemcpyHostToDevice, st));
+    launch_score_init(cand, ocd, hash, stage_hash, 0, cs, sc, st);
+    const double lam = 1.0 / C;
+    std::vector<CandState> host(kCandSlots);
+    for (int pass = 0; pass < 64;) {
+      for (int r = 0; r < 4; ++r, ++pass) {
+        if (kdt == SPSVM_DT_F64)
+          launch_score_pass<double>((const double*)Kc, ldc, y, o, n, cs, partial, nblk, st);
+        else
+          launch_score_pass<float>((const float*)Kc, ldc, y, o, n, cs, partial, nblk, st);
+        launch_score_update(cs, partial, nblk, lam, nullptr, st);
+      }
+      SPSVM_HIP(hipMemcpyAsync(host.data(), cs, kCandSlots * sizeof(CandState), hipMemcpyDeviceToHost, st));
+      SPSVM_HIP(hipStreamSynchronize(st));
+      bool open = false;
+      for (int c = 0; c < ncand; ++c) open |= host[c].status == 0;
+      if (!open) break;
+    }
+    *winner = -1;
+    double best = -HUGE_VAL;
+    for (int c = 0; c < ncand; ++c) {
+      const CandState& s = host[c];
+      s_out[c] = s.s;
+      score_out[c] = s.status == 1 ? s.score : -HUGE_VAL;
+      if (status_out) status_out[c] = s.status;
+      if (passes_out) passes_out[c] = s.passes;
+      if (s.status == 1 && (*winner < 0 || s.score > best)) {
+        best = s.score;
+        *winner = c;
+      }
+    }
   });
 }
 

@@ -517,6 +517,12 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
   }
 }
 
+// MFMA flops a launch_kblock call issues: whole 128 x 64 tiles, k in chunks of 32.
+double kblock_issued_flops(int64_t n, int64_t d, int64_t ncols) {
+  if (n <= 0 || ncols <= 0) return 0.0;
+  return 2.0 * (double)round_up(n, KB_BM) * (double)round_up(ncols, KB_BN) * (double)round_up(d, KB_BK);
+}
+
 template <typename TX, typename TK>
 void launch_kblock(const TX* X, int64_t ldx, int64_t n, int64_t d, const TK* xnorm, const int32_t* cidx, int ncols,
                    TK* out, int64_t ldo, double gamma, hipStream_t st, const Score0& s0, bool colmajor) {
@@ -922,6 +928,18 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
 constexpr int64_t kWideRows = 65536;
 // 256 x 256 tiles from this many columns on (and enough tiles to fill the chip)
 constexpr int64_t kWideCols = 192;
+
+// MFMA flops a launch_kblock_bf16 call issues: whole tiles of the variant the launcher picks, k over ldb, three
+// products per multiply-add with the split correction (one without).
+double kblock_bf16_issued_flops(int64_t n, int64_t ldb, int64_t ncols, bool split) {
+  if (n <= 0 || ncols <= 0) return 0.0;
+  int64_t bm = 128, bn = KB_BN;
+  if (ncols >= kWideCols && ceil_div(n, 256) * ceil_div(ncols, 256) >= 256)
+    bm = bn = 256;
+  else if (n >= kWideRows && ldb >= 256)
+    bm = 256;
+  return 2.0 * (double)round_up(n, bm) * (double)round_up(ncols, bn) * (double)ldb * (split ? 3.0 : 1.0);
+}
 
 void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int64_t ldb, int64_t n,
                         const float* xnorm, const int32_t* cidx, int ncols, float* out, int64_t ldo, double gamma,

@@ -107,6 +107,10 @@ void launch_split_bf16(const TX* X, int64_t n, int64_t d, int64_t ldx, unsigned 
 // The kernel block with split-BF16 products x.z ~ hi.hi' + hi.lo' + lo.hi' from the split copies, FP32 results
 // (same output and fused pass as launch_kblock). lo = nullptr: every X value is a BF16 number (lo = 0), so only
 // hi.hi' is issued (identical result).
+// MFMA flops one launch issues (whole tiles of the variant the launcher picks; three products per multiply-add
+// with the split correction), for the roofline next to the algorithmic 2 n ncols d.
+double kblock_issued_flops(int64_t n, int64_t d, int64_t ncols);
+double kblock_bf16_issued_flops(int64_t n, int64_t ldb, int64_t ncols, bool split);
 void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int64_t ldb, int64_t n,
                         const float* xnorm, const int32_t* cidx, int ncols, float* out, int64_t ldo, double gamma,
                         hipStream_t st, const Score0& s0 = Score0{}, bool colmajor = false);

@@ -304,9 +304,9 @@ __global__ __launch_bounds__(64 * kScoreWaves, 5) void k_score_pass(const TK* __
       Qa += e > 0.0 ? b * b : 0.0;
       Va += (we - ua) * (we + ua);
       fa += chk && ((e > 0.0) != (gap_at(av, b, sp) > 0.0)) ? 1 : 0;
-      // rows whose activity changes inside the window (rare): appended to the slot's list while it has room
-      if (win && fabs(e) <= wt * fabs(b) &&
-          __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < kWinCap) {
+      // rows whose activity changes inside the window (rare): every one is counted, so a list that ran out of
+      // room (count above kWinCap) is seen as incomplete by the update; the first kWinCap are stored
+      if (win && fabs(e) <= wt * fabs(b)) {
         const int k = atomicAdd(cnt, 1);
         if (k < kWinCap) {
           rows[2 * k] = av;
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(256) void k_score_update(CandState* __restrict__ st
     int32_t* cntp = cand_win_count(st) + c;
     const int cnt = *cntp;
     const double w = kWinFrac * fabs(cs.s);
-    const bool usable = w > 0.0 && cnt <= kWinCap;
+    const bool usable = w > 0.0 && cnt <= kWinCap;  // a longer list is incomplete: no window root this pass
     const bool any = cnt > 0;
     WinRoot wr{false, 0.0, 0.0};
     if (usable) {

@@ -65,7 +65,9 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   Plan p;
   const int64_t xe = x_double ? 8 : 4;
   p.ldx = round_up(d, 16 / xe);
-  p.pad_x = p.ldx != d || !x_aligned;
+  // FP32 / FP64 kernel blocks read X with 16-byte vector loads, so rows must start on 16-byte boundaries (else a
+  // padded copy); the mixed-precision blocks read the split BF16 copies instead and never need it
+  p.pad_x = opt.precision != SPSVM_MIXED && (p.ldx != d || !x_aligned);
   p.ldj = padded_ld<double>(d);
   p.n = n;
   p.d = d;
@@ -177,11 +179,11 @@ struct Profiler {
   struct Pending {
     hipEvent_t a, b;
     int cat;
-    double work;
+    double work, work2;
   };
   std::vector<hipEvent_t> pool;
   std::vector<Pending> pending;
-  double seconds[4] = {0, 0, 0, 0}, work[4] = {0, 0, 0, 0};
+  double seconds[4] = {0, 0, 0, 0}, work[4] = {0, 0, 0, 0}, work2[4] = {0, 0, 0, 0};
   int64_t count[4] = {0, 0, 0, 0};
 
   hipEvent_t get() {
@@ -194,8 +196,9 @@ struct Profiler {
     SPSVM_HIP(hipEventCreate(&e));
     return e;
   }
+  // w: algorithmic work of the launch; w2: a second figure (the MFMA flops a kernel block issues)
   template <class F>
-  void timed(int cat, double w, F&& launch) {
+  void timed(int cat, double w, F&& launch, double w2 = 0.0) {
     if (!(mask & (1 << cat)) || (seen[cat]++ % stride) != 0) {
       launch();
       return;
@@ -204,7 +207,7 @@ struct Profiler {
     SPSVM_HIP(hipEventRecord(a, st));
     launch();
     SPSVM_HIP(hipEventRecord(b, st));
-    pending.push_back({a, b, cat, w});
+    pending.push_back({a, b, cat, w, w2});
     if (pending.size() >= 2048) {
       SPSVM_HIP(hipStreamSynchronize(st));
       flush();
@@ -216,6 +219,7 @@ struct Profiler {
       SPSVM_HIP(hipEventElapsedTime(&ms, p.a, p.b));
       seconds[p.cat] += 1e-3 * ms;
       work[p.cat] += p.work;
+      work2[p.cat] += p.work2;
       count[p.cat] += 1;
       pool.push_back(p.a);
       pool.push_back(p.b);
@@ -398,6 +402,14 @@ struct Impl {
       }
     }
     launch_kblock<TX, TK>(Xk, p.ldx, n, d, xnorm, cols, ncols, out, ldo, gamma, st, s0, colmajor);
+  }
+
+  // MFMA flops kblock() issues for ncols columns.
+  double kblock_issued(int64_t ncols) const {
+    if constexpr (std::is_same<TK, float>::value) {
+      if (opt.precision == SPSVM_MIXED) return kblock_bf16_issued_flops(n, p.ldb, ncols, !bf16_exact);
+    }
+    return kblock_issued_flops(n, d, ncols);
   }
 
   // Basis rows m0..m1 of J gathered into XJ64 (FP64), then the FP64 kernel matrix K_JJ of the first m1 rows.
@@ -817,6 +829,7 @@ struct Impl {
         SPSVM_HIP(hipMemsetAsync(&S.sc->fail, 0, 4, st));
         launch_cholesky(S.Hf, p.ldh, m, S.Linv, S.sc, st);
         S.stats->factorizations += 1;
+        S.stats->jitter_retries += 1;
         if (read(&S.sc->fail) == 0) {
           ok = true;
           break;
@@ -890,8 +903,10 @@ struct Impl {
           s0.y = y;
           s0.o = o;
           s0.partial = score_part;
-          prof.timed(kProfKblock, 2.0 * n * ncand * d,
-                     [&] { kblock(cand_table + (size_t)q0 * kCandSlots, kCandSlots * gsz, Kc, ldc, s0, true); });
+          prof.timed(
+              kProfKblock, 2.0 * n * ncand * d,
+              [&] { kblock(cand_table + (size_t)q0 * kCandSlots, kCandSlots * gsz, Kc, ldc, s0, true); },
+              kblock_issued(kCandSlots * gsz));
           for (int j = 0; j < gsz; ++j) {
             const int q = q0 + j;
             const int32_t* cq = cand_table + (size_t)q * kCandSlots;
@@ -969,8 +984,7 @@ struct Impl {
     SPSVM_HIP(hipMemcpyAsync(J, Jh, m * 8, hipMemcpyHostToDevice, st));
     SPSVM_HIP(hipMemcpyAsync(J32, j32.data(), m * 4, hipMemcpyHostToDevice, st));
     const auto t0 = clk::now();
-    prof.timed(kProfKblock, 2.0 * n * m * d,
-               [&] { kblock(J32, (int)m, KXJ, p.ldk); });
+    prof.timed(kProfKblock, 2.0 * n * m * d, [&] { kblock(J32, (int)m, KXJ, p.ldk); }, kblock_issued(m));
     update_basis(0, (int)m);
     SPSVM_HIP(hipMemsetAsync(beta, 0, m * 8, st));
     sync();
@@ -1006,7 +1020,7 @@ struct Impl {
     {
       const double keep = gamma;
       gamma = 0.0;
-      prof.timed(kProfKblock, 2.0 * n * m * d, [&] { kblock(J32, (int)m, D, p.ldk); });
+      prof.timed(kProfKblock, 2.0 * n * m * d, [&] { kblock(J32, (int)m, D, p.ldk); }, kblock_issued(m));
       gamma = keep;
     }
     launch_gather_rows<TX, double>(X, d, J, m, XJ64, p.ldj, st);
@@ -1088,6 +1102,7 @@ struct Impl {
     stats.kblock_launches = prof.count[kProfKblock];
     stats.kblock_seconds = prof.seconds[kProfKblock];
     stats.kblock_flops = prof.work[kProfKblock];
+    stats.kblock_mfma_flops = prof.work2[kProfKblock];
     stats.syrk_launches = prof.count[kProfSyrk];
     stats.syrk_seconds = prof.seconds[kProfSyrk];
     stats.syrk_flops = prof.work[kProfSyrk];

@@ -92,7 +92,8 @@ def test_rbf_block_negative_index_leaves_column():
     assert np.all(np.isnan(o[:, 1])) and np.all(np.isfinite(o[:, [0, 2]]))
 
 
-@pytest.mark.parametrize("m", [1, 5, 63, 64, 65, 130, 500, 1000, 1025, 1100, 2000])
+# 3329, 4000 and 4100 are past the one-workgroup triangular solves (3328): blocked solves, the last block partial
+@pytest.mark.parametrize("m", [1, 5, 63, 64, 65, 130, 500, 1000, 1025, 1100, 2000, 3329, 4000, 4100])
 def test_newton_solve_matches_numpy(m):
     r = np.random.default_rng(m)
     A = r.standard_normal((m, m + 7))
@@ -114,3 +115,69 @@ def test_newton_solve_reports_not_pd():
     with pytest.raises(lib.SpsvmError) as e:
         lib.newton_solve(H, torch.ones(3, dtype=torch.float64, device="cuda"))
     assert e.value.status == 4
+
+
+# -------------------------------------------------------------------------------------------- scoring
+def _scores_vs_oracle(o, y, cols, oc, C):
+    """GPU scores of the candidate columns against the oracle's exact one-coefficient minimisation on the same
+    values (the columns as the FP32 numbers the GPU reads)."""
+    from oracle import spsvm as osp
+
+    Kc = np.ascontiguousarray(np.stack(cols).astype(np.float32))
+    res = lib.score_candidates(torch.tensor(o, device="cuda"), torch.tensor(y, dtype=torch.float32, device="cuda"),
+                               torch.tensor(Kc, device="cuda"), oc, C)
+    a = 1.0 - y * o
+    f0 = 0.5 * float(np.sum(np.maximum(a, 0.0) ** 2))
+    ref = [osp.score_candidate(a, y * Kc[c].astype(np.float64), 1.0 / C, float(oc[c])) for c in range(len(cols))]
+    return res, ref, f0
+
+
+def _check_scores(res, ref, f0):
+    best = max(r[1] for r in ref)
+    for c, (s_or, sc_or) in enumerate(ref):
+        if res["status"][c] == 1:
+            assert abs(res["s"][c] - s_or) <= 1e-9 * (1.0 + abs(s_or)), (c, res["s"][c], s_or)
+            assert abs(res["score"][c] - sc_or) <= 1e-11 * f0, (c, res["score"][c], sc_or)
+        else:  # dropped: it could not have won
+            assert res["status"][c] == 3 and sc_or <= best * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("n,ncand,C", [(5003, 64, 1.0), (777, 59, 10.0), (1, 3, 1.0), (130, 1, 0.5)])
+def test_candidate_scores_match_oracle(n, ncand, C):
+    r = np.random.default_rng(n + ncand)
+    o = r.standard_normal(n) * 0.8
+    y = np.where(r.random(n) < 0.5, 1.0, -1.0)
+    cols = [np.where(r.random(n) < 0.1, 0.0, r.random(n)) for _ in range(ncand)]
+    oc = r.standard_normal(ncand) * 0.5
+    res, ref, f0 = _scores_vs_oracle(o, y, cols, oc, C)
+    _check_scores(res, ref, f0)
+    want = max(range(ncand), key=lambda c: (ref[c][1], -c))
+    assert res["winner"] == want
+
+
+def test_candidate_score_window_overflow_falls_back_to_full_passes():
+    """Two candidates with the same one-dimensional problem psi'(s) = 0.9 s - sum b max(0, a - s b), built from
+    row groups: 1000 rows with b = 0.01, a = 1 (breakpoint 100); a group with breakpoint 9.99 and sum b^2 = 1; 10
+    rows with breakpoint 5. The first Newton point from s = 0 is 9.98503, just below 9.99, and the root (10) lies
+    just above it: both inside the window of |s| / 256 around that point. For candidate 0 the 9.99 group has 100
+    rows, more than the 64 a window list holds, so the list is incomplete and the slot must continue with full
+    passes (4 in all); for candidate 1 the group has 40 rows and the window walk finishes it after 2 passes. Both
+    scores must be the exact minimum."""
+    def block(nc):
+        bc = float(np.float32(np.sqrt(1.0 / nc)))
+        k = np.concatenate([np.full(1000, 0.01), np.full(nc, bc), np.full(10, 0.02)]).astype(np.float32)
+        kd = k.astype(np.float64)
+        a = np.concatenate([np.ones(1000), 9.99 * kd[1000:1000 + nc], 5.0 * kd[1000 + nc:]])
+        return k, 1.0 - a  # y = +1: a = 1 - o
+    k0, o0 = block(100)
+    k1, o1 = block(40)
+    n0, n1 = k0.size, k1.size
+    o = np.concatenate([o0, o1])
+    y = np.ones(n0 + n1)
+    cols = [np.concatenate([k0, np.zeros(n1, np.float32)]), np.concatenate([np.zeros(n0, np.float32), k1])]
+    res, ref, f0 = _scores_vs_oracle(o, y, cols, np.zeros(2), 1.0 / 0.9)
+    assert list(res["status"]) == [1, 1]
+    _check_scores(res, ref, f0)
+    assert abs(ref[0][0] - 10.0) < 1e-6 and abs(ref[1][0] - 10.0) < 1e-6
+    assert res["passes"][1] == 2
+    assert res["passes"][0] >= 3
