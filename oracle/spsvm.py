@@ -15,7 +15,10 @@ re-optimisation of Eq. 4 on the grown basis, as section 4 describes.
 
 Readings of what the paper leaves open (the details are in Keerthi et al., which is not reproduced):
 
-* Bias b = 0 throughout.
+* Bias: b = 0 by default, as section 2 allows; ``bias=True`` fits the offset of Eq. 4 as an unregularised
+  coordinate (its kernel column all ones).
+* Stopping: J grows to J_max; ``eps_stop`` > 0 adds the rule of section 4 (training-error decrease per added
+  vector below eps_stop after a re-optimisation).
 * Candidate score: the exact decrease of f when only the new coefficient is optimised, the other
   coefficients held fixed (a one-dimensional convex piecewise-quadratic problem, solved exactly).
 * Argmax ties: a strictly larger score wins; equal scores go to the lower training-row index.
@@ -167,6 +170,7 @@ def score_candidate(a: np.ndarray, b: np.ndarray, lam: float, o_c: float):
 # ------------------------------------------------------------------------------------------------- Newton
 @dataclasses.dataclass
 class NewtonInfo:
+    bias: float = 0.0  # the fitted offset b (solve_fixed_J with bias=True)
     iterations: int = 0
     factorizations: int = 0
     grad_norm0: float = 0.0
@@ -236,6 +240,30 @@ class TrainResult:
     gaps: list  # per addition step: (best - second best) / best score
     stages: list  # number of additions per stage
     newton_iters: list
+    b: float = 0.0  # offset of Eq. 4 (0 unless trained with bias=True)
+    errors: list = dataclasses.field(default_factory=list)  # training error after each re-optimisation (eps_stop)
+    stop: str = "J_max"  # "J_max", "eps" (the stopping rule fired), "blocked" (no candidate left) or "max_steps"
+
+
+def training_error(y: np.ndarray, o: np.ndarray) -> float:
+    """Fraction of rows the decision values misclassify (y_i o_i <= 0; a zero output counts as an error)."""
+    return float(np.mean(y * o <= 0.0))
+
+
+def stage_stops(err_prev: float, err: float, added: int, eps_stop: float) -> bool:
+    """The stopping rule of section 4: the decrease of the training error over the last re-optimisation, per basis
+    vector its stage added, is below eps_stop (an unchanged or larger error stops too)."""
+    return (err_prev - err) / added < eps_stop
+
+
+def _with_offset(KXJ: np.ndarray, KJJ: np.ndarray):
+    """Design and regulariser matrices of Eq. 4 with the offset b as an extra coordinate (first): its kernel column
+    is all ones, its regulariser row and column are zero, so f(b, beta) keeps the form of the objective above."""
+    n, m = KXJ.shape
+    A = np.concatenate([np.ones((n, 1)), KXJ], axis=1)
+    R = np.zeros((m + 1, m + 1))
+    R[1:, 1:] = KJJ
+    return A, R
 
 
 def _validate(X, y, C, gamma, J_max, groups):
@@ -251,10 +279,18 @@ def _validate(X, y, C, gamma, J_max, groups):
 
 def train(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J_max: int, seed: int = 0, kappa: int = 59,
           growth: float = 0.25, cap: int = 256, tol: float = 1e-10, ftol: float = 1e-14, max_iter: int = 50,
-          max_steps: Optional[int] = None) -> TrainResult:
+          max_steps: Optional[int] = None, bias: bool = False, eps_stop: float = 0.0) -> TrainResult:
     """Greedy basis growth with Newton re-optimisation after each stage (section 4).
 
     ``max_steps`` (timing samples only) stops after that many addition steps, skipping the final Newton.
+    ``bias``: fit the offset b of Eq. 4 (o_i = k_i^T beta + b, b not regularised). The Newton solves treat it as one
+    more coordinate (see ``_with_offset``); a selection step keeps it fixed, so a candidate's regulariser cross term
+    uses (K beta)_c = o_c - b.
+    ``eps_stop`` > 0: the stopping rule of section 4 ("Sparse primal optimization", implementation paragraph), with
+    the value 5e-6 of section 5: after each re-optimisation, stop when the decrease of the training error since the
+    previous re-optimisation, divided by the number of basis vectors the stage added, is below eps_stop. Training
+    error: the fraction of rows with y_i o_i <= 0 (1 at o = 0, before the first stage); a stage that leaves the
+    error unchanged or raises it stops training. J_max stays an upper bound.
     """
     X = np.asarray(X, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
@@ -264,11 +300,14 @@ def train(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J_max: int, seed
     lam = 1.0 / C
     J: list[int] = []
     beta = np.zeros(0)
+    b = 0.0
     KXJ = np.zeros((n, 0))
     o = np.zeros(n)
     used_groups: set = set()
     f_trace = [0.5 * n]
-    gaps, stages, newton_iters = [], [], []
+    gaps, stages, newton_iters, errors = [], [], [], []
+    err_prev = training_error(y, o)
+    stop = "J_max"
     t = 0
     while len(J) < J_max:
         cs = stage_size(len(J), J_max, growth, cap)
@@ -284,7 +323,7 @@ def train(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J_max: int, seed
                 if groups[c] in used_groups:
                     continue
                 k = rbf_block(X, X[c:c + 1], gamma)[:, 0]
-                s, dl = score_candidate(a, y * k, lam, float(o[c]))
+                s, dl = score_candidate(a, y * k, lam, float(o[c]) - b)
                 if best is None or dl > best[0] or (dl == best[0] and c < best[1]):
                     if best is not None:
                         second = max(second, best[0])
@@ -305,25 +344,45 @@ def train(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J_max: int, seed
         t += cs
         stages.append(added)
         if added == 0:
+            stop = "blocked"
             break
         KXJ = np.concatenate([KXJ, np.stack(new_cols, axis=1)], axis=1)
         if max_steps is not None and t >= max_steps:
+            stop = "max_steps"
             break
         KJJ = KXJ[J, :]
-        beta, info = newton_solve(KXJ, KJJ, y, lam, beta, tol=tol, ftol=ftol, max_iter=max_iter)
+        if bias:
+            A, R = _with_offset(KXJ, KJJ)
+            th, info = newton_solve(A, R, y, lam, np.concatenate([[b], beta]), tol=tol, ftol=ftol, max_iter=max_iter)
+            b, beta = float(th[0]), th[1:]
+            o = A @ th
+        else:
+            beta, info = newton_solve(KXJ, KJJ, y, lam, beta, tol=tol, ftol=ftol, max_iter=max_iter)
+            o = KXJ @ beta
         newton_iters.append(info.iterations)
         f_trace.extend(info.f_trace[1:])
-        o = KXJ @ beta
+        if eps_stop > 0.0:
+            err = training_error(y, o)
+            errors.append(err)
+            if stage_stops(err_prev, err, added, eps_stop):
+                stop = "eps"
+                break
+            err_prev = err
     KJJ = KXJ[J, :]
-    F = C * objective(KXJ, KJJ, y, beta, lam)
-    return TrainResult(np.array(J, dtype=np.int64), beta, F, f_trace, gaps, stages, newton_iters)
+    if bias:
+        A, R = _with_offset(KXJ, KJJ)
+        F = C * objective(A, R, y, np.concatenate([[b], beta]), lam)
+    else:
+        F = C * objective(KXJ, KJJ, y, beta, lam)
+    return TrainResult(np.array(J, dtype=np.int64), beta, F, f_trace, gaps, stages, newton_iters, b, errors, stop)
 
 
 def solve_fixed_J(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J, beta0=None, tol: float = 1e-10,
-                  ftol: float = 1e-14, max_iter: int = 50):
-    """Newton re-optimisation of Eq. 4 on a given basis J, from beta0 (default 0).
+                  ftol: float = 1e-14, max_iter: int = 50, bias: bool = False):
+    """Newton re-optimisation of Eq. 4 on a given basis J, from beta0 (default 0; with ``bias`` the offset starts
+    at 0 and is returned in info.bias).
 
-    Returns (beta, F, info) with F the paper-scale objective at the returned beta.
+    Returns (beta, F, info) with F the paper-scale objective at the returned beta (and offset).
     """
     X = np.asarray(X, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
@@ -332,18 +391,28 @@ def solve_fixed_J(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J, beta0
     KJJ = KXJ[J, :]
     lam = 1.0 / C
     b0 = np.zeros(J.size) if beta0 is None else np.asarray(beta0, dtype=np.float64)
+    if bias:
+        A, R = _with_offset(KXJ, KJJ)
+        th, info = newton_solve(A, R, y, lam, np.concatenate([[0.0], b0]), tol=tol, ftol=ftol, max_iter=max_iter)
+        info.bias = float(th[0])
+        return th[1:], C * objective(A, R, y, th, lam), info
     beta, info = newton_solve(KXJ, KJJ, y, lam, b0, tol=tol, ftol=ftol, max_iter=max_iter)
     return beta, C * objective(KXJ, KJJ, y, beta, lam), info
 
 
-def objective_at(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J, beta) -> float:
-    """Paper-scale F(beta) on basis J, everything recomputed in FP64 from X."""
+def objective_at(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J, beta, b: float = 0.0) -> float:
+    """Paper-scale F(beta, b) on basis J, everything recomputed in FP64 from X."""
     X = np.asarray(X, dtype=np.float64)
     J = np.asarray(J, dtype=np.int64)
     KXJ = rbf_block(X, X[J], gamma)
-    return C * objective(KXJ, KXJ[J, :], np.asarray(y, dtype=np.float64), np.asarray(beta, np.float64), 1.0 / C)
+    beta = np.asarray(beta, np.float64)
+    yd = np.asarray(y, dtype=np.float64)
+    if b != 0.0:
+        A, R = _with_offset(KXJ, KXJ[J, :])
+        return C * objective(A, R, yd, np.concatenate([[b], beta]), 1.0 / C)
+    return C * objective(KXJ, KXJ[J, :], yd, beta, 1.0 / C)
 
 
-def predict(X_basis: np.ndarray, beta: np.ndarray, gamma: float, Xt: np.ndarray) -> np.ndarray:
-    """Decision values sum_k beta_k k(x, x_{J_k}) for each row x of Xt."""
-    return rbf_block(Xt, X_basis, gamma) @ np.asarray(beta, dtype=np.float64)
+def predict(X_basis: np.ndarray, beta: np.ndarray, gamma: float, Xt: np.ndarray, b: float = 0.0) -> np.ndarray:
+    """Decision values sum_k beta_k k(x, x_{J_k}) + b for each row x of Xt."""
+    return rbf_block(Xt, X_basis, gamma) @ np.asarray(beta, dtype=np.float64) + b

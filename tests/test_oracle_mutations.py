@@ -145,3 +145,30 @@ def test_draw_ignoring_the_stage_start_basis_is_caught(monkeypatch):
 def test_duplicates_of_winners_not_blocked_is_caught(monkeypatch):
     monkeypatch.setattr(osp, "duplicate_groups", lambda X: np.arange(np.asarray(X).shape[0]))
     assert _replay_fails()
+
+
+def test_regularised_offset_is_caught(monkeypatch):
+    real = osp._with_offset
+
+    def wrong(KXJ, KJJ):
+        A, R = real(KXJ, KJJ)
+        R[0, 0] = 1.0  # b treated like a basis coefficient with unit kernel value
+        return A, R
+
+    monkeypatch.setattr(osp, "_with_offset", wrong)
+    assert pins.dual_qp_bias_error(range(2)) > 1e-3
+
+
+def test_stop_rule_on_absolute_change_is_caught(monkeypatch):
+    monkeypatch.setattr(osp, "stage_stops", lambda ep, e, added, eps: abs(ep - e) / added < eps)
+    assert pins.stop_rule_mismatches() > 0
+
+
+def test_stop_rule_without_per_vector_scaling_is_caught(monkeypatch):
+    monkeypatch.setattr(osp, "stage_stops", lambda ep, e, added, eps: (ep - e) < eps)
+    assert pins.stop_rule_mismatches() > 0
+
+
+def test_training_error_with_strict_sign_is_caught(monkeypatch):
+    monkeypatch.setattr(osp, "training_error", lambda y, o: float(np.mean(y * o < 0.0)))
+    assert pins.stop_rule_mismatches() > 0

@@ -530,3 +530,122 @@ def test_multi_addition_stages_match_bruteforce_replay():
     mism, multi, skipped = stage_replay()
     assert multi >= 8 and skipped >= 1  # the stage-level rules are exercised
     assert mism == 0
+
+
+# ------------------------------------------------------------------------------------ offset b (Eq. 4 with bias)
+def dual_qp_bias_error(seeds=range(5)):
+    """J = all points with the offset b: Eq. 3 with b. Its dual is the L2-SVM dual of the previous pin with the
+    equality constraint sum y_i alpha_i = 0, whose multiplier is b. Supports S are enumerated: on S,
+    (Q_SS + I / C) alpha_S + y_S b = 1 and y_S^T alpha_S = 0; accepted when alpha_S > 0 and every i outside S has
+    (Q alpha)_i + y_i b >= 1. At the optimum beta = y * alpha, the offsets agree and primal = dual."""
+    worst = 0.0
+    for sd in seeds:
+        n = 9
+        X, y = _tiny(n, 2, 450 + sd)
+        C, gamma = [0.7, 3.0, 20.0, 1.0, 5.0][sd], 0.6
+        K = oracle.rbf_block(X, X, gamma)
+        Q = np.outer(y, y) * K
+        found = []
+        for mask in itertools.product([False, True], repeat=n):
+            S = np.array(mask)
+            k = int(S.sum())
+            if k == 0 or abs(int(np.sum(y[S]))) == k:  # both classes are needed for sum y alpha = 0 with alpha > 0
+                continue
+            M = np.zeros((k + 1, k + 1))
+            M[:k, :k] = Q[np.ix_(S, S)] + np.eye(k) / C
+            M[:k, k] = y[S]
+            M[k, :k] = y[S]
+            sol = np.linalg.solve(M, np.concatenate([np.ones(k), [0.0]]))
+            alpha = np.zeros(n)
+            alpha[S] = sol[:k]
+            b = sol[k]
+            if np.any(alpha[S] <= 0) or np.any((Q @ alpha + y * b)[~S] < 1):
+                continue
+            found.append((alpha, b))
+        assert len(found) == 1
+        alpha, b = found[0]
+        dual = alpha.sum() - 0.5 * alpha @ Q @ alpha - alpha @ alpha / (2 * C)
+        beta, F, info = osp.solve_fixed_J(X, y, C, gamma, np.arange(n), bias=True)
+        worst = max(worst, abs(F - dual) / abs(dual), abs(info.bias - b) / (1 + abs(b)))
+        worst = max(worst, float(np.max(np.abs(beta - y * alpha)) / (1 + np.max(np.abs(alpha)))))
+    return worst
+
+
+def test_full_basis_with_offset_matches_dual_qp():
+    assert dual_qp_bias_error() < 1e-10
+
+
+def selection_bias_mismatches(n=40, steps=8, seed=705):
+    """The oracle's first additions with the offset: for each drawn candidate set, the best candidate by a direct
+    search (append the column, minimise the full objective over the new coefficient with b and the other
+    coefficients fixed) must be the one the oracle picked; Newton on (b, beta) after each stage."""
+    X, y = _tiny(n, 3, seed)
+    y = np.where(np.arange(n) % 4 == 0, 1.0, y)  # unbalanced classes, so b matters
+    C, gamma = 2.0, 0.5
+    lam = 1 / C
+    res = osp.train(X, y, C, gamma, J_max=steps, seed=3, kappa=6, bias=True)
+    J, th, mism, t = [], np.zeros(1), 0, 0
+    grp = _dup_groups(X)
+    for step in range(steps):
+        used = {grp[j] for j in J}
+        cands = orng.draw_candidates(3, t, n, 6, lambda i: grp[i] in used)
+        best = None
+        for c in cands:
+            Jc = J + [c]
+            A, R = osp._with_offset(oracle.rbf_block(X, X[Jc], gamma), oracle.rbf_block(X[Jc], X[Jc], gamma))
+
+            def f(s):
+                return osp.objective(A, R, y, np.append(th, s), lam)
+
+            Rr = 1.0
+            while f(Rr) < f(Rr / 2) or f(-Rr) < f(-Rr / 2):
+                Rr *= 2
+            grid = np.linspace(-Rr, Rr, 4001)
+            k = int(np.argmin([f(v) for v in grid]))
+            s = _golden_section(f, grid[max(k - 1, 0)], grid[min(k + 1, 4000)])
+            if best is None or f(s) < best[0] - 1e-12 or (abs(f(s) - best[0]) <= 1e-12 and c < best[1]):
+                best = (f(s), c, s)
+        J.append(best[1])
+        mism += int(best[1] != res.J[step])
+        A, R = osp._with_offset(oracle.rbf_block(X, X[J], gamma), oracle.rbf_block(X[J], X[J], gamma))
+        th, _ = osp.newton_solve(A, R, y, lam, np.append(th, best[2]))
+        t += 1
+    return mism + int(abs(th[0] - res.b) > 1e-8 * (1 + abs(res.b)))
+
+
+def test_selection_with_offset_matches_bruteforce():
+    assert selection_bias_mismatches() == 0
+
+
+# ------------------------------------------------------------------------------------------ stopping rule
+def stop_rule_mismatches():
+    """The stopping rule (section 4, implementation paragraph; eps = 5e-6 in section 5, larger here for a short
+    trace) on two recorded runs: a steadily improving one (binary rows, stops when the decrease per added vector
+    falls below 2e-3) and one whose error rises at a stage (blobs, eps 1e-3). The training error after each stage is
+    recomputed outside the training loop, from the model a run with J_max at that stage's basis size returns
+    (decision values by the prediction routine, errors y_i o_i <= 0, 1 at o = 0), and the run must stop exactly at
+    the first stage whose decrease per added vector is below eps."""
+    import datagen
+
+    bad = 0
+    p = datagen.make_config("binary-100k", n=3000)
+    Xb, yb = datagen.make_blobs(600, 6, seed=17)
+    for X, y, C, gamma, eps in ((p.X, p.y, p.C, p.gamma, 2e-3), (Xb, yb, 1.0, 1 / 6, 1e-3)):
+        X = np.asarray(X, dtype=np.float64)
+        run = osp.train(X, y, C, gamma, 300, seed=2, bias=True, eps_stop=eps)
+        sizes = np.cumsum(run.stages)
+        errs, prev, stop_at = [], 1.0, None
+        for k, m in enumerate(sizes):
+            r = osp.train(X, y, C, gamma, int(m), seed=2, bias=True)
+            e = float(np.mean(y * oracle.predict(X[r.J], r.beta, gamma, X, r.b) <= 0))
+            errs.append(e)
+            if stop_at is None and (prev - e) / run.stages[k] < eps:
+                stop_at = k
+            prev = e
+        bad += int(run.stop != "eps" or stop_at != len(run.stages) - 1)
+        bad += int(np.max(np.abs(np.array(errs) - np.array(run.errors))) > 1.0 / X.shape[0])
+    return bad
+
+
+def test_stopping_rule_on_recorded_traces():
+    assert stop_rule_mismatches() == 0
