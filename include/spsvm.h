@@ -9,7 +9,8 @@
  *
  * over a basis J of training rows that is grown greedily (random candidate subsets, each candidate
  * scored by the loss reduction it brings) and re-optimised by Newton's method after each stage of
- * additions. The bias term is omitted, as section 2 allows. Every step runs in HIP kernels on the GPU;
+ * additions. The bias term is omitted, as section 2 allows, unless spsvm_options.bias asks for it; growth
+ * stops at a given |J| or by the training-error rule of section 4. Every step runs in HIP kernels on the GPU;
  * the host only orchestrates launches.
  *
  * Conventions for every call:
@@ -75,6 +76,14 @@ typedef struct {
   double refactor_frac;    /* the Newton matrix is re-formed and re-factorised when more than this fraction of
                               the violator set changed since the last factorisation (else the last factor is
                               reused; the exact line search keeps every step a descent step); default 0.002 */
+  int32_t bias;            /* 1: fit the offset b of Eq. 4 (decision k_i^T beta + b, b not regularised), solved with
+                              beta in every Newton re-optimisation and held fixed while candidates are scored;
+                              0 (default): b = 0, as section 2 allows */
+  double eps_stop;         /* > 0: the stopping rule of section 4 (implementation paragraph; section 5 uses 5e-6):
+                              after each re-optimisation, training stops when the decrease of the training error
+                              (fraction of rows with y_i o_i <= 0; 1 before the first stage) divided by the number
+                              of vectors the stage added is below eps_stop (an unchanged or larger error stops it);
+                              J_max stays an upper bound. 0 (default): grow J to J_max */
 } spsvm_options;
 
 typedef struct spsvm_model spsvm_model; /* opaque, owned by the library */
@@ -118,6 +127,8 @@ typedef struct {
                                to the k chunk, three products per multiply-add with the split-BF16 correction */
   int64_t jitter_retries;   /* factorisations repeated with a diagonal shift mu * mean(diag H), mu = 1e-14, 1e-12,
                                1e-10, 1e-8 in turn, because the Newton matrix was not numerically positive definite */
+  int64_t stop_reason;      /* 0: |J| reached J_max; 1: the eps_stop rule; 2: no candidate could be added */
+  double train_error;       /* fraction of rows with y_i o_i <= 0 at the returned model (1 with an empty basis) */
 } spsvm_stats;
 
 /* Fills *opt with the defaults listed above. */
@@ -185,11 +196,14 @@ spsvm_status spsvm_train_batch(const void* X, spsvm_dtype xdt, int64_t n, int64_
 spsvm_status spsvm_model_get(const spsvm_model* model, int64_t* m, int64_t* J_idx, double* beta,
                              double* objective);
 
+/* The offset b of a model (0 unless trained with spsvm_options.bias = 1; batched models share the option). */
+spsvm_status spsvm_model_bias(const spsvm_model* model, double* b);
+
 /* Copies the training statistics of a model into *stats. */
 spsvm_status spsvm_model_stats(const spsvm_model* model, spsvm_stats* stats);
 
-/* Decision values out[i] = sum_k beta_k exp(-gamma ||xt_i - x_{J_k}||^2) (the classifier of Eq. 4
- * without bias), evaluated in the model's precision with FP64 accumulation.
+/* Decision values out[i] = sum_k beta_k exp(-gamma ||xt_i - x_{J_k}||^2) + b (the classifier of Eq. 4; b = 0
+ * unless the model was trained with the offset), evaluated in the model's precision with FP64 accumulation.
  *  Xt: device, n_t x d, element type xdt. out: device, n_t doubles. The n_t x m kernel block is never
  *  stored. The model keeps its own copy of X_J, so the training X need not be alive. When d is not a
  *  multiple of 4 (FP32) or 2 (FP64), or Xt is not 16-byte aligned, a padded copy of Xt is allocated for

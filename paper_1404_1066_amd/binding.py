@@ -30,6 +30,7 @@ EXPORTED = (
     "spsvm_train_batch",
     "spsvm_model_get",
     "spsvm_model_stats",
+    "spsvm_model_bias",
     "spsvm_predict",
     "spsvm_model_free",
     "spsvm_status_string",
@@ -64,6 +65,8 @@ class Options(ctypes.Structure):
         ("log_level", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("refactor_frac", ctypes.c_double),
+        ("bias", ctypes.c_int32),
+        ("eps_stop", ctypes.c_double),
     ]
 
 
@@ -98,6 +101,8 @@ class Stats(ctypes.Structure):
         ("chol_flops", ctypes.c_double),
         ("kblock_mfma_flops", ctypes.c_double),
         ("jitter_retries", ctypes.c_int64),
+        ("stop_reason", ctypes.c_int64),
+        ("train_error", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -129,6 +134,7 @@ def load(path: str = LIB_PATH):
                                       ctypes.c_size_t, VP, P(VP)]
     lib.spsvm_model_get.argtypes = [VP, P(I64), P(I64), P(D), P(D)]
     lib.spsvm_model_stats.argtypes = [VP, P(Stats)]
+    lib.spsvm_model_bias.argtypes = [VP, P(D)]
     lib.spsvm_predict.argtypes = [VP, VP, ctypes.c_int, I64, VP, VP]
     lib.spsvm_model_free.argtypes = [VP]
     lib.spsvm_model_free.restype = None
@@ -147,7 +153,7 @@ def load(path: str = LIB_PATH):
                                            P(I32), P(I32), VP, ctypes.c_size_t, VP]
     for name in ("spsvm_score_candidates", "spsvm_score_workspace_bytes", "spsvm_candidate_draw", "spsvm_rbf_block", "spsvm_rbf_block_workspace_bytes", "spsvm_newton_solve_workspace_bytes", "spsvm_newton_solve",
                  "spsvm_train_workspace_bytes", "spsvm_fixed_workspace_bytes", "spsvm_train",
-                 "spsvm_train_fixed_basis", "spsvm_batch_workspace_bytes", "spsvm_train_batch", "spsvm_model_get", "spsvm_model_stats", "spsvm_predict"):
+                 "spsvm_train_fixed_basis", "spsvm_batch_workspace_bytes", "spsvm_train_batch", "spsvm_model_get", "spsvm_model_stats", "spsvm_model_bias", "spsvm_predict"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -224,6 +230,13 @@ class Model:
         _check(load().spsvm_model_get(self._ptr, None, J.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                       beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(F)))
         return J, beta, F.value
+
+    @property
+    def bias(self) -> float:
+        """The offset b of Eq. 4 (0 unless trained with bias=1)."""
+        b = ctypes.c_double()
+        _check(load().spsvm_model_bias(self._ptr, ctypes.byref(b)))
+        return b.value
 
     def stats(self) -> dict:
         s = Stats()

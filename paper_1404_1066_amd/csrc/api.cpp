@@ -50,6 +50,9 @@ spsvm_options resolve(const spsvm_options* opt) {
   if (o.newton_max_iter < 1) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "newton_max_iter must be >= 1");
   if (!(o.refactor_frac >= 0.0) || !std::isfinite(o.refactor_frac))
     throw spsvm::Failure(SPSVM_E_INVALID_ARG, "refactor_frac must be finite and >= 0");
+  if (o.bias != 0 && o.bias != 1) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bias must be 0 or 1");
+  if (!(o.eps_stop >= 0.0) || !std::isfinite(o.eps_stop))
+    throw spsvm::Failure(SPSVM_E_INVALID_ARG, "eps_stop must be finite and >= 0");
   if (o.precision != SPSVM_F64 && o.precision != SPSVM_F32 && o.precision != SPSVM_MIXED)
     throw spsvm::Failure(SPSVM_E_INVALID_ARG, "precision must be SPSVM_F64, SPSVM_F32 or SPSVM_MIXED");
   return o;
@@ -87,6 +90,8 @@ void spsvm_options_default(spsvm_options* o) {
   o->log_level = 0;
   o->profile = 0;
   o->refactor_frac = 0.002;
+  o->bias = 0;
+  o->eps_stop = 0.0;
 }
 
 spsvm_status spsvm_train_workspace_bytes(int64_t n, int64_t d, int64_t J_max, spsvm_dtype xdt,
@@ -169,6 +174,13 @@ spsvm_status spsvm_model_get(const spsvm_model* md, int64_t* m, int64_t* J_idx, 
     if (J_idx && md->m) std::memcpy(J_idx, md->J.data(), md->m * sizeof(int64_t));
     if (beta && md->m) std::memcpy(beta, md->beta.data(), md->m * sizeof(double));
     if (objective) *objective = md->objective;
+  });
+}
+
+spsvm_status spsvm_model_bias(const spsvm_model* md, double* b) {
+  return guarded([&] {
+    if (!md || !b) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "model and b must not be NULL");
+    *b = md->bias;
   });
 }
 
@@ -383,7 +395,7 @@ spsvm_status spsvm_score_candidates(const double* o, const float* y, int64_t n, 
     SPSVM_HIP(hipMemcpyAsync(cand, ch.data(), kCandSlots * 4, hipMemcpyHostToDevice, st));
     SPSVM_HIP(hipMemcpyAsync(ocd, oh.data(), kCandSlots * 8, hipMemcpyHostToDevice, st));
     SPSVM_HIP(hipMemcpyAsync(hash, zh.data(), kCandSlots * 8, hipMemcpyHostToDevice, st));
-    launch_score_init(cand, ocd, hash, stage_hash, 0, cs, sc, st);
+    launch_score_init(cand, ocd, hash, stage_hash, 0, cs, sc, nullptr, st);
     const double lam = 1.0 / C;
     std::vector<CandState> host(kCandSlots);
     for (int pass = 0; pass < 64;) {

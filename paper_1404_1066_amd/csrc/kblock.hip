@@ -989,7 +989,7 @@ __global__ __launch_bounds__(256) void k_kblock_predict(const TX* __restrict__ X
                                                         const TK* __restrict__ Z, int64_t ldz,
                                                         const TK* __restrict__ znorm, int m,
                                                         const double* __restrict__ beta, double* __restrict__ out,
-                                                        double gamma) {
+                                                        double gamma, double bias) {
   using M = Mfma<TK>;
   __shared__ __attribute__((aligned(32))) TK As[KB_BM][KB_LD];
   __shared__ __attribute__((aligned(32))) TK Bs[KB_BN][KB_LD];
@@ -1037,18 +1037,18 @@ __global__ __launch_bounds__(256) void k_kblock_predict(const TX* __restrict__ X
       double v = racc[i][r];
       for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off, kWave);
       const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
-      if ((lane & 15) == 0 && row < n) out[row] = v;
+      if ((lane & 15) == 0 && row < n) out[row] = v + bias;
     }
 }
 
 template <typename TX, typename TK>
 void launch_predict(const TX* Xt, int64_t ldxt, int64_t n, int64_t d, const TK* Z, int64_t ldz, const TK* znorm, int m,
-                    const double* beta, double* out, double gamma, hipStream_t st) {
+                    const double* beta, double* out, double gamma, double bias, hipStream_t st) {
   if (n <= 0) return;
   if (ldxt % Vec16<TX>::n != 0 || ((uintptr_t)Xt & 15u) || ldz % Vec16<TK>::n != 0 || ((uintptr_t)Z & 15u))
     throw Failure(1, "predict: rows must start on 16-byte boundaries");
   hipLaunchKernelGGL((k_kblock_predict<TX, TK>), dim3((unsigned)ceil_div(n, KB_BM)), dim3(256), 0, st, Xt, ldxt, n, d,
-                     Z, ldz, znorm, m, beta, out, gamma);
+                     Z, ldz, znorm, m, beta, out, gamma, bias);
   SPSVM_LAUNCHED();
 }
 
@@ -1123,6 +1123,23 @@ void launch_iota(int32_t* out, int64_t m, hipStream_t st) {
   SPSVM_LAUNCHED();
 }
 
+// K[i * ld + col] = v for every row i (the all-ones column of the offset b).
+template <typename TK>
+__global__ void k_fill_column(TK* K, int64_t rows, int64_t ld, int64_t col, TK v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x)
+    K[i * ld + col] = v;
+}
+
+template <typename TK>
+void launch_fill_column(TK* K, int64_t rows, int64_t ld, int64_t col, double v, hipStream_t st) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL((k_fill_column<TK>), dim3((unsigned)std::min<int64_t>(ceil_div(rows, 256), 4096)), dim3(256), 0,
+                     st, K, rows, ld, col, (TK)v);
+  SPSVM_LAUNCHED();
+}
+template void launch_fill_column<float>(float*, int64_t, int64_t, int64_t, double, hipStream_t);
+template void launch_fill_column<double>(double*, int64_t, int64_t, int64_t, double, hipStream_t);
+
 // ------------------------------------------------------------------------------------- input checks
 // flags[0] |= some X value is NaN or infinite; flags[1] |= some label is not exactly +1 or -1;
 // flags[2] |= some X value is not exactly a BF16 number (then the split-BF16 lo parts are not all zero).
@@ -1157,7 +1174,7 @@ void launch_check_inputs(const TX* X, int64_t total, const float* y, int64_t n, 
   template void launch_kblock<TX, TK>(const TX*, int64_t, int64_t, int64_t, const TK*, const int32_t*, int, TK*, \
                                       int64_t, double, hipStream_t, const Score0&, bool);                                    \
   template void launch_predict<TX, TK>(const TX*, int64_t, int64_t, int64_t, const TK*, int64_t, const TK*, int,  \
-                                       const double*, double*, double, hipStream_t);                          \
+                                       const double*, double*, double, double, hipStream_t);                          \
   template void launch_gather_rows<TX, TK>(const TX*, int64_t, const int64_t*, int64_t, TK*, int64_t, hipStream_t);
 SPSVM_INST(float, float)
 SPSVM_INST(float, double)

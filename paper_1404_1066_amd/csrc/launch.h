@@ -69,6 +69,8 @@ struct NewtonScalars {
   int32_t fail;    // Cholesky met a non-positive pivot
   int32_t n_active_sel;  // candidates still being scored
   int32_t n_in, n_out;   // rows that joined / left the violator set since the last Newton matrix
+  int32_t n_err;         // rows with y_i o_i <= 0 (training errors), counted by launch_count_errors
+  int32_t pad_;
 };
 
 // ----------------------------------------------------------------------------------------- kblock.hip
@@ -95,9 +97,10 @@ template <typename TX, typename TK>
 void launch_kblock(const TX* X, int64_t ldx, int64_t n, int64_t d, const TK* xnorm, const int32_t* cidx, int ncols,
                    TK* out, int64_t ldo, double gamma, hipStream_t st, const Score0& s0 = Score0{},
                    bool colmajor = false);
+// out = sum_k beta_k exp(-gamma |xt - z_k|^2) + bias per row of Xt.
 template <typename TX, typename TK>
 void launch_predict(const TX* Xt, int64_t ldxt, int64_t n, int64_t d, const TK* Z, int64_t ldz, const TK* znorm, int m,
-                    const double* beta, double* out, double gamma, hipStream_t st);
+                    const double* beta, double* out, double gamma, double bias, hipStream_t st);
 // Split-BF16 copies of X for the mixed kernel block: hi = bf16(x), lo = bf16(x - hi) (round to nearest even),
 // n x ldb each with ldb = split_ld(d) (d rounded up to 32, zero padded); lo may be null (not needed).
 int64_t split_ld(int64_t d);
@@ -128,11 +131,15 @@ void launch_check_inputs(const TX* X, int64_t total, const float* y, int64_t n, 
 template <typename TX, typename TK>
 void launch_gather_rows(const TX* X, int64_t d, const int64_t* idx, int64_t m, TK* out, int64_t ldo, hipStream_t st);
 void launch_iota(int32_t* out, int64_t m, hipStream_t st);
+// K[i * ld + col] = v for rows 0 .. rows - 1.
+template <typename TK>
+void launch_fill_column(TK* K, int64_t rows, int64_t ld, int64_t col, double v, hipStream_t st);
 
 // ----------------------------------------------------------------------------------------- select.hip
 // Score slots for step `step` of the candidate table (kCandSlots indices per step, -1 = empty).
+// bias (device, may be null): the offset b included in o; the slots take o_c - b as (K beta)_c.
 void launch_score_init(const int32_t* cand, const double* o, const uint64_t* hash, const uint64_t* stage_hash,
-                       int n_stage, CandState* st, NewtonScalars* sc, hipStream_t s);
+                       int n_stage, CandState* st, NewtonScalars* sc, const double* bias, hipStream_t s);
 // One scoring pass over the n rows for all active slots (candidate block Kc column-major, column stride ldc;
 // partial sums per workgroup), then one workgroup per
 // slot reduces them and advances the slot. Both kernels return at once when every slot is settled.
@@ -145,14 +152,16 @@ void launch_score_update(CandState* st, const double* partial, int nblk, double 
 // kernel block, as one launch.
 void launch_score_init_update(const int32_t* cand, const double* o, const uint64_t* hash, const uint64_t* stage_hash,
                               int n_stage, CandState* st, const double* partial, int nblk, double lam,
-                              hipStream_t s);
+                              const double* bias, hipStream_t s);
 // Argmax of the scored slots and its append (one launch). Kc: the step's candidate columns, column-major
 // (column stride ldc); fused0: its first scoring pass came with the block; m_dev: two ints, step q reads the basis size at
-// m_dev[q & 1] and writes the next at m_dev[(q + 1) & 1].
+// m_dev[q & 1] and writes the next at m_dev[(q + 1) & 1]. The row index goes to J[pos] and J32[pos], the coefficient
+// to beta[pos + off] and (write_col) the column to K_XJ column pos + off.
 template <typename TK>
 void launch_select_append(const CandState* st, const uint64_t* hash, uint64_t* stage_hash, int q, const TK* Kc,
-                          int64_t ldc, int64_t n, double* o, TK* KXJ, int64_t ldk, int64_t* J, double* beta,
-                          int32_t* m_dev, Selection* sel, int32_t* incomplete, int fused0, hipStream_t s);
+                          int64_t ldc, int64_t n, double* o, TK* KXJ, int64_t ldk, int64_t* J, int32_t* J32,
+                          double* beta, int32_t* m_dev, Selection* sel, int32_t* incomplete, int fused0, int off,
+                          bool write_col, hipStream_t s);
 int score_blocks(int64_t n);
 
 // ----------------------------------------------------------------------------------------- newton.hip
@@ -176,6 +185,8 @@ struct CompactBatch {
 };
 void launch_compact_batch(const CompactBatch& b, int64_t n, hipStream_t s);
 int compact_blocks(int64_t n);
+// sc->n_err = number of rows with y_i o_i <= 0 (misclassified; a zero output counts).
+void launch_count_errors(const double* o, const float* y, int64_t n, NewtonScalars* sc, hipStream_t s);
 // Workgroups of a line-search pass over n rows (partial records per workgroup).
 int ls_blocks(int64_t n);
 template <typename TK>

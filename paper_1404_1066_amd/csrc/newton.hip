@@ -160,6 +160,25 @@ void launch_compact_batch(const CompactBatch& b, int64_t n, hipStream_t s) {
   SPSVM_LAUNCHED();
 }
 
+// Training errors for the stopping rule: rows with y_i o_i <= 0, summed per workgroup, then one integer atomic per
+// workgroup (integer sums do not depend on their order) into a count the launcher clears first.
+__global__ __launch_bounds__(256) void k_count_errors(const double* __restrict__ o, const float* __restrict__ y,
+                                                      int64_t n, int32_t* __restrict__ out) {
+  __shared__ int ri[4];
+  int c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c += ((double)y[i] * o[i] <= 0.0) ? 1 : 0;
+  c = block_sum_int(c, ri);
+  if (threadIdx.x == 0 && c) atomicAdd(out, c);
+}
+
+void launch_count_errors(const double* o, const float* y, int64_t n, NewtonScalars* sc, hipStream_t s) {
+  SPSVM_HIP(hipMemsetAsync(&sc->n_err, 0, sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_count_errors, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 1024), 1024))),
+                     dim3(256), 0, s, o, y, n, &sc->n_err);
+  SPSVM_LAUNCHED();
+}
+
 void launch_compact(const double* o, const float* y, int64_t n, const uint8_t* act_ref, uint8_t* act_out, int32_t* I,
                     int32_t* blk_count, double* blk_sum, int32_t* blk_flips, NewtonScalars* sc, hipStream_t s) {
   CompactBatch b{};

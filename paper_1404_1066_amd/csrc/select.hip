@@ -84,10 +84,11 @@ __device__ __forceinline__ double score_upper(const CandState& s, double lam) {
 // dropping a slot whose computed final score could reach the winner's.
 constexpr double kDropMargin = 1e-7;
 
-// 64 threads: one per slot.
+// 64 threads: one per slot. bias (may be null): the model's offset b, which o includes; a candidate's regulariser
+// cross term needs (K beta)_c = o_c - b.
 __global__ void k_score_init(const int32_t* __restrict__ cand, const double* __restrict__ o,
                              const uint64_t* __restrict__ hash, const uint64_t* __restrict__ stage_hash, int n_stage,
-                             CandState* __restrict__ st, NewtonScalars* sc) {
+                             CandState* __restrict__ st, NewtonScalars* sc, const double* __restrict__ bias) {
   __shared__ int red[1];
   __shared__ uint64_t sh[kMaxStageHash];
   const int c = threadIdx.x;
@@ -110,7 +111,7 @@ __global__ void k_score_init(const int32_t* __restrict__ cand, const double* __r
     s.status = 2;
   } else {
     s.status = 0;
-    s.oc = o[s.idx];
+    s.oc = bias ? o[s.idx] - *bias : o[s.idx];
   }
   st[c] = s;
   cand_win_count(st)[c] = 0;
@@ -119,8 +120,8 @@ __global__ void k_score_init(const int32_t* __restrict__ cand, const double* __r
 }
 
 void launch_score_init(const int32_t* cand, const double* o, const uint64_t* hash, const uint64_t* stage_hash,
-                       int n_stage, CandState* st, NewtonScalars* sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_score_init, dim3(1), dim3(kCandSlots), 0, s, cand, o, hash, stage_hash, n_stage, st, sc);
+                       int n_stage, CandState* st, NewtonScalars* sc, const double* bias, hipStream_t s) {
+  hipLaunchKernelGGL(k_score_init, dim3(1), dim3(kCandSlots), 0, s, cand, o, hash, stage_hash, n_stage, st, sc, bias);
   SPSVM_LAUNCHED();
 }
 
@@ -514,7 +515,7 @@ __global__ __launch_bounds__(256) void k_score_init_update(const int32_t* __rest
                                                            const uint64_t* __restrict__ stage_hash, int n_stage,
                                                            CandState* __restrict__ st,
                                                            const double* __restrict__ partial, int nblk,
-                                                           double lam) {
+                                                           double lam, const double* __restrict__ bias) {
   __shared__ double red[4][4];
   __shared__ int taken;
   const int c = blockIdx.x;
@@ -547,7 +548,7 @@ __global__ __launch_bounds__(256) void k_score_init_update(const int32_t* __rest
     return;
   }
   s.status = 0;
-  s.oc = o[idx];
+  s.oc = bias ? o[idx] - *bias : o[idx];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
   for (int b = threadIdx.x; b < nblk; b += 256) {  // in order; several records in flight
@@ -574,9 +575,9 @@ __global__ __launch_bounds__(256) void k_score_init_update(const int32_t* __rest
 
 void launch_score_init_update(const int32_t* cand, const double* o, const uint64_t* hash, const uint64_t* stage_hash,
                               int n_stage, CandState* st, const double* partial, int nblk, double lam,
-                              hipStream_t s) {
+                              const double* bias, hipStream_t s) {
   hipLaunchKernelGGL(k_score_init_update, dim3(kCandSlots), dim3(256), 0, s, cand, o, hash, stage_hash, n_stage, st,
-                     partial, nblk, lam);
+                     partial, nblk, lam, bias);
   SPSVM_LAUNCHED();
 }
 
@@ -590,15 +591,20 @@ void launch_score_init_update(const int32_t* cand, const double* o, const uint64
 // records its index in incomplete[4]; every later step of the same launch sequence then selects nothing
 // either (incomplete[0] is already set when it starts), so o, J and the basis size stay as they were after the
 // last complete step and the stage can be resumed from the recorded step.
+// The basis row's index goes to J[pos] (and J32[pos]); its coefficient and kernel column to position pos + off
+// of beta and K_XJ (off = 1 when the first coordinate is the offset b). write_col = 0 leaves K_XJ alone (its column
+// is formed later from the stage's winners at a higher precision than the candidate block's).
 template <typename TK>
 __global__ __launch_bounds__(256) void k_select_append(const CandState* __restrict__ st,
                                                        const uint64_t* __restrict__ hash,
                                                        uint64_t* __restrict__ stage_hash, int q,
-                                                       int64_t* __restrict__ J, double* __restrict__ beta,
+                                                       int64_t* __restrict__ J, int32_t* __restrict__ J32,
+                                                       double* __restrict__ beta,
                                                        int32_t* __restrict__ m_dev, Selection* __restrict__ sel,
                                                        int32_t* __restrict__ incomplete, int fused0,
                                                        const TK* __restrict__ Kc, int64_t ldc, int64_t n,
-                                                       double* __restrict__ o, TK* __restrict__ KXJ, int64_t ldk) {
+                                                       double* __restrict__ o, TK* __restrict__ KXJ, int64_t ldk,
+                                                       int off, int write_col) {
   __shared__ Selection choice;
   if (threadIdx.x < kWave) {
     const int c = threadIdx.x;
@@ -638,7 +644,8 @@ __global__ __launch_bounds__(256) void k_select_append(const CandState* __restri
         }
         if (r.valid) {
           J[r.pos] = bidx;
-          beta[r.pos] = r.s;
+          J32[r.pos] = bidx;
+          beta[r.pos + off] = r.s;
           stage_hash[q] = hash[bidx];
         }
         m_dev[(q + 1) & 1] = r.pos + (r.valid ? 1 : 0);
@@ -661,17 +668,18 @@ __global__ __launch_bounds__(256) void k_select_append(const CandState* __restri
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const TK k = Kc[(int64_t)r.slot * ldc + i];  // column-major candidate block
     o[i] += r.s * (double)k;
-    KXJ[i * ldk + r.pos] = k;
+    if (write_col) KXJ[i * ldk + r.pos + off] = k;
   }
 }
 
 template <typename TK>
 void launch_select_append(const CandState* st, const uint64_t* hash, uint64_t* stage_hash, int q, const TK* Kc,
-                          int64_t ldc, int64_t n, double* o, TK* KXJ, int64_t ldk, int64_t* J, double* beta,
-                          int32_t* m_dev, Selection* sel, int32_t* incomplete, int fused0, hipStream_t s) {
+                          int64_t ldc, int64_t n, double* o, TK* KXJ, int64_t ldk, int64_t* J, int32_t* J32,
+                          double* beta, int32_t* m_dev, Selection* sel, int32_t* incomplete, int fused0, int off,
+                          bool write_col, hipStream_t s) {
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 2048));
-  hipLaunchKernelGGL((k_select_append<TK>), dim3((unsigned)blocks), dim3(256), 0, s, st, hash, stage_hash, q, J, beta,
-                     m_dev, sel, incomplete, fused0, Kc, ldc, n, o, KXJ, ldk);
+  hipLaunchKernelGGL((k_select_append<TK>), dim3((unsigned)blocks), dim3(256), 0, s, st, hash, stage_hash, q, J, J32,
+                     beta, m_dev, sel, incomplete, fused0, Kc, ldc, n, o, KXJ, ldk, off, write_col ? 1 : 0);
   SPSVM_LAUNCHED();
 }
 
@@ -680,10 +688,10 @@ template void launch_score_pass<float>(const float*, int64_t, const float*, cons
 template void launch_score_pass<double>(const double*, int64_t, const float*, const double*, int64_t, CandState*,
                                         double*, int, hipStream_t);
 template void launch_select_append<float>(const CandState*, const uint64_t*, uint64_t*, int, const float*, int64_t,
-                                          int64_t, double*, float*, int64_t, int64_t*, double*, int32_t*, Selection*,
-                                          int32_t*, int, hipStream_t);
+                                          int64_t, double*, float*, int64_t, int64_t*, int32_t*, double*, int32_t*,
+                                          Selection*, int32_t*, int, int, bool, hipStream_t);
 template void launch_select_append<double>(const CandState*, const uint64_t*, uint64_t*, int, const double*, int64_t,
-                                           int64_t, double*, double*, int64_t, int64_t*, double*, int32_t*,
-                                           Selection*, int32_t*, int, hipStream_t);
+                                           int64_t, double*, double*, int64_t, int64_t*, int32_t*, double*, int32_t*,
+                                           Selection*, int32_t*, int, int, bool, hipStream_t);
 
 }  // namespace spsvm

@@ -75,8 +75,10 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.tk_double = opt.precision == SPSVM_F64;
   p.batch = batch;
   p.slots = batch ? (int)std::max<int64_t>(1, std::min<int64_t>(problems, kBatchSlots)) : 1;
-  p.ldk = round_up(J_max, 4);
-  p.ldh = round_up(J_max, 4);
+  p.off = opt.bias ? 1 : 0;
+  const int64_t Ms = J_max + p.off;  // largest Newton system: the basis vectors and the offset
+  p.ldk = round_up(Ms, 4);
+  p.ldh = round_up(Ms, 4);
   const size_t tk = p.tk_double ? 8 : 4;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -103,13 +105,13 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.flags = take(16);
   p.XJ64 = take((size_t)J_max * p.ldj * 8);
   p.xjnorm = take(J_max * 8);
-  p.KJJ = take((size_t)J_max * p.ldh * 8);
+  p.KJJ = take((size_t)Ms * p.ldh * 8);
   p.iota = take(J_max * 4);
   p.incomplete = take(32);  // [0] a step did not settle, [1] most passes needed, [2] working passes, [3] slot-passes, [4] first step to redo
   p.Xp = take(p.pad_x ? (size_t)n * p.ldx * xe : 0);
   p.D = take(batch ? (size_t)n * p.ldk * tk : 0);
   p.DJJ = take(batch ? (size_t)J_max * p.ldh * 8 : 0);
-  p.G = take(batch ? (size_t)J_max * p.ldh * 8 : 0);
+  p.G = take(batch ? (size_t)Ms * p.ldh * 8 : 0);
   const bool mixed = opt.precision == SPSVM_MIXED;
   p.ldb = split_ld(d);
   p.Xhi = take(mixed ? (size_t)n * p.ldb * 2 : 0);
@@ -131,18 +133,18 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
     q.cblk_cnt = st(nb_c * 4);
     q.cblk_sum = st(nb_c * 8);
     q.cblk_flips = st(nb_c * 4);
-    q.beta = st(J_max * 8);
-    q.dvec = st(J_max * 8);
-    q.g = st(J_max * 8);
-    q.z = st(J_max * 8);
-    q.H = st((size_t)J_max * p.ldh * 8);
-    q.Hf = st((size_t)J_max * p.ldh * 8);
-    q.Linv = st((size_t)ceil_div(J_max, kCholNB) * kCholNB * kCholNB * 8);
-    q.syrk_part = st((batch ? syrk_partial_doubles_batch((int)J_max) : syrk_partial_doubles((int)J_max)) * 8);
+    q.beta = st(Ms * 8);
+    q.dvec = st(Ms * 8);
+    q.g = st(Ms * 8);
+    q.z = st(Ms * 8);
+    q.H = st((size_t)Ms * p.ldh * 8);
+    q.Hf = st((size_t)Ms * p.ldh * 8);
+    q.Linv = st((size_t)ceil_div(Ms, kCholNB) * kCholNB * kCholNB * 8);
+    q.syrk_part = st((batch ? syrk_partial_doubles_batch((int)Ms) : syrk_partial_doubles((int)Ms)) * 8);
     q.grad_part = st((size_t)1024 * 256 * 8);
     q.ls_part = st((size_t)ls_blocks(n) * 6 * 8);
-    q.vJ = st(J_max * 8);
-    q.wJ = st(J_max * 8);
+    q.vJ = st(Ms * 8);
+    q.wJ = st(Ms * 8);
     q.F_in = st(n * 4);
     q.F_out = st(n * 4);
     q.fcnt_in = st(nb_c * 4);
@@ -391,13 +393,14 @@ struct Impl {
     ls = s0.ls;
   }
 
-  // The n x N kernel block in the training precision (split-BF16 products in MIXED mode).
+  // The n x N kernel block in the training precision (split-BF16 products in MIXED mode; single-pass BF16 products,
+  // hi.hi' only, when single_pass is set).
   void kblock(const int32_t* cols, int ncols, TK* out, int64_t ldo, const Score0& s0 = Score0{},
-              bool colmajor = false) {
+              bool colmajor = false, bool single_pass = false) {
     if constexpr (std::is_same<TK, float>::value) {
       if (opt.precision == SPSVM_MIXED) {
-        launch_kblock_bf16(at<unsigned short>(p.Xhi), bf16_exact ? nullptr : at<unsigned short>(p.Xlo), p.ldb, n,
-                           xnorm, cols, ncols, out, ldo, gamma, st, s0, colmajor);
+        launch_kblock_bf16(at<unsigned short>(p.Xhi), bf16_exact || single_pass ? nullptr : at<unsigned short>(p.Xlo),
+                           p.ldb, n, xnorm, cols, ncols, out, ldo, gamma, st, s0, colmajor);
         return;
       }
     }
@@ -405,11 +408,19 @@ struct Impl {
   }
 
   // MFMA flops kblock() issues for ncols columns.
-  double kblock_issued(int64_t ncols) const {
+  double kblock_issued(int64_t ncols, bool single_pass = false) const {
     if constexpr (std::is_same<TK, float>::value) {
-      if (opt.precision == SPSVM_MIXED) return kblock_bf16_issued_flops(n, p.ldb, ncols, !bf16_exact);
+      if (opt.precision == SPSVM_MIXED)
+        return kblock_bf16_issued_flops(n, p.ldb, ncols, !bf16_exact && !single_pass);
     }
     return kblock_issued_flops(n, d, ncols);
+  }
+
+  // MIXED precision on values that are not all BF16 numbers: the candidate columns, which only feed the selection
+  // heuristic's scores, come from single-pass BF16 products; the columns of the stage's winners, which enter K_XJ
+  // and the Newton system, are formed again with the split correction once the stage is complete.
+  bool single_pass_candidates() const {
+    return std::is_same<TK, float>::value && opt.precision == SPSVM_MIXED && !bf16_exact;
   }
 
   // Basis rows m0..m1 of J gathered into XJ64 (FP64), then the FP64 kernel matrix K_JJ of the first m1 rows.
@@ -417,7 +428,8 @@ struct Impl {
     if (m1 <= m0) return;
     launch_gather_rows<TX, double>(X, d, J + m0, m1 - m0, XJ64 + (size_t)m0 * p.ldj, p.ldj, st);
     launch_row_norms<double, double>(XJ64 + (size_t)m0 * p.ldj, m1 - m0, d, p.ldj, xjnorm + m0, st);
-    launch_kblock<double, double>(XJ64, p.ldj, m1, d, xjnorm, iota, m1, KJJ, p.ldh, gamma, st);
+    launch_kblock<double, double>(XJ64, p.ldj, m1, d, xjnorm, iota, m1, KJJ + (size_t)p.off * (p.ldh + 1), p.ldh,
+                                  gamma, st);
   }
 
   void sync() {
@@ -454,6 +466,10 @@ struct Impl {
       launch_split_bf16<TX>(X, n, d, d, at<unsigned short>(p.Xhi), bf16_exact ? nullptr : at<unsigned short>(p.Xlo),
                             p.ldb, st);
     if (f[1]) throw Failure(SPSVM_E_INVALID_ARG, "labels must be exactly +1 or -1");
+    if (p.off) {  // the offset's coordinate: a column of ones in K_XJ, a zero row and column in K_JJ
+      launch_fill_column<TK>(KXJ, n, p.ldk, 0, 1.0, st);
+      SPSVM_HIP(hipMemsetAsync(KJJ, 0, (size_t)(J_max + 1) * p.ldh * 8, st));
+    }
     std::vector<uint64_t> hs = hash_host;
     std::sort(hs.begin(), hs.end());
     const int64_t distinct = std::unique(hs.begin(), hs.end()) - hs.begin();
@@ -865,7 +881,11 @@ struct Impl {
     std::vector<int32_t> table((size_t)opt.chunk_cap * kCandSlots);
     SPSVM_HIP(hipMemsetAsync(o, 0, n * 8, st));
     SPSVM_HIP(hipMemsetAsync(m_dev, 0, 8, st));
+    SPSVM_HIP(hipMemsetAsync(beta, 0, (J_max + p.off) * 8, st));  // with the offset: b = 0 before the first stage
     const int nblk = score_blocks(n);
+    const bool approx = single_pass_candidates();
+    const double* bias_dev = p.off ? beta : nullptr;  // b (coefficient 0) when it is fitted
+    double err_prev = 1.0;  // training error at o = 0: every y_i o_i = 0 counts as an error
     int first_rounds = 4;
     while (m < J_max) {
       const auto t0 = clk::now();
@@ -905,17 +925,17 @@ struct Impl {
           s0.partial = score_part;
           prof.timed(
               kProfKblock, 2.0 * n * ncand * d,
-              [&] { kblock(cand_table + (size_t)q0 * kCandSlots, kCandSlots * gsz, Kc, ldc, s0, true); },
-              kblock_issued(kCandSlots * gsz));
+              [&] { kblock(cand_table + (size_t)q0 * kCandSlots, kCandSlots * gsz, Kc, ldc, s0, true, approx); },
+              kblock_issued(kCandSlots * gsz, approx));
           for (int j = 0; j < gsz; ++j) {
             const int q = q0 + j;
             const int32_t* cq = cand_table + (size_t)q * kCandSlots;
             const TK* Kq = Kc + (size_t)j * kCandSlots * ldc;
             if (j == 0) {
               launch_score_init_update(cq, o, hash, stage_hash, q, cst, score_part, (int)ceil_div(n, kKblockRows),
-                                       lam, st);
+                                       lam, bias_dev, st);
             } else {
-              launch_score_init(cq, o, hash, stage_hash, q, cst, sc, st);
+              launch_score_init(cq, o, hash, stage_hash, q, cst, sc, bias_dev, st);
               prof.timed(kProfScore, (double)n * (opt.kappa * sizeof(TK) + 12.0),
                          [&] { launch_score_pass<TK>(Kq, ldc, y, o, n, cst, score_part, nblk, st); });
               launch_score_update(cst, score_part, nblk, lam, incomplete + 3, st);
@@ -926,8 +946,8 @@ struct Impl {
               launch_score_update(cst, score_part, nblk, lam, incomplete + 3, st);
             }
             stats.score_passes += rounds - (j == 0 ? 1 : 0);
-            launch_select_append<TK>(cst, hash, stage_hash, q, Kq, ldc, n, o, KXJ, p.ldk, J, beta, m_dev, sel,
-                                     incomplete, j == 0 ? 1 : 0, st);
+            launch_select_append<TK>(cst, hash, stage_hash, q, Kq, ldc, n, o, KXJ, p.ldk, J, J32, beta, m_dev, sel,
+                                     incomplete, j == 0 ? 1 : 0, p.off, !approx, st);
           }
         }
         int32_t flags2[8];
@@ -955,18 +975,36 @@ struct Impl {
         for (int64_t j : jn) blocked.push_back(hash_host[j]);
         std::sort(blocked.begin(), blocked.end());
       }
+      if (approx && m_new > m)  // the winners' columns, split-BF16
+        kblock(J32 + m, m_new - m, KXJ + p.off + m, p.ldk);
       const auto t1 = clk::now();
       stats.seconds_select += secs(t0, t1);
-      if (m_new == m) break;
+      if (m_new == m) {
+        stats.stop_reason = 2;
+        break;
+      }
       update_basis(m, m_new);
+      const int added = m_new - m;
       m = m_new;
-      const int its = newton(m);
+      const int its = newton(m + p.off);
       stats.stages += 1;
+      bool stop = false;
+      if (opt.eps_stop > 0.0) {  // the stopping rule of section 4, after the re-optimisation
+        launch_count_errors(o, y, n, sc, st);
+        const double err = (double)read(&sc->n_err) / (double)n;
+        stats.train_error = err;
+        stop = (err_prev - err) / added < opt.eps_stop;
+        err_prev = err;
+      }
       const auto t2 = clk::now();
       stats.seconds_newton += secs(t1, t2);
       if (opt.log_level >= 1)
         std::fprintf(stderr, "[spsvm] stage %lld |J|=%d added=%d newton_iters=%d select=%.3fs newton=%.3fs\n",
                      (long long)stats.stages, m, cs, its, secs(t0, t1), secs(t1, t2));
+      if (stop) {
+        stats.stop_reason = 1;
+        break;
+      }
     }
     return m;
   }
@@ -984,13 +1022,13 @@ struct Impl {
     SPSVM_HIP(hipMemcpyAsync(J, Jh, m * 8, hipMemcpyHostToDevice, st));
     SPSVM_HIP(hipMemcpyAsync(J32, j32.data(), m * 4, hipMemcpyHostToDevice, st));
     const auto t0 = clk::now();
-    prof.timed(kProfKblock, 2.0 * n * m * d, [&] { kblock(J32, (int)m, KXJ, p.ldk); }, kblock_issued(m));
+    prof.timed(kProfKblock, 2.0 * n * m * d, [&] { kblock(J32, (int)m, KXJ + p.off, p.ldk); }, kblock_issued(m));
     update_basis(0, (int)m);
-    SPSVM_HIP(hipMemsetAsync(beta, 0, m * 8, st));
+    SPSVM_HIP(hipMemsetAsync(beta, 0, (m + p.off) * 8, st));
     sync();
     const auto t1 = clk::now();
     stats.seconds_select += secs(t0, t1);
-    newton((int)m);
+    newton((int)m + p.off);
     stats.stages = 1;
     stats.seconds_newton += secs(t1, clk::now());
     return (int)m;
@@ -1034,8 +1072,8 @@ struct Impl {
     for (int64_t a = 0; a < P; ++a) {
       if (done[a]) continue;
       const double g = gs[a];
-      launch_rbf_from_dist<TK>(D, n, (int)m, p.ldk, KXJ, g, st);
-      launch_rbf_from_dist<double>(DJJ, m, (int)m, p.ldh, KJJ, g, st);
+      launch_rbf_from_dist<TK>(D, n, (int)m, p.ldk, KXJ + p.off, g, st);
+      launch_rbf_from_dist<double>(DJJ, m, (int)m, p.ldh, KJJ + (size_t)p.off * (p.ldh + 1), g, st);
       gamma = g;
       std::vector<int64_t> group;
       for (int64_t q = a; q < P; ++q)
@@ -1048,12 +1086,13 @@ struct Impl {
       double* G = at<double>(p.G);
       {
         Slot& S0 = slots[0];
-        const int T = syrk_tile_rows((int)m), ntile = T * (T + 1) / 2;
+        const int ms = (int)m + p.off;  // Newton system: the basis vectors and the offset
+        const int T = syrk_tile_rows(ms), ntile = T * (T + 1) / 2;
         launch_iota(S0.I, n, st);
         const int ns = syrk_splits_batch(ntile, (int)n);
-        prof.timed(kProfSyrk, (double)n * m * (m + 1.0),
-                   [&] { launch_syrk<TK>(KXJ, p.ldk, (int)m, S0.I, (int)n, 0, ntile, ns, S0.syrk_part, st); });
-        launch_syrk_reduce(KJJ, (int)m, 0.0, S0.syrk_part, ns, 0, ntile, 0, G, p.ldh, st);
+        prof.timed(kProfSyrk, (double)n * ms * (ms + 1.0),
+                   [&] { launch_syrk<TK>(KXJ, p.ldk, ms, S0.I, (int)n, 0, ntile, ns, S0.syrk_part, st); });
+        launch_syrk_reduce(KJJ, ms, 0.0, S0.syrk_part, ns, 0, ntile, 0, G, p.ldh, st);
       }
       for (size_t c0 = 0; c0 < group.size(); c0 += Q) {
         const auto t1 = clk::now();
@@ -1067,15 +1106,15 @@ struct Impl {
           S.lam = 1.0 / Cs[q];
           S.K = KXJ;
           S.KJJ = KJJ;
-          launch_scaled_sum_lower(S.H, KJJ, G, S.lam, (int)m, p.ldh, st);
+          launch_scaled_sum_lower(S.H, KJJ, G, S.lam, (int)m + p.off, p.ldh, st);
           SPSVM_HIP(hipMemsetAsync(S.act_fact, 1, n, st));  // every row a violator, as at beta = 0
           S.hb_valid = true;
-          S.m_fact = (int)m;
-          SPSVM_HIP(hipMemsetAsync(S.beta, 0, m * 8, st));
+          S.m_fact = (int)m + p.off;
+          SPSVM_HIP(hipMemsetAsync(S.beta, 0, (m + p.off) * 8, st));
           ids.push_back((int)ids.size());
         }
-        newton_slots((int)m, ids);
-        gemv_slots((int)m, ids, &Slot::beta, &Slot::o);  // o at the final beta, for the models' statistics
+        newton_slots((int)m + p.off, ids);
+        gemv_slots((int)m + p.off, ids, &Slot::beta, &Slot::o);  // o at the final beta, for the models' statistics
         sync();
         const double share = secs(t1, clk::now()) / ids.size();
         for (size_t k = 0; k < ids.size(); ++k) {
@@ -1094,10 +1133,16 @@ struct Impl {
   spsvm_model* build_model(Slot& S, int m, bool o_fresh = false) {
     double F = 0.0;
     NewtonScalars s{};
-    final_eval(S, m, &F, &s, o_fresh);
+    final_eval(S, m > 0 ? m + p.off : 0, &F, &s, o_fresh);  // with the offset the system has one more coordinate
     spsvm_stats& stats = *S.stats;
     stats.n_sv = s.n_sv;
     stats.grad_norm = std::sqrt(s.gnorm2);
+    if (m > 0) {  // training error at the returned model (o is current after final_eval)
+      launch_count_errors(S.o, S.y, n, S.sc, st);
+      stats.train_error = (double)read(&S.sc->n_err) / (double)n;
+    } else {
+      stats.train_error = 1.0;  // o = 0: every row counts as an error
+    }
     sync();
     stats.kblock_launches = prof.count[kProfKblock];
     stats.kblock_seconds = prof.seconds[kProfKblock];
@@ -1129,15 +1174,16 @@ struct Impl {
       md->J.resize(m);
       md->beta.resize(m);
       if (m > 0) {
+        if (p.off) md->bias = read(S.beta);  // coefficient 0 is b
         SPSVM_HIP(hipMemcpyAsync(md->J.data(), J, m * 8, hipMemcpyDeviceToHost, st));
-        SPSVM_HIP(hipMemcpyAsync(md->beta.data(), S.beta, m * 8, hipMemcpyDeviceToHost, st));
+        SPSVM_HIP(hipMemcpyAsync(md->beta.data(), S.beta + p.off, m * 8, hipMemcpyDeviceToHost, st));
         md->ldz = padded_ld<TK>(d);
         SPSVM_HIP(hipMalloc(&md->XJ, (size_t)m * md->ldz * sizeof(TK)));
         SPSVM_HIP(hipMalloc(&md->XJnorm, (size_t)m * sizeof(TK)));
         SPSVM_HIP(hipMalloc(&md->beta_dev, (size_t)m * 8));
         launch_gather_rows<TX, TK>(X, d, J, m, (TK*)md->XJ, md->ldz, st);
         launch_row_norms<TK, TK>((const TK*)md->XJ, m, d, md->ldz, (TK*)md->XJnorm, st);
-        SPSVM_HIP(hipMemcpyAsync(md->beta_dev, S.beta, m * 8, hipMemcpyDeviceToDevice, st));
+        SPSVM_HIP(hipMemcpyAsync(md->beta_dev, S.beta + p.off, m * 8, hipMemcpyDeviceToDevice, st));
         sync();
       }
     } catch (...) {
@@ -1187,7 +1233,7 @@ static void predict_typed(const spsvm_model* md, const TX* Xt, int64_t n_t, doub
   }
   try {
     launch_predict<TX, TK>(A, ld, n_t, d, (const TK*)md->XJ, md->ldz, (const TK*)md->XJnorm, (int)md->m, md->beta_dev,
-                           out, md->gamma, st);
+                           out, md->gamma, md->bias, st);
     SPSVM_HIP(hipStreamSynchronize(st));
   } catch (...) {
     if (tmp) (void)hipFree(tmp);

@@ -12,6 +12,7 @@ struct spsvm_model {
   int64_t m = 0, d = 0, ldz = 0;  // ldz: row stride of the basis copy XJ
   int tk_double = 0;  // kernel values / basis copy in FP64 (else FP32)
   double C = 1.0, gamma = 1.0, objective = 0.0;
+  double bias = 0.0;  // offset b of Eq. 4 (0 unless trained with it)
   std::vector<int64_t> J;
   std::vector<double> beta;
   void* XJ = nullptr;      // device, m x d, element type FP64 or FP32 (tk_double)
@@ -44,6 +45,8 @@ struct Plan {
   bool pad_x = false;  // X is copied with a padded row stride (rows on 16-byte boundaries)
   bool tk_double = false;
   bool batch = false;
+  int off = 0;  // 1 when the offset b is a Newton coordinate: column 0 of K_XJ is all ones, row / column 0 of K_JJ
+                // zero, coefficient 0 is b, and basis vector k sits at position k + 1 of every coefficient array
   size_t bytes = 0;
   // offsets into the workspace (shared by all slots)
   size_t xnorm, hash, KXJ, Kc, J, J32, cand_state, sel, ls, scalars, score_part, cand_table, stage_hash, m_dev, flags,

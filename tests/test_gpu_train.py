@@ -454,3 +454,74 @@ def test_onehot_200k_full_basis_mixed_reaches_oracle_objective():
     dg = model.predict(Xg[torch.tensor(rows, device="cuda")]).cpu().numpy()
     do = oracle.predict(p.X[J], b_or, p.gamma, p.X[rows])
     assert _decision_err(dg, do) <= 1e-4
+
+
+def test_offset_and_stopping_rule_identical_to_oracle_f64():
+    """Eq. 4 with the offset b and the training-error stopping rule of section 4 (here eps = 2e-3 so that it stops
+    after a dozen stages), FP64 path: the same basis, hence the same stopping stage, the same b and objective as
+    the oracle; the reported training error is the oracle's last one."""
+    p = datagen.make_config("binary-100k", n=3000)
+    X = p.X.astype(np.float64)
+    ref = oracle.train(X, p.y, p.C, p.gamma, 300, seed=2, bias=True, eps_stop=2e-3)
+    assert ref.stop == "eps" and len(ref.J) < 300
+    Xg, yg = _dev(X, p.y)
+    model = lib.train(Xg, yg, p.C, p.gamma, 300, seed=2, precision="f64", bias=1, eps_stop=2e-3)
+    J, beta, F = model.get()
+    st = model.stats()
+    assert J.tolist() == ref.J.tolist()
+    assert st["stop_reason"] == 1
+    assert abs(model.bias - ref.b) <= 1e-8 * (1 + abs(ref.b))
+    Fo = osp.objective_at(X, p.y, p.C, p.gamma, J, beta, b=model.bias)
+    assert abs(Fo - ref.F) <= 1e-9 * ref.F and abs(F - Fo) <= 1e-9 * Fo
+    assert abs(st["train_error"] - ref.errors[-1]) <= 1.0 / X.shape[0]
+    dg = model.predict(Xg).cpu().numpy()
+    do = oracle.predict(X[ref.J], ref.beta, p.gamma, X, ref.b)
+    assert _decision_err(dg, do) <= 1e-9
+
+
+def test_offset_blobs_identical_basis_f64():
+    p = datagen.make_config("blobs-2k")
+    y = np.where(np.arange(2000) % 3 == 0, 1.0, -1.0)  # one class in three: the offset is far from 0
+    ref = oracle.train(p.X, y, p.C, p.gamma, p.J_max, seed=0, bias=True)
+    Xg, yg = _dev(p.X, y)
+    model = lib.train(Xg, yg, p.C, p.gamma, p.J_max, seed=0, precision="f64", bias=1)
+    J, beta, F = model.get()
+    assert J.tolist() == ref.J.tolist()
+    assert abs(model.bias - ref.b) <= 1e-8 * (1 + abs(ref.b)) and abs(ref.b) > 0.05
+    Fo = osp.objective_at(p.X, y, p.C, p.gamma, J, beta, b=model.bias)
+    assert abs(Fo - ref.F) <= 1e-9 * ref.F
+
+
+@pytest.mark.parametrize("prec", ["f32", "mixed"])
+def test_offset_greedy_reaches_oracle_objective(prec):
+    X, y = datagen.make_blobs(3001, 21, seed=14, dtype=np.float32)
+    y = np.where(X[:, 0] + 0.5 * X[:, 1] > 1.5, 1.0, -1.0)  # unbalanced classes: the offset matters
+    C, gamma, m = 2.0, 1.0 / 21, 120
+    Xg, yg = _dev(X, y)
+    model = lib.train(Xg, yg, C, gamma, m, seed=3, precision=prec, bias=1)
+    J, beta, F = model.get()
+    b_or, F_or, info = osp.solve_fixed_J(X, y, C, gamma, J, bias=True)
+    Fo = osp.objective_at(X, y, C, gamma, J, beta, b=model.bias)
+    assert abs(Fo - F_or) / F_or <= 1e-6
+    dg = model.predict(Xg).cpu().numpy()
+    do = oracle.predict(X[J], b_or, gamma, X, info.bias)
+    assert _decision_err(dg, do) <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_offset_fixed_basis_and_batch_match_oracle(prec):
+    """The offset in a fixed-basis solve and in a batch of one-vs-rest problems on one basis (FP32 and FP64 kernel
+    values): each model reaches the oracle's optimum of Eq. 4 with b at the same basis."""
+    p = datagen.make_config("mnist-60k", n=2000, J_max=120)
+    sel = [0, 5, 18]
+    Xg = torch.tensor(p.X, device="cuda")
+    Yg = torch.tensor(p.Y[sel], dtype=torch.float32, device="cuda").contiguous()
+    models = lib.train_batch(Xg, Yg, p.C[sel], p.gamma[sel], p.J, precision=prec, bias=1)
+    for q, s_ in enumerate(sel):
+        _, bb, _ = models[q].get()
+        b_or, F_or, info = osp.solve_fixed_J(p.X, p.Y[s_], p.C[s_], p.gamma[s_], p.J, bias=True)
+        Fo = osp.objective_at(p.X, p.Y[s_], p.C[s_], p.gamma[s_], p.J, bb, b=models[q].bias)
+        assert abs(Fo - F_or) / F_or <= (1e-6 if prec == "f32" else 1e-10)
+        single = lib.train_fixed_basis(Xg, Yg[q].contiguous(), p.C[s_], p.gamma[s_], p.J, precision=prec, bias=1)
+        assert abs(single.bias - models[q].bias) <= 1e-6 * (1 + abs(info.bias))
+        assert abs(single.bias - info.bias) <= 1e-4 * (1 + abs(info.bias))
