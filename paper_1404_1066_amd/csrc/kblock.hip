@@ -741,13 +741,17 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
 // Split-BF16 block in 256 x 256 tiles for blocks with many columns (grouped candidate steps, a whole basis):
 // 8 waves in a 4 x 2 grid, each 64 rows x 128 columns (4 x 8 MFMA tiles). Every A fragment read from LDS feeds
 // 8 tiles and every B fragment 4, and each staged byte feeds twice the products of a 256 x 64 tile; two waves
-// share each SIMD. Two LDS stages of one 32-wide k chunk each (unpadded 64-byte rows): chunk t is multiplied
-// from one stage while chunk t + 1 goes from registers into the other, so each chunk costs one barrier.
-// 16-byte LDS accesses are served 8 lanes at a time over 32 four-byte banks; the 16-byte part p of row r is
-// kept at position p ^ ((r >> 1) & 3), which makes both the staging writes (two rows per 8 lanes) and the
-// fragment reads (8 rows at one part) conflict-free. The k chunks, the order of the three products inside a
-// chunk and the epilogue are those of k_kblock_bf16, so both give the same bits.
-template <bool SPLIT>
+// share each SIMD. Two LDS stages of one k chunk each: chunk t is multiplied from one stage while chunk t + 1 goes
+// from registers into the other and chunk t + 2 is loaded from memory into registers, so each chunk costs one
+// barrier and a load has a whole chunk of products to arrive in. The chunk is BK = 32 wide with the split
+// correction (three products per pair of fragments) and 64 wide for single-pass products, whose chunk of 32 would
+// leave too few products per chunk to cover the loads. The k chunks run over ldb (a multiple of 32) in order;
+// a last half chunk of 32 (ldb not a multiple of 64) loads zeros for its missing half and skips its products.
+// 16-byte LDS accesses are served 8 lanes at a time over 32 four-byte banks: the 16-byte part p of row r is kept
+// at position p ^ ((r >> 1) & 3) in 64-byte rows (BK = 32) and p ^ (r & 7) in 128-byte rows (BK = 64), which
+// makes both the staging writes and the fragment reads (8 rows at one part) conflict-free. Within a 32-wide k step
+// the order of the three products and the epilogue are those of k_kblock_bf16, so both give the same bits.
+template <bool SPLIT, int BK>
 __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* __restrict__ hi,
                                                           const unsigned short* __restrict__ lo, int64_t ldb,
                                                           int64_t n, const float* __restrict__ xnorm,
@@ -755,27 +759,30 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
                                                           float* __restrict__ out, int64_t ldo, double gamma,
                                                           const Score0 s0, int cm) {
   constexpr int BM = 256, BN = 256;
+  constexpr int PARTS = BK / 8;               // 16-byte parts per staged row
+  constexpr int NQ = BM * PARTS / 512;        // 16-byte vectors per thread per operand per chunk
   // two stages of the operand chunks during the k loop; afterwards (column-major out) 128 columns of the tile
   // at a time as [column][row]
-  typedef unsigned short Stage[BM][SB_BK];
+  typedef unsigned short Stage[BM][BK];
   static_assert(BM == BN, "one stage type for both operands");
+  static_assert(BK == 32 || BK == 64, "32- or 64-wide k chunks");
   constexpr int kOps = (SPLIT ? 8 : 4) * (int)sizeof(Stage), kTr = 128 * (BM + 4) * 4;
   __shared__ __attribute__((aligned(16))) char smem[kOps > kTr ? kOps : kTr];
   Stage* Ah = reinterpret_cast<Stage*>(smem);
   Stage* Bh = Ah + 2;
   Stage* Al = Ah + 4;  // SPLIT only
   Stage* Bl = Ah + 6;  // SPLIT only
-  auto phys = [](int row, int p) { return p ^ ((row >> 1) & 3); };
+  auto phys = [](int row, int p) { return BK == 32 ? p ^ ((row >> 1) & 3) : p ^ (row & 7); };
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w & 3, wc = w >> 2, g = lane >> 4,
             i16 = lane & 15;
   const TileOf tile = xcd_tile(ceil_div_dev(ncols, BN));
   const int64_t r0 = tile.r * BM, c0 = tile.c * BN;
   if (r0 >= n) return;  // padding of the row-tile count to a multiple of 8
-  const int part = tid & 3;  // which 8 of the chunk's 32 k this thread stages
-  int64_t aoff[2], boff[2];
+  const int part = tid % PARTS;  // which 8 of the chunk's BK values of k this thread stages
+  int64_t aoff[NQ], boff[NQ];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int rr = (tid + 512 * q) >> 2;
+  for (int q = 0; q < NQ; ++q) {
+    const int rr = (tid + 512 * q) / PARTS;
     const int64_t row = r0 + rr, col = c0 + rr;
     aoff[q] = row < n ? row * ldb + 8 * part : -1;
     const int64_t src = col < ncols ? (cidx ? (int64_t)cidx[col] : col) : -1;
@@ -786,22 +793,23 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[i][j] = floatx4{0, 0, 0, 0};
-  u32x4 rah[2], ral[2], rbh[2], rbl[2];
+  u32x4 rah[NQ], ral[NQ], rbh[NQ], rbl[NQ];
   auto fetch = [&](int64_t k0) {
+    const bool in = k0 + 8 * part < ldb;  // a last half chunk reads zeros past ldb
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      rah[q] = aoff[q] >= 0 ? *(const u32x4*)(hi + aoff[q] + k0) : u32x4{0, 0, 0, 0};
-      rbh[q] = boff[q] >= 0 ? *(const u32x4*)(hi + boff[q] + k0) : u32x4{0, 0, 0, 0};
+    for (int q = 0; q < NQ; ++q) {
+      rah[q] = in && aoff[q] >= 0 ? *(const u32x4*)(hi + aoff[q] + k0) : u32x4{0, 0, 0, 0};
+      rbh[q] = in && boff[q] >= 0 ? *(const u32x4*)(hi + boff[q] + k0) : u32x4{0, 0, 0, 0};
       if (SPLIT) {
-        ral[q] = aoff[q] >= 0 ? *(const u32x4*)(lo + aoff[q] + k0) : u32x4{0, 0, 0, 0};
-        rbl[q] = boff[q] >= 0 ? *(const u32x4*)(lo + boff[q] + k0) : u32x4{0, 0, 0, 0};
+        ral[q] = in && aoff[q] >= 0 ? *(const u32x4*)(lo + aoff[q] + k0) : u32x4{0, 0, 0, 0};
+        rbl[q] = in && boff[q] >= 0 ? *(const u32x4*)(lo + boff[q] + k0) : u32x4{0, 0, 0, 0};
       }
     }
   };
   auto store = [&](int b) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int rr = (tid + 512 * q) >> 2, pp = 8 * phys(rr, part);
+    for (int q = 0; q < NQ; ++q) {
+      const int rr = (tid + 512 * q) / PARTS, pp = 8 * phys(rr, part);
       *(u32x4*)&Ah[b][rr][pp] = rah[q];
       *(u32x4*)&Bh[b][rr][pp] = rbh[q];
       if (SPLIT) {
@@ -810,41 +818,47 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
       }
     }
   };
-  auto compute = [&](int b) {
-    bf16x8 ah[4], al[4];
+  auto compute = [&](int b, int ksteps) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int ra = wr * 64 + i * 16 + i16, pa = 8 * phys(ra, g);
-      ah[i] = *(const bf16x8*)&Ah[b][ra][pa];
-      if (SPLIT) al[i] = *(const bf16x8*)&Al[b][ra][pa];
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int rb = wc * 128 + j * 16 + i16, pb = 8 * phys(rb, g);
-      const bf16x8 bh = *(const bf16x8*)&Bh[b][rb][pb];
-      bf16x8 bl;
-      if (SPLIT) bl = *(const bf16x8*)&Bl[b][rb][pb];
+    for (int kk = 0; kk < BK / 32; ++kk) {
+      if (kk >= ksteps) break;  // uniform: the missing half of a last half chunk
+      bf16x8 ah[4], al[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        if (SPLIT) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+        const int ra = wr * 64 + i * 16 + i16, pa = 8 * phys(ra, 4 * kk + g);
+        ah[i] = *(const bf16x8*)&Ah[b][ra][pa];
+        if (SPLIT) al[i] = *(const bf16x8*)&Al[b][ra][pa];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int rb = wc * 128 + j * 16 + i16, pb = 8 * phys(rb, 4 * kk + g);
+        const bf16x8 bh = *(const bf16x8*)&Bh[b][rb][pb];
+        bf16x8 bl;
+        if (SPLIT) bl = *(const bf16x8*)&Bl[b][rb][pb];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (SPLIT) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+          }
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
         }
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
       }
     }
   };
-  const int nk = (int)(ldb / SB_BK);
+  const int nk32 = (int)(ldb / 32);               // 32-wide k steps
+  const int nk = (nk32 * 32 + BK - 1) / BK;        // chunks
+  auto steps_of = [&](int t) { return nk32 - t * (BK / 32) < BK / 32 ? nk32 - t * (BK / 32) : BK / 32; };
   fetch(0);
   store(0);
-  if (nk > 1) fetch(SB_BK);
+  if (nk > 1) fetch(BK);
   __syncthreads();
   for (int t = 0; t < nk; ++t) {
-    compute(t & 1);
+    compute(t & 1, steps_of(t));
     // the other stage was last read for chunk t - 1, which every wave finished before the previous barrier
     if (t + 1 < nk) {
       store((t + 1) & 1);
-      if (t + 2 < nk) fetch((int64_t)(t + 2) * SB_BK);
+      if (t + 2 < nk) fetch((int64_t)(t + 2) * BK);
     }
     __syncthreads();
   }
@@ -954,10 +968,10 @@ void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int6
   if (ncols >= kWideCols && ceil_div(n, 256) * ceil_div(ncols, 256) >= 256) {
     const dim3 grid(xcd_grid(ceil_div(n, 256), ceil_div(ncols, 256)));
     if (lo)
-      hipLaunchKernelGGL((k_kblock_bf16_wide<true>), grid, dim3(512), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
-                         ldo, gamma, s0, cm);
+      hipLaunchKernelGGL((k_kblock_bf16_wide<true, 32>), grid, dim3(512), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols,
+                         out, ldo, gamma, s0, cm);
     else
-      hipLaunchKernelGGL((k_kblock_bf16_wide<false>), grid, dim3(512), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols,
+      hipLaunchKernelGGL((k_kblock_bf16_wide<false, 64>), grid, dim3(512), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols,
                          out, ldo, gamma, s0, cm);
     SPSVM_LAUNCHED();
     return;

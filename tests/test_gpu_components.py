@@ -52,9 +52,10 @@ def test_rbf_block_mixed_within_split_bound(n, d, nc):
 
 
 @pytest.mark.parametrize("n,d,nc,binary", [(70001, 300, 260, False), (66000, 54, 512, False),
-                                           (66000, 123, 256, True)])
+                                           (66000, 123, 256, True), (66000, 90, 300, True)])
 def test_rbf_block_mixed_wide_tiles(n, d, nc, binary):
-    """Blocks of 192 or more columns (with at least 256 tiles) take 256 x 256 tiles. Against the oracle: the split
+    """Blocks of 192 or more columns (with at least 256 tiles) take 256 x 256 tiles (binary rows: single-pass
+    products in 64-wide k chunks; 90 features make the last chunk a half one). Against the oracle: the split
     bound (exact on binary rows). Against 64-column slices of the same block, which take the 64-column tiles: the
     same products are summed in the same order, so the bits agree."""
     X, idx, gamma, K, want = _kblock_case(n, d, nc, "mixed", np.float32, n * 17 + d, binary=binary)
