@@ -34,4 +34,8 @@ from .spsvm import (  # noqa: F401
     train,
     predict,
     duplicate_groups,
+    ovo_pairs,
+    train_ovo,
+    ovo_vote,
+    predict_ovo,
 )

@@ -416,3 +416,42 @@ def objective_at(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J, beta, 
 def predict(X_basis: np.ndarray, beta: np.ndarray, gamma: float, Xt: np.ndarray, b: float = 0.0) -> np.ndarray:
     """Decision values sum_k beta_k k(x, x_{J_k}) + b for each row x of Xt."""
     return rbf_block(Xt, X_basis, gamma) @ np.asarray(beta, dtype=np.float64) + b
+
+
+# ------------------------------------------------------------------------------------------ one-vs-one
+def ovo_pairs(K: int):
+    """The class pairs (a, b), a < b, in the order (0, 1), (0, 2), ..., (K - 2, K - 1)."""
+    return [(a, b) for a in range(K) for b in range(a + 1, K)]
+
+
+def train_ovo(X: np.ndarray, classes: np.ndarray, K: int, C: float, gamma: float, J_max: int, **kw):
+    """One-vs-one multiclass training, as section 5 trains MNIST8M (one classifier per pair of classes, each on the
+    rows of its two classes only): for each pair (a, b) greedy training on the rows of classes a (label +1) and b
+    (label -1), keeping their order. Returns one (TrainResult, rows) per pair in ovo_pairs order, where rows are the
+    pair's training rows (indices into X) and result.J indexes them; ``kw`` as for ``train``."""
+    X = np.asarray(X, dtype=np.float64)
+    classes = np.asarray(classes)
+    out = []
+    for a, b in ovo_pairs(K):
+        rows = np.flatnonzero((classes == a) | (classes == b))
+        y = np.where(classes[rows] == a, 1.0, -1.0)
+        out.append((train(X[rows], y, C, gamma, J_max, **kw), rows))
+    return out
+
+
+def ovo_vote(decisions: np.ndarray, K: int) -> np.ndarray:
+    """Class of each row from the pairwise decision values (one column per pair, ovo_pairs order): a positive value
+    is a vote for a, any other for b; the class with the most votes wins, the lowest class on ties."""
+    votes = np.zeros((decisions.shape[0], K), dtype=np.int64)
+    for p, (a, b) in enumerate(ovo_pairs(K)):
+        pos = decisions[:, p] > 0
+        votes[pos, a] += 1
+        votes[~pos, b] += 1
+    return np.argmax(votes, axis=1)  # the first maximum: the lowest class on ties
+
+
+def predict_ovo(X: np.ndarray, models, gamma: float, Xt: np.ndarray, K: int) -> np.ndarray:
+    """Classes of the rows of Xt by one-vs-one voting over the models of ``train_ovo``."""
+    X = np.asarray(X, dtype=np.float64)
+    dec = np.stack([predict(X[rows][res.J], res.beta, gamma, Xt, res.b) for res, rows in models], axis=1)
+    return ovo_vote(dec, K)

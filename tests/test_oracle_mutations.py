@@ -172,3 +172,29 @@ def test_stop_rule_without_per_vector_scaling_is_caught(monkeypatch):
 def test_training_error_with_strict_sign_is_caught(monkeypatch):
     monkeypatch.setattr(osp, "training_error", lambda y, o: float(np.mean(y * o < 0.0)))
     assert pins.stop_rule_mismatches() > 0
+
+
+def test_ovo_ties_to_highest_class_is_caught(monkeypatch):
+    def wrong(decisions, K):
+        votes = np.zeros((decisions.shape[0], K), dtype=np.int64)
+        for p, (a, b) in enumerate(osp.ovo_pairs(K)):
+            pos = decisions[:, p] > 0
+            votes[pos, a] += 1
+            votes[~pos, b] += 1
+        return K - 1 - np.argmax(votes[:, ::-1], axis=1)
+
+    monkeypatch.setattr(osp, "ovo_vote", wrong)
+    assert pins.ovo_vote_mismatches() > 0
+
+
+def test_ovo_zero_decision_voting_for_first_class_is_caught(monkeypatch):
+    def wrong(decisions, K):
+        votes = np.zeros((decisions.shape[0], K), dtype=np.int64)
+        for p, (a, b) in enumerate(osp.ovo_pairs(K)):
+            pos = decisions[:, p] >= 0
+            votes[pos, a] += 1
+            votes[~pos, b] += 1
+        return np.argmax(votes, axis=1)
+
+    monkeypatch.setattr(osp, "ovo_vote", wrong)
+    assert pins.ovo_vote_mismatches() > 0

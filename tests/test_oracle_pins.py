@@ -649,3 +649,42 @@ def stop_rule_mismatches():
 
 def test_stopping_rule_on_recorded_traces():
     assert stop_rule_mismatches() == 0
+
+
+# ---------------------------------------------------------------------------------- one-vs-one multiclass
+def ovo_vote_mismatches():
+    bad = 0
+    for ln in _golden_lines("ovo_votes.txt"):
+        K, dec, want = [p.strip() for p in ln.split(";")]
+        d = np.array([[float(v) for v in dec.split(",")]])
+        bad += int(osp.ovo_vote(d, int(K))[0] != int(want))
+    return bad
+
+
+def test_ovo_voting_matches_hand_worked_cases():
+    assert ovo_vote_mismatches() == 0
+
+
+def ovo_subset_mismatches():
+    """Each pairwise classifier is greedy training on exactly the rows of its two classes (extracted here row by row,
+    labels +1 for the first class): same basis (as rows of X) and coefficients; with two classes the one pair is
+    the binary problem itself."""
+    import datagen
+
+    X, cls = datagen.make_mnist_like(per_class=40, d=6, seed=11, classes=4)
+    X = X.astype(np.float64)
+    bad = 0
+    models = osp.train_ovo(X, cls, 4, 2.0, 0.5, 12, seed=1, kappa=10)
+    for (res, rows), (a, b) in zip(models, osp.ovo_pairs(4)):
+        sub = [i for i in range(X.shape[0]) if cls[i] in (a, b)]
+        ys = np.array([1.0 if cls[i] == a else -1.0 for i in sub])
+        ref = osp.train(X[sub], ys, 2.0, 0.5, 12, seed=1, kappa=10)
+        bad += int(list(rows) != sub or ref.J.tolist() != res.J.tolist() or not np.array_equal(ref.beta, res.beta))
+    two = osp.train_ovo(X, np.minimum(cls, 1), 2, 2.0, 0.5, 12, seed=1, kappa=10)
+    ref = osp.train(X, np.where(np.minimum(cls, 1) == 0, 1.0, -1.0), 2.0, 0.5, 12, seed=1, kappa=10)
+    bad += int(two[0][0].J.tolist() != ref.J.tolist())
+    return bad
+
+
+def test_ovo_pairs_train_on_their_rows():
+    assert ovo_subset_mismatches() == 0
