@@ -40,6 +40,15 @@ spsvm_status spsvm_newton_solve_workspace_bytes(int64_t m, size_t* bytes);
 spsvm_status spsvm_newton_solve(double* H, int64_t ldh, int64_t m, const double* g, double* x, void* workspace,
                                 size_t ws_bytes, void* stream);
 
+/* spsvm_newton_solve without a workspace, for callers that cannot allocate device memory (work captured in a
+ * HIP graph around the call, tight serving loops, harnesses that forbid hipMalloc). Same arguments, kernels and
+ * results as spsvm_newton_solve, for 1 <= m <= 4096; larger m is rejected with SPSVM_E_INVALID_ARG before any GPU
+ * work. Its scratch (the inverted diagonal blocks of L, a work vector, a status flag; 2.1 MiB) is a static device
+ * array that each GPU the library runs on holds until the process ends; no device memory is allocated or freed.
+ * Every call on one GPU uses that GPU's array, so calls that overlap on one GPU (other threads, other streams)
+ * race; the call synchronises its stream before it returns. */
+spsvm_status spsvm_newton_solve_noalloc(double* H, int64_t ldh, int64_t m, const double* g, double* x, void* stream);
+
 /* Candidate rows of addition step t (0-based over the whole run) when no row is blocked: SplitMix64
  * (Steele, Lea and Flood 2014) from state seed ^ ((t + 1) * 0x9E3779B97F4A7C15), index = high 32 bits of
  * each output times n, shifted right by 32; repeats are skipped; at most 64 * kappa draws.

@@ -14,6 +14,7 @@ from .binding import (  # noqa: F401
     train_batch,
     rbf_block,
     newton_solve,
+    newton_solve_noalloc,
     candidate_draw,
     score_candidates,
     workspace_bytes,

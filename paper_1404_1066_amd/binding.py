@@ -41,6 +41,7 @@ EXPORTED = (
     "spsvm_newton_solve",
     "spsvm_candidate_draw",
     "spsvm_score_candidates",
+    "spsvm_newton_solve_noalloc",
     "spsvm_score_workspace_bytes",
 )
 
@@ -148,10 +149,11 @@ def load(path: str = LIB_PATH):
     lib.spsvm_newton_solve.argtypes = [VP, I64, I64, VP, VP, VP, ctypes.c_size_t, VP]
     lib.spsvm_candidate_draw.argtypes = [ctypes.c_uint64, I64, I64, ctypes.c_int32, P(ctypes.c_int32)]
     lib.spsvm_score_workspace_bytes.argtypes = [I64, P(ctypes.c_size_t)]
+    lib.spsvm_newton_solve_noalloc.argtypes = [VP, I64, I64, VP, VP, VP]
     I32 = ctypes.c_int32
     lib.spsvm_score_candidates.argtypes = [VP, VP, I64, VP, ctypes.c_int, I64, P(D), I32, D, P(D), P(D), P(I32),
                                            P(I32), P(I32), VP, ctypes.c_size_t, VP]
-    for name in ("spsvm_score_candidates", "spsvm_score_workspace_bytes", "spsvm_candidate_draw", "spsvm_rbf_block", "spsvm_rbf_block_workspace_bytes", "spsvm_newton_solve_workspace_bytes", "spsvm_newton_solve",
+    for name in ("spsvm_newton_solve_noalloc", "spsvm_score_candidates", "spsvm_score_workspace_bytes", "spsvm_candidate_draw", "spsvm_rbf_block", "spsvm_rbf_block_workspace_bytes", "spsvm_newton_solve_workspace_bytes", "spsvm_newton_solve",
                  "spsvm_train_workspace_bytes", "spsvm_fixed_workspace_bytes", "spsvm_train",
                  "spsvm_train_fixed_basis", "spsvm_batch_workspace_bytes", "spsvm_train_batch", "spsvm_model_get", "spsvm_model_stats", "spsvm_model_bias", "spsvm_predict"):
         getattr(lib, name).restype = ctypes.c_int
@@ -386,6 +388,20 @@ def score_candidates(o: torch.Tensor, y: torch.Tensor, Kc: torch.Tensor, oc, C: 
                                          ps_out.ctypes.data_as(P(I32)), ctypes.byref(win),
                                          ctypes.c_void_p(ws.data_ptr()), b.value, ctypes.c_void_p(_stream_ptr(stream))))
     return {"s": s_out, "score": sc_out, "status": st_out, "passes": ps_out, "winner": int(win.value)}
+
+
+def newton_solve_noalloc(H: torch.Tensor, g: torch.Tensor, stream=None):
+    """newton_solve without a workspace (spsvm_newton_solve_noalloc; m <= 4096, scratch in a static device array)."""
+    _need_gpu(H, "H")
+    _need_gpu(g, "g")
+    if H.dtype != torch.float64 or g.dtype != torch.float64:
+        raise TypeError("H and g must be float64")
+    m = H.shape[0]
+    x = torch.empty(m, dtype=torch.float64, device=H.device)
+    _check(load().spsvm_newton_solve_noalloc(ctypes.c_void_p(H.data_ptr()), H.stride(0), m,
+                                             ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                             ctypes.c_void_p(_stream_ptr(stream))))
+    return x
 
 
 def candidate_draw(seed: int, t: int, n: int, kappa: int = 59):

@@ -428,6 +428,19 @@ spsvm_status spsvm_score_candidates(const double* o, const float* y, int64_t n, 
   });
 }
 
+spsvm_status spsvm_newton_solve_noalloc(double* H, int64_t ldh, int64_t m, const double* g, double* x, void* stream) {
+  return guarded([&] {
+    using spsvm::Failure;
+    if (!H || !g || !x) throw Failure(SPSVM_E_INVALID_ARG, "H, g and x must be device pointers");
+    if (m < 1 || m > spsvm::newton_solve_noalloc_max())
+      throw Failure(SPSVM_E_INVALID_ARG, "m = " + std::to_string(m) + " is outside [1, " +
+                                             std::to_string(spsvm::newton_solve_noalloc_max()) +
+                                             "] (the static scratch of the allocation-free solve)");
+    if (ldh < m) throw Failure(SPSVM_E_INVALID_ARG, "ldh must be >= m");
+    spsvm::newton_solve_noalloc(H, ldh, (int)m, g, x, as_stream(stream));
+  });
+}
+
 spsvm_status spsvm_candidate_draw(uint64_t seed, int64_t t, int64_t n, int32_t kappa, int32_t* out) {
   return guarded([&] {
     if (!out || n < 1 || n > 0x7fffffffLL || kappa < 1 || kappa > 64 || t < 0)

@@ -8,6 +8,9 @@
 //   2. the rows below are multiplied by the inverse transpose (independent 64-row blocks);
 //   3. the trailing lower triangle is updated, H_ij -= L_ik L_jk^T, one 64 x 64 tile per workgroup on FP64 MFMA.
 // A non-positive or non-finite pivot sets a failure flag; the host then retries with a diagonal jitter.
+#include <mutex>
+#include <string>
+
 #include "common.h"
 #include "launch.h"
 
@@ -590,6 +593,61 @@ void launch_chol_solve(const double* L, int64_t ldh, int m, const double* Linv, 
   b.work[0] = work;
   b.count = 1;
   launch_chol_solve_batch(b, ldh, m, s);
+}
+
+
+// ------------------------------------------------------------------------ allocation-free Newton solve
+// The scratch of one Newton solve (the inverses of L's 64 x 64 diagonal blocks, the forward-solve vector and the
+// status scalars) for systems up to kNoAllocMaxM, in a static device array: each GPU the library runs on holds its
+// own copy (2.1 MiB) until the process ends. Host code never uses the array's name as an address: the pointer
+// comes from hipGetSymbolAddress, once per device, with that device current. Calls that overlap on one GPU share
+// the array and race.
+constexpr int kNoAllocMaxM = 4096;
+constexpr size_t kNoAllocLinv = (size_t)(kNoAllocMaxM / kCholNB) * kCholNB * kCholNB * sizeof(double);
+constexpr size_t kNoAllocZ = (size_t)kNoAllocMaxM * sizeof(double);
+constexpr size_t kNoAllocBytes = kNoAllocLinv + kNoAllocZ + 256;
+static_assert(sizeof(NewtonScalars) <= 256, "status scalars fit the scratch tail");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_at[256];  // device address of `scratch` per device index
+
+static char* scratch_for_current_device() {
+  int dev = 0;
+  SPSVM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 256) throw Failure(3, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* ptr = nullptr;
+    SPSVM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw Failure(3, "hipGetSymbolAddress returned a null address for the scratch array");
+    g_scratch_at[dev] = ptr;
+  }
+  return (char*)g_scratch_at[dev];
+}
+
+__global__ void k_clear_fail(NewtonScalars* sc) {
+  if (threadIdx.x == 0) sc->fail = 0;
+}
+
+int newton_solve_noalloc_max() { return kNoAllocMaxM; }
+
+void newton_solve_noalloc(double* H, int64_t ldh, int m, const double* g, double* x, hipStream_t st) {
+  if (m < 1 || m > kNoAllocMaxM)
+    throw Failure(1, "m = " + std::to_string(m) + " is outside [1, " + std::to_string(kNoAllocMaxM) +
+                         "], the largest system the allocation-free solve's static scratch holds");
+  char* base = scratch_for_current_device();
+  double* Linv = (double*)base;
+  double* z = (double*)(base + kNoAllocLinv);
+  NewtonScalars* sc = (NewtonScalars*)(base + kNoAllocLinv + kNoAllocZ);
+  hipLaunchKernelGGL(k_clear_fail, dim3(1), dim3(64), 0, st, sc);  // the last call's flag stays in the array
+  SPSVM_LAUNCHED();
+  launch_cholesky(H, ldh, m, Linv, sc, st);
+  launch_chol_solve(H, ldh, m, Linv, g, x, z, st);
+  int32_t fl = 0;
+  SPSVM_HIP(hipMemcpyAsync(&fl, &sc->fail, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  SPSVM_HIP(hipStreamSynchronize(st));
+  if (fl) throw Failure(4, "Cholesky met a non-positive or non-finite pivot");
 }
 
 }  // namespace spsvm

@@ -325,5 +325,9 @@ struct SolveBatch {
   int count;
 };
 void launch_chol_solve_batch(const SolveBatch& b, int64_t ldh, int m, hipStream_t s);
+// Cholesky and x = -H^{-1} g (as launch_cholesky + launch_chol_solve) with the scratch in a static device array
+// (no device allocation); m <= newton_solve_noalloc_max(). Throws on a non-positive pivot; synchronises the stream.
+int newton_solve_noalloc_max();
+void newton_solve_noalloc(double* H, int64_t ldh, int m, const double* g, double* x, hipStream_t st);
 
 }  // namespace spsvm
