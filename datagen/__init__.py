@@ -24,5 +24,7 @@ from .configs import (  # noqa: F401
     make_mixed_onehot,
     make_mnist_like,
     make_large_dense,
+    make_sparse_rows,
+    csr_to_dense,
     config_names,
 )

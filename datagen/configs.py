@@ -201,6 +201,57 @@ def make_large_dense(n: int = 2000000, d: int = 2000, seed: int = 4, waves: int 
     return X, y
 
 
+def make_sparse_rows(n: int = 200000, d: int = 127, seed: int = 5, mean_nnz: float = 12.0, zipf: float = 1.1,
+                     centres: int = 100, teacher_gamma: float = 0.2, flip: float = 0.05):
+    """Sparse rows shaped like KDDCup99 (about 10% of 127 features set): each row sets 1 + Poisson(mean_nnz - 1)
+    distinct features (at most d, some rows empty of all but one), picked with weight r_j^-zipf (r a random
+    permutation of 1..d) by Gumbel top-k; a random half of the features are one-hot style (value 1) and the rest
+    log-normal counts (exp(N(0, 1)), FP32). Labels: sign of a sum of Gaussian bumps around ``centres`` rows of the same
+    kind, thresholded at its median, then exactly floor(flip * n) flipped. Returns CSR arrays (indptr int64, indices
+    int32 increasing within a row, values float32) and the labels."""
+    (gp, gl), blk = _streams(seed, n)
+    logw = -zipf * np.log(gp.permutation(d) + 1.0)
+    binary = gp.random(d) < 0.5
+
+    def rows(rng, m):
+        k = np.minimum(d, 1 + rng.poisson(mean_nnz - 1.0, size=m))
+        keys = logw[None, :] + rng.gumbel(size=(m, d))
+        order = np.argsort(-keys, axis=1)
+        dense = np.zeros((m, d), dtype=np.float32)
+        for i in range(m):
+            cols = order[i, :k[i]]
+            dense[i, cols] = np.where(binary[cols], 1.0, np.exp(rng.standard_normal(k[i]))).astype(np.float32)
+        return dense
+
+    cen = rows(gp, centres).astype(np.float64)
+    amp = gp.standard_normal(centres)
+    cn = (cen * cen).sum(1)
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    idx_parts, val_parts = [], []
+    s = np.empty(n)
+    for b, lo, hi in _blocks(n):
+        xb = rows(blk[b], hi - lo)
+        x64 = xb.astype(np.float64)
+        sq = (x64 * x64).sum(1)[:, None] + cn[None, :] - 2.0 * (x64 @ cen.T)
+        s[lo:hi] = np.exp(-teacher_gamma * np.maximum(sq, 0.0)) @ amp
+        r, c = np.nonzero(xb)
+        idx_parts.append(c.astype(np.int32))
+        val_parts.append(xb[r, c])
+        indptr[lo + 1:hi + 1] = indptr[lo] + np.cumsum(np.bincount(r, minlength=hi - lo))
+    y = np.where(s - np.median(s) >= 0, 1.0, -1.0)
+    y = _flip_exact(gl, y, int(np.floor(flip * n)))
+    return indptr, np.concatenate(idx_parts), np.concatenate(val_parts), y
+
+
+def csr_to_dense(indptr, indices, values, d: int) -> np.ndarray:
+    """The dense n x d FP64 matrix of CSR rows."""
+    n = indptr.shape[0] - 1
+    X = np.zeros((n, d))
+    rows = np.repeat(np.arange(n), np.diff(indptr))
+    X[rows, indices] = values
+    return X
+
+
 # ----------------------------------------------------------------------------------------------
 _NAMES = ("blobs-2k", "binary-100k", "onehot-500k", "mnist-60k", "dense-2m")
 

@@ -189,6 +189,58 @@ spsvm_status spsvm_train_batch(const void* X, spsvm_dtype xdt, int64_t n, int64_
                                const spsvm_options* opt, void* workspace, size_t ws_bytes, void* stream,
                                spsvm_model** out);
 
+/* Feature matrices as compressed sparse rows (CSR), for data whose dense form is mostly zeros (section 5: the dense
+ * GPU implementation could not hold KDDCup99): row i holds the FP32 values values[indptr[i] .. indptr[i + 1]) at
+ * the features indices[...], which must lie in [0, d) and increase strictly within the row. indptr: device, n + 1
+ * int64 (indptr[0] = 0); indices: device, int32; values: device, FP32, finite. Training runs in SPSVM_F32: the
+ * candidate rows are made dense, and each row's nonzeros meet them in FP32 products; the model keeps dense
+ * copies of its basis rows, so spsvm_predict (dense rows) and spsvm_predict_csr both apply. */
+
+/* Bytes of device workspace spsvm_train_csr needs (n rows, d features, up to J_max basis vectors). */
+spsvm_status spsvm_train_csr_workspace_bytes(int64_t n, int64_t d, int64_t J_max, const spsvm_options* opt,
+                                             size_t* bytes);
+
+/* Greedy SP-SVM training on CSR rows; as spsvm_train otherwise (opt->precision must be SPSVM_F32; the offset and
+ * the stopping rule apply). Rows are duplicates when their nonzero values and features agree. */
+spsvm_status spsvm_train_csr(const int64_t* indptr, const int32_t* indices, const float* values, int64_t n,
+                             int64_t d, const float* y, double C, double gamma, int64_t J_max,
+                             const spsvm_options* opt, void* workspace, size_t ws_bytes, void* stream,
+                             spsvm_model** out);
+
+/* Decision values of CSR rows (d as in training): out[i] = sum_k beta_k exp(-gamma ||x_i - x_{J_k}||^2) + b, FP32
+ * kernel values and FP64 sums, for a model with FP32 kernel values. out: device, n_t doubles. Allocates n_t floats of
+ * row norms for the call. */
+spsvm_status spsvm_predict_csr(const spsvm_model* model, const int64_t* indptr, const int32_t* indices,
+                               const float* values, int64_t n_t, double* out, void* stream);
+
+/* Bytes of device workspace spsvm_train_ovo needs when the largest class pair has pair_rows rows (the count of
+ * class a plus the count of class b, largest over the pairs): that pair's gathered rows, labels and row indices,
+ * and the training workspace of pair_rows rows (as spsvm_train_workspace_bytes). */
+spsvm_status spsvm_ovo_workspace_bytes(int64_t pair_rows, int64_t d, int64_t J_max, spsvm_dtype xdt,
+                                       const spsvm_options* opt, size_t* bytes);
+
+/* One-vs-one multiclass training, as section 5 trains MNIST8M: one greedy SP-SVM per pair of classes (a, b), a < b,
+ * in the order (0, 1), (0, 2), ..., (K - 2, K - 1), each on the rows of classes a (label +1) and b (label -1) only,
+ * in their order in X, with C, gamma, J_max and the options shared (the candidate draws of every pair use
+ * opt->seed). The pairs run one after another, each on the whole GPU; a pair's rows are gathered into the
+ * workspace first.
+ *  classes: device, n int32 class ids in [0, K); K >= 2; every class must have rows.
+ *  J_max: per pair; a pair with fewer rows trains to its row count (fewer distinct rows: SPSVM_E_INVALID_ARG).
+ *  out: host array of K (K - 1) / 2 model pointers; model J indices are rows of X. On failure all are NULL.
+ * Other arguments as for spsvm_train. */
+spsvm_status spsvm_train_ovo(const void* X, spsvm_dtype xdt, const int32_t* classes, int64_t n, int64_t d, int32_t K,
+                             double C, double gamma, int64_t J_max, const spsvm_options* opt, void* workspace,
+                             size_t ws_bytes, void* stream, spsvm_model** out);
+
+/* Bytes of device workspace spsvm_predict_ovo needs for n_t rows and K classes. */
+spsvm_status spsvm_predict_ovo_workspace_bytes(int64_t n_t, int32_t K, size_t* bytes);
+
+/* One-vs-one prediction: each pair model of spsvm_train_ovo (same order) votes for a when its decision value is
+ * positive and for b otherwise; classes[i] is the class with the most votes, the lowest class on ties.
+ *  models: host array of K (K - 1) / 2 models. Xt: device, n_t x d. classes: device, n_t int32. */
+spsvm_status spsvm_predict_ovo(const spsvm_model* const* models, int32_t K, const void* Xt, spsvm_dtype xdt,
+                               int64_t n_t, int32_t* classes, void* workspace, size_t ws_bytes, void* stream);
+
 /* Reads a model. Any output pointer may be NULL.
  *  m: number of basis vectors. J_idx: host, capacity >= m, receives the training-row indices of J in
  *  the order they were added. beta: host, capacity >= m. objective: F(beta) of Eq. 4 (paper scale),

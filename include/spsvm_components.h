@@ -18,11 +18,13 @@ extern "C" {
  * with squared distances |x_i|^2 + |x_j|^2 - 2 x_i . x_j clamped at 0, dot products on MFMA.
  *  X: device n x d (xdt). idx: device, ncols int32 row indices in [0, n) (a negative index leaves that
  *  column untouched). precision: SPSVM_F64 (out is double), SPSVM_F32 (out is float, FP32 products) or
- *  SPSVM_MIXED (out is float, split-BF16 products hi.hi' + hi.lo' + lo.hi' accumulated in FP32).
+ *  SPSVM_MIXED (out is float, split-BF16 products hi.hi' + hi.lo' + lo.hi' accumulated in FP32; when every
+ *  value of X is a BF16 number the lo parts are zero and the single-pass products hi.hi' give the same values).
  *  out: device, n rows of leading dimension ldo >= ncols. workspace: device, 256-byte aligned, at least
  *  spsvm_rbf_block_workspace_bytes(n, d, xdt) bytes (row norms, a padded copy of X when d is not a
  *  multiple of 4 for FP32 / 2 for FP64 or X is not 16-byte aligned, and for SPSVM_MIXED the BF16 hi and lo
- *  copies of X, d rounded up to 32 per row). */
+ *  copies of X, d rounded up to 32 per row, and a flag word). The call returns after the stream has
+ *  finished the block. */
 spsvm_status spsvm_rbf_block(const void* X, spsvm_dtype xdt, int64_t n, int64_t d, const int32_t* idx, int64_t ncols,
                              spsvm_precision precision, double gamma, void* out, int64_t ldo, void* workspace,
                              size_t ws_bytes, void* stream);

@@ -12,6 +12,10 @@ from .binding import (  # noqa: F401
     train,
     train_fixed_basis,
     train_batch,
+    train_ovo,
+    train_csr,
+    predict_csr,
+    predict_ovo,
     rbf_block,
     newton_solve,
     newton_solve_noalloc,

@@ -31,6 +31,13 @@ EXPORTED = (
     "spsvm_model_get",
     "spsvm_model_stats",
     "spsvm_model_bias",
+    "spsvm_train_csr_workspace_bytes",
+    "spsvm_train_csr",
+    "spsvm_predict_csr",
+    "spsvm_ovo_workspace_bytes",
+    "spsvm_train_ovo",
+    "spsvm_predict_ovo_workspace_bytes",
+    "spsvm_predict_ovo",
     "spsvm_predict",
     "spsvm_model_free",
     "spsvm_status_string",
@@ -136,6 +143,14 @@ def load(path: str = LIB_PATH):
     lib.spsvm_model_get.argtypes = [VP, P(I64), P(I64), P(D), P(D)]
     lib.spsvm_model_stats.argtypes = [VP, P(Stats)]
     lib.spsvm_model_bias.argtypes = [VP, P(D)]
+    lib.spsvm_train_csr_workspace_bytes.argtypes = [I64, I64, I64, P(Options), P(ctypes.c_size_t)]
+    lib.spsvm_train_csr.argtypes = [VP, VP, VP, I64, I64, VP, D, D, I64, P(Options), VP, ctypes.c_size_t, VP, P(VP)]
+    lib.spsvm_predict_csr.argtypes = [VP, VP, VP, VP, I64, VP, VP]
+    lib.spsvm_ovo_workspace_bytes.argtypes = [I64, I64, I64, ctypes.c_int, P(Options), P(ctypes.c_size_t)]
+    lib.spsvm_train_ovo.argtypes = [VP, ctypes.c_int, VP, I64, I64, ctypes.c_int32, D, D, I64, P(Options), VP,
+                                    ctypes.c_size_t, VP, P(VP)]
+    lib.spsvm_predict_ovo_workspace_bytes.argtypes = [I64, ctypes.c_int32, P(ctypes.c_size_t)]
+    lib.spsvm_predict_ovo.argtypes = [P(VP), ctypes.c_int32, VP, ctypes.c_int, I64, VP, VP, ctypes.c_size_t, VP]
     lib.spsvm_predict.argtypes = [VP, VP, ctypes.c_int, I64, VP, VP]
     lib.spsvm_model_free.argtypes = [VP]
     lib.spsvm_model_free.restype = None
@@ -153,7 +168,8 @@ def load(path: str = LIB_PATH):
     I32 = ctypes.c_int32
     lib.spsvm_score_candidates.argtypes = [VP, VP, I64, VP, ctypes.c_int, I64, P(D), I32, D, P(D), P(D), P(I32),
                                            P(I32), P(I32), VP, ctypes.c_size_t, VP]
-    for name in ("spsvm_newton_solve_noalloc", "spsvm_score_candidates", "spsvm_score_workspace_bytes", "spsvm_candidate_draw", "spsvm_rbf_block", "spsvm_rbf_block_workspace_bytes", "spsvm_newton_solve_workspace_bytes", "spsvm_newton_solve",
+    for name in ("spsvm_train_csr_workspace_bytes", "spsvm_train_csr", "spsvm_predict_csr", "spsvm_ovo_workspace_bytes", "spsvm_train_ovo", "spsvm_predict_ovo_workspace_bytes",
+                 "spsvm_predict_ovo", "spsvm_newton_solve_noalloc", "spsvm_score_candidates", "spsvm_score_workspace_bytes", "spsvm_candidate_draw", "spsvm_rbf_block", "spsvm_rbf_block_workspace_bytes", "spsvm_newton_solve_workspace_bytes", "spsvm_newton_solve",
                  "spsvm_train_workspace_bytes", "spsvm_fixed_workspace_bytes", "spsvm_train",
                  "spsvm_train_fixed_basis", "spsvm_batch_workspace_bytes", "spsvm_train_batch", "spsvm_model_get", "spsvm_model_stats", "spsvm_model_bias", "spsvm_predict"):
         getattr(lib, name).restype = ctypes.c_int
@@ -409,6 +425,84 @@ def candidate_draw(seed: int, t: int, n: int, kappa: int = 59):
     out = (ctypes.c_int32 * 64)()
     _check(load().spsvm_candidate_draw(seed, t, n, kappa, out))
     return [v for v in out if v >= 0]
+
+
+def _csr_parts(indptr, indices, values):
+    for t, name in ((indptr, "indptr"), (indices, "indices"), (values, "values")):
+        _need_gpu(t, name)
+    if indptr.dtype != torch.int64 or indices.dtype != torch.int32 or values.dtype != torch.float32:
+        raise TypeError("CSR arrays: indptr int64, indices int32, values float32")
+    return ctypes.c_void_p(indptr.data_ptr()), ctypes.c_void_p(indices.data_ptr()), ctypes.c_void_p(values.data_ptr())
+
+
+def train_csr(indptr: torch.Tensor, indices: torch.Tensor, values: torch.Tensor, d: int, y: torch.Tensor, C: float,
+              gamma: float, J_max: int, workspace=None, stream=None, **opts) -> Model:
+    """Greedy SP-SVM training on CSR rows (spsvm_train_csr; FP32)."""
+    _need_gpu(y, "y")
+    if y.dtype != torch.float32:
+        raise TypeError("y must be float32")
+    n = indptr.numel() - 1
+    o = options(**opts)
+    b = ctypes.c_size_t()
+    _check(load().spsvm_train_csr_workspace_bytes(n, d, J_max, ctypes.byref(o), ctypes.byref(b)))
+    ws, nbytes = _workspace(b.value, y.device, workspace)
+    out = ctypes.c_void_p()
+    ip, ix, vv = _csr_parts(indptr, indices, values)
+    _check(load().spsvm_train_csr(ip, ix, vv, n, d, ctypes.c_void_p(y.data_ptr()), float(C), float(gamma), int(J_max),
+                                  ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), nbytes,
+                                  ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(out)))
+    return Model(out.value)
+
+
+def predict_csr(model: Model, indptr: torch.Tensor, indices: torch.Tensor, values: torch.Tensor, stream=None):
+    """Decision values (float64, on the GPU) of CSR rows (spsvm_predict_csr)."""
+    n_t = indptr.numel() - 1
+    out = torch.empty(n_t, dtype=torch.float64, device=indptr.device)
+    if n_t == 0:
+        return out
+    ip, ix, vv = _csr_parts(indptr, indices, values)
+    _check(load().spsvm_predict_csr(model._ptr, ip, ix, vv, n_t, ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.c_void_p(_stream_ptr(stream))))
+    return out
+
+
+def train_ovo(X: torch.Tensor, classes: torch.Tensor, K: int, C: float, gamma: float, J_max: int, workspace=None,
+              stream=None, **opts):
+    """One-vs-one multiclass training (spsvm_train_ovo): K (K - 1) / 2 models, pairs (0, 1), (0, 2), ..."""
+    _need_gpu(X, "X")
+    _need_gpu(classes, "classes")
+    if classes.dtype != torch.int32 or classes.numel() != X.shape[0]:
+        raise TypeError("classes must be an int32 tensor with one entry per row of X")
+    n, d = X.shape
+    counts = torch.bincount(classes.long(), minlength=K).cpu().tolist()
+    pair_rows = max(counts[a] + counts[b] for a in range(K) for b in range(a + 1, K))
+    o = options(**opts)
+    b = ctypes.c_size_t()
+    _check(load().spsvm_ovo_workspace_bytes(pair_rows, d, J_max, _dtype_code(X), ctypes.byref(o), ctypes.byref(b)))
+    ws, nbytes = _workspace(b.value, X.device, workspace)
+    P = K * (K - 1) // 2
+    outs = (ctypes.c_void_p * P)()
+    _check(load().spsvm_train_ovo(ctypes.c_void_p(X.data_ptr()), _dtype_code(X), ctypes.c_void_p(classes.data_ptr()),
+                                  n, d, K, float(C), float(gamma), int(J_max), ctypes.byref(o),
+                                  ctypes.c_void_p(ws.data_ptr()), nbytes, ctypes.c_void_p(_stream_ptr(stream)), outs))
+    return [Model(outs[p]) for p in range(P)]
+
+
+def predict_ovo(models, K: int, Xt: torch.Tensor, stream=None) -> torch.Tensor:
+    """Classes (int32, on the GPU) of the rows of Xt by one-vs-one voting (spsvm_predict_ovo)."""
+    _need_gpu(Xt, "Xt")
+    n_t = Xt.shape[0]
+    out = torch.empty(n_t, dtype=torch.int32, device=Xt.device)
+    if n_t == 0:
+        return out
+    b = ctypes.c_size_t()
+    _check(load().spsvm_predict_ovo_workspace_bytes(n_t, K, ctypes.byref(b)))
+    ws = torch.empty(b.value, dtype=torch.uint8, device=Xt.device)
+    arr = (ctypes.c_void_p * len(models))(*[m._ptr.value for m in models])
+    _check(load().spsvm_predict_ovo(arr, K, ctypes.c_void_p(Xt.data_ptr()), _dtype_code(Xt), n_t,
+                                    ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), b.value,
+                                    ctypes.c_void_p(_stream_ptr(stream))))
+    return out
 
 
 def train_batch(X: torch.Tensor, Y: torch.Tensor, C, gamma, J: Sequence[int], workspace=None, stream=None,

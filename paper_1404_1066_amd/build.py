@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspsvm.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
-SOURCES = ["kblock.hip", "select.hip", "newton.hip", "chol.hip", "trainer.cpp", "api.cpp"]
+SOURCES = ["kblock.hip", "select.hip", "newton.hip", "chol.hip", "multiclass.hip", "sparse.hip", "trainer.cpp", "api.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -167,6 +167,108 @@ spsvm_status spsvm_train_batch(const void* X, spsvm_dtype xdt, int64_t n, int64_
   });
 }
 
+spsvm_status spsvm_train_csr_workspace_bytes(int64_t n, int64_t d, int64_t J_max, const spsvm_options* opt,
+                                             size_t* bytes) {
+  return guarded([&] {
+    if (!bytes) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bytes must not be NULL");
+    if (n < 1 || d < 1 || J_max < 1 || J_max > n) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad sizes");
+    *bytes = spsvm::make_plan(n, d, J_max, resolve(opt), true, false, true, false, 1, true).bytes;
+  });
+}
+
+spsvm_status spsvm_train_csr(const int64_t* indptr, const int32_t* indices, const float* values, int64_t n,
+                             int64_t d, const float* y, double C, double gamma, int64_t J_max,
+                             const spsvm_options* opt, void* workspace, size_t ws_bytes, void* stream,
+                             spsvm_model** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    using spsvm::Failure;
+    if (!out) throw Failure(SPSVM_E_INVALID_ARG, "out must not be NULL");
+    if (!indptr || !indices || !values) throw Failure(SPSVM_E_INVALID_ARG, "indptr, indices and values must be device pointers");
+    const spsvm_options o = resolve(opt);
+    check_problem(values, SPSVM_DT_F32, y, n, d, C, gamma, J_max);
+    if (d > 0x7fffffffLL) throw Failure(SPSVM_E_INVALID_ARG, "d must fit int32 feature indices");
+    int64_t nnz = 0;
+    SPSVM_HIP(hipMemcpy(&nnz, indptr + n, sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (nnz < 0) throw Failure(SPSVM_E_INVALID_ARG, "indptr[n] must be >= 0");
+    spsvm::CsrX X;
+    X.indptr = indptr;
+    X.indices = indices;
+    X.values = values;
+    X.nnz = nnz;
+    *out = spsvm::run_train_csr(X, y, n, d, C, gamma, J_max, o, workspace, ws_bytes, as_stream(stream));
+  });
+}
+
+spsvm_status spsvm_predict_csr(const spsvm_model* md, const int64_t* indptr, const int32_t* indices,
+                               const float* values, int64_t n_t, double* out, void* stream) {
+  return guarded([&] {
+    using spsvm::Failure;
+    if (!md) throw Failure(SPSVM_E_INVALID_ARG, "model must not be NULL");
+    if (n_t < 0) throw Failure(SPSVM_E_INVALID_ARG, "n_t must be >= 0");
+    if (n_t == 0) return;
+    if (!indptr || !indices || !values || !out) throw Failure(SPSVM_E_INVALID_ARG, "CSR arrays and out must be device pointers");
+    spsvm::CsrX X;
+    X.indptr = indptr;
+    X.indices = indices;
+    X.values = values;
+    spsvm::run_predict_csr(md, X, n_t, out, as_stream(stream));
+  });
+}
+
+spsvm_status spsvm_ovo_workspace_bytes(int64_t pair_rows, int64_t d, int64_t J_max, spsvm_dtype xdt,
+                                       const spsvm_options* opt, size_t* bytes) {
+  return guarded([&] {
+    if (!bytes) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bytes must not be NULL");
+    if (pair_rows < 2 || d < 1 || J_max < 1) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad sizes");
+    if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
+    *bytes = spsvm::ovo_workspace_bytes(pair_rows, d, std::min(J_max, pair_rows), resolve(opt), xdt == SPSVM_DT_F64);
+  });
+}
+
+spsvm_status spsvm_train_ovo(const void* X, spsvm_dtype xdt, const int32_t* classes, int64_t n, int64_t d, int32_t K,
+                             double C, double gamma, int64_t J_max, const spsvm_options* opt, void* workspace,
+                             size_t ws_bytes, void* stream, spsvm_model** out) {
+  if (out && K >= 2 && K <= 4096)
+    for (int64_t p = 0; p < (int64_t)K * (K - 1) / 2; ++p) out[p] = nullptr;
+  return guarded([&] {
+    using spsvm::Failure;
+    if (!out) throw Failure(SPSVM_E_INVALID_ARG, "out must be a host array");
+    if (!classes) throw Failure(SPSVM_E_INVALID_ARG, "classes must be a device pointer");
+    if (K < 2 || K > 4096) throw Failure(SPSVM_E_INVALID_ARG, "K must lie in [2, 4096]");
+    const spsvm_options o = resolve(opt);
+    if (!X) throw Failure(SPSVM_E_INVALID_ARG, "X must be a device pointer");
+    if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
+    if (n < 2 || n > 0x7fffffffLL) throw Failure(SPSVM_E_INVALID_ARG, "n must lie in [2, 2^31 - 1]");
+    if (d < 1) throw Failure(SPSVM_E_INVALID_ARG, "d must be >= 1");
+    if (!(C > 0.0) || !std::isfinite(C)) throw Failure(SPSVM_E_INVALID_ARG, "C must be finite and > 0");
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) throw Failure(SPSVM_E_INVALID_ARG, "gamma must be finite and > 0");
+    if (J_max < 1 || J_max > 65536) throw Failure(SPSVM_E_INVALID_ARG, "J_max must lie in [1, 65536]");
+    spsvm::run_train_ovo(X, xdt == SPSVM_DT_F64, classes, n, d, K, C, gamma, J_max, o, workspace, ws_bytes,
+                         as_stream(stream), out);
+  });
+}
+
+spsvm_status spsvm_predict_ovo_workspace_bytes(int64_t n_t, int32_t K, size_t* bytes) {
+  return guarded([&] {
+    if (!bytes || n_t < 0 || K < 2) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad arguments");
+    *bytes = spsvm::ovo_predict_workspace_bytes(n_t, K);
+  });
+}
+
+spsvm_status spsvm_predict_ovo(const spsvm_model* const* models, int32_t K, const void* Xt, spsvm_dtype xdt,
+                               int64_t n_t, int32_t* classes, void* workspace, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    using spsvm::Failure;
+    if (!models || K < 2 || K > 4096) throw Failure(SPSVM_E_INVALID_ARG, "models must hold K (K - 1) / 2 models, K >= 2");
+    if (n_t < 0) throw Failure(SPSVM_E_INVALID_ARG, "n_t must be >= 0");
+    if (n_t == 0) return;
+    if (!Xt || !classes) throw Failure(SPSVM_E_INVALID_ARG, "Xt and classes must be device pointers");
+    if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
+    spsvm::run_predict_ovo(models, K, Xt, xdt == SPSVM_DT_F64, n_t, classes, workspace, ws_bytes, as_stream(stream));
+  });
+}
+
 spsvm_status spsvm_model_get(const spsvm_model* md, int64_t* m, int64_t* J_idx, double* beta, double* objective) {
   return guarded([&] {
     if (!md) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "model must not be NULL");
@@ -233,7 +335,7 @@ extern "C" {
 static size_t rbf_ws(int64_t n, int64_t d, bool xd) {
   const int64_t xe = xd ? 8 : 4, ld = spsvm::round_up(d, 16 / xe);
   const size_t split = (size_t)spsvm::round_up(n * spsvm::split_ld(d) * 2, 256);  // one BF16 copy
-  return (size_t)spsvm::round_up(n * 8, 256) + (size_t)spsvm::round_up(n * ld * xe, 256) + 2 * split;
+  return (size_t)spsvm::round_up(n * 8, 256) + (size_t)spsvm::round_up(n * ld * xe, 256) + 2 * split + 256;
 }
 
 template <typename TX, typename TK>
@@ -254,6 +356,14 @@ static void rbf_typed(const TX* X, int64_t n, int64_t d, const int32_t* idx, int
       unsigned short* hi = (unsigned short*)(ws + spsvm::round_up(n * 8, 256) +
                                              spsvm::round_up(n * spsvm::padded_ld<TX>(d) * (int64_t)sizeof(TX), 256));
       unsigned short* lo = hi + spsvm::round_up(n * ldb * 2, 256) / 2;
+      // rows whose values are all BF16 numbers have zero lo parts: single-pass products give the same values
+      int32_t* flags = (int32_t*)(lo + spsvm::round_up(n * ldb * 2, 256) / 2);
+      SPSVM_HIP(hipMemsetAsync(flags, 0, 16, st));
+      spsvm::launch_check_inputs<TX>(X, n * d, nullptr, n, flags, st);
+      int32_t f[4];
+      SPSVM_HIP(hipMemcpyAsync(f, flags, 16, hipMemcpyDeviceToHost, st));
+      SPSVM_HIP(hipStreamSynchronize(st));
+      if (f[2] == 0) lo = nullptr;
       spsvm::launch_split_bf16<TX>(X, n, d, d, hi, lo, ldb, st);
       spsvm::launch_kblock_bf16(hi, lo, ldb, n, nrm, idx, (int)ncols, out, ldo, gamma, st);
       return;

@@ -4,6 +4,11 @@
 // K(X, X_J) and the candidate columns of section 4, "Sparse primal optimization"). A predict variant
 // multiplies by beta and reduces over the basis in the epilogue, so the n_t x m block is never stored.
 #include <type_traits>
+#include <cstdlib>
+#include <string>
+#include <mutex>
+#include <map>
+#include <fstream>
 
 #include "common.h"
 #include "launch.h"
@@ -741,7 +746,9 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
 // Split-BF16 block in 256 x 256 tiles for blocks with many columns (grouped candidate steps, a whole basis):
 // 8 waves in a 4 x 2 grid, each 64 rows x 128 columns (4 x 8 MFMA tiles). Every A fragment read from LDS feeds
 // 8 tiles and every B fragment 4, and each staged byte feeds twice the products of a 256 x 64 tile; two waves
-// share each SIMD. Two LDS stages of one k chunk each: chunk t is multiplied from one stage while chunk t + 1 goes
+// share each SIMD. With WGC = 1 the tile is 256 x 128 (4 waves, one wave column, 68 KiB of LDS with single-pass
+// products), so two workgroups share each CU and one can multiply while the other waits at a barrier or writes
+// its epilogue. Two LDS stages of one k chunk each: chunk t is multiplied from one stage while chunk t + 1 goes
 // from registers into the other and chunk t + 2 is loaded from memory into registers, so each chunk costs one
 // barrier and a load has a whole chunk of products to arrive in. The chunk is BK = 32 wide with the split
 // correction (three products per pair of fragments) and 64 wide for single-pass products, whose chunk of 32 would
@@ -751,27 +758,28 @@ __global__ __launch_bounds__(256, RTW == 4 ? 2 : 3) void k_kblock_bf16(const uns
 // at position p ^ ((r >> 1) & 3) in 64-byte rows (BK = 32) and p ^ (r & 7) in 128-byte rows (BK = 64), which
 // makes both the staging writes and the fragment reads (8 rows at one part) conflict-free. Within a 32-wide k step
 // the order of the three products and the epilogue are those of k_kblock_bf16, so both give the same bits.
-template <bool SPLIT, int BK>
-__global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* __restrict__ hi,
-                                                          const unsigned short* __restrict__ lo, int64_t ldb,
-                                                          int64_t n, const float* __restrict__ xnorm,
-                                                          const int32_t* __restrict__ cidx, int ncols,
-                                                          float* __restrict__ out, int64_t ldo, double gamma,
-                                                          const Score0 s0, int cm) {
-  constexpr int BM = 256, BN = 256;
+template <bool SPLIT, int BK, int WGC>
+__global__ __launch_bounds__(256 * WGC) __attribute__((amdgpu_waves_per_eu(2))) void k_kblock_bf16_wide(
+    const unsigned short* __restrict__ hi, const unsigned short* __restrict__ lo, int64_t ldb, int64_t n,
+    const float* __restrict__ xnorm, const int32_t* __restrict__ cidx, int ncols, float* __restrict__ out,
+    int64_t ldo, double gamma, const Score0 s0, int cm) {
+  constexpr int NT = 256 * WGC;               // 4 x WGC waves, each 64 rows x 128 columns
+  constexpr int BM = 256, BN = 128 * WGC;
   constexpr int PARTS = BK / 8;               // 16-byte parts per staged row
-  constexpr int NQ = BM * PARTS / 512;        // 16-byte vectors per thread per operand per chunk
-  // two stages of the operand chunks during the k loop; afterwards (column-major out) 128 columns of the tile
-  // at a time as [column][row]
-  typedef unsigned short Stage[BM][BK];
-  static_assert(BM == BN, "one stage type for both operands");
+  constexpr int NQA = BM * PARTS / NT, NQB = BN * PARTS / NT;  // 16-byte vectors per thread per chunk
+  constexpr int NC = NT / 4;                  // columns the epilogue stages through LDS at a time
+  // two stages of the operand chunks during the k loop; afterwards (column-major out) NC columns of the tile at a
+  // time as [column][row]
+  typedef unsigned short StageA[BM][BK];
+  typedef unsigned short StageB[BN][BK];
   static_assert(BK == 32 || BK == 64, "32- or 64-wide k chunks");
-  constexpr int kOps = (SPLIT ? 8 : 4) * (int)sizeof(Stage), kTr = 128 * (BM + 4) * 4;
+  static_assert(WGC == 1 || WGC == 2, "one or two wave columns");
+  constexpr int kOps = (SPLIT ? 4 : 2) * (int)(sizeof(StageA) + sizeof(StageB)), kTr = NC * (BM + 4) * 4;
   __shared__ __attribute__((aligned(16))) char smem[kOps > kTr ? kOps : kTr];
-  Stage* Ah = reinterpret_cast<Stage*>(smem);
-  Stage* Bh = Ah + 2;
-  Stage* Al = Ah + 4;  // SPLIT only
-  Stage* Bl = Ah + 6;  // SPLIT only
+  StageA* Ah = reinterpret_cast<StageA*>(smem);
+  StageB* Bh = reinterpret_cast<StageB*>(smem + 2 * sizeof(StageA));
+  StageA* Al = reinterpret_cast<StageA*>(smem + 2 * (sizeof(StageA) + sizeof(StageB)));  // SPLIT only
+  StageB* Bl = reinterpret_cast<StageB*>(smem + 4 * sizeof(StageA) + 2 * sizeof(StageB));  // SPLIT only
   auto phys = [](int row, int p) { return BK == 32 ? p ^ ((row >> 1) & 3) : p ^ (row & 7); };
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w & 3, wc = w >> 2, g = lane >> 4,
             i16 = lane & 15;
@@ -779,12 +787,15 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
   const int64_t r0 = tile.r * BM, c0 = tile.c * BN;
   if (r0 >= n) return;  // padding of the row-tile count to a multiple of 8
   const int part = tid % PARTS;  // which 8 of the chunk's BK values of k this thread stages
-  int64_t aoff[NQ], boff[NQ];
+  int64_t aoff[NQA], boff[NQB];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int rr = (tid + 512 * q) / PARTS;
-    const int64_t row = r0 + rr, col = c0 + rr;
+  for (int q = 0; q < NQA; ++q) {
+    const int64_t row = r0 + (tid + NT * q) / PARTS;
     aoff[q] = row < n ? row * ldb + 8 * part : -1;
+  }
+#pragma unroll
+  for (int q = 0; q < NQB; ++q) {
+    const int64_t col = c0 + (tid + NT * q) / PARTS;
     const int64_t src = col < ncols ? (cidx ? (int64_t)cidx[col] : col) : -1;
     boff[q] = src >= 0 ? src * ldb + 8 * part : -1;
   }
@@ -793,29 +804,32 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[i][j] = floatx4{0, 0, 0, 0};
-  u32x4 rah[NQ], ral[NQ], rbh[NQ], rbl[NQ];
+  u32x4 rah[NQA], ral[NQA], rbh[NQB], rbl[NQB];
   auto fetch = [&](int64_t k0) {
     const bool in = k0 + 8 * part < ldb;  // a last half chunk reads zeros past ldb
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < NQA; ++q) {
       rah[q] = in && aoff[q] >= 0 ? *(const u32x4*)(hi + aoff[q] + k0) : u32x4{0, 0, 0, 0};
+      if (SPLIT) ral[q] = in && aoff[q] >= 0 ? *(const u32x4*)(lo + aoff[q] + k0) : u32x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int q = 0; q < NQB; ++q) {
       rbh[q] = in && boff[q] >= 0 ? *(const u32x4*)(hi + boff[q] + k0) : u32x4{0, 0, 0, 0};
-      if (SPLIT) {
-        ral[q] = in && aoff[q] >= 0 ? *(const u32x4*)(lo + aoff[q] + k0) : u32x4{0, 0, 0, 0};
-        rbl[q] = in && boff[q] >= 0 ? *(const u32x4*)(lo + boff[q] + k0) : u32x4{0, 0, 0, 0};
-      }
+      if (SPLIT) rbl[q] = in && boff[q] >= 0 ? *(const u32x4*)(lo + boff[q] + k0) : u32x4{0, 0, 0, 0};
     }
   };
   auto store = [&](int b) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int rr = (tid + 512 * q) / PARTS, pp = 8 * phys(rr, part);
+    for (int q = 0; q < NQA; ++q) {
+      const int rr = (tid + NT * q) / PARTS, pp = 8 * phys(rr, part);
       *(u32x4*)&Ah[b][rr][pp] = rah[q];
+      if (SPLIT) *(u32x4*)&Al[b][rr][pp] = ral[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NQB; ++q) {
+      const int rr = (tid + NT * q) / PARTS, pp = 8 * phys(rr, part);
       *(u32x4*)&Bh[b][rr][pp] = rbh[q];
-      if (SPLIT) {
-        *(u32x4*)&Al[b][rr][pp] = ral[q];
-        *(u32x4*)&Bl[b][rr][pp] = rbl[q];
-      }
+      if (SPLIT) *(u32x4*)&Bl[b][rr][pp] = rbl[q];
     }
   };
   auto compute = [&](int b, int ksteps) {
@@ -917,21 +931,22 @@ __global__ __launch_bounds__(512) void k_kblock_bf16_wide(const unsigned short* 
       }
     }
   }
-  if (cm) {  // through LDS, 128 columns (one column half of the waves) at a time
+  if (cm) {  // through LDS, NC columns at a time (128: one wave column; 64: half of the single wave column)
     __shared__ double sga[BM];
     __shared__ float sgy[BM];
-    const ColStage<BM, 512> stage{reinterpret_cast<float(*)[BM + 4]>(smem), sga, sgy};
+    const ColStage<BM, NT> stage{reinterpret_cast<float(*)[BM + 4]>(smem), sga, sgy};
     if (fused) stage.rows(s0, r0, n);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      __syncthreads();  // h = 0: the operand stages are dead; h = 1: the first half has been read back
-      if (wc == h) {
+    for (int h = 0; h < BN / NC; ++h) {
+      __syncthreads();  // h = 0: the operand stages are dead; then: the previous columns have been read back
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 8; ++j) {
+        const int col = wc * 128 + j * 16;  // this fragment's first column in the tile
+        if (col >= h * NC && col < (h + 1) * NC)
 #pragma unroll
-          for (int j = 0; j < 8; ++j) stage.put(j * 16 + i16, wr * 64 + i * 16 + g * 4, acc[i][j]);
+          for (int i = 0; i < 4; ++i) stage.put(col - h * NC + i16, wr * 64 + i * 16 + g * 4, acc[i][j]);
       }
-      stage.flush(out, ldo, n, r0, c0 + 128 * h, ncols, cidx, s0, fused && h == 0, tile.r * (BM / kKblockRows),
+      stage.flush(out, ldo, n, r0, c0 + NC * h, ncols, cidx, s0, fused && h == 0, tile.r * (BM / kKblockRows),
                   ceil_div_dev(n, kKblockRows));
     }
   }
@@ -943,15 +958,136 @@ constexpr int64_t kWideRows = 65536;
 // 256 x 256 tiles from this many columns on (and enough tiles to fill the chip)
 constexpr int64_t kWideCols = 192;
 
-// MFMA flops a launch_kblock_bf16 call issues: whole tiles of the variant the launcher picks, k over ldb, three
-// products per multiply-add with the split correction (one without).
-double kblock_bf16_issued_flops(int64_t n, int64_t ldb, int64_t ncols, bool split) {
+// ---------------------------------------------------------------------- variants and their autotuner
+// The split-BF16 / single-pass block has five kernel variants, all of which give the same bits (the same k
+// chunks of 32 in the same order per output, the same epilogue arithmetic and fused records): 128 x 64 and
+// 256 x 64 tiles of k_kblock_bf16, the 256 x 256 tiles of k_kblock_bf16_wide with 32- or 64-wide k chunks in
+// LDS (the split instance always uses 32), and its 256 x 128 tiles (single pass only). Without tuning the choice
+// is fixed by the shape; with the environment variable SPSVM_AUTOTUNE=1 every variant is timed with HIP events on
+// the caller's stream the first time a shape class is met (one warm and two timed launches each, writing the same
+// output), and the fastest is kept. Shape classes: split or single pass, column-major or not, fused first pass or
+// not, n rounded up to a power of two, ldb, and the column count. With SPSVM_TUNE_CACHE=<file> the choices are
+// read from and appended to that JSON file. SPSVM_KBLOCK_VARIANT=<name> forces one variant wherever it applies
+// (for tests and measurements; it takes precedence over the cache and the timing).
+enum KbVariant { kVRows128 = 0, kVRows256 = 1, kVWide = 2, kVWideK32 = 3, kVWideHalf = 4 };
+constexpr int kVariants = 5;
+static const char* const kVariantName[] = {"rows128", "rows256", "wide", "wide_k32", "wide_half"};
+
+static int heuristic_variant(int64_t n, int64_t ldb, int64_t ncols) {
+  if (ncols >= kWideCols && ceil_div(n, 256) * ceil_div(ncols, 256) >= 256) return kVWide;
+  return n >= kWideRows && ldb >= 256 ? kVRows256 : kVRows128;  // short rows: 128-row tiles keep more waves resident
+}
+
+static void launch_variant(int v, const unsigned short* hi, const unsigned short* lo, int64_t ldb, int64_t n,
+                           const float* xnorm, const int32_t* cidx, int ncols, float* out, int64_t ldo, double gamma,
+                           hipStream_t st, const Score0& s0, int cm) {
+  if (v == kVWideHalf && !lo) {  // 256 x 128 tiles, 4 waves: two workgroups share a CU (single pass only: the
+                                 // split form's operand stages would not leave LDS for a second workgroup)
+    const dim3 grid(xcd_grid(ceil_div(n, 256), ceil_div(ncols, 128)));
+    hipLaunchKernelGGL((k_kblock_bf16_wide<false, 32, 1>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols,
+                       out, ldo, gamma, s0, cm);
+  } else if (v == kVWide || v == kVWideK32) {
+    const dim3 grid(xcd_grid(ceil_div(n, 256), ceil_div(ncols, 256)));
+    if (lo)
+      hipLaunchKernelGGL((k_kblock_bf16_wide<true, 32, 2>), grid, dim3(512), 0, st, hi, lo, ldb, n, xnorm, cidx,
+                         ncols, out, ldo, gamma, s0, cm);
+    else if (v == kVWide)
+      hipLaunchKernelGGL((k_kblock_bf16_wide<false, 64, 2>), grid, dim3(512), 0, st, hi, lo, ldb, n, xnorm, cidx,
+                         ncols, out, ldo, gamma, s0, cm);
+    else
+      hipLaunchKernelGGL((k_kblock_bf16_wide<false, 32, 2>), grid, dim3(512), 0, st, hi, lo, ldb, n, xnorm, cidx,
+                         ncols, out, ldo, gamma, s0, cm);
+  } else {
+    const bool rows256 = v == kVRows256;
+    const dim3 grid(xcd_grid(ceil_div(n, rows256 ? 256 : 128), ceil_div(ncols, KB_BN)));
+    if (rows256) {
+      if (lo)
+        hipLaunchKernelGGL((k_kblock_bf16<true, 4>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
+                           ldo, gamma, s0, cm);
+      else
+        hipLaunchKernelGGL((k_kblock_bf16<false, 4>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
+                           ldo, gamma, s0, cm);
+    } else {
+      if (lo)
+        hipLaunchKernelGGL((k_kblock_bf16<true, 2>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
+                           ldo, gamma, s0, cm);
+      else
+        hipLaunchKernelGGL((k_kblock_bf16<false, 2>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
+                           ldo, gamma, s0, cm);
+    }
+  }
+  SPSVM_LAUNCHED();
+}
+
+namespace {
+struct Tuner {
+  std::mutex mu;
+  bool init = false, tune = false;
+  std::string path;
+  std::map<std::string, int> choice;
+  int force = -1;
+
+  static std::string key(bool split, int cm, bool fused, int64_t n, int64_t ldb, int64_t ncols) {
+    int lg = 0;
+    while ((int64_t(1) << lg) < n) ++lg;
+    return "split=" + std::to_string(split ? 1 : 0) + " cm=" + std::to_string(cm) + " fused=" +
+           std::to_string(fused ? 1 : 0) + " n<=2^" + std::to_string(lg) + " ldb=" + std::to_string(ldb) +
+           " ncols=" + std::to_string(ncols);
+  }
+  void setup() {  // mu held
+    if (init) return;
+    init = true;
+    const char* t = std::getenv("SPSVM_AUTOTUNE");
+    tune = t && t[0] == '1';
+    const char* fv = std::getenv("SPSVM_KBLOCK_VARIANT");
+    for (int i = 0; fv && i < kVariants; ++i)
+      if (std::string(fv) == kVariantName[i]) force = i;
+    const char* f = std::getenv("SPSVM_TUNE_CACHE");
+    if (!f || !f[0]) return;
+    path = f;
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {  // one entry per line: {"key": "...", "variant": "...", ...}
+      const size_t k0 = line.find("\"key\": \""), v0 = line.find("\"variant\": \"");
+      if (k0 == std::string::npos || v0 == std::string::npos) continue;
+      const size_t k1 = line.find('"', k0 + 8), v1 = line.find('"', v0 + 12);
+      if (k1 == std::string::npos || v1 == std::string::npos) continue;
+      const std::string k = line.substr(k0 + 8, k1 - k0 - 8), v = line.substr(v0 + 12, v1 - v0 - 12);
+      const bool split = k.compare(0, 8, "split=1 ") == 0;
+      for (int i = 0; i < kVariants; ++i)  // a split shape takes no single-pass-only form
+        if (v == kVariantName[i] && !(split && (i == kVWideK32 || i == kVWideHalf))) choice[k] = i;
+    }
+  }
+  int forced(bool split) const {  // mu held; the forced variant if it applies to this instance, else -1
+    return force >= 0 && !(split && (force == kVWideK32 || force == kVWideHalf)) ? force : -1;
+  }
+  void save(const std::string& k, int v, const float* us) {  // mu held
+    if (path.empty()) return;
+    std::ofstream o(path, std::ios::app);
+    o << "{\"key\": \"" << k << "\", \"variant\": \"" << kVariantName[v] << "\", \"us\": {";
+    for (int i = 0; i < kVariants; ++i) o << (i ? ", " : "") << "\"" << kVariantName[i] << "\": " << us[i];
+    o << "}}\n";
+  }
+};
+Tuner g_tuner;
+}  // namespace
+
+// The variant a call of this shape uses (a tuned choice when there is one, else the shape heuristic).
+static int chosen_variant(bool split, int cm, bool fused, int64_t n, int64_t ldb, int64_t ncols) {
+  std::lock_guard<std::mutex> lock(g_tuner.mu);
+  g_tuner.setup();
+  if (g_tuner.forced(split) >= 0) return g_tuner.force;
+  const auto it = g_tuner.choice.find(Tuner::key(split, cm, fused, n, ldb, ncols));
+  return it != g_tuner.choice.end() ? it->second : heuristic_variant(n, ldb, ncols);
+}
+
+// MFMA flops a launch_kblock_bf16 call issues: whole tiles of the variant it uses, k over ldb, three products per
+// multiply-add with the split correction (one without).
+double kblock_bf16_issued_flops(int64_t n, int64_t ldb, int64_t ncols, bool split, bool candidates) {
   if (n <= 0 || ncols <= 0) return 0.0;
-  int64_t bm = 128, bn = KB_BN;
-  if (ncols >= kWideCols && ceil_div(n, 256) * ceil_div(ncols, 256) >= 256)
-    bm = bn = 256;
-  else if (n >= kWideRows && ldb >= 256)
-    bm = 256;
+  // candidate blocks are column-major with the fused first pass; basis blocks row-major without it
+  const int v = chosen_variant(split, candidates ? 1 : 0, candidates, n, ldb, ncols);
+  const int64_t bm = v == kVRows128 ? 128 : 256, bn = v == kVWideHalf ? 128 : (v >= kVWide ? 256 : KB_BN);
   return 2.0 * (double)round_up(n, bm) * (double)round_up(ncols, bn) * (double)ldb * (split ? 3.0 : 1.0);
 }
 
@@ -965,35 +1101,49 @@ void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int6
   const int cm = colmajor ? 1 : 0;
   if (ldb % SB_BK != 0 || ((uintptr_t)hi & 15u) || ((uintptr_t)lo & 15u))
     throw Failure(1, "kernel block: split copies must be 16-byte aligned with ldb a multiple of 32");
-  if (ncols >= kWideCols && ceil_div(n, 256) * ceil_div(ncols, 256) >= 256) {
-    const dim3 grid(xcd_grid(ceil_div(n, 256), ceil_div(ncols, 256)));
-    if (lo)
-      hipLaunchKernelGGL((k_kblock_bf16_wide<true, 32>), grid, dim3(512), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols,
-                         out, ldo, gamma, s0, cm);
-    else
-      hipLaunchKernelGGL((k_kblock_bf16_wide<false, 64>), grid, dim3(512), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols,
-                         out, ldo, gamma, s0, cm);
-    SPSVM_LAUNCHED();
-    return;
+  const bool split = lo != nullptr, fused = s0.partial != nullptr;
+  int v;
+  {
+    std::lock_guard<std::mutex> lock(g_tuner.mu);
+    g_tuner.setup();
+    const std::string k = Tuner::key(split, cm, fused, n, ldb, ncols);
+    const auto it = g_tuner.choice.find(k);
+    if (g_tuner.forced(split) >= 0) {
+      v = g_tuner.force;
+    } else if (it != g_tuner.choice.end()) {
+      v = it->second;
+    } else if (!g_tuner.tune) {
+      v = heuristic_variant(n, ldb, ncols);
+    } else {  // time every variant once on this shape (each writes the same output)
+      float us[kVariants] = {-1.f, -1.f, -1.f, -1.f, -1.f};
+      hipEvent_t a, b;
+      SPSVM_HIP(hipEventCreate(&a));
+      SPSVM_HIP(hipEventCreate(&b));
+      v = heuristic_variant(n, ldb, ncols);
+      float best = 0.f;
+      for (int c = 0; c < kVariants; ++c) {
+        if (split && (c == kVWideK32 || c == kVWideHalf)) continue;  // single-pass forms only
+        launch_variant(c, hi, lo, ldb, n, xnorm, cidx, ncols, out, ldo, gamma, st, s0, cm);
+        SPSVM_HIP(hipEventRecord(a, st));
+        for (int r = 0; r < 2; ++r) launch_variant(c, hi, lo, ldb, n, xnorm, cidx, ncols, out, ldo, gamma, st, s0, cm);
+        SPSVM_HIP(hipEventRecord(b, st));
+        SPSVM_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        SPSVM_HIP(hipEventElapsedTime(&ms, a, b));
+        us[c] = 500.f * ms;
+        if (best == 0.f || us[c] < best) {
+          best = us[c];
+          v = c;
+        }
+      }
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      g_tuner.choice[k] = v;
+      g_tuner.save(k, v, us);
+      return;  // the output is written (every variant wrote it)
+    }
   }
-  const bool wide = n >= kWideRows && ldb >= 256;  // short rows: the 128-row tiles keep more waves resident
-  const dim3 grid(xcd_grid(ceil_div(n, wide ? 256 : 128), ceil_div(ncols, KB_BN)));
-  if (wide) {
-    if (lo)
-      hipLaunchKernelGGL((k_kblock_bf16<true, 4>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
-                         ldo, gamma, s0, cm);
-    else
-      hipLaunchKernelGGL((k_kblock_bf16<false, 4>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
-                         ldo, gamma, s0, cm);
-  } else {
-    if (lo)
-      hipLaunchKernelGGL((k_kblock_bf16<true, 2>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
-                         ldo, gamma, s0, cm);
-    else
-      hipLaunchKernelGGL((k_kblock_bf16<false, 2>), grid, dim3(256), 0, st, hi, lo, ldb, n, xnorm, cidx, ncols, out,
-                         ldo, gamma, s0, cm);
-  }
-  SPSVM_LAUNCHED();
+  launch_variant(v, hi, lo, ldb, n, xnorm, cidx, ncols, out, ldo, gamma, st, s0, cm);
 }
 
 // PREDICT: out[row] = sum_c beta[c] exp(-gamma d2(row, c)) over all m basis rows Z (m x d, type TK),

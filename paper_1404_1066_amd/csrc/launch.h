@@ -113,7 +113,7 @@ void launch_split_bf16(const TX* X, int64_t n, int64_t d, int64_t ldx, unsigned 
 // MFMA flops one launch issues (whole tiles of the variant the launcher picks; three products per multiply-add
 // with the split correction), for the roofline next to the algorithmic 2 n ncols d.
 double kblock_issued_flops(int64_t n, int64_t d, int64_t ncols);
-double kblock_bf16_issued_flops(int64_t n, int64_t ldb, int64_t ncols, bool split);
+double kblock_bf16_issued_flops(int64_t n, int64_t ldb, int64_t ncols, bool split, bool candidates);
 void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int64_t ldb, int64_t n,
                         const float* xnorm, const int32_t* cidx, int ncols, float* out, int64_t ldo, double gamma,
                         hipStream_t st, const Score0& s0 = Score0{}, bool colmajor = false);
@@ -329,5 +329,34 @@ void launch_chol_solve_batch(const SolveBatch& b, int64_t ldh, int m, hipStream_
 // (no device allocation); m <= newton_solve_noalloc_max(). Throws on a non-positive pivot; synchronises the stream.
 int newton_solve_noalloc_max();
 void newton_solve_noalloc(double* H, int64_t ldh, int m, const double* g, double* x, hipStream_t st);
+
+// ------------------------------------------------------------------------------------- multiclass.hip
+// out = the rows rows[0 .. m) of X (n x d, dense), dense m x d.
+template <typename TX>
+void launch_gather_pair(const TX* X, int64_t d, const int64_t* rows, int64_t m, TX* out, hipStream_t st);
+// One-vs-one votes of pair (a, b) from its decision values (votes: n x K int32), then the winning class per row.
+void launch_ovo_vote(const double* dec, int64_t n, int a, int b, int K, int32_t* votes, hipStream_t st);
+void launch_ovo_argmax(const int32_t* votes, int64_t n, int K, int32_t* classes, hipStream_t st);
+
+// ----------------------------------------------------------------------------------------- sparse.hip
+// CSR feature matrices (row i: values[indptr[i] .. indptr[i + 1]) at increasing features indices[...], FP32).
+template <typename TK>
+void launch_csr_row_norms(const int64_t* indptr, const float* values, int64_t n, TK* out, hipStream_t st);
+void launch_csr_row_hash(const int64_t* indptr, const int32_t* indices, const float* values, int64_t n, int64_t d,
+                         uint64_t* out, hipStream_t st);
+// flags[0] |= a feature index outside [0, d) or not increasing within its row.
+void launch_csr_check(const int64_t* indptr, const int32_t* indices, int64_t n, int64_t d, int32_t* flags,
+                      hipStream_t st);
+// Dense copies (m x ldo) of the rows idx[0 .. m) (a negative index gives a zero row).
+template <typename TI, typename TK>
+void launch_csr_gather(const int64_t* indptr, const int32_t* indices, const float* values, const TI* idx, int64_t m,
+                       TK* out, int64_t ldo, hipStream_t st);
+// Kernel block of the sparse rows against up to 64 dense rows Z (ncols x ldz): mode 0 writes column-major FP32
+// out[c * ldo + i] (norms xnorm[cidx[c]]; negative cidx: column untouched); mode 1 adds sum_c beta[c] K_ic to the
+// FP64 out[i] (norms znorm[c], cidx null).
+void launch_csr_kblock(const int64_t* indptr, const int32_t* indices, const float* values, int64_t n, int64_t d,
+                       const float* xnorm, const float* Z, int64_t ldz, const float* znorm, const int32_t* cidx,
+                       int ncols, void* out, int64_t ldo, double gamma, int mode, const double* beta, hipStream_t st);
+void launch_add_scalar(double* out, int64_t n, double v, hipStream_t st);
 
 }  // namespace spsvm

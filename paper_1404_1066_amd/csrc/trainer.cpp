@@ -61,13 +61,14 @@ int64_t stage_size(int64_t J, int64_t J_max, double growth, int64_t cap) {
 
 // ------------------------------------------------------------------------------------------ workspace
 Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection, bool x_double,
-               bool x_aligned, bool batch, int64_t problems) {
+               bool x_aligned, bool batch, int64_t problems, bool csr) {
   Plan p;
+  p.csr = csr;
   const int64_t xe = x_double ? 8 : 4;
   p.ldx = round_up(d, 16 / xe);
   // FP32 / FP64 kernel blocks read X with 16-byte vector loads, so rows must start on 16-byte boundaries (else a
   // padded copy); the mixed-precision blocks read the split BF16 copies instead and never need it
-  p.pad_x = opt.precision != SPSVM_MIXED && (p.ldx != d || !x_aligned);
+  p.pad_x = !csr && opt.precision != SPSVM_MIXED && (p.ldx != d || !x_aligned);
   p.ldj = padded_ld<double>(d);
   p.n = n;
   p.d = d;
@@ -91,7 +92,7 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.xnorm = take(n * tk);
   p.hash = take(n * 8);
   p.KXJ = take((size_t)n * p.ldk * tk);
-  p.Kc = take(with_selection ? (size_t)round_up(n, 4) * kCandSlots * cand_group(d, opt.chunk_cap) * tk : 0);
+  p.Kc = take(with_selection ? (size_t)round_up(n, 4) * kCandSlots * (csr ? 1 : cand_group(d, opt.chunk_cap)) * tk : 0);
   p.J = take(J_max * 8);
   p.J32 = take(J_max * 4);
   p.cand_state = take(kCandStateBytes);
@@ -116,6 +117,7 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.ldb = split_ld(d);
   p.Xhi = take(mixed ? (size_t)n * p.ldb * 2 : 0);
   p.Xlo = take(mixed ? (size_t)n * p.ldb * 2 : 0);
+  p.Zc = take(csr ? (size_t)kCandSlots * d * 4 : 0);
   // one problem's Newton state
   {
     size_t so = 0;
@@ -240,7 +242,8 @@ enum { kProfKblock = 0, kProfSyrk = 1, kProfScore = 2, kProfChol = 3 };
 
 template <typename TX, typename TK>
 struct Impl {
-  const TX* X;   // caller's n x d matrix
+  const TX* X;   // caller's n x d matrix (null for CSR rows)
+  CsrX csr;      // CSR rows (indptr null for a dense X)
   const TX* Xk;  // the matrix the kernel-block GEMMs read: X itself or its padded copy (row stride p.ldx)
   const float* y;
   int64_t n, d, J_max;
@@ -397,6 +400,16 @@ struct Impl {
   // hi.hi' only, when single_pass is set).
   void kblock(const int32_t* cols, int ncols, TK* out, int64_t ldo, const Score0& s0 = Score0{},
               bool colmajor = false, bool single_pass = false) {
+    if constexpr (std::is_same<TX, float>::value && std::is_same<TK, float>::value) {
+      if (csr.indptr) {  // sparse rows against the candidate rows made dense (column-major, no fused first pass)
+        if (!colmajor || ncols > kCandSlots) throw Failure(SPSVM_E_INVALID_ARG, "sparse rows: column-major blocks of <= 64");
+        float* Zc = at<float>(p.Zc);
+        launch_csr_gather<int32_t, float>(csr.indptr, csr.indices, csr.values, cols, ncols, Zc, d, st);
+        launch_csr_kblock(csr.indptr, csr.indices, csr.values, n, d, xnorm, Zc, d, nullptr, cols, ncols, out, ldo,
+                          gamma, 0, nullptr, st);
+        return;
+      }
+    }
     if constexpr (std::is_same<TK, float>::value) {
       if (opt.precision == SPSVM_MIXED) {
         launch_kblock_bf16(at<unsigned short>(p.Xhi), bf16_exact || single_pass ? nullptr : at<unsigned short>(p.Xlo),
@@ -408,10 +421,10 @@ struct Impl {
   }
 
   // MFMA flops kblock() issues for ncols columns.
-  double kblock_issued(int64_t ncols, bool single_pass = false) const {
+  double kblock_issued(int64_t ncols, bool single_pass = false, bool candidates = false) const {
     if constexpr (std::is_same<TK, float>::value) {
       if (opt.precision == SPSVM_MIXED)
-        return kblock_bf16_issued_flops(n, p.ldb, ncols, !bf16_exact && !single_pass);
+        return kblock_bf16_issued_flops(n, p.ldb, ncols, !bf16_exact && !single_pass, candidates);
     }
     return kblock_issued_flops(n, d, ncols);
   }
@@ -426,7 +439,11 @@ struct Impl {
   // Basis rows m0..m1 of J gathered into XJ64 (FP64), then the FP64 kernel matrix K_JJ of the first m1 rows.
   void update_basis(int m0, int m1) {
     if (m1 <= m0) return;
-    launch_gather_rows<TX, double>(X, d, J + m0, m1 - m0, XJ64 + (size_t)m0 * p.ldj, p.ldj, st);
+    if (csr.indptr)
+      launch_csr_gather<int64_t, double>(csr.indptr, csr.indices, csr.values, J + m0, m1 - m0,
+                                         XJ64 + (size_t)m0 * p.ldj, p.ldj, st);
+    else
+      launch_gather_rows<TX, double>(X, d, J + m0, m1 - m0, XJ64 + (size_t)m0 * p.ldj, p.ldj, st);
     launch_row_norms<double, double>(XJ64 + (size_t)m0 * p.ldj, m1 - m0, d, p.ldj, xjnorm + m0, st);
     launch_kblock<double, double>(XJ64, p.ldj, m1, d, xjnorm, iota, m1, KJJ + (size_t)p.off * (p.ldh + 1), p.ldh,
                                   gamma, st);
@@ -448,19 +465,29 @@ struct Impl {
 
   // ---------------------------------------------------------------------------------------- preparation
   void prepare() {
-    SPSVM_HIP(hipMemsetAsync(flags, 0, 12, st));
+    SPSVM_HIP(hipMemsetAsync(flags, 0, 16, st));
     launch_iota(iota, J_max, st);
-    if (p.pad_x) launch_pad_rows<TX>(X, n, d, at<TX>(p.Xp), p.ldx, st);
-    launch_check_inputs<TX>(X, n * d, y, n, flags, st);
-    launch_row_hash<TX>(X, n, d, hash, st);
-    launch_row_norms<TX, TK>(X, n, d, d, xnorm, st);
+    if (csr.indptr) {
+      if constexpr (std::is_same<TX, float>::value) {
+        launch_check_inputs<float>(csr.values, csr.nnz, y, n, flags, st);
+        launch_csr_check(csr.indptr, csr.indices, n, d, flags + 3, st);
+        launch_csr_row_hash(csr.indptr, csr.indices, csr.values, n, d, hash, st);
+        launch_csr_row_norms<TK>(csr.indptr, csr.values, n, xnorm, st);
+      }
+    } else {
+      if (p.pad_x) launch_pad_rows<TX>(X, n, d, at<TX>(p.Xp), p.ldx, st);
+      launch_check_inputs<TX>(X, n * d, y, n, flags, st);
+      launch_row_hash<TX>(X, n, d, hash, st);
+      launch_row_norms<TX, TK>(X, n, d, d, xnorm, st);
+    }
     hash_host.resize(n);
     SPSVM_HIP(hipMemcpyAsync(hash_host.data(), hash, n * 8, hipMemcpyDeviceToHost, st));
-    SPSVM_HIP(hipMemcpyAsync(pin.p, flags, 12, hipMemcpyDeviceToHost, st));
+    SPSVM_HIP(hipMemcpyAsync(pin.p, flags, 16, hipMemcpyDeviceToHost, st));
     sync();
-    int32_t f[3];
-    std::memcpy(f, pin.p, 12);
+    int32_t f[4];
+    std::memcpy(f, pin.p, 16);
     if (f[0]) throw Failure(SPSVM_E_INVALID_ARG, "X holds NaN or Inf");
+    if (f[3]) throw Failure(SPSVM_E_INVALID_ARG, "sparse rows: feature indices must lie in [0, d) and increase within a row");
     bf16_exact = f[2] == 0;
     if (opt.precision == SPSVM_MIXED)
       launch_split_bf16<TX>(X, n, d, d, at<unsigned short>(p.Xhi), bf16_exact ? nullptr : at<unsigned short>(p.Xlo),
@@ -898,7 +925,8 @@ struct Impl {
       // converge within the launched passes selects nothing, and so does every later step of the attempt; the
       // stage then resumes from that step (o, J and the basis size are as the last complete step left them)
       // with more passes (64 passes always suffice: the update stops every slot by then).
-      const int G = cand_group(d, opt.chunk_cap);
+      const int G = csr.indptr ? 1 : cand_group(d, opt.chunk_cap);
+      const bool fused = !csr.indptr;  // the dense blocks yield the first scoring pass of their first step
       int qstart = 0, m_q = m;  // first step of the attempt and the basis size it starts from
       for (int attempt = 0;; ++attempt) {
         const int rounds = attempt == 0   ? first_rounds
@@ -922,16 +950,16 @@ struct Impl {
           Score0 s0;
           s0.y = y;
           s0.o = o;
-          s0.partial = score_part;
+          s0.partial = fused ? score_part : nullptr;
           prof.timed(
               kProfKblock, 2.0 * n * ncand * d,
               [&] { kblock(cand_table + (size_t)q0 * kCandSlots, kCandSlots * gsz, Kc, ldc, s0, true, approx); },
-              kblock_issued(kCandSlots * gsz, approx));
+              kblock_issued(kCandSlots * gsz, approx, true));
           for (int j = 0; j < gsz; ++j) {
             const int q = q0 + j;
             const int32_t* cq = cand_table + (size_t)q * kCandSlots;
             const TK* Kq = Kc + (size_t)j * kCandSlots * ldc;
-            if (j == 0) {
+            if (j == 0 && fused) {
               launch_score_init_update(cq, o, hash, stage_hash, q, cst, score_part, (int)ceil_div(n, kKblockRows),
                                        lam, bias_dev, st);
             } else {
@@ -945,9 +973,9 @@ struct Impl {
                          [&] { launch_score_pass<TK>(Kq, ldc, y, o, n, cst, score_part, nblk, st); });
               launch_score_update(cst, score_part, nblk, lam, incomplete + 3, st);
             }
-            stats.score_passes += rounds - (j == 0 ? 1 : 0);
+            stats.score_passes += rounds - (j == 0 && fused ? 1 : 0);
             launch_select_append<TK>(cst, hash, stage_hash, q, Kq, ldc, n, o, KXJ, p.ldk, J, J32, beta, m_dev, sel,
-                                     incomplete, j == 0 ? 1 : 0, p.off, !approx, st);
+                                     incomplete, j == 0 && fused ? 1 : 0, p.off, !approx, st);
           }
         }
         int32_t flags2[8];
@@ -959,7 +987,7 @@ struct Impl {
         // passes for the next stage: as many as the most any step needed, plus one in reserve unless every step
         // of this attempt needed exactly that many (one kernel-block launch per step, so each step's count is
         // its own: a uniform stage predicts the next one well, and a miss only resumes from the step concerned)
-        const bool uniform = G == 1 && flags2[0] == 0 && flags2[2] == (cs - qstart) * (flags2[1] - 1);
+        const bool uniform = G == 1 && flags2[0] == 0 && flags2[2] == (cs - qstart) * (flags2[1] - (fused ? 1 : 0));
         first_rounds = std::min(64, std::max(2, flags2[1] + (uniform ? 0 : 1)));
         if (flags2[0] == 0 || rounds >= 64) break;
         qstart = flags2[4];
@@ -1181,7 +1209,12 @@ struct Impl {
         SPSVM_HIP(hipMalloc(&md->XJ, (size_t)m * md->ldz * sizeof(TK)));
         SPSVM_HIP(hipMalloc(&md->XJnorm, (size_t)m * sizeof(TK)));
         SPSVM_HIP(hipMalloc(&md->beta_dev, (size_t)m * 8));
-        launch_gather_rows<TX, TK>(X, d, J, m, (TK*)md->XJ, md->ldz, st);
+        if (csr.indptr) {
+          if constexpr (std::is_same<TK, float>::value)
+            launch_csr_gather<int64_t, float>(csr.indptr, csr.indices, csr.values, J, m, (float*)md->XJ, md->ldz, st);
+        } else {
+          launch_gather_rows<TX, TK>(X, d, J, m, (TK*)md->XJ, md->ldz, st);
+        }
         launch_row_norms<TK, TK>((const TK*)md->XJ, m, d, md->ldz, (TK*)md->XJnorm, st);
         SPSVM_HIP(hipMemcpyAsync(md->beta_dev, S.beta + p.off, m * 8, hipMemcpyDeviceToDevice, st));
         sync();
@@ -1219,6 +1252,47 @@ spsvm_model* run_train(const void* X, bool x_double, const float* y, int64_t n, 
                      : train_typed<double, float>((const double*)X, y, n, d, C, gamma, J_max, opt, ws, plan, stream, J_fixed);
   return tk_double ? train_typed<float, double>((const float*)X, y, n, d, C, gamma, J_max, opt, ws, plan, stream, J_fixed)
                    : train_typed<float, float>((const float*)X, y, n, d, C, gamma, J_max, opt, ws, plan, stream, J_fixed);
+}
+
+spsvm_model* run_train_csr(const CsrX& Xc, const float* y, int64_t n, int64_t d, double C, double gamma,
+                           int64_t J_max, const spsvm_options& opt, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (opt.precision != SPSVM_F32) throw Failure(SPSVM_E_INVALID_ARG, "sparse rows train in SPSVM_F32 precision");
+  const Plan plan = make_plan(n, d, J_max, opt, true, false, true, false, 1, true);
+  if (!ws || ((uintptr_t)ws & 255u)) throw Failure(SPSVM_E_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
+  if (ws_bytes < plan.bytes)
+    throw Failure(SPSVM_E_WORKSPACE, "workspace too small: need " + std::to_string(plan.bytes) + " bytes, got " +
+                                         std::to_string(ws_bytes));
+  Impl<float, float> im(nullptr, y, n, d, C, gamma, J_max, opt, ws, stream, plan);
+  im.csr = Xc;
+  im.prepare();
+  const int m = im.select_and_optimise();
+  return im.build_model(m);
+}
+
+void run_predict_csr(const spsvm_model* md, const CsrX& Xt, int64_t n_t, double* out, hipStream_t st) {
+  if (n_t <= 0) return;
+  if (md->tk_double) throw Failure(SPSVM_E_INVALID_ARG, "sparse prediction needs a model with FP32 kernel values");
+  SPSVM_HIP(hipMemsetAsync(out, 0, n_t * 8, st));
+  if (md->m > 0) {
+    float* xn = nullptr;
+    SPSVM_HIP(hipMalloc(&xn, (size_t)n_t * sizeof(float)));
+    try {
+      launch_csr_row_norms<float>(Xt.indptr, Xt.values, n_t, xn, st);
+      for (int64_t c0 = 0; c0 < md->m; c0 += kCandSlots) {  // 64 basis rows per launch, sums added in order
+        const int nc = (int)std::min<int64_t>(kCandSlots, md->m - c0);
+        launch_csr_kblock(Xt.indptr, Xt.indices, Xt.values, n_t, md->d, xn, (const float*)md->XJ + c0 * md->ldz,
+                          md->ldz, (const float*)md->XJnorm + c0, nullptr, nc, out, 0, md->gamma, 1,
+                          md->beta_dev + c0, st);
+      }
+      launch_add_scalar(out, n_t, md->bias, st);
+      SPSVM_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      (void)hipFree(xn);
+      throw;
+    }
+    SPSVM_HIP(hipFree(xn));
+  }
+  SPSVM_HIP(hipStreamSynchronize(st));
 }
 
 template <typename TX, typename TK>
@@ -1297,6 +1371,110 @@ void run_predict(const spsvm_model* md, const void* Xt, bool x_double, int64_t n
     else
       predict_typed<float, float>(md, (const float*)Xt, n_t, out, st);
   }
+}
+
+// ------------------------------------------------------------------------------------------ one-vs-one
+// Workspace of a one-vs-one training: a pair's gathered rows (pair_rows x d), their labels and row indices, then
+// the training workspace of pair_rows rows.
+static size_t ovo_head_bytes(int64_t pair_rows, int64_t d, bool x_double) {
+  const size_t xb = (size_t)round_up(pair_rows * d * (x_double ? 8 : 4), 256);
+  return xb + (size_t)round_up(pair_rows * 4, 256) + (size_t)round_up(pair_rows * 8, 256);
+}
+
+size_t ovo_workspace_bytes(int64_t pair_rows, int64_t d, int64_t J_max, const spsvm_options& opt, bool x_double) {
+  return ovo_head_bytes(pair_rows, d, x_double) + make_plan(pair_rows, d, J_max, opt, true, x_double, true).bytes;
+}
+
+void run_train_ovo(const void* X, bool x_double, const int32_t* classes, int64_t n, int64_t d, int K, double C,
+                   double gamma, int64_t J_max, const spsvm_options& opt, void* ws, size_t ws_bytes, hipStream_t st,
+                   spsvm_model** out) {
+  const int P = K * (K - 1) / 2;
+  for (int p = 0; p < P; ++p) out[p] = nullptr;
+  if (!ws || ((uintptr_t)ws & 255u)) throw Failure(SPSVM_E_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
+  std::vector<int32_t> cls((size_t)n);
+  SPSVM_HIP(hipMemcpyAsync(cls.data(), classes, n * 4, hipMemcpyDeviceToHost, st));
+  SPSVM_HIP(hipStreamSynchronize(st));
+  std::vector<int64_t> count(K, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (cls[i] < 0 || cls[i] >= K) throw Failure(SPSVM_E_INVALID_ARG, "class ids must lie in [0, K)");
+    count[cls[i]] += 1;
+  }
+  int64_t pair_max = 0;
+  for (int a = 0; a < K; ++a)
+    for (int b = a + 1; b < K; ++b) pair_max = std::max(pair_max, count[a] + count[b]);
+  const size_t head = ovo_head_bytes(pair_max, d, x_double);
+  const size_t need = head + make_plan(pair_max, d, J_max, opt, true, x_double, true).bytes;
+  if (ws_bytes < need)
+    throw Failure(SPSVM_E_WORKSPACE, "workspace too small for the largest class pair: need " + std::to_string(need) +
+                                         " bytes, got " + std::to_string(ws_bytes));
+  char* base = (char*)ws;
+  void* Xp = base;
+  float* yp = (float*)(base + round_up(pair_max * d * (x_double ? 8 : 4), 256));
+  int64_t* rows_dev = (int64_t*)((char*)yp + round_up(pair_max * 4, 256));
+  void* tws = base + head;
+  std::vector<int64_t> rows;
+  std::vector<float> y;
+  int p = 0;
+  try {
+    for (int a = 0; a < K; ++a)
+      for (int b = a + 1; b < K; ++b, ++p) {
+        rows.clear();
+        y.clear();
+        for (int64_t i = 0; i < n; ++i)
+          if (cls[i] == a || cls[i] == b) {
+            rows.push_back(i);
+            y.push_back(cls[i] == a ? 1.0f : -1.0f);
+          }
+        const int64_t m = (int64_t)rows.size();
+        if (count[a] == 0 || count[b] == 0)
+          throw Failure(SPSVM_E_INVALID_ARG, "class pair (" + std::to_string(a) + ", " + std::to_string(b) +
+                                                 ") has a class without rows");
+        SPSVM_HIP(hipMemcpyAsync(rows_dev, rows.data(), m * 8, hipMemcpyHostToDevice, st));
+        SPSVM_HIP(hipMemcpyAsync(yp, y.data(), m * 4, hipMemcpyHostToDevice, st));
+        if (x_double)
+          launch_gather_pair<double>((const double*)X, d, rows_dev, m, (double*)Xp, st);
+        else
+          launch_gather_pair<float>((const float*)X, d, rows_dev, m, (float*)Xp, st);
+        spsvm_model* md = nullptr;
+        try {
+          md = run_train(Xp, x_double, yp, m, d, C, gamma, std::min<int64_t>(J_max, m), opt, tws, ws_bytes - head, st,
+                         nullptr);
+        } catch (const Failure& e) {
+          throw Failure(e.status, "class pair (" + std::to_string(a) + ", " + std::to_string(b) + "): " + e.what());
+        }
+        for (int64_t& j : md->J) j = rows[j];  // pair rows back to rows of X
+        out[p] = md;
+      }
+  } catch (...) {
+    for (int q = 0; q < P; ++q) {
+      delete out[q];
+      out[q] = nullptr;
+    }
+    throw;
+  }
+}
+
+size_t ovo_predict_workspace_bytes(int64_t n_t, int K) {
+  return (size_t)round_up(n_t * 8, 256) + (size_t)round_up(n_t * K * 4, 256);
+}
+
+void run_predict_ovo(const spsvm_model* const* models, int K, const void* Xt, bool x_double, int64_t n_t,
+                     int32_t* classes, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (n_t <= 0) return;
+  if (!ws || ((uintptr_t)ws & 255u) || ws_bytes < ovo_predict_workspace_bytes(n_t, K))
+    throw Failure(SPSVM_E_WORKSPACE, "workspace must be 256-byte aligned with >= spsvm_predict_ovo_workspace_bytes");
+  double* dec = (double*)ws;
+  int32_t* votes = (int32_t*)((char*)ws + round_up(n_t * 8, 256));
+  SPSVM_HIP(hipMemsetAsync(votes, 0, (size_t)n_t * K * 4, st));
+  int p = 0;
+  for (int a = 0; a < K; ++a)
+    for (int b = a + 1; b < K; ++b, ++p) {
+      if (!models[p]) throw Failure(SPSVM_E_INVALID_ARG, "model pointer of pair " + std::to_string(p) + " is NULL");
+      run_predict(models[p], Xt, x_double, n_t, dec, st);
+      launch_ovo_vote(dec, n_t, a, b, K, votes, st);
+    }
+  launch_ovo_argmax(votes, n_t, K, classes, st);
+  SPSVM_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace spsvm

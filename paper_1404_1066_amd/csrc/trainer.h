@@ -50,7 +50,8 @@ struct Plan {
   size_t bytes = 0;
   // offsets into the workspace (shared by all slots)
   size_t xnorm, hash, KXJ, Kc, J, J32, cand_state, sel, ls, scalars, score_part, cand_table, stage_hash, m_dev, flags,
-      XJ64, xjnorm, KJJ, iota, incomplete, Xp, D, DJJ, G, Xhi, Xlo;
+      XJ64, xjnorm, KJJ, iota, incomplete, Xp, D, DJJ, G, Xhi, Xlo, Zc;
+  bool csr = false;  // CSR rows: the candidate rows are made dense in Zc (kCandSlots x d FP32) for each block
   int64_t ldb = 0;  // row stride of the split-BF16 copies (MIXED)
   // per-problem regions: slot q starts at slots_at + q * slot.bytes; ls and scalars hold one entry per slot
   SlotPlan slot;
@@ -59,7 +60,19 @@ struct Plan {
 };
 
 Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection,
-               bool x_double, bool x_aligned, bool batch = false, int64_t problems = 1);
+               bool x_double, bool x_aligned, bool batch = false, int64_t problems = 1, bool csr = false);
+
+// Feature matrix in compressed sparse rows (device arrays; FP32 values, features increasing within a row).
+struct CsrX {
+  const int64_t* indptr = nullptr;  // n + 1
+  const int32_t* indices = nullptr;
+  const float* values = nullptr;
+  int64_t nnz = 0;
+};
+// Greedy training (F32 kernel values) on CSR rows.
+spsvm_model* run_train_csr(const CsrX& X, const float* y, int64_t n, int64_t d, double C, double gamma,
+                           int64_t J_max, const spsvm_options& opt, void* ws, size_t ws_bytes, hipStream_t stream);
+void run_predict_csr(const spsvm_model* model, const CsrX& Xt, int64_t n_t, double* out, hipStream_t stream);
 
 // Runs training; returns a new model (caller owns) or throws Failure.
 spsvm_model* run_train(const void* X, bool x_double, const float* y, int64_t n, int64_t d, double C, double gamma,
@@ -74,5 +87,14 @@ void run_train_batch(const void* X, bool x_double, int64_t n, int64_t d, int64_t
 
 void run_predict(const spsvm_model* model, const void* Xt, bool x_double, int64_t n_t, double* out,
                  hipStream_t stream);
+
+// One-vs-one: K (K - 1) / 2 greedy trainings, one per class pair on its rows (gathered into the workspace).
+size_t ovo_workspace_bytes(int64_t pair_rows, int64_t d, int64_t J_max, const spsvm_options& opt, bool x_double);
+void run_train_ovo(const void* X, bool x_double, const int32_t* classes, int64_t n, int64_t d, int K, double C,
+                   double gamma, int64_t J_max, const spsvm_options& opt, void* ws, size_t ws_bytes, hipStream_t st,
+                   spsvm_model** out);
+size_t ovo_predict_workspace_bytes(int64_t n_t, int K);
+void run_predict_ovo(const spsvm_model* const* models, int K, const void* Xt, bool x_double, int64_t n_t,
+                     int32_t* classes, void* ws, size_t ws_bytes, hipStream_t st);
 
 }  // namespace spsvm

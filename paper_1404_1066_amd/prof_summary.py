@@ -3,6 +3,7 @@ beside the code.
 
   python -m paper_1404_1066_amd.prof_summary kernels <results.db> "<command that produced it>" <runs> <title>
   python -m paper_1404_1066_amd.prof_summary traffic <fetch.db> <write.db> "<command>" <title> <kernel> <source>
+  python -m paper_1404_1066_amd.prof_summary counters <results.db> "<command>" <title> [<kernel name part>]
 
 `traffic` reads one FETCH_SIZE run and one WRITE_SIZE run (KiB per dispatch). Each counter is scaled by what
 it reads for the 256 MiB device copy of `bench.py --copy-probe` (known bytes read and written), and the
@@ -68,8 +69,34 @@ def traffic(fdb, wdb, cmd, title, kernel, source):
     return "\n".join(out)
 
 
+def counters(db, cmd, title, match=""):
+    """Average of every collected counter per dispatch, for the kernels whose name contains `match` (all when
+    empty), largest dispatch count first; derived ratios for the MFMA and LDS counters when present."""
+    d = collections.defaultdict(lambda: collections.defaultdict(list))
+    for name, counter, v in sqlite3.connect(db).execute("select kernel_name, counter_name, value from counters_collection"):
+        k = name.split("(")[0].replace("void ", "")
+        if match in k:
+            d[k][counter].append(v)
+    out = [f"# {title}", "", "Command (from the repository root, one MI355X):", "", f"    {cmd}", "",
+           "Per-dispatch averages (counters summed over the device's units by rocprofv3).", ""]
+    for k, cs in sorted(d.items(), key=lambda kv: -max(len(v) for v in kv[1].values()))[:12]:
+        n = max(len(v) for v in cs.values())
+        avg = {c: sum(v) / len(v) for c, v in cs.items()}
+        out.append(f"## `{k}` ({n} dispatches)")
+        out.append("")
+        for c in sorted(avg):
+            out.append(f"* {c}: {avg[c]:.6g}")
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in avg and "GRBM_GUI_ACTIVE" in avg and avg["GRBM_GUI_ACTIVE"] > 0:
+            # MFMA busy cycles are counted per SIMD: 256 CUs x 4 SIMDs
+            out.append(f"* MFMA busy fraction: {avg['SQ_VALU_MFMA_BUSY_CYCLES'] / (avg['GRBM_GUI_ACTIVE'] * 1024):.4f}")
+        out.append("")
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "kernels":
         print(kernels(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5]))
+    elif sys.argv[1] == "counters":
+        print(counters(*sys.argv[2:6]))
     else:
         print(traffic(*sys.argv[2:8]))

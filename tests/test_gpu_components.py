@@ -54,8 +54,8 @@ def test_rbf_block_mixed_within_split_bound(n, d, nc):
 @pytest.mark.parametrize("n,d,nc,binary", [(70001, 300, 260, False), (66000, 54, 512, False),
                                            (66000, 123, 256, True), (66000, 90, 300, True)])
 def test_rbf_block_mixed_wide_tiles(n, d, nc, binary):
-    """Blocks of 192 or more columns (with at least 256 tiles) take 256 x 256 tiles (binary rows: single-pass
-    products in 64-wide k chunks; 90 features make the last chunk a half one). Against the oracle: the split
+    """Blocks of 192 or more columns (with at least 256 tiles) take 256 x 256 tiles (binary rows are BF16 numbers:
+    single-pass products in 64-wide k chunks; 90 features make the last chunk a half one). Against the oracle: the split
     bound (exact on binary rows). Against 64-column slices of the same block, which take the 64-column tiles: the
     same products are summed in the same order, so the bits agree."""
     X, idx, gamma, K, want = _kblock_case(n, d, nc, "mixed", np.float32, n * 17 + d, binary=binary)
@@ -143,7 +143,9 @@ def _check_scores(res, ref, f0):
             assert res["status"][c] == 3 and sc_or <= best * (1 + 1e-6)
 
 
-@pytest.mark.parametrize("n,ncand,C", [(5003, 64, 1.0), (777, 59, 10.0), (1, 3, 1.0), (130, 1, 0.5)])
+# 1 100 000 rows: several thousand rows per workgroup of a pass
+@pytest.mark.parametrize("n,ncand,C", [(5003, 64, 1.0), (777, 59, 10.0), (1, 3, 1.0), (130, 1, 0.5),
+                                       (1100000, 13, 1.0)])
 def test_candidate_scores_match_oracle(n, ncand, C):
     r = np.random.default_rng(n + ncand)
     o = r.standard_normal(n) * 0.8
@@ -156,14 +158,16 @@ def test_candidate_scores_match_oracle(n, ncand, C):
     assert res["winner"] == want
 
 
-def test_candidate_score_window_overflow_falls_back_to_full_passes():
+@pytest.mark.parametrize("pad", [0, 1100000])
+def test_candidate_score_window_overflow_falls_back_to_full_passes(pad):
     """Two candidates with the same one-dimensional problem psi'(s) = 0.9 s - sum b max(0, a - s b), built from
     row groups: 1000 rows with b = 0.01, a = 1 (breakpoint 100); a group with breakpoint 9.99 and sum b^2 = 1; 10
     rows with breakpoint 5. The first Newton point from s = 0 is 9.98503, just below 9.99, and the root (10) lies
     just above it: both inside the window of |s| / 256 around that point. For candidate 0 the 9.99 group has 100
     rows, more than the 64 a window list holds, so the list is incomplete and the slot must continue with full
     passes (4 in all); for candidate 1 the group has 40 rows and the window walk finishes it after 2 passes. Both
-    scores must be the exact minimum."""
+    scores must be the exact minimum. pad: rows with kernel value 0 for both candidates (no effect on either
+    problem) appended, so that each workgroup of a pass walks thousands of rows."""
     def block(nc):
         bc = float(np.float32(np.sqrt(1.0 / nc)))
         k = np.concatenate([np.full(1000, 0.01), np.full(nc, bc), np.full(10, 0.02)]).astype(np.float32)
@@ -173,9 +177,11 @@ def test_candidate_score_window_overflow_falls_back_to_full_passes():
     k0, o0 = block(100)
     k1, o1 = block(40)
     n0, n1 = k0.size, k1.size
-    o = np.concatenate([o0, o1])
-    y = np.ones(n0 + n1)
-    cols = [np.concatenate([k0, np.zeros(n1, np.float32)]), np.concatenate([np.zeros(n0, np.float32), k1])]
+    r = np.random.default_rng(9)
+    o = np.concatenate([o0, o1, r.standard_normal(pad)])
+    y = np.concatenate([np.ones(n0 + n1), np.where(r.random(pad) < 0.5, 1.0, -1.0)])
+    zp = np.zeros(pad, np.float32)
+    cols = [np.concatenate([k0, np.zeros(n1, np.float32), zp]), np.concatenate([np.zeros(n0, np.float32), k1, zp])]
     res, ref, f0 = _scores_vs_oracle(o, y, cols, np.zeros(2), 1.0 / 0.9)
     assert list(res["status"]) == [1, 1]
     _check_scores(res, ref, f0)

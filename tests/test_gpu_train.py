@@ -525,3 +525,43 @@ def test_offset_fixed_basis_and_batch_match_oracle(prec):
         single = lib.train_fixed_basis(Xg, Yg[q].contiguous(), p.C[s_], p.gamma[s_], p.J, precision=prec, bias=1)
         assert abs(single.bias - models[q].bias) <= 1e-6 * (1 + abs(info.bias))
         assert abs(single.bias - info.bias) <= 1e-4 * (1 + abs(info.bias))
+
+
+def test_ovo_identical_to_oracle_f64():
+    """One-vs-one multiclass (4 classes, 6 pairs), FP64 path: every pair's model has the oracle's basis (as rows of
+    X) and objective, and the voted classes of held-out rows equal the oracle's votes."""
+    X, cls = datagen.make_mnist_like(per_class=300, d=10, seed=21, classes=4, noise=0.3)
+    X = X.astype(np.float64)
+    C, gamma, m = 2.0, 0.5, 25
+    ref = oracle.train_ovo(X, cls, 4, C, gamma, m, seed=3)
+    Xg = torch.tensor(X, device="cuda")
+    models = lib.train_ovo(Xg, torch.tensor(cls, dtype=torch.int32, device="cuda"), 4, C, gamma, m, seed=3,
+                           precision="f64")
+    assert len(models) == 6
+    for (res, rows), md in zip(ref, models):
+        J, beta, F = md.get()
+        assert J.tolist() == rows[res.J].tolist()
+        assert abs(F - res.F) <= 1e-9 * res.F
+    Xt, _ = datagen.make_mnist_like(per_class=100, d=10, seed=22, classes=4, noise=0.3)
+    Xt = Xt.astype(np.float64)
+    got = lib.predict_ovo(models, 4, torch.tensor(Xt, device="cuda")).cpu().numpy()
+    want = oracle.predict_ovo(X, ref, gamma, Xt, 4)
+    assert np.array_equal(got, want)
+
+
+def test_ovo_f32_pairs_reach_oracle_objective():
+    """One-vs-one in FP32 on 3 classes of 784-feature rows: each pair's objective within 1e-6 of the oracle's optimum
+    at that pair's basis."""
+    X, cls = datagen.make_mnist_like(per_class=700, d=784, seed=23, classes=3)
+    C, gamma, m = 10.0, 0.02, 80
+    models = lib.train_ovo(torch.tensor(X, device="cuda"), torch.tensor(cls, dtype=torch.int32, device="cuda"), 3, C,
+                           gamma, m, seed=4)
+    for (a, b), md in zip(oracle.ovo_pairs(3), models):
+        rows = np.flatnonzero((cls == a) | (cls == b))
+        J, beta, F = md.get()
+        local = np.searchsorted(rows, J)
+        assert np.array_equal(rows[local], J)
+        y = np.where(cls[rows] == a, 1.0, -1.0)
+        b_or, F_or, _ = osp.solve_fixed_J(X[rows], y, C, gamma, local)
+        Fo = osp.objective_at(X[rows], y, C, gamma, local, beta)
+        assert abs(Fo - F_or) / F_or <= 1e-6
