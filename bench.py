@@ -113,6 +113,8 @@ def roofline_entry(stats, bit, precision):
         achieved = work / sec / 1e12
         fp64 = pre in ("syrk", "chol") or precision == "f64"
         peak = PEAKS["fp64_mfma_TFLOPs"] if fp64 else PEAKS["fp32_mfma_TFLOPs"]
+        if pre == "kblock" and precision == "mixed":  # split-BF16 products: priced against the BF16 peak
+            peak = PEAKS["bf16_mfma_TFLOPs"]
         u = "TFLOP/s"
     return {"kernel": pre, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": u,
             "frac": round(achieved / peak, 4), "traffic": None, "launches": launches,

@@ -2,11 +2,16 @@
 // system of each Newton step, section 4, "Primal optimization": second-order steps expressed as dense
 // linear algebra).
 //
-// Right-looking blocked algorithm with 64-wide panels. Per panel k:
+// Right-looking blocked algorithm in two levels: outer panels of 256 columns, each factored as four inner panels
+// of 64. Per inner panel k:
 //   1. one workgroup factors the 64 x 64 diagonal block in LDS and writes its inverse (for the panel solve
 //      and for the triangular solves later);
 //   2. the rows below are multiplied by the inverse transpose (independent 64-row blocks);
-//   3. the trailing lower triangle is updated, H_ij -= L_ik L_jk^T, one 64 x 64 tile per workgroup on FP64 MFMA.
+//   3. the rest of the outer panel (its columns right of k, every row below) is updated, H_ij -= L_ik L_jk^T,
+//      one 64 x 64 tile per workgroup on FP64 MFMA.
+// After the fourth inner panel the trailing lower triangle right of the outer panel is updated once with all
+// 256 of its columns (H_ij -= L_i,K L_j,K^T, K the outer panel): each tile of the trailing matrix is read and
+// written once per 256 columns instead of once per 64, and its MFMA chain is four times longer.
 // A non-positive or non-finite pivot sets a failure flag; the host then retries with a diagonal jitter.
 #include <mutex>
 #include <string>
@@ -260,53 +265,70 @@ __device__ __forceinline__ void tri_tile(int t, int& tr, int& tc) {
   tc = t - r * (r + 1) / 2;
 }
 
+// Tile (tr, tc) of a launch over the lower triangle (ctiles = 0: tri_tile of the workgroup index) or over a strip
+// of ctiles tile columns and every tile row at or below each (the rest of an outer panel). False: no tile.
+__device__ __forceinline__ bool update_tile(int ctiles, int& tr, int& tc) {
+  if (ctiles == 0) {
+    tri_tile(blockIdx.x, tr, tc);
+    return true;
+  }
+  tr = blockIdx.x / ctiles;
+  tc = blockIdx.x - tr * ctiles;
+  return tc <= tr;
+}
+
 // Operands come straight from global memory (no LDS, no barrier): wave (wr, wc) owns a 32 x 32 block and lane
-// group g takes the panel columns k0 + 16 g .. k0 + 16 g + 15, so in MFMA step s the four lane groups supply
-// four distinct columns and every column enters the sum once; each lane loads its rows' 16 values as four
-// 32-byte vectors. The strictly upper block of a diagonal tile is skipped.
-__global__ __launch_bounds__(256) void k_chol_update(const CholBatch bt, int64_t ldh, int m, int k0) {
+// group g takes the columns kp + 64 q + 16 g .. + 15 of each 64-column chunk q of the panel [kp, kp + kw), so in
+// MFMA step s the four lane groups supply four distinct columns and every column enters the sum once; each lane
+// loads its rows' 16 values of a chunk as four 32-byte vectors. The tiles start at row and column `base`; the
+// strictly upper block of a diagonal tile is skipped.
+__global__ __launch_bounds__(256) void k_chol_update(const CholBatch bt, int64_t ldh, int m, int kp, int kw, int base,
+                                                     int ctiles) {
   double* __restrict__ H = bt.H[blockIdx.z];
   int tr, tc;
-  tri_tile(blockIdx.x, tr, tc);
-  const int base = k0 + NB;
+  if (!update_tile(ctiles, tr, tc)) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, i16 = lane & 15;
   const int wr = w >> 1, wc = w & 1;
   if (tr == tc && wr < wc) return;  // wave-uniform
   const int ra = base + tr * NB + wr * 32, rb = base + tc * NB + wc * 32;
-  double av[2][16], bv[2][16];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int row = ra + i * 16 + i16;
-    const double* p = H + (int64_t)(row < m ? row : k0) * ldh + k0 + 16 * g;
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const doublex4 v = row < m ? *(const doublex4*)(p + 4 * h) : doublex4{0, 0, 0, 0};
-#pragma unroll
-      for (int e = 0; e < 4; ++e) av[i][4 * h + e] = v[e];
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int row = rb + j * 16 + i16;
-    const double* p = H + (int64_t)(row < m ? row : k0) * ldh + k0 + 16 * g;
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const doublex4 v = row < m ? *(const doublex4*)(p + 4 * h) : doublex4{0, 0, 0, 0};
-#pragma unroll
-      for (int e = 0; e < 4; ++e) bv[j][4 * h + e] = v[e];
-    }
-  }
+  if (ra >= m || rb >= m) return;
   doublex4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0, 0, 0, 0};
+  for (int k0 = kp; k0 < kp + kw; k0 += NB) {
+    double av[2][16], bv[2][16];
 #pragma unroll
-  for (int st = 0; st < 16; ++st)
+    for (int i = 0; i < 2; ++i) {
+      const int row = ra + i * 16 + i16;
+      const double* p = H + (int64_t)(row < m ? row : k0) * ldh + k0 + 16 * g;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int h = 0; h < 4; ++h) {
+        const doublex4 v = row < m ? *(const doublex4*)(p + 4 * h) : doublex4{0, 0, 0, 0};
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][st], bv[j][st], acc[i][j], 0, 0, 0);
+        for (int e = 0; e < 4; ++e) av[i][4 * h + e] = v[e];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int row = rb + j * 16 + i16;
+      const double* p = H + (int64_t)(row < m ? row : k0) * ldh + k0 + 16 * g;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const doublex4 v = row < m ? *(const doublex4*)(p + 4 * h) : doublex4{0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bv[j][4 * h + e] = v[e];
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < 16; ++st)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][st], bv[j][st], acc[i][j], 0, 0, 0);
+  }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -320,13 +342,13 @@ __global__ __launch_bounds__(256) void k_chol_update(const CholBatch bt, int64_t
 }
 
 // The same update with 128 x 128 tiles for large trailing matrices: each wave owns a 64 x 64 block (4 x 4
-// MFMA tiles), half the loads per MFMA of the 64 x 64 tiles. The panel's 64 columns are taken in quarters of
+// MFMA tiles), half the loads per MFMA of the 64 x 64 tiles. The panel's columns are taken in quarters of
 // 16 (lane group g: columns 4 g .. 4 g + 3 of the quarter, one 32-byte load per row).
-__global__ __launch_bounds__(256) void k_chol_update128(const CholBatch bt, int64_t ldh, int m, int k0) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_chol_update128(
+    const CholBatch bt, int64_t ldh, int m, int kp, int kw, int base) {
   double* __restrict__ H = bt.H[blockIdx.z];
   int tr, tc;
   tri_tile(blockIdx.x, tr, tc);
-  const int base = k0 + NB;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, i16 = lane & 15;
   const int wr = w >> 1, wc = w & 1;
   if (tr == tc && wr < wc) return;  // wave-uniform
@@ -337,9 +359,9 @@ __global__ __launch_bounds__(256) void k_chol_update128(const CholBatch bt, int6
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0, 0, 0, 0};
-  for (int qt = 0; qt < 4; ++qt) {  // quarters of the panel: lane group g takes columns 16 qt + 4 g .. + 3
+  for (int qt = 0; qt < kw / 16; ++qt) {  // quarters of 16 columns: lane group g takes columns 16 qt + 4 g .. + 3
     double av[4][4], bv[4][4];
-    const int kc = k0 + 16 * qt + 4 * g;
+    const int kc = kp + 16 * qt + 4 * g;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = ra + i * 16 + i16;
@@ -374,24 +396,40 @@ __global__ __launch_bounds__(256) void k_chol_update128(const CholBatch bt, int6
       }
 }
 
+// Columns of an outer panel (four inner panels of 64).
+constexpr int kCholOuter = 4 * NB;
+
 // All slots share m and ldh; each panel step is one launch per kernel for the whole batch.
 void launch_cholesky_batch(const CholBatch& b, int64_t ldh, int m, hipStream_t s) {
   if (b.count <= 0 || m <= 0) return;
   if (b.count > kMaxBatch) throw Failure(1, "Cholesky batch: too many slots");
   const unsigned nz = (unsigned)b.count;
-  for (int k0 = 0; k0 < m; k0 += NB) {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, nz), dim3(256), 0, s, b, ldh, m, k0);
-    SPSVM_LAUNCHED();
-    const int rest = m - k0 - NB;
-    if (rest <= 0) break;
-    const int nblk = (int)ceil_div(rest, NB);
-    hipLaunchKernelGGL(k_trsm_panel, dim3(nblk, 1, nz), dim3(256), 0, s, b, ldh, m, k0);
-    SPSVM_LAUNCHED();
+  for (int K0 = 0; K0 < m; K0 += kCholOuter) {
+    const int kend = std::min(K0 + kCholOuter, m);
+    for (int k0 = K0; k0 < kend; k0 += NB) {
+      hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, nz), dim3(256), 0, s, b, ldh, m, k0);
+      SPSVM_LAUNCHED();
+      const int rest = m - k0 - NB;
+      if (rest <= 0) return;
+      const int nblk = (int)ceil_div(rest, NB);
+      hipLaunchKernelGGL(k_trsm_panel, dim3(nblk, 1, nz), dim3(256), 0, s, b, ldh, m, k0);
+      SPSVM_LAUNCHED();
+      const int ct = (int)ceil_div(std::max(kend - k0 - NB, 0), NB);  // tile columns left in the outer panel
+      if (ct > 0) {
+        hipLaunchKernelGGL(k_chol_update, dim3(nblk * ct, 1, nz), dim3(256), 0, s, b, ldh, m, k0, NB, k0 + NB, ct);
+        SPSVM_LAUNCHED();
+      }
+    }
+    const int rest = m - kend;  // the trailing matrix right of the outer panel, all of its columns at once
+    if (rest <= 0) return;
     if (rest >= 512 && nz >= 4) {  // many problems: the larger tiles; one problem: more, smaller workgroups
       const int nb2 = (int)ceil_div(rest, 128);
-      hipLaunchKernelGGL(k_chol_update128, dim3(nb2 * (nb2 + 1) / 2, 1, nz), dim3(256), 0, s, b, ldh, m, k0);
+      hipLaunchKernelGGL(k_chol_update128, dim3(nb2 * (nb2 + 1) / 2, 1, nz), dim3(256), 0, s, b, ldh, m, K0,
+                         kend - K0, kend);
     } else {
-      hipLaunchKernelGGL(k_chol_update, dim3(nblk * (nblk + 1) / 2, 1, nz), dim3(256), 0, s, b, ldh, m, k0);
+      const int nblk = (int)ceil_div(rest, NB);
+      hipLaunchKernelGGL(k_chol_update, dim3(nblk * (nblk + 1) / 2, 1, nz), dim3(256), 0, s, b, ldh, m, K0,
+                         kend - K0, kend, 0);
     }
     SPSVM_LAUNCHED();
   }

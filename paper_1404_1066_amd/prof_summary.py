@@ -87,8 +87,11 @@ def counters(db, cmd, title, match=""):
         for c in sorted(avg):
             out.append(f"* {c}: {avg[c]:.6g}")
         if "SQ_VALU_MFMA_BUSY_CYCLES" in avg and "GRBM_GUI_ACTIVE" in avg and avg["GRBM_GUI_ACTIVE"] > 0:
-            # MFMA busy cycles are counted per SIMD: 256 CUs x 4 SIMDs
-            out.append(f"* MFMA busy fraction: {avg['SQ_VALU_MFMA_BUSY_CYCLES'] / (avg['GRBM_GUI_ACTIVE'] * 1024):.4f}")
+            # GRBM_GUI_ACTIVE arrives summed over the 8 XCDs (each counts the kernel's cycles); MFMA busy cycles
+            # are summed over the 1024 SIMDs (256 CUs x 4)
+            cyc = avg["GRBM_GUI_ACTIVE"] / 8
+            out.append(f"* GPU cycles per XCD: {cyc:.6g}")
+            out.append(f"* MFMA busy fraction: {avg['SQ_VALU_MFMA_BUSY_CYCLES'] / (cyc * 1024):.4f}")
         out.append("")
     return "\n".join(out)
 

@@ -220,10 +220,11 @@ def test_batch_equals_fixed_basis_and_oracle():
 
 
 def test_batch_large_basis_matches_oracle():
-    """Six problems on a shared basis of 700 rows: the batched Cholesky then uses its 128 x 128 trailing-update
-    tiles (the triangular solves of this size run one workgroup per problem); each model reaches the oracle's
-    optimum."""
-    p = datagen.make_config("mnist-60k", n=3000, J_max=700)
+    """Six problems on a shared basis of 900 rows: the batched Cholesky's trailing update right of the first
+    256-column outer panel (644 rows) takes the 128 x 128 tiles with all 256 panel columns, the next one the
+    64 x 64 tiles (the triangular solves of this size run one workgroup per problem); each model reaches the
+    oracle's optimum."""
+    p = datagen.make_config("mnist-60k", n=3000, J_max=900)
     sel = [1, 5, 9, 13, 17, 21]  # one gamma: a lockstep group of six
     Xg = torch.tensor(p.X, device="cuda")
     Yg = torch.tensor(p.Y[sel], dtype=torch.float32, device="cuda").contiguous()
