@@ -32,6 +32,8 @@ from .spsvm import (  # noqa: F401
     newton_solve,
     solve_fixed_J,
     train,
+    SharedResult,
+    train_shared,
     predict,
     duplicate_groups,
     ovo_pairs,

@@ -377,6 +377,108 @@ def train(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J_max: int, seed
     return TrainResult(np.array(J, dtype=np.int64), beta, F, f_trace, gaps, stages, newton_iters, b, errors, stop)
 
 
+@dataclasses.dataclass
+class SharedResult:
+    J: np.ndarray  # the shared basis
+    beta: np.ndarray  # P x |J|, one coefficient row per problem
+    F: np.ndarray  # paper-scale objective C_p f_p of each problem
+    totals: list  # per addition step: the winner's summed score
+    stages: list  # number of additions per stage
+
+
+def _shared_total(decreases) -> float:
+    """Score of a candidate for the shared basis: the problems' decreases of f_p added in problem order."""
+    total = 0.0
+    for dl in decreases:
+        total += dl
+    return total
+
+
+def _candidate_columns(X: np.ndarray, c: int, gamma) -> list:
+    """Kernel column of row c for each problem (computed once per distinct gamma)."""
+    kg = {}
+    for g in gamma:
+        if g not in kg:
+            kg[g] = rbf_block(X, X[c:c + 1], g)[:, 0]
+    return [kg[g] for g in gamma]
+
+
+def train_shared(X: np.ndarray, Y: np.ndarray, C, gamma, J_max: int, seed: int = 0, kappa: int = 59,
+                 growth: float = 0.25, cap: int = 256, tol: float = 1e-10, ftol: float = 1e-14,
+                 max_iter: int = 50) -> SharedResult:
+    """Greedy growth of one basis shared by P problems on the same rows (labels Y[p], C[p], gamma[p]), with Newton
+    re-optimisation of every problem after each stage: the selection of section 4 applied to the batch.
+
+    The candidates of a step are drawn as for one problem (same stream, J frozen at the stage start, duplicates of
+    members skipped). A candidate's score is the sum over the problems, in problem order, of each problem's exact
+    one-coefficient decrease of f_p = F_p / C_p (its own kernel column, coefficients and outputs); the largest sum
+    wins (lower row on ties), and every problem takes the winner with its own one-dimensional optimum as the
+    coefficient. Without the bias and the stopping rule.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.atleast_2d(np.asarray(Y, dtype=np.float64))
+    P, n = Y.shape
+    C = np.broadcast_to(np.asarray(C, dtype=np.float64), (P,))
+    gamma = np.broadcast_to(np.asarray(gamma, dtype=np.float64), (P,))
+    groups = duplicate_groups(X)
+    for q in range(P):
+        _validate(X, Y[q], C[q], gamma[q], J_max, groups)
+    lam = 1.0 / C
+    J: list[int] = []
+    beta = [np.zeros(0) for _ in range(P)]
+    o = np.zeros((P, n))
+    cols = [[] for _ in range(P)]  # kernel columns of the basis, per problem
+    used_groups: set = set()
+    totals, stages = [], []
+    t = 0
+    while len(J) < J_max:
+        cs = stage_size(len(J), J_max, growth, cap)
+        frozen = set(used_groups)
+        draws = [draw_candidates(seed, t + q, n, kappa, lambda i: groups[i] in frozen) for q in range(cs)]
+        added = 0
+        for q in range(cs):
+            best = None  # (summed score, index, coefficients, columns)
+            for c in draws[q]:
+                if groups[c] in used_groups:
+                    continue
+                ks = _candidate_columns(X, c, gamma)
+                ss, dls = [], []
+                for p in range(P):
+                    sp, dl = score_candidate(1.0 - Y[p] * o[p], Y[p] * ks[p], lam[p], float(o[p, c]))
+                    ss.append(sp)
+                    dls.append(dl)
+                total = _shared_total(dls)
+                if best is None or total > best[0] or (total == best[0] and c < best[1]):
+                    best = (total, c, ss, ks)
+            if best is None:
+                continue
+            total, c, ss, ks = best
+            totals.append(total)
+            J.append(c)
+            used_groups.add(groups[c])
+            for p in range(P):
+                beta[p] = np.append(beta[p], ss[p])
+                o[p] = o[p] + ss[p] * ks[p]
+                cols[p].append(ks[p])
+            added += 1
+        t += cs
+        stages.append(added)
+        if added == 0:
+            break
+        for p in range(P):
+            KXJ = np.stack(cols[p], axis=1)
+            beta[p], _ = newton_solve(KXJ, KXJ[J, :], Y[p], lam[p], beta[p], tol=tol, ftol=ftol, max_iter=max_iter)
+            o[p] = KXJ @ beta[p]
+    F = np.zeros(P)
+    for p in range(P):
+        if J:
+            KXJ = np.stack(cols[p], axis=1)
+            F[p] = C[p] * objective(KXJ, KXJ[J, :], Y[p], beta[p], lam[p])
+        else:
+            F[p] = C[p] * 0.5 * n
+    return SharedResult(np.array(J, dtype=np.int64), np.array(beta), F, totals, stages)
+
+
 def solve_fixed_J(X: np.ndarray, y: np.ndarray, C: float, gamma: float, J, beta0=None, tol: float = 1e-10,
                   ftol: float = 1e-14, max_iter: int = 50, bias: bool = False):
     """Newton re-optimisation of Eq. 4 on a given basis J, from beta0 (default 0; with ``bias`` the offset starts

@@ -71,7 +71,8 @@ def traffic(fdb, wdb, cmd, title, kernel, source):
 
 def counters(db, cmd, title, match=""):
     """Average of every collected counter per dispatch, for the kernels whose name contains `match` (all when
-    empty), largest dispatch count first; derived ratios for the MFMA and LDS counters when present."""
+    empty), the twelve with the most GPU cycles over all their dispatches first (dispatch count when no cycle
+    counter was collected); derived ratios for the MFMA counters when present."""
     d = collections.defaultdict(lambda: collections.defaultdict(list))
     for name, counter, v in sqlite3.connect(db).execute("select kernel_name, counter_name, value from counters_collection"):
         k = name.split("(")[0].replace("void ", "")
@@ -79,7 +80,11 @@ def counters(db, cmd, title, match=""):
             d[k][counter].append(v)
     out = [f"# {title}", "", "Command (from the repository root, one MI355X):", "", f"    {cmd}", "",
            "Per-dispatch averages (counters summed over the device's units by rocprofv3).", ""]
-    for k, cs in sorted(d.items(), key=lambda kv: -max(len(v) for v in kv[1].values()))[:12]:
+    def weight(cs):
+        v = cs.get("GRBM_GUI_ACTIVE")
+        return sum(v) if v else max(len(x) for x in cs.values())
+
+    for k, cs in sorted(d.items(), key=lambda kv: -weight(kv[1]))[:12]:
         n = max(len(v) for v in cs.values())
         avg = {c: sum(v) / len(v) for c, v in cs.items()}
         out.append(f"## `{k}` ({n} dispatches)")

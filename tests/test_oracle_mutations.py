@@ -198,3 +198,42 @@ def test_ovo_zero_decision_voting_for_first_class_is_caught(monkeypatch):
 
     monkeypatch.setattr(osp, "ovo_vote", wrong)
     assert pins.ovo_vote_mismatches() > 0
+
+
+def _shared_fails(**kw):
+    mism, _ = pins.shared_replay(**kw)
+    return mism > 0
+
+
+def test_shared_score_from_first_problem_only_is_caught(monkeypatch):
+    monkeypatch.setattr(osp, "_shared_total", lambda dls: dls[0])
+    assert _shared_fails(steps=6)
+
+
+def test_shared_score_as_maximum_is_caught(monkeypatch):
+    monkeypatch.setattr(osp, "_shared_total", lambda dls: max(dls))
+    assert _shared_fails(steps=6)
+
+
+def test_shared_columns_with_one_gamma_are_caught(monkeypatch):
+    def wrong(X, c, gamma):
+        k = oracle.rbf_block(X, X[c:c + 1], gamma[0])[:, 0]
+        return [k for _ in gamma]
+
+    monkeypatch.setattr(osp, "_candidate_columns", wrong)
+    assert _shared_fails(steps=6)
+
+
+def test_shared_coefficient_of_first_problem_for_all_is_caught(monkeypatch):
+    real = osp.score_candidate
+    first = {}
+
+    def wrong(a, b, lam, o_c):
+        # the first problem's coefficient (recognised by its lambda) is handed to every problem of the step
+        s, dl = real(a, b, lam, o_c)
+        if lam == 0.5:
+            first["s"] = s
+        return first.get("s", s), dl
+
+    monkeypatch.setattr(osp, "score_candidate", wrong)
+    assert _shared_fails(n=36, steps=12, seed=731, growth=1.0)

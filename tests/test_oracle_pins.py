@@ -688,3 +688,104 @@ def ovo_subset_mismatches():
 
 def test_ovo_pairs_train_on_their_rows():
     assert ovo_subset_mismatches() == 0
+
+
+# ----------------------------------------------------------------------------- shared basis for a batch of problems
+def shared_single_mismatches():
+    """One problem, and two identical copies of it: the shared growth is the single-problem growth (same basis,
+    same coefficients; two equal decreases add up exactly to twice one, so the order of the sums is unchanged)."""
+    X, y = _tiny(60, 3, 720)
+    a = osp.train(X, y, 2.0, 0.5, 12, seed=3, kappa=6)
+    bad = 0
+    for Y in (y[None], np.stack([y, y])):
+        b = osp.train_shared(X, Y, 2.0, 0.5, 12, seed=3, kappa=6)
+        bad += int(not np.array_equal(a.J, b.J))
+        bad += sum(int(not np.array_equal(a.beta, row)) for row in b.beta)
+        bad += sum(int(F != a.F) for F in b.F)
+    return bad
+
+
+def _shared_tiny(n, seed):
+    r = np.random.default_rng(seed)
+    X = r.standard_normal((n, 3))
+    Y = np.stack([np.where(X[:, 0] + 0.3 * r.standard_normal(n) > 0, 1.0, -1.0),
+                  np.where(X[:, 1] - 0.5 * X[:, 2] > 0.2, 1.0, -1.0),
+                  np.where(X[:, 0] * X[:, 1] > 0, 1.0, -1.0)])
+    return X, Y, np.array([2.0, 0.5, 8.0]), np.array([0.5, 0.5, 1.5])
+
+
+def shared_replay(n=40, steps=8, seed=725, growth=0.25):
+    """Brute-force replay of the shared growth of three problems (own labels, C and gamma): each drawn candidate is
+    appended to every problem, each problem's full objective is minimised over its new coefficient by golden
+    section, and the candidate with the largest sum of the problems' decreases must be the oracle's pick; the
+    winner enters every problem with that problem's coefficient, and every problem is re-optimised by Newton after
+    the stage (growth 0.25: one addition per stage here; growth 1: stages of 1, 1, 2, 4, ..., whose later picks
+    depend on the coefficients of the earlier ones). Draws block J as it stood at the stage start; a drawn row
+    already in J is skipped. Returns (mismatches, steps at which the problems' own best candidates differ)."""
+    X, Y, C, gamma = _shared_tiny(n, seed)
+    lam = 1.0 / C
+    res = osp.train_shared(X, Y, C, gamma, J_max=steps, seed=3, kappa=6, growth=growth)
+    groups = _dup_groups(X)
+    J, betas = [], [np.zeros(0) for _ in range(3)]
+    mism = disagree = 0
+    t = 0
+    while len(J) < steps:
+        cs = min(steps - len(J), max(1, int(math.floor(growth * len(J)))))
+        frozen = {groups[j] for j in J}
+        for q in range(cs):
+            cands = orng.draw_candidates(3, t + q, n, 6, lambda i: groups[i] in frozen)
+            best, own = None, [None] * 3
+            for c in cands:
+                if groups[c] in {groups[j] for j in J}:
+                    continue
+                Jc = J + [c]
+                total, ss = 0.0, []
+                for p in range(3):
+                    K = oracle.rbf_block(X, X[Jc], gamma[p])
+
+                    def f(s):
+                        return osp.objective(K, K[Jc], Y[p], np.append(betas[p], s), lam[p])
+
+                    R = 1.0
+                    while f(R) < f(R / 2) or f(-R) < f(-R / 2):
+                        R *= 2
+                    grid = np.linspace(-R, R, 2001)
+                    k = int(np.argmin([f(v) for v in grid]))
+                    s = _golden_section(f, grid[max(k - 1, 0)], grid[min(k + 1, 2000)])
+                    dec = f(0.0) - f(s)
+                    total += dec
+                    ss.append(s)
+                    if own[p] is None or dec > own[p][0] + 1e-12:
+                        own[p] = (dec, c)
+                if best is None or total > best[0] + 1e-12 or (abs(total - best[0]) <= 1e-12 and c < best[1]):
+                    best = (total, c, ss)
+            disagree += int(len({o[1] for o in own}) > 1)
+            k = len(J)
+            if k >= len(res.J) or best[1] != res.J[k]:
+                mism += 1
+            J.append(best[1])
+            for p in range(3):
+                betas[p] = np.append(betas[p], best[2][p])
+        for p in range(3):
+            K = oracle.rbf_block(X, X[J], gamma[p])
+            betas[p], _ = osp.newton_solve(K, K[J], Y[p], lam[p], betas[p])
+        t += cs
+    for p in range(3):
+        mism += int(not np.allclose(betas[p], res.beta[p], rtol=1e-8, atol=1e-10))
+    return mism, disagree
+
+
+def test_shared_basis_single_problem_is_plain_training():
+    assert shared_single_mismatches() == 0
+
+
+def test_shared_basis_matches_bruteforce_replay():
+    mism, disagree = shared_replay()
+    assert disagree >= 2  # the problems' own best candidates differ: the sum decides
+    assert mism == 0
+
+
+def test_shared_basis_multi_addition_stages_match_bruteforce_replay():
+    mism, disagree = shared_replay(n=36, steps=12, seed=731, growth=1.0)
+    assert disagree >= 2
+    assert mism == 0
