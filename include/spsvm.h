@@ -189,6 +189,26 @@ spsvm_status spsvm_train_batch(const void* X, spsvm_dtype xdt, int64_t n, int64_
                                const spsvm_options* opt, void* workspace, size_t ws_bytes, void* stream,
                                spsvm_model** out);
 
+/* Greedy growth of one basis shared by P problems on the same rows (the selection of section 4, "Sparse primal
+ * optimization", applied to a one-vs-rest x (C, gamma) batch), each problem re-optimised by Newton after every
+ * stage. Every step draws one candidate set as spsvm_train does (same stream and rules); each problem scores every
+ * candidate exactly (the decrease of its f_p = F_p / C_p when only the new coefficient is optimised, with its own
+ * labels, C and gamma), and the candidate with the largest sum of the problems' scores (added in problem order)
+ * joins the basis of every problem, each with its own one-dimensional optimum as the starting coefficient.
+ *  Y: device, P x n labels (+1 / -1). C, gamma: host, P values each, finite and > 0. J_max: basis size to reach,
+ *  1 .. number of distinct rows. opt: as for spsvm_train; the offset (bias) and the stopping rule (eps_stop) are
+ *  not available here (SPSVM_E_INVALID_ARG). out: host array of P model pointers, all on the same basis; on
+ *  failure every entry is NULL. Other arguments as for spsvm_train. */
+spsvm_status spsvm_train_shared(const void* X, spsvm_dtype xdt, int64_t n, int64_t d, int64_t P, const float* Y,
+                                const double* C, const double* gamma, int64_t J_max, const spsvm_options* opt,
+                                void* workspace, size_t ws_bytes, void* stream, spsvm_model** out);
+
+/* Bytes of device workspace spsvm_train_shared needs: per distinct value of gamma (host, P values) an n x J_max
+ * kernel block, its K_JJ and a candidate block; per problem its outputs, coefficients and candidate-scoring state;
+ * the Newton state of min(P, 64) problems solved in lockstep. */
+spsvm_status spsvm_train_shared_workspace_bytes(int64_t n, int64_t d, int64_t P, const double* gamma, int64_t J_max,
+                                                spsvm_dtype xdt, const spsvm_options* opt, size_t* bytes);
+
 /* Feature matrices as compressed sparse rows (CSR), for data whose dense form is mostly zeros (section 5: the dense
  * GPU implementation could not hold KDDCup99): row i holds the FP32 values values[indptr[i] .. indptr[i + 1]) at
  * the features indices[...], which must lie in [0, d) and increase strictly within the row. indptr: device, n + 1

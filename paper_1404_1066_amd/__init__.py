@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     train,
     train_fixed_basis,
     train_batch,
+    train_shared,
     train_ovo,
     train_csr,
     predict_csr,

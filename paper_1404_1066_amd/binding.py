@@ -28,6 +28,8 @@ EXPORTED = (
     "spsvm_train_fixed_basis",
     "spsvm_batch_workspace_bytes",
     "spsvm_train_batch",
+    "spsvm_train_shared_workspace_bytes",
+    "spsvm_train_shared",
     "spsvm_model_get",
     "spsvm_model_stats",
     "spsvm_model_bias",
@@ -140,6 +142,10 @@ def load(path: str = LIB_PATH):
     lib.spsvm_batch_workspace_bytes.argtypes = [I64, I64, I64, I64, ctypes.c_int, P(Options), P(ctypes.c_size_t)]
     lib.spsvm_train_batch.argtypes = [VP, ctypes.c_int, I64, I64, I64, VP, P(D), P(D), P(I64), I64, P(Options), VP,
                                       ctypes.c_size_t, VP, P(VP)]
+    lib.spsvm_train_shared_workspace_bytes.argtypes = [I64, I64, I64, P(D), I64, ctypes.c_int, P(Options),
+                                                       P(ctypes.c_size_t)]
+    lib.spsvm_train_shared.argtypes = [VP, ctypes.c_int, I64, I64, I64, VP, P(D), P(D), I64, P(Options), VP,
+                                       ctypes.c_size_t, VP, P(VP)]
     lib.spsvm_model_get.argtypes = [VP, P(I64), P(I64), P(D), P(D)]
     lib.spsvm_model_stats.argtypes = [VP, P(Stats)]
     lib.spsvm_model_bias.argtypes = [VP, P(D)]
@@ -168,7 +174,7 @@ def load(path: str = LIB_PATH):
     I32 = ctypes.c_int32
     lib.spsvm_score_candidates.argtypes = [VP, VP, I64, VP, ctypes.c_int, I64, P(D), I32, D, P(D), P(D), P(I32),
                                            P(I32), P(I32), VP, ctypes.c_size_t, VP]
-    for name in ("spsvm_train_csr_workspace_bytes", "spsvm_train_csr", "spsvm_predict_csr", "spsvm_ovo_workspace_bytes", "spsvm_train_ovo", "spsvm_predict_ovo_workspace_bytes",
+    for name in ("spsvm_train_shared_workspace_bytes", "spsvm_train_shared", "spsvm_train_csr_workspace_bytes", "spsvm_train_csr", "spsvm_predict_csr", "spsvm_ovo_workspace_bytes", "spsvm_train_ovo", "spsvm_predict_ovo_workspace_bytes",
                  "spsvm_predict_ovo", "spsvm_newton_solve_noalloc", "spsvm_score_candidates", "spsvm_score_workspace_bytes", "spsvm_candidate_draw", "spsvm_rbf_block", "spsvm_rbf_block_workspace_bytes", "spsvm_newton_solve_workspace_bytes", "spsvm_newton_solve",
                  "spsvm_train_workspace_bytes", "spsvm_fixed_workspace_bytes", "spsvm_train",
                  "spsvm_train_fixed_basis", "spsvm_batch_workspace_bytes", "spsvm_train_batch", "spsvm_model_get", "spsvm_model_stats", "spsvm_model_bias", "spsvm_predict"):
@@ -503,6 +509,32 @@ def predict_ovo(models, K: int, Xt: torch.Tensor, stream=None) -> torch.Tensor:
                                     ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), b.value,
                                     ctypes.c_void_p(_stream_ptr(stream))))
     return out
+
+
+def train_shared(X: torch.Tensor, Y: torch.Tensor, C, gamma, J_max: int, workspace=None, stream=None, **opts):
+    """Greedy growth of one basis shared by P problems (labels Y[p], C[p], gamma[p]); returns P models on it."""
+    import numpy as np
+
+    _need_gpu(X, "X")
+    _need_gpu(Y, "Y")
+    if Y.dtype != torch.float32 or Y.dim() != 2 or Y.shape[1] != X.shape[0]:
+        raise TypeError("Y must be a P x n float32 tensor")
+    n, d = X.shape
+    P = Y.shape[0]
+    Ch = np.ascontiguousarray(np.asarray(C, dtype=np.float64).reshape(P))
+    gh = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(P))
+    o = options(**opts)
+    nb = ctypes.c_size_t()
+    gp = gh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(load().spsvm_train_shared_workspace_bytes(n, d, P, gp, int(J_max), _dtype_code(X), ctypes.byref(o),
+                                                     ctypes.byref(nb)))
+    ws, nbytes = _workspace(nb.value, X.device, workspace)
+    outs = (ctypes.c_void_p * P)()
+    _check(load().spsvm_train_shared(ctypes.c_void_p(X.data_ptr()), _dtype_code(X), n, d, P,
+                                     ctypes.c_void_p(Y.data_ptr()), Ch.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     gp, int(J_max), ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), nbytes,
+                                     ctypes.c_void_p(_stream_ptr(stream)), outs))
+    return [Model(outs[p]) for p in range(P)]
 
 
 def train_batch(X: torch.Tensor, Y: torch.Tensor, C, gamma, J: Sequence[int], workspace=None, stream=None,

@@ -167,6 +167,37 @@ spsvm_status spsvm_train_batch(const void* X, spsvm_dtype xdt, int64_t n, int64_
   });
 }
 
+spsvm_status spsvm_train_shared_workspace_bytes(int64_t n, int64_t d, int64_t P, const double* gamma, int64_t J_max,
+                                                spsvm_dtype xdt, const spsvm_options* opt, size_t* bytes) {
+  return guarded([&] {
+    if (!bytes || !gamma) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bytes and gamma must not be NULL");
+    if (n < 1 || d < 1 || J_max < 1 || J_max > n || P < 1 || P > (1 << 20))
+      throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bad sizes");
+    if (xdt != SPSVM_DT_F32 && xdt != SPSVM_DT_F64) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "unknown dtype");
+    *bytes = spsvm::make_plan(n, d, J_max, resolve(opt), true, xdt == SPSVM_DT_F64, false, true, P, false,
+                              spsvm::distinct_gammas(gamma, P))
+                 .bytes;
+  });
+}
+
+spsvm_status spsvm_train_shared(const void* X, spsvm_dtype xdt, int64_t n, int64_t d, int64_t P, const float* Y,
+                                const double* C, const double* gamma, int64_t J_max, const spsvm_options* opt,
+                                void* workspace, size_t ws_bytes, void* stream, spsvm_model** out) {
+  if (out && P > 0 && P <= (1 << 20))
+    for (int64_t p = 0; p < P; ++p) out[p] = nullptr;
+  return guarded([&] {
+    using spsvm::Failure;
+    if (!out || !C || !gamma) throw Failure(SPSVM_E_INVALID_ARG, "out, C and gamma must be host arrays");
+    if (P < 1 || P > (1 << 20)) throw Failure(SPSVM_E_INVALID_ARG, "P must lie in [1, 2^20]");
+    const spsvm_options o = resolve(opt);
+    if (o.bias || o.eps_stop > 0.0)
+      throw Failure(SPSVM_E_INVALID_ARG, "the shared basis takes neither the offset nor the stopping rule");
+    for (int64_t p = 0; p < P; ++p) check_problem(X, xdt, Y, n, d, C[p], gamma[p], J_max);
+    spsvm::run_train_shared(X, xdt == SPSVM_DT_F64, n, d, P, Y, C, gamma, J_max, o, workspace, ws_bytes,
+                            as_stream(stream), out);
+  });
+}
+
 spsvm_status spsvm_train_csr_workspace_bytes(int64_t n, int64_t d, int64_t J_max, const spsvm_options* opt,
                                              size_t* bytes) {
   return guarded([&] {

@@ -143,9 +143,10 @@ void launch_score_init(const int32_t* cand, const double* o, const uint64_t* has
 // One scoring pass over the n rows for all active slots (candidate block Kc column-major, column stride ldc;
 // partial sums per workgroup), then one workgroup per
 // slot reduces them and advances the slot. Both kernels return at once when every slot is settled.
+// nodrop: no slot is dropped (every score is exact: the shared-basis selection sums them over problems).
 template <typename TK>
 void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, CandState* st,
-                       double* partial, int nblk, hipStream_t s);
+                       double* partial, int nblk, hipStream_t s, bool nodrop = false);
 // live (may be null): incremented once per slot that the pass scored (for the byte count of the passes).
 void launch_score_update(CandState* st, const double* partial, int nblk, double lam, int32_t* live, hipStream_t s);
 // launch_score_init followed by launch_score_update on the nblk records of a first pass that came with the
@@ -163,6 +164,18 @@ void launch_select_append(const CandState* st, const uint64_t* hash, uint64_t* s
                           double* beta, int32_t* m_dev, Selection* sel, int32_t* incomplete, int fused0, int off,
                           bool write_col, hipStream_t s);
 int score_blocks(int64_t n);
+// One basis shared by P problems: argmax over the slots of the sum of the problems' scores (problem p's slot states
+// at st0 + p * stride bytes), appended to J / J32 like launch_select_append; then per problem its coefficient and
+// o += s k (launch_shared_append), and per gamma the winner's column into its K_XJ (launch_shared_column).
+void launch_shared_select(const CandState* st0, int64_t stride, int P, const uint64_t* hash, uint64_t* stage_hash,
+                          int q, int64_t* J, int32_t* J32, int32_t* m_dev, Selection* sel, int32_t* incomplete,
+                          hipStream_t s);
+template <typename TK>
+void launch_shared_append(const Selection* sel, const CandState* st, const TK* Kc, int64_t ldc, int64_t n, double* o,
+                          double* beta, hipStream_t s);
+template <typename TK>
+void launch_shared_column(const Selection* sel, const TK* Kc, int64_t ldc, int64_t n, TK* KXJ, int64_t ldk,
+                          hipStream_t s);
 
 // ----------------------------------------------------------------------------------------- newton.hip
 template <typename TK>

@@ -256,7 +256,7 @@ __global__ __launch_bounds__(64 * kScoreWaves, 5) void k_score_pass(const TK* __
                                                                   int32_t* __restrict__ drop,
                                                                   int32_t* __restrict__ wcnt,
                                                                   double* __restrict__ wrows,
-                                                                  double* __restrict__ partial) {
+                                                                  double* __restrict__ partial, int nodrop) {
   __shared__ double sh[kScoreWaves][4][kCandSlots];
   __shared__ double red[4][kCandSlots];
   __shared__ int act[kCandSlots];
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(64 * kScoreWaves, 5) void k_score_pass(const TK* __
   const int status = st[lane].status;
   double best = status == 1 ? st[lane].score : (status == 0 ? st[lane].lb : -__builtin_huge_val());
   for (int off = 32; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off, kWave));
-  const bool dropped = status == 0 && st[lane].ub < best - kDropMargin * fabs(best);
+  const bool dropped = !nodrop && status == 0 && st[lane].ub < best - kDropMargin * fabs(best);
   if (blockIdx.x == 0 && q == 0) drop[lane] = dropped ? 1 : 0;
   const bool live = status == 0 && !dropped;
   const unsigned long long mask = __ballot(live);
@@ -494,10 +494,10 @@ int score_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>
 
 template <typename TK>
 void launch_score_pass(const TK* Kc, int64_t ldc, const float* y, const double* o, int64_t n, CandState* st,
-                       double* partial, int nblk, hipStream_t s) {
+                       double* partial, int nblk, hipStream_t s, bool nodrop) {
   const int64_t rows = round_up(ceil_div(n, nblk), kScoreWaves);
   hipLaunchKernelGGL((k_score_pass<TK>), dim3(nblk), dim3(64 * kScoreWaves), 0, s, Kc, ldc, y, o, n, rows, st,
-                     cand_drop_flags(st), cand_win_count(st), cand_win_rows(st), partial);
+                     cand_drop_flags(st), cand_win_count(st), cand_win_rows(st), partial, nodrop ? 1 : 0);
   SPSVM_LAUNCHED();
 }
 
@@ -683,10 +683,137 @@ void launch_select_append(const CandState* st, const uint64_t* hash, uint64_t* s
   SPSVM_LAUNCHED();
 }
 
+// ------------------------------------------------------------------ one basis shared by a batch of problems
+// Argmax over the slots of the sum of P problems' exact scores (problem p's slot states at st0 + p * stride bytes;
+// every problem scored the same candidates, no slot dropped). A slot counts only when every problem finished it;
+// the sum runs in problem order; the largest sum wins, the lower row on ties. The winner's row goes to J[pos] and
+// J32[pos], its hash to the stage list; the pending / incomplete protocol is that of k_select_append.
+__global__ __launch_bounds__(kCandSlots) void k_shared_select(const char* __restrict__ st0, int64_t stride, int P,
+                                                              const uint64_t* __restrict__ hash,
+                                                              uint64_t* __restrict__ stage_hash, int q,
+                                                              int64_t* __restrict__ J, int32_t* __restrict__ J32,
+                                                              int32_t* __restrict__ m_dev,
+                                                              Selection* __restrict__ sel,
+                                                              int32_t* __restrict__ incomplete) {
+  const int c = threadIdx.x;
+  const bool after_fail = incomplete[0] != 0;
+  const int idx = reinterpret_cast<const CandState*>(st0)[c].idx;
+  bool all_done = true, any_active = false;
+  double total = 0.0;
+  int mp = 0, work = 0;
+  for (int p = 0; p < P; ++p) {
+    const CandState& s = reinterpret_cast<const CandState*>(st0 + (int64_t)p * stride)[c];
+    all_done = all_done && s.status == 1;
+    any_active = any_active || s.status == 0;
+    total += s.status == 1 ? s.score : 0.0;
+    mp = max(mp, s.passes);
+    work += s.passes;
+  }
+  const int pending = __any(any_active);
+  const bool ok = !pending && !after_fail && all_done && idx >= 0 && !(total != total);
+  double best = ok ? total : -__builtin_huge_val();
+  int bidx = ok ? idx : 0x7fffffff;
+  int bslot = c;
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, kWave);
+    const int oi = __shfl_xor(bidx, off, kWave);
+    const int os = __shfl_xor(bslot, off, kWave);
+    if (ob > best || (ob == best && oi < bidx)) {
+      best = ob;
+      bidx = oi;
+      bslot = os;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    mp = max(mp, __shfl_xor(mp, off, kWave));
+    work += __shfl_xor(work, off, kWave);
+  }
+  if (c == 0) {
+    Selection r;
+    r.valid = bidx != 0x7fffffff;
+    r.slot = bslot;
+    r.idx = bidx;
+    r.score = best;
+    r.s = 0.0;  // per problem: the slot's point in that problem's state
+    r.pos = m_dev[q & 1];
+    if (pending && !after_fail) {
+      incomplete[0] = 1;
+      incomplete[4] = q;
+    }
+    if (r.valid) {
+      J[r.pos] = bidx;
+      J32[r.pos] = bidx;
+      stage_hash[q] = hash[bidx];
+    }
+    m_dev[(q + 1) & 1] = r.pos + (r.valid ? 1 : 0);
+    *sel = r;
+    atomicMax(&incomplete[1], mp);  // largest number of passes any slot of any problem needed in this stage
+    atomicAdd(&incomplete[2], work);
+  }
+}
+
+void launch_shared_select(const CandState* st0, int64_t stride, int P, const uint64_t* hash, uint64_t* stage_hash,
+                          int q, int64_t* J, int32_t* J32, int32_t* m_dev, Selection* sel, int32_t* incomplete,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_shared_select, dim3(1), dim3(kCandSlots), 0, s, (const char*)st0, stride, P, hash, stage_hash,
+                     q, J, J32, m_dev, sel, incomplete);
+  SPSVM_LAUNCHED();
+}
+
+// One problem's append of the shared winner: its coefficient (the problem's one-dimensional optimum, the point
+// of the winning slot in its state) to beta[pos], and o += s k_winner.
+template <typename TK>
+__global__ __launch_bounds__(256) void k_shared_append(const Selection* __restrict__ sel,
+                                                       const CandState* __restrict__ st,
+                                                       const TK* __restrict__ Kc, int64_t ldc, int64_t n,
+                                                       double* __restrict__ o, double* __restrict__ beta) {
+  const Selection r = *sel;
+  if (!r.valid) return;
+  const double s = st[r.slot].s;
+  if (blockIdx.x == 0 && threadIdx.x == 0) beta[r.pos] = s;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    o[i] += s * (double)Kc[(int64_t)r.slot * ldc + i];
+}
+
+// The winner's column of one gamma's candidate block into that gamma's K_XJ (column pos).
+template <typename TK>
+__global__ __launch_bounds__(256) void k_shared_column(const Selection* __restrict__ sel, const TK* __restrict__ Kc,
+                                                       int64_t ldc, int64_t n, TK* __restrict__ KXJ, int64_t ldk) {
+  const Selection r = *sel;
+  if (!r.valid) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    KXJ[i * ldk + r.pos] = Kc[(int64_t)r.slot * ldc + i];
+}
+
+template <typename TK>
+void launch_shared_append(const Selection* sel, const CandState* st, const TK* Kc, int64_t ldc, int64_t n, double* o,
+                          double* beta, hipStream_t s) {
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 2048));
+  hipLaunchKernelGGL((k_shared_append<TK>), dim3((unsigned)blocks), dim3(256), 0, s, sel, st, Kc, ldc, n, o, beta);
+  SPSVM_LAUNCHED();
+}
+
+template <typename TK>
+void launch_shared_column(const Selection* sel, const TK* Kc, int64_t ldc, int64_t n, TK* KXJ, int64_t ldk,
+                          hipStream_t s) {
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 2048));
+  hipLaunchKernelGGL((k_shared_column<TK>), dim3((unsigned)blocks), dim3(256), 0, s, sel, Kc, ldc, n, KXJ, ldk);
+  SPSVM_LAUNCHED();
+}
+
+template void launch_shared_append<float>(const Selection*, const CandState*, const float*, int64_t, int64_t, double*,
+                                          double*, hipStream_t);
+template void launch_shared_append<double>(const Selection*, const CandState*, const double*, int64_t, int64_t,
+                                           double*, double*, hipStream_t);
+template void launch_shared_column<float>(const Selection*, const float*, int64_t, int64_t, float*, int64_t,
+                                          hipStream_t);
+template void launch_shared_column<double>(const Selection*, const double*, int64_t, int64_t, double*, int64_t,
+                                           hipStream_t);
+
 template void launch_score_pass<float>(const float*, int64_t, const float*, const double*, int64_t, CandState*,
-                                       double*, int, hipStream_t);
+                                       double*, int, hipStream_t, bool);
 template void launch_score_pass<double>(const double*, int64_t, const float*, const double*, int64_t, CandState*,
-                                        double*, int, hipStream_t);
+                                        double*, int, hipStream_t, bool);
 template void launch_select_append<float>(const CandState*, const uint64_t*, uint64_t*, int, const float*, int64_t,
                                           int64_t, double*, float*, int64_t, int64_t*, int32_t*, double*, int32_t*,
                                           Selection*, int32_t*, int, int, bool, hipStream_t);

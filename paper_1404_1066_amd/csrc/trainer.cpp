@@ -61,7 +61,7 @@ int64_t stage_size(int64_t J, int64_t J_max, double growth, int64_t cap) {
 
 // ------------------------------------------------------------------------------------------ workspace
 Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection, bool x_double,
-               bool x_aligned, bool batch, int64_t problems, bool csr) {
+               bool x_aligned, bool batch, int64_t problems, bool csr, int shared_gammas) {
   Plan p;
   p.csr = csr;
   const int64_t xe = x_double ? 8 : 4;
@@ -110,9 +110,24 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.iota = take(J_max * 4);
   p.incomplete = take(32);  // [0] a step did not settle, [1] most passes needed, [2] working passes, [3] slot-passes, [4] first step to redo
   p.Xp = take(p.pad_x ? (size_t)n * p.ldx * xe : 0);
-  p.D = take(batch ? (size_t)n * p.ldk * tk : 0);
-  p.DJJ = take(batch ? (size_t)J_max * p.ldh * 8 : 0);
-  p.G = take(batch ? (size_t)Ms * p.ldh * 8 : 0);
+  const bool fixed_batch = batch && shared_gammas == 0;  // the distances and K^T K of a given shared basis
+  p.D = take(fixed_batch ? (size_t)n * p.ldk * tk : 0);
+  p.DJJ = take(fixed_batch ? (size_t)J_max * p.ldh * 8 : 0);
+  p.G = take(fixed_batch ? (size_t)Ms * p.ldh * 8 : 0);
+  if (shared_gammas > 0) {
+    p.shared_gammas = shared_gammas;
+    p.problems = problems;
+    auto arr = [&](size_t each, int64_t count, size_t* stride) {
+      *stride = (size_t)round_up((int64_t)std::max<size_t>(each, 1), 256);
+      return take(*stride * (size_t)std::max<int64_t>(count, 1));
+    };
+    p.sh_K = arr((size_t)n * p.ldk * tk, shared_gammas - 1, &p.sh_K_stride);
+    p.sh_KJJ = arr((size_t)Ms * p.ldh * 8, shared_gammas - 1, &p.sh_KJJ_stride);
+    p.sh_Kc = arr((size_t)round_up(n, 4) * kCandSlots * tk, shared_gammas - 1, &p.sh_Kc_stride);
+    p.sh_o = arr((size_t)n * 8, problems, &p.sh_o_stride);
+    p.sh_beta = arr((size_t)Ms * 8, problems, &p.sh_beta_stride);
+    p.sh_cst = arr(kCandStateBytes, problems, &p.sh_cst_stride);
+  }
   const bool mixed = opt.precision == SPSVM_MIXED;
   p.ldb = split_ld(d);
   p.Xhi = take(mixed ? (size_t)n * p.ldb * 2 : 0);
@@ -1156,6 +1171,179 @@ struct Impl {
     }
   }
 
+  // ------------------------------------------------------------- batched problems, one greedy basis for all
+  // The selection of section 4 for P problems on the same rows at once. Each step draws one candidate set (as for
+  // one problem); every problem scores every candidate exactly with its own kernel column (one candidate block per
+  // distinct gamma), labels, C and outputs, and no candidate is dropped (one that cannot win a problem may win the
+  // sum); the largest sum of the problems' decreases wins (lower row on ties) and enters every problem with that
+  // problem's one-dimensional optimum. After each stage every problem is re-optimised by Newton, the problems of
+  // one gamma in lockstep on that gamma's kernel block, each from a freshly formed H.
+  int shared(int64_t P, const float* Y, const double* Cs, const double* gs, spsvm_model** outs) {
+    std::vector<double> gam;
+    std::vector<int> gof(P);
+    for (int64_t q = 0; q < P; ++q) {
+      int g = 0;
+      while (g < (int)gam.size() && gam[g] != gs[q]) ++g;
+      if (g == (int)gam.size()) gam.push_back(gs[q]);
+      gof[q] = g;
+    }
+    const int G = (int)gam.size();
+    if (G != p.shared_gammas || P != p.problems) throw Failure(SPSVM_E_INVALID_ARG, "shared basis: plan mismatch");
+    auto Kg = [&](int g) { return g == 0 ? KXJ : at<TK>(p.sh_K + (size_t)(g - 1) * p.sh_K_stride); };
+    auto KJJg = [&](int g) { return g == 0 ? KJJ : at<double>(p.sh_KJJ + (size_t)(g - 1) * p.sh_KJJ_stride); };
+    auto Kcg = [&](int g) { return g == 0 ? Kc : at<TK>(p.sh_Kc + (size_t)(g - 1) * p.sh_Kc_stride); };
+    auto op = [&](int64_t q) { return at<double>(p.sh_o + (size_t)q * p.sh_o_stride); };
+    auto bp = [&](int64_t q) { return at<double>(p.sh_beta + (size_t)q * p.sh_beta_stride); };
+    auto cp = [&](int64_t q) { return at<CandState>(p.sh_cst + (size_t)q * p.sh_cst_stride); };
+    for (int64_t q = 0; q < P; ++q) {
+      SPSVM_HIP(hipMemsetAsync(op(q), 0, n * 8, st));
+      SPSVM_HIP(hipMemsetAsync(bp(q), 0, J_max * 8, st));
+    }
+    SPSVM_HIP(hipMemsetAsync(m_dev, 0, 8, st));
+    std::vector<spsvm_stats> pstats(P);
+    int m = 0;
+    int64_t t = 0;
+    std::vector<uint64_t> blocked;
+    std::vector<int32_t> table((size_t)opt.chunk_cap * kCandSlots);
+    const int nblk = score_blocks(n);
+    const int64_t ldc = round_up(n, 4);
+    int first_rounds = 4;
+    while (m < J_max) {
+      const auto t0 = clk::now();
+      const int cs = (int)stage_size(m, J_max, opt.growth, opt.chunk_cap);
+      for (int q = 0; q < cs; ++q) draw_step(opt.seed, t + q, n, opt.kappa, hash_host, blocked, &table[(size_t)q * kCandSlots]);
+      int32_t* tp = (int32_t*)((char*)pin.p + kPinnedScalars);
+      std::memcpy(tp, table.data(), (size_t)cs * kCandSlots * 4);
+      SPSVM_HIP(hipMemcpyAsync(cand_table, tp, (size_t)cs * kCandSlots * 4, hipMemcpyHostToDevice, st));
+      // attempts and resumption as in the single-problem selection: a step whose slots did not all settle in any
+      // problem selects nothing, nor do the later steps of the attempt, and the stage resumes from it
+      int qstart = 0, m_q = m;
+      for (int attempt = 0;; ++attempt) {
+        const int rounds = attempt == 0   ? first_rounds
+                           : attempt == 1 ? std::min(64, first_rounds + 2)
+                           : attempt == 2 ? std::min(64, std::max(12, 2 * first_rounds + 4))
+                                          : 64;
+        {
+          int32_t* mh = (int32_t*)((char*)pin.p + 8192);
+          *mh = m_q;
+          SPSVM_HIP(hipMemcpyAsync(m_dev + (qstart & 1), mh, 4, hipMemcpyHostToDevice, st));
+        }
+        if (attempt > 0) stats.stage_redos += 1;
+        SPSVM_HIP(hipMemsetAsync(incomplete, 0, 32, st));
+        for (int q = qstart; q < cs; ++q) {
+          const int32_t* cq = cand_table + (size_t)q * kCandSlots;
+          for (int g = 0; g < G; ++g) {
+            gamma = gam[g];
+            prof.timed(kProfKblock, 2.0 * n * kCandSlots * d, [&] { kblock(cq, kCandSlots, Kcg(g), ldc, Score0{}, true); },
+                       kblock_issued(kCandSlots));
+          }
+          for (int64_t pq = 0; pq < P; ++pq) {
+            const float* yq = Y + pq * n;
+            launch_score_init(cq, op(pq), hash, stage_hash, q, cp(pq), sc, nullptr, st);
+            for (int r = 0; r < rounds; ++r) {
+              prof.timed(kProfScore, (double)n * (opt.kappa * sizeof(TK) + 12.0),
+                         [&] { launch_score_pass<TK>(Kcg(gof[pq]), ldc, yq, op(pq), n, cp(pq), score_part, nblk, st, true); });
+              launch_score_update(cp(pq), score_part, nblk, 1.0 / Cs[pq], incomplete + 3, st);
+            }
+          }
+          stats.score_passes += (int64_t)rounds * P;
+          launch_shared_select(cp(0), (int64_t)p.sh_cst_stride, (int)P, hash, stage_hash, q, J, J32, m_dev, sel,
+                               incomplete, st);
+          for (int64_t pq = 0; pq < P; ++pq)
+            launch_shared_append<TK>(sel, cp(pq), Kcg(gof[pq]), ldc, n, op(pq), bp(pq), st);
+          for (int g = 0; g < G; ++g) launch_shared_column<TK>(sel, Kcg(g), ldc, n, Kg(g), p.ldk, st);
+        }
+        int32_t flags2[8];
+        SPSVM_HIP(hipMemcpyAsync(pin.p, incomplete, 32, hipMemcpyDeviceToHost, st));
+        sync();
+        std::memcpy(flags2, pin.p, 32);
+        first_rounds = std::min(64, std::max(2, flags2[1] + 1));
+        if (flags2[0] == 0 || rounds >= 64) break;
+        qstart = flags2[4];
+        m_q = read(m_dev + (qstart & 1));
+      }
+      t += cs;
+      const int m_new = read(m_dev + (cs & 1));
+      stats.additions += m_new - m;
+      if (m_new > m) {
+        std::vector<int64_t> jn(m_new - m);
+        SPSVM_HIP(hipMemcpyAsync(jn.data(), J + m, (m_new - m) * 8, hipMemcpyDeviceToHost, st));
+        sync();
+        for (int64_t j : jn) blocked.push_back(hash_host[j]);
+        std::sort(blocked.begin(), blocked.end());
+      }
+      const auto t1 = clk::now();
+      stats.seconds_select += secs(t0, t1);
+      if (m_new == m) {
+        stats.stop_reason = 2;
+        break;
+      }
+      // basis rows in FP64 and each gamma's K_JJ
+      launch_gather_rows<TX, double>(X, d, J + m, m_new - m, XJ64 + (size_t)m * p.ldj, p.ldj, st);
+      launch_row_norms<double, double>(XJ64 + (size_t)m * p.ldj, m_new - m, d, p.ldj, xjnorm + m, st);
+      for (int g = 0; g < G; ++g)
+        launch_kblock<double, double>(XJ64, p.ldj, m_new, d, xjnorm, iota, m_new, KJJg(g), p.ldh, gam[g], st);
+      m = m_new;
+      // Newton for every problem, the problems of one gamma in lockstep
+      const int Q = (int)slots.size();
+      for (int g = 0; g < G; ++g) {
+        std::vector<int64_t> group;
+        for (int64_t q = 0; q < P; ++q)
+          if (gof[q] == g) group.push_back(q);
+        for (size_t c0 = 0; c0 < group.size(); c0 += Q) {
+          std::vector<int> ids;
+          for (size_t k = c0; k < group.size() && k < c0 + Q; ++k) {
+            const int64_t q = group[k];
+            Slot& S = slots[ids.size()];
+            S.y = Y + q * n;
+            S.C = Cs[q];
+            S.lam = 1.0 / Cs[q];
+            S.K = Kg(g);
+            S.KJJ = KJJg(g);
+            S.hb_valid = false;
+            S.stats = &pstats[q];
+            SPSVM_HIP(hipMemcpyAsync(S.beta, bp(q), m * 8, hipMemcpyDeviceToDevice, st));
+            ids.push_back((int)ids.size());
+          }
+          newton_slots(m, ids);
+          for (size_t k = 0; k < ids.size(); ++k) {
+            const int64_t q = group[c0 + k];
+            Slot& S = slots[ids[k]];
+            SPSVM_HIP(hipMemcpyAsync(bp(q), S.beta, m * 8, hipMemcpyDeviceToDevice, st));
+            SPSVM_HIP(hipMemcpyAsync(op(q), S.o, n * 8, hipMemcpyDeviceToDevice, st));
+          }
+        }
+      }
+      sync();
+      stats.stages += 1;
+      stats.seconds_newton += secs(t1, clk::now());
+    }
+    // models: every problem on the shared basis, with its coefficients and outputs
+    for (int64_t q = 0; q < P; ++q) {
+      const int g = gof[q];
+      Slot& S = slots[0];
+      S.y = Y + q * n;
+      S.C = Cs[q];
+      S.lam = 1.0 / Cs[q];
+      S.K = Kg(g);
+      S.KJJ = KJJg(g);
+      gamma = gam[g];
+      spsvm_stats own = stats;  // the shared selection's counters, then this problem's Newton counters
+      own.newton_iters = pstats[q].newton_iters;
+      own.factorizations = pstats[q].factorizations;
+      own.incremental_factorizations = pstats[q].incremental_factorizations;
+      own.ls_passes = pstats[q].ls_passes;
+      own.iter_cap_hits = pstats[q].iter_cap_hits;
+      own.jitter_retries = pstats[q].jitter_retries;
+      S.own = own;
+      S.stats = &S.own;
+      SPSVM_HIP(hipMemcpyAsync(S.beta, bp(q), (size_t)std::max(m, 1) * 8, hipMemcpyDeviceToDevice, st));
+      SPSVM_HIP(hipMemcpyAsync(S.o, op(q), n * 8, hipMemcpyDeviceToDevice, st));
+      outs[q] = build_model(S, m, true);
+    }
+    return m;
+  }
+
   spsvm_model* build_model(int m) { return build_model(slots[0], m); }
 
   spsvm_model* build_model(Slot& S, int m, bool o_fresh = false) {
@@ -1353,6 +1541,54 @@ void run_train_batch(const void* X, bool x_double, int64_t n, int64_t d, int64_t
       batch_typed<float, double>((const float*)X, n, d, P, Y, C, gamma, J, m, opt, ws, plan, stream, out);
     else
       batch_typed<float, float>((const float*)X, n, d, P, Y, C, gamma, J, m, opt, ws, plan, stream, out);
+  }
+}
+
+int distinct_gammas(const double* gamma, int64_t P) {
+  std::vector<double> g;
+  for (int64_t q = 0; q < P; ++q)
+    if (std::find(g.begin(), g.end(), gamma[q]) == g.end()) g.push_back(gamma[q]);
+  return (int)g.size();
+}
+
+template <typename TX, typename TK>
+static void shared_typed(const TX* X, int64_t n, int64_t d, int64_t P, const float* Y, const double* C,
+                         const double* gamma, int64_t J_max, const spsvm_options& opt, void* ws, const Plan& plan,
+                         hipStream_t st, spsvm_model** out) {
+  Impl<TX, TK> im(X, Y, n, d, C[0], gamma[0], J_max, opt, ws, st, plan);
+  im.prepare_batch(Y, n * P);
+  try {
+    im.shared(P, Y, C, gamma, out);
+  } catch (...) {
+    for (int64_t p = 0; p < P; ++p) {
+      delete out[p];
+      out[p] = nullptr;
+    }
+    throw;
+  }
+}
+
+void run_train_shared(const void* X, bool x_double, int64_t n, int64_t d, int64_t P, const float* Y, const double* C,
+                      const double* gamma, int64_t J_max, const spsvm_options& opt, void* ws, size_t ws_bytes,
+                      hipStream_t stream, spsvm_model** out) {
+  const Plan plan = make_plan(n, d, J_max, opt, true, x_double, ((uintptr_t)X & 15u) == 0, true, P, false,
+                              distinct_gammas(gamma, P));
+  if (!ws || ((uintptr_t)ws & 255u)) throw Failure(SPSVM_E_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
+  if (ws_bytes < plan.bytes)
+    throw Failure(SPSVM_E_WORKSPACE, "workspace too small: need " + std::to_string(plan.bytes) + " bytes, got " +
+                                         std::to_string(ws_bytes));
+  for (int64_t p = 0; p < P; ++p) out[p] = nullptr;
+  const bool tk_double = opt.precision == SPSVM_F64;
+  if (x_double) {
+    if (tk_double)
+      shared_typed<double, double>((const double*)X, n, d, P, Y, C, gamma, J_max, opt, ws, plan, stream, out);
+    else
+      shared_typed<double, float>((const double*)X, n, d, P, Y, C, gamma, J_max, opt, ws, plan, stream, out);
+  } else {
+    if (tk_double)
+      shared_typed<float, double>((const float*)X, n, d, P, Y, C, gamma, J_max, opt, ws, plan, stream, out);
+    else
+      shared_typed<float, float>((const float*)X, n, d, P, Y, C, gamma, J_max, opt, ws, plan, stream, out);
   }
 }
 

@@ -57,10 +57,17 @@ struct Plan {
   SlotPlan slot;
   size_t slots_at = 0;
   int slots = 1;
+  // one basis shared by a batch (shared_gammas > 0): per distinct gamma g >= 1 its K_XJ, K_JJ and candidate block
+  // (gamma 0 uses KXJ, KJJ and Kc above), per problem its outputs o, coefficients and scoring slot states
+  int shared_gammas = 0;
+  int64_t problems = 1;
+  size_t sh_K = 0, sh_KJJ = 0, sh_Kc = 0, sh_o = 0, sh_beta = 0, sh_cst = 0;
+  size_t sh_K_stride = 0, sh_KJJ_stride = 0, sh_Kc_stride = 0, sh_o_stride = 0, sh_beta_stride = 0, sh_cst_stride = 0;
 };
 
 Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bool with_selection,
-               bool x_double, bool x_aligned, bool batch = false, int64_t problems = 1, bool csr = false);
+               bool x_double, bool x_aligned, bool batch = false, int64_t problems = 1, bool csr = false,
+               int shared_gammas = 0);
 
 // Feature matrix in compressed sparse rows (device arrays; FP32 values, features increasing within a row).
 struct CsrX {
@@ -84,6 +91,14 @@ spsvm_model* run_train(const void* X, bool x_double, const float* y, int64_t n, 
 void run_train_batch(const void* X, bool x_double, int64_t n, int64_t d, int64_t P, const float* Y, const double* C,
                      const double* gamma, const int64_t* J, int64_t m, const spsvm_options& opt, void* ws,
                      size_t ws_bytes, hipStream_t stream, spsvm_model** out);
+
+// Greedy growth of one basis (up to J_max rows) shared by P problems (labels Y + p n, C[p], gamma[p]), each
+// re-optimised after every stage; out receives P models on the same basis.
+void run_train_shared(const void* X, bool x_double, int64_t n, int64_t d, int64_t P, const float* Y, const double* C,
+                      const double* gamma, int64_t J_max, const spsvm_options& opt, void* ws, size_t ws_bytes,
+                      hipStream_t stream, spsvm_model** out);
+// Distinct values among gamma[0 .. P), in order of first appearance.
+int distinct_gammas(const double* gamma, int64_t P);
 
 void run_predict(const spsvm_model* model, const void* Xt, bool x_double, int64_t n_t, double* out,
                  hipStream_t stream);

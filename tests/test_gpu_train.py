@@ -566,3 +566,69 @@ def test_ovo_f32_pairs_reach_oracle_objective():
         b_or, F_or, _ = osp.solve_fixed_J(X[rows], y, C, gamma, local)
         Fo = osp.objective_at(X[rows], y, C, gamma, local, beta)
         assert abs(Fo - F_or) / F_or <= 1e-6
+
+
+# ------------------------------------------------------------------------------ one greedy basis for a batch
+def _shared_case(P=4, n_per=300, d=20):
+    X, cls = datagen.make_mnist_like(per_class=n_per, d=d, seed=31, classes=5)
+    Y = np.stack([np.where(cls == c, 1.0, -1.0) for c in range(P)])
+    C = np.array([1.0, 10.0, 1.0, 10.0, 3.0, 0.5])[:P]
+    gamma = np.array([0.1, 0.1, 0.3, 0.3, 0.1, 0.3])[:P]
+    return X.astype(np.float64), Y, C, gamma
+
+
+def test_shared_basis_identical_to_oracle_f64():
+    """Four one-vs-rest problems (two C, two gamma) grow one basis: the FP64 path picks the oracle's basis step for
+    step and reaches each problem's objective."""
+    X, Y, C, gamma = _shared_case()
+    ref = osp.train_shared(X, Y, C, gamma, 40, seed=2, kappa=20)
+    Xg = torch.tensor(X, device="cuda")
+    Yg = torch.tensor(Y, dtype=torch.float32, device="cuda")
+    models = lib.train_shared(Xg, Yg, C, gamma, 40, seed=2, kappa=20, precision="f64")
+    for p, md in enumerate(models):
+        J, beta, F = md.get()
+        assert J.tolist() == ref.J.tolist()
+        assert abs(F - ref.F[p]) <= 1e-9 * ref.F[p]
+        assert np.max(np.abs(beta - ref.beta[p])) <= 1e-6 * max(1.0, np.max(np.abs(ref.beta[p])))
+
+
+@pytest.mark.parametrize("prec", ["f32", "mixed"])
+def test_shared_basis_reaches_oracle_objective(prec):
+    """F32 and MIXED: every problem's coefficients reach the oracle's optimum at the shared basis the GPU chose (both
+    sides of 1e-6), and its decision values match the oracle's there."""
+    X, Y, C, gamma = _shared_case(P=6)
+    Xf = X.astype(np.float32)
+    Xg = torch.tensor(Xf, device="cuda")
+    Yg = torch.tensor(Y, dtype=torch.float32, device="cuda")
+    models = lib.train_shared(Xg, Yg, C, gamma, 60, seed=4, kappa=24, precision=prec)
+    J0 = models[0].get()[0]
+    Xt, _ = datagen.make_mnist_like(per_class=60, d=20, seed=32, classes=5)
+    for p, md in enumerate(models):
+        J, beta, F = md.get()
+        assert J.tolist() == J0.tolist() and len(J) == 60
+        X64 = Xf.astype(np.float64)
+        b_or, F_or, _ = osp.solve_fixed_J(X64, Y[p], C[p], gamma[p], J)
+        Fo = osp.objective_at(X64, Y[p], C[p], gamma[p], J, beta)
+        assert abs(Fo - F_or) / F_or <= 1e-6, (p, Fo, F_or)
+        dg = md.predict(torch.tensor(Xt, device="cuda")).cpu().numpy()
+        do = oracle.predict(X64[J], b_or, gamma[p], Xt.astype(np.float64))
+        assert _decision_err(dg, do) <= 1e-4
+
+
+def test_shared_basis_one_problem_is_plain_training():
+    X, Y, C, gamma = _shared_case(P=1)
+    Xg = torch.tensor(X, device="cuda")
+    Yg = torch.tensor(Y, dtype=torch.float32, device="cuda")
+    sh = lib.train_shared(Xg, Yg, C, gamma, 30, seed=7, kappa=16, precision="f64")[0].get()
+    one = lib.train(Xg, Yg[0].contiguous(), C[0], gamma[0], 30, seed=7, kappa=16, precision="f64").get()
+    assert sh[0].tolist() == one[0].tolist()
+    assert abs(sh[2] - one[2]) <= 1e-12 * one[2]
+
+
+def test_shared_basis_rejects_offset_and_stop_rule():
+    X, Y, C, gamma = _shared_case(P=2)
+    Xg = torch.tensor(X, device="cuda")
+    Yg = torch.tensor(Y, dtype=torch.float32, device="cuda")
+    for kw in ({"bias": 1}, {"eps_stop": 1e-3}):
+        with pytest.raises(lib.SpsvmError):
+            lib.train_shared(Xg, Yg, C, gamma, 10, **kw)
