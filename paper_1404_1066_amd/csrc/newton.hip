@@ -4,7 +4,7 @@
 //   grad f  = lambda K_JJ beta + K_I^T (o_I - y_I),     H = lambda K_JJ + K_I^T K_I,   I = {i : a_i > 0}.
 // K_JJ is kept as its own FP64 matrix (computed from the basis rows), so the regulariser stays positive
 // definite whatever precision the n x |J| block K_XJ is stored in.
-// Kernels: GEMV o = K_XJ x (one wave per row), violator compaction (wave ballot + block prefix sums),
+// Kernels: GEMV o = K_XJ x (one wave per 4 rows), violator compaction (wave ballot + block prefix sums),
 // gradient (GEMV^T over the compacted rows), the SYRK of H over the compacted rows with MFMA, and the
 // exact line search along d (bracketed semismooth Newton on the piecewise-linear derivative).
 // All reductions run in a fixed order, so results are bitwise reproducible.
@@ -14,35 +14,78 @@
 namespace spsvm {
 
 // ------------------------------------------------------------------------------------------------ GEMV
+// Each wave takes 4 consecutive rows; lane l reads the 4 values j = 4 l + 256 u .. + 3 of every row (one 16-byte
+// load per row for FP32, 32 bytes for FP64) and the matching 4 values of x once for all 4 rows, two chunks in flight.
+// Row rows start on 16-byte (FP32) / 32-byte (FP64) boundaries: ld is a multiple of 4 and K, x are aligned. A
+// lane's products are added in column order, then the wave's 64 partial sums by xor butterfly.
+template <typename TK>
+struct Vec4Of;
+template <>
+struct Vec4Of<float> {
+  typedef floatx4 T;
+};
+template <>
+struct Vec4Of<double> {
+  typedef doublex4 T;
+};
+
+constexpr int kGemvRows = 4;  // rows per wave
+
 template <typename TK>
 __global__ __launch_bounds__(256) void k_gemv(const TK* __restrict__ K, int64_t ldk, int64_t n, int m,
                                               const double* __restrict__ x, double* __restrict__ out) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
+  typedef typename Vec4Of<TK>::T V;
   const int lane = threadIdx.x & (kWave - 1);
-  if (row >= n) return;
-  const TK* k = K + row * ldk;
-  double s = 0.0;
-  int j = lane;
-  for (; j + 3 * kWave < m; j += 4 * kWave) {  // four loads in flight, summed in the same order
-    TK kv[4];
-    double xv[4];
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + threadIdx.x / kWave) * kGemvRows;
+  if (r0 >= n) return;
+  const TK* rp[kGemvRows];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      kv[u] = k[j + u * kWave];
-      xv[u] = x[j + u * kWave];
+  for (int r = 0; r < kGemvRows; ++r) rp[r] = K + (r0 + r < n ? r0 + r : r0) * ldk;
+  double s[kGemvRows] = {0.0, 0.0, 0.0, 0.0};
+  const int m4 = m & ~3;
+  auto add = [&](const doublex4& xv, const V* kv) {
+#pragma unroll
+    for (int r = 0; r < kGemvRows; ++r)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) s[r] += (double)kv[r][e] * xv[e];
+  };
+  int j = 4 * lane;
+  for (; j + 4 * kWave < m4; j += 8 * kWave) {  // two chunks of 256 columns: all loads first
+    const doublex4 x0 = *(const doublex4*)(x + j), x1 = *(const doublex4*)(x + j + 4 * kWave);
+    V k0[kGemvRows], k1[kGemvRows];
+#pragma unroll
+    for (int r = 0; r < kGemvRows; ++r) {
+      k0[r] = *(const V*)(rp[r] + j);
+      k1[r] = *(const V*)(rp[r] + j + 4 * kWave);
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) s += (double)kv[u] * xv[u];
+    add(x0, k0);
+    add(x1, k1);
   }
-  for (; j < m; j += kWave) s += (double)k[j] * x[j];
-  s = wave_sum(s);
-  if (lane == 0) out[row] = s;
+  for (; j < m4; j += 4 * kWave) {
+    const doublex4 x0 = *(const doublex4*)(x + j);
+    V k0[kGemvRows];
+#pragma unroll
+    for (int r = 0; r < kGemvRows; ++r) k0[r] = *(const V*)(rp[r] + j);
+    add(x0, k0);
+  }
+  if (lane < m - m4) {  // the last m % 4 columns, one per lane
+    const int c = m4 + lane;
+#pragma unroll
+    for (int r = 0; r < kGemvRows; ++r) s[r] += (double)rp[r][c] * x[c];
+  }
+#pragma unroll
+  for (int r = 0; r < kGemvRows; ++r) {
+    const double t = wave_sum(s[r]);
+    if (lane == 0 && r0 + r < n) out[r0 + r] = t;
+  }
 }
 
 template <typename TK>
 void launch_gemv(const TK* K, int64_t ldk, int64_t n, int m, const double* x, double* out, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((k_gemv<TK>), dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s, K, ldk, n, m, x, out);
+  if (ldk % 4 != 0 || ((uintptr_t)K & (4 * sizeof(TK) - 1)) || ((uintptr_t)x & 31u))
+    throw Failure(1, "GEMV: rows and x must be aligned to 4 values");
+  hipLaunchKernelGGL((k_gemv<TK>), dim3((unsigned)ceil_div(n, 4 * kGemvRows)), dim3(256), 0, s, K, ldk, n, m, x, out);
   SPSVM_LAUNCHED();
 }
 
