@@ -239,6 +239,18 @@ void launch_compact(const double* o, const float* y, int64_t n, const uint8_t* a
 }
 
 // -------------------------------------------------------------------------------------------- gradient
+// Lane value l of v (l uniform across the wave): v_readlane, no LDS traffic.
+__device__ __forceinline__ int lane_int(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double lane_double(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Partial sums of K_I^T (o_I - y_I) over a chunk of violator rows, one column per thread. The rows' indices and
+// coefficients o_i - y_i are loaded 64 at a time, one row per lane, and handed to the wave with v_readlane, so the
+// only per-row load is the 256 bytes of the wave's columns; eight rows' loads are in flight, summed in row order.
 template <typename TK>
 __global__ __launch_bounds__(256) void k_grad_partial(const TK* __restrict__ K, int64_t ldk, int m,
                                                       const int32_t* __restrict__ I,
@@ -249,33 +261,29 @@ __global__ __launch_bounds__(256) void k_grad_partial(const TK* __restrict__ K, 
   // gridDim.y chunks split it evenly
   const int n_sv = sc->n_sv;
   const int rows_per_chunk = n_sv > (int)gridDim.y ? (n_sv + (int)gridDim.y - 1) / (int)gridDim.y : 1;
+  const int lane = threadIdx.x & (kWave - 1);
   const int k = blockIdx.x * 256 + threadIdx.x;
   const int lo = blockIdx.y * rows_per_chunk;
   const int hi = lo + rows_per_chunk < n_sv ? lo + rows_per_chunk : n_sv;
-  if (k >= m) return;
+  if (blockIdx.x * 256 + (threadIdx.x & ~(kWave - 1)) >= m) return;  // whole wave past the last column
+  const int kc = k < m ? k : m - 1;  // lanes past the last column load a valid column and store nothing
   double acc = 0.0;
-  int r = lo;
-  for (; r + 8 <= hi; r += 8) {  // eight rows' loads in flight, summed in row order
-    int64_t iv[8];
+  for (int r = lo; r < hi; r += kWave) {
+    const int rr = r + lane;
+    const int iv = rr < hi ? I[rr] : 0;
+    const double cv = rr < hi ? o[iv] - (double)y[iv] : 0.0;
+    const int cnt = hi - r < kWave ? hi - r : kWave;
+    int u = 0;
+    for (; u + 8 <= cnt; u += 8) {
+      TK kv[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) iv[u] = I[r + u];
-    TK kv[8];
-    double ov[8];
-    float yv[8];
+      for (int e = 0; e < 8; ++e) kv[e] = K[(int64_t)lane_int(iv, u + e) * ldk + kc];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      kv[u] = K[iv[u] * ldk + k];
-      ov[u] = o[iv[u]];
-      yv[u] = y[iv[u]];
+      for (int e = 0; e < 8; ++e) acc += (double)kv[e] * lane_double(cv, u + e);
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc += (double)kv[u] * (ov[u] - (double)yv[u]);
+    for (; u < cnt; ++u) acc += (double)K[(int64_t)lane_int(iv, u) * ldk + kc] * lane_double(cv, u);
   }
-  for (; r < hi; ++r) {
-    const int64_t i = I[r];
-    acc += (double)K[i * ldk + k] * (o[i] - (double)y[i]);
-  }
-  partial[(int64_t)blockIdx.y * m + k] = acc;
+  if (k < m) partial[(int64_t)blockIdx.y * m + k] = acc;
 }
 
 // g = lambda v + sum of the chunk partials, with v = K_JJ beta. Each workgroup owns 64 columns; lane group j
