@@ -316,17 +316,7 @@ __global__ __launch_bounds__(64 * kScoreWaves, 5) void k_score_pass(const TK* __
       }
     };
     // chunks of U consecutive rows per lane (contiguous loads from the column), even rows summed apart from odd
-    int64_t i = lo + (int64_t)(q * R + r) * U;
-    for (; i + U - 1 < hi; i += step) {
-      float yv[U];
-      double ov[U];
-      TK kv[U];  // converted where used: a conversion here would wait for the load
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        yv[u] = y[i + u];
-        ov[u] = o[i + u];
-        kv[u] = kc[i + u];
-      }
+    auto chunk = [&](const float* yv, const double* ov, const TK* kv) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const double av = margin_gap(yv[u], ov[u]);
@@ -335,6 +325,38 @@ __global__ __launch_bounds__(64 * kScoreWaves, 5) void k_score_pass(const TK* __
           one(av, b, P2, Q2, V2, fl2);
         else
           one(av, b, P, Q, V, fl);
+      }
+    };
+    int64_t i = lo + (int64_t)(q * R + r) * U;
+    if (R == 1) {
+      // more than 32 live slots: every live lane of the wave takes the same rows, so y and o are read with
+      // scalar loads (the row offset made wave-uniform) and the vector loads carry candidate values only
+      int64_t iu = lo + (int64_t)__builtin_amdgcn_readfirstlane(q) * U;
+      for (; iu + U - 1 < hi; iu += step) {
+        float yv[U];
+        double ov[U];
+        TK kv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          yv[u] = y[iu + u];
+          ov[u] = o[iu + u];
+          kv[u] = kc[iu + u];
+        }
+        chunk(yv, ov, kv);
+      }
+      i = iu;
+    } else {
+      for (; i + U - 1 < hi; i += step) {
+        float yv[U];
+        double ov[U];
+        TK kv[U];  // converted where used: a conversion here would wait for the load
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          yv[u] = y[i + u];
+          ov[u] = o[i + u];
+          kv[u] = kc[i + u];
+        }
+        chunk(yv, ov, kv);
       }
     }
     for (; i < hi; ++i) one(margin_gap(y[i], o[i]), (double)y[i] * (double)kc[i], P, Q, V, fl);  // partial chunk
