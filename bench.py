@@ -410,10 +410,14 @@ def main():
             dg = models[0].predict(Xg[torch.tensor(rows, device="cuda")]).cpu().numpy()
             do = oracle.predict(p.X[J], beta, p.gamma, p.X[rows])
             derr = float(np.max(np.abs(dg - do) / np.maximum(1.0, np.abs(do))))
+            where = {"dense-2m": "test_dense_2m_rows_full_basis_reach_oracle_objective (the same rows at n = 100000, "
+                                 "|J| = 4000)",
+                     "onehot-500k": "test_onehot_200k_full_basis_mixed_reaches_oracle_objective (the same recipe at "
+                                    "n = 200000, |J| = 3000)"}.get(args.workload)
             out["parity"] = {
                 "kind": "sampled: the GPU model's decisions on 500 rows against the oracle's FP64 kernel at the same "
-                        "(J, beta); objective parity at this size is in tests/test_gpu_train.py::"
-                        "test_dense_2m_rows_full_basis_reach_oracle_objective (same rows at n = 100000, |J| = 4000)",
+                        "(J, beta)" + (f"; objective parity at this size is in tests/test_gpu_train.py::{where}"
+                                       if where else ""),
                 "decision_max_rel": derr, "decision_ok": bool(derr <= 1e-4), "m": int(len(J)),
                 "gpu_grad_norm": stats[0]["grad_norm"], "F_gpu_self": F}
 

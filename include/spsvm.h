@@ -84,6 +84,12 @@ typedef struct {
                               (fraction of rows with y_i o_i <= 0; 1 before the first stage) divided by the number
                               of vectors the stage added is below eps_stop (an unchanged or larger error stops it);
                               J_max stays an upper bound. 0 (default): grow J to J_max */
+  int32_t kxj_host;        /* 1: hold the n x |J| kernel block K_XJ in pinned host memory, which the call allocates
+                              and frees before it returns, instead of in the workspace: for n |J| beyond the GPU's
+                              memory (the method needs O(|J| n) memory, section 4). Every pass over K_XJ (outputs,
+                              gradient, Newton matrix, appended columns) then streams it over the host link; the
+                              kernels and results are those of 0. spsvm_train, spsvm_train_fixed_basis and
+                              spsvm_train_csr only. 0 (default): K_XJ in the workspace */
 } spsvm_options;
 
 typedef struct spsvm_model spsvm_model; /* opaque, owned by the library */

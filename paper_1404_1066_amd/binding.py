@@ -77,6 +77,7 @@ class Options(ctypes.Structure):
         ("refactor_frac", ctypes.c_double),
         ("bias", ctypes.c_int32),
         ("eps_stop", ctypes.c_double),
+        ("kxj_host", ctypes.c_int32),
     ]
 
 

@@ -53,6 +53,7 @@ spsvm_options resolve(const spsvm_options* opt) {
   if (o.bias != 0 && o.bias != 1) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "bias must be 0 or 1");
   if (!(o.eps_stop >= 0.0) || !std::isfinite(o.eps_stop))
     throw spsvm::Failure(SPSVM_E_INVALID_ARG, "eps_stop must be finite and >= 0");
+  if (o.kxj_host != 0 && o.kxj_host != 1) throw spsvm::Failure(SPSVM_E_INVALID_ARG, "kxj_host must be 0 or 1");
   if (o.precision != SPSVM_F64 && o.precision != SPSVM_F32 && o.precision != SPSVM_MIXED)
     throw spsvm::Failure(SPSVM_E_INVALID_ARG, "precision must be SPSVM_F64, SPSVM_F32 or SPSVM_MIXED");
   return o;
@@ -92,6 +93,7 @@ void spsvm_options_default(spsvm_options* o) {
   o->refactor_frac = 0.002;
   o->bias = 0;
   o->eps_stop = 0.0;
+  o->kxj_host = 0;
 }
 
 spsvm_status spsvm_train_workspace_bytes(int64_t n, int64_t d, int64_t J_max, spsvm_dtype xdt,
@@ -161,6 +163,7 @@ spsvm_status spsvm_train_batch(const void* X, spsvm_dtype xdt, int64_t n, int64_
     if (!out || !C || !gamma || !J) throw Failure(SPSVM_E_INVALID_ARG, "out, C, gamma and J must be host arrays");
     if (P < 1 || P > (1 << 20)) throw Failure(SPSVM_E_INVALID_ARG, "P must lie in [1, 2^20]");
     const spsvm_options o = resolve(opt);
+    if (o.kxj_host) throw Failure(SPSVM_E_INVALID_ARG, "kxj_host does not apply to batches");
     for (int64_t p = 0; p < P; ++p) check_problem(X, xdt, Y, n, d, C[p], gamma[p], m);
     spsvm::run_train_batch(X, xdt == SPSVM_DT_F64, n, d, P, Y, C, gamma, J, m, o, workspace, ws_bytes,
                            as_stream(stream), out);
@@ -190,8 +193,8 @@ spsvm_status spsvm_train_shared(const void* X, spsvm_dtype xdt, int64_t n, int64
     if (!out || !C || !gamma) throw Failure(SPSVM_E_INVALID_ARG, "out, C and gamma must be host arrays");
     if (P < 1 || P > (1 << 20)) throw Failure(SPSVM_E_INVALID_ARG, "P must lie in [1, 2^20]");
     const spsvm_options o = resolve(opt);
-    if (o.bias || o.eps_stop > 0.0)
-      throw Failure(SPSVM_E_INVALID_ARG, "the shared basis takes neither the offset nor the stopping rule");
+    if (o.bias || o.eps_stop > 0.0 || o.kxj_host)
+      throw Failure(SPSVM_E_INVALID_ARG, "the shared basis takes neither the offset, the stopping rule nor kxj_host");
     for (int64_t p = 0; p < P; ++p) check_problem(X, xdt, Y, n, d, C[p], gamma[p], J_max);
     spsvm::run_train_shared(X, xdt == SPSVM_DT_F64, n, d, P, Y, C, gamma, J_max, o, workspace, ws_bytes,
                             as_stream(stream), out);

@@ -91,7 +91,8 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   const int64_t cap = with_selection ? opt.chunk_cap : 1;
   p.xnorm = take(n * tk);
   p.hash = take(n * 8);
-  p.KXJ = take((size_t)n * p.ldk * tk);
+  p.kxj_host = opt.kxj_host != 0;
+  p.KXJ = take(p.kxj_host ? 0 : (size_t)n * p.ldk * tk);
   p.Kc = take(with_selection ? (size_t)round_up(n, 4) * kCandSlots * (csr ? 1 : cand_group(d, opt.chunk_cap)) * tk : 0);
   p.J = take(J_max * 8);
   p.J32 = take(J_max * 4);
@@ -311,6 +312,15 @@ struct Impl {
   };
   std::vector<Slot> slots;
   Pinned pin_slots;
+  void* host_k = nullptr;  // pinned host memory holding K_XJ (kxj_host)
+  ~Impl() {
+    if (host_k) {
+      (void)hipStreamSynchronize(st);
+      (void)hipHostFree(host_k);
+    }
+  }
+  Impl(const Impl&) = delete;
+  Impl& operator=(const Impl&) = delete;
 
   template <typename T>
   T* at(size_t off) {
@@ -327,7 +337,12 @@ struct Impl {
     prof.stride = std::max(1, (o_.profile >> 8) & 0xFF);
     Xk = p.pad_x ? at<TX>(p.Xp) : X;
     xnorm = at<TK>(p.xnorm);
-    KXJ = at<TK>(p.KXJ);
+    if (p.kxj_host) {  // K_XJ beyond the workspace: pinned host memory, mapped for the kernels
+      SPSVM_HIP(hipHostMalloc(&host_k, (size_t)n * p.ldk * sizeof(TK), hipHostMallocDefault));
+      KXJ = (TK*)host_k;
+    } else {
+      KXJ = at<TK>(p.KXJ);
+    }
     Kc = at<TK>(p.Kc);
     hash = at<uint64_t>(p.hash);
     stage_hash = at<uint64_t>(p.stage_hash);

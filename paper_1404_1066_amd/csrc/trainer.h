@@ -52,6 +52,7 @@ struct Plan {
   size_t xnorm, hash, KXJ, Kc, J, J32, cand_state, sel, ls, scalars, score_part, cand_table, stage_hash, m_dev, flags,
       XJ64, xjnorm, KJJ, iota, incomplete, Xp, D, DJJ, G, Xhi, Xlo, Zc;
   bool csr = false;  // CSR rows: the candidate rows are made dense in Zc (kCandSlots x d FP32) for each block
+  bool kxj_host = false;  // K_XJ lives in pinned host memory (not in the workspace; KXJ offset unused)
   int64_t ldb = 0;  // row stride of the split-BF16 copies (MIXED)
   // per-problem regions: slot q starts at slots_at + q * slot.bytes; ls and scalars hold one entry per slot
   SlotPlan slot;

@@ -632,3 +632,22 @@ def test_shared_basis_rejects_offset_and_stop_rule():
     for kw in ({"bias": 1}, {"eps_stop": 1e-3}):
         with pytest.raises(lib.SpsvmError):
             lib.train_shared(Xg, Yg, C, gamma, 10, **kw)
+
+
+@pytest.mark.parametrize("prec", ["f32", "mixed"])
+def test_kxj_in_host_memory_gives_the_same_model(prec):
+    """K_XJ held in pinned host memory (kxj_host = 1: every pass over it streams it over the host link) runs the same
+    kernels on the same values, so greedy training and a fixed-basis solve return bit for bit the models made with
+    K_XJ in the workspace, and the workspace shrinks by the block."""
+    n, d, m = 20001, 40, 150
+    X, y = datagen.make_blobs(n, d, seed=33, dtype=np.float32)
+    Xg, yg = _dev(X, y)
+    a = lib.train(Xg, yg, 1.0, 1.0 / d, m, seed=3, precision=prec).get()
+    b = lib.train(Xg, yg, 1.0, 1.0 / d, m, seed=3, precision=prec, kxj_host=1).get()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+    fa = lib.train_fixed_basis(Xg, yg, 1.0, 1.0 / d, a[0], precision=prec).get()
+    fb = lib.train_fixed_basis(Xg, yg, 1.0, 1.0 / d, a[0], precision=prec, kxj_host=1).get()
+    assert np.array_equal(fa[1], fb[1]) and fa[2] == fb[2]
+    wa = lib.workspace_bytes(n, d, m, precision=prec)
+    wb = lib.workspace_bytes(n, d, m, precision=prec, kxj_host=1)
+    assert wa - wb >= n * 152 * 4 - 256  # the block (ldk = 152), less the 256 bytes every sub-buffer takes at least
