@@ -399,10 +399,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // Columns of an outer panel (four inner panels of 64).
 constexpr int kCholOuter = 4 * NB;
 
-// All slots share m and ldh; each panel step is one launch per kernel for the whole batch.
-void launch_cholesky_batch(const CholBatch& b, int64_t ldh, int m, hipStream_t s) {
-  if (b.count <= 0 || m <= 0) return;
-  if (b.count > kMaxBatch) throw Failure(1, "Cholesky batch: too many slots");
+// The panel chain of one group of problems: each panel step is one launch per kernel for the whole group.
+static void cholesky_chain(const CholBatch& b, int64_t ldh, int m, hipStream_t s) {
   const unsigned nz = (unsigned)b.count;
   for (int K0 = 0; K0 < m; K0 += kCholOuter) {
     const int kend = std::min(K0 + kCholOuter, m);
@@ -433,6 +431,64 @@ void launch_cholesky_batch(const CholBatch& b, int64_t ldh, int m, hipStream_t s
     }
     SPSVM_LAUNCHED();
   }
+}
+
+// Side streams for batched factorisations. A panel chain is a sequence of dependent launches whose diagonal-block
+// step runs one workgroup per problem, so most of the chip idles during it; a batch is therefore split into up to
+// kCholStreams groups whose chains run at the same time on their own streams (default priority), forked from and
+// joined back to the caller's stream with events, and each group's diagonal steps overlap the others' updates.
+// The streams and events are created once per device and kept until the process ends; the enqueueing is
+// serialised by a mutex (a later call may reuse the events once its predecessor's waits are enqueued).
+constexpr int kCholStreams = 4;
+struct CholStreams {
+  hipStream_t st[kCholStreams - 1];
+  hipEvent_t fork, join[kCholStreams - 1];
+};
+static std::mutex g_cs_mu;
+static CholStreams* g_cs[256];
+
+static CholStreams* chol_streams_locked() {  // g_cs_mu held
+  int dev = 0;
+  SPSVM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 256) throw Failure(1, "Cholesky streams: device index out of range");
+  if (!g_cs[dev]) {
+    CholStreams* c = new CholStreams();
+    for (int i = 0; i < kCholStreams - 1; ++i) {
+      SPSVM_HIP(hipStreamCreateWithFlags(&c->st[i], hipStreamNonBlocking));
+      SPSVM_HIP(hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming));
+    }
+    SPSVM_HIP(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+    g_cs[dev] = c;
+  }
+  return g_cs[dev];
+}
+
+// All slots share m and ldh. Batches of 8 or more problems run as up to kCholStreams concurrent groups.
+void launch_cholesky_batch(const CholBatch& b, int64_t ldh, int m, hipStream_t s) {
+  if (b.count <= 0 || m <= 0) return;
+  if (b.count > kMaxBatch) throw Failure(1, "Cholesky batch: too many slots");
+  const int groups = b.count >= 8 ? std::min(kCholStreams, b.count / 4) : 1;
+  if (groups <= 1) {
+    cholesky_chain(b, ldh, m, s);
+    return;
+  }
+  std::lock_guard<std::mutex> lock(g_cs_mu);
+  CholStreams* cs = chol_streams_locked();
+  SPSVM_HIP(hipEventRecord(cs->fork, s));
+  for (int g = 0; g < groups; ++g) {
+    CholBatch sub{};
+    for (int q = g * b.count / groups; q < (g + 1) * b.count / groups; ++q) {
+      sub.H[sub.count] = b.H[q];
+      sub.Linv[sub.count] = b.Linv[q];
+      sub.sc[sub.count] = b.sc[q];
+      ++sub.count;
+    }
+    hipStream_t gs = g == 0 ? s : cs->st[g - 1];
+    if (g > 0) SPSVM_HIP(hipStreamWaitEvent(gs, cs->fork, 0));
+    cholesky_chain(sub, ldh, m, gs);
+    if (g > 0) SPSVM_HIP(hipEventRecord(cs->join[g - 1], gs));
+  }
+  for (int g = 1; g < groups; ++g) SPSVM_HIP(hipStreamWaitEvent(s, cs->join[g - 1], 0));
 }
 
 void launch_cholesky(double* H, int64_t ldh, int m, double* Linv, NewtonScalars* sc, hipStream_t s) {
