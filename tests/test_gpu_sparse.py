@@ -53,3 +53,15 @@ def test_csr_invalid_indices_rejected():
     with pytest.raises(lib.SpsvmError) as e:
         lib.train_csr(*_dev_csr(ip, ix, v), 5, y, 1.0, 0.5, 1)
     assert e.value.status == 1 and "feature indices" in str(e.value)
+
+
+def test_csr_with_kxj_in_host_memory_gives_the_same_model():
+    """CSR rows with the offset and K_XJ in pinned host memory: bit for bit the model made with K_XJ in the
+    workspace (the offset's column of ones is written to host memory too)."""
+    ip, ix, v, y = datagen.make_sparse_rows(8000, 127, seed=9)
+    args = (*_dev_csr(ip, ix, v), 127, torch.tensor(y, dtype=torch.float32, device="cuda"), 10.0, 0.1, 60)
+    a = lib.train_csr(*args, seed=2, bias=1)
+    b = lib.train_csr(*args, seed=2, bias=1, kxj_host=1)
+    Ja, ba, Fa = a.get()
+    Jb, bb, Fb = b.get()
+    assert np.array_equal(Ja, Jb) and np.array_equal(ba, bb) and Fa == Fb and a.bias == b.bias

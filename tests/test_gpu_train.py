@@ -651,3 +651,22 @@ def test_kxj_in_host_memory_gives_the_same_model(prec):
     wa = lib.workspace_bytes(n, d, m, precision=prec)
     wb = lib.workspace_bytes(n, d, m, precision=prec, kxj_host=1)
     assert wa - wb >= n * 152 * 4 - 256  # the block (ldk = 152), less the 256 bytes every sub-buffer takes at least
+
+
+def test_shared_basis_more_problems_than_slots_f64():
+    """66 problems, 65 of them on one gamma (more than the 64 Newton slots: that group is solved in two rounds of
+    slots) and one on another: the FP64 shared basis equals the oracle's step for step, and the objectives match."""
+    X, cls = datagen.make_mnist_like(per_class=80, d=6, seed=41, classes=5)
+    X = X.astype(np.float64)
+    P = 66
+    Y = np.stack([np.where(cls == (q % 5), 1.0, -1.0) for q in range(P)])
+    C = np.array([0.5 + 0.25 * (q % 7) for q in range(P)])
+    gamma = np.array([1.5 if q == 40 else 0.5 for q in range(P)])
+    ref = osp.train_shared(X, Y, C, gamma, 12, seed=6, kappa=8)
+    models = lib.train_shared(torch.tensor(X, device="cuda"), torch.tensor(Y, dtype=torch.float32, device="cuda"),
+                              C, gamma, 12, seed=6, kappa=8, precision="f64")
+    assert len(models) == P
+    for q in (0, 1, 40, 63, 64, 65):
+        J, beta, F = models[q].get()
+        assert J.tolist() == ref.J.tolist()
+        assert abs(F - ref.F[q]) <= 1e-9 * ref.F[q]
