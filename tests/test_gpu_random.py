@@ -60,3 +60,74 @@ def test_random_training_matches_oracle(seed):
     dg = model.predict(torch.tensor(Xd, dtype=dt, device="cuda")).cpu().numpy()
     do = oracle.predict(Xd[J], b_or, gamma, Xd, info.bias)
     assert float(np.max(np.abs(dg - do) / np.maximum(1.0, np.abs(do)))) <= 1e-4
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_batch_matches_oracle(seed):
+    """Batched Newton solves on a random shared basis: random problem count, labels, C and gamma per problem."""
+    r = np.random.default_rng(9500 + seed)
+    n, d = int(r.integers(60, 2000)), int(r.integers(2, 120))
+    X, _ = datagen.make_blobs(n, d, seed=100 + seed)
+    P = int(r.integers(1, 9))
+    Y = np.where(r.standard_normal((P, n)) + X[:, :1].T > 0, 1.0, -1.0)
+    C = 10.0 ** r.uniform(-1, 2, P)
+    gamma = 10.0 ** r.uniform(-1.5, 0.5, P) / d
+    m = int(r.integers(1, min(n, 150) + 1))
+    J = np.sort(r.choice(n, m, replace=False))
+    prec = ["f64", "f32", "mixed"][seed % 3]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    Xd = X if prec == "f64" else X.astype(np.float32).astype(np.float64)
+    models = lib.train_batch(torch.tensor(Xd, dtype=dt, device="cuda"),
+                             torch.tensor(Y, dtype=torch.float32, device="cuda"), C, gamma, J, precision=prec)
+    for q in range(P):
+        _, beta, _ = models[q].get()
+        b_or, F_or, _ = osp.solve_fixed_J(Xd, Y[q], C[q], gamma[q], J)
+        Fo = osp.objective_at(Xd, Y[q], C[q], gamma[q], J, beta)
+        assert abs(Fo - F_or) / F_or <= 1e-6, (q, Fo, F_or)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_shared_basis_reaches_oracle_objective(seed):
+    """A greedily grown shared basis for random problems: every problem at the oracle's optimum on that basis."""
+    r = np.random.default_rng(9700 + seed)
+    n, d = int(r.integers(100, 1500)), int(r.integers(2, 60))
+    X, _ = datagen.make_blobs(n, d, seed=200 + seed)
+    P = int(r.integers(1, 6))
+    Y = np.where(r.standard_normal((P, n)) + X[:, 1:2].T > 0, 1.0, -1.0)
+    C = 10.0 ** r.uniform(-1, 2, P)
+    gamma = np.repeat(10.0 ** r.uniform(-1.5, 0.5, 2) / d, (P + 1) // 2)[:P]
+    J_max = int(r.integers(1, min(n, 80) + 1))
+    prec = ["f64", "f32", "mixed"][seed % 3]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    Xd = X if prec == "f64" else X.astype(np.float32).astype(np.float64)
+    models = lib.train_shared(torch.tensor(Xd, dtype=dt, device="cuda"),
+                              torch.tensor(Y, dtype=torch.float32, device="cuda"), C, gamma, J_max,
+                              seed=int(r.integers(0, 1 << 30)), precision=prec)
+    J0 = models[0].get()[0]
+    assert len(J0) == J_max
+    for q in range(P):
+        J, beta, _ = models[q].get()
+        assert J.tolist() == J0.tolist()
+        b_or, F_or, _ = osp.solve_fixed_J(Xd, Y[q], C[q], gamma[q], J)
+        Fo = osp.objective_at(Xd, Y[q], C[q], gamma[q], J, beta)
+        assert abs(Fo - F_or) / F_or <= 1e-6, (q, Fo, F_or)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_csr_training_reaches_oracle_objective(seed):
+    """CSR rows of random size and width, with or without the offset."""
+    r = np.random.default_rng(9900 + seed)
+    n, d = int(r.integers(200, 6000)), int(r.integers(4, 400))
+    ip, ix, v, y = datagen.make_sparse_rows(n, d, seed=300 + seed, mean_nnz=max(2.0, d / 10))
+    X = datagen.csr_to_dense(ip, ix, v, d)
+    groups = len(np.unique(X, axis=0))
+    J_max = int(r.integers(1, min(groups, 100) + 1))
+    C, gamma, bias = float(10.0 ** r.uniform(-1, 2)), float(10.0 ** r.uniform(-1.5, 0) * 10 / d), seed % 2
+    dev = [torch.tensor(a, device="cuda") for a in (ip, ix, v)]
+    model = lib.train_csr(*dev, d, torch.tensor(y, dtype=torch.float32, device="cuda"), C, gamma, J_max,
+                          seed=int(r.integers(0, 1 << 30)), bias=bias)
+    J, beta, _ = model.get()
+    assert len(J) == J_max
+    b_or, F_or, _ = osp.solve_fixed_J(X, y, C, gamma, J, bias=bool(bias))
+    Fo = osp.objective_at(X, y, C, gamma, J, beta, b=model.bias)
+    assert abs(Fo - F_or) / F_or <= 1e-6, (Fo, F_or)
