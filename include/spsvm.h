@@ -88,8 +88,8 @@ typedef struct {
                               and frees before it returns, instead of in the workspace: for n |J| beyond the GPU's
                               memory (the method needs O(|J| n) memory, section 4). Every pass over K_XJ (outputs,
                               gradient, Newton matrix, appended columns) then streams it over the host link; the
-                              kernels and results are those of 0. spsvm_train, spsvm_train_fixed_basis and
-                              spsvm_train_csr only. 0 (default): K_XJ in the workspace */
+                              kernels and results are those of 0. The batched calls (spsvm_train_batch,
+                              spsvm_train_shared) reject it. 0 (default): K_XJ in the workspace */
 } spsvm_options;
 
 typedef struct spsvm_model spsvm_model; /* opaque, owned by the library */
