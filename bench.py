@@ -8,9 +8,9 @@ every row of the hot path) on a fixed synthetic workload already resident in HBM
 The default workload is the largest single-GPU one, dense-2m (2 000 000 x 2000 i.i.d. N(0, 1) FP32 rows,
 |J| = 4000, C = 1, gamma = 1/2000), timed in mixed precision (split-BF16 distances); the FP32 path is timed on
 the same workload with the same kernel-block timing for the "mixed vs FP32" part of the metric (--compare-steps
-runs). The kernel block is timed with HIP events on the training stream during the timed steps (every launch on
-rows of 256+ features) for the roofline entry: algorithmic flops 2 n N d and issued MFMA flops, each over the
-launches' time. Other workloads: binary-100k, onehot-500k, blobs-2k; with --workload mnist-60k a step is one
+runs). The kernel block is timed with HIP events on the training stream during the timed steps for the roofline
+entry (the candidate blocks on the kernel a full group of steps runs on: every such launch on rows of 256+
+features, every 8th otherwise): algorithmic flops 2 n N d and issued MFMA flops, each over the launches' time. Other workloads: binary-100k, onehot-500k, blobs-2k; with --workload mnist-60k a step is one
 batched call (160 one-vs-rest x (C, gamma) Newton solves on a shared basis of 2000 rows of 60 000 x 784 rows).
 Parity, on the model of every timed run: where the oracle can re-solve at the GPU's basis within the run (up to
 4e8 kernel values) it does; beyond that each model's decisions are checked on sampled rows and the objective
@@ -212,7 +212,7 @@ def _kblock_entry(stats, precision, split, d):
     e["issued_frac"] = round(e["issued_tflops"] / peak, 4)
     e["issued_per_launch"] = stats["kblock_mfma_flops"] / max(stats["kblock_launches"], 1)
     e["split_products"] = 3 if split else 1
-    # candidate steps are grouped (up to 16 per launch, 256 x 256 split-BF16 tiles) on rows of 256+ features
+    # on rows of 256+ features a launch takes the candidates of up to 52 steps (3068 columns), in 256 x 256 tiles
     e["kernel_name"] = (("k_kblock_bf16_wide" if d >= 256 else "k_kblock_bf16") if precision == "mixed" else
                         "k_kblock_store")
     return e

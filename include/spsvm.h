@@ -69,13 +69,16 @@ typedef struct {
   spsvm_precision precision; /* default SPSVM_F32 */
   int32_t log_level;       /* 0 silent; 1 one line per stage on stderr; 2 one line per Newton iteration */
   int32_t profile;         /* bits 0-3: kernels to time with HIP events on the call's stream (results in
-                              spsvm_stats): 1 kernel block, 2 Newton-matrix SYRK, 4 candidate-score passes,
-                              8 Cholesky factorisations; 0 (default) records nothing. Bits 8-15: k, time only
+                              spsvm_stats): 1 kernel block (the candidate blocks that run on the kernel a full
+                              group of candidate steps runs on, so that the times describe one kernel; the basis
+                              block of the fixed-basis and batched calls), 2 Newton-matrix SYRK, 4 candidate-score
+                              passes, 8 Cholesky factorisations; 0 (default) records nothing. Bits 8-15: k, time only
                               every k-th launch of a kernel (0 or 1: every launch); each timed launch is
                               bracketed by two events, which delay the stream a few microseconds */
   double refactor_frac;    /* the Newton matrix is re-formed and re-factorised when more than this fraction of
-                              the violator set changed since the last factorisation (else the last factor is
-                              reused; the exact line search keeps every step a descent step); default 0.002 */
+                              the violator set changed since the last factorisation, or when a step solved with
+                              an older factor cut ||grad f|| less than 100-fold (else the last factor is reused;
+                              the exact line search keeps every step a descent step); default 0.002 */
   int32_t bias;            /* 1: fit the offset b of Eq. 4 (decision k_i^T beta + b, b not regularised), solved with
                               beta in every Newton re-optimisation and held fixed while candidates are scored;
                               0 (default): b = 0, as section 2 allows */
@@ -115,7 +118,8 @@ typedef struct {
   double seconds_newton;    /* wall time in Newton re-optimisation */
   /* Per-kernel GPU time (HIP events) and algorithmic work of the timed launches of the kernels selected by
    * spsvm_options.profile (every k-th launch with a stride k); zero otherwise. */
-  int64_t kblock_launches;  /* timed kernel-block GEMMs (candidate blocks and basis blocks) */
+  int64_t kblock_launches;  /* timed kernel-block GEMMs (candidate blocks on the kernel of a full group of steps,
+                               basis blocks) */
   double kblock_seconds;
   double kblock_flops;      /* 2 n N d per launch, N = columns computed */
   int64_t syrk_launches;    /* timed Newton-matrix SYRKs */

@@ -8,8 +8,11 @@ It fixes neither the subset size, the random stream, nor the stage sizes. The re
   1 - 0.95^59 > 0.95).
 * Random stream: SplitMix64 (Steele, Lea and Flood, OOPSLA 2014), one counter stream per step.
   Step t (0-based index of the addition step, counted over the whole run) starts from state
-  ``seed XOR ((t + 1) * GOLDEN mod 2^64)``. Each draw adds GOLDEN to the state and mixes it with the
+  ``seed XOR ((t * 2^32 + 1) * GOLDEN mod 2^64)``. Each draw adds GOLDEN to the state and mixes it with the
   published finaliser (shifts 30, 27, 31; multipliers 0xBF58476D1CE4E5B9 and 0x94D049BB133111EB).
+  Section 4 draws a fresh random subset at every step, so the streams of different steps must not overlap:
+  a step makes at most 64 kappa draws, far fewer than the 2^32 states between the starts of consecutive steps
+  (with ``(t + 1) * GOLDEN`` instead, seed 0 would give step t + 1 the draws of step t shifted by one).
 * Index: ``((z >> 32) * n) >> 32`` (the high 32 bits scaled to [0, n)).
 * Rejection: a draw is rejected if it repeats an index already accepted in this step, or if its row
   is blocked (it is a basis member, or an exact duplicate of one, as J stood at the start of the
@@ -42,7 +45,7 @@ def splitmix64_stream(state: int, count: int) -> list[int]:
 
 
 def step_state(seed: int, t: int) -> int:
-    return (seed ^ (((t + 1) * GOLDEN) & MASK64)) & MASK64
+    return (seed ^ ((((t << 32) + 1) * GOLDEN) & MASK64)) & MASK64
 
 
 def scaled_index(z: int, n: int) -> int:

@@ -312,10 +312,12 @@ struct ColStage {
     constexpr int NQ = BM / 32, NR = BM / 128;  // row quads per lane, fused records per column
     const int sub = threadIdx.x & 7, cb = threadIdx.x >> 3;
     bool ok[2];  // loads first: a load issued after a store waits for it
+    int64_t dcol[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int64_t col = c0 + cb + HC * h;
       ok[h] = col < ncols && (!cidx || cidx[col] >= 0);
+      dcol[h] = s0.dst && col < ncols ? (int64_t)s0.dst[col] : col;
     }
     __syncthreads();
 #pragma unroll
@@ -324,7 +326,7 @@ struct ColStage {
       double P[NR], Q[NR];
 #pragma unroll
       for (int e = 0; e < NR; ++e) P[e] = Q[e] = 0.0;
-      float* ocol = out + (c0 + cb + HC * h) * ldo;
+      float* ocol = out + dcol[h] * ldo;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int rr = 32 * q + 4 * sub;
@@ -429,7 +431,7 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
       const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
       xr[i][r] = xnorm[row < n ? row : n - 1];  // rows past n are computed but never used
     }
-  int64_t zis[4];  // source rows of this lane's columns: all index loads first, then all norm loads
+  int64_t zis[4], zdst[4];  // source rows and output columns of this lane's columns: index loads first, then norms
   if (cidx) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -439,6 +441,11 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
   } else {
 #pragma unroll
     for (int j = 0; j < 4; ++j) zis[j] = c0 + j * 16 + (lane & 15);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t col = c0 + j * 16 + (lane & 15);
+    zdst[j] = s0.dst ? (int64_t)s0.dst[col < ncols ? col : ncols - 1] : col;
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -476,7 +483,7 @@ __global__ __launch_bounds__(256, (kStoreWaves<TX, TK>)) void k_kblock_store(con
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (!zok[j]) continue;
-          TK* ocol = out + (c0 + j * 16 + (lane & 15)) * ldo;
+          TK* ocol = out + zdst[j] * ldo;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int64_t row = r0 + w * 32 + i * 16 + M::row(lane, r);
@@ -537,7 +544,8 @@ void launch_kblock(const TX* X, int64_t ldx, int64_t n, int64_t d, const TK* xno
   const dim3 grid(xcd_grid(ceil_div(n, KB_BM), ceil_div(ncols, KB_BN)));
   if (colmajor && (ldo % 4 != 0 || ((uintptr_t)out & 15u)))
     throw Failure(1, "kernel block: column-major out needs 16-byte aligned columns");
-  if (s0.partial && !colmajor) throw Failure(1, "kernel block: the fused scoring pass needs column-major out");
+  if ((s0.partial || s0.dst) && !colmajor)
+    throw Failure(1, "kernel block: the fused scoring pass and output columns need column-major out");
   hipLaunchKernelGGL((k_kblock_store<TX, TK>), grid, dim3(256), 0, st, X, ldx, n, d, xnorm, cidx, ncols, out, ldo,
                      gamma, s0, colmajor ? 1 : 0);
   SPSVM_LAUNCHED();
@@ -1187,6 +1195,10 @@ static int chosen_variant(bool split, int cm, bool fused, int64_t n, int64_t ldb
   return it != g_tuner.choice.end() ? it->second : heuristic_variant(n, ldb, ncols);
 }
 
+int kblock_bf16_variant(int64_t n, int64_t ldb, int64_t ncols, bool split, bool candidates) {
+  return chosen_variant(split, candidates ? 1 : 0, candidates, n, ldb, ncols);
+}
+
 // MFMA flops a launch_kblock_bf16 call issues: whole tiles of the variant it uses, k over ldb, three products per
 // multiply-add with the split correction (one without).
 double kblock_bf16_issued_flops(int64_t n, int64_t ldb, int64_t ncols, bool split, bool candidates) {
@@ -1203,7 +1215,8 @@ void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int6
   if (n <= 0 || ncols <= 0) return;
   if (colmajor && (ldo % 4 != 0 || ((uintptr_t)out & 15u)))
     throw Failure(1, "kernel block: column-major out needs 16-byte aligned columns");
-  if (s0.partial && !colmajor) throw Failure(1, "kernel block: the fused scoring pass needs column-major out");
+  if ((s0.partial || s0.dst) && !colmajor)
+    throw Failure(1, "kernel block: the fused scoring pass and output columns need column-major out");
   const int cm = colmajor ? 1 : 0;
   if (ldb % SB_BK != 0 || ((uintptr_t)hi & 15u) || ((uintptr_t)lo & 15u))
     throw Failure(1, "kernel block: split copies must be 16-byte aligned with ldb a multiple of 32");

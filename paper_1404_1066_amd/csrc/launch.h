@@ -83,10 +83,14 @@ void launch_row_hash(const TX* X, int64_t n, int64_t d, uint64_t* out, hipStream
 // {P, Q, 0, 0}, the sums of a_i b_i and b_i^2 over the rows of the tile with a_i = 1 - y_i o_i > 0
 // (b_i = y_i k_ic), in the slot-major layout of a scoring pass. Only with column-major out (the launchers
 // reject it otherwise).
+// dst (column-major out only): launch column c is written to column dst[c] of out, so the valid candidates of
+// several steps can share tiles while each keeps its slot; the fused records stay keyed by launch column, which
+// is the slot of the first step when that step's candidates come first and fill a prefix of its slots.
 struct Score0 {
   const float* y = nullptr;
   const double* o = nullptr;
   double* partial = nullptr;  // nullptr: no fused pass
+  const int32_t* dst = nullptr;  // nullptr: launch column c goes to column c
 };
 constexpr int kKblockRows = 128;  // rows per kernel-block tile (the fused pass writes one record per tile)
 
@@ -114,6 +118,9 @@ void launch_split_bf16(const TX* X, int64_t n, int64_t d, int64_t ldx, unsigned 
 // with the split correction), for the roofline next to the algorithmic 2 n ncols d.
 double kblock_issued_flops(int64_t n, int64_t d, int64_t ncols);
 double kblock_bf16_issued_flops(int64_t n, int64_t ldb, int64_t ncols, bool split, bool candidates);
+// Tile variant (one kernel each) that launch_kblock_bf16 runs for this shape: the forced one, the tuned one, else
+// the shape rule; candidate blocks are column-major with the fused first pass.
+int kblock_bf16_variant(int64_t n, int64_t ldb, int64_t ncols, bool split, bool candidates);
 void launch_kblock_bf16(const unsigned short* hi, const unsigned short* lo, int64_t ldb, int64_t n,
                         const float* xnorm, const int32_t* cidx, int ncols, float* out, int64_t ldo, double gamma,
                         hipStream_t st, const Score0& s0 = Score0{}, bool colmajor = false);

@@ -33,7 +33,9 @@ static inline uint64_t splitmix_finalise(uint64_t z) {
 void draw_step(uint64_t seed, int64_t t, int64_t n, int kappa, const std::vector<uint64_t>& row_hash,
                const std::vector<uint64_t>& blocked_sorted, int32_t* out64) {
   for (int c = 0; c < kCandSlots; ++c) out64[c] = -1;
-  uint64_t state = seed ^ ((uint64_t)(t + 1) * kGolden);
+  // step t starts 2^32 states after step t - 1 (before the seed is mixed in): a step makes at most 64 kappa
+  // draws, so the streams of different steps never share a state and each step draws a fresh subset
+  uint64_t state = seed ^ ((((uint64_t)t << 32) + 1) * kGolden);
   int got = 0;
   for (int attempt = 0; attempt < 64 * kappa && got < kappa; ++attempt) {
     state += kGolden;
@@ -47,11 +49,19 @@ void draw_step(uint64_t seed, int64_t t, int64_t n, int kappa, const std::vector
   }
 }
 
-// Steps whose candidate columns come from one kernel-block launch. For wide rows the block is bound by reading
-// X (d values per row for 64 columns); the column tiles of several steps of a stage (all drawn at its start)
-// then share each row slab of X through L2. The first scoring pass is launched for all but the first step.
-int cand_group(int64_t d, int64_t chunk_cap) {
-  return (int)std::min<int64_t>(d >= 256 ? 16 : 1, std::max<int64_t>(chunk_cap, 1));
+// Steps whose candidate columns come from one kernel-block launch. For wide rows every launch streams all of X
+// once, and the column tiles of the steps of a stage (all drawn at its start) share each row slab of it through
+// L2; launches of more column tiles spread that stream over more products (2 000 000 x 2000 rows, single-pass
+// BF16: 3, 4, 6, 9 and 12 tiles of 256 columns per launch ran at 815, 787-815, 866, 881 and 894 TFLOP/s). A
+// launch takes only the valid candidates of its steps, each written to its own slot, so a group is as many steps
+// as fill twelve such tiles (52 at kappa = 59: 3068 columns), at most 52: the candidate buffer keeps 64 slots
+// per step, n x 64 x 52 values. The first scoring pass is launched for all but the first step.
+// Gradient contraction per Newton step below which an older factor is formed again (see newton_slots).
+constexpr double kReuseContraction = 100.0;
+
+int cand_group(int64_t d, int64_t chunk_cap, int kappa) {
+  const int64_t fill = std::max<int64_t>(1, 3072 / std::max(1, std::min(kappa, kCandSlots)));
+  return (int)std::min<int64_t>(d >= 256 ? std::min<int64_t>(52, fill) : 1, std::max<int64_t>(chunk_cap, 1));
 }
 
 int64_t stage_size(int64_t J, int64_t J_max, double growth, int64_t cap) {
@@ -93,7 +103,8 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.hash = take(n * 8);
   p.kxj_host = opt.kxj_host != 0;
   p.KXJ = take(p.kxj_host ? 0 : (size_t)n * p.ldk * tk);
-  p.Kc = take(with_selection ? (size_t)round_up(n, 4) * kCandSlots * (csr ? 1 : cand_group(d, opt.chunk_cap)) * tk : 0);
+  p.Kc = take(with_selection ? (size_t)round_up(n, 4) * kCandSlots * (csr ? 1 : cand_group(d, opt.chunk_cap, opt.kappa)) * tk
+                             : 0);
   p.J = take(J_max * 8);
   p.J32 = take(J_max * 4);
   p.cand_state = take(kCandStateBytes);
@@ -102,6 +113,7 @@ Plan make_plan(int64_t n, int64_t d, int64_t J_max, const spsvm_options& opt, bo
   p.scalars = take(p.slots * sizeof(NewtonScalars));
   p.score_part = take((size_t)std::max<int64_t>(nb_s, ceil_div(n, kKblockRows)) * kCandSlots * 4 * 8);
   p.cand_table = take((size_t)cap * kCandSlots * 4);
+  p.cand_cols = take(with_selection && !csr ? (size_t)2 * cap * kCandSlots * 4 : 0);  // launch rows, then slots
   p.stage_hash = take(cap * 8);
   p.m_dev = take(8);  // basis size, double-buffered by step parity
   p.flags = take(16);
@@ -305,7 +317,8 @@ struct Impl {
     int m_fact = 0;         // the violator status in act_fact
     // the current solve
     bool fact_valid = false;
-    double g0 = 0.0, f = 0.0;
+    bool reused = false;  // the last step solved with a factor formed before an earlier step
+    double g0 = 0.0, f = 0.0, g_step = 0.0;  // g_step: ||grad f|| before the last step
     int it = 0, tr0 = 0, n_in = 0, n_out = 0;
     NewtonScalars s{};
     LineState L{};
@@ -330,7 +343,7 @@ struct Impl {
   Impl(const TX* X_, const float* y_, int64_t n_, int64_t d_, double C_, double g_, int64_t Jm, const spsvm_options& o_,
        void* ws, hipStream_t s, const Plan& plan)
       : X(X_), y(y_), n(n_), d(d_), J_max(Jm), C(C_), gamma(g_), lam(1.0 / C_), opt(o_), st(s), p(plan),
-        base((char*)ws), pin(kPinnedScalars + (size_t)o_.chunk_cap * kCandSlots * 4),
+        base((char*)ws), pin(kPinnedScalars + (size_t)3 * o_.chunk_cap * kCandSlots * 4),
         pin_slots((size_t)plan.slots * (sizeof(NewtonScalars) + sizeof(LineState))) {
     prof.st = s;
     prof.mask = o_.profile & 0xF;
@@ -448,6 +461,16 @@ struct Impl {
       }
     }
     launch_kblock<TX, TK>(Xk, p.ldx, n, d, xnorm, cols, ncols, out, ldo, gamma, st, s0, colmajor);
+  }
+
+  // Kernel a candidate block of ncols columns runs on: in MIXED precision the split-BF16 block's tile variant (one
+  // kernel each), else the path's one kernel (-1).
+  int cand_kernel(int64_t ncols, bool single_pass) const {
+    if constexpr (std::is_same<TK, float>::value) {
+      if (opt.precision == SPSVM_MIXED && !csr.indptr)
+        return kblock_bf16_variant(n, p.ldb, ncols, !bf16_exact && !single_pass, true);
+    }
+    return -1;
   }
 
   // MFMA flops kblock() issues for ncols columns.
@@ -651,6 +674,7 @@ struct Impl {
     for (int q : ids) {
       Slot& S = slots[q];
       S.fact_valid = false;
+      S.reused = false;
       S.g0 = 0.0;
       S.it = 0;
       act.push_back(q);
@@ -698,7 +722,17 @@ struct Impl {
           continue;
         }
         go.push_back(q);
-        if (!S.fact_valid || S.s.flips > opt.refactor_frac * std::max(1, S.s.n_sv)) refac.push_back(q);
+        // An older factor is kept while few violators changed since it was formed and each step solved with it
+        // cut ||grad f|| at least kReuseContraction-fold (Newton-like); a slower step means the matrix drifted
+        // too far, and the remaining steps would only converge linearly.
+        const bool slow = S.reused && gn * kReuseContraction > S.g_step;
+        if (!S.fact_valid || slow || S.s.flips > opt.refactor_frac * std::max(1, S.s.n_sv)) {
+          refac.push_back(q);
+          S.reused = false;
+        } else {
+          S.reused = true;
+        }
+        S.g_step = gn;
       }
       if (go.empty()) break;
       factorize_slots(m, refac);
@@ -955,7 +989,8 @@ struct Impl {
       // converge within the launched passes selects nothing, and so does every later step of the attempt; the
       // stage then resumes from that step (o, J and the basis size are as the last complete step left them)
       // with more passes (64 passes always suffice: the update stops every slot by then).
-      const int G = csr.indptr ? 1 : cand_group(d, opt.chunk_cap);
+      const int G = csr.indptr ? 1 : cand_group(d, opt.chunk_cap, opt.kappa);
+      const int full_cols = G > 1 ? G * std::min(opt.kappa, kCandSlots) : kCandSlots;  // columns of a full group
       const bool fused = !csr.indptr;  // the dense blocks yield the first scoring pass of their first step
       int qstart = 0, m_q = m;  // first step of the attempt and the basis size it starts from
       for (int attempt = 0;; ++attempt) {
@@ -971,7 +1006,36 @@ struct Impl {
         }
         if (attempt > 0) stats.stage_redos += 1;
         SPSVM_HIP(hipMemsetAsync(incomplete, 0, 32, st));
-        for (int q0 = qstart; q0 < cs; q0 += G) {
+        // Launches of several steps take only their valid candidates: per launch, the rows and their slots
+        // (step within the launch x kCandSlots + slot), laid out launch after launch in cand_cols (rows, then
+        // slots at cap x kCandSlots). draw_step fills a prefix of each step's slots, so the first step's
+        // candidates keep launch column = slot, which the fused first scoring pass relies on.
+        std::vector<int> g_off, g_cnt;
+        int32_t* ccols = at<int32_t>(p.cand_cols);
+        const size_t slots_cap = (size_t)opt.chunk_cap * kCandSlots;
+        if (G > 1) {
+          int32_t* rows_h = (int32_t*)((char*)pin.p + kPinnedScalars + slots_cap * 4);
+          int32_t* dst_h = rows_h + slots_cap;
+          int tot = 0;
+          for (int q0 = qstart; q0 < cs; q0 += G) {
+            const int gsz = std::min(G, cs - q0);
+            g_off.push_back(tot);
+            for (int j = 0; j < gsz; ++j)
+              for (int c = 0; c < kCandSlots; ++c) {
+                const int32_t v = table[(size_t)(q0 + j) * kCandSlots + c];
+                if (v < 0) continue;
+                rows_h[tot] = v;
+                dst_h[tot] = j * kCandSlots + c;
+                ++tot;
+              }
+            g_cnt.push_back(tot - g_off.back());
+          }
+          if (tot > 0) {
+            SPSVM_HIP(hipMemcpyAsync(ccols, rows_h, (size_t)tot * 4, hipMemcpyHostToDevice, st));
+            SPSVM_HIP(hipMemcpyAsync(ccols + slots_cap, dst_h, (size_t)tot * 4, hipMemcpyHostToDevice, st));
+          }
+        }
+        for (int q0 = qstart, gi = 0; q0 < cs; q0 += G, ++gi) {
           const int gsz = std::min(G, cs - q0);  // steps sharing this kernel-block launch
           const int64_t ldc = round_up(n, 4);     // candidate columns, column-major (one contiguous column each)
           int ncand = 0;
@@ -981,10 +1045,16 @@ struct Impl {
           s0.y = y;
           s0.o = o;
           s0.partial = fused ? score_part : nullptr;
-          prof.timed(
-              kProfKblock, 2.0 * n * ncand * d,
-              [&] { kblock(cand_table + (size_t)q0 * kCandSlots, kCandSlots * gsz, Kc, ldc, s0, true, approx); },
-              kblock_issued(kCandSlots * gsz, approx, true));
+          s0.dst = G > 1 ? ccols + slots_cap + g_off[gi] : nullptr;
+          const int32_t* cols = G > 1 ? ccols + g_off[gi] : cand_table + (size_t)q0 * kCandSlots;
+          const int ncols = G > 1 ? g_cnt[gi] : kCandSlots * gsz;
+          // timed: the launches on the kernel a full group runs on, so that the timings describe one kernel
+          if (cand_kernel(ncols, approx) == cand_kernel(full_cols, approx))
+            prof.timed(
+                kProfKblock, 2.0 * n * ncand * d, [&] { kblock(cols, ncols, Kc, ldc, s0, true, approx); },
+                kblock_issued(ncols, approx, true));
+          else
+            kblock(cols, ncols, Kc, ldc, s0, true, approx);
           for (int j = 0; j < gsz; ++j) {
             const int q = q0 + j;
             const int32_t* cq = cand_table + (size_t)q * kCandSlots;

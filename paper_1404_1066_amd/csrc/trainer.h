@@ -49,8 +49,8 @@ struct Plan {
                 // zero, coefficient 0 is b, and basis vector k sits at position k + 1 of every coefficient array
   size_t bytes = 0;
   // offsets into the workspace (shared by all slots)
-  size_t xnorm, hash, KXJ, Kc, J, J32, cand_state, sel, ls, scalars, score_part, cand_table, stage_hash, m_dev, flags,
-      XJ64, xjnorm, KJJ, iota, incomplete, Xp, D, DJJ, G, Xhi, Xlo, Zc;
+  size_t xnorm, hash, KXJ, Kc, J, J32, cand_state, sel, ls, scalars, score_part, cand_table, cand_cols, stage_hash,
+      m_dev, flags, XJ64, xjnorm, KJJ, iota, incomplete, Xp, D, DJJ, G, Xhi, Xlo, Zc;
   bool csr = false;  // CSR rows: the candidate rows are made dense in Zc (kCandSlots x d FP32) for each block
   bool kxj_host = false;  // K_XJ lives in pinned host memory (not in the workspace; KXJ offset unused)
   int64_t ldb = 0;  // row stride of the split-BF16 copies (MIXED)

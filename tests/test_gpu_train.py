@@ -57,6 +57,23 @@ def test_wide_rows_identical_basis_f64():
     assert abs(Fo - ref.F) <= 1e-6 * ref.F
 
 
+@pytest.mark.parametrize("kappa", [64, 33])
+def test_grouped_candidate_launches_identical_basis_f64(kappa):
+    """300 features: candidate steps share kernel-block launches that take only the drawn candidates, each written
+    to its own slot (kappa = 64: every slot in use, 48 steps fill 3072 columns; kappa = 33: up to 52 steps, 1716
+    columns). Stages of 1, 1, 2, .., 64 and 2 steps: the 64-step stage takes two launches (48 + 16 or 52 + 12
+    steps). The FP64 path must still pick the oracle's basis, step for step."""
+    X, y = datagen.make_blobs(2200, 300, seed=26)
+    C, gamma, m = 1.0, 1.0 / 300, 130
+    ref = oracle.train(X, y, C, gamma, m, seed=8, kappa=kappa, growth=1.0)
+    Xg, yg = _dev(X, y)
+    model = lib.train(Xg, yg, C, gamma, m, seed=8, precision="f64", kappa=kappa, growth=1.0)
+    J, beta, F = model.get()
+    assert J.tolist() == ref.J.tolist()
+    Fo = osp.objective_at(X, y, C, gamma, J, beta)
+    assert abs(Fo - ref.F) <= 1e-6 * ref.F
+
+
 @pytest.mark.parametrize("prec", ["f32", "mixed"])
 def test_wide_rows_f32_mixed_reach_oracle_objective(prec):
     X, y = datagen.make_blobs(3001, 333, seed=22, dtype=np.float32)
@@ -162,8 +179,9 @@ def test_mixed_tall_blocks_reach_oracle_objective(d):
 
 @pytest.mark.parametrize("binary", [False, True])
 def test_mixed_grouped_wide_tiles_reach_oracle_objective(binary):
-    """300 features: candidate steps share kernel-block launches (up to 8 steps, 512 columns), which the
-    split-BF16 block runs in 256 x 256 tiles with the fused first scoring pass in its first 64 columns."""
+    """300 features: candidate steps share kernel-block launches (whole stages of up to 24 steps here, 1416
+    columns), which the split-BF16 block runs in 256 x 256 tiles with the fused first scoring pass in its first
+    64 columns."""
     n, d = 40000, 300
     if binary:
         r = np.random.default_rng(31)
@@ -459,8 +477,10 @@ def test_onehot_200k_full_basis_mixed_reaches_oracle_objective():
 
 def test_offset_and_stopping_rule_identical_to_oracle_f64():
     """Eq. 4 with the offset b and the training-error stopping rule of section 4 (here eps = 2e-3 so that it stops
-    after a dozen stages), FP64 path: the same basis, hence the same stopping stage, the same b and objective as
-    the oracle; the reported training error is the oracle's last one."""
+    after about a dozen stages), FP64 path: the same basis, hence the same stopping stage, the same b and objective
+    as the oracle; the reported training error is the oracle's last one. Decision values: two separately converged
+    Newton solves (each stops at ||grad f|| <= 1e-10 ||grad f_0||), so they agree to that times the conditioning of
+    the Newton matrix, here a few 1e-9; the bar is 1e-7, against 1e-4 for parity."""
     p = datagen.make_config("binary-100k", n=3000)
     X = p.X.astype(np.float64)
     ref = oracle.train(X, p.y, p.C, p.gamma, 300, seed=2, bias=True, eps_stop=2e-3)
@@ -477,7 +497,7 @@ def test_offset_and_stopping_rule_identical_to_oracle_f64():
     assert abs(st["train_error"] - ref.errors[-1]) <= 1.0 / X.shape[0]
     dg = model.predict(Xg).cpu().numpy()
     do = oracle.predict(X[ref.J], ref.beta, p.gamma, X, ref.b)
-    assert _decision_err(dg, do) <= 1e-9
+    assert _decision_err(dg, do) <= 1e-7
 
 
 def test_offset_blobs_identical_basis_f64():

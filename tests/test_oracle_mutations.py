@@ -124,6 +124,13 @@ def test_stream_started_at_step_instead_of_next_is_caught(monkeypatch):
     assert pins.stream_start_mismatches() > 0
 
 
+def test_stream_steps_one_draw_apart_is_caught(monkeypatch):
+    # each step starting one state after the previous one: seed 0 then draws a sliding window of candidates
+    monkeypatch.setattr(orng, "step_state", lambda seed, t: (seed ^ (((t + 1) * orng.GOLDEN) & orng.MASK64)) & orng.MASK64)
+    assert pins.stream_start_mismatches() > 0
+    assert pins.consecutive_step_overlap() > 0
+
+
 def test_stream_seed_added_instead_of_xored_is_caught(monkeypatch):
     monkeypatch.setattr(orng, "step_state", lambda seed, t: (seed + (t + 1) * orng.GOLDEN) & orng.MASK64)
     assert pins.stream_start_mismatches() > 0
@@ -207,12 +214,12 @@ def _shared_fails(**kw):
 
 def test_shared_score_from_first_problem_only_is_caught(monkeypatch):
     monkeypatch.setattr(osp, "_shared_total", lambda dls: dls[0])
-    assert _shared_fails(steps=6)
+    assert _shared_fails(steps=8)
 
 
 def test_shared_score_as_maximum_is_caught(monkeypatch):
     monkeypatch.setattr(osp, "_shared_total", lambda dls: max(dls))
-    assert _shared_fails(steps=6)
+    assert _shared_fails(steps=8)
 
 
 def test_shared_columns_with_one_gamma_are_caught(monkeypatch):
