@@ -129,6 +129,20 @@ void launch_score_init(const int32_t* cand, const double* o, const uint64_t* has
 // pass sums, the flip counts and the window lists agree row by row.
 __device__ __forceinline__ double gap_at(double a, double b, double z) { return __fma_rn(-z, b, a); }
 
+// For a label y = +-1 (the entry points reject any other value), y o and y k are o and k with their sign
+// flipped when y < 0, exactly: a_i = 1 - y_i o_i as margin_gap gives it, with the sign taken by integer
+// operations (scalar ones where y and o are the same for the whole wave) instead of a conversion and an FP64
+// product, and b_i = y_i k_i from an exact FP32 product (FP64 values: the sign flipped).
+__device__ __forceinline__ double gap_pm1(float y, double o) {
+  const long long sign = (long long)(__float_as_uint(y) & 0x80000000u) << 32;
+  return __dadd_rn(1.0, -__longlong_as_double(__double_as_longlong(o) ^ sign));
+}
+__device__ __forceinline__ double signed_pm1(float y, float k) { return (double)(y * k); }
+__device__ __forceinline__ double signed_pm1(float y, double k) {
+  const long long sign = (long long)(__float_as_uint(y) & 0x80000000u) << 32;
+  return __longlong_as_double(__double_as_longlong(k) ^ sign);
+}
+
 constexpr double kWinFrac = 1.0 / 256.0;  // window half-width relative to |s|
 
 struct WinRoot {
@@ -299,10 +313,12 @@ __global__ __launch_bounds__(64 * kScoreWaves, 5) void k_score_pass(const TK* __
     auto one = [&](double av, double b, double& Pa, double& Qa, double& Va, int& fa) {
       const double e = gap_at(av, b, s);
       const double ua = fmax(av, 0.0), we = fmax(e, 0.0);
-      // selects rather than branches (adding an exact zero leaves a sum unchanged), so that no control flow
-      // keeps the compiler from issuing a chunk's loads together
-      Pa += e > 0.0 ? av * b : 0.0;
-      Qa += e > 0.0 ? b * b : 0.0;
+      // b where the row is active at s, else an exact zero (whose products add nothing): one select, not a
+      // branch, so that no control flow keeps the compiler from issuing a chunk's loads together, feeds both
+      // sums, each one fused multiply-add (the pass is bound by its vector ALU instructions)
+      const double bm = e > 0.0 ? b : 0.0;
+      Pa = __fma_rn(av, bm, Pa);
+      Qa = __fma_rn(bm, bm, Qa);
       Va += (we - ua) * (we + ua);
       fa += chk && ((e > 0.0) != (gap_at(av, b, sp) > 0.0)) ? 1 : 0;
       // rows whose activity changes inside the window (rare): every one is counted, so a list that ran out of
@@ -316,11 +332,12 @@ __global__ __launch_bounds__(64 * kScoreWaves, 5) void k_score_pass(const TK* __
       }
     };
     // chunks of U consecutive rows per lane (contiguous loads from the column), even rows summed apart from odd
-    auto chunk = [&](const float* yv, const double* ov, const TK* kv) {
+    // (uniform: y and o are the same in every lane, where the sign of a_i is best taken by scalar operations)
+    auto chunk = [&](auto uniform, const float* yv, const double* ov, const TK* kv) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const double av = margin_gap(yv[u], ov[u]);
-        const double b = (double)yv[u] * (double)kv[u];
+        const double av = decltype(uniform)::value ? gap_pm1(yv[u], ov[u]) : margin_gap(yv[u], ov[u]);
+        const double b = signed_pm1(yv[u], kv[u]);
         if (u & 1)
           one(av, b, P2, Q2, V2, fl2);
         else
@@ -342,7 +359,7 @@ __global__ __launch_bounds__(64 * kScoreWaves, 5) void k_score_pass(const TK* __
           ov[u] = o[iu + u];
           kv[u] = kc[iu + u];
         }
-        chunk(yv, ov, kv);
+        chunk(std::true_type{}, yv, ov, kv);
       }
       i = iu;
     } else {
@@ -356,10 +373,10 @@ __global__ __launch_bounds__(64 * kScoreWaves, 5) void k_score_pass(const TK* __
           ov[u] = o[i + u];
           kv[u] = kc[i + u];
         }
-        chunk(yv, ov, kv);
+        chunk(std::false_type{}, yv, ov, kv);
       }
     }
-    for (; i < hi; ++i) one(margin_gap(y[i], o[i]), (double)y[i] * (double)kc[i], P, Q, V, fl);  // partial chunk
+    for (; i < hi; ++i) one(margin_gap(y[i], o[i]), signed_pm1(y[i], kc[i]), P, Q, V, fl);  // partial chunk
     P += P2;
     Q += Q2;
     V += V2;
