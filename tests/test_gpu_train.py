@@ -57,12 +57,13 @@ def test_wide_rows_identical_basis_f64():
     assert abs(Fo - ref.F) <= 1e-6 * ref.F
 
 
-@pytest.mark.parametrize("kappa", [64, 33])
+@pytest.mark.parametrize("kappa", [64, 33, 1])
 def test_grouped_candidate_launches_identical_basis_f64(kappa):
     """300 features: candidate steps share kernel-block launches that take only the drawn candidates, each written
     to its own slot (kappa = 64: every slot in use, 48 steps fill 3072 columns; kappa = 33: up to 52 steps, 1716
-    columns). Stages of 1, 1, 2, .., 64 and 2 steps: the 64-step stage takes two launches (48 + 16 or 52 + 12
-    steps). The FP64 path must still pick the oracle's basis, step for step."""
+    columns; kappa = 1: 52 one-candidate steps in one 64-column tile). Stages of 1, 1, 2, .., 64 and 2 steps: the
+    64-step stage takes two launches (48 + 16 or 52 + 12 steps). The FP64 path must still pick the oracle's basis,
+    step for step."""
     X, y = datagen.make_blobs(2200, 300, seed=26)
     C, gamma, m = 1.0, 1.0 / 300, 130
     ref = oracle.train(X, y, C, gamma, m, seed=8, kappa=kappa, growth=1.0)
