@@ -32,15 +32,6 @@ constexpr int NB_LD = NB + 1;
 constexpr int SB = 16;
 
 // Grid z = slot of the batch.
-// Value of v in lane l of the wave (l the same for every lane, a constant once the loops are unrolled): two
-// v_readlane reads of the halves instead of a 64-bit shuffle through the LDS crossbar.
-__device__ __forceinline__ double lane_value(double v, int l) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 __global__ __launch_bounds__(256) void k_potrf_diag(const CholBatch bt, int64_t ldh, int m, int k0) {
   double* __restrict__ H = bt.H[blockIdx.z];
   double* __restrict__ Linv = bt.Linv[blockIdx.z];
@@ -48,6 +39,7 @@ __global__ __launch_bounds__(256) void k_potrf_diag(const CholBatch bt, int64_t 
   __shared__ double A[NB][NB_LD];
   __shared__ double X[NB][NB_LD];
   __shared__ double Rd[SB];
+  __shared__ __attribute__((aligned(16))) double Cj[SB];  // column j of the sub-block being factored
   __shared__ int bad;
   const int nb = m - k0 < NB ? m - k0 : NB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, i16 = lane & 15;
@@ -71,43 +63,45 @@ __global__ __launch_bounds__(256) void k_potrf_diag(const CholBatch bt, int64_t 
   for (int kb = 0; kb < NB / SB; ++kb) {
     const int c0 = kb * SB;
     if (w == 0) {
-      // Unblocked factorisation and inversion of the 16 x 16 diagonal sub-block in registers: lane l < 16
-      // holds column l (a[i] = A[c0 + i][c0 + l]); column j is broadcast with lane reads.
-      double a[SB], x[SB];
+      // Unblocked Cholesky factorisation and inversion of the 16 x 16 diagonal sub-block: lane l < 16 holds row l
+      // (r[i] = A[c0 + l][c0 + i], i <= l). Step j: every lane puts its column-j entry in LDS and the wave reads
+      // the column back as broadcasts (one store and eight 16-byte reads, no lane reads); the rows below j take
+      // L[l][j] = r[j] / L[j][j] and subtract L[l][j] L[i][j] from every r[i], i > j. For i > l that entry is in
+      // the unused upper triangle, so the update needs no test; lanes 16..63 shadow row 0 and write nothing.
+      const int lr = lane < SB ? lane : 0;
+      double r[SB], x[SB];
 #pragma unroll
-      for (int i = 0; i < SB; ++i) a[i] = lane < SB ? A[c0 + i][c0 + lane] : 0.0;
+      for (int i = 0; i < SB; ++i) r[i] = A[c0 + lr][c0 + i];
       bool badl = false;
+      double rdl = 1.0;  // 1 / L[lane][lane]
 #pragma unroll
       for (int j = 0; j < SB; ++j) {
-        double pc[SB];
+        if (lane < SB) Cj[lane] = r[j];
+        __builtin_amdgcn_wave_barrier();
+        double cj[SB];
 #pragma unroll
-        for (int i = 0; i < SB; ++i) pc[i] = lane_value(a[i], j);
-        const double piv = pc[j];
+        for (int i = 0; i < SB; ++i) cj[i] = Cj[i];
+        __builtin_amdgcn_wave_barrier();
+        const double piv = cj[j];
         const bool ok = piv > 0.0 && piv < __builtin_huge_val();
         badl |= !ok;
-        double alj = 0.0;
+        // 1 / sqrt(piv) from the hardware estimate and one Newton step (relative error squared, far below FP64
+        // rounding), then L[j][j] = piv / sqrt(piv): four dependent operations instead of a sqrt and a division
+        const double pv = ok ? piv : 1.0, y0 = __builtin_amdgcn_rsq(pv);
+        const double rd = y0 * __fma_rn(-0.5 * pv * y0, y0, 1.5), d = pv * rd;
+        const double lj = r[j] * rd;  // L[lane][j] for the rows below j
 #pragma unroll
-        for (int i = 0; i < SB; ++i) alj = (lane == i) ? pc[i] : alj;
-        const double rpiv = ok ? 1.0 / piv : 0.0;  // one reciprocal per column, shared by the lanes
-        alj *= rpiv;
-#pragma unroll
-        for (int i = 0; i < SB; ++i)
-          if (lane > j && lane < SB && i >= lane) a[i] -= pc[i] * alj;
+        for (int i = j + 1; i < SB; ++i) r[i] = __fma_rn(-lj, cj[i] * rd, r[i]);
+        r[j] = lane == j ? d : lj;
+        rdl = lane == j ? rd : rdl;
       }
-      double dg = 1.0;
-#pragma unroll
-      for (int i = 0; i < SB; ++i) dg = (lane == i) ? a[i] : dg;
-      dg = (dg > 0.0 && dg < __builtin_huge_val()) ? sqrt(dg) : 1.0;
-      const double rdg = 1.0 / dg;
-#pragma unroll
-      for (int i = 0; i < SB; ++i) a[i] = (i == lane) ? dg : (i > lane ? a[i] * rdg : a[i]);
-      // L's column `lane` goes to LDS; then column lane of the inverse, x_i = (e_lane[i] - sum_{q < i} L[i][q]
+      // L's row `lane` goes to LDS; then column lane of the inverse, x_i = (e_lane[i] - sum_{q < i} L[i][q]
       // x_q) / L[i][i], with L read back at addresses common to the wave (LDS broadcasts; one wave, in order)
       if (lane < SB) {
 #pragma unroll
         for (int i = 0; i < SB; ++i)
-          if (i >= lane) A[c0 + i][c0 + lane] = a[i];
-        Rd[lane] = rdg;
+          if (i <= lane) A[c0 + lane][c0 + i] = r[i];
+        Rd[lane] = rdl;
       }
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
