@@ -83,7 +83,9 @@ __global__ __launch_bounds__(256) void k_potrf_diag(const CholBatch bt, int64_t 
         for (int i = 0; i < SB; ++i) cj[i] = Cj[i];
         __builtin_amdgcn_wave_barrier();
         const double piv = cj[j];
-        const bool ok = piv > 0.0 && piv < __builtin_huge_val();
+        // a pivot must be a positive normal number (a subnormal one is as good as zero here, and the hardware
+        // estimate below need not take it): else the factorisation is reported as not positive definite
+        const bool ok = piv >= 2.2250738585072014e-308 && piv < __builtin_huge_val();
         badl |= !ok;
         // 1 / sqrt(piv) from the hardware estimate and one Newton step (relative error squared, far below FP64
         // rounding), then L[j][j] = piv / sqrt(piv): four dependent operations instead of a sqrt and a division
