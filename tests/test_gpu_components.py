@@ -111,8 +111,11 @@ def test_newton_solve_matches_numpy(m):
     assert torch.isnan(Hd[upper]).all()
 
 
-def test_newton_solve_reports_not_pd():
-    H = torch.tensor(np.diag([1.0, -1.0, 2.0]), device="cuda")
+@pytest.mark.parametrize("bad", [-1.0, 0.0, 1e-310])
+def test_newton_solve_reports_not_pd(bad):
+    """A pivot that is negative, zero or subnormal (as good as zero at FP64 scale) is reported as not positive
+    definite, not turned into an infinite factor."""
+    H = torch.tensor(np.diag([1.0, bad, 2.0]), device="cuda")
     with pytest.raises(lib.SpsvmError) as e:
         lib.newton_solve(H, torch.ones(3, dtype=torch.float64, device="cuda"))
     assert e.value.status == 4
