@@ -65,7 +65,8 @@ spsvm_status spsvm_candidate_draw(uint64_t seed, int64_t t, int64_t n, int32_t k
  *   a_i = 1 - y_i o_i, b_i = y_i k_c[i],  score_c = psi_c(0) - min_s psi_c(s) >= 0.
  * The same passes and updates as greedy training run (64 candidate slots, semismooth Newton on psi_c' with the
  * window walk, candidates that cannot win dropped), up to 64 passes.
- *  o: device, n doubles (current outputs K_XJ beta). y: device, n floats, +1 or -1.
+ *  o: device, n doubles (current outputs K_XJ beta). y: device, n floats, each exactly +1 or -1 (checked on the
+ *    device first: SPSVM_E_INVALID_ARG otherwise).
  *  Kc: device, the ncand candidate columns, column-major: column c (n values of type kdt) starts at
  *    Kc + c * ldc elements, ldc >= n. oc: host, ncand doubles, o at each candidate's row. 1 <= ncand <= 64.
  *  s_out, score_out: host, ncand doubles: the minimiser and the score of each candidate with status 1; a dropped

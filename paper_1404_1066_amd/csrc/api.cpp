@@ -528,7 +528,16 @@ spsvm_status spsvm_score_candidates(const double* o, const float* y, int64_t n, 
     double* ocd = (double*)(w + 256);
     uint64_t* hash = (uint64_t*)(w + 768);
     uint64_t* stage_hash = (uint64_t*)(w + 1280);
+    int32_t* flags = (int32_t*)(w + 1792);  // input checks (3 words)
     NewtonScalars* sc = (NewtonScalars*)(w + 2048);
+    {  // labels exactly +1 or -1 (the passes take y_i o_i as o_i with its sign flipped where y_i = -1)
+      SPSVM_HIP(hipMemsetAsync(flags, 0, 16, st));
+      launch_check_inputs<float>(nullptr, 0, y, n, flags, st);
+      int32_t f[4] = {0, 0, 0, 0};
+      SPSVM_HIP(hipMemcpyAsync(f, flags, 16, hipMemcpyDeviceToHost, st));
+      SPSVM_HIP(hipStreamSynchronize(st));
+      if (f[1]) throw Failure(SPSVM_E_INVALID_ARG, "labels must be exactly +1 or -1");
+    }
     std::vector<int32_t> ch(kCandSlots, -1);
     std::vector<double> oh(kCandSlots, 0.0);
     std::vector<uint64_t> zh(kCandSlots, 0);

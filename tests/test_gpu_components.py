@@ -161,6 +161,18 @@ def test_candidate_scores_match_oracle(n, ncand, C):
     assert res["winner"] == want
 
 
+@pytest.mark.parametrize("label", [0.5, 0.0, float("nan")])
+def test_candidate_scores_reject_labels_other_than_plus_minus_one(label):
+    n = 1000
+    y = torch.ones(n, dtype=torch.float32, device="cuda")
+    y[n // 2] = label
+    o = torch.zeros(n, dtype=torch.float64, device="cuda")
+    Kc = torch.rand(3, n, dtype=torch.float32, device="cuda")
+    with pytest.raises(lib.SpsvmError) as e:
+        lib.score_candidates(o, y, Kc, np.zeros(3), 1.0)
+    assert e.value.status == 1
+
+
 @pytest.mark.parametrize("pad", [0, 1100000])
 def test_candidate_score_window_overflow_falls_back_to_full_passes(pad):
     """Two candidates with the same one-dimensional problem psi'(s) = 0.9 s - sum b max(0, a - s b), built from
